@@ -1,0 +1,224 @@
+"""Dense (no-symmetry) matrix-product-state TEBD in complex128.
+
+Test infrastructure (see the package header).  This is the oracle for the
+GPU path: it runs the same algorithm -- the two-site update by SVD of the
+paper's Sec. II -- without using the U(1) structure anywhere.
+
+Representation (Sec. II, Eq. (E1)): sites s = 0..L-1 (the paper's 1..M),
+bonds b = 0..L with bond b between site b-1 and site b; bonds 0 and L have
+dimension 1.  Two storage forms, identical in exact arithmetic:
+
+* ``vidal``:    Gamma[s] of shape (chi_s, d, chi_{s+1}) and lambda[b], the
+                amplitude being Gamma[0] lambda[1] Gamma[1] ... Gamma[L-1].
+* ``hastings``: B[s] = Gamma[s] lambda[s+1] (column-scaled), so the
+                amplitude is the plain product B[0] B[1] ... B[L-1] and the
+                update needs no division by lambda.  This is the default and
+                the form the GPU path stores.
+
+Two-site update on sites (s, s+1) (TEBD; the paper's "local updates"):
+
+1. theta~ = B[s] B[s+1] contracted over bond s+1, shape (chi_s, d, d, chi_{s+2});
+2. apply the projected two-mode gate P_d G P_d on the two physical indices;
+3. theta = lambda[s] * theta~ (row scaling), reshaped (chi_s d) x (d chi_{s+2});
+4. full SVD theta = U S V^dagger (LAPACK);
+5. keep K singular values by the cut rule of ``truncation``;
+6. B[s+1] = V^dagger[:K], lambda[s+1] = S[:K], B[s] = theta~ V[:, :K]
+   (= lambda[s]^-1 U S in exact arithmetic); no renormalisation.
+
+Charge audit (bookkeeping reference, independent of the block structure):
+for every bond the oracle keeps Q[b], the matrix of the photon number of
+sites < b in the left Schmidt basis of bond b.  A gate on bond s+1 updates
+Q[s+1] = U_K^dagger (Q[s] (x) 1 + 1 (x) diag(0..d-1)) U_K.  Its eigenvalues
+are integers when the kept subspace is closed under the charge; the bond's
+right-charge labels of Eq. (E3) are N minus those eigenvalues.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import scipy.linalg
+
+from . import twomode
+
+
+@dataclass
+class CutResult:
+    kept: int
+    discarded: float        # sum of squared dropped singular values
+    total: float            # sum of all squared singular values
+    margin: float           # (s[K-1] - s[K]) / s[0]; inf when nothing dropped
+
+
+def truncation(s: np.ndarray, chi_max: int, cutoff: float, zero_tol: float) -> CutResult:
+    """Global cut over one two-site matrix's singular values (sorted descending).
+
+    K = min(chi_max, K_eps, K_zero) where
+      K_eps  = smallest K with sum_{i>=K} s_i^2 <= cutoff * sum_i s_i^2,
+      K_zero = number of s_i > zero_tol * s_0  (numerically-zero values dropped),
+    chi_max <= 0 meaning no cap.  K is at least 1.  The discarded weight is
+    sum_{i>=K} s_i^2.  Sec. II names chi as the maximum bond dimension; the
+    weight criterion and the zero floor are readings (the paper is silent).
+    """
+    s = np.asarray(s, dtype=np.float64)
+    n = s.size
+    if n == 0 or not (s[0] > 0.0) or not np.all(np.isfinite(s)):
+        raise FloatingPointError("two-site matrix vanished or is not finite")
+    sq = s * s
+    tail = np.zeros(n + 1)
+    tail[:n] = np.cumsum(sq[::-1])[::-1]
+    total = float(tail[0])
+    k_eps = int(np.argmax(tail <= cutoff * total))   # first index meeting the bound
+    k_zero = int(np.sum(s > zero_tol * s[0]))
+    k = min(k_eps, k_zero)
+    if chi_max and chi_max > 0:
+        k = min(k, chi_max)
+    k = max(k, 1)
+    margin = float((s[k - 1] - s[k]) / s[0]) if k < n else math.inf
+    return CutResult(kept=k, discarded=float(tail[k]), total=total, margin=margin)
+
+
+def _svd(m: np.ndarray):
+    try:
+        return scipy.linalg.svd(m, full_matrices=False, lapack_driver="gesdd")
+    except np.linalg.LinAlgError:
+        return scipy.linalg.svd(m, full_matrices=False, lapack_driver="gesvd")
+
+
+@dataclass
+class GateRecord:
+    site: int
+    kept: int
+    discarded: float
+    margin: float
+    leak: float             # norm of theta lost to the local cutoff (P_d)
+    audit_ok: bool
+
+
+class DenseMPS:
+    """Dense MPS of L modes with local dimension d, started in a Fock product state."""
+
+    def __init__(self, occupation: Sequence[int], d: int, chi_max: int = 0,
+                 cutoff: float = 0.0, zero_tol: float = 1e-13, form: str = "hastings"):
+        occ = [int(x) for x in occupation]
+        if any(o < 0 or o >= d for o in occ):
+            raise ValueError("occupation outside 0..d-1")
+        if form not in ("hastings", "vidal"):
+            raise ValueError(form)
+        self.L, self.d, self.N = len(occ), d, sum(occ)
+        self.chi_max, self.cutoff, self.zero_tol, self.form = chi_max, cutoff, zero_tol, form
+        self.t: List[np.ndarray] = []          # B (hastings) or Gamma (vidal)
+        for o in occ:
+            a = np.zeros((1, d, 1), dtype=np.complex128)
+            a[0, o, 0] = 1.0
+            self.t.append(a)
+        self.lam: List[np.ndarray] = [np.ones(1) for _ in range(self.L + 1)]
+        left = np.concatenate([[0], np.cumsum(occ)])
+        self.q: List[np.ndarray] = [np.array([[float(left[b])]], dtype=np.complex128)
+                                    for b in range(self.L + 1)]
+        self.records: List[GateRecord] = []
+
+    # ------------------------------------------------------------------ update
+    def apply_gate(self, site: int, u: np.ndarray) -> GateRecord:
+        s, d = site, self.d
+        if not 0 <= s < self.L - 1:
+            raise IndexError("gate site out of range")
+        a, b = self.t[s], self.t[s + 1]
+        chl, chr_ = a.shape[0], b.shape[2]
+        if self.form == "hastings":
+            th = np.einsum("xiy,yjz->xijz", a, b)
+            lam_l = self.lam[s]
+        else:
+            th = np.einsum("xiy,y,yjz,z->xijz", a, self.lam[s + 1], b, self.lam[s + 2])
+            lam_l = self.lam[s]
+        g4 = twomode.dense(np.asarray(u, dtype=np.complex128), d).reshape(d, d, d, d)
+        before = float(np.sum(np.abs(lam_l[:, None, None, None] * th) ** 2))
+        th = np.einsum("pqmn,xmnz->xpqz", g4, th)
+        theta = lam_l[:, None, None, None] * th
+        after = float(np.sum(np.abs(theta) ** 2))
+        mat = theta.reshape(chl * d, d * chr_)
+        uu, sv, vh = _svd(mat)
+        cut = truncation(sv, self.chi_max, self.cutoff, self.zero_tol)
+        k = cut.kept
+        vk = vh[:k]
+        if self.form == "hastings":
+            self.t[s + 1] = vk.reshape(k, d, chr_)
+            self.t[s] = (th.reshape(chl * d, d * chr_) @ vk.conj().T).reshape(chl, d, k)
+        else:
+            self.t[s] = (uu[:, :k] / np.repeat(self.lam[s], d)[:, None]).reshape(chl, d, k)
+            self.t[s + 1] = (vk.reshape(k, d, chr_) / self.lam[s + 2][None, None, :])
+        self.lam[s + 1] = sv[:k].copy()
+        # charge audit of the new bond s+1
+        qrow = np.kron(self.q[s], np.eye(d)) + np.kron(np.eye(chl), np.diag(np.arange(d)))
+        uk = uu[:, :k]
+        self.q[s + 1] = uk.conj().T @ qrow @ uk
+        ev = np.linalg.eigvalsh(self.q[s + 1])
+        ok = bool(np.all(np.abs(ev - np.round(ev)) <= 1e-6))
+        rec = GateRecord(site=s, kept=k, discarded=cut.discarded, margin=cut.margin,
+                         leak=before - after, audit_ok=ok)
+        self.records.append(rec)
+        return rec
+
+    def run(self, gates) -> "DenseMPS":
+        for g in gates:
+            self.apply_gate(g.site, g.u)
+        return self
+
+    # ------------------------------------------------------------- read-outs
+    def site_matrices(self) -> List[np.ndarray]:
+        """The Hastings tensors B[s] (shape chi_s x d x chi_{s+1}) in either form."""
+        if self.form == "hastings":
+            return self.t
+        return [self.t[s] * self.lam[s + 1][None, None, :] for s in range(self.L)]
+
+    def amplitude(self, occ: Sequence[int]) -> complex:
+        """c_{i_1..i_L} by contracting the chain, Eq. (E1).  Occupations >= d are
+        outside the local space and give 0; a wrong photon number is still
+        contracted (it is zero only up to rounding in this dense form)."""
+        occ = [int(x) for x in occ]
+        if any(o < 0 or o >= self.d for o in occ):
+            return 0.0 + 0.0j
+        bs = self.site_matrices()
+        v = np.ones((1,), dtype=np.complex128)
+        for s, o in enumerate(occ):
+            v = v @ bs[s][:, o, :]
+        return complex(v[0])
+
+    def amplitudes(self, patterns: np.ndarray) -> np.ndarray:
+        pats = np.asarray(patterns, dtype=np.int64)
+        bs = self.site_matrices()
+        out = np.zeros(pats.shape[0], dtype=np.complex128)
+        valid = np.all((pats >= 0) & (pats < self.d), axis=1)
+        idx = np.nonzero(valid)[0]
+        if idx.size:
+            v = np.ones((idx.size, 1), dtype=np.complex128)
+            for s in range(self.L):
+                blk = bs[s][:, pats[idx, s], :]          # (chi_s, n, chi_{s+1})
+                v = np.einsum("nx,xny->ny", v, blk)
+            out[idx] = v[:, 0]
+        return out
+
+    def norm2(self) -> float:
+        """<psi|psi> by full contraction of the transfer matrices."""
+        e = np.ones((1, 1), dtype=np.complex128)
+        for bt in self.site_matrices():
+            e = np.einsum("ab,aic,bid->cd", e, bt.conj(), bt)
+        return float(e[0, 0].real)
+
+    def bond_dims(self) -> List[int]:
+        return [self.lam[b].size for b in range(self.L + 1)]
+
+    def bond_charges(self, bond: int) -> Dict[int, int]:
+        """Right-charge histogram of a bond from the charge audit (Eq. (E3))."""
+        ev = np.linalg.eigvalsh(self.q[bond])
+        hist: Dict[int, int] = {}
+        for e in ev:
+            c = self.N - int(round(float(e)))
+            hist[c] = hist.get(c, 0) + 1
+        return dict(sorted(hist.items()))
+
+    def audit_clean(self, bond: int, tol: float = 1e-6) -> bool:
+        ev = np.linalg.eigvalsh(self.q[bond])
+        return bool(np.all(np.abs(ev - np.round(ev)) <= tol))
