@@ -1,0 +1,202 @@
+"""Benchmark of the U(1)-symmetric MPS gate path on one MI355X.
+
+Workload: the linear-optics boson-sampling circuit with L = 32 modes,
+16 single photons in modes 0-15, local dimension d = 4, 32 brickwork layers
+of seeded beam splitters (496 gates), chi_max = 512, discarded-weight cutoff
+1e-12, complex128 arithmetic.  One step is the whole circuit from the Fock
+product state (every gate is one two-site update: Theta formation, gate,
+per-sector Jacobi SVD, cut, update); the gates of a layer go through the
+device together.  The state for every step is created before the timed
+region (inputs resident in HBM).
+
+Printed: one JSON line (stdout) with gate applies/s, the roofline of the
+dominant kernel (HIP events on the library's stream over the timed region)
+and the CPU oracle timed on a bounded prefix of the same circuit.
+Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
+CLASS_NAMES = ["jacobi_rows<0,512>", "jacobi_rows<1,1024>", "jacobi_rows<2,1024>",
+               "jacobi_rows<4,1024>", "jacobi_rows<8,1024>", "jacobi_rows<16,512>",
+               "jacobi_rows<32,256>"]
+METRIC = "gate applies/s + sector-GEMM TFLOP/s at χ=2048 vs plain; p50/p99 latency"
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = int(k), min(int(k) + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(cfg, seconds: float):
+    """The oracle (dense TEBD, NumPy/LAPACK) on the first layers of the same circuit."""
+    from oracle import dense_mps
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    m = dense_mps.DenseMPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"])
+    t0 = time.perf_counter()
+    gates = 0
+    nl = 0
+    for lay in cfg["layers"]:
+        for g in lay:
+            m.apply_gate(g.site, g.u)
+            gates += 1
+        nl += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    el = time.perf_counter() - t0
+    return {"value": gates / el, "unit": "gate applies/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"first {nl} of {len(cfg['layers'])} layers ({gates} gates) of the same circuit, "
+                      f"max bond dim reached {max(m.bond_dims())}; dense (chi*d)x(d*chi) complex128 "
+                      f"SVD per gate; {el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2303_11409_amd import MPS, TorchDevice
+    from workloads import circuits
+
+    torch.cuda.set_device(0)
+    cfg = circuits.config_plain_gpu()
+    layers = [([g.site for g in lay], [g.u for g in lay]) for lay in cfg["layers"]]
+    ngates = sum(len(s) for s, _ in layers)
+    dev = TorchDevice()
+
+    def new_state():
+        return MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"], device=dev)
+
+    def run(m):
+        for sites, us in layers:
+            m.apply_layer(sites, us)
+        m.sync()
+
+    for w in range(args.warmup):
+        t = time.perf_counter()
+        m = new_state()
+        run(m)
+        m.close()
+        log(f"warmup {w + 1}/{args.warmup}: {time.perf_counter() - t:.2f} s")
+
+    states = [new_state() for _ in range(args.steps)]
+    for m in states:
+        m.set_timing(True)
+        m.reset_stats()
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for i, m in enumerate(states):
+        ts = time.perf_counter()
+        run(m)
+        lat.append(time.perf_counter() - ts)
+        log(f"step {i + 1}/{args.steps}: {lat[-1]:.3f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    agg = None
+    for m in states:
+        st = m.stats()
+        if agg is None:
+            agg = st
+        else:
+            for k, v in st.items():
+                if isinstance(v, list):
+                    agg[k] = [a + b for a, b in zip(agg[k], v)]
+                elif k == "min_margin":
+                    agg[k] = min(agg[k], v)
+                elif k == "max_discarded":
+                    agg[k] = max(agg[k], v)
+                else:
+                    agg[k] += v
+    norm_loss = 1.0 - states[0].norm2()
+    max_chi = max(states[0].bond_dims())
+    for m in states:
+        m.close()
+
+    ci = int(np.argmax(agg["jacobi_class_ms"]))
+    cls_ms = agg["jacobi_class_ms"][ci]
+    cls_launch = max(agg["jacobi_class_launches"][ci], 1)
+    cls_flops = agg["jacobi_class_flops"][ci]
+    per_launch_flops = cls_flops / cls_launch
+    avg_ms = cls_ms / cls_launch
+    achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "kernel": CLASS_NAMES[ci], "avg_launch_ms": avg_ms,
+                "flops_per_launch": per_launch_flops, "launches": cls_launch}
+    value = args.steps * ngates / elapsed
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "gate applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "boson-sampling brickwork L=32, N=16 photons in modes 0-15, d=4, "
+                               "32 layers (496 beam splitters, seed 2), chi_max=512, cutoff 1e-12, "
+                               "complex128 (plain form)",
+                   "L": 32, "photons": 16, "d": 4, "layers": 32, "gates_per_step": ngates,
+                   "chi_max": 512, "cutoff": 1e-12, "form": "plain complex128, layer-batched"},
+        "roofline": roofline,
+        "latency_s": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "unit": "s per circuit"},
+        "kernels": {
+            "theta_tflops": agg["theta_flops"] / max(agg["theta_ms"], 1e-9) / 1e9,
+            "jacobi_tflops": agg["jacobi_flops"] / max(agg["jacobi_ms"], 1e-9) / 1e9,
+            "theta_ms": agg["theta_ms"] / args.steps, "jacobi_ms": agg["jacobi_ms"] / args.steps,
+            "select_ms": agg["select_ms"] / args.steps, "update_ms": agg["update_ms"] / args.steps,
+            "jacobi_class_ms": [x / args.steps for x in agg["jacobi_class_ms"]],
+            "jacobi_sweeps_per_sector": agg["sweeps"] / max(agg["sectors"], 1),
+        },
+        "result": {"norm_loss": norm_loss, "max_bond_dim": max_chi,
+                   "max_discarded": agg["max_discarded"], "min_cut_margin": agg["min_margin"]},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded prefix ...")
+        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,215 @@
+/*
+ * u1mps.h -- C ABI of the MI355X (gfx950) U(1)-symmetric MPS gate engine.
+ *
+ * The library applies photon-number-conserving two-mode gates (beam
+ * splitters of a linear-optics circuit) to a matrix-product state whose bond
+ * indices carry right-charge labels, and reads out amplitudes and norms.
+ *
+ * What is computed follows Sec. II of "Towards Symmetry-Aware Efficient
+ * Simulation of Quantum Systems and Beyond" (arXiv 2303.11409):
+ *   - the state is the Vidal-form MPS of Eq. (E1), sites 0..L-1 (the paper's
+ *     1..M), bonds 0..L, bond b between site b-1 and site b;
+ *   - every bond index alpha carries its right-charge c_b(alpha), the number
+ *     of photons on sites b..L-1 (Eq. (E3)); the Kronecker deltas of Eq. (E2)
+ *     fix the physical index of site s to c_s(alpha) - c_{s+1}(beta), so site
+ *     tensors carry no physical index; boundary charges are c_0 = N and
+ *     c_L = 0 (Eq. (E4));
+ *   - a two-site update builds Theta(m) for every middle charge m, takes its
+ *     SVD, and keeps the largest singular values over all m together, at most
+ *     chi of them (the block-sparse SVDs of Sec. II).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *   Complex numbers cross the boundary as mps_z (two doubles, re then im).
+ *   Every array argument is a HOST pointer unless stated otherwise; the
+ *   library copies inputs before it returns and never keeps caller memory.
+ *   The caller owns every output array; the library owns mps_t and all
+ *   device memory it obtained through mps_device.
+ *   A mode unitary u2 is 2x2 row-major {u00, u01, u10, u11} and maps creation
+ *   operators column-wise: a0^+ -> u00 a0^+ + u10 a1^+, a1^+ -> u01 a0^+ +
+ *   u11 a1^+.  A gate on `site` acts on modes site and site+1.
+ *   Errors: every call returns an mps_status; MPS_OK is 0, errors are
+ *   negative.  Argument and charge errors are detected before any state
+ *   changes.  A device-side failure (Jacobi non-convergence, a vanished or
+ *   non-finite two-site matrix) is reported by the call that detects it;
+ *   the state is then unspecified and the handle should be destroyed.
+ *   mps_last_error() returns a thread-local message for the last failure.
+ *   One handle must not be used from two threads at once.
+ */
+#ifndef U1MPS_H
+#define U1MPS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mps_state* mps_t;
+typedef struct { double re, im; } mps_z;
+
+typedef enum {
+  MPS_OK = 0,
+  MPS_E_ARG = -1,      /* bad argument (range, NULL, overlapping gates, ...)      */
+  MPS_E_CHARGE = -2,   /* charge labels violate Eqs. (E2)-(E4)                     */
+  MPS_E_NOMEM = -3,    /* the allocator returned NULL                              */
+  MPS_E_DEVICE = -4,   /* a HIP runtime call failed                                */
+  MPS_E_NOCONV = -5,   /* a Jacobi SVD did not converge within max_sweeps          */
+  MPS_E_NUMERIC = -6   /* a two-site matrix vanished or held a non-finite value    */
+} mps_status;
+
+/* Device memory and stream hooks.  alloc(bytes, ctx) returns a device
+ * pointer (NULL on failure); release(ptr, ctx) returns it.  Both may be NULL,
+ * in which case hipMalloc/hipFree are used.  `stream` is a hipStream_t on
+ * which every kernel and copy of the handle is issued (NULL: the null
+ * stream).  The struct is copied by mps_create. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*release)(void* ptr, void* ctx);
+  void* ctx;
+  void* stream;
+} mps_device;
+
+/* Truncation and solver options.
+ *   chi_max    cap on every bond dimension (Sec. II's chi); <= 0 means none.
+ *   cutoff     eps of the discarded-weight rule: keep the smallest K with
+ *              sum_{i>=K} s_i^2 <= eps * sum_i s_i^2 over the singular values
+ *              of all sectors of one two-site update; 0 disables it.
+ *   zero_tol   singular values <= zero_tol * s_max are dropped as numerical
+ *              zeros (default 1e-13).
+ *   max_sweeps Jacobi sweep limit per sector (default 40).
+ *   jacobi_tol rotate a row pair while |<x,y>| > tol * |x| |y|; <= 0 means
+ *              sqrt(row length) * 2^-52.
+ * The kept count is K = max(1, min(chi_max, K_eps, K_zero)). */
+typedef struct {
+  int chi_max;
+  double cutoff;
+  double zero_tol;
+  int max_sweeps;
+  double jacobi_tol;
+} mps_opts;
+
+/* Per-handle counters, accumulated since creation or mps_reset_stats.
+ * *_ms are kernel times from HIP events on the handle's stream; they are
+ * filled only while timing is enabled (mps_set_timing).  Flop figures are
+ * algorithmic: 8*nL*nM*nR per charge triple for Theta formation, and for the
+ * Jacobi kernel 16*len per row pair inspected, 20*len per rotation applied,
+ * 6*len per row for the final norms. */
+typedef struct {
+  long long gates;             /* two-site updates applied                  */
+  long long layers;            /* batched launches (mps_apply_layer calls)  */
+  long long sectors;           /* Theta(m) sectors decomposed               */
+  long long sweeps;            /* Jacobi sweeps summed over sectors         */
+  long long rotations;         /* Jacobi rotations applied                  */
+  long long pairs;             /* Jacobi row pairs inspected                */
+  double theta_flops, jacobi_flops, update_flops;
+  double theta_ms, jacobi_ms, select_ms, update_ms;
+  long long theta_launches, jacobi_launches, select_launches, update_launches;
+  double max_discarded;        /* largest per-gate discarded weight          */
+  double min_margin;           /* smallest (s_{K-1} - s_K)/s_0 at a cut      */
+  /* Jacobi kernel split by row-length class: class i holds rows of length
+   * <= 64 * 2^(i-1) for i = 1..6 (64 .. 2048) and longer rows for i = 0. */
+  double jacobi_class_ms[7];
+  double jacobi_class_flops[7];
+  long long jacobi_class_launches[7];
+  long long jacobi_class_sectors[7];
+} mps_stats;
+
+/* Fill *o with the defaults: chi_max 0, cutoff 0, zero_tol 1e-13,
+ * max_sweeps 40, jacobi_tol 0. */
+void mps_default_opts(mps_opts* o);
+
+/* Create a state of L sites with local dimension d (occupations 0..d-1,
+ * Eq. (E1)) and n_photons = N photons.
+ *   bond_dim[L+1]    dimension of every bond; bond_dim[0] = bond_dim[L] = 1.
+ *   bond_charge[]    right-charges (Eq. (E3)) of every bond index, bonds 0..L
+ *                    concatenated (sum of bond_dim entries); bond 0 is {N}
+ *                    and bond L is {0} (Eq. (E4)); every charge in [0, N].
+ *   gamma            NULL, or L host pointers; gamma[s] is the Vidal tensor
+ *                    Gamma[s] as a bond_dim[s] x bond_dim[s+1] row-major
+ *                    complex matrix in the caller's index order; entries
+ *                    whose charge difference lies outside 0..d-1 must be 0.
+ *   lambda           NULL, or L+1 host pointers to the Schmidt values of
+ *                    every bond (bond 0 and L: {1}).  Required with gamma.
+ * With gamma == NULL every bond must have dimension 1 and the state is the
+ * Fock product state whose occupations are the charge differences.
+ * Bond indices are reordered internally by ascending charge (stable).
+ * Errors: MPS_E_ARG, MPS_E_CHARGE, MPS_E_NOMEM, MPS_E_DEVICE. */
+mps_status mps_create(int L, int d, int n_photons, const int* bond_dim,
+                      const int* bond_charge, const mps_z* const* gamma,
+                      const double* const* lambda, const mps_opts* opts,
+                      const mps_device* dev, mps_t* out);
+
+/* Convenience: the Fock product state |occupation[0], ..., occupation[L-1]>. */
+mps_status mps_create_product(int L, int d, const int* occupation,
+                              const mps_opts* opts, const mps_device* dev,
+                              mps_t* out);
+
+/* Release every resource of the handle (NULL is accepted). */
+mps_status mps_destroy(mps_t h);
+
+/* One two-site update on sites (site, site+1): Theta formation by charge-
+ * sector-matched products, the gate applied block by block per total local
+ * photon number n (its elements are those of the symmetric power of u2,
+ * projected to occupations < d), per-middle-charge SVD, one cut over all
+ * sectors, and the new site tensors, Schmidt values and bond charges.
+ *   discarded  out, may be NULL: sum of the dropped squared singular values.
+ * Errors: MPS_E_ARG, MPS_E_NOCONV, MPS_E_NUMERIC, MPS_E_NOMEM, MPS_E_DEVICE. */
+mps_status mps_apply_gate(mps_t h, int site, const mps_z u2[4], double* discarded);
+
+/* The same update for ngates gates on pairwise disjoint site pairs
+ * (|site_i - site_j| >= 2), executed together: one launch per step for all
+ * of them.  u2s holds ngates 2x2 matrices back to back; discarded[ngates]
+ * (may be NULL) receives each gate's weight.  The result equals applying the
+ * gates one by one in any order. */
+mps_status mps_apply_layer(mps_t h, int ngates, const int* sites,
+                           const mps_z* u2s, double* discarded);
+
+/* Re-truncate bond `bond` (1..L-1) from its stored Schmidt values with the
+ * same rule (chi_max, cutoff, the handle's zero_tol), without an SVD: the
+ * dropped Schmidt vectors are removed from sites bond-1 and bond.  Exact
+ * when the state is in canonical form.  discarded may be NULL. */
+mps_status mps_truncate(mps_t h, int bond, int chi_max, double cutoff,
+                        double* discarded);
+
+/* Amplitudes c_{i_1..i_L} (Eq. (E2)) of `count` occupation patterns,
+ * occ[count*L] row-major; out[count].  A pattern whose photon number differs
+ * from N, with an occupation outside 0..d-1, or whose charge path meets a
+ * charge absent from a bond gives exactly 0. */
+mps_status mps_amplitude(mps_t h, int count, const int* occ, mps_z* out);
+
+/* <psi|psi> by full contraction of the transfer matrices (not sum lambda^2). */
+mps_status mps_norm(mps_t h, double* norm2);
+
+/* Bookkeeping of bond `bond` (0..L): its distinct charges in ascending
+ * order and their multiplicities.  cap is the capacity of charge[] and
+ * count[]; *nsec receives the number of sectors (MPS_E_ARG if > cap). */
+mps_status mps_bond_sectors(mps_t h, int bond, int cap, int* nsec,
+                            int* charge, int* count);
+
+/* Schmidt values of bond `bond`, ordered by ascending charge and, within a
+ * charge, descending value.  *n receives the bond dimension. */
+mps_status mps_bond_lambda(mps_t h, int bond, int cap, int* n, double* lambda);
+
+/* Copy site tensor B[site] = Gamma[site] lambda[site+1] as a dense
+ * rows x cols row-major matrix (rows: bond `site`, cols: bond `site`+1, both
+ * in ascending-charge order).  cap is out's capacity in elements. */
+mps_status mps_site_tensor(mps_t h, int site, size_t cap, int* rows, int* cols,
+                           mps_z* out);
+
+/* Enable (1) or disable (0) HIP-event timing of every kernel launch. */
+mps_status mps_set_timing(mps_t h, int on);
+mps_status mps_get_stats(mps_t h, mps_stats* s);
+mps_status mps_reset_stats(mps_t h);
+
+/* Wait for all work of the handle; reports deferred device errors. */
+mps_status mps_sync(mps_t h);
+
+/* Thread-local text of the last error (never NULL). */
+const char* mps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* U1MPS_H */

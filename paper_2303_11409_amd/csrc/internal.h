@@ -1,0 +1,110 @@
+// Internal work-list records shared by the host runtime and the gfx950 kernels.
+//
+// Storage (all device, complex128 as double2):
+//   site tensor B[s] = Gamma[s] * lambda[s+1] is a dense chi_s x chi_{s+1}
+//   row-major "frame" whose rows (bond s) and columns (bond s+1) are sorted by
+//   ascending right-charge.  Entries whose charge difference lies outside
+//   0..d-1 are structural zeros (Eq. (E2)); kernels address only the allowed
+//   blocks, and the update kernels write the zeros explicitly.  Because the
+//   charges are sorted, every charge window [c, c+d-1] of a bond is one
+//   contiguous index range, so each Theta(m) sector and each update block is
+//   a strided submatrix.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace u1mps {
+
+constexpr int kMaxD = 8;          // local dimension limit (occupations 0..7)
+constexpr int kThetaTile = 32;    // Theta output tile edge
+constexpr int kGemmTile = 32;     // generic ZGEMM tile edge
+
+// One two-site update inside a batch.
+struct GateWork {
+  const double2* bl;      // B[s]   frame, chi_s x chi_{s+1}, row stride ldl
+  const double2* br;      // B[s+1] frame, chi_{s+1} x chi_{s+2}, row stride ldr
+  const double* lam_l;    // lambda of bond s (chi_s)
+  int ldl, ldr;
+  int coef;               // offset of this gate's (2d-1) x d x d coefficients
+  int d;
+  int sec_begin, sec_end; // sector range [begin, end) in the batch's sector list
+  int keep_cap;           // largest admissible new bond dimension
+  int chi_max;            // <= 0: none
+  double cutoff;
+  double zero_tol;
+};
+
+// One middle-charge sector Theta(m) of one gate.
+struct SectorWork {
+  int gate;               // index into the batch's GateWork list
+  int m;                  // middle charge
+  int r, c;               // Theta(m) is r x c
+  int rlo, clo;           // first row (bond s index) / column (bond s+2 index)
+  long long off;          // element offset of Theta(m) in the theta workspaces
+  int sig;                // offset of this sector's r singular values / row order
+  int kmax;               // min(r, c): at most this many values enter the cut
+};
+
+// One 32x32 output tile of one (cL, cR) charge pair of one gate.  The tile
+// accumulates the products B[s](cL, cM) B[s+1](cM, cR) for every middle
+// charge cM of the old bond that lies in the window, then mixes them with
+// the gate block G^(n), n = cL - cR, into every new sector m of the window.
+struct ThetaTile {
+  int gate;
+  int row0, nrow;         // rows of the tile, bond s index space
+  int col0, ncol;         // columns of the tile, bond s+2 index space
+  int n;                  // total local photon number of the pair
+  int nin, nout;
+  int k0[kMaxD], kn[kMaxD], a[kMaxD];      // input segments: start, length, cL - cM
+  int sec[kMaxD], p[kMaxD];                // output sector, cL - m
+  int orow[kMaxD], ocol[kMaxD];            // tile origin inside Theta(m)
+};
+
+// A generic complex GEMM problem C = op(A) op(B) (+ C when beta_one).
+// op 0 = as stored (row-major), op 1 = conjugate transpose of the stored matrix.
+struct GemmWork {
+  const double2* a;
+  const double2* b;
+  double2* c;
+  int m, n, k;
+  int lda, ldb, ldc;
+  int opa, opb;
+  int beta_one;
+  int tiles_n;            // ceil(n / kGemmTile)
+  int tile_begin;         // first flattened tile of this problem
+};
+
+// New-row descriptor for the update of B[s+1] and lambda[s+1].
+struct RowWork {
+  int gate;               // GateWork index (for the output pointers)
+  int sector;             // SectorWork index
+  int j;                  // rank inside the sector (0 = largest value)
+  int row;                // row of the new frame
+};
+
+// Output pointers of one gate's update.
+struct UpdateWork {
+  double2* br_new;        // new B[s+1] frame, chi' x chi_{s+2}, stride ldr
+  double* lam_new;        // new lambda (chi')
+  int ldr;                // chi_{s+2}
+};
+
+// Result of the cut of one gate, written by the select kernel.
+struct CutOut {
+  int kept;
+  int flags;              // bit 0: vanished/non-finite
+  double discarded;
+  double total;
+  double margin;
+};
+
+// Per-sector Jacobi statistics.
+struct JacobiOut {
+  int sweeps;
+  int rotations;
+  int converged;
+  int pad;
+};
+
+}  // namespace u1mps

@@ -1,0 +1,42 @@
+// Launch wrappers of the gfx950 kernels (kernels.hip).  Every pointer is a
+// device pointer; every launch goes to the given stream.
+#pragma once
+
+#include "internal.h"
+
+namespace u1mps {
+
+hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntiles,
+                        const SectorWork* secs, const double2* coef, double2* raw,
+                        double2* scaled, int maxw, hipStream_t st);
+
+// Row-length class of the Jacobi kernel: E complex per lane per row, 0 = streaming.
+int jacobi_class(int len);
+hipError_t launch_jacobi(int ecls, const SectorWork* secs, const int* list, int count, int maxrows,
+                         double2* theta, double* sigma, int* order, JacobiOut* stats,
+                         int max_sweeps, double tol, hipStream_t st);
+
+hipError_t launch_select(const GateWork* gates, int ngates, const SectorWork* secs,
+                         const double* sigma, double* gsv, int* gsk, const long long* scratch_off,
+                         int* kept, CutOut* cut, int maxP, hipStream_t st);
+
+hipError_t launch_update_rows(const RowWork* rows, int nrows, const SectorWork* secs,
+                              const UpdateWork* upd, const double2* vh, const double* sigma,
+                              const int* order, hipStream_t st);
+
+hipError_t launch_zero_fill(double2* const* ptrs, const long long* counts, int nranges,
+                            long long maxcount, hipStream_t st);
+
+hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_t st);
+
+hipError_t launch_amplitude(const double2* const* sites, const int* ld, const int2* bondmap,
+                            const int* occ, double2* out, int count, int L, int d, int N,
+                            int maxdim, hipStream_t st);
+
+hipError_t launch_gather_cols(const double2* src, int lds, double2* dst, int ldd, int rows,
+                              const int* map, int ncols, hipStream_t st);
+hipError_t launch_gather_rows(const double2* src, int lds, double2* dst, int ldd, const int* map,
+                              int nrows, int cols, hipStream_t st);
+hipError_t launch_gather_vec(const double* src, double* dst, const int* map, int n, hipStream_t st);
+
+}  // namespace u1mps

@@ -1,0 +1,768 @@
+// gfx950 kernels of the U(1)-symmetric MPS two-site update and read-outs.
+//
+// Steps of one update on sites (s, s+1) (Sec. II of arXiv 2303.11409):
+//   theta_kernel   Theta~(cL, m, cR) = sum_cM G^(n)[(cL-m), (cL-cM)] B[s](cL,cM) B[s+1](cM,cR)
+//                  (charge-sector-matched products, gate mixed per n = cL - cR
+//                  in the epilogue), plus Theta = lambda_s * Theta~ for the SVD.
+//   jacobi_rows    one-sided (Hestenes) Jacobi on the rows of every Theta(m):
+//                  rotations until all row pairs are orthogonal; the row norms
+//                  are the singular values and the normalised rows are V^dagger.
+//   select_kernel  one cut over all sectors of a gate: sort, discarded-weight
+//                  rule, chi cap, kept count per sector (FP64).
+//   update_*       new B[s+1] = kept V^dagger rows, lambda = kept values,
+//                  new B[s] = Theta~ V_kept (generic complex GEMM).
+// Wave64 throughout: reductions use cross-lane shuffles over 64 lanes.
+#include "kernels.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace u1mps {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ void cfma(double2& acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Theta formation.  One workgroup (256 threads, 16 x 16) per 32 x 32 tile of
+// one (cL, cR) pair; each thread owns rows ty, ty+16 and columns tx, tx+16.
+template <int W>
+__global__ void __launch_bounds__(256)
+theta_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ tiles,
+             const SectorWork* __restrict__ secs, const double2* __restrict__ coef,
+             double2* __restrict__ th_raw, double2* __restrict__ th_scaled) {
+  __shared__ ThetaTile t;
+  __shared__ double2 as[kThetaTile][17];
+  __shared__ double2 bs[16][kThetaTile + 1];
+  if (threadIdx.x == 0) t = tiles[blockIdx.x];
+  __syncthreads();
+  const GateWork g = gates[t.gate];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+
+  double2 out[W][2][2];
+#pragma unroll
+  for (int i = 0; i < W; ++i)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) out[i][a][b] = make_double2(0.0, 0.0);
+
+  for (int j = 0; j < t.nin; ++j) {
+    double2 p[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) p[a][b] = make_double2(0.0, 0.0);
+    const int kb = t.k0[j], ke = t.k0[j] + t.kn[j];
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+      // A tile: 32 rows x 16 k, two elements per thread
+      for (int e = threadIdx.x; e < kThetaTile * 16; e += 256) {
+        const int r = e >> 4, kk = e & 15;
+        const int k = k0 + kk;
+        double2 v = make_double2(0.0, 0.0);
+        if (r < t.nrow && k < ke) v = g.bl[(size_t)(t.row0 + r) * g.ldl + k];
+        as[r][kk] = v;
+      }
+      // B tile: 16 k x 32 columns
+      for (int e = threadIdx.x; e < 16 * kThetaTile; e += 256) {
+        const int kk = e >> 5, c = e & 31;
+        const int k = k0 + kk;
+        double2 v = make_double2(0.0, 0.0);
+        if (c < t.ncol && k < ke) v = g.br[(size_t)k * g.ldr + t.col0 + c];
+        bs[kk][c] = v;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < 16; ++kk) {
+        const double2 a0 = as[ty][kk], a1 = as[ty + 16][kk];
+        const double2 b0 = bs[kk][tx], b1 = bs[kk][tx + 16];
+        cfma(p[0][0], a0, b0);
+        cfma(p[0][1], a0, b1);
+        cfma(p[1][0], a1, b0);
+        cfma(p[1][1], a1, b1);
+      }
+      __syncthreads();
+    }
+    // gate mix: out_i += G^(n)[p_i][a_j] * P_j
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      if (i < t.nout) {
+        const double2 gc = coef[g.coef + (t.n * g.d + t.p[i]) * g.d + t.a[j]];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) cfma(out[i][a][b], gc, p[a][b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    if (i < t.nout) {
+      const SectorWork s = secs[t.sec[i]];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int r = ty + 16 * a;
+        if (r >= t.nrow) continue;
+        const double lam = g.lam_l[t.row0 + r];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int c = tx + 16 * b;
+          if (c >= t.ncol) continue;
+          const size_t idx = (size_t)s.off + (size_t)(t.orow[i] + r) * s.c + (t.ocol[i] + c);
+          const double2 v = out[i][a][b];
+          th_raw[idx] = v;
+          th_scaled[idx] = make_double2(lam * v.x, lam * v.y);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi on the rows of Theta(m).  One workgroup per sector; each
+// wavefront takes whole row pairs of the current round-robin step (circle
+// method: n' - 1 steps of n'/2 disjoint pairs cover all pairs once), loads
+// both rows into registers (E complex per lane per row), forms
+// alpha = |x|^2, beta = |y|^2, gamma = <x, y> with wave reductions, and
+// rotates when |gamma| > tol sqrt(alpha beta):
+//   zeta = (beta - alpha) / (2|gamma|), t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+//   c = 1/sqrt(1 + t^2), s = c t, e = gamma/|gamma|,
+//   x' = c x - s e y,  y' = s conj(e) x + c y   (makes <x', y'> = 0).
+// E == 0 selects the streaming form for rows longer than 64 * 32.
+__device__ __forceinline__ void rr_pair(int step, int k, int np, int& i, int& j) {
+  const int q = np - 1;
+  if (k == 0) {
+    i = step % q;
+    j = q;
+  } else {
+    i = (step + k) % q;
+    j = (step - k + q) % q;
+  }
+}
+
+template <int E, int NT>
+__global__ void __launch_bounds__(NT)
+jacobi_rows(const SectorWork* __restrict__ secs, const int* __restrict__ list,
+            double2* __restrict__ theta, double* __restrict__ sigma, int* __restrict__ order,
+            JacobiOut* __restrict__ stats, int max_sweeps, double tol_opt) {
+  extern __shared__ double jsm[];          // n doubles: row norms
+  __shared__ int rotated;
+  __shared__ int rot_total;
+  const int sid = list[blockIdx.x];
+  const SectorWork sw = secs[sid];
+  const int n = sw.r, len = sw.c;
+  double2* x = theta + sw.off;
+  const double tol = tol_opt > 0.0 ? tol_opt : sqrt((double)len) * DBL_EPSILON;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int np = n + (n & 1);
+  if (threadIdx.x == 0) rot_total = 0;
+
+  int sweeps = 0;
+  bool converged = (n < 2);
+  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+    __syncthreads();
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    int my_rot = 0;
+    for (int step = 0; step < np - 1; ++step) {
+      for (int k = wave; k < np / 2; k += nwaves) {
+        int i, j;
+        rr_pair(step, k, np, i, j);
+        if (i >= n || j >= n) continue;
+        double2* xi = x + (size_t)i * len;
+        double2* xj = x + (size_t)j * len;
+        double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+        if constexpr (E > 0) {
+          double2 vx[E], vy[E];
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int col = lane + 64 * e;
+            vx[e] = col < len ? xi[col] : make_double2(0.0, 0.0);
+            vy[e] = col < len ? xj[col] : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            al = fma(vx[e].x, vx[e].x, fma(vx[e].y, vx[e].y, al));
+            be = fma(vy[e].x, vy[e].x, fma(vy[e].y, vy[e].y, be));
+            gr = fma(vx[e].x, vy[e].x, fma(vx[e].y, vy[e].y, gr));
+            gi = fma(vx[e].y, vy[e].x, fma(-vx[e].x, vy[e].y, gi));
+          }
+          al = wave_sum(al); be = wave_sum(be); gr = wave_sum(gr); gi = wave_sum(gi);
+          const double ag = sqrt(gr * gr + gi * gi);
+          if (ag > tol * sqrt(al) * sqrt(be)) {
+            const double zeta = (be - al) / (2.0 * ag);
+            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + tt * tt);
+            const double s = c * tt;
+            const double er = gr / ag, ei = gi / ag;
+            const double wr = s * er, wi = s * ei;      // s e
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+              const int col = lane + 64 * e;
+              if (col < len) {
+                const double2 a = vx[e], b = vy[e];
+                // x' = c a - (s e) b ; y' = conj(s e) a + c b
+                double2 xa, yb;
+                xa.x = c * a.x - (wr * b.x - wi * b.y);
+                xa.y = c * a.y - (wr * b.y + wi * b.x);
+                yb.x = (wr * a.x + wi * a.y) + c * b.x;
+                yb.y = (wr * a.y - wi * a.x) + c * b.y;
+                xi[col] = xa;
+                xj[col] = yb;
+              }
+            }
+            ++my_rot;
+          }
+        } else {
+          for (int col = lane; col < len; col += 64) {
+            const double2 a = xi[col], b = xj[col];
+            al = fma(a.x, a.x, fma(a.y, a.y, al));
+            be = fma(b.x, b.x, fma(b.y, b.y, be));
+            gr = fma(a.x, b.x, fma(a.y, b.y, gr));
+            gi = fma(a.y, b.x, fma(-a.x, b.y, gi));
+          }
+          al = wave_sum(al); be = wave_sum(be); gr = wave_sum(gr); gi = wave_sum(gi);
+          const double ag = sqrt(gr * gr + gi * gi);
+          if (ag > tol * sqrt(al) * sqrt(be)) {
+            const double zeta = (be - al) / (2.0 * ag);
+            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            const double c = 1.0 / sqrt(1.0 + tt * tt);
+            const double s = c * tt;
+            const double wr = s * gr / ag, wi = s * gi / ag;
+            for (int col = lane; col < len; col += 64) {
+              const double2 a = xi[col], b = xj[col];
+              double2 xa, yb;
+              xa.x = c * a.x - (wr * b.x - wi * b.y);
+              xa.y = c * a.y - (wr * b.y + wi * b.x);
+              yb.x = (wr * a.x + wi * a.y) + c * b.x;
+              yb.y = (wr * a.y - wi * a.x) + c * b.y;
+              xi[col] = xa;
+              xj[col] = yb;
+            }
+            ++my_rot;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if (lane == 0 && my_rot) {
+      atomicAdd(&rotated, 1);
+      atomicAdd(&rot_total, my_rot);
+    }
+    __syncthreads();
+    ++sweeps;
+    converged = (rotated == 0);
+  }
+  __syncthreads();
+  // row norms -> singular values; normalise rows (V^dagger rows)
+  for (int i = wave; i < n; i += nwaves) {
+    double2* xi = x + (size_t)i * len;
+    double ss = 0.0;
+    for (int col = lane; col < len; col += 64) {
+      const double2 a = xi[col];
+      ss = fma(a.x, a.x, fma(a.y, a.y, ss));
+    }
+    ss = wave_sum(ss);
+    const double nr = sqrt(ss);
+    if (nr > 0.0) {
+      const double inv = 1.0 / nr;
+      for (int col = lane; col < len; col += 64) {
+        const double2 a = xi[col];
+        xi[col] = make_double2(a.x * inv, a.y * inv);
+      }
+    }
+    if (lane == 0) jsm[i] = nr;
+  }
+  __syncthreads();
+  // order rows by descending value (ties: lower row first)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = jsm[i];
+    int rank = 0;
+    for (int k = 0; k < n; ++k) {
+      const double w = jsm[k];
+      rank += (w > v) || (w == v && k < i);
+    }
+    sigma[sw.sig + rank] = v;
+    order[sw.sig + rank] = i;
+  }
+  if (threadIdx.x == 0) {
+    JacobiOut o;
+    o.sweeps = sweeps;
+    o.rotations = rot_total;
+    o.converged = converged ? 1 : 0;
+    o.pad = 0;
+    stats[sid] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cut over all sectors of one gate.  One workgroup per gate.  Entries are
+// (value, key) with key = local sector << 20 | rank; they are sorted by value
+// descending, then key ascending (bitonic network), and the kept count is
+//   K = max(1, min(K_eps, K_zero, chi_max, keep_cap, T)).
+__device__ __forceinline__ bool sel_before(double va, int ka, double vb, int kb) {
+  return va > vb || (va == vb && ka < kb);
+}
+
+__global__ void __launch_bounds__(1024)
+select_kernel(const GateWork* __restrict__ gates, const SectorWork* __restrict__ secs,
+              const double* __restrict__ sigma, double* __restrict__ gsv, int* __restrict__ gsk,
+              const long long* __restrict__ scratch_off, int* __restrict__ kept,
+              CutOut* __restrict__ cut, int lds_cap) {
+  extern __shared__ double ssm[];
+  __shared__ int cnt[1024];
+  __shared__ double chunk[1024];
+  __shared__ int kmin, kzero, nf_flag;
+  __shared__ double disc_sh;
+  __shared__ int total_sh;
+  const int gi = blockIdx.x;
+  const GateWork g = gates[gi];
+  const int nsec = g.sec_end - g.sec_begin;
+  const int tid = threadIdx.x, nt = blockDim.x;
+
+  // total number of candidate values
+  if (tid == 0) {
+    int t = 0;
+    for (int s = g.sec_begin; s < g.sec_end; ++s) t += secs[s].kmax;
+    total_sh = t;
+  }
+  for (int s = tid; s < nsec && s < 1024; s += nt) cnt[s] = 0;
+  __syncthreads();
+  const int T = total_sh;
+  int P = 1;
+  while (P < T) P <<= 1;
+  double* sv;
+  int* sk;
+  if (P <= lds_cap) {
+    sv = ssm;
+    sk = reinterpret_cast<int*>(ssm + P);
+  } else {
+    sv = gsv + scratch_off[gi];
+    sk = gsk + scratch_off[gi];
+  }
+  // gather
+  for (int i = tid; i < P; i += nt) {
+    sv[i] = -1.0;
+    sk[i] = 0x7fffffff;
+  }
+  __syncthreads();
+  {
+    // each sector's first kmax values, sector by sector
+    int base = 0;
+    for (int s = g.sec_begin; s < g.sec_end; ++s) {
+      const SectorWork w = secs[s];
+      for (int j = tid; j < w.kmax; j += nt) {
+        sv[base + j] = sigma[w.sig + j];
+        sk[base + j] = ((s - g.sec_begin) << 20) | j;
+      }
+      base += w.kmax;
+    }
+  }
+  __syncthreads();
+  // bitonic sort, best first
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < P; i += nt) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const double va = sv[i], vb = sv[ixj];
+          const int ka = sk[i], kb = sk[ixj];
+          const bool up = (i & k) == 0;
+          const bool sw = up ? sel_before(vb, kb, va, ka) : sel_before(va, ka, vb, kb);
+          if (sw) {
+            sv[i] = vb; sv[ixj] = va;
+            sk[i] = kb; sk[ixj] = ka;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const double s0 = sv[0];
+  bool bad = !(s0 > 0.0) || !isfinite(s0);
+  // chunked sums of squares over the T valid entries, in sorted order
+  const int C = (T + nt - 1) / nt;
+  const int cb = tid * C, ce = min(T, cb + C);
+  double part = 0.0;
+  int nonfinite = 0;
+  for (int i = cb; i < ce; ++i) {
+    const double v = sv[i];
+    if (!isfinite(v)) nonfinite = 1;
+    part = fma(v, v, part);
+  }
+  chunk[tid] = part;
+  if (tid == 0) { kmin = T; kzero = 0; nf_flag = 0; disc_sh = 0.0; }
+  __syncthreads();
+  if (nonfinite) atomicOr(&nf_flag, 1);
+  __syncthreads();
+  if (nf_flag) bad = true;
+  if (tid == 0) {
+    // suffix sums of the chunk sums, fixed order
+    double run = 0.0;
+    for (int t = nt - 1; t >= 0; --t) {
+      const double v = chunk[t];
+      chunk[t] = run;          // sum of chunks after t
+      run += v;
+    }
+    disc_sh = run;             // temporarily: total weight W
+  }
+  __syncthreads();
+  const double W = disc_sh;
+  const double thr = g.cutoff * W;
+  const double zthr = g.zero_tol * s0;
+  int my_kmin = T, my_kz = 0;
+  {
+    double run = chunk[tid];
+    for (int i = ce - 1; i >= cb; --i) {
+      run = fma(sv[i], sv[i], run);
+      if (run <= thr) my_kmin = i;
+      if (sv[i] > zthr) ++my_kz;
+    }
+  }
+  atomicMin(&kmin, my_kmin);
+  atomicAdd(&kzero, my_kz);
+  __syncthreads();
+  int K = min(kmin, kzero);
+  if (g.chi_max > 0) K = min(K, g.chi_max);
+  K = min(K, g.keep_cap);
+  K = min(K, T);
+  K = max(K, 1);
+  // tail weight at K
+  if (K < T && K >= cb && K < ce) {
+    double run = chunk[tid];
+    for (int i = ce - 1; i >= K; --i) run = fma(sv[i], sv[i], run);
+    disc_sh = run;
+  }
+  __syncthreads();
+  if (K >= T && tid == 0) disc_sh = 0.0;
+  for (int i = tid; i < K; i += nt) atomicAdd(&cnt[sk[i] >> 20], 1);
+  __syncthreads();
+  for (int s = tid; s < nsec; s += nt) kept[g.sec_begin + s] = cnt[s];
+  if (tid == 0) {
+    CutOut o;
+    o.kept = K;
+    o.flags = bad ? 1 : 0;
+    o.discarded = disc_sh;
+    o.total = W;
+    o.margin = K < T ? (sv[K - 1] - sv[K]) / s0 : INFINITY;
+    cut[gi] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Update of B[s+1] and lambda[s+1]: one workgroup per new row.
+__global__ void __launch_bounds__(256)
+update_rows_kernel(const RowWork* __restrict__ rows, const SectorWork* __restrict__ secs,
+                   const UpdateWork* __restrict__ upd, const double2* __restrict__ vh,
+                   const double* __restrict__ sigma, const int* __restrict__ order) {
+  const RowWork rw = rows[blockIdx.x];
+  const SectorWork s = secs[rw.sector];
+  const UpdateWork u = upd[rw.gate];
+  const int src = order[s.sig + rw.j];
+  const double2* xr = vh + s.off + (size_t)src * s.c;
+  double2* dst = u.br_new + (size_t)rw.row * u.ldr;
+  for (int col = threadIdx.x; col < u.ldr; col += blockDim.x) {
+    const int cc = col - s.clo;
+    dst[col] = (cc >= 0 && cc < s.c) ? xr[cc] : make_double2(0.0, 0.0);
+  }
+  if (threadIdx.x == 0) u.lam_new[rw.row] = sigma[s.sig + rw.j];
+}
+
+// Fill a list of device ranges with zeros (grid-stride per range).
+__global__ void __launch_bounds__(256)
+zero_fill_kernel(double2* const* __restrict__ ptrs, const long long* __restrict__ counts, int nranges) {
+  for (int r = 0; r < nranges; ++r) {
+    double2* p = ptrs[r];
+    const long long n = counts[r];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+      p[i] = make_double2(0.0, 0.0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Generic batched complex GEMM, 32 x 32 tiles, k-chunks of 16 through LDS.
+__global__ void __launch_bounds__(256)
+zgemm_kernel(const GemmWork* __restrict__ probs, int nprob) {
+  __shared__ double2 as[kGemmTile][17];
+  __shared__ double2 bs[16][kGemmTile + 1];
+  // locate the problem of this tile
+  int lo = 0, hi = nprob - 1;
+  const int tile = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  const GemmWork w = probs[lo];
+  const int local = tile - w.tile_begin;
+  const int tm = local / w.tiles_n, tn = local % w.tiles_n;
+  const int row0 = tm * kGemmTile, col0 = tn * kGemmTile;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double2 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < w.k; k0 += 16) {
+    for (int e = threadIdx.x; e < kGemmTile * 16; e += 256) {
+      const int r = e >> 4, kk = e & 15;
+      const int i = row0 + r, k = k0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (i < w.m && k < w.k)
+        v = w.opa ? cconj(w.a[(size_t)k * w.lda + i]) : w.a[(size_t)i * w.lda + k];
+      as[r][kk] = v;
+    }
+    for (int e = threadIdx.x; e < 16 * kGemmTile; e += 256) {
+      const int kk = e >> 5, c = e & 31;
+      const int j = col0 + c, k = k0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (j < w.n && k < w.k)
+        v = w.opb ? cconj(w.b[(size_t)j * w.ldb + k]) : w.b[(size_t)k * w.ldb + j];
+      bs[kk][c] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 16; ++kk) {
+      const double2 a0 = as[ty][kk], a1 = as[ty + 16][kk];
+      const double2 b0 = bs[kk][tx], b1 = bs[kk][tx + 16];
+      cfma(acc[0][0], a0, b0);
+      cfma(acc[0][1], a0, b1);
+      cfma(acc[1][0], a1, b0);
+      cfma(acc[1][1], a1, b1);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int i = row0 + ty + 16 * a;
+    if (i >= w.m) continue;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int j = col0 + tx + 16 * b;
+      if (j >= w.n) continue;
+      double2* cp = w.c + (size_t)i * w.ldc + j;
+      double2 v = acc[a][b];
+      if (w.beta_one) {
+        const double2 o = *cp;
+        v.x += o.x;
+        v.y += o.y;
+      }
+      *cp = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Amplitudes: one workgroup per pattern.  The charge path c_{s+1} = c_s - occ_s
+// selects one block of every site tensor (Eq. (E2)); the amplitude is the
+// product of those blocks.  Any missing charge gives exactly zero.
+__global__ void __launch_bounds__(256)
+amplitude_kernel(const double2* const* __restrict__ sites, const int* __restrict__ ld,
+                 const int2* __restrict__ bondmap, const int* __restrict__ occ,
+                 double2* __restrict__ out, int L, int d, int N, int maxdim) {
+  extern __shared__ double2 vsm[];
+  double2* v0 = vsm;
+  double2* v1 = vsm + maxdim;
+  __shared__ int ok;
+  const int pat = blockIdx.x;
+  const int* o = occ + (size_t)pat * L;
+  if (threadIdx.x == 0) {
+    int c = N, good = 1;
+    for (int s = 0; s < L; ++s) {
+      const int x = o[s];
+      if (x < 0 || x >= d) { good = 0; break; }
+      c -= x;
+      if (c < 0) { good = 0; break; }
+      if (bondmap[(size_t)(s + 1) * (N + 1) + c].y == 0) { good = 0; break; }
+    }
+    if (c != 0) good = 0;
+    ok = good;
+  }
+  if (threadIdx.x == 0) v0[0] = make_double2(1.0, 0.0);
+  __syncthreads();
+  if (!ok) {
+    if (threadIdx.x == 0) out[pat] = make_double2(0.0, 0.0);
+    return;
+  }
+  int c = N;
+  int n0 = 1, off0 = bondmap[c].x;   // bond 0 holds only charge N
+  for (int s = 0; s < L; ++s) {
+    const int c1 = c - o[s];
+    const int2 b1 = bondmap[(size_t)(s + 1) * (N + 1) + c1];
+    const double2* B = sites[s];
+    const int lds = ld[s];
+    for (int j = threadIdx.x; j < b1.y; j += blockDim.x) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int i = 0; i < n0; ++i) cfma(acc, v0[i], B[(size_t)(off0 + i) * lds + b1.x + j]);
+      v1[j] = acc;
+    }
+    __syncthreads();
+    double2* tmp = v0; v0 = v1; v1 = tmp;
+    n0 = b1.y;
+    off0 = b1.x;
+    c = c1;
+  }
+  if (threadIdx.x == 0) out[pat] = v0[0];
+}
+
+// Gather kernels for re-truncation: dst[r][j] = src[r][map[j]] / src[map[r]][j].
+__global__ void __launch_bounds__(256)
+gather_cols_kernel(const double2* __restrict__ src, int lds, double2* __restrict__ dst, int ldd,
+                   int rows, const int* __restrict__ map, int ncols) {
+  const long long total = (long long)rows * ncols;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e / ncols), j = (int)(e % ncols);
+    dst[(size_t)r * ldd + j] = src[(size_t)r * lds + map[j]];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+gather_rows_kernel(const double2* __restrict__ src, int lds, double2* __restrict__ dst, int ldd,
+                   const int* __restrict__ map, int nrows, int cols) {
+  const long long total = (long long)nrows * cols;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int r = (int)(e / cols), j = (int)(e % cols);
+    dst[(size_t)r * ldd + j] = src[(size_t)map[r] * lds + j];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+gather_vec_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                  const int* __restrict__ map, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[map[i]];
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+
+hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntiles,
+                        const SectorWork* secs, const double2* coef, double2* raw,
+                        double2* scaled, int maxw, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (maxw <= 4)
+    hipLaunchKernelGGL(theta_kernel<4>, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, raw, scaled);
+  else
+    hipLaunchKernelGGL(theta_kernel<kMaxD>, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, raw, scaled);
+  return hipGetLastError();
+}
+
+int jacobi_class(int len) {
+  if (len <= 64) return 1;
+  if (len <= 128) return 2;
+  if (len <= 256) return 4;
+  if (len <= 512) return 8;
+  if (len <= 1024) return 16;
+  if (len <= 2048) return 32;
+  return 0;
+}
+
+hipError_t launch_jacobi(int ecls, const SectorWork* secs, const int* list, int count, int maxrows,
+                         double2* theta, double* sigma, int* order, JacobiOut* stats,
+                         int max_sweeps, double tol, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const size_t smem = (size_t)maxrows * sizeof(double);
+#define U1MPS_JAC(EE, NN)                                                                   \
+  hipLaunchKernelGGL((jacobi_rows<EE, NN>), dim3(count), dim3(NN), smem, st, secs, list, theta, \
+                     sigma, order, stats, max_sweeps, tol)
+  // threads per workgroup shrink as the rows held in registers grow
+  switch (ecls) {
+    case 1: U1MPS_JAC(1, 1024); break;
+    case 2: U1MPS_JAC(2, 1024); break;
+    case 4: U1MPS_JAC(4, 1024); break;
+    case 8: U1MPS_JAC(8, 1024); break;
+    case 16: U1MPS_JAC(16, 512); break;
+    case 32: U1MPS_JAC(32, 256); break;
+    default: U1MPS_JAC(0, 512); break;
+  }
+#undef U1MPS_JAC
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const GateWork* gates, int ngates, const SectorWork* secs,
+                         const double* sigma, double* gsv, int* gsk, const long long* scratch_off,
+                         int* kept, CutOut* cut, int maxP, hipStream_t st) {
+  if (ngates <= 0) return hipSuccess;
+  // LDS holds P doubles + P ints when P <= 4096 (48 KiB); larger goes to global scratch
+  const int lds_cap = 4096;
+  const int P = maxP <= lds_cap ? maxP : 0;
+  const size_t smem = (size_t)P * (sizeof(double) + sizeof(int));
+  hipLaunchKernelGGL(select_kernel, dim3(ngates), dim3(1024), smem, st, gates, secs, sigma, gsv,
+                     gsk, scratch_off, kept, cut, P > 0 ? lds_cap : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_rows(const RowWork* rows, int nrows, const SectorWork* secs,
+                              const UpdateWork* upd, const double2* vh, const double* sigma,
+                              const int* order, hipStream_t st) {
+  if (nrows <= 0) return hipSuccess;
+  hipLaunchKernelGGL(update_rows_kernel, dim3(nrows), dim3(256), 0, st, rows, secs, upd, vh, sigma, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_fill(double2* const* ptrs, const long long* counts, int nranges,
+                            long long maxcount, hipStream_t st) {
+  if (nranges <= 0 || maxcount <= 0) return hipSuccess;
+  long long blocks = (maxcount + 255) / 256;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(zero_fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, ptrs, counts, nranges);
+  return hipGetLastError();
+}
+
+hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_t st) {
+  if (nprob <= 0 || ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zgemm_kernel, dim3(ntiles), dim3(256), 0, st, probs, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_amplitude(const double2* const* sites, const int* ld, const int2* bondmap,
+                            const int* occ, double2* out, int count, int L, int d, int N,
+                            int maxdim, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  const size_t smem = (size_t)2 * maxdim * sizeof(double2);
+  hipLaunchKernelGGL(amplitude_kernel, dim3(count), dim3(256), smem, st, sites, ld, bondmap, occ, out, L, d, N, maxdim);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_cols(const double2* src, int lds, double2* dst, int ldd, int rows,
+                              const int* map, int ncols, hipStream_t st) {
+  const long long total = (long long)rows * ncols;
+  if (total <= 0) return hipSuccess;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(gather_cols_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, lds, dst, ldd, rows, map, ncols);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const double2* src, int lds, double2* dst, int ldd, const int* map,
+                              int nrows, int cols, hipStream_t st) {
+  const long long total = (long long)nrows * cols;
+  if (total <= 0) return hipSuccess;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, lds, dst, ldd, map, nrows, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_vec(const double* src, double* dst, const int* map, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_vec_kernel, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, map, n);
+  return hipGetLastError();
+}
+
+}  // namespace u1mps

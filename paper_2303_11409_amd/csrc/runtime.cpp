@@ -1,0 +1,1218 @@
+// Host runtime of the U(1)-symmetric MPS engine: the C ABI of u1mps.h.
+//
+// Per batch of gates (one brickwork layer, or a single gate) the runtime
+//   1. enumerates the charge sectors on the host (integer bookkeeping:
+//      middle charges m, Theta(m) shapes, (cL, cR) tiles with their cM
+//      windows -- the "loop over allowed charge values" of Sec. II),
+//   2. builds the gate blocks G^(n) from the 2x2 mode unitary,
+//   3. uploads one packed work list and launches theta, Jacobi and select
+//      kernels for all gates together,
+//   4. reads back the kept count of every sector (the only host sync of the
+//      batch), rebuilds the middle bonds' charge tables and launches the
+//      update kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/u1mps.h"
+#include "internal.h"
+#include "kernels.h"
+
+using namespace u1mps;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+mps_status fail(mps_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(MPS_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define STCHK(expr)                  \
+  do {                               \
+    mps_status s_ = (expr);          \
+    if (s_ != MPS_OK) return s_;     \
+  } while (0)
+
+struct Bond {
+  std::vector<int> charge;   // ascending
+  std::vector<int> count;
+  std::vector<int> off;      // prefix sums, size charge.size() + 1
+  int dim() const { return off.empty() ? 0 : off.back(); }
+  int find(int c) const {
+    auto it = std::lower_bound(charge.begin(), charge.end(), c);
+    return (it != charge.end() && *it == c) ? int(it - charge.begin()) : -1;
+  }
+  int lower(int c) const { return int(std::lower_bound(charge.begin(), charge.end(), c) - charge.begin()); }
+  void finish() {
+    off.assign(charge.size() + 1, 0);
+    for (size_t i = 0; i < charge.size(); ++i) off[i + 1] = off[i] + count[i];
+  }
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+struct PinBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
+enum Kind { K_THETA = 0, K_SELECT, K_UPDATE, K_JACOBI0 };   // K_JACOBI0 + class index
+
+// Index of a Jacobi row-length class (E complex per lane) in the stats arrays.
+int class_index(int e) {
+  switch (e) {
+    case 1: return 1;
+    case 2: return 2;
+    case 4: return 3;
+    case 8: return 4;
+    case 16: return 5;
+    case 32: return 6;
+    default: return 0;
+  }
+}
+
+struct Pending {
+  int kind;
+  hipEvent_t a, b;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct mps_state {
+  int L = 0, d = 0, N = 0;
+  mps_opts opts{};
+  mps_device dev{};
+  hipStream_t st = nullptr;
+  std::vector<Bond> bonds;       // L + 1
+  std::vector<int> cap;          // per bond: largest admissible dimension
+  std::vector<double*> lam;      // per bond, cap[b] doubles
+  std::vector<double2*> site;    // per site, cap[s] * cap[s+1] complex
+  // workspaces (grow-only)
+  DevBuf th_raw, th_scaled, sigma, order, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc;
+  PinBuf stage_plan, stage_upd, stage_res, stage_misc;
+  mps_stats stats{};
+  bool timing = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+void* dalloc(mps_state* h, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (h->dev.alloc) return h->dev.alloc(bytes, h->dev.ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dfree(mps_state* h, void* p) {
+  if (!p) return;
+  if (h->dev.release) h->dev.release(p, h->dev.ctx);
+  else (void)hipFree(p);
+}
+
+mps_status ensure(mps_state* h, DevBuf& b, size_t bytes) {
+  if (b.cap >= bytes) return MPS_OK;
+  size_t nb = std::max(bytes, b.cap + b.cap / 2);
+  nb = align256(nb);
+  if (b.p) {
+    HIPCHK(hipStreamSynchronize(h->st));
+    dfree(h, b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  void* p = dalloc(h, nb);
+  if (!p) return fail(MPS_E_NOMEM, "device allocation of %zu bytes failed", nb);
+  b.p = p;
+  b.cap = nb;
+  return MPS_OK;
+}
+
+mps_status ensure_pin(PinBuf& b, size_t bytes) {
+  if (b.cap >= bytes) return MPS_OK;
+  size_t nb = align256(std::max(bytes, b.cap + b.cap / 2));
+  if (b.p) {
+    (void)hipHostFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, nb, hipHostMallocDefault) != hipSuccess || !p)
+    return fail(MPS_E_NOMEM, "pinned host allocation of %zu bytes failed", nb);
+  b.p = p;
+  b.cap = nb;
+  return MPS_OK;
+}
+
+// Packs several host arrays into one pinned block; offsets are 256-aligned.
+struct Packer {
+  struct Item {
+    const void* src;
+    size_t bytes;
+    size_t off;
+  };
+  std::vector<Item> items;
+  size_t total = 0;
+  size_t add(const void* src, size_t bytes) {
+    const size_t off = total;
+    items.push_back({src, bytes, off});
+    total = align256(total + std::max<size_t>(bytes, 1));
+    return off;
+  }
+  void write(void* dst) const {
+    for (const Item& it : items)
+      if (it.bytes) std::memcpy(static_cast<char*>(dst) + it.off, it.src, it.bytes);
+  }
+};
+
+template <class T>
+T* at(const DevBuf& b, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(b.p) + off);
+}
+
+// ---- timing ----------------------------------------------------------------
+mps_status ev_get(mps_state* h, hipEvent_t* e) {
+  if (!h->pool.empty()) {
+    *e = h->pool.back();
+    h->pool.pop_back();
+    return MPS_OK;
+  }
+  HIPCHK(hipEventCreate(e));
+  return MPS_OK;
+}
+
+struct Timer {
+  mps_state* h;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  bool on = false;
+  Timer(mps_state* hh, int k) : h(hh), kind(k) {}
+  mps_status start() {
+    if (!h->timing) return MPS_OK;
+    STCHK(ev_get(h, &a));
+    STCHK(ev_get(h, &b));
+    HIPCHK(hipEventRecord(a, h->st));
+    on = true;
+    return MPS_OK;
+  }
+  mps_status stop() {
+    if (!on) return MPS_OK;
+    HIPCHK(hipEventRecord(b, h->st));
+    h->pending.push_back({kind, a, b});
+    on = false;
+    return MPS_OK;
+  }
+};
+
+// Called after a stream synchronisation: fold finished event pairs into stats.
+mps_status drain_events(mps_state* h) {
+  for (const Pending& p : h->pending) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
+    if (p.kind >= K_JACOBI0) {
+      h->stats.jacobi_ms += ms;
+      h->stats.jacobi_class_ms[p.kind - K_JACOBI0] += ms;
+    } else if (p.kind == K_THETA) {
+      h->stats.theta_ms += ms;
+    } else if (p.kind == K_SELECT) {
+      h->stats.select_ms += ms;
+    } else {
+      h->stats.update_ms += ms;
+    }
+    h->pool.push_back(p.a);
+    h->pool.push_back(p.b);
+  }
+  h->pending.clear();
+  return MPS_OK;
+}
+
+// ---- gate blocks -----------------------------------------------------------
+// G^(n)[p][a] = <p, n-p| G |a, n-a>.  The input state |a, b> is
+// (a0^+)^a (a1^+)^b / sqrt(a! b!) |0>; substituting a0^+ -> u00 X + u10 Y and
+// a1^+ -> u01 X + u11 Y and expanding the product as a polynomial in X (the
+// power of Y is fixed by the degree), the coefficient of X^p Y^(n-p) times
+// sqrt(p! (n-p)!) is the element.  Occupations >= d are dropped (cutoff).
+void gate_blocks(const mps_z u[4], int d, double2* out) {
+  using C = std::complex<double>;
+  const C u00(u[0].re, u[0].im), u01(u[1].re, u[1].im), u10(u[2].re, u[2].im), u11(u[3].re, u[3].im);
+  double fact[2 * kMaxD + 2];
+  fact[0] = 1.0;
+  for (int i = 1; i < 2 * kMaxD + 2; ++i) fact[i] = fact[i - 1] * i;
+  const int nb = 2 * d - 1;
+  for (int i = 0; i < nb * d * d; ++i) out[i] = make_double2(0.0, 0.0);
+  for (int n = 0; n < nb; ++n) {
+    for (int a = std::max(0, n - d + 1); a <= std::min(d - 1, n); ++a) {
+      const int b = n - a;
+      std::vector<C> poly(1, C(1.0, 0.0));
+      auto mulf = [&](C cx, C cy) {       // poly *= (cx X + cy Y)
+        std::vector<C> nx(poly.size() + 1, C(0.0, 0.0));
+        for (size_t k = 0; k < poly.size(); ++k) {
+          nx[k] += cy * poly[k];
+          nx[k + 1] += cx * poly[k];
+        }
+        poly.swap(nx);
+      };
+      for (int i = 0; i < a; ++i) mulf(u00, u10);
+      for (int i = 0; i < b; ++i) mulf(u01, u11);
+      for (int p = std::max(0, n - d + 1); p <= std::min(d - 1, n); ++p) {
+        const C v = poly[p] * std::sqrt(fact[p] * fact[n - p] / (fact[a] * fact[b]));
+        out[(n * d + p) * d + a] = make_double2(v.real(), v.imag());
+      }
+    }
+  }
+}
+
+// ---- capacities ------------------------------------------------------------
+// Largest Schmidt rank a bond can reach: sum over charges c of
+// min(#left strings with N-c photons, #right strings with c photons),
+// strings over the sites of each side with occupations < d.
+std::vector<double> strings_count(int sites, int d, int N) {
+  std::vector<double> cnt(N + 1, 0.0), nx(N + 1);
+  cnt[0] = 1.0;
+  for (int s = 0; s < sites; ++s) {
+    std::fill(nx.begin(), nx.end(), 0.0);
+    for (int n = 0; n <= N; ++n)
+      for (int a = 0; a < d && a <= n; ++a) nx[n] += cnt[n - a];
+    cnt.swap(nx);
+  }
+  return cnt;
+}
+
+mps_status compute_caps(mps_state* h) {
+  h->cap.assign(h->L + 1, 1);
+  for (int b = 0; b <= h->L; ++b) {
+    const std::vector<double> left = strings_count(b, h->d, h->N);
+    const std::vector<double> right = strings_count(h->L - b, h->d, h->N);
+    double tot = 0.0;
+    for (int c = 0; c <= h->N; ++c) tot += std::min(left[h->N - c], right[c]);
+    if (h->opts.chi_max > 0) tot = std::min(tot, double(h->opts.chi_max));
+    tot = std::max(tot, double(h->bonds[b].dim()));
+    if (tot > 65536.0)
+      return fail(MPS_E_ARG, "bond %d could reach dimension %.3g; set chi_max", b, tot);
+    h->cap[b] = std::max(1, int(tot));
+  }
+  return MPS_OK;
+}
+
+// ---- batch plan ------------------------------------------------------------
+struct GatePlan {
+  int site;
+  int sec_begin, sec_end;
+};
+
+struct BatchPlan {
+  std::vector<GateWork> gates;
+  std::vector<SectorWork> secs;
+  std::vector<ThetaTile> tiles;
+  std::vector<double2> coef;
+  std::vector<GatePlan> gp;
+  std::vector<int> jlist;                 // sector ids grouped by Jacobi class
+  std::vector<int> jclass_begin, jclass_count, jclass_maxrows, jclass_e;
+  std::vector<long long> sel_off;         // global sort scratch offsets
+  long long sel_scratch = 0;
+  int maxP = 1;
+  long long th_elems = 0;
+  int sig_elems = 0;
+  int maxw = 1;
+  double theta_flops = 0.0;
+};
+
+mps_status plan_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s, BatchPlan& P) {
+  const int d = h->d;
+  P.gates.resize(ng);
+  P.gp.resize(ng);
+  P.coef.assign((size_t)ng * (2 * d - 1) * d * d, make_double2(0.0, 0.0));
+  for (int g = 0; g < ng; ++g) {
+    const int s = sites[g];
+    const Bond& BL = h->bonds[s];
+    const Bond& BM = h->bonds[s + 1];
+    const Bond& BR = h->bonds[s + 2];
+    gate_blocks(u2s + 4 * g, d, P.coef.data() + (size_t)g * (2 * d - 1) * d * d);
+    GateWork gw{};
+    gw.bl = h->site[s];
+    gw.br = h->site[s + 1];
+    gw.lam_l = h->lam[s];
+    gw.ldl = BM.dim();
+    gw.ldr = BR.dim();
+    gw.coef = g * (2 * d - 1) * d * d;
+    gw.d = d;
+    gw.sec_begin = (int)P.secs.size();
+    gw.keep_cap = h->cap[s + 1];
+    gw.chi_max = h->opts.chi_max;
+    gw.cutoff = h->opts.cutoff;
+    gw.zero_tol = h->opts.zero_tol;
+    // sectors: every middle charge m with rows (cL in [m, m+d-1]) and
+    // columns (cR in [m-d+1, m]) present
+    const int mlo = std::max(BL.charge.front() - (d - 1), BR.charge.front());
+    const int mhi = std::min(BL.charge.back(), BR.charge.back() + (d - 1));
+    std::vector<int> secmap(std::max(0, mhi - mlo + 1), -1);
+    int T = 0;
+    for (int m = mlo; m <= mhi; ++m) {
+      const int i0 = BL.lower(m), i1 = BL.lower(m + d);
+      const int j0 = BR.lower(m - d + 1), j1 = BR.lower(m + 1);
+      const int r = BL.off[i1] - BL.off[i0];
+      const int c = BR.off[j1] - BR.off[j0];
+      if (r <= 0 || c <= 0) continue;
+      SectorWork sw{};
+      sw.gate = g;
+      sw.m = m;
+      sw.r = r;
+      sw.c = c;
+      sw.rlo = BL.off[i0];
+      sw.clo = BR.off[j0];
+      sw.off = P.th_elems;
+      sw.sig = P.sig_elems;
+      sw.kmax = std::min(r, c);
+      secmap[m - mlo] = (int)P.secs.size();
+      P.secs.push_back(sw);
+      P.th_elems += (long long)r * c;
+      P.sig_elems += r;
+      T += sw.kmax;
+    }
+    gw.sec_end = (int)P.secs.size();
+    if (gw.sec_end == gw.sec_begin) return fail(MPS_E_CHARGE, "gate at site %d has no charge sector", s);
+    if (gw.sec_end - gw.sec_begin > 1024) return fail(MPS_E_ARG, "more than 1024 sectors in one update");
+    int Pp = 1;
+    while (Pp < T) Pp <<= 1;
+    P.maxP = std::max(P.maxP, Pp);
+    P.sel_off.push_back(P.sel_scratch);
+    P.sel_scratch += Pp;
+    // tiles
+    for (size_t a = 0; a < BL.charge.size(); ++a) {
+      const int cL = BL.charge[a];
+      for (size_t b = 0; b < BR.charge.size(); ++b) {
+        const int cR = BR.charge[b];
+        const int n = cL - cR;
+        if (n < 0 || n > 2 * d - 2) continue;
+        const int wlo = std::max(cR, cL - d + 1), whi = std::min(cL, cR + d - 1);
+        ThetaTile base{};
+        base.gate = g;
+        base.n = n;
+        for (int m = wlo; m <= whi; ++m) {
+          const int si = (m >= mlo && m <= mhi) ? secmap[m - mlo] : -1;
+          if (si < 0) return fail(MPS_E_CHARGE, "internal: sector %d missing at site %d", m, s);
+          const SectorWork& sw = P.secs[si];
+          base.sec[base.nout] = si;
+          base.p[base.nout] = cL - m;
+          base.orow[base.nout] = BL.off[a] - sw.rlo;
+          base.ocol[base.nout] = BR.off[b] - sw.clo;
+          ++base.nout;
+        }
+        int ksum = 0;
+        for (int cM = wlo; cM <= whi; ++cM) {
+          const int mi = BM.find(cM);
+          if (mi < 0) continue;
+          base.k0[base.nin] = BM.off[mi];
+          base.kn[base.nin] = BM.count[mi];
+          base.a[base.nin] = cL - cM;
+          ksum += BM.count[mi];
+          ++base.nin;
+        }
+        P.maxw = std::max(P.maxw, base.nout);
+        const int nL = BL.count[a], nR = BR.count[b];
+        P.theta_flops += 8.0 * nL * double(ksum) * nR;
+        for (int ti = 0; ti < nL; ti += kThetaTile) {
+          for (int tj = 0; tj < nR; tj += kThetaTile) {
+            ThetaTile t = base;
+            t.row0 = BL.off[a] + ti;
+            t.nrow = std::min(kThetaTile, nL - ti);
+            t.col0 = BR.off[b] + tj;
+            t.ncol = std::min(kThetaTile, nR - tj);
+            for (int i = 0; i < t.nout; ++i) {
+              t.orow[i] += ti;
+              t.ocol[i] += tj;
+            }
+            P.tiles.push_back(t);
+          }
+        }
+      }
+    }
+    P.gates[g] = gw;
+    P.gp[g] = {s, gw.sec_begin, gw.sec_end};
+  }
+  // Jacobi classes
+  const int classes[] = {1, 2, 4, 8, 16, 32, 0};
+  for (int ec : classes) {
+    const int begin = (int)P.jlist.size();
+    int maxrows = 1;
+    for (size_t i = 0; i < P.secs.size(); ++i) {
+      if (jacobi_class(P.secs[i].c) != ec) continue;
+      P.jlist.push_back((int)i);
+      maxrows = std::max(maxrows, P.secs[i].r);
+    }
+    const int cnt = (int)P.jlist.size() - begin;
+    if (cnt) {
+      P.jclass_begin.push_back(begin);
+      P.jclass_count.push_back(cnt);
+      P.jclass_maxrows.push_back(maxrows);
+      P.jclass_e.push_back(ec);
+    }
+  }
+  return MPS_OK;
+}
+
+bool valid_handle(mps_t h) { return h != nullptr && h->L > 0; }
+
+mps_status check_device_limits(mps_state* h, const BatchPlan& P) {
+  for (size_t i = 0; i < P.jclass_maxrows.size(); ++i)
+    if ((size_t)P.jclass_maxrows[i] * sizeof(double) > 64 * 1024)
+      return fail(MPS_E_ARG, "sector with %d rows exceeds the Jacobi kernel's LDS budget", P.jclass_maxrows[i]);
+  (void)h;
+  return MPS_OK;
+}
+
+// ---- the batched two-site update ------------------------------------------
+mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s, double* discarded) {
+  BatchPlan P;
+  STCHK(plan_batch(h, ng, sites, u2s, P));
+  STCHK(check_device_limits(h, P));
+  const int ns = (int)P.secs.size();
+
+  // workspaces
+  STCHK(ensure(h, h->th_raw, (size_t)P.th_elems * sizeof(double2)));
+  STCHK(ensure(h, h->th_scaled, (size_t)P.th_elems * sizeof(double2)));
+  STCHK(ensure(h, h->sigma, (size_t)P.sig_elems * sizeof(double)));
+  STCHK(ensure(h, h->order, (size_t)P.sig_elems * sizeof(int)));
+  if (P.maxP > 4096) {
+    STCHK(ensure(h, h->sel_v, (size_t)P.sel_scratch * sizeof(double)));
+    STCHK(ensure(h, h->sel_k, (size_t)P.sel_scratch * sizeof(int)));
+  }
+  // packed work list
+  Packer pk;
+  const size_t o_gates = pk.add(P.gates.data(), P.gates.size() * sizeof(GateWork));
+  const size_t o_secs = pk.add(P.secs.data(), P.secs.size() * sizeof(SectorWork));
+  const size_t o_tiles = pk.add(P.tiles.data(), P.tiles.size() * sizeof(ThetaTile));
+  const size_t o_coef = pk.add(P.coef.data(), P.coef.size() * sizeof(double2));
+  const size_t o_jlist = pk.add(P.jlist.data(), P.jlist.size() * sizeof(int));
+  const size_t o_seloff = pk.add(P.sel_off.data(), P.sel_off.size() * sizeof(long long));
+  const size_t o_kept = pk.add(nullptr, (size_t)ns * sizeof(int));
+  const size_t o_cut = pk.add(nullptr, (size_t)ng * sizeof(CutOut));
+  const size_t o_jst = pk.add(nullptr, (size_t)ns * sizeof(JacobiOut));
+  const size_t upload = o_kept;  // everything before the outputs is uploaded
+  STCHK(ensure(h, h->plan, pk.total));
+  STCHK(ensure_pin(h->stage_plan, upload));
+  pk.write(h->stage_plan.p);
+  HIPCHK(hipMemcpyAsync(h->plan.p, h->stage_plan.p, upload, hipMemcpyHostToDevice, h->st));
+
+  const GateWork* d_gates = at<GateWork>(h->plan, o_gates);
+  const SectorWork* d_secs = at<SectorWork>(h->plan, o_secs);
+  double2* raw = static_cast<double2*>(h->th_raw.p);
+  double2* scaled = static_cast<double2*>(h->th_scaled.p);
+  double* sig = static_cast<double*>(h->sigma.p);
+  int* ord = static_cast<int*>(h->order.p);
+
+  {
+    Timer tm(h, K_THETA);
+    STCHK(tm.start());
+    HIPCHK(launch_theta(d_gates, at<ThetaTile>(h->plan, o_tiles), (int)P.tiles.size(), d_secs,
+                        at<double2>(h->plan, o_coef), raw, scaled, P.maxw, h->st));
+    STCHK(tm.stop());
+  }
+  for (size_t c = 0; c < P.jclass_e.size(); ++c) {
+    const int ci = class_index(P.jclass_e[c]);
+    Timer tm(h, K_JACOBI0 + ci);
+    STCHK(tm.start());
+    HIPCHK(launch_jacobi(P.jclass_e[c], d_secs, at<int>(h->plan, o_jlist) + P.jclass_begin[c],
+                         P.jclass_count[c], P.jclass_maxrows[c], scaled, sig, ord,
+                         at<JacobiOut>(h->plan, o_jst), h->opts.max_sweeps, h->opts.jacobi_tol,
+                         h->st));
+    STCHK(tm.stop());
+    h->stats.jacobi_class_launches[ci] += 1;
+  }
+  {
+    Timer tm(h, K_SELECT);
+    STCHK(tm.start());
+    HIPCHK(launch_select(d_gates, ng, d_secs, sig, static_cast<double*>(h->sel_v.p),
+                         static_cast<int*>(h->sel_k.p), at<long long>(h->plan, o_seloff),
+                         at<int>(h->plan, o_kept), at<CutOut>(h->plan, o_cut), P.maxP, h->st));
+    STCHK(tm.stop());
+  }
+  // read back kept counts, cut results and Jacobi statistics
+  const size_t res_bytes = pk.total - o_kept;
+  STCHK(ensure_pin(h->stage_res, res_bytes));
+  HIPCHK(hipMemcpyAsync(h->stage_res.p, at<char>(h->plan, o_kept), res_bytes, hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  STCHK(drain_events(h));
+  const char* rb = static_cast<const char*>(h->stage_res.p);
+  const int* kept = reinterpret_cast<const int*>(rb);
+  const CutOut* cut = reinterpret_cast<const CutOut*>(rb + (o_cut - o_kept));
+  const JacobiOut* jst = reinterpret_cast<const JacobiOut*>(rb + (o_jst - o_kept));
+
+  for (int s = 0; s < ns; ++s) {
+    const SectorWork& sw = P.secs[s];
+    h->stats.sectors += 1;
+    h->stats.sweeps += jst[s].sweeps;
+    h->stats.rotations += jst[s].rotations;
+    const double pairs = double(jst[s].sweeps) * sw.r * (sw.r - 1) / 2.0;
+    h->stats.pairs += (long long)pairs;
+    const double jf = 16.0 * sw.c * pairs + 20.0 * sw.c * jst[s].rotations + 6.0 * sw.c * sw.r;
+    const int ci = class_index(jacobi_class(sw.c));
+    h->stats.jacobi_flops += jf;
+    h->stats.jacobi_class_flops[ci] += jf;
+    h->stats.jacobi_class_sectors[ci] += 1;
+    if (!jst[s].converged)
+      return fail(MPS_E_NOCONV, "Jacobi SVD of sector m=%d (%dx%d) did not converge in %d sweeps",
+                  sw.m, sw.r, sw.c, h->opts.max_sweeps);
+  }
+  for (int g = 0; g < ng; ++g)
+    if (cut[g].flags) return fail(MPS_E_NUMERIC, "two-site matrix at site %d vanished or is not finite", sites[g]);
+  h->stats.theta_flops += P.theta_flops;
+
+  // new bond tables and update lists
+  std::vector<RowWork> rows;
+  std::vector<UpdateWork> upds(ng);
+  std::vector<double2*> fill_ptr(ng);
+  std::vector<long long> fill_cnt(ng);
+  std::vector<GemmWork> gemms;
+  long long maxfill = 0;
+  int ntiles = 0;
+  std::vector<Bond> newb(ng);
+  for (int g = 0; g < ng; ++g) {
+    const int s = sites[g];
+    const int chil = h->bonds[s].dim();
+    const int chir = h->bonds[s + 2].dim();
+    Bond& nb = newb[g];
+    for (int i = P.gp[g].sec_begin; i < P.gp[g].sec_end; ++i) {
+      if (kept[i] <= 0) continue;
+      nb.charge.push_back(P.secs[i].m);
+      nb.count.push_back(kept[i]);
+    }
+    nb.finish();
+    const int chin = nb.dim();
+    if (chin > h->cap[s + 1] || chin <= 0)
+      return fail(MPS_E_NUMERIC, "internal: new bond dimension %d outside 1..%d", chin, h->cap[s + 1]);
+    upds[g].br_new = h->site[s + 1];
+    upds[g].lam_new = h->lam[s + 1];
+    upds[g].ldr = chir;
+    fill_ptr[g] = h->site[s];
+    fill_cnt[g] = (long long)chil * chin;
+    maxfill = std::max(maxfill, fill_cnt[g]);
+    int k = 0;
+    for (int i = P.gp[g].sec_begin; i < P.gp[g].sec_end; ++i) {
+      if (kept[i] <= 0) continue;
+      const SectorWork& sw = P.secs[i];
+      const int o = nb.off[k];
+      for (int j = 0; j < kept[i]; ++j) rows.push_back({g, i, j, o + j});
+      GemmWork gw{};
+      gw.a = raw + sw.off;
+      gw.lda = sw.c;
+      gw.b = h->site[s + 1] + (size_t)o * chir + sw.clo;
+      gw.ldb = chir;
+      gw.c = h->site[s] + (size_t)sw.rlo * chin + o;
+      gw.ldc = chin;
+      gw.m = sw.r;
+      gw.n = kept[i];
+      gw.k = sw.c;
+      gw.opa = 0;
+      gw.opb = 1;
+      gw.beta_one = 0;
+      gw.tiles_n = (gw.n + kGemmTile - 1) / kGemmTile;
+      gw.tile_begin = ntiles;
+      ntiles += ((gw.m + kGemmTile - 1) / kGemmTile) * gw.tiles_n;
+      gemms.push_back(gw);
+      h->stats.update_flops += 8.0 * sw.r * double(sw.c) * kept[i];
+      ++k;
+    }
+    if (discarded) discarded[g] = cut[g].discarded;
+    h->stats.max_discarded = std::max(h->stats.max_discarded, cut[g].discarded);
+    if (std::isfinite(cut[g].margin))
+      h->stats.min_margin = std::min(h->stats.min_margin, cut[g].margin);
+  }
+  Packer pu;
+  const size_t u_rows = pu.add(rows.data(), rows.size() * sizeof(RowWork));
+  const size_t u_upd = pu.add(upds.data(), upds.size() * sizeof(UpdateWork));
+  const size_t u_fp = pu.add(fill_ptr.data(), fill_ptr.size() * sizeof(double2*));
+  const size_t u_fc = pu.add(fill_cnt.data(), fill_cnt.size() * sizeof(long long));
+  const size_t u_gemm = pu.add(gemms.data(), gemms.size() * sizeof(GemmWork));
+  STCHK(ensure(h, h->upd, pu.total));
+  STCHK(ensure_pin(h->stage_upd, pu.total));
+  pu.write(h->stage_upd.p);
+  HIPCHK(hipMemcpyAsync(h->upd.p, h->stage_upd.p, pu.total, hipMemcpyHostToDevice, h->st));
+  {
+    Timer tm(h, K_UPDATE);
+    STCHK(tm.start());
+    HIPCHK(launch_update_rows(at<RowWork>(h->upd, u_rows), (int)rows.size(), d_secs,
+                              at<UpdateWork>(h->upd, u_upd), scaled, sig, ord, h->st));
+    HIPCHK(launch_zero_fill(at<double2*>(h->upd, u_fp), at<long long>(h->upd, u_fc), ng, maxfill, h->st));
+    HIPCHK(launch_zgemm(at<GemmWork>(h->upd, u_gemm), (int)gemms.size(), ntiles, h->st));
+    STCHK(tm.stop());
+  }
+  for (int g = 0; g < ng; ++g) h->bonds[sites[g] + 1] = newb[g];
+  h->stats.gates += ng;
+  h->stats.layers += 1;
+  h->stats.theta_launches += 1;
+  h->stats.jacobi_launches += (long long)P.jclass_e.size();
+  h->stats.select_launches += 1;
+  h->stats.update_launches += 3;
+  return MPS_OK;
+}
+
+mps_status destroy_buffers(mps_state* h) {
+  if (h->st) (void)hipStreamSynchronize(h->st);
+  for (double* p : h->lam) dfree(h, p);
+  for (double2* p : h->site) dfree(h, p);
+  h->lam.clear();
+  h->site.clear();
+  DevBuf* bufs[] = {&h->th_raw, &h->th_scaled, &h->sigma, &h->order, &h->plan, &h->upd,
+                    &h->norm_e0, &h->norm_e1, &h->norm_t, &h->sel_v, &h->sel_k, &h->misc};
+  for (DevBuf* b : bufs) {
+    dfree(h, b->p);
+    b->p = nullptr;
+    b->cap = 0;
+  }
+  PinBuf* pins[] = {&h->stage_plan, &h->stage_upd, &h->stage_res, &h->stage_misc};
+  for (PinBuf* b : pins) {
+    if (b->p) (void)hipHostFree(b->p);
+    b->p = nullptr;
+    b->cap = 0;
+  }
+  for (const Pending& p : h->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  h->pending.clear();
+  for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+  h->pool.clear();
+  return MPS_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+void mps_default_opts(mps_opts* o) {
+  if (!o) return;
+  o->chi_max = 0;
+  o->cutoff = 0.0;
+  o->zero_tol = 1e-13;
+  o->max_sweeps = 40;
+  o->jacobi_tol = 0.0;
+}
+
+const char* mps_last_error(void) { return g_err.c_str(); }
+
+mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const int* bond_charge,
+                      const mps_z* const* gamma, const double* const* lambda, const mps_opts* opts,
+                      const mps_device* dev, mps_t* out) {
+  if (!out) return fail(MPS_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (L < 2) return fail(MPS_E_ARG, "L must be at least 2");
+  if (d < 2 || d > kMaxD) return fail(MPS_E_ARG, "d must lie in 2..%d", kMaxD);
+  if (n_photons < 0) return fail(MPS_E_ARG, "negative photon number");
+  if (!bond_dim || !bond_charge) return fail(MPS_E_ARG, "bond_dim and bond_charge are required");
+  if (gamma && !lambda) return fail(MPS_E_ARG, "lambda is required with gamma");
+  if (bond_dim[0] != 1 || bond_dim[L] != 1) return fail(MPS_E_ARG, "bond 0 and bond L must have dimension 1");
+  for (int b = 0; b <= L; ++b) {
+    if (bond_dim[b] < 1) return fail(MPS_E_ARG, "bond %d has dimension %d", b, bond_dim[b]);
+    if (!gamma && bond_dim[b] != 1) return fail(MPS_E_ARG, "a product state needs every bond of dimension 1");
+  }
+  mps_opts o;
+  mps_default_opts(&o);
+  if (opts) o = *opts;
+  if (o.max_sweeps <= 0) return fail(MPS_E_ARG, "max_sweeps must be positive");
+  if (!(o.cutoff >= 0.0) || !(o.zero_tol >= 0.0)) return fail(MPS_E_ARG, "cutoff and zero_tol must be >= 0");
+
+  // charge tables with a stable sort of every bond by charge
+  std::vector<Bond> bonds(L + 1);
+  std::vector<std::vector<int>> perm(L + 1);
+  size_t pos = 0;
+  for (int b = 0; b <= L; ++b) {
+    const int n = bond_dim[b];
+    std::vector<int> ch(bond_charge + pos, bond_charge + pos + n);
+    pos += n;
+    for (int c : ch)
+      if (c < 0 || c > n_photons) return fail(MPS_E_CHARGE, "bond %d has charge %d outside 0..N", b, c);
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return ch[a] < ch[c]; });
+    perm[b] = idx;
+    Bond& B = bonds[b];
+    for (int i = 0; i < n; ++i) {
+      const int c = ch[idx[i]];
+      if (B.charge.empty() || B.charge.back() != c) {
+        B.charge.push_back(c);
+        B.count.push_back(0);
+      }
+      B.count.back() += 1;
+    }
+    B.finish();
+  }
+  if (bonds[0].charge[0] != n_photons) return fail(MPS_E_CHARGE, "bond 0 must carry charge N (Eq. E4)");
+  if (bonds[L].charge[0] != 0) return fail(MPS_E_CHARGE, "bond L must carry charge 0 (Eq. E4)");
+  // every left charge must connect to some right charge with 0 <= cL - cR <= d-1
+  for (int s = 0; s < L; ++s) {
+    for (int c : bonds[s].charge) {
+      bool ok = false;
+      for (int c2 : bonds[s + 1].charge)
+        if (c - c2 >= 0 && c - c2 <= d - 1) ok = true;
+      if (!ok) return fail(MPS_E_CHARGE, "charge %d on bond %d has no admissible partner on bond %d", c, s, s + 1);
+    }
+  }
+  // host site tensors B = Gamma * lambda_{s+1}, in sorted order, checked against Eq. (E2)
+  std::vector<std::vector<double2>> hsite(L);
+  std::vector<std::vector<double>> hlam(L + 1);
+  pos = 0;
+  std::vector<size_t> start(L + 1);
+  for (int b = 0; b <= L; ++b) {
+    start[b] = pos;
+    pos += bond_dim[b];
+  }
+  for (int b = 0; b <= L; ++b) {
+    hlam[b].resize(bond_dim[b]);
+    for (int i = 0; i < bond_dim[b]; ++i) {
+      const double v = lambda ? lambda[b][perm[b][i]] : 1.0;
+      if (!std::isfinite(v)) return fail(MPS_E_ARG, "non-finite lambda on bond %d", b);
+      hlam[b][i] = v;
+    }
+  }
+  for (int s = 0; s < L; ++s) {
+    const int rdim = bond_dim[s], cdim = bond_dim[s + 1];
+    hsite[s].assign((size_t)rdim * cdim, make_double2(0.0, 0.0));
+    for (int i = 0; i < rdim; ++i) {
+      const int ci = bond_charge[start[s] + perm[s][i]];
+      for (int j = 0; j < cdim; ++j) {
+        const int cj = bond_charge[start[s + 1] + perm[s + 1][j]];
+        double2 v;
+        if (gamma) {
+          const mps_z z = gamma[s][(size_t)perm[s][i] * cdim + perm[s + 1][j]];
+          v = make_double2(z.re * hlam[s + 1][j], z.im * hlam[s + 1][j]);
+          const bool allowed = (ci - cj >= 0 && ci - cj <= d - 1);
+          if (!allowed && (z.re != 0.0 || z.im != 0.0))
+            return fail(MPS_E_CHARGE, "site %d entry (%d,%d) violates the charge rule (Eq. E2)", s, i, j);
+          if (!std::isfinite(z.re) || !std::isfinite(z.im)) return fail(MPS_E_ARG, "non-finite gamma");
+        } else {
+          v = (ci - cj >= 0 && ci - cj <= d - 1) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+        }
+        hsite[s][(size_t)i * cdim + j] = v;
+      }
+    }
+  }
+
+  mps_state* h = new (std::nothrow) mps_state();
+  if (!h) return fail(MPS_E_NOMEM, "handle allocation failed");
+  h->L = L;
+  h->d = d;
+  h->N = n_photons;
+  h->opts = o;
+  if (dev) h->dev = *dev;
+  h->st = static_cast<hipStream_t>(h->dev.stream);
+  h->bonds = bonds;
+  h->stats.min_margin = INFINITY;
+  mps_status s = compute_caps(h);
+  if (s != MPS_OK) {
+    delete h;
+    return s;
+  }
+  h->lam.assign(L + 1, nullptr);
+  h->site.assign(L, nullptr);
+  for (int b = 0; b <= L && s == MPS_OK; ++b) {
+    h->lam[b] = static_cast<double*>(dalloc(h, (size_t)h->cap[b] * sizeof(double)));
+    if (!h->lam[b]) s = fail(MPS_E_NOMEM, "lambda allocation failed");
+  }
+  for (int t = 0; t < L && s == MPS_OK; ++t) {
+    h->site[t] = static_cast<double2*>(dalloc(h, (size_t)h->cap[t] * h->cap[t + 1] * sizeof(double2)));
+    if (!h->site[t]) s = fail(MPS_E_NOMEM, "site allocation failed");
+  }
+  if (s == MPS_OK) {
+    // upload through pinned staging, one synchronisation
+    size_t bytes = 0;
+    for (int b = 0; b <= L; ++b) bytes = align256(bytes + hlam[b].size() * sizeof(double));
+    for (int t = 0; t < L; ++t) bytes = align256(bytes + hsite[t].size() * sizeof(double2));
+    s = ensure_pin(h->stage_misc, bytes);
+    if (s == MPS_OK) {
+      char* base = static_cast<char*>(h->stage_misc.p);
+      size_t o2 = 0;
+      hipError_t e = hipSuccess;
+      for (int b = 0; b <= L && e == hipSuccess; ++b) {
+        const size_t nb = hlam[b].size() * sizeof(double);
+        std::memcpy(base + o2, hlam[b].data(), nb);
+        e = hipMemcpyAsync(h->lam[b], base + o2, nb, hipMemcpyHostToDevice, h->st);
+        o2 = align256(o2 + nb);
+      }
+      for (int t = 0; t < L && e == hipSuccess; ++t) {
+        const size_t nb = hsite[t].size() * sizeof(double2);
+        std::memcpy(base + o2, hsite[t].data(), nb);
+        e = hipMemcpyAsync(h->site[t], base + o2, nb, hipMemcpyHostToDevice, h->st);
+        o2 = align256(o2 + nb);
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(h->st);
+      if (e != hipSuccess) s = fail(MPS_E_DEVICE, "upload failed: %s", hipGetErrorString(e));
+    }
+  }
+  if (s != MPS_OK) {
+    destroy_buffers(h);
+    delete h;
+    return s;
+  }
+  *out = h;
+  return MPS_OK;
+}
+
+mps_status mps_create_product(int L, int d, const int* occupation, const mps_opts* opts,
+                              const mps_device* dev, mps_t* out) {
+  if (!occupation) return fail(MPS_E_ARG, "occupation is NULL");
+  if (L < 2) return fail(MPS_E_ARG, "L must be at least 2");
+  std::vector<int> dims(L + 1, 1), ch(L + 1, 0);
+  int N = 0;
+  for (int i = 0; i < L; ++i) {
+    if (occupation[i] < 0 || occupation[i] >= d)
+      return fail(MPS_E_ARG, "occupation %d of mode %d outside 0..d-1", occupation[i], i);
+    N += occupation[i];
+  }
+  int c = N;
+  for (int b = 0; b <= L; ++b) {
+    ch[b] = c;
+    if (b < L) c -= occupation[b];
+  }
+  return mps_create(L, d, N, dims.data(), ch.data(), nullptr, nullptr, opts, dev, out);
+}
+
+mps_status mps_destroy(mps_t h) {
+  if (!h) return MPS_OK;
+  destroy_buffers(h);
+  delete h;
+  return MPS_OK;
+}
+
+mps_status mps_apply_layer(mps_t h, int ngates, const int* sites, const mps_z* u2s, double* discarded) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (ngates < 0) return fail(MPS_E_ARG, "negative gate count");
+  if (ngates == 0) return MPS_OK;
+  if (!sites || !u2s) return fail(MPS_E_ARG, "sites and u2s are required");
+  std::vector<int> order(ngates);
+  for (int g = 0; g < ngates; ++g) {
+    if (sites[g] < 0 || sites[g] > h->L - 2) return fail(MPS_E_ARG, "gate site %d outside 0..L-2", sites[g]);
+    for (int k = 0; k < 4; ++k)
+      if (!std::isfinite(u2s[4 * g + k].re) || !std::isfinite(u2s[4 * g + k].im))
+        return fail(MPS_E_ARG, "non-finite gate element");
+    order[g] = sites[g];
+  }
+  std::sort(order.begin(), order.end());
+  for (int g = 1; g < ngates; ++g)
+    if (order[g] - order[g - 1] < 2) return fail(MPS_E_ARG, "gates of one layer must act on disjoint site pairs");
+  return apply_batch(h, ngates, sites, u2s, discarded);
+}
+
+mps_status mps_apply_gate(mps_t h, int site, const mps_z u2[4], double* discarded) {
+  if (!u2) return fail(MPS_E_ARG, "u2 is NULL");
+  return mps_apply_layer(h, 1, &site, u2, discarded);
+}
+
+mps_status mps_truncate(mps_t h, int bond, int chi_max, double cutoff, double* discarded) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (bond < 1 || bond > h->L - 1) return fail(MPS_E_ARG, "bond %d outside 1..L-1", bond);
+  if (!(cutoff >= 0.0)) return fail(MPS_E_ARG, "cutoff must be >= 0");
+  const Bond& B = h->bonds[bond];
+  std::vector<SectorWork> secs(B.charge.size());
+  int T = 0;
+  for (size_t i = 0; i < B.charge.size(); ++i) {
+    SectorWork sw{};
+    sw.gate = 0;
+    sw.m = B.charge[i];
+    sw.r = B.count[i];
+    sw.c = B.count[i];
+    sw.sig = B.off[i];
+    sw.kmax = B.count[i];
+    secs[i] = sw;
+    T += sw.kmax;
+  }
+  GateWork gw{};
+  gw.sec_begin = 0;
+  gw.sec_end = (int)secs.size();
+  gw.keep_cap = h->cap[bond];
+  gw.chi_max = chi_max;
+  gw.cutoff = cutoff;
+  gw.zero_tol = h->opts.zero_tol;
+  int Pp = 1;
+  while (Pp < T) Pp <<= 1;
+  long long zero = 0;
+  Packer pk;
+  const size_t o_g = pk.add(&gw, sizeof gw);
+  const size_t o_s = pk.add(secs.data(), secs.size() * sizeof(SectorWork));
+  const size_t o_z = pk.add(&zero, sizeof zero);
+  const size_t o_kept = pk.add(nullptr, secs.size() * sizeof(int));
+  const size_t o_cut = pk.add(nullptr, sizeof(CutOut));
+  STCHK(ensure(h, h->plan, pk.total));
+  STCHK(ensure_pin(h->stage_plan, pk.total));
+  if (Pp > 4096) {
+    STCHK(ensure(h, h->sel_v, (size_t)Pp * sizeof(double)));
+    STCHK(ensure(h, h->sel_k, (size_t)Pp * sizeof(int)));
+  }
+  HIPCHK(hipStreamSynchronize(h->st));
+  pk.write(h->stage_plan.p);
+  HIPCHK(hipMemcpyAsync(h->plan.p, h->stage_plan.p, o_kept, hipMemcpyHostToDevice, h->st));
+  HIPCHK(launch_select(at<GateWork>(h->plan, o_g), 1, at<SectorWork>(h->plan, o_s), h->lam[bond],
+                       static_cast<double*>(h->sel_v.p), static_cast<int*>(h->sel_k.p),
+                       at<long long>(h->plan, o_z), at<int>(h->plan, o_kept), at<CutOut>(h->plan, o_cut),
+                       Pp, h->st));
+  STCHK(ensure_pin(h->stage_res, pk.total - o_kept));
+  HIPCHK(hipMemcpyAsync(h->stage_res.p, at<char>(h->plan, o_kept), pk.total - o_kept,
+                        hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  const int* kept = static_cast<const int*>(h->stage_res.p);
+  CutOut co;
+  std::memcpy(&co, static_cast<const char*>(h->stage_res.p) + (o_cut - o_kept), sizeof co);
+  if (co.flags) return fail(MPS_E_NUMERIC, "bond %d has no positive finite Schmidt value", bond);
+  // maps of kept indices (each charge keeps its leading values)
+  Bond nb;
+  std::vector<int> map;
+  for (size_t i = 0; i < secs.size(); ++i) {
+    if (kept[i] <= 0) continue;
+    nb.charge.push_back(B.charge[i]);
+    nb.count.push_back(kept[i]);
+    for (int j = 0; j < kept[i]; ++j) map.push_back(B.off[i] + j);
+  }
+  nb.finish();
+  const int chin = nb.dim();
+  const int chil = h->bonds[bond - 1].dim(), chio = B.dim(), chir = h->bonds[bond + 1].dim();
+  const size_t tmp_elems = std::max((size_t)chil * chin, (size_t)chin * chir) + (size_t)chin;
+  STCHK(ensure(h, h->misc, align256(map.size() * sizeof(int)) + tmp_elems * sizeof(double2)));
+  STCHK(ensure_pin(h->stage_misc, map.size() * sizeof(int)));
+  std::memcpy(h->stage_misc.p, map.data(), map.size() * sizeof(int));
+  int* d_map = static_cast<int*>(h->misc.p);
+  double2* tmp = at<double2>(h->misc, align256(map.size() * sizeof(int)));
+  HIPCHK(hipMemcpyAsync(d_map, h->stage_misc.p, map.size() * sizeof(int), hipMemcpyHostToDevice, h->st));
+  HIPCHK(launch_gather_cols(h->site[bond - 1], chio, tmp, chin, chil, d_map, chin, h->st));
+  HIPCHK(hipMemcpyAsync(h->site[bond - 1], tmp, (size_t)chil * chin * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(launch_gather_rows(h->site[bond], chir, tmp, chir, d_map, chin, chir, h->st));
+  HIPCHK(hipMemcpyAsync(h->site[bond], tmp, (size_t)chin * chir * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
+  double* tl = reinterpret_cast<double*>(tmp);
+  HIPCHK(launch_gather_vec(h->lam[bond], tl, d_map, chin, h->st));
+  HIPCHK(hipMemcpyAsync(h->lam[bond], tl, (size_t)chin * sizeof(double), hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  h->bonds[bond] = nb;
+  if (discarded) *discarded = co.discarded;
+  return MPS_OK;
+}
+
+mps_status mps_amplitude(mps_t h, int count, const int* occ, mps_z* out) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (count < 0) return fail(MPS_E_ARG, "negative count");
+  if (count == 0) return MPS_OK;
+  if (!occ || !out) return fail(MPS_E_ARG, "occ and out are required");
+  const int L = h->L, N = h->N;
+  std::vector<int2> bmap((size_t)(L + 1) * (N + 1), make_int2(0, 0));
+  int maxdim = 1;
+  for (int b = 0; b <= L; ++b) {
+    const Bond& B = h->bonds[b];
+    for (size_t i = 0; i < B.charge.size(); ++i)
+      bmap[(size_t)b * (N + 1) + B.charge[i]] = make_int2(B.off[i], B.count[i]);
+    maxdim = std::max(maxdim, B.dim());
+  }
+  std::vector<int> ld(L);
+  std::vector<const double2*> sp(L);
+  for (int s = 0; s < L; ++s) {
+    ld[s] = h->bonds[s + 1].dim();
+    sp[s] = h->site[s];
+  }
+  Packer pk;
+  const size_t o_sp = pk.add(sp.data(), sp.size() * sizeof(double2*));
+  const size_t o_ld = pk.add(ld.data(), ld.size() * sizeof(int));
+  const size_t o_bm = pk.add(bmap.data(), bmap.size() * sizeof(int2));
+  const size_t o_occ = pk.add(occ, (size_t)count * L * sizeof(int));
+  const size_t o_out = pk.add(nullptr, (size_t)count * sizeof(double2));
+  if ((size_t)2 * maxdim * sizeof(double2) > 64 * 1024) return fail(MPS_E_ARG, "bond dimension too large for the amplitude kernel");
+  STCHK(ensure(h, h->misc, pk.total));
+  HIPCHK(hipStreamSynchronize(h->st));
+  STCHK(ensure_pin(h->stage_misc, pk.total));
+  pk.write(h->stage_misc.p);
+  HIPCHK(hipMemcpyAsync(h->misc.p, h->stage_misc.p, o_out, hipMemcpyHostToDevice, h->st));
+  HIPCHK(launch_amplitude(at<const double2*>(h->misc, o_sp), at<int>(h->misc, o_ld), at<int2>(h->misc, o_bm),
+                          at<int>(h->misc, o_occ), at<double2>(h->misc, o_out), count, L, h->d, N, maxdim,
+                          h->st));
+  HIPCHK(hipMemcpyAsync(static_cast<char*>(h->stage_misc.p) + o_out, at<char>(h->misc, o_out),
+                        (size_t)count * sizeof(double2), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  std::memcpy(out, static_cast<char*>(h->stage_misc.p) + o_out, (size_t)count * sizeof(double2));
+  return MPS_OK;
+}
+
+mps_status mps_norm(mps_t h, double* norm2) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (!norm2) return fail(MPS_E_ARG, "norm2 is NULL");
+  const int L = h->L, d = h->d;
+  int maxdim = 1;
+  for (int b = 0; b <= L; ++b) maxdim = std::max(maxdim, h->bonds[b].dim());
+  const size_t esz = (size_t)maxdim * maxdim;
+  STCHK(ensure(h, h->norm_e0, esz * sizeof(double2)));
+  STCHK(ensure(h, h->norm_e1, esz * sizeof(double2)));
+  STCHK(ensure(h, h->norm_t, (size_t)d * esz * sizeof(double2)));
+  double2* e[2] = {static_cast<double2*>(h->norm_e0.p), static_cast<double2*>(h->norm_e1.p)};
+  double2* tbuf = static_cast<double2*>(h->norm_t.p);
+  // per site: problems T_c' = E[w, w] B[w, c'] and E'[c', c'] = B[w, c']^dagger T_c'
+  std::vector<std::vector<GemmWork>> p1(L), p2(L);
+  std::vector<int> nt1(L, 0), nt2(L, 0);
+  std::vector<double2*> fptr(L);
+  std::vector<long long> fcnt(L);
+  for (int s = 0; s < L; ++s) {
+    const Bond& B0 = h->bonds[s];
+    const Bond& B1 = h->bonds[s + 1];
+    const int ld0 = B0.dim(), ld1 = B1.dim();
+    double2* ein = e[s & 1];
+    double2* eout = e[(s + 1) & 1];
+    fptr[s] = eout;
+    fcnt[s] = (long long)ld1 * ld1;
+    size_t toff = 0;
+    for (size_t i = 0; i < B1.charge.size(); ++i) {
+      const int cp = B1.charge[i];
+      const int w0 = B0.off[B0.lower(cp)], w1 = B0.off[B0.lower(cp + d)];
+      if (w1 <= w0) continue;
+      const int nn = B1.count[i], o1 = B1.off[i], kw = w1 - w0;
+      GemmWork a{};
+      a.a = ein + (size_t)w0 * ld0 + w0;
+      a.lda = ld0;
+      a.b = h->site[s] + (size_t)w0 * ld1 + o1;
+      a.ldb = ld1;
+      a.c = tbuf + toff;
+      a.ldc = nn;
+      a.m = kw;
+      a.n = nn;
+      a.k = kw;
+      a.tiles_n = (nn + kGemmTile - 1) / kGemmTile;
+      a.tile_begin = nt1[s];
+      nt1[s] += ((kw + kGemmTile - 1) / kGemmTile) * a.tiles_n;
+      p1[s].push_back(a);
+      GemmWork b{};
+      b.a = h->site[s] + (size_t)w0 * ld1 + o1;
+      b.lda = ld1;
+      b.opa = 1;
+      b.b = tbuf + toff;
+      b.ldb = nn;
+      b.c = eout + (size_t)o1 * ld1 + o1;
+      b.ldc = ld1;
+      b.m = nn;
+      b.n = nn;
+      b.k = kw;
+      b.tiles_n = (nn + kGemmTile - 1) / kGemmTile;
+      b.tile_begin = nt2[s];
+      nt2[s] += ((nn + kGemmTile - 1) / kGemmTile) * b.tiles_n;
+      p2[s].push_back(b);
+      toff += (size_t)kw * nn;
+    }
+    if (toff > (size_t)d * esz) return fail(MPS_E_ARG, "internal: norm scratch too small");
+  }
+  Packer pk;
+  std::vector<size_t> o1(L), o2(L);
+  for (int s = 0; s < L; ++s) {
+    o1[s] = pk.add(p1[s].data(), p1[s].size() * sizeof(GemmWork));
+    o2[s] = pk.add(p2[s].data(), p2[s].size() * sizeof(GemmWork));
+  }
+  const size_t o_fp = pk.add(fptr.data(), fptr.size() * sizeof(double2*));
+  const size_t o_fc = pk.add(fcnt.data(), fcnt.size() * sizeof(long long));
+  const double2 one = make_double2(1.0, 0.0);
+  const size_t o_one = pk.add(&one, sizeof one);
+  HIPCHK(hipStreamSynchronize(h->st));
+  STCHK(ensure(h, h->misc, pk.total));
+  STCHK(ensure_pin(h->stage_misc, pk.total + sizeof(double2)));
+  pk.write(h->stage_misc.p);
+  HIPCHK(hipMemcpyAsync(h->misc.p, h->stage_misc.p, pk.total, hipMemcpyHostToDevice, h->st));
+  HIPCHK(hipMemcpyAsync(e[0], at<double2>(h->misc, o_one), sizeof(double2), hipMemcpyDeviceToDevice, h->st));
+  for (int s = 0; s < L; ++s) {
+    HIPCHK(launch_zero_fill(at<double2*>(h->misc, o_fp) + s, at<long long>(h->misc, o_fc) + s, 1, fcnt[s], h->st));
+    HIPCHK(launch_zgemm(at<GemmWork>(h->misc, o1[s]), (int)p1[s].size(), nt1[s], h->st));
+    HIPCHK(launch_zgemm(at<GemmWork>(h->misc, o2[s]), (int)p2[s].size(), nt2[s], h->st));
+  }
+  double2* res = reinterpret_cast<double2*>(static_cast<char*>(h->stage_misc.p) + pk.total);
+  HIPCHK(hipMemcpyAsync(res, e[L & 1], sizeof(double2), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  *norm2 = res->x;
+  return MPS_OK;
+}
+
+mps_status mps_bond_sectors(mps_t h, int bond, int cap, int* nsec, int* charge, int* count) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (bond < 0 || bond > h->L) return fail(MPS_E_ARG, "bond %d outside 0..L", bond);
+  const Bond& B = h->bonds[bond];
+  if (nsec) *nsec = (int)B.charge.size();
+  if ((int)B.charge.size() > cap) return fail(MPS_E_ARG, "capacity %d < %zu sectors", cap, B.charge.size());
+  for (size_t i = 0; i < B.charge.size(); ++i) {
+    if (charge) charge[i] = B.charge[i];
+    if (count) count[i] = B.count[i];
+  }
+  return MPS_OK;
+}
+
+mps_status mps_bond_lambda(mps_t h, int bond, int cap, int* n, double* lambda) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (bond < 0 || bond > h->L) return fail(MPS_E_ARG, "bond %d outside 0..L", bond);
+  const int dim = h->bonds[bond].dim();
+  if (n) *n = dim;
+  if (dim > cap) return fail(MPS_E_ARG, "capacity %d < dimension %d", cap, dim);
+  if (!lambda) return fail(MPS_E_ARG, "lambda is NULL");
+  HIPCHK(hipMemcpyAsync(lambda, h->lam[bond], (size_t)dim * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return MPS_OK;
+}
+
+mps_status mps_site_tensor(mps_t h, int site, size_t cap, int* rows, int* cols, mps_z* out) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (site < 0 || site >= h->L) return fail(MPS_E_ARG, "site %d outside 0..L-1", site);
+  const int r = h->bonds[site].dim(), c = h->bonds[site + 1].dim();
+  if (rows) *rows = r;
+  if (cols) *cols = c;
+  if ((size_t)r * c > cap) return fail(MPS_E_ARG, "capacity too small");
+  if (!out) return fail(MPS_E_ARG, "out is NULL");
+  HIPCHK(hipMemcpyAsync(out, h->site[site], (size_t)r * c * sizeof(double2), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return MPS_OK;
+}
+
+mps_status mps_set_timing(mps_t h, int on) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  HIPCHK(hipStreamSynchronize(h->st));
+  STCHK(drain_events(h));
+  h->timing = on != 0;
+  return MPS_OK;
+}
+
+mps_status mps_get_stats(mps_t h, mps_stats* s) {
+  if (!valid_handle(h) || !s) return fail(MPS_E_ARG, "invalid handle or NULL stats");
+  HIPCHK(hipStreamSynchronize(h->st));
+  STCHK(drain_events(h));
+  *s = h->stats;
+  return MPS_OK;
+}
+
+mps_status mps_reset_stats(mps_t h) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  HIPCHK(hipStreamSynchronize(h->st));
+  STCHK(drain_events(h));
+  h->stats = mps_stats{};
+  h->stats.min_margin = INFINITY;
+  return MPS_OK;
+}
+
+mps_status mps_sync(mps_t h) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  HIPCHK(hipStreamSynchronize(h->st));
+  return drain_events(h);
+}
+
+}  // extern "C"

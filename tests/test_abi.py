@@ -1,0 +1,78 @@
+"""The C ABI library loads and exports every declared entry point (no GPU).
+
+Also exercises argument and charge validation, which the library performs
+on the host before it touches the device.
+"""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2303_11409_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "u1mps.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mps_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for required in ("mps_create", "mps_apply_gate", "mps_truncate", "mps_amplitude", "mps_norm"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load_library()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    assert sorted(binding.EXPORTS) == declared_symbols()
+
+
+def test_default_options():
+    lib = binding.lib()
+    o = binding.mps_opts()
+    lib.mps_default_opts(C.byref(o))
+    assert (o.chi_max, o.cutoff, o.zero_tol, o.max_sweeps, o.jacobi_tol) == (0, 0.0, 1e-13, 40, 0.0)
+
+
+def _create(L, d, N, dims, charges):
+    lib = binding.lib()
+    h = C.c_void_p()
+    cd = (C.c_int * len(dims))(*dims)
+    cc = (C.c_int * len(charges))(*charges)
+    st = lib.mps_create(L, d, N, cd, cc, None, None, None, None, C.byref(h))
+    return st, lib.mps_last_error().decode(), h
+
+
+def test_charge_validation_errors():
+    # bond 0 must carry N, bond L must carry 0 (Eq. E4)
+    st, msg, h = _create(3, 3, 2, [1, 1, 1, 1], [1, 1, 0, 0])
+    assert st == -2 and "bond 0" in msg and not h.value
+    st, msg, _ = _create(3, 3, 2, [1, 1, 1, 1], [2, 1, 0, 1])
+    assert st == -2
+    # a charge step larger than d-1 has no admissible partner (Eq. E2)
+    st, msg, _ = _create(3, 2, 3, [1, 1, 1, 1], [3, 1, 0, 0])
+    assert st == -2 and "partner" in msg
+    # charge outside 0..N
+    st, msg, _ = _create(3, 3, 2, [1, 1, 1, 1], [2, 5, 0, 0])
+    assert st == -2
+
+
+def test_argument_errors():
+    lib = binding.lib()
+    h = C.c_void_p()
+    occ = (C.c_int * 4)(1, 0, 5, 0)
+    assert lib.mps_create_product(4, 3, occ, None, None, C.byref(h)) == -1
+    assert lib.mps_create_product(1, 3, occ, None, None, C.byref(h)) == -1
+    occ2 = (C.c_int * 4)(1, 0, 1, 0)
+    assert lib.mps_create_product(4, 1, occ2, None, None, C.byref(h)) == -1
+    assert lib.mps_apply_gate(None, 0, None, None) == -1
+    assert lib.mps_norm(None, None) == -1
+    assert lib.mps_destroy(None) == 0
+    assert isinstance(lib.mps_last_error(), bytes)

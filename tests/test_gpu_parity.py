@@ -1,0 +1,212 @@
+"""Parity of the HIP gate path with the CPU oracle (needs an MI355X).
+
+Tolerances (complex128 path): amplitudes agree normwise and per amplitude to
+1e-10 relative to the largest reference amplitude; Schmidt values to
+1e-10 * s_max of the bond; norms to 1e-10 absolute.  Bond bookkeeping (the
+charge multiplicities of every bond) must be identical to the oracle's
+charge audit, except at cuts the oracle reports as near-ties (margin below
+1e-9), which none of these seeded cases has.
+"""
+import numpy as np
+import pytest
+
+from oracle import dense_mps, fock, permanent
+from workloads import circuits
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def mps_cls():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    from paper_2303_11409_amd import MPS
+    return MPS
+
+
+def close_amps(got, ref, tol=TOL):
+    scale = max(float(np.max(np.abs(ref))), 1e-300)
+    per = float(np.max(np.abs(got - ref))) / scale
+    normwise = float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+    assert per <= tol and normwise <= tol, (per, normwise)
+    return per
+
+
+def run_gpu(MPS, occ, d, gates, chi_max=0, cutoff=0.0, layered=False, layers=None):
+    m = MPS(occ, d, chi_max=chi_max, cutoff=cutoff)
+    disc = []
+    if layered:
+        for lay in layers:
+            disc.extend(m.apply_layer([g.site for g in lay], [g.u for g in lay]))
+    else:
+        for g in gates:
+            disc.append(m.apply_gate(g.site, g.u))
+    return m, np.array(disc)
+
+
+def check_bookkeeping(m, ref):
+    for b in range(m.L + 1):
+        assert ref.audit_clean(b), b
+        assert m.bond_sectors(b) == ref.bond_charges(b), (b, m.bond_sectors(b), ref.bond_charges(b))
+
+
+def check_lambdas(m, ref):
+    for b in range(1, m.L):
+        got = np.sort(m.bond_lambda(b))[::-1]
+        exp = ref.lam[b]
+        assert got.shape == exp.shape, b
+        assert np.max(np.abs(got - exp)) <= TOL * exp[0], b
+
+
+def test_exact_clements_circuit(mps_cls):
+    cfg = circuits.config_small_exact()
+    pats = circuits.all_patterns(8, 4, 5)
+    m, _ = run_gpu(mps_cls, cfg["occupation"], 5, cfg["gates"])
+    ref = dense_mps.DenseMPS(cfg["occupation"], 5).run(cfg["gates"])
+    perm = np.array([permanent.fock_amplitude(cfg["unitary"], cfg["occupation"], p) for p in pats])
+    amp = m.amplitudes(pats)
+    assert np.max(np.abs(amp - perm)) < 1e-12
+    close_amps(amp, ref.amplitudes(pats))
+    assert abs(m.norm2() - 1.0) < 1e-13
+    check_bookkeeping(m, ref)
+    check_lambdas(m, ref)
+    m.close()
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small_circuits_vs_brute_force(mps_cls, seed):
+    rng = np.random.default_rng(500 + seed)
+    L = int(rng.integers(2, 7))
+    d = int(rng.integers(2, 6))
+    occ = [int(x) for x in rng.integers(0, d, size=L)]
+    if sum(occ) == 0:
+        occ[0] = 1
+    gates = [circuits.Gate(int(rng.integers(0, L - 1)),
+                           circuits.haar_unitary(2, int(rng.integers(1 << 30)))) for _ in range(4 * L)]
+    m, _ = run_gpu(mps_cls, occ, d, gates)
+    st = fock.run(occ, d, gates)
+    pats = circuits.all_patterns(L, sum(occ), d)
+    ref = np.array([st.amplitude(p) for p in pats])
+    got = m.amplitudes(pats)
+    assert np.max(np.abs(got - ref)) < 1e-12
+    assert abs(m.norm2() - st.norm2()) < 1e-12
+    m.close()
+
+
+def test_truncated_brickwork_vs_oracle(mps_cls):
+    cfg = circuits.config_brickwork(12, 6, "first", 3, 12, 10, 1e-12, 21, "t")
+    m, disc = run_gpu(mps_cls, cfg["occupation"], 3, cfg["gates"], chi_max=10, cutoff=1e-12)
+    ref = dense_mps.DenseMPS(cfg["occupation"], 3, chi_max=10, cutoff=1e-12).run(cfg["gates"])
+    odisc = np.array([r.discarded for r in ref.records])
+    assert min(r.margin for r in ref.records) > 1e-9
+    assert np.max(np.abs(disc - odisc)) <= 1e-12
+    pats = circuits.sample_patterns(12, 6, 3, 300, 3)
+    close_amps(m.amplitudes(pats), ref.amplitudes(pats))
+    assert abs(m.norm2() - ref.norm2()) <= TOL
+    check_bookkeeping(m, ref)
+    check_lambdas(m, ref)
+    m.close()
+
+
+def test_layer_batch_equals_sequential(mps_cls):
+    cfg = circuits.config_brickwork(14, 7, "first", 4, 10, 24, 1e-12, 31, "t")
+    a, da = run_gpu(mps_cls, cfg["occupation"], 4, cfg["gates"], chi_max=24, cutoff=1e-12)
+    b, db = run_gpu(mps_cls, cfg["occupation"], 4, None, chi_max=24, cutoff=1e-12, layered=True,
+                    layers=cfg["layers"])
+    pats = circuits.sample_patterns(14, 7, 4, 200, 5)
+    # per-sector arithmetic does not depend on what else shares the launch
+    assert np.array_equal(a.amplitudes(pats), b.amplitudes(pats))
+    assert np.array_equal(da, db)
+    for k in range(15):
+        assert a.bond_sectors(k) == b.bond_sectors(k)
+    a.close()
+    b.close()
+
+
+def test_conservation_exact_zeros(mps_cls):
+    cfg = circuits.config_small_exact()
+    m, _ = run_gpu(mps_cls, cfg["occupation"], 5, cfg["gates"])
+    rng = np.random.default_rng(8)
+    bad = rng.integers(0, 5, size=(300, 8))
+    bad = bad[bad.sum(1) != 4]
+    assert np.all(m.amplitudes(bad) == 0.0)
+    assert np.all(m.amplitudes(np.array([[5, 0, 0, 0, 0, 0, 0, -1]])) == 0.0)
+    m.close()
+
+
+def test_charge_ranges_every_bond(mps_cls):
+    cfg = circuits.config_brickwork(16, 8, "first", 4, 12, 32, 1e-12, 41, "t")
+    m, _ = run_gpu(mps_cls, cfg["occupation"], 4, None, chi_max=32, cutoff=1e-12, layered=True,
+                   layers=cfg["layers"])
+    L, N, d = 16, 8, 4
+    for b in range(L + 1):
+        lo, hi = max(0, N - b * (d - 1)), min(N, (L - b) * (d - 1))
+        for c in m.bond_sectors(b):
+            assert lo <= c <= hi
+    m.close()
+
+
+def test_large_sector_prefix_of_the_32_mode_workload(mps_cls):
+    """First six layers of the L=32, N=16, d=4, chi_max=512 circuit: bonds reach
+    chi = 512 with sectors of a few hundred rows (several tiles, ragged tails)."""
+    cfg = circuits.config_plain_gpu()
+    layers = cfg["layers"][:6]
+    gates = [g for lay in layers for g in lay]
+    m, disc = run_gpu(mps_cls, cfg["occupation"], 4, None, chi_max=512, cutoff=1e-12, layered=True,
+                      layers=layers)
+    ref = dense_mps.DenseMPS(cfg["occupation"], 4, chi_max=512, cutoff=1e-12).run(gates)
+    assert max(m.bond_dims()) == 512
+    assert min(r.margin for r in ref.records) > 1e-9
+    odisc = np.array([r.discarded for r in ref.records])
+    assert np.max(np.abs(disc - odisc)) <= 1e-12
+    check_bookkeeping(m, ref)
+    check_lambdas(m, ref)
+    pats = circuits.sample_patterns(32, 16, 4, 256, 102)
+    close_amps(m.amplitudes(pats), ref.amplitudes(pats))
+    assert abs(m.norm2() - ref.norm2()) <= TOL
+    m.close()
+
+
+def test_truncate_matches_identity_gate_cut(mps_cls):
+    # d > N and no cut while evolving: the state stays canonical, so cutting a
+    # bond from its Schmidt values equals an SVD-based cut with the new cap
+    cfg = circuits.config_brickwork(10, 4, "first", 5, 8, 0, 0.0, 51, "t")
+    m, _ = run_gpu(mps_cls, cfg["occupation"], 5, cfg["gates"])
+    ref = dense_mps.DenseMPS(cfg["occupation"], 5).run(cfg["gates"])
+    disc = m.truncate(5, 6, 0.0)
+    ref.chi_max = 6
+    rec = ref.apply_gate(4, np.eye(2))
+    assert abs(disc - rec.discarded) <= 1e-12
+    assert m.bond_sectors(5) == ref.bond_charges(5)
+    pats = circuits.sample_patterns(10, 4, 5, 200, 6)
+    close_amps(m.amplitudes(pats), ref.amplitudes(pats))
+    m.close()
+
+
+def test_vacuum_and_edges(mps_cls):
+    # no photons: every charge is 0 and gates act trivially
+    m = mps_cls([0, 0, 0], 3)
+    m.apply_gate(0, circuits.beam_splitter(0.3, 0.2))
+    m.apply_gate(1, circuits.beam_splitter(0.7, 1.2))
+    assert abs(m.amplitudes([[0, 0, 0]])[0] - 1.0) < 1e-15
+    assert abs(m.norm2() - 1.0) < 1e-15
+    m.close()
+    # two modes, d = 2 with two photons: the |1,1> Hong-Ou-Mandel zero
+    u = np.array([[1, -1], [1, 1]], dtype=complex) / np.sqrt(2)
+    m = mps_cls([1, 1], 3)
+    m.apply_gate(0, u)
+    a = m.amplitudes([[1, 1], [2, 0], [0, 2]])
+    assert abs(a[0]) < 1e-15 and abs(abs(a[1]) ** 2 - 0.5) < 1e-14
+    m.close()
+    # with d = 2 the cutoff removes every output of |1,1>: the two-site matrix
+    # vanishes, which the device reports as MPS_E_NUMERIC
+    from paper_2303_11409_amd import MPSError
+    m = mps_cls([1, 1], 2)
+    with pytest.raises(MPSError) as ei:
+        m.apply_gate(0, u)
+    assert ei.value.status == -6
+    m.close()
