@@ -78,8 +78,9 @@ typedef struct {
  *   zero_tol   singular values <= zero_tol * s_max are dropped as numerical
  *              zeros (default 1e-13).
  *   max_sweeps Jacobi sweep limit per sector (default 40).
- *   jacobi_tol rotate a row pair while |<x,y>| > tol * |x| |y|; <= 0 means
- *              sqrt(row length) * 2^-52.
+ *   jacobi_tol rotate a vector pair while |<x,y>| > tol * |x| |y|; <= 0
+ *              means (vector length) * 2^-52.  The SVD of an r x c sector
+ *              orthogonalises its min(r, c) rows or columns.
  * The kept count is K = max(1, min(chi_max, K_eps, K_zero)). */
 typedef struct {
   int chi_max;
@@ -93,8 +94,9 @@ typedef struct {
  * *_ms are kernel times from HIP events on the handle's stream; they are
  * filled only while timing is enabled (mps_set_timing).  Flop figures are
  * algorithmic: 8*nL*nM*nR per charge triple for Theta formation, and for the
- * Jacobi kernel 16*len per row pair inspected, 20*len per rotation applied,
- * 6*len per row for the final norms. */
+ * Jacobi kernel (vectors of length len = max(r, c)) 16*len per vector pair
+ * inspected, 20*len per rotation applied (plus 20*min(r, c) for the rotation
+ * accumulator of a tall sector), 6*len per vector for the final norms. */
 typedef struct {
   long long gates;             /* two-site updates applied                  */
   long long layers;            /* batched launches (mps_apply_layer calls)  */

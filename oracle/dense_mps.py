@@ -204,7 +204,8 @@ class DenseMPS:
         """<psi|psi> by full contraction of the transfer matrices."""
         e = np.ones((1, 1), dtype=np.complex128)
         for bt in self.site_matrices():
-            e = np.einsum("ab,aic,bid->cd", e, bt.conj(), bt)
+            # E'[c, d] = sum_i sum_ab conj(B[a, i, c]) E[a, b] B[b, i, d]
+            e = sum(bt[:, i, :].conj().T @ (e @ bt[:, i, :]) for i in range(bt.shape[1]))
         return float(e[0, 0].real)
 
     def bond_dims(self) -> List[int]:

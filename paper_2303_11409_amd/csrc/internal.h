@@ -44,6 +44,8 @@ struct SectorWork {
   long long off;          // element offset of Theta(m) in the theta workspaces
   int sig;                // offset of this sector's r singular values / row order
   int kmax;               // min(r, c): at most this many values enter the cut
+  int tall;               // r > c: the SVD orthogonalises the c columns instead
+  long long acc;          // tall only: element offset of the c x c rotation accumulator
 };
 
 // One 32x32 output tile of one (cL, cR) charge pair of one gate.  The tile

@@ -10,10 +10,11 @@ hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntile
                         const SectorWork* secs, const double2* coef, double2* raw,
                         double2* scaled, int maxw, hipStream_t st);
 
-// Row-length class of the Jacobi kernel: E complex per lane per row, 0 = streaming.
+// Vector-length class of the Jacobi kernel: E complex per lane per vector, 0 = streaming.
 int jacobi_class(int len);
+// The SVD runs on min(r, c) vectors of length max(r, c); maxrows bounds min(r, c).
 hipError_t launch_jacobi(int ecls, const SectorWork* secs, const int* list, int count, int maxrows,
-                         double2* theta, double* sigma, int* order, JacobiOut* stats,
+                         double2* theta, double2* acc, double* sigma, int* order, JacobiOut* stats,
                          int max_sweeps, double tol, hipStream_t st);
 
 hipError_t launch_select(const GateWork* gates, int ngates, const SectorWork* secs,

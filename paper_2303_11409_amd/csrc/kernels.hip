@@ -121,10 +121,12 @@ theta_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ t
         for (int b = 0; b < 2; ++b) {
           const int c = tx + 16 * b;
           if (c >= t.ncol) continue;
-          const size_t idx = (size_t)s.off + (size_t)(t.orow[i] + r) * s.c + (t.ocol[i] + c);
+          const size_t rr = (size_t)(t.orow[i] + r), cc = (size_t)(t.ocol[i] + c);
           const double2 v = out[i][a][b];
-          th_raw[idx] = v;
-          th_scaled[idx] = make_double2(lam * v.x, lam * v.y);
+          th_raw[(size_t)s.off + rr * s.c + cc] = v;
+          // the SVD input of a tall sector is stored transposed (its columns as rows)
+          const size_t si = s.tall ? (size_t)s.off + cc * s.r + rr : (size_t)s.off + rr * s.c + cc;
+          th_scaled[si] = make_double2(lam * v.x, lam * v.y);
         }
       }
     }
@@ -132,16 +134,24 @@ theta_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ t
 }
 
 // ---------------------------------------------------------------------------
-// One-sided Jacobi on the rows of Theta(m).  One workgroup per sector; each
-// wavefront takes whole row pairs of the current round-robin step (circle
-// method: n' - 1 steps of n'/2 disjoint pairs cover all pairs once), loads
-// both rows into registers (E complex per lane per row), forms
+// One-sided (Hestenes) Jacobi SVD of Theta(m), on the min(r, c) vectors of
+// length max(r, c): the rows of Theta when r <= c, else its columns (the
+// theta kernel stores a tall sector transposed).  One workgroup per sector;
+// each wavefront takes whole vector pairs of the current round-robin step
+// (circle method: n' - 1 steps of n'/2 disjoint pairs cover all pairs once),
+// holds both vectors in registers (E complex per lane), forms
 // alpha = |x|^2, beta = |y|^2, gamma = <x, y> with wave reductions, and
-// rotates when |gamma| > tol sqrt(alpha beta):
+// rotates unless |gamma| <= tol sqrt(alpha beta) or the pair is below the
+// rounding floor of the whole sector:
 //   zeta = (beta - alpha) / (2|gamma|), t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
 //   c = 1/sqrt(1 + t^2), s = c t, e = gamma/|gamma|,
 //   x' = c x - s e y,  y' = s conj(e) x + c y   (makes <x', y'> = 0).
-// E == 0 selects the streaming form for rows longer than 64 * 32.
+// With J the product of all rotations, J X = S Y with orthonormal rows Y:
+//   wide (X = Theta):    V^dagger = Y, the normalised vectors;
+//   tall (X = Theta^T):  V^dagger = conj(J), accumulated in A (c x c) from I.
+// The V^dagger rows are left in the sector's theta_scaled slot (stride c);
+// the singular values (vector norms) and the order that sorts them
+// descending go to sigma/order.  E == 0 streams vectors longer than 64 * 32.
 __device__ __forceinline__ void rr_pair(int step, int k, int np, int& i, int& j) {
   const int q = np - 1;
   if (k == 0) {
@@ -153,22 +163,51 @@ __device__ __forceinline__ void rr_pair(int step, int k, int np, int& i, int& j)
   }
 }
 
+__device__ __forceinline__ void rot_pair(double2& a, double2& b, double c, double wr, double wi) {
+  // a' = c a - w b ; b' = conj(w) a + c b, with w = s e
+  const double2 x = a, y = b;
+  a.x = c * x.x - (wr * y.x - wi * y.y);
+  a.y = c * x.y - (wr * y.y + wi * y.x);
+  b.x = (wr * x.x + wi * x.y) + c * y.x;
+  b.y = (wr * x.y - wi * x.x) + c * y.y;
+}
+
 template <int E, int NT>
 __global__ void __launch_bounds__(NT)
 jacobi_rows(const SectorWork* __restrict__ secs, const int* __restrict__ list,
-            double2* __restrict__ theta, double* __restrict__ sigma, int* __restrict__ order,
-            JacobiOut* __restrict__ stats, int max_sweeps, double tol_opt) {
-  extern __shared__ double jsm[];          // n doubles: row norms
+            double2* __restrict__ theta, double2* __restrict__ accbuf, double* __restrict__ sigma,
+            int* __restrict__ order, JacobiOut* __restrict__ stats, int max_sweeps, double tol_opt) {
+  extern __shared__ double jsm[];          // n doubles: vector norms
   __shared__ int rotated;
   __shared__ int rot_total;
+  __shared__ double wsum[NT / 64];
   const int sid = list[blockIdx.x];
   const SectorWork sw = secs[sid];
-  const int n = sw.r, len = sw.c;
+  const bool tall = sw.tall != 0;
+  const int n = tall ? sw.c : sw.r;        // number of vectors
+  const int len = tall ? sw.r : sw.c;      // vector length
   double2* x = theta + sw.off;
-  const double tol = tol_opt > 0.0 ? tol_opt : sqrt((double)len) * DBL_EPSILON;
+  double2* acc = tall ? accbuf + sw.acc : nullptr;
+  const double tol = tol_opt > 0.0 ? tol_opt : (double)len * DBL_EPSILON;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   const int np = n + (n & 1);
   if (threadIdx.x == 0) rot_total = 0;
+  // accumulator = identity; squared Frobenius norm of the sector
+  if (tall)
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x)
+      acc[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
+  double fro = 0.0;
+  for (int e = threadIdx.x; e < n * len; e += blockDim.x) {
+    const double2 a = x[e];
+    fro = fma(a.x, a.x, fma(a.y, a.y, fro));
+  }
+  fro = wave_sum(fro);
+  if (lane == 0) wsum[wave] = fro;
+  __syncthreads();
+  fro = 0.0;
+  for (int w = 0; w < nwaves; ++w) fro += wsum[w];
+  // pairs whose inner product is below this are rounding noise of the sector
+  const double floor_g = (double)len * DBL_EPSILON * DBL_EPSILON * fro;
 
   int sweeps = 0;
   bool converged = (n < 2);
@@ -185,6 +224,8 @@ jacobi_rows(const SectorWork* __restrict__ secs, const int* __restrict__ list,
         double2* xi = x + (size_t)i * len;
         double2* xj = x + (size_t)j * len;
         double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+        double c = 1.0, wr = 0.0, wi = 0.0;
+        bool rot = false;
         if constexpr (E > 0) {
           double2 vx[E], vy[E];
 #pragma unroll
@@ -202,29 +243,23 @@ jacobi_rows(const SectorWork* __restrict__ secs, const int* __restrict__ list,
           }
           al = wave_sum(al); be = wave_sum(be); gr = wave_sum(gr); gi = wave_sum(gi);
           const double ag = sqrt(gr * gr + gi * gi);
-          if (ag > tol * sqrt(al) * sqrt(be)) {
+          if (ag > tol * sqrt(al) * sqrt(be) && ag > floor_g) {
             const double zeta = (be - al) / (2.0 * ag);
             const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + tt * tt);
+            c = 1.0 / sqrt(1.0 + tt * tt);
             const double s = c * tt;
-            const double er = gr / ag, ei = gi / ag;
-            const double wr = s * er, wi = s * ei;      // s e
+            wr = s * gr / ag;
+            wi = s * gi / ag;
+            rot = true;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
               const int col = lane + 64 * e;
               if (col < len) {
-                const double2 a = vx[e], b = vy[e];
-                // x' = c a - (s e) b ; y' = conj(s e) a + c b
-                double2 xa, yb;
-                xa.x = c * a.x - (wr * b.x - wi * b.y);
-                xa.y = c * a.y - (wr * b.y + wi * b.x);
-                yb.x = (wr * a.x + wi * a.y) + c * b.x;
-                yb.y = (wr * a.y - wi * a.x) + c * b.y;
-                xi[col] = xa;
-                xj[col] = yb;
+                rot_pair(vx[e], vy[e], c, wr, wi);
+                xi[col] = vx[e];
+                xj[col] = vy[e];
               }
             }
-            ++my_rot;
           }
         } else {
           for (int col = lane; col < len; col += 64) {
@@ -236,24 +271,34 @@ jacobi_rows(const SectorWork* __restrict__ secs, const int* __restrict__ list,
           }
           al = wave_sum(al); be = wave_sum(be); gr = wave_sum(gr); gi = wave_sum(gi);
           const double ag = sqrt(gr * gr + gi * gi);
-          if (ag > tol * sqrt(al) * sqrt(be)) {
+          if (ag > tol * sqrt(al) * sqrt(be) && ag > floor_g) {
             const double zeta = (be - al) / (2.0 * ag);
             const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + tt * tt);
+            c = 1.0 / sqrt(1.0 + tt * tt);
             const double s = c * tt;
-            const double wr = s * gr / ag, wi = s * gi / ag;
+            wr = s * gr / ag;
+            wi = s * gi / ag;
+            rot = true;
             for (int col = lane; col < len; col += 64) {
-              const double2 a = xi[col], b = xj[col];
-              double2 xa, yb;
-              xa.x = c * a.x - (wr * b.x - wi * b.y);
-              xa.y = c * a.y - (wr * b.y + wi * b.x);
-              yb.x = (wr * a.x + wi * a.y) + c * b.x;
-              yb.y = (wr * a.y - wi * a.x) + c * b.y;
-              xi[col] = xa;
-              xj[col] = yb;
+              double2 a = xi[col], b = xj[col];
+              rot_pair(a, b, c, wr, wi);
+              xi[col] = a;
+              xj[col] = b;
             }
-            ++my_rot;
           }
+        }
+        if (rot) {
+          if (tall) {
+            double2* ai = acc + (size_t)i * n;
+            double2* aj = acc + (size_t)j * n;
+            for (int col = lane; col < n; col += 64) {
+              double2 a = ai[col], b = aj[col];
+              rot_pair(a, b, c, wr, wi);
+              ai[col] = a;
+              aj[col] = b;
+            }
+          }
+          ++my_rot;
         }
       }
       __syncthreads();
@@ -267,7 +312,7 @@ jacobi_rows(const SectorWork* __restrict__ secs, const int* __restrict__ list,
     converged = (rotated == 0);
   }
   __syncthreads();
-  // row norms -> singular values; normalise rows (V^dagger rows)
+  // vector norms -> singular values; V^dagger rows into the sector's slot
   for (int i = wave; i < n; i += nwaves) {
     double2* xi = x + (size_t)i * len;
     double ss = 0.0;
@@ -277,7 +322,7 @@ jacobi_rows(const SectorWork* __restrict__ secs, const int* __restrict__ list,
     }
     ss = wave_sum(ss);
     const double nr = sqrt(ss);
-    if (nr > 0.0) {
+    if (!tall && nr > 0.0) {
       const double inv = 1.0 / nr;
       for (int col = lane; col < len; col += 64) {
         const double2 a = xi[col];
@@ -287,7 +332,11 @@ jacobi_rows(const SectorWork* __restrict__ secs, const int* __restrict__ list,
     if (lane == 0) jsm[i] = nr;
   }
   __syncthreads();
-  // order rows by descending value (ties: lower row first)
+  if (tall) {
+    // V^dagger = conj(J): row i of the accumulator, conjugated, stride c = n
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) x[e] = cconj(acc[e]);
+  }
+  // order vectors by descending value (ties: lower index first)
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const double v = jsm[i];
     int rank = 0;
@@ -673,13 +722,13 @@ int jacobi_class(int len) {
 }
 
 hipError_t launch_jacobi(int ecls, const SectorWork* secs, const int* list, int count, int maxrows,
-                         double2* theta, double* sigma, int* order, JacobiOut* stats,
+                         double2* theta, double2* acc, double* sigma, int* order, JacobiOut* stats,
                          int max_sweeps, double tol, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const size_t smem = (size_t)maxrows * sizeof(double);
 #define U1MPS_JAC(EE, NN)                                                                   \
   hipLaunchKernelGGL((jacobi_rows<EE, NN>), dim3(count), dim3(NN), smem, st, secs, list, theta, \
-                     sigma, order, stats, max_sweeps, tol)
+                     acc, sigma, order, stats, max_sweeps, tol)
   // threads per workgroup shrink as the rows held in registers grow
   switch (ecls) {
     case 1: U1MPS_JAC(1, 1024); break;

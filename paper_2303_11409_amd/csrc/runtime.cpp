@@ -113,7 +113,7 @@ struct mps_state {
   std::vector<double*> lam;      // per bond, cap[b] doubles
   std::vector<double2*> site;    // per site, cap[s] * cap[s+1] complex
   // workspaces (grow-only)
-  DevBuf th_raw, th_scaled, sigma, order, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc;
+  DevBuf th_raw, th_scaled, acc, sigma, order, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc;
   PinBuf stage_plan, stage_upd, stage_res, stage_misc;
   mps_stats stats{};
   bool timing = false;
@@ -185,9 +185,11 @@ struct Packer {
     total = align256(total + std::max<size_t>(bytes, 1));
     return off;
   }
+  // Copies the items that have a source; items added with src == nullptr are
+  // device-side outputs and only reserve space.
   void write(void* dst) const {
     for (const Item& it : items)
-      if (it.bytes) std::memcpy(static_cast<char*>(dst) + it.off, it.src, it.bytes);
+      if (it.src && it.bytes) std::memcpy(static_cast<char*>(dst) + it.off, it.src, it.bytes);
   }
 };
 
@@ -338,6 +340,7 @@ struct BatchPlan {
   long long sel_scratch = 0;
   int maxP = 1;
   long long th_elems = 0;
+  long long acc_elems = 0;
   int sig_elems = 0;
   int maxw = 1;
   double theta_flops = 0.0;
@@ -389,6 +392,9 @@ mps_status plan_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s, 
       sw.off = P.th_elems;
       sw.sig = P.sig_elems;
       sw.kmax = std::min(r, c);
+      sw.tall = r > c ? 1 : 0;
+      sw.acc = P.acc_elems;
+      if (sw.tall) P.acc_elems += (long long)c * c;
       secmap[m - mlo] = (int)P.secs.size();
       P.secs.push_back(sw);
       P.th_elems += (long long)r * c;
@@ -462,9 +468,10 @@ mps_status plan_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s, 
     const int begin = (int)P.jlist.size();
     int maxrows = 1;
     for (size_t i = 0; i < P.secs.size(); ++i) {
-      if (jacobi_class(P.secs[i].c) != ec) continue;
+      const SectorWork& sw = P.secs[i];
+      if (jacobi_class(std::max(sw.r, sw.c)) != ec) continue;
       P.jlist.push_back((int)i);
-      maxrows = std::max(maxrows, P.secs[i].r);
+      maxrows = std::max(maxrows, std::min(sw.r, sw.c));
     }
     const int cnt = (int)P.jlist.size() - begin;
     if (cnt) {
@@ -497,6 +504,7 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
   // workspaces
   STCHK(ensure(h, h->th_raw, (size_t)P.th_elems * sizeof(double2)));
   STCHK(ensure(h, h->th_scaled, (size_t)P.th_elems * sizeof(double2)));
+  STCHK(ensure(h, h->acc, (size_t)std::max<long long>(P.acc_elems, 1) * sizeof(double2)));
   STCHK(ensure(h, h->sigma, (size_t)P.sig_elems * sizeof(double)));
   STCHK(ensure(h, h->order, (size_t)P.sig_elems * sizeof(int)));
   if (P.maxP > 4096) {
@@ -539,7 +547,8 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
     Timer tm(h, K_JACOBI0 + ci);
     STCHK(tm.start());
     HIPCHK(launch_jacobi(P.jclass_e[c], d_secs, at<int>(h->plan, o_jlist) + P.jclass_begin[c],
-                         P.jclass_count[c], P.jclass_maxrows[c], scaled, sig, ord,
+                         P.jclass_count[c], P.jclass_maxrows[c], scaled,
+                         static_cast<double2*>(h->acc.p), sig, ord,
                          at<JacobiOut>(h->plan, o_jst), h->opts.max_sweeps, h->opts.jacobi_tol,
                          h->st));
     STCHK(tm.stop());
@@ -569,10 +578,12 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
     h->stats.sectors += 1;
     h->stats.sweeps += jst[s].sweeps;
     h->stats.rotations += jst[s].rotations;
-    const double pairs = double(jst[s].sweeps) * sw.r * (sw.r - 1) / 2.0;
+    const int nv = std::min(sw.r, sw.c), len = std::max(sw.r, sw.c);
+    const double pairs = double(jst[s].sweeps) * nv * (nv - 1) / 2.0;
     h->stats.pairs += (long long)pairs;
-    const double jf = 16.0 * sw.c * pairs + 20.0 * sw.c * jst[s].rotations + 6.0 * sw.c * sw.r;
-    const int ci = class_index(jacobi_class(sw.c));
+    const double jf = 16.0 * len * pairs + 20.0 * (len + (sw.tall ? nv : 0)) * double(jst[s].rotations) +
+                      6.0 * len * nv;
+    const int ci = class_index(jacobi_class(len));
     h->stats.jacobi_flops += jf;
     h->stats.jacobi_class_flops[ci] += jf;
     h->stats.jacobi_class_sectors[ci] += 1;
@@ -679,7 +690,7 @@ mps_status destroy_buffers(mps_state* h) {
   for (double2* p : h->site) dfree(h, p);
   h->lam.clear();
   h->site.clear();
-  DevBuf* bufs[] = {&h->th_raw, &h->th_scaled, &h->sigma, &h->order, &h->plan, &h->upd,
+  DevBuf* bufs[] = {&h->th_raw, &h->th_scaled, &h->acc, &h->sigma, &h->order, &h->plan, &h->upd,
                     &h->norm_e0, &h->norm_e1, &h->norm_t, &h->sel_v, &h->sel_k, &h->misc};
   for (DevBuf* b : bufs) {
     dfree(h, b->p);
