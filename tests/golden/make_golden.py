@@ -1,0 +1,67 @@
+"""Writes the stored oracle results used by the full-size GPU parity test.
+
+Runs ONLY the CPU oracle (oracle/dense_mps.py) on the seeded workload from
+workloads/circuits.py and stores, as JSON text:
+  * the amplitudes of 1024 occupation patterns drawn uniformly (seed 102)
+    plus the input pattern,
+  * <psi|psi> by full contraction,
+  * every bond's right-charge histogram from the oracle's charge audit,
+  * every gate's discarded weight and cut margin,
+  * the Schmidt values of the central bonds.
+
+Usage:  python tests/golden/make_golden.py L32_N16_d4_chi512
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+from oracle import dense_mps  # noqa: E402
+from workloads import circuits  # noqa: E402
+
+WORKLOADS = {
+    "L32_N16_d4_chi512": lambda: circuits.config_plain_gpu(),
+}
+
+
+def main(name: str) -> None:
+    cfg = WORKLOADS[name]()
+    L, d = cfg["L"], cfg["d"]
+    N = sum(cfg["occupation"])
+    m = dense_mps.DenseMPS(cfg["occupation"], d, chi_max=cfg["chi_max"], cutoff=cfg["cutoff"])
+    t0 = time.time()
+    for li, lay in enumerate(cfg["layers"]):
+        for g in lay:
+            m.apply_gate(g.site, g.u)
+        print(f"layer {li + 1}/{len(cfg['layers'])} chi {max(m.bond_dims())} "
+              f"{time.time() - t0:.0f} s", flush=True)
+    pats = circuits.sample_patterns(L, N, d, 1024, 102)
+    pats = np.vstack([pats, np.array(cfg["occupation"], dtype=np.int32)[None, :]])
+    amp = m.amplitudes(pats)
+    out = {
+        "workload": name,
+        "generator": "tests/golden/make_golden.py (oracle/dense_mps.py only)",
+        "L": L, "d": d, "N": N, "chi_max": cfg["chi_max"], "cutoff": cfg["cutoff"],
+        "patterns": pats.tolist(),
+        "amp_re": amp.real.tolist(), "amp_im": amp.imag.tolist(),
+        "norm2": m.norm2(),
+        "bond_charges": [{str(k): v for k, v in m.bond_charges(b).items()} for b in range(L + 1)],
+        "audit_clean": [m.audit_clean(b) for b in range(L + 1)],
+        "discarded": [r.discarded for r in m.records],
+        "margin": [r.margin if np.isfinite(r.margin) else None for r in m.records],
+        "lambda_center": {str(b): m.lam[b].tolist() for b in (L // 2 - 1, L // 2, L // 2 + 1)},
+        "oracle_seconds": time.time() - t0,
+    }
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "L32_N16_d4_chi512")

@@ -210,3 +210,31 @@ def test_vacuum_and_edges(mps_cls):
         m.apply_gate(0, u)
     assert ei.value.status == -6
     m.close()
+
+
+def test_full_32_mode_circuit_vs_stored_oracle(mps_cls):
+    """The whole L=32, N=16, d=4, chi_max=512 circuit (496 gates, the benchmark
+    workload) against the oracle's stored results (tests/golden, written by
+    make_golden.py from oracle/ only): 1025 amplitudes, norm, every bond's charge
+    multiplicities, every gate's discarded weight, central Schmidt values."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "L32_N16_d4_chi512.json")
+    ref = json.load(open(path))
+    cfg = circuits.config_plain_gpu()
+    m, disc = run_gpu(mps_cls, cfg["occupation"], 4, None, chi_max=512, cutoff=1e-12, layered=True,
+                      layers=cfg["layers"])
+    # gates in layer order == stored order (the stored run applied them layer by layer)
+    assert np.max(np.abs(disc - np.array(ref["discarded"]))) <= 1e-12
+    for b in range(33):
+        exp = {int(k): v for k, v in ref["bond_charges"][b].items()}
+        assert m.bond_sectors(b) == exp, b
+    for b, lam in ref["lambda_center"].items():
+        got = np.sort(m.bond_lambda(int(b)))[::-1]
+        lam = np.array(lam)
+        assert got.shape == lam.shape and np.max(np.abs(got - lam)) <= TOL * lam[0]
+    pats = np.array(ref["patterns"], dtype=np.int32)
+    amp = np.array(ref["amp_re"]) + 1j * np.array(ref["amp_im"])
+    close_amps(m.amplitudes(pats), amp)
+    assert abs(m.norm2() - ref["norm2"]) <= 1e-9 * ref["norm2"]
+    m.close()
