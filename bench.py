@@ -27,9 +27,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
-CLASS_NAMES = ["jacobi_rows<0,512>", "jacobi_rows<1,1024>", "jacobi_rows<2,1024>",
-               "jacobi_rows<4,1024>", "jacobi_rows<8,1024>", "jacobi_rows<16,512>",
-               "jacobi_rows<32,256>"]
 METRIC = "gate applies/s + sector-GEMM TFLOP/s at χ=2048 vs plain; p50/p99 latency"
 
 
@@ -135,9 +132,7 @@ def main() -> int:
             agg = st
         else:
             for k, v in st.items():
-                if isinstance(v, list):
-                    agg[k] = [a + b for a, b in zip(agg[k], v)]
-                elif k == "min_margin":
+                if k == "min_margin":
                     agg[k] = min(agg[k], v)
                 elif k == "max_discarded":
                     agg[k] = max(agg[k], v)
@@ -148,17 +143,16 @@ def main() -> int:
     for m in states:
         m.close()
 
-    ci = int(np.argmax(agg["jacobi_class_ms"]))
-    cls_ms = agg["jacobi_class_ms"][ci]
-    cls_launch = max(agg["jacobi_class_launches"][ci], 1)
-    cls_flops = agg["jacobi_class_flops"][ci]
-    per_launch_flops = cls_flops / cls_launch
-    avg_ms = cls_ms / cls_launch
+    # dominant kernel: the blocked Jacobi step (one launch per round-robin step)
+    launches = max(agg["jacobi_launches"], 1)
+    per_launch_flops = agg["jacobi_flops"] / launches
+    avg_ms = agg["jacobi_ms"] / launches
     achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                "kernel": CLASS_NAMES[ci], "avg_launch_ms": avg_ms,
-                "flops_per_launch": per_launch_flops, "launches": cls_launch}
+                "kernel": "jacobi_block_step", "avg_launch_ms": avg_ms,
+                "flops_per_launch": per_launch_flops, "launches": launches}
+    props = torch.cuda.get_device_properties(0)
     value = args.steps * ngates / elapsed
     out = {
         "metric": METRIC,
@@ -184,10 +178,14 @@ def main() -> int:
             "theta_tflops": agg["theta_flops"] / max(agg["theta_ms"], 1e-9) / 1e9,
             "jacobi_tflops": agg["jacobi_flops"] / max(agg["jacobi_ms"], 1e-9) / 1e9,
             "theta_ms": agg["theta_ms"] / args.steps, "jacobi_ms": agg["jacobi_ms"] / args.steps,
+            "jacobi_aux_ms": agg["jacobi_aux_ms"] / args.steps,
             "select_ms": agg["select_ms"] / args.steps, "update_ms": agg["update_ms"] / args.steps,
-            "jacobi_class_ms": [x / args.steps for x in agg["jacobi_class_ms"]],
+            "jacobi_launches_per_step": agg["jacobi_launches"] / args.steps,
             "jacobi_sweeps_per_sector": agg["sweeps"] / max(agg["sectors"], 1),
         },
+        "device": {"name": props.name, "cus": props.multi_processor_count,
+                   "lds_per_block": getattr(props, "shared_memory_per_block", None),
+                   "lds_per_cu": getattr(props, "shared_memory_per_multiprocessor", None)},
         "result": {"norm_loss": norm_loss, "max_bond_dim": max_chi,
                    "max_discarded": agg["max_discarded"], "min_cut_margin": agg["min_margin"]},
     }

@@ -6,7 +6,11 @@
  * indices carry right-charge labels, and reads out amplitudes and norms.
  *
  * What is computed follows Sec. II of "Towards Symmetry-Aware Efficient
- * Simulation of Quantum Systems and Beyond" (arXiv 2303.11409):
+ * Simulation of Quantum Systems and Beyond" (arXiv 2303.11409).  (E1)-(E4)
+ * name the four displayed relations of that section in order: the Vidal-form
+ * amplitude, the U(1) amplitude with Kronecker deltas, the right-charge
+ * definition, and the charge balance with its boundary values.
+ *
  *   - the state is the Vidal-form MPS of Eq. (E1), sites 0..L-1 (the paper's
  *     1..M), bonds 0..L, bond b between site b-1 and site b;
  *   - every bond index alpha carries its right-charge c_b(alpha), the number
@@ -93,28 +97,23 @@ typedef struct {
 /* Per-handle counters, accumulated since creation or mps_reset_stats.
  * *_ms are kernel times from HIP events on the handle's stream; they are
  * filled only while timing is enabled (mps_set_timing).  Flop figures are
- * algorithmic: 8*nL*nM*nR per charge triple for Theta formation, and for the
- * Jacobi kernel (vectors of length len = max(r, c)) 16*len per vector pair
- * inspected, 20*len per rotation applied (plus 20*min(r, c) for the rotation
- * accumulator of a tall sector), 6*len per vector for the final norms. */
+ * algorithmic: 8*nL*nM*nR per charge triple for Theta formation; for the
+ * blocked Jacobi step kernel 8*nv^2*len per block-pair Gram matrix formed and
+ * 8*nv^2*len per block pair rotated (nv vectors of length len = max(r, c);
+ * plus the c x c accumulator of a tall sector); 8*r*c*K per sector for the
+ * update product. */
 typedef struct {
-  long long gates;             /* two-site updates applied                  */
-  long long layers;            /* batched launches (mps_apply_layer calls)  */
-  long long sectors;           /* Theta(m) sectors decomposed               */
-  long long sweeps;            /* Jacobi sweeps summed over sectors         */
-  long long rotations;         /* Jacobi rotations applied                  */
-  long long pairs;             /* Jacobi row pairs inspected                */
+  long long gates;             /* two-site updates applied                    */
+  long long layers;            /* batches (mps_apply_layer calls)             */
+  long long sectors;           /* Theta(m) sectors decomposed                 */
+  long long sweeps;            /* Jacobi sweeps summed over sectors           */
+  long long rotations;         /* Jacobi block pairs rotated                  */
   double theta_flops, jacobi_flops, update_flops;
-  double theta_ms, jacobi_ms, select_ms, update_ms;
-  long long theta_launches, jacobi_launches, select_launches, update_launches;
-  double max_discarded;        /* largest per-gate discarded weight          */
-  double min_margin;           /* smallest (s_{K-1} - s_K)/s_0 at a cut      */
-  /* Jacobi kernel split by row-length class: class i holds rows of length
-   * <= 64 * 2^(i-1) for i = 1..6 (64 .. 2048) and longer rows for i = 0. */
-  double jacobi_class_ms[7];
-  double jacobi_class_flops[7];
-  long long jacobi_class_launches[7];
-  long long jacobi_class_sectors[7];
+  double theta_ms, jacobi_ms, jacobi_aux_ms, select_ms, update_ms;
+  long long theta_launches, jacobi_launches, jacobi_aux_launches, select_launches,
+      update_launches;
+  double max_discarded;        /* largest per-gate discarded weight            */
+  double min_margin;           /* smallest (s_{K-1} - s_K)/s_0 at a cut        */
 } mps_stats;
 
 /* Fill *o with the defaults: chi_max 0, cutoff 0, zero_tol 1e-13,

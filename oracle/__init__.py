@@ -3,7 +3,10 @@
 This package is a plain, slow, obviously-correct complex128 reference written
 from the paper's statement of the method (Sec. II: the Vidal-form MPS of
 Eq. (E1), the right-charge labels and Kronecker deltas of Eqs. (E2)-(E4), and
-the two-site update by SVD with a bond-dimension cap chi).  It deliberately
+the two-site update by SVD with a bond-dimension cap chi).  (E1)-(E4) name the
+four displayed relations of Sec. II in order: the Vidal-form amplitude, the
+U(1) amplitude with Kronecker deltas, the right-charge definition, and the
+charge balance with c = N on the left and 0 on the right.  It deliberately
 uses NO symmetry: the MPS is dense, the two-site matrix is the full
 (chi*d) x (d*chi) matrix and its SVD is LAPACK's.  It shares no code with the
 GPU library and imports nothing from it.

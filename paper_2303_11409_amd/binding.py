@@ -9,9 +9,12 @@ import of this module fails loudly -- there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
-from typing import Dict, Iterable, List, Optional, Sequence
+import sys
+import weakref
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
@@ -48,15 +51,14 @@ class mps_opts(C.Structure):
 
 class mps_stats(C.Structure):
     _fields_ = [("gates", C.c_longlong), ("layers", C.c_longlong), ("sectors", C.c_longlong),
-                ("sweeps", C.c_longlong), ("rotations", C.c_longlong), ("pairs", C.c_longlong),
+                ("sweeps", C.c_longlong), ("rotations", C.c_longlong),
                 ("theta_flops", C.c_double), ("jacobi_flops", C.c_double), ("update_flops", C.c_double),
-                ("theta_ms", C.c_double), ("jacobi_ms", C.c_double), ("select_ms", C.c_double),
-                ("update_ms", C.c_double),
+                ("theta_ms", C.c_double), ("jacobi_ms", C.c_double), ("jacobi_aux_ms", C.c_double),
+                ("select_ms", C.c_double), ("update_ms", C.c_double),
                 ("theta_launches", C.c_longlong), ("jacobi_launches", C.c_longlong),
-                ("select_launches", C.c_longlong), ("update_launches", C.c_longlong),
-                ("max_discarded", C.c_double), ("min_margin", C.c_double),
-                ("jacobi_class_ms", C.c_double * 7), ("jacobi_class_flops", C.c_double * 7),
-                ("jacobi_class_launches", C.c_longlong * 7), ("jacobi_class_sectors", C.c_longlong * 7)]
+                ("jacobi_aux_launches", C.c_longlong), ("select_launches", C.c_longlong),
+                ("update_launches", C.c_longlong),
+                ("max_discarded", C.c_double), ("min_margin", C.c_double)]
 
 
 EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_destroy", "mps_apply_gate",
@@ -69,6 +71,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"u1mps HIP library not built: {path} is missing "
                           "(run __graft_entry__.build())")
+    # PyTorch ships its own HIP runtime with the same SONAME as the system
+    # one.  Loading torch first makes the library bind to that runtime, so the
+    # streams and device memory torch hands over are valid in the library.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P = C.POINTER
     h = C.c_void_p
@@ -115,11 +121,6 @@ def _check(status: int) -> None:
         raise MPSError(status, lib().mps_last_error().decode())
 
 
-def _zarr(u: np.ndarray) -> C.Array:
-    u = np.ascontiguousarray(np.asarray(u, dtype=np.complex128))
-    return np.ctypeslib.as_ctypes(u.view(np.float64).reshape(-1)) if u.size else (C.c_double * 0)()
-
-
 class TorchDevice:
     """Allocator and stream hooks backed by PyTorch's caching allocator."""
 
@@ -140,10 +141,13 @@ class TorchDevice:
             except Exception:      # the library reports MPS_E_NOMEM
                 return None
 
+        delete = torch.cuda.caching_allocator_delete
+
         def _free(ptr, _ctx):
-            if ptr:
+            # at interpreter shutdown the process returns device memory itself
+            if ptr and not sys.is_finalizing():
                 self._live.pop(ptr, None)
-                torch.cuda.caching_allocator_delete(ptr)
+                delete(ptr)
 
         self._alloc_cb = ALLOC_FN(_alloc)
         self._free_cb = FREE_FN(_free)
@@ -155,6 +159,19 @@ class TorchDevice:
         d.ctx = None
         d.stream = C.c_void_p(self.stream.cuda_stream)
         return d
+
+
+_OPEN: "weakref.WeakSet[MPS]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all() -> None:
+    # release handles while torch (their allocator) is still alive
+    for m in list(_OPEN):
+        try:
+            m.close()
+        except Exception:
+            pass
 
 
 class MPS:
@@ -177,6 +194,7 @@ class MPS:
         occ = (C.c_int * self.L)(*[int(x) for x in occupation])
         _check(self._lib.mps_create_product(self.L, d, occ, C.byref(self._opts),
                                             C.byref(self._dev_struct), C.byref(self._h)))
+        _OPEN.add(self)
 
     @classmethod
     def from_vidal(cls, d: int, n_photons: int, bond_charges: List[Sequence[int]],
@@ -201,6 +219,7 @@ class MPS:
         l_ptrs = (C.POINTER(C.c_double) * (L + 1))(*[l.ctypes.data_as(C.POINTER(C.c_double)) for l in l_keep])
         _check(obj._lib.mps_create(L, d, n_photons, c_dims, c_ch, g_ptrs, l_ptrs, C.byref(obj._opts),
                                    C.byref(obj._dev_struct), C.byref(obj._h)))
+        _OPEN.add(obj)
         return obj
 
     # -------------------------------------------------------------- lifetime

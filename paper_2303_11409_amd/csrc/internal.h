@@ -101,12 +101,27 @@ struct CutOut {
   double margin;
 };
 
-// Per-sector Jacobi statistics.
+// Blocked Jacobi: vectors are grouped in blocks of kJB; one round-robin step
+// pairs the nb blocks of a sector into nb/2 block pairs, each handled by one
+// workgroup.
+constexpr int kJB = 16;
+constexpr int kJP = 2 * kJB;
+
+struct JacobiBlockWork {
+  int sector;             // SectorWork index
+  int nb;                 // number of blocks, even (an empty block pads odd counts)
+  int pair_begin;         // flattened index of this sector's first block pair
+};
+
+// Per-sector Jacobi state and statistics.
 struct JacobiOut {
-  int sweeps;
-  int rotations;
+  int sweeps;             // sweeps in which the sector was still active
+  int rotations;          // block pairs rotated, summed over sweeps
   int converged;
-  int pad;
+  int rot_this_sweep;     // block pairs rotated in the current sweep
+  unsigned long long gram_units;    // sum over evaluated pairs of nv^2 * len
+  unsigned long long apply_units;   // sum over rotated pairs of nv^2 * (len + tall accumulator len)
+  double fro2;            // squared Frobenius norm of the sector (rotation invariant)
 };
 
 }  // namespace u1mps

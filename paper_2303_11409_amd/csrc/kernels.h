@@ -10,12 +10,17 @@ hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntile
                         const SectorWork* secs, const double2* coef, double2* raw,
                         double2* scaled, int maxw, hipStream_t st);
 
-// Vector-length class of the Jacobi kernel: E complex per lane per vector, 0 = streaming.
-int jacobi_class(int len);
-// The SVD runs on min(r, c) vectors of length max(r, c); maxrows bounds min(r, c).
-hipError_t launch_jacobi(int ecls, const SectorWork* secs, const int* list, int count, int maxrows,
-                         double2* theta, double2* acc, double* sigma, int* order, JacobiOut* stats,
-                         int max_sweeps, double tol, hipStream_t st);
+// Blocked one-sided Jacobi SVD of every listed sector (vectors: min(r, c)
+// rows or columns of length max(r, c)); st holds per-sector state.
+hipError_t launch_jacobi_init(const SectorWork* secs, const int* list, int count,
+                              const double2* theta, double2* acc, JacobiOut* st, hipStream_t s);
+hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiBlockWork* jb, int njb, int npairs,
+                              int step, double2* theta, double2* acc, JacobiOut* st, double tol,
+                              int max_inner, hipStream_t s);
+hipError_t launch_jacobi_sweep_end(const int* list, int count, JacobiOut* st, int* active, hipStream_t s);
+hipError_t launch_jacobi_finalize(const SectorWork* secs, const int* list, int count, int maxrows,
+                                  double2* theta, const double2* acc, double* sigma, int* order,
+                                  hipStream_t s);
 
 hipError_t launch_select(const GateWork* gates, int ngates, const SectorWork* secs,
                          const double* sigma, double* gsv, int* gsk, const long long* scratch_off,

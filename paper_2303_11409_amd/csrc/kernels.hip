@@ -36,6 +36,14 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// FP64 matrix-core product D[16x16] += A[16x4] B[4x16] on one wavefront.
+// Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; register r of lane
+// l holds D[4 r + l / 16][l % 16].
+typedef double v4d __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v4d mfma16x16x4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 // ---------------------------------------------------------------------------
 // Theta formation.  One workgroup (256 threads, 16 x 16) per 32 x 32 tile of
 // one (cL, cR) pair; each thread owns rows ty, ty+16 and columns tx, tx+16.
@@ -134,24 +142,27 @@ theta_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ t
 }
 
 // ---------------------------------------------------------------------------
-// One-sided (Hestenes) Jacobi SVD of Theta(m), on the min(r, c) vectors of
-// length max(r, c): the rows of Theta when r <= c, else its columns (the
-// theta kernel stores a tall sector transposed).  One workgroup per sector;
-// each wavefront takes whole vector pairs of the current round-robin step
-// (circle method: n' - 1 steps of n'/2 disjoint pairs cover all pairs once),
-// holds both vectors in registers (E complex per lane), forms
-// alpha = |x|^2, beta = |y|^2, gamma = <x, y> with wave reductions, and
-// rotates unless |gamma| <= tol sqrt(alpha beta) or the pair is below the
-// rounding floor of the whole sector:
+// One-sided (Hestenes) Jacobi SVD of Theta(m), blocked.
+//
+// The SVD runs on the min(r, c) vectors of length max(r, c): the rows of
+// Theta when r <= c, else its columns (the theta kernel stores a tall sector
+// transposed).  A vector pair (x, y) with alpha = |x|^2, beta = |y|^2,
+// gamma = <x, y> is made orthogonal by the rotation
 //   zeta = (beta - alpha) / (2|gamma|), t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
-//   c = 1/sqrt(1 + t^2), s = c t, e = gamma/|gamma|,
-//   x' = c x - s e y,  y' = s conj(e) x + c y   (makes <x', y'> = 0).
+//   c = 1/sqrt(1 + t^2), s = c t, w = s gamma/|gamma|,
+//   x' = c x - w y,  y' = conj(w) x + c y,
+// applied while |gamma| > tol sqrt(alpha beta) and |gamma| is above the
+// rounding floor of the sector.  Vectors are grouped in blocks of kJB; a
+// round-robin (circle method) schedule over the blocks pairs every two
+// blocks once per sweep.  For a block pair the workgroup forms the Gram
+// matrix G = X X^H of its 2 kJB vectors, applies the same rotations to G
+// (G <- U G U^H) until its off-diagonal is below tolerance, accumulating
+// W = prod U, and finally rotates the vectors, X <- W X.  Convergence is
+// always judged on a Gram matrix freshly formed from the vectors, so the
+// stopping rule is the same pairwise-cosine test as for the unblocked method.
 // With J the product of all rotations, J X = S Y with orthonormal rows Y:
 //   wide (X = Theta):    V^dagger = Y, the normalised vectors;
 //   tall (X = Theta^T):  V^dagger = conj(J), accumulated in A (c x c) from I.
-// The V^dagger rows are left in the sector's theta_scaled slot (stride c);
-// the singular values (vector norms) and the order that sorts them
-// descending go to sigma/order.  E == 0 streams vectors longer than 64 * 32.
 __device__ __forceinline__ void rr_pair(int step, int k, int np, int& i, int& j) {
   const int q = np - 1;
   if (k == 0) {
@@ -163,8 +174,8 @@ __device__ __forceinline__ void rr_pair(int step, int k, int np, int& i, int& j)
   }
 }
 
+// a' = c a - w b ; b' = conj(w) a + c b, with w = wr + i wi
 __device__ __forceinline__ void rot_pair(double2& a, double2& b, double c, double wr, double wi) {
-  // a' = c a - w b ; b' = conj(w) a + c b, with w = s e
   const double2 x = a, y = b;
   a.x = c * x.x - (wr * y.x - wi * y.y);
   a.y = c * x.y - (wr * y.y + wi * y.x);
@@ -172,147 +183,325 @@ __device__ __forceinline__ void rot_pair(double2& a, double2& b, double c, doubl
   b.y = (wr * x.y - wi * x.x) + c * y.y;
 }
 
-template <int E, int NT>
-__global__ void __launch_bounds__(NT)
-jacobi_rows(const SectorWork* __restrict__ secs, const int* __restrict__ list,
-            double2* __restrict__ theta, double2* __restrict__ accbuf, double* __restrict__ sigma,
-            int* __restrict__ order, JacobiOut* __restrict__ stats, int max_sweeps, double tol_opt) {
-  extern __shared__ double jsm[];          // n doubles: vector norms
-  __shared__ int rotated;
-  __shared__ int rot_total;
-  __shared__ double wsum[NT / 64];
+__device__ __forceinline__ bool jac_rotation(double al, double be, double gr, double gi, double tol,
+                                             double floor_g, double& c, double& wr, double& wi) {
+  const double ag = sqrt(gr * gr + gi * gi);
+  if (!(ag > tol * sqrt(al) * sqrt(be)) || !(ag > floor_g)) return false;
+  const double zeta = (be - al) / (2.0 * ag);
+  const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  c = 1.0 / sqrt(1.0 + tt * tt);
+  const double s = c * tt;
+  wr = s * gr / ag;
+  wi = s * gi / ag;
+  return true;
+}
+
+__device__ __forceinline__ double jac_tol(double tol_opt, int len) {
+  return tol_opt > 0.0 ? tol_opt : (double)len * DBL_EPSILON;
+}
+
+// One workgroup per sector: reset state, squared Frobenius norm, A = I.
+__global__ void __launch_bounds__(256)
+jacobi_init(const SectorWork* __restrict__ secs, const int* __restrict__ list,
+            const double2* __restrict__ theta, double2* __restrict__ accbuf,
+            JacobiOut* __restrict__ st) {
+  __shared__ double wsum[4];
   const int sid = list[blockIdx.x];
   const SectorWork sw = secs[sid];
   const bool tall = sw.tall != 0;
-  const int n = tall ? sw.c : sw.r;        // number of vectors
-  const int len = tall ? sw.r : sw.c;      // vector length
-  double2* x = theta + sw.off;
-  double2* acc = tall ? accbuf + sw.acc : nullptr;
-  const double tol = tol_opt > 0.0 ? tol_opt : (double)len * DBL_EPSILON;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  const int np = n + (n & 1);
-  if (threadIdx.x == 0) rot_total = 0;
-  // accumulator = identity; squared Frobenius norm of the sector
-  if (tall)
+  const int n = tall ? sw.c : sw.r;
+  const int len = tall ? sw.r : sw.c;
+  const double2* x = theta + sw.off;
+  if (tall) {
+    double2* a = accbuf + sw.acc;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x)
-      acc[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
-  double fro = 0.0;
-  for (int e = threadIdx.x; e < n * len; e += blockDim.x) {
-    const double2 a = x[e];
-    fro = fma(a.x, a.x, fma(a.y, a.y, fro));
+      a[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
   }
-  fro = wave_sum(fro);
-  if (lane == 0) wsum[wave] = fro;
+  double f = 0.0;
+  for (int e = threadIdx.x; e < n * len; e += blockDim.x) {
+    const double2 v = x[e];
+    f = fma(v.x, v.x, fma(v.y, v.y, f));
+  }
+  f = wave_sum(f);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = f;
   __syncthreads();
-  fro = 0.0;
-  for (int w = 0; w < nwaves; ++w) fro += wsum[w];
-  // pairs whose inner product is below this are rounding noise of the sector
-  const double floor_g = (double)len * DBL_EPSILON * DBL_EPSILON * fro;
+  if (threadIdx.x == 0) {
+    JacobiOut o;
+    o.sweeps = 0;
+    o.rotations = 0;
+    o.converged = n < 2 ? 1 : 0;
+    o.rot_this_sweep = 0;
+    o.gram_units = 0;
+    o.apply_units = 0;
+    o.fro2 = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    st[sid] = o;
+  }
+}
 
-  int sweeps = 0;
-  bool converged = (n < 2);
-  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+// Load rows rows_of(r) (r < kJP), columns [c0, c0 + 32) of a row-major
+// matrix with row length len into an LDS tile; invalid entries are zero.
+__device__ __forceinline__ void jac_load_chunk(double2 (*xs)[33], const double2* __restrict__ x,
+                                               int len, int c0, int vI, int vJ, int n) {
+  for (int e = threadIdx.x; e < kJP * 32; e += blockDim.x) {
+    const int r = e >> 5, cc = e & 31;
+    const int v = r < kJB ? vI + r : vJ + (r - kJB);
+    const int lim = r < kJB ? min(vI + kJB, n) : min(vJ + kJB, n);
+    const int col = c0 + cc;
+    double2 val = make_double2(0.0, 0.0);
+    if (v < lim && col < len) val = x[(size_t)v * len + col];
+    xs[r][cc] = val;
+  }
+}
+
+// X_IJ <- W X_IJ for one row-major matrix (rows of length len), in column
+// chunks of 32, on the matrix cores: wave w computes the 16 x 16 output
+// quadrant (rows 16 (w / 2), columns 16 (w % 2)) of each chunk as four real
+// products per k-step, Or = Wr Xr - Wi Xi and Oi = Wr Xi + Wi Xr.
+__device__ void jac_apply(double2 (*xs)[33], double2 (*ws)[kJP + 1], double2* __restrict__ x,
+                          int len, int vI, int vJ, int n) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R = (wave >> 1) * 16, Cq = (wave & 1) * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int c0 = 0; c0 < len; c0 += 32) {
+    jac_load_chunk(xs, x, len, c0, vI, vJ, n);
     __syncthreads();
-    if (threadIdx.x == 0) rotated = 0;
+    v4d orr = {0.0, 0.0, 0.0, 0.0}, oi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < kJP; k0 += 4) {
+      const double2 wv = ws[R + li][k0 + lk];      // A = W[R + i][k]
+      const double2 xv = xs[k0 + lk][Cq + li];     // B = X[k][C + j]
+      orr = mfma16x16x4(wv.x, xv.x, orr);
+      orr = mfma16x16x4(-wv.y, xv.y, orr);
+      oi = mfma16x16x4(wv.x, xv.y, oi);
+      oi = mfma16x16x4(wv.y, xv.x, oi);
+    }
     __syncthreads();
-    int my_rot = 0;
-    for (int step = 0; step < np - 1; ++step) {
-      for (int k = wave; k < np / 2; k += nwaves) {
-        int i, j;
-        rr_pair(step, k, np, i, j);
-        if (i >= n || j >= n) continue;
-        double2* xi = x + (size_t)i * len;
-        double2* xj = x + (size_t)j * len;
-        double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = R + 4 * r + lk;
+      const int v = row < kJB ? vI + row : vJ + (row - kJB);
+      const int lim = row < kJB ? min(vI + kJB, n) : min(vJ + kJB, n);
+      const int col = c0 + Cq + li;
+      if (v < lim && col < len) x[(size_t)v * len + col] = make_double2(orr[r], oi[r]);
+    }
+  }
+}
+
+// Rotations of the Gram matrix gs (in LDS) until no pair exceeds the
+// threshold; W accumulates the product.  Returns true if any rotation was made.
+__device__ bool jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], double* rc, double* rwr,
+                             double* rwi, int* rflag, int* anyrot, double tol, double floor_g,
+                             int max_inner) {
+  const int tid = threadIdx.x;
+  bool any_total = false;
+  for (int inner = 0; inner < max_inner; ++inner) {
+    __syncthreads();
+    if (tid == 0) *anyrot = 0;
+    __syncthreads();
+    for (int s2 = 0; s2 < kJP - 1; ++s2) {
+      if (tid < kJP / 2) {
+        int p, q;
+        rr_pair(s2, tid, kJP, p, q);
         double c = 1.0, wr = 0.0, wi = 0.0;
-        bool rot = false;
-        if constexpr (E > 0) {
-          double2 vx[E], vy[E];
-#pragma unroll
-          for (int e = 0; e < E; ++e) {
-            const int col = lane + 64 * e;
-            vx[e] = col < len ? xi[col] : make_double2(0.0, 0.0);
-            vy[e] = col < len ? xj[col] : make_double2(0.0, 0.0);
-          }
-#pragma unroll
-          for (int e = 0; e < E; ++e) {
-            al = fma(vx[e].x, vx[e].x, fma(vx[e].y, vx[e].y, al));
-            be = fma(vy[e].x, vy[e].x, fma(vy[e].y, vy[e].y, be));
-            gr = fma(vx[e].x, vy[e].x, fma(vx[e].y, vy[e].y, gr));
-            gi = fma(vx[e].y, vy[e].x, fma(-vx[e].x, vy[e].y, gi));
-          }
-          al = wave_sum(al); be = wave_sum(be); gr = wave_sum(gr); gi = wave_sum(gi);
-          const double ag = sqrt(gr * gr + gi * gi);
-          if (ag > tol * sqrt(al) * sqrt(be) && ag > floor_g) {
-            const double zeta = (be - al) / (2.0 * ag);
-            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            const double s = c * tt;
-            wr = s * gr / ag;
-            wi = s * gi / ag;
-            rot = true;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-              const int col = lane + 64 * e;
-              if (col < len) {
-                rot_pair(vx[e], vy[e], c, wr, wi);
-                xi[col] = vx[e];
-                xj[col] = vy[e];
-              }
-            }
-          }
-        } else {
-          for (int col = lane; col < len; col += 64) {
-            const double2 a = xi[col], b = xj[col];
-            al = fma(a.x, a.x, fma(a.y, a.y, al));
-            be = fma(b.x, b.x, fma(b.y, b.y, be));
-            gr = fma(a.x, b.x, fma(a.y, b.y, gr));
-            gi = fma(a.y, b.x, fma(-a.x, b.y, gi));
-          }
-          al = wave_sum(al); be = wave_sum(be); gr = wave_sum(gr); gi = wave_sum(gi);
-          const double ag = sqrt(gr * gr + gi * gi);
-          if (ag > tol * sqrt(al) * sqrt(be) && ag > floor_g) {
-            const double zeta = (be - al) / (2.0 * ag);
-            const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            c = 1.0 / sqrt(1.0 + tt * tt);
-            const double s = c * tt;
-            wr = s * gr / ag;
-            wi = s * gi / ag;
-            rot = true;
-            for (int col = lane; col < len; col += 64) {
-              double2 a = xi[col], b = xj[col];
-              rot_pair(a, b, c, wr, wi);
-              xi[col] = a;
-              xj[col] = b;
-            }
-          }
-        }
-        if (rot) {
-          if (tall) {
-            double2* ai = acc + (size_t)i * n;
-            double2* aj = acc + (size_t)j * n;
-            for (int col = lane; col < n; col += 64) {
-              double2 a = ai[col], b = aj[col];
-              rot_pair(a, b, c, wr, wi);
-              ai[col] = a;
-              aj[col] = b;
-            }
-          }
-          ++my_rot;
-        }
+        const double2 gpq = gs[p][q];
+        const bool r = jac_rotation(gs[p][p].x, gs[q][q].x, gpq.x, gpq.y, tol, floor_g, c, wr, wi);
+        rflag[tid] = r ? 1 : 0;
+        rc[tid] = c;
+        rwr[tid] = wr;
+        rwi[tid] = wi;
+        if (r) *anyrot = 1;
+      }
+      __syncthreads();
+      // rows of G and W: U acts from the left
+      for (int it = tid; it < (kJP / 2) * kJP; it += blockDim.x) {
+        const int pr = it / kJP, col = it % kJP;
+        if (!rflag[pr]) continue;
+        int p, q;
+        rr_pair(s2, pr, kJP, p, q);
+        rot_pair(gs[p][col], gs[q][col], rc[pr], rwr[pr], rwi[pr]);
+        rot_pair(ws[p][col], ws[q][col], rc[pr], rwr[pr], rwi[pr]);
+      }
+      __syncthreads();
+      // columns of G: U^H acts from the right (the conjugate coefficient)
+      for (int it = tid; it < (kJP / 2) * kJP; it += blockDim.x) {
+        const int pr = it / kJP, row = it % kJP;
+        if (!rflag[pr]) continue;
+        int p, q;
+        rr_pair(s2, pr, kJP, p, q);
+        rot_pair(gs[row][p], gs[row][q], rc[pr], rwr[pr], -rwi[pr]);
       }
       __syncthreads();
     }
-    if (lane == 0 && my_rot) {
-      atomicAdd(&rotated, 1);
-      atomicAdd(&rot_total, my_rot);
-    }
-    __syncthreads();
-    ++sweeps;
-    converged = (rotated == 0);
+    const bool a = *anyrot != 0;
+    any_total = any_total || a;
+    if (!a) break;
   }
   __syncthreads();
-  // vector norms -> singular values; V^dagger rows into the sector's slot
+  return any_total;
+}
+
+// One round-robin step for every active sector: one workgroup per block pair.
+//
+// A block pair that fails the convergence test is rotated in two passes.
+// Pass 0 diagonalises its Gram matrix only down to kJacLoose relative
+// off-diagonal or the Gram's own rounding level (kJacNoise * eps * max
+// diagonal): rotations of G itself carry errors of order eps * max|G|, which
+// would leave the smallest vectors of the pair with cosines of
+// eps * s_max^2 / (s_p s_q) if pursued further.  Pass 1 forms the Gram matrix
+// afresh from the rotated vectors; it is then nearly diagonal, its rotations
+// are small, their errors are relative to each vector's own norm, and it is
+// driven to the full tolerance.
+constexpr double kJacLoose = 1e-8;
+constexpr double kJacNoise = 64.0;
+
+__global__ void __launch_bounds__(256)
+jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __restrict__ jb,
+                  int njb, int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
+                  JacobiOut* __restrict__ st, double tol_opt, int max_inner) {
+  __shared__ double2 xs[kJP][33];
+  __shared__ double2 gs[kJP][kJP + 1];
+  __shared__ double2 ws[kJP][kJP + 1];
+  __shared__ double rc[kJP / 2], rwr[kJP / 2], rwi[kJP / 2];
+  __shared__ int rflag[kJP / 2];
+  __shared__ int need, anyrot;
+  __shared__ double gmax;
+  int lo = 0, hi = njb - 1;
+  const int pid = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jb[mid].pair_begin <= pid) lo = mid; else hi = mid - 1;
+  }
+  const JacobiBlockWork w = jb[lo];
+  if (step >= w.nb - 1) return;
+  const int sid = w.sector;
+  if (st[sid].converged) return;
+  const SectorWork sw = secs[sid];
+  const bool tall = sw.tall != 0;
+  const int n = tall ? sw.c : sw.r;
+  const int len = tall ? sw.r : sw.c;
+  double2* x = theta + sw.off;
+  const double tol = jac_tol(tol_opt, len);
+  const double floor_g = (double)len * DBL_EPSILON * DBL_EPSILON * st[sid].fro2;
+  int bi, bj;
+  rr_pair(step, pid - w.pair_begin, w.nb, bi, bj);
+  const int vI = bi * kJB, vJ = bj * kJB;
+  const int nI = max(0, min(kJB, n - vI)), nJ = max(0, min(kJB, n - vJ));
+  const int nv = nI + nJ;
+  const int tid = threadIdx.x;
+  // a block paired with the empty padding block still orthogonalises its own vectors
+  if (nv < 2) return;
+  const int p0 = 2 * (tid >> 4), q0 = 2 * (tid & 15);
+  bool fresh = false;          // gs holds the Gram matrix of the current vectors
+  for (int pass = 0; pass < 2; ++pass) {
+    if (!fresh) {
+      // ---- Gram matrix G = X X^H on the matrix cores: wave w forms quadrant
+      // (P, Q) = (16 (w / 2), 16 (w % 2)); Gr = Xr Xr^T + Xi Xi^T,
+      // Gi = Xi Xr^T - Xr Xi^T over k-steps of 4 columns.
+      const int lane = tid & 63, wave = tid >> 6;
+      const int P = (wave >> 1) * 16, Q = (wave & 1) * 16;
+      const int li = lane & 15, lk = lane >> 4;
+      v4d grr = {0.0, 0.0, 0.0, 0.0}, gii = {0.0, 0.0, 0.0, 0.0};
+      for (int c0 = 0; c0 < len; c0 += 32) {
+        jac_load_chunk(xs, x, len, c0, vI, vJ, n);
+        __syncthreads();
+#pragma unroll
+        for (int k0 = 0; k0 < 32; k0 += 4) {
+          const double2 av = xs[P + li][k0 + lk];     // A = X[P + i][k]
+          const double2 bv = xs[Q + li][k0 + lk];     // B = X[Q + j][k] (transposed)
+          grr = mfma16x16x4(av.x, bv.x, grr);
+          grr = mfma16x16x4(av.y, bv.y, grr);
+          gii = mfma16x16x4(av.y, bv.x, gii);
+          gii = mfma16x16x4(-av.x, bv.y, gii);
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gs[P + 4 * r + lk][Q + li] = make_double2(grr[r], gii[r]);
+      if (tid == 0) atomicAdd(&st[sid].gram_units, (unsigned long long)nv * nv * len);
+    }
+    if (tid == 0) need = 0;
+    __syncthreads();
+    // ---- any pair above tolerance?
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int p = p0 + i, q = q0 + j;
+        if (p < q) {
+          double c, wr, wi;
+          const double2 gpq = gs[p][q];
+          if (jac_rotation(gs[p][p].x, gs[q][q].x, gpq.x, gpq.y, tol, floor_g, c, wr, wi))
+            atomicOr(&need, 1);
+        }
+      }
+    if (tid == 0) {
+      double m = 0.0;
+      for (int r = 0; r < kJP; ++r) m = fmax(m, gs[r][r].x);
+      gmax = m;
+    }
+    __syncthreads();
+    if (!need) break;
+    if (pass == 0 && tid == 0) atomicAdd(&st[sid].rot_this_sweep, 1);
+    // ---- diagonalise G by rotations, W = accumulated product
+    for (int e = tid; e < kJP * kJP; e += blockDim.x) {
+      const int r = e / kJP, c = e % kJP;
+      ws[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    }
+    const double ptol = pass == 0 ? fmax(tol, kJacLoose) : tol;
+    const double pfloor = pass == 0 ? fmax(floor_g, kJacNoise * DBL_EPSILON * gmax) : floor_g;
+    const bool rotated = jac_gram_eig(gs, ws, rc, rwr, rwi, rflag, &anyrot, ptol, pfloor, max_inner);
+    if (!rotated) {
+      // nothing above the coarse thresholds: gs is still the Gram matrix of
+      // the unchanged vectors, go straight to the full-tolerance pass
+      fresh = true;
+      continue;
+    }
+    // ---- rotate the vectors (and the accumulator of a tall sector)
+    jac_apply(xs, ws, x, len, vI, vJ, n);
+    if (tall) jac_apply(xs, ws, accbuf + sw.acc, n, vI, vJ, n);
+    if (tid == 0) atomicAdd(&st[sid].apply_units, (unsigned long long)nv * nv * (len + (tall ? n : 0)));
+    fresh = false;
+    __syncthreads();
+  }
+}
+
+// After a sweep: a sector with no rotated block pair is converged.  One
+// workgroup; *active receives 1 if any sector still rotates.
+__global__ void __launch_bounds__(1024)
+jacobi_sweep_end(const int* __restrict__ list, int count, JacobiOut* __restrict__ st,
+                 int* __restrict__ active) {
+  __shared__ int act;
+  if (threadIdx.x == 0) act = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    const int s = list[i];
+    JacobiOut o = st[s];
+    if (o.converged) continue;
+    o.sweeps += 1;
+    o.rotations += o.rot_this_sweep;
+    if (o.rot_this_sweep == 0) o.converged = 1;
+    else atomicOr(&act, 1);
+    o.rot_this_sweep = 0;
+    st[s] = o;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *active = act;
+}
+
+// One workgroup per sector: vector norms -> singular values, V^dagger rows
+// into the sector's slot (stride c), order by descending value.
+__global__ void __launch_bounds__(256)
+jacobi_finalize(const SectorWork* __restrict__ secs, const int* __restrict__ list,
+                double2* __restrict__ theta, const double2* __restrict__ accbuf,
+                double* __restrict__ sigma, int* __restrict__ order) {
+  extern __shared__ double jsm[];          // n doubles
+  const int sid = list[blockIdx.x];
+  const SectorWork sw = secs[sid];
+  const bool tall = sw.tall != 0;
+  const int n = tall ? sw.c : sw.r;
+  const int len = tall ? sw.r : sw.c;
+  double2* x = theta + sw.off;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
   for (int i = wave; i < n; i += nwaves) {
     double2* xi = x + (size_t)i * len;
     double ss = 0.0;
@@ -333,10 +522,9 @@ jacobi_rows(const SectorWork* __restrict__ secs, const int* __restrict__ list,
   }
   __syncthreads();
   if (tall) {
-    // V^dagger = conj(J): row i of the accumulator, conjugated, stride c = n
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) x[e] = cconj(acc[e]);
+    const double2* a = accbuf + sw.acc;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) x[e] = cconj(a[e]);
   }
-  // order vectors by descending value (ties: lower index first)
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const double v = jsm[i];
     int rank = 0;
@@ -346,14 +534,6 @@ jacobi_rows(const SectorWork* __restrict__ secs, const int* __restrict__ list,
     }
     sigma[sw.sig + rank] = v;
     order[sw.sig + rank] = i;
-  }
-  if (threadIdx.x == 0) {
-    JacobiOut o;
-    o.sweeps = sweeps;
-    o.rotations = rot_total;
-    o.converged = converged ? 1 : 0;
-    o.pad = 0;
-    stats[sid] = o;
   }
 }
 
@@ -711,35 +891,33 @@ hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntile
   return hipGetLastError();
 }
 
-int jacobi_class(int len) {
-  if (len <= 64) return 1;
-  if (len <= 128) return 2;
-  if (len <= 256) return 4;
-  if (len <= 512) return 8;
-  if (len <= 1024) return 16;
-  if (len <= 2048) return 32;
-  return 0;
+hipError_t launch_jacobi_init(const SectorWork* secs, const int* list, int count,
+                              const double2* theta, double2* acc, JacobiOut* st, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_init, dim3(count), dim3(256), 0, s, secs, list, theta, acc, st);
+  return hipGetLastError();
 }
 
-hipError_t launch_jacobi(int ecls, const SectorWork* secs, const int* list, int count, int maxrows,
-                         double2* theta, double2* acc, double* sigma, int* order, JacobiOut* stats,
-                         int max_sweeps, double tol, hipStream_t st) {
+hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiBlockWork* jb, int njb, int npairs,
+                              int step, double2* theta, double2* acc, JacobiOut* st, double tol,
+                              int max_inner, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_block_step, dim3(npairs), dim3(256), 0, s, secs, jb, njb, step, theta, acc,
+                     st, tol, max_inner);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_sweep_end(const int* list, int count, JacobiOut* st, int* active, hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_sweep_end, dim3(1), dim3(1024), 0, s, list, count, st, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_finalize(const SectorWork* secs, const int* list, int count, int maxrows,
+                                  double2* theta, const double2* acc, double* sigma, int* order,
+                                  hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const size_t smem = (size_t)maxrows * sizeof(double);
-#define U1MPS_JAC(EE, NN)                                                                   \
-  hipLaunchKernelGGL((jacobi_rows<EE, NN>), dim3(count), dim3(NN), smem, st, secs, list, theta, \
-                     acc, sigma, order, stats, max_sweeps, tol)
-  // threads per workgroup shrink as the rows held in registers grow
-  switch (ecls) {
-    case 1: U1MPS_JAC(1, 1024); break;
-    case 2: U1MPS_JAC(2, 1024); break;
-    case 4: U1MPS_JAC(4, 1024); break;
-    case 8: U1MPS_JAC(8, 1024); break;
-    case 16: U1MPS_JAC(16, 512); break;
-    case 32: U1MPS_JAC(32, 256); break;
-    default: U1MPS_JAC(0, 512); break;
-  }
-#undef U1MPS_JAC
+  hipLaunchKernelGGL(jacobi_finalize, dim3(count), dim3(256), smem, s, secs, list, theta, acc, sigma, order);
   return hipGetLastError();
 }
 

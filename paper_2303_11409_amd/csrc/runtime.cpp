@@ -79,20 +79,7 @@ struct PinBuf {
   size_t cap = 0;
 };
 
-enum Kind { K_THETA = 0, K_SELECT, K_UPDATE, K_JACOBI0 };   // K_JACOBI0 + class index
-
-// Index of a Jacobi row-length class (E complex per lane) in the stats arrays.
-int class_index(int e) {
-  switch (e) {
-    case 1: return 1;
-    case 2: return 2;
-    case 4: return 3;
-    case 8: return 4;
-    case 16: return 5;
-    case 32: return 6;
-    default: return 0;
-  }
-}
+enum Kind { K_THETA = 0, K_SELECT, K_UPDATE, K_JACOBI, K_JACOBI_AUX };
 
 struct Pending {
   int kind;
@@ -100,6 +87,9 @@ struct Pending {
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Rotation sweeps over a block pair's Gram matrix before the block is rotated.
+constexpr int kMaxInnerSweeps = 12;
 
 }  // namespace
 
@@ -114,7 +104,7 @@ struct mps_state {
   std::vector<double2*> site;    // per site, cap[s] * cap[s+1] complex
   // workspaces (grow-only)
   DevBuf th_raw, th_scaled, acc, sigma, order, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc;
-  PinBuf stage_plan, stage_upd, stage_res, stage_misc;
+  PinBuf stage_plan, stage_upd, stage_res, stage_misc, stage_flag;
   mps_stats stats{};
   bool timing = false;
   std::vector<Pending> pending;
@@ -237,15 +227,12 @@ mps_status drain_events(mps_state* h) {
   for (const Pending& p : h->pending) {
     float ms = 0.f;
     HIPCHK(hipEventElapsedTime(&ms, p.a, p.b));
-    if (p.kind >= K_JACOBI0) {
-      h->stats.jacobi_ms += ms;
-      h->stats.jacobi_class_ms[p.kind - K_JACOBI0] += ms;
-    } else if (p.kind == K_THETA) {
-      h->stats.theta_ms += ms;
-    } else if (p.kind == K_SELECT) {
-      h->stats.select_ms += ms;
-    } else {
-      h->stats.update_ms += ms;
+    switch (p.kind) {
+      case K_THETA: h->stats.theta_ms += ms; break;
+      case K_SELECT: h->stats.select_ms += ms; break;
+      case K_JACOBI: h->stats.jacobi_ms += ms; break;
+      case K_JACOBI_AUX: h->stats.jacobi_aux_ms += ms; break;
+      default: h->stats.update_ms += ms; break;
     }
     h->pool.push_back(p.a);
     h->pool.push_back(p.b);
@@ -334,8 +321,9 @@ struct BatchPlan {
   std::vector<ThetaTile> tiles;
   std::vector<double2> coef;
   std::vector<GatePlan> gp;
-  std::vector<int> jlist;                 // sector ids grouped by Jacobi class
-  std::vector<int> jclass_begin, jclass_count, jclass_maxrows, jclass_e;
+  std::vector<int> jlist;                 // every sector id
+  std::vector<JacobiBlockWork> jblocks;   // block schedule per sector
+  int jpairs = 0, jmaxnb = 2, jmaxrows = 1;
   std::vector<long long> sel_off;         // global sort scratch offsets
   long long sel_scratch = 0;
   int maxP = 1;
@@ -462,24 +450,18 @@ mps_status plan_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s, 
     P.gates[g] = gw;
     P.gp[g] = {s, gw.sec_begin, gw.sec_end};
   }
-  // Jacobi classes
-  const int classes[] = {1, 2, 4, 8, 16, 32, 0};
-  for (int ec : classes) {
-    const int begin = (int)P.jlist.size();
-    int maxrows = 1;
-    for (size_t i = 0; i < P.secs.size(); ++i) {
-      const SectorWork& sw = P.secs[i];
-      if (jacobi_class(std::max(sw.r, sw.c)) != ec) continue;
-      P.jlist.push_back((int)i);
-      maxrows = std::max(maxrows, std::min(sw.r, sw.c));
-    }
-    const int cnt = (int)P.jlist.size() - begin;
-    if (cnt) {
-      P.jclass_begin.push_back(begin);
-      P.jclass_count.push_back(cnt);
-      P.jclass_maxrows.push_back(maxrows);
-      P.jclass_e.push_back(ec);
-    }
+  // blocked Jacobi schedule: min(r, c) vectors in blocks of kJB, block count even
+  for (size_t i = 0; i < P.secs.size(); ++i) {
+    const SectorWork& sw = P.secs[i];
+    const int nv = std::min(sw.r, sw.c);
+    int nb = (nv + kJB - 1) / kJB;
+    nb += nb & 1;
+    nb = std::max(nb, 2);
+    P.jlist.push_back((int)i);
+    P.jblocks.push_back({(int)i, nb, P.jpairs});
+    P.jpairs += nb / 2;
+    P.jmaxnb = std::max(P.jmaxnb, nb);
+    P.jmaxrows = std::max(P.jmaxrows, nv);
   }
   return MPS_OK;
 }
@@ -487,9 +469,8 @@ mps_status plan_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s, 
 bool valid_handle(mps_t h) { return h != nullptr && h->L > 0; }
 
 mps_status check_device_limits(mps_state* h, const BatchPlan& P) {
-  for (size_t i = 0; i < P.jclass_maxrows.size(); ++i)
-    if ((size_t)P.jclass_maxrows[i] * sizeof(double) > 64 * 1024)
-      return fail(MPS_E_ARG, "sector with %d rows exceeds the Jacobi kernel's LDS budget", P.jclass_maxrows[i]);
+  if ((size_t)P.jmaxrows * sizeof(double) > 64 * 1024)
+    return fail(MPS_E_ARG, "sector with %d vectors exceeds the Jacobi finalize LDS budget", P.jmaxrows);
   (void)h;
   return MPS_OK;
 }
@@ -518,10 +499,12 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
   const size_t o_tiles = pk.add(P.tiles.data(), P.tiles.size() * sizeof(ThetaTile));
   const size_t o_coef = pk.add(P.coef.data(), P.coef.size() * sizeof(double2));
   const size_t o_jlist = pk.add(P.jlist.data(), P.jlist.size() * sizeof(int));
+  const size_t o_jblk = pk.add(P.jblocks.data(), P.jblocks.size() * sizeof(JacobiBlockWork));
   const size_t o_seloff = pk.add(P.sel_off.data(), P.sel_off.size() * sizeof(long long));
   const size_t o_kept = pk.add(nullptr, (size_t)ns * sizeof(int));
   const size_t o_cut = pk.add(nullptr, (size_t)ng * sizeof(CutOut));
   const size_t o_jst = pk.add(nullptr, (size_t)ns * sizeof(JacobiOut));
+  const size_t o_active = pk.add(nullptr, sizeof(int));
   const size_t upload = o_kept;  // everything before the outputs is uploaded
   STCHK(ensure(h, h->plan, pk.total));
   STCHK(ensure_pin(h->stage_plan, upload));
@@ -542,17 +525,41 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
                         at<double2>(h->plan, o_coef), raw, scaled, P.maxw, h->st));
     STCHK(tm.stop());
   }
-  for (size_t c = 0; c < P.jclass_e.size(); ++c) {
-    const int ci = class_index(P.jclass_e[c]);
-    Timer tm(h, K_JACOBI0 + ci);
-    STCHK(tm.start());
-    HIPCHK(launch_jacobi(P.jclass_e[c], d_secs, at<int>(h->plan, o_jlist) + P.jclass_begin[c],
-                         P.jclass_count[c], P.jclass_maxrows[c], scaled,
-                         static_cast<double2*>(h->acc.p), sig, ord,
-                         at<JacobiOut>(h->plan, o_jst), h->opts.max_sweeps, h->opts.jacobi_tol,
-                         h->st));
-    STCHK(tm.stop());
-    h->stats.jacobi_class_launches[ci] += 1;
+  {
+    JacobiOut* d_jst = at<JacobiOut>(h->plan, o_jst);
+    const int* d_jlist = at<int>(h->plan, o_jlist);
+    double2* d_acc = static_cast<double2*>(h->acc.p);
+    int* d_active = at<int>(h->plan, o_active);
+    STCHK(ensure_pin(h->stage_flag, sizeof(int)));
+    {
+      Timer tm(h, K_JACOBI_AUX);
+      STCHK(tm.start());
+      HIPCHK(launch_jacobi_init(d_secs, d_jlist, ns, scaled, d_acc, d_jst, h->st));
+      STCHK(tm.stop());
+      h->stats.jacobi_aux_launches += 1;
+    }
+    for (int sweep = 0; sweep < h->opts.max_sweeps; ++sweep) {
+      Timer tm(h, K_JACOBI);
+      STCHK(tm.start());
+      for (int step = 0; step < P.jmaxnb - 1; ++step)
+        HIPCHK(launch_jacobi_step(d_secs, at<JacobiBlockWork>(h->plan, o_jblk), ns, P.jpairs, step, scaled,
+                                  d_acc, d_jst, h->opts.jacobi_tol, kMaxInnerSweeps, h->st));
+      STCHK(tm.stop());
+      h->stats.jacobi_launches += P.jmaxnb - 1;
+      Timer ta(h, K_JACOBI_AUX);
+      STCHK(ta.start());
+      HIPCHK(launch_jacobi_sweep_end(d_jlist, ns, d_jst, d_active, h->st));
+      STCHK(ta.stop());
+      h->stats.jacobi_aux_launches += 1;
+      HIPCHK(hipMemcpyAsync(h->stage_flag.p, d_active, sizeof(int), hipMemcpyDeviceToHost, h->st));
+      HIPCHK(hipStreamSynchronize(h->st));
+      if (*static_cast<volatile int*>(h->stage_flag.p) == 0) break;
+    }
+    Timer tf(h, K_JACOBI_AUX);
+    STCHK(tf.start());
+    HIPCHK(launch_jacobi_finalize(d_secs, d_jlist, ns, P.jmaxrows, scaled, d_acc, sig, ord, h->st));
+    STCHK(tf.stop());
+    h->stats.jacobi_aux_launches += 1;
   }
   {
     Timer tm(h, K_SELECT);
@@ -578,15 +585,7 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
     h->stats.sectors += 1;
     h->stats.sweeps += jst[s].sweeps;
     h->stats.rotations += jst[s].rotations;
-    const int nv = std::min(sw.r, sw.c), len = std::max(sw.r, sw.c);
-    const double pairs = double(jst[s].sweeps) * nv * (nv - 1) / 2.0;
-    h->stats.pairs += (long long)pairs;
-    const double jf = 16.0 * len * pairs + 20.0 * (len + (sw.tall ? nv : 0)) * double(jst[s].rotations) +
-                      6.0 * len * nv;
-    const int ci = class_index(jacobi_class(len));
-    h->stats.jacobi_flops += jf;
-    h->stats.jacobi_class_flops[ci] += jf;
-    h->stats.jacobi_class_sectors[ci] += 1;
+    h->stats.jacobi_flops += 8.0 * double(jst[s].gram_units) + 8.0 * double(jst[s].apply_units);
     if (!jst[s].converged)
       return fail(MPS_E_NOCONV, "Jacobi SVD of sector m=%d (%dx%d) did not converge in %d sweeps",
                   sw.m, sw.r, sw.c, h->opts.max_sweeps);
@@ -678,7 +677,6 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
   h->stats.gates += ng;
   h->stats.layers += 1;
   h->stats.theta_launches += 1;
-  h->stats.jacobi_launches += (long long)P.jclass_e.size();
   h->stats.select_launches += 1;
   h->stats.update_launches += 3;
   return MPS_OK;
@@ -697,7 +695,7 @@ mps_status destroy_buffers(mps_state* h) {
     b->p = nullptr;
     b->cap = 0;
   }
-  PinBuf* pins[] = {&h->stage_plan, &h->stage_upd, &h->stage_res, &h->stage_misc};
+  PinBuf* pins[] = {&h->stage_plan, &h->stage_upd, &h->stage_res, &h->stage_misc, &h->stage_flag};
   for (PinBuf* b : pins) {
     if (b->p) (void)hipHostFree(b->p);
     b->p = nullptr;
