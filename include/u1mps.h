@@ -81,10 +81,12 @@ typedef struct {
  *              of all sectors of one two-site update; 0 disables it.
  *   zero_tol   singular values <= zero_tol * s_max are dropped as numerical
  *              zeros (default 1e-13).
- *   max_sweeps Jacobi sweep limit per sector (default 40).
+ *   max_sweeps Jacobi sweep limit per sector (default 40): blocked sweeps
+ *              first (at most 24), then scalar sweeps on the vectors of any
+ *              sector still rotating.
  *   jacobi_tol rotate a vector pair while |<x,y>| > tol * |x| |y|; <= 0
- *              means (vector length) * 2^-52.  The SVD of an r x c sector
- *              orthogonalises its min(r, c) rows or columns.
+ *              means max(vector length, 64) * 2^-52.  The SVD of an r x c
+ *              sector orthogonalises its min(r, c) rows or columns.
  * The kept count is K = max(1, min(chi_max, K_eps, K_zero)). */
 typedef struct {
   int chi_max;
@@ -112,6 +114,7 @@ typedef struct {
   double theta_ms, jacobi_ms, jacobi_aux_ms, select_ms, update_ms;
   long long theta_launches, jacobi_launches, jacobi_aux_launches, select_launches,
       update_launches;
+  long long polish_launches;   /* batches that needed the scalar Jacobi finish */
   double max_discarded;        /* largest per-gate discarded weight            */
   double min_margin;           /* smallest (s_{K-1} - s_K)/s_0 at a cut        */
 } mps_stats;

@@ -57,7 +57,7 @@ class mps_stats(C.Structure):
                 ("select_ms", C.c_double), ("update_ms", C.c_double),
                 ("theta_launches", C.c_longlong), ("jacobi_launches", C.c_longlong),
                 ("jacobi_aux_launches", C.c_longlong), ("select_launches", C.c_longlong),
-                ("update_launches", C.c_longlong),
+                ("update_launches", C.c_longlong), ("polish_launches", C.c_longlong),
                 ("max_discarded", C.c_double), ("min_margin", C.c_double)]
 
 

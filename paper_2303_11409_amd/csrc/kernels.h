@@ -12,12 +12,20 @@ hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntile
 
 // Blocked one-sided Jacobi SVD of every listed sector (vectors: min(r, c)
 // rows or columns of length max(r, c)); st holds per-sector state.
+// perm and norm2 hold, per sector from its sigma offset, the vector order by
+// descending norm and the vectors' squared norms.
 hipError_t launch_jacobi_init(const SectorWork* secs, const int* list, int count,
-                              const double2* theta, double2* acc, JacobiOut* st, hipStream_t s);
+                              const double2* theta, double2* acc, JacobiOut* st, int* perm,
+                              double* norm2, hipStream_t s);
 hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiBlockWork* jb, int njb, int npairs,
-                              int step, double2* theta, double2* acc, JacobiOut* st, double tol,
-                              int max_inner, hipStream_t s);
+                              int step, double2* theta, double2* acc, JacobiOut* st, const int* perm,
+                              double* norm2, double tol, int max_inner, hipStream_t s);
+hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count, const JacobiOut* st,
+                              int* perm, const double* norm2, hipStream_t s);
 hipError_t launch_jacobi_sweep_end(const int* list, int count, JacobiOut* st, int* active, hipStream_t s);
+// Scalar sweeps on the vectors for sectors the blocked sweeps left unconverged.
+hipError_t launch_jacobi_polish(const SectorWork* secs, const int* list, int count, double2* theta,
+                                double2* acc, JacobiOut* st, double tol, int max_sweeps, hipStream_t s);
 hipError_t launch_jacobi_finalize(const SectorWork* secs, const int* list, int count, int maxrows,
                                   double2* theta, const double2* acc, double* sigma, int* order,
                                   hipStream_t s);

@@ -196,15 +196,20 @@ __device__ __forceinline__ bool jac_rotation(double al, double be, double gr, do
   return true;
 }
 
+// Default threshold: (vector length) * eps, but never below 2 * kJP * eps,
+// the rounding level of the kJP-term combinations X <- W X that rotate a
+// block pair (short vectors would otherwise be held to a test they cannot
+// pass).
 __device__ __forceinline__ double jac_tol(double tol_opt, int len) {
-  return tol_opt > 0.0 ? tol_opt : (double)len * DBL_EPSILON;
+  return tol_opt > 0.0 ? tol_opt : (double)max(len, 2 * kJP) * DBL_EPSILON;
 }
 
-// One workgroup per sector: reset state, squared Frobenius norm, A = I.
+// One workgroup per sector: reset state, vector norms, identity order,
+// squared Frobenius norm, A = I.
 __global__ void __launch_bounds__(256)
 jacobi_init(const SectorWork* __restrict__ secs, const int* __restrict__ list,
             const double2* __restrict__ theta, double2* __restrict__ accbuf,
-            JacobiOut* __restrict__ st) {
+            JacobiOut* __restrict__ st, int* __restrict__ perm, double* __restrict__ norm2) {
   __shared__ double wsum[4];
   const int sid = list[blockIdx.x];
   const SectorWork sw = secs[sid];
@@ -212,18 +217,28 @@ jacobi_init(const SectorWork* __restrict__ secs, const int* __restrict__ list,
   const int n = tall ? sw.c : sw.r;
   const int len = tall ? sw.r : sw.c;
   const double2* x = theta + sw.off;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (tall) {
     double2* a = accbuf + sw.acc;
     for (int e = threadIdx.x; e < n * n; e += blockDim.x)
       a[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
   }
   double f = 0.0;
-  for (int e = threadIdx.x; e < n * len; e += blockDim.x) {
-    const double2 v = x[e];
-    f = fma(v.x, v.x, fma(v.y, v.y, f));
+  for (int i = wave; i < n; i += 4) {
+    const double2* xi = x + (size_t)i * len;
+    double ss = 0.0;
+    for (int col = lane; col < len; col += 64) {
+      const double2 v = xi[col];
+      ss = fma(v.x, v.x, fma(v.y, v.y, ss));
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) {
+      norm2[sw.sig + i] = ss;
+      perm[sw.sig + i] = i;
+    }
+    f += ss;
   }
-  f = wave_sum(f);
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = f;
+  if (lane == 0) wsum[wave] = f;
   __syncthreads();
   if (threadIdx.x == 0) {
     JacobiOut o;
@@ -238,17 +253,16 @@ jacobi_init(const SectorWork* __restrict__ secs, const int* __restrict__ list,
   }
 }
 
-// Load rows rows_of(r) (r < kJP), columns [c0, c0 + 32) of a row-major
-// matrix with row length len into an LDS tile; invalid entries are zero.
+// Load rows vrow[r] (r < kJP; -1 = absent), columns [c0, c0 + 32) of a
+// row-major matrix with row length len into an LDS tile (absent entries 0).
 __device__ __forceinline__ void jac_load_chunk(double2 (*xs)[33], const double2* __restrict__ x,
-                                               int len, int c0, int vI, int vJ, int n) {
+                                               int len, int c0, const int* vrow) {
   for (int e = threadIdx.x; e < kJP * 32; e += blockDim.x) {
     const int r = e >> 5, cc = e & 31;
-    const int v = r < kJB ? vI + r : vJ + (r - kJB);
-    const int lim = r < kJB ? min(vI + kJB, n) : min(vJ + kJB, n);
+    const int v = vrow[r];
     const int col = c0 + cc;
     double2 val = make_double2(0.0, 0.0);
-    if (v < lim && col < len) val = x[(size_t)v * len + col];
+    if (v >= 0 && col < len) val = x[(size_t)v * len + col];
     xs[r][cc] = val;
   }
 }
@@ -258,12 +272,12 @@ __device__ __forceinline__ void jac_load_chunk(double2 (*xs)[33], const double2*
 // quadrant (rows 16 (w / 2), columns 16 (w % 2)) of each chunk as four real
 // products per k-step, Or = Wr Xr - Wi Xi and Oi = Wr Xi + Wi Xr.
 __device__ void jac_apply(double2 (*xs)[33], double2 (*ws)[kJP + 1], double2* __restrict__ x,
-                          int len, int vI, int vJ, int n) {
+                          int len, const int* vrow) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R = (wave >> 1) * 16, Cq = (wave & 1) * 16;
   const int li = lane & 15, lk = lane >> 4;
   for (int c0 = 0; c0 < len; c0 += 32) {
-    jac_load_chunk(xs, x, len, c0, vI, vJ, n);
+    jac_load_chunk(xs, x, len, c0, vrow);
     __syncthreads();
     v4d orr = {0.0, 0.0, 0.0, 0.0}, oi = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -278,13 +292,20 @@ __device__ void jac_apply(double2 (*xs)[33], double2 (*ws)[kJP + 1], double2* __
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = R + 4 * r + lk;
-      const int v = row < kJB ? vI + row : vJ + (row - kJB);
-      const int lim = row < kJB ? min(vI + kJB, n) : min(vJ + kJB, n);
+      const int v = vrow[R + 4 * r + lk];
       const int col = c0 + Cq + li;
-      if (v < lim && col < len) x[(size_t)v * len + col] = make_double2(orr[r], oi[r]);
+      if (v >= 0 && col < len) x[(size_t)v * len + col] = make_double2(orr[r], oi[r]);
     }
   }
+}
+
+// Pair k of round-robin step s over the kJP rows of a block pair, as (p, q)
+// with p < q: the rotation always reads the upper-triangle entry.
+__device__ __forceinline__ void jac_pair_ordered(int s, int k, int& p, int& q) {
+  int i, j;
+  rr_pair(s, k, kJP, i, j);
+  p = min(i, j);
+  q = max(i, j);
 }
 
 // Rotations of the Gram matrix gs (in LDS) until no pair exceeds the
@@ -301,7 +322,7 @@ __device__ bool jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], dou
     for (int s2 = 0; s2 < kJP - 1; ++s2) {
       if (tid < kJP / 2) {
         int p, q;
-        rr_pair(s2, tid, kJP, p, q);
+        jac_pair_ordered(s2, tid, p, q);
         double c = 1.0, wr = 0.0, wi = 0.0;
         const double2 gpq = gs[p][q];
         const bool r = jac_rotation(gs[p][p].x, gs[q][q].x, gpq.x, gpq.y, tol, floor_g, c, wr, wi);
@@ -317,7 +338,7 @@ __device__ bool jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], dou
         const int pr = it / kJP, col = it % kJP;
         if (!rflag[pr]) continue;
         int p, q;
-        rr_pair(s2, pr, kJP, p, q);
+        jac_pair_ordered(s2, pr, p, q);
         rot_pair(gs[p][col], gs[q][col], rc[pr], rwr[pr], rwi[pr]);
         rot_pair(ws[p][col], ws[q][col], rc[pr], rwr[pr], rwi[pr]);
       }
@@ -327,7 +348,7 @@ __device__ bool jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], dou
         const int pr = it / kJP, row = it % kJP;
         if (!rflag[pr]) continue;
         int p, q;
-        rr_pair(s2, pr, kJP, p, q);
+        jac_pair_ordered(s2, pr, p, q);
         rot_pair(gs[row][p], gs[row][q], rc[pr], rwr[pr], -rwi[pr]);
       }
       __syncthreads();
@@ -357,7 +378,8 @@ constexpr double kJacNoise = 64.0;
 __global__ void __launch_bounds__(256)
 jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __restrict__ jb,
                   int njb, int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
-                  JacobiOut* __restrict__ st, double tol_opt, int max_inner) {
+                  JacobiOut* __restrict__ st, const int* __restrict__ perm, double* __restrict__ norm2,
+                  double tol_opt, int max_inner) {
   __shared__ double2 xs[kJP][33];
   __shared__ double2 gs[kJP][kJP + 1];
   __shared__ double2 ws[kJP][kJP + 1];
@@ -365,6 +387,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
   __shared__ int rflag[kJP / 2];
   __shared__ int need, anyrot;
   __shared__ double gmax;
+  __shared__ int vrow[kJP];
   int lo = 0, hi = njb - 1;
   const int pid = blockIdx.x;
   while (lo < hi) {
@@ -390,6 +413,13 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
   const int tid = threadIdx.x;
   // a block paired with the empty padding block still orthogonalises its own vectors
   if (nv < 2) return;
+  // block I holds the vectors at sorted positions 16 I .. 16 I + 15
+  if (tid < kJP) {
+    const int pos = tid < kJB ? vI + tid : vJ + (tid - kJB);
+    const int lim = tid < kJB ? vI + nI : vJ + nJ;
+    vrow[tid] = pos < lim ? perm[sw.sig + pos] : -1;
+  }
+  __syncthreads();
   const int p0 = 2 * (tid >> 4), q0 = 2 * (tid & 15);
   bool fresh = false;          // gs holds the Gram matrix of the current vectors
   for (int pass = 0; pass < 2; ++pass) {
@@ -402,7 +432,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
       const int li = lane & 15, lk = lane >> 4;
       v4d grr = {0.0, 0.0, 0.0, 0.0}, gii = {0.0, 0.0, 0.0, 0.0};
       for (int c0 = 0; c0 < len; c0 += 32) {
-        jac_load_chunk(xs, x, len, c0, vI, vJ, n);
+        jac_load_chunk(xs, x, len, c0, vrow);
         __syncthreads();
 #pragma unroll
         for (int k0 = 0; k0 < 32; k0 += 4) {
@@ -417,6 +447,15 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) gs[P + 4 * r + lk][Q + li] = make_double2(grr[r], gii[r]);
+      __syncthreads();
+      // The two triangles come from different accumulation orders and differ
+      // in the last bits; every decision must see one value per pair, so the
+      // matrix is made exactly Hermitian from its upper triangle.
+      for (int e = tid; e < kJP * kJP; e += blockDim.x) {
+        const int r = e / kJP, c = e % kJP;
+        if (r > c) gs[r][c] = cconj(gs[c][r]);
+        else if (r == c) gs[r][c].y = 0.0;
+      }
       if (tid == 0) atomicAdd(&st[sid].gram_units, (unsigned long long)nv * nv * len);
     }
     if (tid == 0) need = 0;
@@ -457,11 +496,94 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
       continue;
     }
     // ---- rotate the vectors (and the accumulator of a tall sector)
-    jac_apply(xs, ws, x, len, vI, vJ, n);
-    if (tall) jac_apply(xs, ws, accbuf + sw.acc, n, vI, vJ, n);
+    jac_apply(xs, ws, x, len, vrow);
+    if (tall) jac_apply(xs, ws, accbuf + sw.acc, n, vrow);
     if (tid == 0) atomicAdd(&st[sid].apply_units, (unsigned long long)nv * nv * (len + (tall ? n : 0)));
     fresh = false;
     __syncthreads();
+  }
+  // latest squared norms of the pair's vectors (the Gram diagonal; after a
+  // rotation the rotated Gram's diagonal), for the next sweep's ordering
+  __syncthreads();
+  if (tid < kJP && vrow[tid] >= 0) norm2[sw.sig + vrow[tid]] = gs[tid][tid].x;
+}
+
+// Scalar one-sided Jacobi sweeps on the vectors themselves, for the rare
+// sector the blocked sweeps leave unconverged.  One workgroup per listed
+// sector; each wavefront takes whole vector pairs of a round-robin step,
+// forms alpha, beta, gamma with wave reductions and rotates both vectors (and
+// the accumulator rows of a tall sector).  A 2x2 rotation has only two-term
+// rounding, so it reaches cosines of order sqrt(len) eps, well inside the
+// tolerance.  Runs up to max_sweeps sweeps and marks the sector converged
+// when a sweep rotates nothing.
+__global__ void __launch_bounds__(256)
+jacobi_polish(const SectorWork* __restrict__ secs, const int* __restrict__ list,
+              double2* __restrict__ theta, double2* __restrict__ accbuf,
+              JacobiOut* __restrict__ st, double tol_opt, int max_sweeps) {
+  __shared__ int rotated;
+  const int sid = list[blockIdx.x];
+  if (st[sid].converged) return;
+  const SectorWork sw = secs[sid];
+  const bool tall = sw.tall != 0;
+  const int n = tall ? sw.c : sw.r;
+  const int len = tall ? sw.r : sw.c;
+  double2* x = theta + sw.off;
+  double2* acc = tall ? accbuf + sw.acc : nullptr;
+  const double tol = jac_tol(tol_opt, len);
+  const double floor_g = (double)len * DBL_EPSILON * DBL_EPSILON * st[sid].fro2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int np = n + (n & 1);
+  bool converged = false;
+  int sweeps = 0;
+  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+    __syncthreads();
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int step = 0; step < np - 1; ++step) {
+      for (int k = wave; k < np / 2; k += nwaves) {
+        int i, j;
+        rr_pair(step, k, np, i, j);
+        if (i >= n || j >= n) continue;
+        double2* xi = x + (size_t)i * len;
+        double2* xj = x + (size_t)j * len;
+        double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+        for (int col = lane; col < len; col += 64) {
+          const double2 a = xi[col], b = xj[col];
+          al = fma(a.x, a.x, fma(a.y, a.y, al));
+          be = fma(b.x, b.x, fma(b.y, b.y, be));
+          gr = fma(a.x, b.x, fma(a.y, b.y, gr));
+          gi = fma(a.y, b.x, fma(-a.x, b.y, gi));
+        }
+        al = wave_sum(al); be = wave_sum(be); gr = wave_sum(gr); gi = wave_sum(gi);
+        double c, wr, wi;
+        if (!jac_rotation(al, be, gr, gi, tol, floor_g, c, wr, wi)) continue;
+        for (int col = lane; col < len; col += 64) {
+          double2 a = xi[col], b = xj[col];
+          rot_pair(a, b, c, wr, wi);
+          xi[col] = a;
+          xj[col] = b;
+        }
+        if (tall) {
+          double2* ai = acc + (size_t)i * n;
+          double2* aj = acc + (size_t)j * n;
+          for (int col = lane; col < n; col += 64) {
+            double2 a = ai[col], b = aj[col];
+            rot_pair(a, b, c, wr, wi);
+            ai[col] = a;
+            aj[col] = b;
+          }
+        }
+        if (lane == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    ++sweeps;
+    converged = rotated == 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st[sid].sweeps += sweeps;
+    st[sid].converged = converged ? 1 : 0;
   }
 }
 
@@ -486,6 +608,29 @@ jacobi_sweep_end(const int* __restrict__ list, int count, JacobiOut* __restrict_
   }
   __syncthreads();
   if (threadIdx.x == 0) *active = act;
+}
+
+// Between sweeps: order every still-active sector's vectors by descending
+// norm (ties: lower index first), so that blocks hold vectors of similar
+// size.  One workgroup per sector.
+__global__ void __launch_bounds__(256)
+jacobi_sort(const SectorWork* __restrict__ secs, const int* __restrict__ list,
+            const JacobiOut* __restrict__ st, int* __restrict__ perm,
+            const double* __restrict__ norm2) {
+  const int sid = list[blockIdx.x];
+  if (st[sid].converged) return;
+  const SectorWork sw = secs[sid];
+  const int n = sw.tall ? sw.c : sw.r;
+  const double* nv = norm2 + sw.sig;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = nv[i];
+    int rank = 0;
+    for (int k = 0; k < n; ++k) {
+      const double w = nv[k];
+      rank += (w > v) || (w == v && k < i);
+    }
+    perm[sw.sig + rank] = i;
+  }
 }
 
 // One workgroup per sector: vector norms -> singular values, V^dagger rows
@@ -892,23 +1037,38 @@ hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntile
 }
 
 hipError_t launch_jacobi_init(const SectorWork* secs, const int* list, int count,
-                              const double2* theta, double2* acc, JacobiOut* st, hipStream_t s) {
+                              const double2* theta, double2* acc, JacobiOut* st, int* perm,
+                              double* norm2, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_init, dim3(count), dim3(256), 0, s, secs, list, theta, acc, st);
+  hipLaunchKernelGGL(jacobi_init, dim3(count), dim3(256), 0, s, secs, list, theta, acc, st, perm, norm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count, const JacobiOut* st,
+                              int* perm, const double* norm2, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_sort, dim3(count), dim3(256), 0, s, secs, list, st, perm, norm2);
   return hipGetLastError();
 }
 
 hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiBlockWork* jb, int njb, int npairs,
-                              int step, double2* theta, double2* acc, JacobiOut* st, double tol,
-                              int max_inner, hipStream_t s) {
+                              int step, double2* theta, double2* acc, JacobiOut* st, const int* perm,
+                              double* norm2, double tol, int max_inner, hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
   hipLaunchKernelGGL(jacobi_block_step, dim3(npairs), dim3(256), 0, s, secs, jb, njb, step, theta, acc,
-                     st, tol, max_inner);
+                     st, perm, norm2, tol, max_inner);
   return hipGetLastError();
 }
 
 hipError_t launch_jacobi_sweep_end(const int* list, int count, JacobiOut* st, int* active, hipStream_t s) {
   hipLaunchKernelGGL(jacobi_sweep_end, dim3(1), dim3(1024), 0, s, list, count, st, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_polish(const SectorWork* secs, const int* list, int count, double2* theta,
+                                double2* acc, JacobiOut* st, double tol, int max_sweeps, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_polish, dim3(count), dim3(256), 0, s, secs, list, theta, acc, st, tol, max_sweeps);
   return hipGetLastError();
 }
 

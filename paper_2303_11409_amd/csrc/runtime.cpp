@@ -90,6 +90,8 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Rotation sweeps over a block pair's Gram matrix before the block is rotated.
 constexpr int kMaxInnerSweeps = 12;
+// Blocked sweeps before an unconverged sector is finished by scalar sweeps.
+constexpr int kBlockedSweeps = 24;
 
 }  // namespace
 
@@ -103,7 +105,7 @@ struct mps_state {
   std::vector<double*> lam;      // per bond, cap[b] doubles
   std::vector<double2*> site;    // per site, cap[s] * cap[s+1] complex
   // workspaces (grow-only)
-  DevBuf th_raw, th_scaled, acc, sigma, order, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc;
+  DevBuf th_raw, th_scaled, acc, sigma, order, jperm, jnorm, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc;
   PinBuf stage_plan, stage_upd, stage_res, stage_misc, stage_flag;
   mps_stats stats{};
   bool timing = false;
@@ -488,6 +490,8 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
   STCHK(ensure(h, h->acc, (size_t)std::max<long long>(P.acc_elems, 1) * sizeof(double2)));
   STCHK(ensure(h, h->sigma, (size_t)P.sig_elems * sizeof(double)));
   STCHK(ensure(h, h->order, (size_t)P.sig_elems * sizeof(int)));
+  STCHK(ensure(h, h->jperm, (size_t)P.sig_elems * sizeof(int)));
+  STCHK(ensure(h, h->jnorm, (size_t)P.sig_elems * sizeof(double)));
   if (P.maxP > 4096) {
     STCHK(ensure(h, h->sel_v, (size_t)P.sel_scratch * sizeof(double)));
     STCHK(ensure(h, h->sel_k, (size_t)P.sel_scratch * sizeof(int)));
@@ -529,31 +533,48 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
     JacobiOut* d_jst = at<JacobiOut>(h->plan, o_jst);
     const int* d_jlist = at<int>(h->plan, o_jlist);
     double2* d_acc = static_cast<double2*>(h->acc.p);
+    int* d_perm = static_cast<int*>(h->jperm.p);
+    double* d_norm = static_cast<double*>(h->jnorm.p);
     int* d_active = at<int>(h->plan, o_active);
     STCHK(ensure_pin(h->stage_flag, sizeof(int)));
     {
       Timer tm(h, K_JACOBI_AUX);
       STCHK(tm.start());
-      HIPCHK(launch_jacobi_init(d_secs, d_jlist, ns, scaled, d_acc, d_jst, h->st));
+      HIPCHK(launch_jacobi_init(d_secs, d_jlist, ns, scaled, d_acc, d_jst, d_perm, d_norm, h->st));
       STCHK(tm.stop());
       h->stats.jacobi_aux_launches += 1;
     }
-    for (int sweep = 0; sweep < h->opts.max_sweeps; ++sweep) {
+    // blocked sweeps; a sector still rotating after kBlockedSweeps of them is
+    // finished by scalar sweeps on its vectors
+    const int blocked = std::min(h->opts.max_sweeps, kBlockedSweeps);
+    int still_active = 1;
+    for (int sweep = 0; sweep < blocked; ++sweep) {
       Timer tm(h, K_JACOBI);
       STCHK(tm.start());
       for (int step = 0; step < P.jmaxnb - 1; ++step)
         HIPCHK(launch_jacobi_step(d_secs, at<JacobiBlockWork>(h->plan, o_jblk), ns, P.jpairs, step, scaled,
-                                  d_acc, d_jst, h->opts.jacobi_tol, kMaxInnerSweeps, h->st));
+                                  d_acc, d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, h->st));
       STCHK(tm.stop());
       h->stats.jacobi_launches += P.jmaxnb - 1;
       Timer ta(h, K_JACOBI_AUX);
       STCHK(ta.start());
       HIPCHK(launch_jacobi_sweep_end(d_jlist, ns, d_jst, d_active, h->st));
+      HIPCHK(launch_jacobi_sort(d_secs, d_jlist, ns, d_jst, d_perm, d_norm, h->st));
       STCHK(ta.stop());
-      h->stats.jacobi_aux_launches += 1;
+      h->stats.jacobi_aux_launches += 2;
       HIPCHK(hipMemcpyAsync(h->stage_flag.p, d_active, sizeof(int), hipMemcpyDeviceToHost, h->st));
       HIPCHK(hipStreamSynchronize(h->st));
-      if (*static_cast<volatile int*>(h->stage_flag.p) == 0) break;
+      still_active = *static_cast<volatile int*>(h->stage_flag.p);
+      if (!still_active) break;
+    }
+    if (still_active && h->opts.max_sweeps > blocked) {
+      Timer tp(h, K_JACOBI_AUX);
+      STCHK(tp.start());
+      HIPCHK(launch_jacobi_polish(d_secs, d_jlist, ns, scaled, d_acc, d_jst, h->opts.jacobi_tol,
+                                  h->opts.max_sweeps - blocked, h->st));
+      STCHK(tp.stop());
+      h->stats.jacobi_aux_launches += 1;
+      h->stats.polish_launches += 1;
     }
     Timer tf(h, K_JACOBI_AUX);
     STCHK(tf.start());
@@ -688,7 +709,7 @@ mps_status destroy_buffers(mps_state* h) {
   for (double2* p : h->site) dfree(h, p);
   h->lam.clear();
   h->site.clear();
-  DevBuf* bufs[] = {&h->th_raw, &h->th_scaled, &h->acc, &h->sigma, &h->order, &h->plan, &h->upd,
+  DevBuf* bufs[] = {&h->th_raw, &h->th_scaled, &h->acc, &h->jperm, &h->jnorm, &h->sigma, &h->order, &h->plan, &h->upd,
                     &h->norm_e0, &h->norm_e1, &h->norm_t, &h->sel_v, &h->sel_k, &h->misc};
   for (DevBuf* b : bufs) {
     dfree(h, b->p);
