@@ -185,14 +185,20 @@ __device__ __forceinline__ void rot_pair(double2& a, double2& b, double c, doubl
 
 __device__ __forceinline__ bool jac_rotation(double al, double be, double gr, double gi, double tol,
                                              double floor_g, double& c, double& wr, double& wi) {
-  const double ag = sqrt(gr * gr + gi * gi);
-  if (!(ag > tol * sqrt(al) * sqrt(be)) || !(ag > floor_g)) return false;
-  const double zeta = (be - al) / (2.0 * ag);
-  const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  c = 1.0 / sqrt(1.0 + tt * tt);
-  const double s = c * tt;
-  wr = s * gr / ag;
-  wi = s * gi / ag;
+  // test on squares: |gamma|^2 > tol^2 alpha beta and |gamma| > floor
+  const double g2 = gr * gr + gi * gi;
+  if (!(g2 > tol * tol * al * be) || !(g2 > floor_g * floor_g)) return false;
+  // with delta = beta - alpha, D = |delta| + sqrt(delta^2 + 4|gamma|^2) and
+  // E = sqrt(D^2 + 4|gamma|^2):  c = D / E,  w = 2 sgn(delta) gamma / E --
+  // the same rotation as t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+  // zeta = delta / (2|gamma|), c = 1/sqrt(1 + t^2), w = c t gamma/|gamma|
+  const double delta = be - al;
+  const double D = fabs(delta) + sqrt(delta * delta + 4.0 * g2);
+  const double inv = 1.0 / sqrt(D * D + 4.0 * g2);
+  const double sg = delta >= 0.0 ? 2.0 * inv : -2.0 * inv;
+  c = D * inv;
+  wr = sg * gr;
+  wi = sg * gi;
   return true;
 }
 
@@ -309,53 +315,55 @@ __device__ __forceinline__ void jac_pair_ordered(int s, int k, int& p, int& q) {
 }
 
 // Rotations of the Gram matrix gs (in LDS) until no pair exceeds the
-// threshold; W accumulates the product.  Returns true if any rotation was made.
-__device__ bool jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], double* rc, double* rwr,
-                             double* rwi, int* rflag, int* anyrot, double tol, double floor_g,
-                             int max_inner) {
+// threshold; W accumulates the product.  Returns true if any rotation was
+// made.  A round-robin step rotates 16 disjoint pairs at once,
+// G <- U G U^H and W <- U W with U block diagonal over the pairs: 16 threads
+// compute the pairs' rotations into rot[], then thread t = 16 A + B updates
+// the 2 x 2 blocks (rows of pair A) x (columns of pair B) of G and W in
+// place (each block is read and written by its owner only).
+__device__ bool jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], double4* rot,
+                             double tol, double floor_g, int max_inner) {
   const int tid = threadIdx.x;
+  const int A = tid >> 4, B = tid & 15;
   bool any_total = false;
   for (int inner = 0; inner < max_inner; ++inner) {
-    __syncthreads();
-    if (tid == 0) *anyrot = 0;
-    __syncthreads();
+    int any_sweep = 0;
     for (int s2 = 0; s2 < kJP - 1; ++s2) {
+      int flag = 0;
       if (tid < kJP / 2) {
         int p, q;
         jac_pair_ordered(s2, tid, p, q);
         double c = 1.0, wr = 0.0, wi = 0.0;
-        const double2 gpq = gs[p][q];
-        const bool r = jac_rotation(gs[p][p].x, gs[q][q].x, gpq.x, gpq.y, tol, floor_g, c, wr, wi);
-        rflag[tid] = r ? 1 : 0;
-        rc[tid] = c;
-        rwr[tid] = wr;
-        rwi[tid] = wi;
-        if (r) *anyrot = 1;
+        const double2 g = gs[p][q];
+        flag = jac_rotation(gs[p][p].x, gs[q][q].x, g.x, g.y, tol, floor_g, c, wr, wi) ? 1 : 0;
+        rot[tid] = make_double4(c, wr, wi, flag ? 1.0 : 0.0);
       }
-      __syncthreads();
-      // rows of G and W: U acts from the left
-      for (int it = tid; it < (kJP / 2) * kJP; it += blockDim.x) {
-        const int pr = it / kJP, col = it % kJP;
-        if (!rflag[pr]) continue;
-        int p, q;
-        jac_pair_ordered(s2, pr, p, q);
-        rot_pair(gs[p][col], gs[q][col], rc[pr], rwr[pr], rwi[pr]);
-        rot_pair(ws[p][col], ws[q][col], rc[pr], rwr[pr], rwi[pr]);
-      }
-      __syncthreads();
-      // columns of G: U^H acts from the right (the conjugate coefficient)
-      for (int it = tid; it < (kJP / 2) * kJP; it += blockDim.x) {
-        const int pr = it / kJP, row = it % kJP;
-        if (!rflag[pr]) continue;
-        int p, q;
-        jac_pair_ordered(s2, pr, p, q);
-        rot_pair(gs[row][p], gs[row][q], rc[pr], rwr[pr], -rwi[pr]);
+      if (!__syncthreads_or(flag)) continue;
+      any_sweep = 1;
+      int pa, qa, pb, qb;
+      jac_pair_ordered(s2, A, pa, qa);
+      jac_pair_ordered(s2, B, pb, qb);
+      const double4 ra = rot[A], rb = rot[B];
+      if (ra.w != 0.0 || rb.w != 0.0) {
+        double2 g00 = gs[pa][pb], g01 = gs[pa][qb], g10 = gs[qa][pb], g11 = gs[qa][qb];
+        if (ra.w != 0.0) {        // rows pa, qa: U from the left, also on W
+          double2 w00 = ws[pa][pb], w01 = ws[pa][qb], w10 = ws[qa][pb], w11 = ws[qa][qb];
+          rot_pair(g00, g10, ra.x, ra.y, ra.z);
+          rot_pair(g01, g11, ra.x, ra.y, ra.z);
+          rot_pair(w00, w10, ra.x, ra.y, ra.z);
+          rot_pair(w01, w11, ra.x, ra.y, ra.z);
+          ws[pa][pb] = w00; ws[pa][qb] = w01; ws[qa][pb] = w10; ws[qa][qb] = w11;
+        }
+        if (rb.w != 0.0) {        // columns pb, qb: U^H from the right
+          rot_pair(g00, g01, rb.x, rb.y, -rb.z);
+          rot_pair(g10, g11, rb.x, rb.y, -rb.z);
+        }
+        gs[pa][pb] = g00; gs[pa][qb] = g01; gs[qa][pb] = g10; gs[qa][qb] = g11;
       }
       __syncthreads();
     }
-    const bool a = *anyrot != 0;
-    any_total = any_total || a;
-    if (!a) break;
+    any_total = any_total || any_sweep;
+    if (!any_sweep) break;
   }
   __syncthreads();
   return any_total;
@@ -383,11 +391,10 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
   __shared__ double2 xs[kJP][33];
   __shared__ double2 gs[kJP][kJP + 1];
   __shared__ double2 ws[kJP][kJP + 1];
-  __shared__ double rc[kJP / 2], rwr[kJP / 2], rwi[kJP / 2];
-  __shared__ int rflag[kJP / 2];
-  __shared__ int need, anyrot;
+  __shared__ int need;
   __shared__ double gmax;
   __shared__ int vrow[kJP];
+  __shared__ double4 rot[kJP / 2];
   int lo = 0, hi = njb - 1;
   const int pid = blockIdx.x;
   while (lo < hi) {
@@ -488,7 +495,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
     }
     const double ptol = pass == 0 ? fmax(tol, kJacLoose) : tol;
     const double pfloor = pass == 0 ? fmax(floor_g, kJacNoise * DBL_EPSILON * gmax) : floor_g;
-    const bool rotated = jac_gram_eig(gs, ws, rc, rwr, rwi, rflag, &anyrot, ptol, pfloor, max_inner);
+    const bool rotated = jac_gram_eig(gs, ws, rot, ptol, pfloor, max_inner);
     if (!rotated) {
       // nothing above the coarse thresholds: gs is still the Gram matrix of
       // the unchanged vectors, go straight to the full-tolerance pass
