@@ -188,13 +188,14 @@ __device__ __forceinline__ bool jac_rotation(double al, double be, double gr, do
   // test on squares: |gamma|^2 > tol^2 alpha beta and |gamma| > floor
   const double g2 = gr * gr + gi * gi;
   if (!(g2 > tol * tol * al * be) || !(g2 > floor_g * floor_g)) return false;
-  // with delta = beta - alpha, D = |delta| + sqrt(delta^2 + 4|gamma|^2) and
-  // E = sqrt(D^2 + 4|gamma|^2):  c = D / E,  w = 2 sgn(delta) gamma / E --
+  // with delta = beta - alpha, r = sqrt(delta^2 + 4|gamma|^2), D = |delta| + r:
+  // c = D / E, w = 2 sgn(delta) gamma / E with E^2 = D^2 + 4|gamma|^2 = 2 r D --
   // the same rotation as t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
   // zeta = delta / (2|gamma|), c = 1/sqrt(1 + t^2), w = c t gamma/|gamma|
   const double delta = be - al;
-  const double D = fabs(delta) + sqrt(delta * delta + 4.0 * g2);
-  const double inv = 1.0 / sqrt(D * D + 4.0 * g2);
+  const double r = sqrt(delta * delta + 4.0 * g2);
+  const double D = fabs(delta) + r;
+  const double inv = rsqrt(2.0 * r * D);
   const double sg = delta >= 0.0 ? 2.0 * inv : -2.0 * inv;
   c = D * inv;
   wr = sg * gr;
@@ -314,20 +315,44 @@ __device__ __forceinline__ void jac_pair_ordered(int s, int k, int& p, int& q) {
   q = max(i, j);
 }
 
+// True if the pair (p, q) of a Gram matrix with diagonal alpha, beta and
+// off-diagonal gamma is above the rotation threshold (the test of
+// jac_rotation without computing the rotation).
+__device__ __forceinline__ bool jac_needs(double al, double be, double2 g, double tol, double floor_g) {
+  const double g2 = g.x * g.x + g.y * g.y;
+  return g2 > tol * tol * al * be && g2 > floor_g * floor_g;
+}
+
+// True if any off-diagonal pair of the Hermitian gs is above the threshold:
+// thread t checks the upper-triangle entries of its 2 x 2 block (rows
+// 2 (t / 16), columns 2 (t % 16)).  Uniform across the workgroup.
+__device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 1], double tol, double floor_g) {
+  const int p0 = 2 * (threadIdx.x >> 4), q0 = 2 * (threadIdx.x & 15);
+  int f = 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int p = p0 + i, q = q0 + j;
+      if (p < q && jac_needs(gs[p][p].x, gs[q][q].x, gs[p][q], tol, floor_g)) f = 1;
+    }
+  return __syncthreads_or(f) != 0;
+}
+
 // Rotations of the Gram matrix gs (in LDS) until no pair exceeds the
-// threshold; W accumulates the product.  Returns true if any rotation was
-// made.  A round-robin step rotates 16 disjoint pairs at once,
-// G <- U G U^H and W <- U W with U block diagonal over the pairs: 16 threads
-// compute the pairs' rotations into rot[], then thread t = 16 A + B updates
-// the 2 x 2 blocks (rows of pair A) x (columns of pair B) of G and W in
-// place (each block is read and written by its owner only).
-__device__ bool jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], double4* rot,
+// threshold; W accumulates the product.  The caller has established that
+// some pair is above it.  A round-robin step rotates 16 disjoint pairs at
+// once, G <- U G U^H and W <- U W with U block diagonal over the pairs: 16
+// threads compute the pairs' rotations into rot[], then thread t = 16 A + B
+// updates the 2 x 2 blocks (rows of pair A) x (columns of pair B) of G and W
+// in place (each block is read and written by its owner only).  After each
+// sweep one parallel test over all pairs replaces the sweep that would find
+// nothing to rotate (it would leave G and W unchanged).
+__device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], double4* rot,
                              double tol, double floor_g, int max_inner) {
   const int tid = threadIdx.x;
   const int A = tid >> 4, B = tid & 15;
-  bool any_total = false;
   for (int inner = 0; inner < max_inner; ++inner) {
-    int any_sweep = 0;
     for (int s2 = 0; s2 < kJP - 1; ++s2) {
       int flag = 0;
       if (tid < kJP / 2) {
@@ -339,7 +364,6 @@ __device__ bool jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], dou
         rot[tid] = make_double4(c, wr, wi, flag ? 1.0 : 0.0);
       }
       if (!__syncthreads_or(flag)) continue;
-      any_sweep = 1;
       int pa, qa, pb, qb;
       jac_pair_ordered(s2, A, pa, qa);
       jac_pair_ordered(s2, B, pb, qb);
@@ -362,11 +386,9 @@ __device__ bool jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], dou
       }
       __syncthreads();
     }
-    any_total = any_total || any_sweep;
-    if (!any_sweep) break;
+    if (!jac_any_above(gs, tol, floor_g)) break;
   }
   __syncthreads();
-  return any_total;
 }
 
 // One round-robin step for every active sector: one workgroup per block pair.
@@ -391,7 +413,6 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
   __shared__ double2 xs[kJP][33];
   __shared__ double2 gs[kJP][kJP + 1];
   __shared__ double2 ws[kJP][kJP + 1];
-  __shared__ int need;
   __shared__ double gmax;
   __shared__ int vrow[kJP];
   __shared__ double4 rot[kJP / 2];
@@ -427,7 +448,6 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
     vrow[tid] = pos < lim ? perm[sw.sig + pos] : -1;
   }
   __syncthreads();
-  const int p0 = 2 * (tid >> 4), q0 = 2 * (tid & 15);
   bool fresh = false;          // gs holds the Gram matrix of the current vectors
   for (int pass = 0; pass < 2; ++pass) {
     if (!fresh) {
@@ -465,27 +485,16 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
       }
       if (tid == 0) atomicAdd(&st[sid].gram_units, (unsigned long long)nv * nv * len);
     }
-    if (tid == 0) need = 0;
     __syncthreads();
-    // ---- any pair above tolerance?
+    // ---- largest squared norm (for the coarse noise floor) and any pair
+    // above tolerance?  The barrier inside jac_any_above publishes gmax.
+    if (tid < 64) {
+      double m = tid < kJP ? gs[tid][tid].x : 0.0;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int p = p0 + i, q = q0 + j;
-        if (p < q) {
-          double c, wr, wi;
-          const double2 gpq = gs[p][q];
-          if (jac_rotation(gs[p][p].x, gs[q][q].x, gpq.x, gpq.y, tol, floor_g, c, wr, wi))
-            atomicOr(&need, 1);
-        }
-      }
-    if (tid == 0) {
-      double m = 0.0;
-      for (int r = 0; r < kJP; ++r) m = fmax(m, gs[r][r].x);
-      gmax = m;
+      for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+      if (tid == 0) gmax = m;
     }
-    __syncthreads();
+    const bool need = jac_any_above(gs, tol, floor_g);
     if (!need) break;
     if (pass == 0 && tid == 0) atomicAdd(&st[sid].rot_this_sweep, 1);
     // ---- diagonalise G by rotations, W = accumulated product
@@ -493,15 +502,16 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
       const int r = e / kJP, c = e % kJP;
       ws[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
     }
+    __syncthreads();
     const double ptol = pass == 0 ? fmax(tol, kJacLoose) : tol;
     const double pfloor = pass == 0 ? fmax(floor_g, kJacNoise * DBL_EPSILON * gmax) : floor_g;
-    const bool rotated = jac_gram_eig(gs, ws, rot, ptol, pfloor, max_inner);
-    if (!rotated) {
+    if (pass == 0 && !jac_any_above(gs, ptol, pfloor)) {
       // nothing above the coarse thresholds: gs is still the Gram matrix of
       // the unchanged vectors, go straight to the full-tolerance pass
       fresh = true;
       continue;
     }
+    jac_gram_eig(gs, ws, rot, ptol, pfloor, max_inner);
     // ---- rotate the vectors (and the accumulator of a tall sector)
     jac_apply(xs, ws, x, len, vrow);
     if (tall) jac_apply(xs, ws, accbuf + sw.acc, n, vrow);
