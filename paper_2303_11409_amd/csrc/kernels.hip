@@ -260,17 +260,53 @@ jacobi_init(const SectorWork* __restrict__ secs, const int* __restrict__ list,
   }
 }
 
-// Load rows vrow[r] (r < kJP; -1 = absent), columns [c0, c0 + 32) of a
-// row-major matrix with row length len into an LDS tile (absent entries 0).
-__device__ __forceinline__ void jac_load_chunk(double2 (*xs)[33], const double2* __restrict__ x,
-                                               int len, int c0, const int* vrow) {
-  for (int e = threadIdx.x; e < kJP * 32; e += blockDim.x) {
-    const int r = e >> 5, cc = e & 31;
-    const int v = vrow[r];
-    const int col = c0 + cc;
-    double2 val = make_double2(0.0, 0.0);
-    if (v >= 0 && col < len) val = x[(size_t)v * len + col];
-    xs[r][cc] = val;
+// Column chunks of the kJP rows vrow[r] (-1 = absent) of a row-major matrix
+// with row length len.  A chunk is 32 columns; each of the 256 threads moves
+// kJChunkRegs of its elements (rows 8 k + tid / 32, column tid % 32), so a
+// wavefront reads two contiguous 512-byte row segments per load.  Absent
+// rows and columns past len read as 0 and issue no load.
+constexpr int kJChunkRegs = kJP * 32 / 256;
+
+__device__ __forceinline__ void jac_fetch(double2 (&v)[kJChunkRegs], const double2* __restrict__ x,
+                                          int len, int c0, const int* vrow) {
+  const int cc = threadIdx.x & 31, col = c0 + cc;
+#pragma unroll
+  for (int k = 0; k < kJChunkRegs; ++k) {
+    const int row = vrow[8 * k + (threadIdx.x >> 5)];
+    v[k] = make_double2(0.0, 0.0);
+    if (row >= 0 && col < len) v[k] = x[(size_t)row * len + col];
+  }
+}
+
+__device__ __forceinline__ void jac_stage(double2 (*xs)[33], const double2 (&v)[kJChunkRegs]) {
+  const int cc = threadIdx.x & 31;
+#pragma unroll
+  for (int k = 0; k < kJChunkRegs; ++k) xs[8 * k + (threadIdx.x >> 5)][cc] = v[k];
+}
+
+// Runs body(c0) for every chunk [c0, c0 + 32) of the rows, with the chunk
+// staged in xs.  Two chunks are in flight in registers while the body works
+// on the staged one, so the loads of chunk c0 + 64 overlap the body of c0.
+// The body may overwrite columns [c0, c0 + 32) of x (the loads in flight
+// are of later columns).
+template <class Body>
+__device__ __forceinline__ void jac_chunk_loop(double2 (*xs)[33], const double2* x, int len,
+                                               const int* vrow, Body&& body) {
+  double2 ra[kJChunkRegs], rb[kJChunkRegs];
+  jac_fetch(ra, x, len, 0, vrow);
+  jac_fetch(rb, x, len, 32, vrow);
+  for (int c0 = 0; c0 < len; c0 += 64) {
+    jac_stage(xs, ra);
+    __syncthreads();
+    jac_fetch(ra, x, len, c0 + 64, vrow);
+    body(c0);
+    __syncthreads();
+    if (c0 + 32 >= len) break;
+    jac_stage(xs, rb);
+    __syncthreads();
+    jac_fetch(rb, x, len, c0 + 96, vrow);
+    body(c0 + 32);
+    __syncthreads();
   }
 }
 
@@ -283,9 +319,7 @@ __device__ void jac_apply(double2 (*xs)[33], double2 (*ws)[kJP + 1], double2* __
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R = (wave >> 1) * 16, Cq = (wave & 1) * 16;
   const int li = lane & 15, lk = lane >> 4;
-  for (int c0 = 0; c0 < len; c0 += 32) {
-    jac_load_chunk(xs, x, len, c0, vrow);
-    __syncthreads();
+  jac_chunk_loop(xs, x, len, vrow, [&](int c0) {
     v4d orr = {0.0, 0.0, 0.0, 0.0}, oi = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k0 = 0; k0 < kJP; k0 += 4) {
@@ -296,12 +330,54 @@ __device__ void jac_apply(double2 (*xs)[33], double2 (*ws)[kJP + 1], double2* __
       oi = mfma16x16x4(wv.x, xv.y, oi);
       oi = mfma16x16x4(wv.y, xv.x, oi);
     }
-    __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int v = vrow[R + 4 * r + lk];
       const int col = c0 + Cq + li;
       if (v >= 0 && col < len) x[(size_t)v * len + col] = make_double2(orr[r], oi[r]);
+    }
+  });
+}
+
+// Gram matrix G = X X^H of the kJP rows into gs, on the matrix cores, with
+// three real products: Gr = Xr Xr^T + Xi Xi^T (symmetric) and Gi = M - M^T
+// with M = Xi Xr^T.  Waves 0, 1, 2 form the Gr quadrants (0,0), (0,16),
+// (16,16) and the same quadrants of M; wave 3 forms M's quadrant (16,0).
+// Gr's diagonal quadrants give both triangles with different rounding;
+// every decision must see one value per pair, so gs is made exactly
+// Hermitian from its upper triangle.  M passes through xs.
+__device__ void jac_gram(double2 (*xs)[33], double2 (*gs)[kJP + 1], const double2* x, int len,
+                         const int* vrow) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int P = wave >= 2 ? 16 : 0, Q = (wave == 1 || wave == 2) ? 16 : 0;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool has_gr = wave < 3;
+  v4d gra = {0.0, 0.0, 0.0, 0.0}, grb = {0.0, 0.0, 0.0, 0.0}, mm = {0.0, 0.0, 0.0, 0.0};
+  jac_chunk_loop(xs, x, len, vrow, [&](int) {
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 4) {
+      const double2 av = xs[P + li][k0 + lk];     // A = X[P + i][k]
+      const double2 bv = xs[Q + li][k0 + lk];     // B = X[Q + j][k] (transposed)
+      if (has_gr) {
+        gra = mfma16x16x4(av.x, bv.x, gra);
+        grb = mfma16x16x4(av.y, bv.y, grb);
+      }
+      mm = mfma16x16x4(av.y, bv.x, mm);
+    }
+  });
+  // the loop ended on a barrier: xs is free
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (has_gr) gs[P + 4 * r + lk][Q + li] = make_double2(gra[r] + grb[r], 0.0);
+    xs[P + 4 * r + lk][Q + li] = make_double2(mm[r], 0.0);
+  }
+  __syncthreads();
+  for (int e = tid; e < kJP * kJP; e += blockDim.x) {
+    const int r = e / kJP, c = e % kJP;
+    if (r < c) {
+      const double2 g = make_double2(gs[r][c].x, xs[r][c].x - xs[c][r].x);
+      gs[r][c] = g;
+      gs[c][r] = cconj(g);
     }
   }
 }
@@ -451,38 +527,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
   bool fresh = false;          // gs holds the Gram matrix of the current vectors
   for (int pass = 0; pass < 2; ++pass) {
     if (!fresh) {
-      // ---- Gram matrix G = X X^H on the matrix cores: wave w forms quadrant
-      // (P, Q) = (16 (w / 2), 16 (w % 2)); Gr = Xr Xr^T + Xi Xi^T,
-      // Gi = Xi Xr^T - Xr Xi^T over k-steps of 4 columns.
-      const int lane = tid & 63, wave = tid >> 6;
-      const int P = (wave >> 1) * 16, Q = (wave & 1) * 16;
-      const int li = lane & 15, lk = lane >> 4;
-      v4d grr = {0.0, 0.0, 0.0, 0.0}, gii = {0.0, 0.0, 0.0, 0.0};
-      for (int c0 = 0; c0 < len; c0 += 32) {
-        jac_load_chunk(xs, x, len, c0, vrow);
-        __syncthreads();
-#pragma unroll
-        for (int k0 = 0; k0 < 32; k0 += 4) {
-          const double2 av = xs[P + li][k0 + lk];     // A = X[P + i][k]
-          const double2 bv = xs[Q + li][k0 + lk];     // B = X[Q + j][k] (transposed)
-          grr = mfma16x16x4(av.x, bv.x, grr);
-          grr = mfma16x16x4(av.y, bv.y, grr);
-          gii = mfma16x16x4(av.y, bv.x, gii);
-          gii = mfma16x16x4(-av.x, bv.y, gii);
-        }
-        __syncthreads();
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) gs[P + 4 * r + lk][Q + li] = make_double2(grr[r], gii[r]);
-      __syncthreads();
-      // The two triangles come from different accumulation orders and differ
-      // in the last bits; every decision must see one value per pair, so the
-      // matrix is made exactly Hermitian from its upper triangle.
-      for (int e = tid; e < kJP * kJP; e += blockDim.x) {
-        const int r = e / kJP, c = e % kJP;
-        if (r > c) gs[r][c] = cconj(gs[c][r]);
-        else if (r == c) gs[r][c].y = 0.0;
-      }
+      jac_gram(xs, gs, x, len, vrow);
       if (tid == 0) atomicAdd(&st[sid].gram_units, (unsigned long long)nv * nv * len);
     }
     __syncthreads();
