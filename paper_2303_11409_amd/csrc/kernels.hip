@@ -391,6 +391,34 @@ __device__ __forceinline__ void jac_pair_ordered(int s, int k, int& p, int& q) {
   q = max(i, j);
 }
 
+// Pair k of round-robin step s over the kJP rows as (p, q), p < q: the pairs
+// of rr_pair(s, k, kJP), (s + k, s - k) mod (kJP - 1) and (s, kJP - 1) for
+// k = 0, computed with selects instead of divisions (s < kJP - 1, k < kJP / 2).
+__device__ __forceinline__ void jac_pair_fast(int s, int k, int& p, int& q) {
+  int i = s + k;
+  i = i >= kJP - 1 ? i - (kJP - 1) : i;
+  int j = s - k;
+  j = j < 0 ? j + (kJP - 1) : j;
+  j = k == 0 ? kJP - 1 : j;
+  p = min(i, j);
+  q = max(i, j);
+}
+
+// Workgroup-wide OR of a predicate with one barrier: lane 0 of each
+// wavefront publishes its wavefront's ballot in slot `parity` of flags, which
+// alternates between calls, so a slot is rewritten only after every thread
+// has passed the barrier of the call in between.  Every thread of the
+// workgroup must make the same sequence of calls.
+__device__ __forceinline__ bool block_any(int pred, int4* flags, int& parity) {
+  const bool w = __ballot(pred) != 0ull;
+  int* f = reinterpret_cast<int*>(flags + parity);
+  if ((threadIdx.x & 63) == 0) f[threadIdx.x >> 6] = w ? 1 : 0;
+  __syncthreads();
+  const int4 v = flags[parity];
+  parity ^= 1;
+  return (v.x | v.y | v.z | v.w) != 0;
+}
+
 // True if the pair (p, q) of a Gram matrix with diagonal alpha, beta and
 // off-diagonal gamma is above the rotation threshold (the test of
 // jac_rotation without computing the rotation).
@@ -402,7 +430,8 @@ __device__ __forceinline__ bool jac_needs(double al, double be, double2 g, doubl
 // True if any off-diagonal pair of the Hermitian gs is above the threshold:
 // thread t checks the upper-triangle entries of its 2 x 2 block (rows
 // 2 (t / 16), columns 2 (t % 16)).  Uniform across the workgroup.
-__device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 1], double tol, double floor_g) {
+__device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 1], double tol, double floor_g,
+                                              int4* anyf, int& parity) {
   const int p0 = 2 * (threadIdx.x >> 4), q0 = 2 * (threadIdx.x & 15);
   int f = 0;
 #pragma unroll
@@ -412,7 +441,7 @@ __device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 1], double tol
       const int p = p0 + i, q = q0 + j;
       if (p < q && jac_needs(gs[p][p].x, gs[q][q].x, gs[p][q], tol, floor_g)) f = 1;
     }
-  return __syncthreads_or(f) != 0;
+  return block_any(f, anyf, parity);
 }
 
 // Rotations of the Gram matrix gs (in LDS) until no pair exceeds the
@@ -425,29 +454,31 @@ __device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 1], double tol
 // sweep one parallel test over all pairs replaces the sweep that would find
 // nothing to rotate (it would leave G and W unchanged).
 __device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], double4* rot,
-                             double tol, double floor_g, int max_inner) {
+                             double tol, double floor_g, int max_inner, int4* anyf, int& parity) {
   const int tid = threadIdx.x;
   const int A = tid >> 4, B = tid & 15;
   for (int inner = 0; inner < max_inner; ++inner) {
     for (int s2 = 0; s2 < kJP - 1; ++s2) {
+      // G and W change only in update phases, each closed by a barrier, so
+      // this thread's block is read before the rotations are published
+      int pa, qa, pb, qb;
+      jac_pair_fast(s2, A, pa, qa);
+      jac_pair_fast(s2, B, pb, qb);
+      double2 g00 = gs[pa][pb], g01 = gs[pa][qb], g10 = gs[qa][pb], g11 = gs[qa][qb];
+      double2 w00 = ws[pa][pb], w01 = ws[pa][qb], w10 = ws[qa][pb], w11 = ws[qa][qb];
       int flag = 0;
       if (tid < kJP / 2) {
         int p, q;
-        jac_pair_ordered(s2, tid, p, q);
+        jac_pair_fast(s2, tid, p, q);
         double c = 1.0, wr = 0.0, wi = 0.0;
         const double2 g = gs[p][q];
         flag = jac_rotation(gs[p][p].x, gs[q][q].x, g.x, g.y, tol, floor_g, c, wr, wi) ? 1 : 0;
         rot[tid] = make_double4(c, wr, wi, flag ? 1.0 : 0.0);
       }
-      if (!__syncthreads_or(flag)) continue;
-      int pa, qa, pb, qb;
-      jac_pair_ordered(s2, A, pa, qa);
-      jac_pair_ordered(s2, B, pb, qb);
+      if (!block_any(flag, anyf, parity)) continue;
       const double4 ra = rot[A], rb = rot[B];
       if (ra.w != 0.0 || rb.w != 0.0) {
-        double2 g00 = gs[pa][pb], g01 = gs[pa][qb], g10 = gs[qa][pb], g11 = gs[qa][qb];
         if (ra.w != 0.0) {        // rows pa, qa: U from the left, also on W
-          double2 w00 = ws[pa][pb], w01 = ws[pa][qb], w10 = ws[qa][pb], w11 = ws[qa][qb];
           rot_pair(g00, g10, ra.x, ra.y, ra.z);
           rot_pair(g01, g11, ra.x, ra.y, ra.z);
           rot_pair(w00, w10, ra.x, ra.y, ra.z);
@@ -462,7 +493,7 @@ __device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], dou
       }
       __syncthreads();
     }
-    if (!jac_any_above(gs, tol, floor_g)) break;
+    if (!jac_any_above(gs, tol, floor_g, anyf, parity)) break;
   }
   __syncthreads();
 }
@@ -492,6 +523,8 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
   __shared__ double gmax;
   __shared__ int vrow[kJP];
   __shared__ double4 rot[kJP / 2];
+  __shared__ int4 anyf[2];
+  int parity = 0;
   int lo = 0, hi = njb - 1;
   const int pid = blockIdx.x;
   while (lo < hi) {
@@ -539,7 +572,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
       for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
       if (tid == 0) gmax = m;
     }
-    const bool need = jac_any_above(gs, tol, floor_g);
+    const bool need = jac_any_above(gs, tol, floor_g, anyf, parity);
     if (!need) break;
     if (pass == 0 && tid == 0) atomicAdd(&st[sid].rot_this_sweep, 1);
     // ---- diagonalise G by rotations, W = accumulated product
@@ -550,13 +583,13 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
     __syncthreads();
     const double ptol = pass == 0 ? fmax(tol, kJacLoose) : tol;
     const double pfloor = pass == 0 ? fmax(floor_g, kJacNoise * DBL_EPSILON * gmax) : floor_g;
-    if (pass == 0 && !jac_any_above(gs, ptol, pfloor)) {
+    if (pass == 0 && !jac_any_above(gs, ptol, pfloor, anyf, parity)) {
       // nothing above the coarse thresholds: gs is still the Gram matrix of
       // the unchanged vectors, go straight to the full-tolerance pass
       fresh = true;
       continue;
     }
-    jac_gram_eig(gs, ws, rot, ptol, pfloor, max_inner);
+    jac_gram_eig(gs, ws, rot, ptol, pfloor, max_inner, anyf, parity);
     // ---- rotate the vectors (and the accumulator of a tall sector)
     jac_apply(xs, ws, x, len, vrow);
     if (tall) jac_apply(xs, ws, accbuf + sw.acc, n, vrow);
