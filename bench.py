@@ -27,6 +27,33 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
+
+# HBM bytes per launch of jacobi_block_step on this workload, from two
+# rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline`
+# (FETCH_SIZE, WRITE_SIZE; mean over the launches) scaled by the same counters
+# on a plain 256 MiB copy (`bench.py --copy-probe`: FETCH_SIZE reads 131085.2
+# KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99982 and writes
+# by 1).  Valid only for the kernel source it was taken on.
+MEASURED_TRAFFIC = {
+    "kernels_sha256": "891f9fd10b1e72786f253c0c0a11d5199d9652c78535f391823423c426ab1a59",
+    "fetch_kib": 21003.362, "write_kib": 35415.419,
+    "fetch_scale": 262144.0 / 131085.208, "write_scale": 1.0,
+}
+
+
+def measured_traffic():
+    """Bytes per launch from the counters, or None once the kernel source changed."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2303_11409_amd", "csrc", "kernels.hip")
+    try:
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    t = MEASURED_TRAFFIC
+    if sha != t["kernels_sha256"]:
+        return None
+    return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 METRIC = "gate applies/s + sector-GEMM TFLOP/s at χ=2048 vs plain; p50/p99 latency"
 
 
@@ -69,6 +96,23 @@ def cpu_baseline(cfg, seconds: float):
                       f"SVD per gate; {el:.1f} s"}
 
 
+def copy_probe(torch) -> int:
+    """Three launches of a plain copy of a known size: FETCH_SIZE and WRITE_SIZE of
+    these dispatches, divided by the bytes moved, scale the counters read on the
+    Jacobi kernel to HBM bytes."""
+    n = 1 << 25                                   # 2^25 float64 = 256 MiB
+    src = torch.arange(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ok = bool(torch.equal(dst, src))
+    print(json.dumps({"copy_probe": {"bytes_read_per_launch": n * 8, "bytes_written_per_launch": n * 8,
+                                     "launches": 3, "ok": ok}}), flush=True)
+    return 0 if ok else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +120,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 256 MiB device-to-device copy three times (the "
+                         "reference kernel for scaling HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -85,6 +132,9 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.copy_probe:
+        return copy_probe(torch)
 
     from paper_2303_11409_amd import MPS, TorchDevice
     from workloads import circuits
@@ -149,7 +199,7 @@ def main() -> int:
     avg_ms = agg["jacobi_ms"] / launches
     achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
                 "kernel": "jacobi_block_step", "avg_launch_ms": avg_ms,
                 "flops_per_launch": per_launch_flops, "launches": launches}
     props = torch.cuda.get_device_properties(0)
