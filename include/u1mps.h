@@ -106,7 +106,7 @@ typedef struct {
  * update product. */
 typedef struct {
   long long gates;             /* two-site updates applied                    */
-  long long layers;            /* batches (mps_apply_layer calls)             */
+  long long layers;            /* layers (apply calls touching this state)    */
   long long sectors;           /* Theta(m) sectors decomposed                 */
   long long sweeps;            /* Jacobi sweeps summed over sectors           */
   long long rotations;         /* Jacobi block pairs rotated                  */
@@ -168,6 +168,21 @@ mps_status mps_apply_gate(mps_t h, int site, const mps_z u2[4], double* discarde
  * gates one by one in any order. */
 mps_status mps_apply_layer(mps_t h, int ngates, const int* sites,
                            const mps_z* u2s, double* discarded);
+
+/* Batching form: one layer of each of nh independent states (different
+ * circuits, sizes and cut options, one local dimension d, one stream),
+ * executed together -- the updates of all states share every launch, so
+ * the device holds many independent sectors at once (the paper's
+ * independent two-site updates, Sec. II, across circuits).  State i takes
+ * ngates[i] gates (0 allowed) on pairwise disjoint site pairs; sites and u2s
+ * hold the gates of all states back to back in state order, as does
+ * discarded (may be NULL).  hs[0]'s workspaces and its max_sweeps and
+ * jacobi_tol serve the batch; each state keeps its own chi_max, cutoff and
+ * zero_tol.  The result for each state equals mps_apply_layer on it alone.
+ * If any update fails no state changes.  A state may appear once.
+ * Errors: as mps_apply_layer; MPS_E_ARG for mixed d or streams. */
+mps_status mps_apply_batch(int nh, const mps_t* hs, const int* ngates,
+                           const int* sites, const mps_z* u2s, double* discarded);
 
 /* Re-truncate bond `bond` (1..L-1) from its stored Schmidt values with the
  * same rule (chi_max, cutoff, the handle's zero_tol), without an SVD: the

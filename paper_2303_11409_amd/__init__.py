@@ -5,4 +5,4 @@ gate, per-sector Jacobi SVD, global truncation, update) runs in the HIP
 kernels of ``libu1mps.so`` behind the C ABI of ``include/u1mps.h``;
 ``binding`` is its ctypes wrapper.
 """
-from .binding import MPS, MPSError, TorchDevice, lib  # noqa: F401
+from .binding import MPS, MPSError, TorchDevice, apply_batch, lib  # noqa: F401

@@ -14,7 +14,7 @@ import ctypes as C
 import os
 import sys
 import weakref
-from typing import Dict, List, Optional, Sequence
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -62,7 +62,7 @@ class mps_stats(C.Structure):
 
 
 EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_destroy", "mps_apply_gate",
-           "mps_apply_layer", "mps_truncate", "mps_amplitude", "mps_norm", "mps_bond_sectors",
+           "mps_apply_layer", "mps_apply_batch", "mps_truncate", "mps_amplitude", "mps_norm", "mps_bond_sectors",
            "mps_bond_lambda", "mps_site_tensor", "mps_set_timing", "mps_get_stats",
            "mps_reset_stats", "mps_sync", "mps_last_error"]
 
@@ -87,6 +87,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mps_destroy": (st, [h]),
         "mps_apply_gate": (st, [h, C.c_int, P(mps_z), P(C.c_double)]),
         "mps_apply_layer": (st, [h, C.c_int, P(C.c_int), P(mps_z), P(C.c_double)]),
+        "mps_apply_batch": (st, [C.c_int, P(h), P(C.c_int), P(C.c_int), P(mps_z), P(C.c_double)]),
         "mps_truncate": (st, [h, C.c_int, C.c_int, C.c_double, P(C.c_double)]),
         "mps_amplitude": (st, [h, C.c_int, P(C.c_int), P(mps_z)]),
         "mps_norm": (st, [h, P(C.c_double)]),
@@ -323,3 +324,34 @@ class MPS:
 
     def sync(self) -> None:
         _check(self._lib.mps_sync(self._h))
+
+
+def apply_batch(states: Sequence["MPS"], layers: Sequence[Tuple[Sequence[int], Sequence[np.ndarray]]]
+                ) -> List[np.ndarray]:
+    """One layer of each state in one call of mps_apply_batch (the batching form).
+
+    layers[i] = (sites, us) for states[i]; empty layers are allowed.  Returns
+    each state's discarded weights."""
+    if len(states) != len(layers):
+        raise ValueError("one layer per state")
+    n = len(states)
+    if n == 0:
+        return []
+    lib_ = states[0]._lib
+    hs = (C.c_void_p * n)(*[m._h for m in states])
+    counts = [len(s) for s, _ in layers]
+    total = sum(counts)
+    c_counts = (C.c_int * n)(*counts)
+    c_sites = (C.c_int * max(total, 1))(*[int(x) for s, _ in layers for x in s])
+    mats = [np.asarray(u, dtype=np.complex128).reshape(2, 2) for _, us in layers for u in us]
+    if len(mats) != total:
+        raise ValueError("one 2x2 matrix per gate")
+    zu = np.ascontiguousarray(np.stack(mats)) if mats else np.zeros((1, 2, 2), dtype=np.complex128)
+    disc = np.zeros(max(total, 1), dtype=np.float64)
+    _check(lib_.mps_apply_batch(n, hs, c_counts, c_sites, zu.ctypes.data_as(C.POINTER(mps_z)),
+                                disc.ctypes.data_as(C.POINTER(C.c_double))))
+    out, o = [], 0
+    for c in counts:
+        out.append(disc[o:o + c].copy())
+        o += c
+    return out

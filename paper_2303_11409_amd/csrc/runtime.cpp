@@ -336,17 +336,27 @@ struct BatchPlan {
   double theta_flops = 0.0;
 };
 
-mps_status plan_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s, BatchPlan& P) {
-  const int d = h->d;
+// One two-site update of a batch: the state it acts on, its left site and its
+// 2x2 mode unitary.  A batch may mix states (of one local dimension d).
+struct GateRef {
+  mps_state* h;
+  int site;
+  const mps_z* u;
+};
+
+mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
+  const int ng = (int)refs.size();
+  const int d = refs[0].h->d;
   P.gates.resize(ng);
   P.gp.resize(ng);
   P.coef.assign((size_t)ng * (2 * d - 1) * d * d, make_double2(0.0, 0.0));
   for (int g = 0; g < ng; ++g) {
-    const int s = sites[g];
+    mps_state* h = refs[g].h;
+    const int s = refs[g].site;
     const Bond& BL = h->bonds[s];
     const Bond& BM = h->bonds[s + 1];
     const Bond& BR = h->bonds[s + 2];
-    gate_blocks(u2s + 4 * g, d, P.coef.data() + (size_t)g * (2 * d - 1) * d * d);
+    gate_blocks(refs[g].u, d, P.coef.data() + (size_t)g * (2 * d - 1) * d * d);
     GateWork gw{};
     gw.bl = h->site[s];
     gw.br = h->site[s + 1];
@@ -478,9 +488,16 @@ mps_status check_device_limits(mps_state* h, const BatchPlan& P) {
 }
 
 // ---- the batched two-site update ------------------------------------------
-mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s, double* discarded) {
+// The update of every gate in refs, all in one set of launches on the stream of
+// refs[0]'s state, whose workspaces, timing and Jacobi options (max_sweeps,
+// jacobi_tol) serve the whole batch.  Per-gate and per-sector statistics go
+// to the state each gate belongs to.  No state changes unless every gate of
+// the batch succeeds.
+mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
+  mps_state* h = refs[0].h;
+  const int ng = (int)refs.size();
   BatchPlan P;
-  STCHK(plan_batch(h, ng, sites, u2s, P));
+  STCHK(plan_batch(refs, P));
   STCHK(check_device_limits(h, P));
   const int ns = (int)P.secs.size();
 
@@ -603,16 +620,20 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
 
   for (int s = 0; s < ns; ++s) {
     const SectorWork& sw = P.secs[s];
-    h->stats.sectors += 1;
-    h->stats.sweeps += jst[s].sweeps;
-    h->stats.rotations += jst[s].rotations;
-    h->stats.jacobi_flops += 8.0 * double(jst[s].gram_units) + 8.0 * double(jst[s].apply_units);
     if (!jst[s].converged)
       return fail(MPS_E_NOCONV, "Jacobi SVD of sector m=%d (%dx%d) did not converge in %d sweeps",
                   sw.m, sw.r, sw.c, h->opts.max_sweeps);
   }
   for (int g = 0; g < ng; ++g)
-    if (cut[g].flags) return fail(MPS_E_NUMERIC, "two-site matrix at site %d vanished or is not finite", sites[g]);
+    if (cut[g].flags)
+      return fail(MPS_E_NUMERIC, "two-site matrix at site %d vanished or is not finite", refs[g].site);
+  for (int s = 0; s < ns; ++s) {
+    mps_stats& gs = refs[P.secs[s].gate].h->stats;
+    gs.sectors += 1;
+    gs.sweeps += jst[s].sweeps;
+    gs.rotations += jst[s].rotations;
+    gs.jacobi_flops += 8.0 * double(jst[s].gram_units) + 8.0 * double(jst[s].apply_units);
+  }
   h->stats.theta_flops += P.theta_flops;
 
   // new bond tables and update lists
@@ -625,9 +646,10 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
   int ntiles = 0;
   std::vector<Bond> newb(ng);
   for (int g = 0; g < ng; ++g) {
-    const int s = sites[g];
-    const int chil = h->bonds[s].dim();
-    const int chir = h->bonds[s + 2].dim();
+    mps_state* hg = refs[g].h;
+    const int s = refs[g].site;
+    const int chil = hg->bonds[s].dim();
+    const int chir = hg->bonds[s + 2].dim();
     Bond& nb = newb[g];
     for (int i = P.gp[g].sec_begin; i < P.gp[g].sec_end; ++i) {
       if (kept[i] <= 0) continue;
@@ -636,12 +658,12 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
     }
     nb.finish();
     const int chin = nb.dim();
-    if (chin > h->cap[s + 1] || chin <= 0)
-      return fail(MPS_E_NUMERIC, "internal: new bond dimension %d outside 1..%d", chin, h->cap[s + 1]);
-    upds[g].br_new = h->site[s + 1];
-    upds[g].lam_new = h->lam[s + 1];
+    if (chin > hg->cap[s + 1] || chin <= 0)
+      return fail(MPS_E_NUMERIC, "internal: new bond dimension %d outside 1..%d", chin, hg->cap[s + 1]);
+    upds[g].br_new = hg->site[s + 1];
+    upds[g].lam_new = hg->lam[s + 1];
     upds[g].ldr = chir;
-    fill_ptr[g] = h->site[s];
+    fill_ptr[g] = hg->site[s];
     fill_cnt[g] = (long long)chil * chin;
     maxfill = std::max(maxfill, fill_cnt[g]);
     int k = 0;
@@ -653,9 +675,9 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
       GemmWork gw{};
       gw.a = raw + sw.off;
       gw.lda = sw.c;
-      gw.b = h->site[s + 1] + (size_t)o * chir + sw.clo;
+      gw.b = hg->site[s + 1] + (size_t)o * chir + sw.clo;
       gw.ldb = chir;
-      gw.c = h->site[s] + (size_t)sw.rlo * chin + o;
+      gw.c = hg->site[s] + (size_t)sw.rlo * chin + o;
       gw.ldc = chin;
       gw.m = sw.r;
       gw.n = kept[i];
@@ -667,13 +689,9 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
       gw.tile_begin = ntiles;
       ntiles += ((gw.m + kGemmTile - 1) / kGemmTile) * gw.tiles_n;
       gemms.push_back(gw);
-      h->stats.update_flops += 8.0 * sw.r * double(sw.c) * kept[i];
+      hg->stats.update_flops += 8.0 * sw.r * double(sw.c) * kept[i];
       ++k;
     }
-    if (discarded) discarded[g] = cut[g].discarded;
-    h->stats.max_discarded = std::max(h->stats.max_discarded, cut[g].discarded);
-    if (std::isfinite(cut[g].margin))
-      h->stats.min_margin = std::min(h->stats.min_margin, cut[g].margin);
   }
   Packer pu;
   const size_t u_rows = pu.add(rows.data(), rows.size() * sizeof(RowWork));
@@ -694,12 +712,38 @@ mps_status apply_batch(mps_state* h, int ng, const int* sites, const mps_z* u2s,
     HIPCHK(launch_zgemm(at<GemmWork>(h->upd, u_gemm), (int)gemms.size(), ntiles, h->st));
     STCHK(tm.stop());
   }
-  for (int g = 0; g < ng; ++g) h->bonds[sites[g] + 1] = newb[g];
-  h->stats.gates += ng;
-  h->stats.layers += 1;
+  for (int g = 0; g < ng; ++g) {
+    mps_state* hg = refs[g].h;
+    hg->bonds[refs[g].site + 1] = newb[g];
+    if (discarded) discarded[g] = cut[g].discarded;
+    hg->stats.gates += 1;
+    hg->stats.max_discarded = std::max(hg->stats.max_discarded, cut[g].discarded);
+    if (std::isfinite(cut[g].margin)) hg->stats.min_margin = std::min(hg->stats.min_margin, cut[g].margin);
+    if (g == 0 || refs[g - 1].h != hg) hg->stats.layers += 1;
+  }
   h->stats.theta_launches += 1;
   h->stats.select_launches += 1;
   h->stats.update_launches += 3;
+  return MPS_OK;
+}
+
+// Argument checks of one state's layer: sites in range, finite gates, disjoint pairs.
+mps_status check_layer(mps_t h, int ngates, const int* sites, const mps_z* u2s) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (ngates < 0) return fail(MPS_E_ARG, "negative gate count");
+  if (ngates == 0) return MPS_OK;
+  if (!sites || !u2s) return fail(MPS_E_ARG, "sites and u2s are required");
+  std::vector<int> order(ngates);
+  for (int g = 0; g < ngates; ++g) {
+    if (sites[g] < 0 || sites[g] > h->L - 2) return fail(MPS_E_ARG, "gate site %d outside 0..L-2", sites[g]);
+    for (int k = 0; k < 4; ++k)
+      if (!std::isfinite(u2s[4 * g + k].re) || !std::isfinite(u2s[4 * g + k].im))
+        return fail(MPS_E_ARG, "non-finite gate element");
+    order[g] = sites[g];
+  }
+  std::sort(order.begin(), order.end());
+  for (int g = 1; g < ngates; ++g)
+    if (order[g] - order[g - 1] < 2) return fail(MPS_E_ARG, "gates of one layer must act on disjoint site pairs");
   return MPS_OK;
 }
 
@@ -932,22 +976,39 @@ mps_status mps_destroy(mps_t h) {
 }
 
 mps_status mps_apply_layer(mps_t h, int ngates, const int* sites, const mps_z* u2s, double* discarded) {
-  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
-  if (ngates < 0) return fail(MPS_E_ARG, "negative gate count");
+  STCHK(check_layer(h, ngates, sites, u2s));
   if (ngates == 0) return MPS_OK;
-  if (!sites || !u2s) return fail(MPS_E_ARG, "sites and u2s are required");
-  std::vector<int> order(ngates);
-  for (int g = 0; g < ngates; ++g) {
-    if (sites[g] < 0 || sites[g] > h->L - 2) return fail(MPS_E_ARG, "gate site %d outside 0..L-2", sites[g]);
-    for (int k = 0; k < 4; ++k)
-      if (!std::isfinite(u2s[4 * g + k].re) || !std::isfinite(u2s[4 * g + k].im))
-        return fail(MPS_E_ARG, "non-finite gate element");
-    order[g] = sites[g];
+  std::vector<GateRef> refs(ngates);
+  for (int g = 0; g < ngates; ++g) refs[g] = {h, sites[g], u2s + 4 * g};
+  return apply_batch(refs, discarded);
+}
+
+mps_status mps_apply_batch(int nh, const mps_t* hs, const int* ngates, const int* sites, const mps_z* u2s,
+                           double* discarded) {
+  if (nh < 0) return fail(MPS_E_ARG, "negative state count");
+  if (nh == 0) return MPS_OK;
+  if (!hs || !ngates) return fail(MPS_E_ARG, "hs and ngates are required");
+  std::vector<GateRef> refs;
+  long long off = 0;
+  for (int i = 0; i < nh; ++i) {
+    mps_t h = hs[i];
+    if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle at index %d", i);
+    for (int k = 0; k < i; ++k)
+      if (hs[k] == h) return fail(MPS_E_ARG, "state %d appears twice in one batch", i);
+    if (ngates[i] < 0) return fail(MPS_E_ARG, "negative gate count for state %d", i);
+    if (ngates[i] == 0) continue;
+    if (!sites || !u2s) return fail(MPS_E_ARG, "sites and u2s are required");
+    STCHK(check_layer(h, ngates[i], sites + off, u2s + 4 * off));
+    if (!refs.empty()) {
+      mps_state* h0 = refs[0].h;
+      if (h->d != h0->d) return fail(MPS_E_ARG, "states of one batch must share the local dimension");
+      if (h->st != h0->st) return fail(MPS_E_ARG, "states of one batch must share one stream");
+    }
+    for (int g = 0; g < ngates[i]; ++g) refs.push_back({h, sites[off + g], u2s + 4 * (off + g)});
+    off += ngates[i];
   }
-  std::sort(order.begin(), order.end());
-  for (int g = 1; g < ngates; ++g)
-    if (order[g] - order[g - 1] < 2) return fail(MPS_E_ARG, "gates of one layer must act on disjoint site pairs");
-  return apply_batch(h, ngates, sites, u2s, discarded);
+  if (refs.empty()) return MPS_OK;
+  return apply_batch(refs, discarded);
 }
 
 mps_status mps_apply_gate(mps_t h, int site, const mps_z u2[4], double* discarded) {

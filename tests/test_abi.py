@@ -76,3 +76,16 @@ def test_argument_errors():
     assert lib.mps_norm(None, None) == -1
     assert lib.mps_destroy(None) == 0
     assert isinstance(lib.mps_last_error(), bytes)
+
+
+def test_apply_batch_argument_errors():
+    """mps_apply_batch rejects bad arguments before touching any device state."""
+    lib = binding.lib()
+    assert lib.mps_apply_batch(0, None, None, None, None, None) == 0
+    assert lib.mps_apply_batch(-1, None, None, None, None, None) == -1
+    hs = (C.c_void_p * 2)(None, None)
+    counts = (C.c_int * 2)(1, 0)
+    sites = (C.c_int * 1)(0)
+    assert lib.mps_apply_batch(2, hs, counts, sites, None, None) == -1
+    assert "invalid handle" in lib.mps_last_error().decode()
+    assert lib.mps_apply_batch(2, hs, None, sites, None, None) == -1

@@ -238,3 +238,44 @@ def test_full_32_mode_circuit_vs_stored_oracle(mps_cls):
     close_amps(m.amplitudes(pats), amp)
     assert abs(m.norm2() - ref["norm2"]) <= 1e-9 * ref["norm2"]
     m.close()
+
+
+def test_batching_form_equals_each_state_alone(mps_cls):
+    """Batching form: the layers of several circuits of different sizes, cuts and
+    depths go through mps_apply_batch together; every state ends bitwise equal
+    to the same circuit run alone (per-sector work does not depend on what
+    shares the launch), and one of them matches the oracle."""
+    from paper_2303_11409_amd import apply_batch
+    mix = circuits.config_batch_mix(5, seed=11, l_range=(6, 14), chi_choices=(8, 16, 32))
+    alone = []
+    for cfg in mix:
+        m, disc = run_gpu(mps_cls, cfg["occupation"], 4, None, chi_max=cfg["chi_max"], cutoff=cfg["cutoff"],
+                          layered=True, layers=cfg["layers"])
+        alone.append((m, disc))
+    states = [mps_cls(cfg["occupation"], 4, chi_max=cfg["chi_max"], cutoff=cfg["cutoff"]) for cfg in mix]
+    discs = [[] for _ in mix]
+    depth = max(len(cfg["layers"]) for cfg in mix)
+    for k in range(depth):
+        lays = []
+        for cfg in mix:
+            lay = cfg["layers"][k] if k < len(cfg["layers"]) else []
+            lays.append(([g.site for g in lay], [g.u for g in lay]))
+        for i, d in enumerate(apply_batch(states, lays)):
+            discs[i].extend(d)
+    for i, cfg in enumerate(mix):
+        m0, d0 = alone[i]
+        L, N = cfg["L"], cfg["L"] // 2
+        pats = circuits.sample_patterns(L, N, 4, 100, 17 + i)
+        assert np.array_equal(states[i].amplitudes(pats), m0.amplitudes(pats)), cfg["name"]
+        assert np.array_equal(np.array(discs[i]), d0), cfg["name"]
+        for b in range(L + 1):
+            assert states[i].bond_sectors(b) == m0.bond_sectors(b), (cfg["name"], b)
+    cfg = mix[0]
+    ref = dense_mps.DenseMPS(cfg["occupation"], 4, chi_max=cfg["chi_max"], cutoff=cfg["cutoff"]).run(cfg["gates"])
+    pats = circuits.sample_patterns(cfg["L"], cfg["L"] // 2, 4, 100, 3)
+    close_amps(states[0].amplitudes(pats), ref.amplitudes(pats))
+    check_bookkeeping(states[0], ref)
+    for m in states:
+        m.close()
+    for m, _ in alone:
+        m.close()

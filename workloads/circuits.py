@@ -273,3 +273,22 @@ def config_plain_gpu(seed: int = 2) -> dict:
 def config_precision(seed: int = 3, chi_max: int = 2048) -> dict:
     """L=64, 32 photons in even modes, d=4, 64 brickwork layers, chi_max=2048."""
     return config_brickwork(64, 32, "even", 4, 64, chi_max, 1e-12, seed, f"L64_N32_d4_chi{chi_max}")
+
+
+def config_batch_mix(n_circuits: int = 512, seed: int = 4, l_range=(16, 48),
+                     chi_choices=(64, 128, 256, 512), cutoff: float = 1e-12,
+                     depth_scale: float = 1.0) -> list:
+    """The batching-form mix: circuit i has L ~ U{l_range}, floor(L/2) single
+    photons in the first floor(L/2) modes, d = 4, a brickwork of depth
+    round(depth_scale * L) with circuit seed 4000 + i, chi_max drawn from
+    chi_choices, discarded-weight cutoff 1e-12.  L and chi_max are drawn from
+    numpy.random.default_rng(seed) in circuit order (L first)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n_circuits):
+        L = int(rng.integers(l_range[0], l_range[1] + 1))
+        chi = int(chi_choices[int(rng.integers(0, len(chi_choices)))])
+        depth = max(1, int(round(depth_scale * L)))
+        out.append(config_brickwork(L, L // 2, "first", 4, depth, chi, cutoff, 4000 + i,
+                                    f"mix{i}_L{L}_chi{chi}"))
+    return out
