@@ -11,8 +11,11 @@ region (inputs resident in HBM).
 
 Printed: one JSON line (stdout) with gate applies/s, the roofline of the
 dominant kernel (HIP events on the library's stream over the timed region)
-and the CPU oracle timed on a bounded prefix of the same circuit.
-Progress goes to stderr.
+and the CPU oracle timed on a bounded prefix of the same circuit; under
+"forms", the batching form (several circuits per launch: copies of this
+circuit with other seeds, and the first circuits of the mixed-size workload)
+and the serving form (Poisson arrivals, continuous batching, p50/p99 latency
+from arrival to result).  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -113,6 +116,63 @@ def copy_probe(torch) -> int:
     return 0 if ok else 1
 
 
+def run_batched(cfgs, MPS, apply_batch, dev, keep_first=False):
+    """The batching form: layer k of every circuit in one mps_apply_batch call.
+    States are created before the timed region.  Returns (gates, seconds, first
+    state if keep_first)."""
+    import torch
+    states = [MPS(c["occupation"], c["d"], chi_max=c["chi_max"], cutoff=c["cutoff"], device=dev) for c in cfgs]
+    lays = []
+    depth = max(len(c["layers"]) for c in cfgs)
+    for k in range(depth):
+        row = []
+        for c in cfgs:
+            lay = c["layers"][k] if k < len(c["layers"]) else []
+            row.append(([g.site for g in lay], [g.u for g in lay]))
+        lays.append(row)
+    gates = sum(len(s) for row in lays for s, _ in row)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for row in lays:
+        apply_batch(states, row)
+    for m in states:
+        m.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    first = states[0] if keep_first else None
+    for m in states[1 if keep_first else 0:]:
+        m.close()
+    return gates, el, first
+
+
+def run_serving(args, rate, dev, circuits):
+    """One serving window: Poisson arrivals at `rate` of the serving mix, continuous
+    batching, results read out at completion; no drain after the window."""
+    import numpy as np
+    from paper_2303_11409_amd import serving
+    n = int(rate * args.serve_seconds * 1.2) + 8
+    specs = circuits.serving_mix_specs(n, seed=5)
+    reqs = serving.poisson_requests(specs, rate=rate, seed=5, build=circuits.config_from_spec, n_patterns=16)
+    srv = serving.Server(int(args.serve_budget_gib * 2**30), max_active=args.serve_max_active, device=dev)
+    rep = srv.run(reqs, until=args.serve_seconds)
+    lat = rep.latencies()
+    arrived = sum(1 for r in reqs if r.arrival < rep.seconds)
+    done_gates = sum(len(r.cfg["gates"]) for r in rep.completed)
+    mean_gates = float(np.mean([sp["depth"] * (sp["L"] // 2) - (sp["depth"] // 2) * (1 - sp["L"] % 2)
+                                for sp in specs]))
+    return {
+        "arrival_rate": rate, "window_s": rep.seconds, "arrived": arrived, "completed": len(rep.completed),
+        "pending": rep.pending, "iterations": rep.iterations, "peak_active": rep.peak_active,
+        "peak_admitted_gib": rep.peak_bytes / 2**30,
+        "gate_applies_per_s": rep.gates / rep.seconds,
+        "completed_gate_applies_per_s": done_gates / rep.seconds,
+        "requests_per_s": len(rep.completed) / rep.seconds,
+        "latency_s": {"p50": percentile(list(lat), 50), "p99": percentile(list(lat), 99),
+                      "max": float(lat.max()) if lat.size else None},
+        "offered_gate_applies_per_s": rate * mean_gates,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +180,17 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-copies", type=int, default=8,
+                    help="batching form: seeds of the same circuit run together (0 = skip)")
+    ap.add_argument("--mix-circuits", type=int, default=64,
+                    help="batching form: first circuits of the mixed-size workload run together (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="serving form: length of each serving window (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="serving form: arrivals per second")
+    ap.add_argument("--serve-low-rate", type=float, default=0.5,
+                    help="serving form: a second window at this rate, within the device's capacity (0 = skip)")
+    ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--serve-budget-gib", type=float, default=96.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the "
                          "reference kernel for scaling HBM byte counters)")
@@ -136,7 +207,7 @@ def main() -> int:
     if args.copy_probe:
         return copy_probe(torch)
 
-    from paper_2303_11409_amd import MPS, TorchDevice
+    from paper_2303_11409_amd import MPS, TorchDevice, apply_batch
     from workloads import circuits
 
     torch.cuda.set_device(0)
@@ -190,8 +261,37 @@ def main() -> int:
                     agg[k] += v
     norm_loss = 1.0 - states[0].norm2()
     max_chi = max(states[0].bond_dims())
+    probe = circuits.sample_patterns(32, 16, 4, 64, 102)
+    plain_amps = states[0].amplitudes(probe)
     for m in states:
         m.close()
+
+    forms = {}
+    if args.batch_copies > 0:
+        B = args.batch_copies
+        log(f"batching form: {B} seeds of the same circuit ...")
+        cfgs = [circuits.config_plain_gpu(seed=2 + i) for i in range(B)]
+        g, el, first = run_batched(cfgs, MPS, apply_batch, dev, keep_first=True)
+        same = bool(np.array_equal(first.amplitudes(probe), plain_amps))
+        first.close()
+        forms["batching_same_circuit"] = {
+            "workload": f"{B} circuits: the plain workload with circuit seeds 2..{B + 1}, "
+                        "each layer of all circuits in one mps_apply_batch call",
+            "circuits": B, "gates": g, "seconds": el, "value": g / el, "unit": "gate applies/s",
+            "vs_plain": (g / el) / (args.steps * ngates / elapsed),
+            "seed2_bitwise_equal_to_plain": same}
+        log(f"  {g / el:.1f} gate applies/s")
+    if args.mix_circuits > 0:
+        n = args.mix_circuits
+        log(f"batching form: first {n} circuits of the mixed workload ...")
+        cfgs = circuits.config_batch_mix(512)[:n]
+        g, el, _ = run_batched(cfgs, MPS, apply_batch, dev)
+        forms["batching_mix"] = {
+            "workload": f"first {n} of 512 mixed circuits (circuit i: L ~ U{{16..48}}, floor(L/2) photons "
+                        "in the first modes, d=4, depth L, chi_max ~ U{64,128,256,512}, cutoff 1e-12, "
+                        "seed 4000+i; mix seed 4), complex128, layer k of all circuits in one call",
+            "circuits": n, "gates": g, "seconds": el, "value": g / el, "unit": "gate applies/s"}
+        log(f"  {g / el:.1f} gate applies/s")
 
     # dominant kernel: the blocked Jacobi step (one launch per round-robin step)
     launches = max(agg["jacobi_launches"], 1)
@@ -204,6 +304,23 @@ def main() -> int:
                 "flops_per_launch": per_launch_flops, "launches": launches}
     props = torch.cuda.get_device_properties(0)
     value = args.steps * ngates / elapsed
+    if args.serve_seconds > 0:
+        log(f"serving form: {args.serve_seconds:.0f} s at {args.serve_rate:g} requests/s ...")
+        forms["serving"] = run_serving(args, args.serve_rate, dev, circuits)
+        forms["serving"]["workload"] = (
+            "Poisson arrivals of the serving mix (95% batching-mix circuits, 5% L=64, 32 photons, "
+            "chi_max=1024, depth 64; request j seed 5000+j, 16 sampled amplitudes each), admitted by "
+            f"an HBM budget of {args.serve_budget_gib:g} GiB and at most {args.serve_max_active} active, "
+            "one batch call per layer of all active requests; window without drain")
+        log(f"  {forms['serving']['gate_applies_per_s']:.1f} gate applies/s, "
+            f"{forms['serving']['completed']} completed")
+        if args.serve_low_rate > 0:
+            log(f"serving form: {args.serve_seconds:.0f} s at {args.serve_low_rate:g} requests/s ...")
+            low = run_serving(args, args.serve_low_rate, dev, circuits)
+            low["note"] = "same mix at an arrival rate within the device's capacity"
+            forms["serving_low_rate"] = low
+            log(f"  {low['gate_applies_per_s']:.1f} gate applies/s, {low['completed']} completed")
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -236,6 +353,7 @@ def main() -> int:
         "device": {"name": props.name, "cus": props.multi_processor_count,
                    "lds_per_block": getattr(props, "shared_memory_per_block", None),
                    "lds_per_cu": getattr(props, "shared_memory_per_multiprocessor", None)},
+        "forms": forms,
         "result": {"norm_loss": norm_loss, "max_bond_dim": max_chi,
                    "max_discarded": agg["max_discarded"], "min_cut_margin": agg["min_margin"]},
     }

@@ -279,3 +279,33 @@ def test_batching_form_equals_each_state_alone(mps_cls):
         m.close()
     for m, _ in alone:
         m.close()
+
+
+def test_serving_form_results_equal_each_request_alone(mps_cls):
+    """Serving form: requests arriving at different times share batch calls with
+    whatever is running; each request's result (norm, discarded weight,
+    amplitudes, bond dimensions) is bitwise the same as the circuit run alone."""
+    from paper_2303_11409_amd import serving
+    cfgs = circuits.config_serving_mix(6, seed=21, l_range=(6, 12), chi_choices=(8, 16, 32),
+                                       large_frac=0.2, large_L=14, large_chi=48)
+    reqs = serving.poisson_requests(cfgs, rate=1.0, seed=2, n_patterns=16)
+    for i, r in enumerate(reqs):
+        r.arrival = [0, 0, 2, 5, 6, 14][i]
+    clock = {"t": -1.0}
+
+    def tick():
+        clock["t"] += 1.0
+        return clock["t"]
+
+    rep = serving.Server(1 << 34, clock=tick).run(reqs)
+    assert len(rep.completed) == len(cfgs) and rep.iterations < sum(len(c["layers"]) for c in cfgs)
+    for r in rep.completed:
+        c = r.cfg
+        m = mps_cls(c["occupation"], 4, chi_max=c["chi_max"], cutoff=c["cutoff"])
+        disc = 0.0
+        for lay in c["layers"]:
+            disc += float(np.sum(m.apply_layer([g.site for g in lay], [g.u for g in lay])))
+        assert np.array_equal(r.result["amplitudes"], m.amplitudes(r.patterns)), c["name"]
+        assert r.result["norm2"] == m.norm2() and r.result["discarded"] == disc, c["name"]
+        assert r.result["bond_dims"] == m.bond_dims(), c["name"]
+        m.close()

@@ -1,0 +1,92 @@
+"""Host logic of the serving form (CPU): the bond-dimension bound used for HBM
+admission, and the continuous-batching scheduler driven with a stand-in state
+class (no device)."""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2303_11409_amd import serving
+from workloads import circuits
+
+
+def brute_caps(L, N, d):
+    """Schmidt-rank bound of every cut of an N-photon state with occupations < d,
+    by enumerating the strings on each side."""
+    caps = []
+    for b in range(L + 1):
+        left = {}
+        for s in itertools.product(range(d), repeat=b):
+            left[sum(s)] = left.get(sum(s), 0) + 1
+        right = {}
+        for s in itertools.product(range(d), repeat=L - b):
+            right[sum(s)] = right.get(sum(s), 0) + 1
+        caps.append(max(1, sum(min(left.get(N - c, 0), right.get(c, 0)) for c in range(N + 1))))
+    return caps
+
+
+@pytest.mark.parametrize("L,N,d", [(6, 3, 4), (7, 4, 3), (5, 5, 2), (8, 4, 5)])
+def test_bond_caps_match_enumeration(L, N, d):
+    assert serving.bond_caps(L, N, d, 0) == brute_caps(L, N, d)
+    capped = serving.bond_caps(L, N, d, 5)
+    assert capped == [min(5, c) for c in brute_caps(L, N, d)]
+
+
+class FakeState:
+    live = 0
+
+    def __init__(self, occ, d, chi_max=0, cutoff=0.0, device=None):
+        self.occ = list(occ)
+        FakeState.live += 1
+
+    def close(self):
+        FakeState.live -= 1
+
+    def norm2(self):
+        return 1.0
+
+    def amplitudes(self, p):
+        return np.zeros(len(p), dtype=np.complex128)
+
+    def bond_dims(self):
+        return [1] * (len(self.occ) + 1)
+
+
+def test_scheduler_continuous_batching_and_budget(monkeypatch):
+    calls = []
+
+    def fake_batch(states, layers):
+        calls.append(len(states))
+        return [np.zeros(len(s)) for s, _ in layers]
+
+    monkeypatch.setattr(serving, "MPS", FakeState)
+    monkeypatch.setattr(serving, "apply_batch", fake_batch)
+    cfgs = circuits.config_batch_mix(6, seed=3, l_range=(6, 10), chi_choices=(8, 16))
+    reqs = serving.poisson_requests(cfgs, rate=1.0, seed=1, n_patterns=4)
+    for i, r in enumerate(reqs):            # arrivals in simulated time units
+        r.arrival = [0, 0, 3, 4, 30, 31][i]
+    clock = {"t": -1.0}
+
+    def tick():
+        clock["t"] += 1.0
+        return clock["t"]
+
+    per = [serving.state_bytes(c["L"], sum(c["occupation"]), 4, c["chi_max"]) for c in cfgs]
+    budget = max(per) * 2                   # at most about two requests at a time
+    rep = serving.Server(budget, clock=tick).run(reqs)
+    assert len(rep.completed) == 6 and rep.pending == 0
+    assert rep.peak_bytes <= budget
+    assert FakeState.live == 0              # every state released
+    assert max(calls) >= 2                  # requests overlapped in one batch call
+    assert rep.gates == sum(len(c["gates"]) for c in cfgs)
+    for r in rep.completed:
+        assert r.done_at >= r.admitted_at >= r.arrival
+        assert r.result["amplitudes"].shape == (4,)
+
+
+def test_scheduler_rejects_oversized_request(monkeypatch):
+    monkeypatch.setattr(serving, "MPS", FakeState)
+    cfgs = circuits.config_batch_mix(1, seed=3, l_range=(8, 8), chi_choices=(16,))
+    reqs = serving.poisson_requests(cfgs, rate=1.0, seed=1)
+    with pytest.raises(ValueError):
+        serving.Server(1000).run(reqs)

@@ -292,3 +292,39 @@ def config_batch_mix(n_circuits: int = 512, seed: int = 4, l_range=(16, 48),
         out.append(config_brickwork(L, L // 2, "first", 4, depth, chi, cutoff, 4000 + i,
                                     f"mix{i}_L{L}_chi{chi}"))
     return out
+
+
+def serving_mix_specs(n_requests: int, seed: int = 5, large_frac: float = 0.05,
+                      l_range=(16, 48), chi_choices=(64, 128, 256, 512), large_chi: int = 1024,
+                      large_L: int = 64, depth_scale: float = 1.0) -> list:
+    """The serving-form request mix, as light specs (built into circuits by
+    config_from_spec): request j is, with probability large_frac, a large
+    circuit (large_L modes, large_L/2 photons in the first modes, d = 4, depth
+    large_L, chi_max = large_chi), else a circuit of the batching mix's
+    distribution (L ~ U{l_range}, floor(L/2) photons in the first modes, depth
+    L, chi_max ~ chi_choices); circuit seed 5000 + j, cutoff 1e-12.  The kind,
+    L and chi_max are drawn from numpy.random.default_rng(seed) in request
+    order."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(n_requests):
+        if rng.random() < large_frac:
+            L, chi = large_L, large_chi
+        else:
+            L = int(rng.integers(l_range[0], l_range[1] + 1))
+            chi = int(chi_choices[int(rng.integers(0, len(chi_choices)))])
+        depth = max(1, int(round(depth_scale * L)))
+        out.append(dict(L=L, n_photons=L // 2, d=4, depth=depth, chi_max=chi, cutoff=1e-12,
+                        seed=5000 + j, name=f"req{j}_L{L}_chi{chi}"))
+    return out
+
+
+def config_from_spec(spec: dict) -> dict:
+    """The brickwork circuit a serving spec names."""
+    return config_brickwork(spec["L"], spec["n_photons"], "first", spec["d"], spec["depth"],
+                            spec["chi_max"], spec["cutoff"], spec["seed"], spec["name"])
+
+
+def config_serving_mix(n_requests: int, seed: int = 5, **kw) -> list:
+    """The serving-form request mix as built circuits (see serving_mix_specs)."""
+    return [config_from_spec(s) for s in serving_mix_specs(n_requests, seed, **kw)]
