@@ -87,13 +87,23 @@ typedef struct {
  *   jacobi_tol rotate a vector pair while |<x,y>| > tol * |x| |y|; <= 0
  *              means max(vector length, 64) * 2^-52.  The SVD of an r x c
  *              sector orthogonalises its min(r, c) rows or columns.
+ *   form       MPS_FORM_PLAIN_C128 (default): every step in complex128.
+ *              MPS_FORM_SPLIT_BF16X3: the charge-triple products of Theta
+ *              formation run on the matrix cores with each operand split into
+ *              two BF16 parts and three BF16 products per real product,
+ *              accumulated in FP32 (relative error of order 1e-5 per
+ *              product); the gate mix, the Jacobi SVD, the cut and the update
+ *              stay FP64.
  * The kept count is K = max(1, min(chi_max, K_eps, K_zero)). */
+typedef enum { MPS_FORM_PLAIN_C128 = 0, MPS_FORM_SPLIT_BF16X3 = 1 } mps_form;
+
 typedef struct {
   int chi_max;
   double cutoff;
   double zero_tol;
   int max_sweeps;
   double jacobi_tol;
+  int form;                    /* mps_form */
 } mps_opts;
 
 /* Per-handle counters, accumulated since creation or mps_reset_stats.
@@ -117,6 +127,12 @@ typedef struct {
   long long polish_launches;   /* batches that needed the scalar Jacobi finish */
   double max_discarded;        /* largest per-gate discarded weight            */
   double min_margin;           /* smallest (s_{K-1} - s_K)/s_0 at a cut        */
+  double gemm_ms;              /* split-BF16 form: the charge-triple products  */
+  long long gemm_launches;     /*   (theta_ms then covers the gate mix)        */
+  double gemm_mfma_flops;      /* split-BF16 form: flops the BF16 matrix-core  */
+                               /*   products execute, tile padding included    */
+                               /*   (24 per complex multiply-add: 4 real       */
+                               /*   products x 3 split terms x 2)              */
 } mps_stats;
 
 /* Fill *o with the defaults: chi_max 0, cutoff 0, zero_tol 1e-13,
@@ -180,7 +196,7 @@ mps_status mps_apply_layer(mps_t h, int ngates, const int* sites,
  * jacobi_tol serve the batch; each state keeps its own chi_max, cutoff and
  * zero_tol.  The result for each state equals mps_apply_layer on it alone.
  * If any update fails no state changes.  A state may appear once.
- * Errors: as mps_apply_layer; MPS_E_ARG for mixed d or streams. */
+ * Errors: as mps_apply_layer; MPS_E_ARG for mixed d, forms or streams. */
 mps_status mps_apply_batch(int nh, const mps_t* hs, const int* ngates,
                            const int* sites, const mps_z* u2s, double* discarded);
 

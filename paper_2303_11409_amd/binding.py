@@ -44,9 +44,13 @@ class mps_device(C.Structure):
     _fields_ = [("alloc", ALLOC_FN), ("release", FREE_FN), ("ctx", C.c_void_p), ("stream", C.c_void_p)]
 
 
+FORM_PLAIN_C128 = 0          # every step in complex128
+FORM_SPLIT_BF16X3 = 1        # Theta's charge-triple products in split BF16 on the matrix cores
+
+
 class mps_opts(C.Structure):
     _fields_ = [("chi_max", C.c_int), ("cutoff", C.c_double), ("zero_tol", C.c_double),
-                ("max_sweeps", C.c_int), ("jacobi_tol", C.c_double)]
+                ("max_sweeps", C.c_int), ("jacobi_tol", C.c_double), ("form", C.c_int)]
 
 
 class mps_stats(C.Structure):
@@ -58,7 +62,9 @@ class mps_stats(C.Structure):
                 ("theta_launches", C.c_longlong), ("jacobi_launches", C.c_longlong),
                 ("jacobi_aux_launches", C.c_longlong), ("select_launches", C.c_longlong),
                 ("update_launches", C.c_longlong), ("polish_launches", C.c_longlong),
-                ("max_discarded", C.c_double), ("min_margin", C.c_double)]
+                ("max_discarded", C.c_double), ("min_margin", C.c_double),
+                ("gemm_ms", C.c_double), ("gemm_launches", C.c_longlong),
+                ("gemm_mfma_flops", C.c_double)]
 
 
 EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_destroy", "mps_apply_gate",
@@ -180,14 +186,14 @@ class MPS:
 
     def __init__(self, occupation: Sequence[int], d: int, chi_max: int = 0, cutoff: float = 0.0,
                  zero_tol: float = 1e-13, max_sweeps: int = 40, jacobi_tol: float = 0.0,
-                 device: Optional[TorchDevice] = None, _handle=None):
+                 device: Optional[TorchDevice] = None, form: int = FORM_PLAIN_C128, _handle=None):
         self._lib = lib()
         self.L = len(occupation)
         self.d = d
         self.N = int(sum(occupation))
         self._dev = device if device is not None else TorchDevice()
         self._dev_struct = self._dev.struct()
-        self._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol)
+        self._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form))
         self._h = C.c_void_p()
         if _handle is not None:
             self._h = _handle
@@ -201,7 +207,8 @@ class MPS:
     def from_vidal(cls, d: int, n_photons: int, bond_charges: List[Sequence[int]],
                    gammas: List[np.ndarray], lambdas: List[np.ndarray], chi_max: int = 0,
                    cutoff: float = 0.0, zero_tol: float = 1e-13, max_sweeps: int = 40,
-                   jacobi_tol: float = 0.0, device: Optional[TorchDevice] = None) -> "MPS":
+                   jacobi_tol: float = 0.0, device: Optional[TorchDevice] = None,
+                   form: int = FORM_PLAIN_C128) -> "MPS":
         L = len(gammas)
         dims = [len(c) for c in bond_charges]
         obj = cls.__new__(cls)
@@ -209,7 +216,7 @@ class MPS:
         obj.L, obj.d, obj.N = L, d, n_photons
         obj._dev = device if device is not None else TorchDevice()
         obj._dev_struct = obj._dev.struct()
-        obj._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol)
+        obj._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form))
         obj._h = C.c_void_p()
         c_dims = (C.c_int * (L + 1))(*dims)
         flat = [int(c) for b in bond_charges for c in b]

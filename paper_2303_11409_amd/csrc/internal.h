@@ -61,6 +61,29 @@ struct ThetaTile {
   int k0[kMaxD], kn[kMaxD], a[kMaxD];      // input segments: start, length, cL - cM
   int sec[kMaxD], p[kMaxD];                // output sector, cL - m
   int orow[kMaxD], ocol[kMaxD];            // tile origin inside Theta(m)
+  // split-BF16 form only: the products P_j = B[s](cL, segment j) B[s+1](., cR)
+  // of the tile's charge pair sit in the complex64 scratch at poff[j], row-major
+  // with row length ldp (= the pair's column count); the tile starts at
+  // row pr0, column pc0 of them
+  long long poff[kMaxD];
+  int pr0, pc0, ldp;
+};
+
+// Split-BF16 sector product (precision form): C (m x n, complex64, row-major,
+// ldc) = A (m x k) B (k x n), A and B complex128 row-major; each real product
+// runs as three BF16 products of the operands' high and low parts with FP32
+// accumulation.
+constexpr int kSgTile = 64;       // output tile edge
+constexpr int kSgK = 32;          // k chunk staged per step
+
+struct SplitGemm {
+  const double2* a;
+  const double2* b;
+  float2* c;
+  int m, n, k;
+  int lda, ldb, ldc;
+  int tiles_n;            // ceil(n / kSgTile)
+  int tile_begin;         // first flattened tile of this problem
 };
 
 // A generic complex GEMM problem C = op(A) op(B) (+ C when beta_one).

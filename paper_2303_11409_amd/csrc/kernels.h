@@ -42,6 +42,11 @@ hipError_t launch_zero_fill(double2* const* ptrs, const long long* counts, int n
                             long long maxcount, hipStream_t st);
 
 hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_t st);
+// Precision form: split-BF16 charge-triple products into the complex64
+// scratch, then the gate mix into the Theta workspaces.
+hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, hipStream_t st);
+hipError_t launch_theta_mix(const GateWork* gates, const ThetaTile* tiles, int ntiles, const SectorWork* secs,
+                            const double2* coef, const float2* pbuf, double2* raw, double2* scaled, hipStream_t st);
 
 hipError_t launch_amplitude(const double2* const* sites, const int* ld, const int2* bondmap,
                             const int* occ, double2* out, int count, int L, int d, int N,

@@ -1120,6 +1120,181 @@ gather_vec_kernel(const double* __restrict__ src, double* __restrict__ dst,
 // ---------------------------------------------------------------------------
 // Host launchers.
 
+// ---------------------------------------------------------------------------
+// Precision form of Theta formation: the charge-triple products on the matrix
+// cores in split BF16, then the gate mix into the FP64 Theta workspaces.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// x = h + l with h = bf16(x), l = bf16(x - h): |x - h - l| <= 2^-18 |x|
+// (after the float conversion of x, which adds 2^-24 |x|).
+__device__ __forceinline__ void split_bf16(double x, __bf16& h, __bf16& l) {
+  const float xf = (float)x;
+  h = (__bf16)xf;
+  l = (__bf16)(xf - (float)h);
+}
+
+// LDS planes of one k chunk: [plane][row or column][k], planes (re hi, re lo,
+// im hi, im lo); rows padded to 40 bf16 (80 bytes) so that every 8-element
+// operand read is one aligned 16-byte access.
+constexpr int kSgRow = kSgK + 8;
+
+// 8 consecutive complex elements per thread of a 64 x 32 chunk of A (row t/4,
+// columns 8 (t%4) ..) and of a 32 x 64 chunk of B (column t%64, rows
+// 8 (t/64) ..); out-of-range entries are 0 and issue no load.
+struct SgRegs {
+  double2 a[8], b[8];
+};
+
+__device__ __forceinline__ void sg_fetch(SgRegs& r, const SplitGemm& w, int row0, int col0, int k0) {
+  const int t = threadIdx.x;
+  const int ar = row0 + (t >> 2), ak = k0 + 8 * (t & 3);
+  const int bc = col0 + (t & 63), bk = k0 + 8 * (t >> 6);
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    r.a[e] = make_double2(0.0, 0.0);
+    r.b[e] = make_double2(0.0, 0.0);
+    if (ar < w.m && ak + e < w.k) r.a[e] = w.a[(size_t)ar * w.lda + ak + e];
+    if (bc < w.n && bk + e < w.k) r.b[e] = w.b[(size_t)(bk + e) * w.ldb + bc];
+  }
+}
+
+__device__ __forceinline__ void sg_stage(const SgRegs& r, __bf16 (*as)[kSgTile][kSgRow],
+                                         __bf16 (*bs)[kSgTile][kSgRow]) {
+  const int t = threadIdx.x;
+  bf16x8 p0, p1, p2, p3;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    __bf16 h, l;
+    split_bf16(r.a[e].x, h, l); p0[e] = h; p1[e] = l;
+    split_bf16(r.a[e].y, h, l); p2[e] = h; p3[e] = l;
+  }
+  const int ar = t >> 2, ak = 8 * (t & 3);
+  *reinterpret_cast<bf16x8*>(&as[0][ar][ak]) = p0;
+  *reinterpret_cast<bf16x8*>(&as[1][ar][ak]) = p1;
+  *reinterpret_cast<bf16x8*>(&as[2][ar][ak]) = p2;
+  *reinterpret_cast<bf16x8*>(&as[3][ar][ak]) = p3;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    __bf16 h, l;
+    split_bf16(r.b[e].x, h, l); p0[e] = h; p1[e] = l;
+    split_bf16(r.b[e].y, h, l); p2[e] = h; p3[e] = l;
+  }
+  const int bc = t & 63, bk = 8 * (t >> 6);
+  *reinterpret_cast<bf16x8*>(&bs[0][bc][bk]) = p0;
+  *reinterpret_cast<bf16x8*>(&bs[1][bc][bk]) = p1;
+  *reinterpret_cast<bf16x8*>(&bs[2][bc][bk]) = p2;
+  *reinterpret_cast<bf16x8*>(&bs[3][bc][bk]) = p3;
+}
+
+// One 64 x 64 output tile per workgroup; wave w computes the 32 x 32 quadrant
+// (rows 32 (w / 2), columns 32 (w % 2)) with v_mfma_f32_32x32x16_bf16.  Lane l
+// supplies A[i = l % 32][k = 8 (l / 32) + e] and B[k = 8 (l / 32) + e][j = l % 32]
+// (e = 0..7); its accumulator register r holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+// Per k step: Re = Ar Br - Ai Bi and Im = Ar Bi + Ai Br, each real product as
+// hi*hi + hi*lo + lo*hi (the lo*lo term is below the split's error).
+__global__ void __launch_bounds__(256)
+split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
+  __shared__ __align__(16) __bf16 as[4][kSgTile][kSgRow];
+  __shared__ __align__(16) __bf16 bs[4][kSgTile][kSgRow];
+  int lo = 0, hi = nprob - 1;
+  const int tile = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  const SplitGemm w = probs[lo];
+  const int local = tile - w.tile_begin;
+  const int row0 = (local / w.tiles_n) * kSgTile, col0 = (local % w.tiles_n) * kSgTile;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R = 32 * (wave >> 1), Cq = 32 * (wave & 1);
+  const int li = lane & 31, lk = 8 * (lane >> 5);
+  f32x16 crp = {}, crn = {}, cim = {};
+  SgRegs rg;
+  sg_fetch(rg, w, row0, col0, 0);
+  for (int k0 = 0; k0 < w.k; k0 += kSgK) {
+    sg_stage(rg, as, bs);
+    __syncthreads();
+    if (k0 + kSgK < w.k) sg_fetch(rg, w, row0, col0, k0 + kSgK);   // in flight during the products
+#pragma unroll
+    for (int ks = 0; ks < kSgK; ks += 16) {
+      const bf16x8 arh = *reinterpret_cast<const bf16x8*>(&as[0][R + li][ks + lk]);
+      const bf16x8 arl = *reinterpret_cast<const bf16x8*>(&as[1][R + li][ks + lk]);
+      const bf16x8 aih = *reinterpret_cast<const bf16x8*>(&as[2][R + li][ks + lk]);
+      const bf16x8 ail = *reinterpret_cast<const bf16x8*>(&as[3][R + li][ks + lk]);
+      const bf16x8 brh = *reinterpret_cast<const bf16x8*>(&bs[0][Cq + li][ks + lk]);
+      const bf16x8 brl = *reinterpret_cast<const bf16x8*>(&bs[1][Cq + li][ks + lk]);
+      const bf16x8 bih = *reinterpret_cast<const bf16x8*>(&bs[2][Cq + li][ks + lk]);
+      const bf16x8 bil = *reinterpret_cast<const bf16x8*>(&bs[3][Cq + li][ks + lk]);
+      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brh, crp, 0, 0, 0);
+      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, bih, crn, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bih, cim, 0, 0, 0);
+      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brl, crp, 0, 0, 0);
+      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, bil, crn, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bil, cim, 0, 0, 0);
+      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, brh, crp, 0, 0, 0);
+      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, bih, crn, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bih, cim, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brh, cim, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brl, cim, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, brh, cim, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int j = col0 + Cq + li;
+  if (j < w.n) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = row0 + R + 8 * (r >> 2) + (lane >> 5) * 4 + (r & 3);
+      if (i < w.m) w.c[(size_t)i * w.ldc + j] = make_float2(crp[r] - crn[r], cim[r]);
+    }
+  }
+}
+
+// Gate mix of the precision form: for the 32 x 32 tile of one charge pair,
+// Theta~(cL, m, cR) = sum_j G^(n)[cL - m][a_j] P_j with the products P_j from
+// the scratch (complex64, upcast), written like the plain kernel's epilogue.
+__global__ void __launch_bounds__(256)
+theta_mix_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ tiles,
+                 const SectorWork* __restrict__ secs, const double2* __restrict__ coef,
+                 const float2* __restrict__ pbuf, double2* __restrict__ th_raw,
+                 double2* __restrict__ th_scaled) {
+  const ThetaTile& t = tiles[blockIdx.x];
+  const GateWork g = gates[t.gate];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int nin = t.nin, nout = t.nout;
+  for (int a = 0; a < 2; ++a) {
+    const int r = ty + 16 * a;
+    if (r >= t.nrow) continue;
+    const double lam = g.lam_l[t.row0 + r];
+    for (int b = 0; b < 2; ++b) {
+      const int c = tx + 16 * b;
+      if (c >= t.ncol) continue;
+      double2 pv[kMaxD];
+#pragma unroll
+      for (int j = 0; j < kMaxD; ++j) {
+        pv[j] = make_double2(0.0, 0.0);
+        if (j < nin) {
+          const float2 f = pbuf[t.poff[j] + (size_t)(t.pr0 + r) * t.ldp + t.pc0 + c];
+          pv[j] = make_double2(f.x, f.y);
+        }
+      }
+      for (int i = 0; i < nout; ++i) {
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < kMaxD; ++j)
+          if (j < nin) cfma(v, coef[g.coef + (t.n * g.d + t.p[i]) * g.d + t.a[j]], pv[j]);
+        const SectorWork s = secs[t.sec[i]];
+        const size_t rr = (size_t)(t.orow[i] + r), cc = (size_t)(t.ocol[i] + c);
+        th_raw[(size_t)s.off + rr * s.c + cc] = v;
+        const size_t si = s.tall ? (size_t)s.off + cc * s.r + rr : (size_t)s.off + rr * s.c + cc;
+        th_scaled[si] = make_double2(lam * v.x, lam * v.y);
+      }
+    }
+  }
+}
+
 hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntiles,
                         const SectorWork* secs, const double2* coef, double2* raw,
                         double2* scaled, int maxw, hipStream_t st) {
@@ -1209,6 +1384,19 @@ hipError_t launch_zero_fill(double2* const* ptrs, const long long* counts, int n
 hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_t st) {
   if (nprob <= 0 || ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(zgemm_kernel, dim3(ntiles), dim3(256), 0, st, probs, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, hipStream_t st) {
+  if (nprob <= 0 || ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(split_gemm_kernel, dim3(ntiles), dim3(256), 0, st, probs, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_theta_mix(const GateWork* gates, const ThetaTile* tiles, int ntiles, const SectorWork* secs,
+                            const double2* coef, const float2* pbuf, double2* raw, double2* scaled, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(theta_mix_kernel, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, pbuf, raw, scaled);
   return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 #include <cmath>
 #include <complex>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -79,7 +80,7 @@ struct PinBuf {
   size_t cap = 0;
 };
 
-enum Kind { K_THETA = 0, K_SELECT, K_UPDATE, K_JACOBI, K_JACOBI_AUX };
+enum Kind { K_THETA = 0, K_SELECT, K_UPDATE, K_JACOBI, K_JACOBI_AUX, K_GEMM };
 
 struct Pending {
   int kind;
@@ -105,7 +106,8 @@ struct mps_state {
   std::vector<double*> lam;      // per bond, cap[b] doubles
   std::vector<double2*> site;    // per site, cap[s] * cap[s+1] complex
   // workspaces (grow-only)
-  DevBuf th_raw, th_scaled, acc, sigma, order, jperm, jnorm, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc;
+  DevBuf th_raw, th_scaled, acc, sigma, order, jperm, jnorm, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc,
+      pbuf;
   PinBuf stage_plan, stage_upd, stage_res, stage_misc, stage_flag;
   mps_stats stats{};
   bool timing = false;
@@ -234,6 +236,7 @@ mps_status drain_events(mps_state* h) {
       case K_SELECT: h->stats.select_ms += ms; break;
       case K_JACOBI: h->stats.jacobi_ms += ms; break;
       case K_JACOBI_AUX: h->stats.jacobi_aux_ms += ms; break;
+      case K_GEMM: h->stats.gemm_ms += ms; break;
       default: h->stats.update_ms += ms; break;
     }
     h->pool.push_back(p.a);
@@ -334,6 +337,12 @@ struct BatchPlan {
   int sig_elems = 0;
   int maxw = 1;
   double theta_flops = 0.0;
+  // split-BF16 form: one product per charge triple into the complex64 scratch
+  bool split = false;
+  std::vector<SplitGemm> sg;              // c holds the scratch offset until upload
+  int sg_tiles = 0;
+  long long p_elems = 0;
+  double sg_mfma_flops = 0.0;
 };
 
 // One two-site update of a batch: the state it acts on, its left site and its
@@ -347,6 +356,7 @@ struct GateRef {
 mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
   const int ng = (int)refs.size();
   const int d = refs[0].h->d;
+  P.split = refs[0].h->opts.form == MPS_FORM_SPLIT_BF16X3;
   P.gates.resize(ng);
   P.gp.resize(ng);
   P.coef.assign((size_t)ng * (2 * d - 1) * d * d, make_double2(0.0, 0.0));
@@ -443,9 +453,34 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
         P.maxw = std::max(P.maxw, base.nout);
         const int nL = BL.count[a], nR = BR.count[b];
         P.theta_flops += 8.0 * nL * double(ksum) * nR;
+        if (P.split) {
+          base.ldp = nR;
+          for (int j = 0; j < base.nin; ++j) {
+            base.poff[j] = P.p_elems;
+            SplitGemm sg{};
+            sg.a = gw.bl + (size_t)BL.off[a] * gw.ldl + base.k0[j];
+            sg.lda = gw.ldl;
+            sg.b = gw.br + (size_t)base.k0[j] * gw.ldr + BR.off[b];
+            sg.ldb = gw.ldr;
+            sg.c = reinterpret_cast<float2*>((uintptr_t)(P.p_elems * (long long)sizeof(float2)));
+            sg.ldc = nR;
+            sg.m = nL;
+            sg.n = nR;
+            sg.k = base.kn[j];
+            sg.tiles_n = (nR + kSgTile - 1) / kSgTile;
+            sg.tile_begin = P.sg_tiles;
+            P.sg_tiles += ((nL + kSgTile - 1) / kSgTile) * sg.tiles_n;
+            P.sg_mfma_flops += 24.0 * kSgTile * kSgTile * double(kSgK) *
+                               (((nL + kSgTile - 1) / kSgTile) * sg.tiles_n) * ((sg.k + kSgK - 1) / kSgK);
+            P.sg.push_back(sg);
+            P.p_elems += (long long)nL * nR;
+          }
+        }
         for (int ti = 0; ti < nL; ti += kThetaTile) {
           for (int tj = 0; tj < nR; tj += kThetaTile) {
             ThetaTile t = base;
+            t.pr0 = ti;
+            t.pc0 = tj;
             t.row0 = BL.off[a] + ti;
             t.nrow = std::min(kThetaTile, nL - ti);
             t.col0 = BR.off[b] + tj;
@@ -509,6 +544,11 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   STCHK(ensure(h, h->order, (size_t)P.sig_elems * sizeof(int)));
   STCHK(ensure(h, h->jperm, (size_t)P.sig_elems * sizeof(int)));
   STCHK(ensure(h, h->jnorm, (size_t)P.sig_elems * sizeof(double)));
+  if (P.split) {
+    STCHK(ensure(h, h->pbuf, (size_t)std::max<long long>(P.p_elems, 1) * sizeof(float2)));
+    float2* pb = static_cast<float2*>(h->pbuf.p);
+    for (SplitGemm& g : P.sg) g.c = pb + (reinterpret_cast<uintptr_t>(g.c) / sizeof(float2));
+  }
   if (P.maxP > 4096) {
     STCHK(ensure(h, h->sel_v, (size_t)P.sel_scratch * sizeof(double)));
     STCHK(ensure(h, h->sel_k, (size_t)P.sel_scratch * sizeof(int)));
@@ -522,6 +562,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   const size_t o_jlist = pk.add(P.jlist.data(), P.jlist.size() * sizeof(int));
   const size_t o_jblk = pk.add(P.jblocks.data(), P.jblocks.size() * sizeof(JacobiBlockWork));
   const size_t o_seloff = pk.add(P.sel_off.data(), P.sel_off.size() * sizeof(long long));
+  const size_t o_sg = pk.add(P.sg.data(), P.sg.size() * sizeof(SplitGemm));
   const size_t o_kept = pk.add(nullptr, (size_t)ns * sizeof(int));
   const size_t o_cut = pk.add(nullptr, (size_t)ng * sizeof(CutOut));
   const size_t o_jst = pk.add(nullptr, (size_t)ns * sizeof(JacobiOut));
@@ -539,7 +580,22 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   double* sig = static_cast<double*>(h->sigma.p);
   int* ord = static_cast<int*>(h->order.p);
 
-  {
+  if (P.split) {
+    {
+      Timer tg(h, K_GEMM);
+      STCHK(tg.start());
+      HIPCHK(launch_split_gemm(at<SplitGemm>(h->plan, o_sg), (int)P.sg.size(), P.sg_tiles, h->st));
+      STCHK(tg.stop());
+      h->stats.gemm_launches += 1;
+      h->stats.gemm_mfma_flops += P.sg_mfma_flops;
+    }
+    Timer tm(h, K_THETA);
+    STCHK(tm.start());
+    HIPCHK(launch_theta_mix(d_gates, at<ThetaTile>(h->plan, o_tiles), (int)P.tiles.size(), d_secs,
+                            at<double2>(h->plan, o_coef), static_cast<const float2*>(h->pbuf.p), raw, scaled,
+                            h->st));
+    STCHK(tm.stop());
+  } else {
     Timer tm(h, K_THETA);
     STCHK(tm.start());
     HIPCHK(launch_theta(d_gates, at<ThetaTile>(h->plan, o_tiles), (int)P.tiles.size(), d_secs,
@@ -754,7 +810,7 @@ mps_status destroy_buffers(mps_state* h) {
   h->lam.clear();
   h->site.clear();
   DevBuf* bufs[] = {&h->th_raw, &h->th_scaled, &h->acc, &h->jperm, &h->jnorm, &h->sigma, &h->order, &h->plan, &h->upd,
-                    &h->norm_e0, &h->norm_e1, &h->norm_t, &h->sel_v, &h->sel_k, &h->misc};
+                    &h->norm_e0, &h->norm_e1, &h->norm_t, &h->sel_v, &h->sel_k, &h->misc, &h->pbuf};
   for (DevBuf* b : bufs) {
     dfree(h, b->p);
     b->p = nullptr;
@@ -788,6 +844,7 @@ void mps_default_opts(mps_opts* o) {
   o->zero_tol = 1e-13;
   o->max_sweeps = 40;
   o->jacobi_tol = 0.0;
+  o->form = MPS_FORM_PLAIN_C128;
 }
 
 const char* mps_last_error(void) { return g_err.c_str(); }
@@ -812,6 +869,7 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
   if (opts) o = *opts;
   if (o.max_sweeps <= 0) return fail(MPS_E_ARG, "max_sweeps must be positive");
   if (!(o.cutoff >= 0.0) || !(o.zero_tol >= 0.0)) return fail(MPS_E_ARG, "cutoff and zero_tol must be >= 0");
+  if (o.form != MPS_FORM_PLAIN_C128 && o.form != MPS_FORM_SPLIT_BF16X3) return fail(MPS_E_ARG, "unknown form %d", o.form);
 
   // charge tables with a stable sort of every bond by charge
   std::vector<Bond> bonds(L + 1);
@@ -1003,6 +1061,7 @@ mps_status mps_apply_batch(int nh, const mps_t* hs, const int* ngates, const int
       mps_state* h0 = refs[0].h;
       if (h->d != h0->d) return fail(MPS_E_ARG, "states of one batch must share the local dimension");
       if (h->st != h0->st) return fail(MPS_E_ARG, "states of one batch must share one stream");
+      if (h->opts.form != h0->opts.form) return fail(MPS_E_ARG, "states of one batch must share the form");
     }
     for (int g = 0; g < ngates[i]; ++g) refs.push_back({h, sites[off + g], u2s + 4 * (off + g)});
     off += ngates[i];

@@ -89,3 +89,16 @@ def test_apply_batch_argument_errors():
     assert lib.mps_apply_batch(2, hs, counts, sites, None, None) == -1
     assert "invalid handle" in lib.mps_last_error().decode()
     assert lib.mps_apply_batch(2, hs, None, sites, None, None) == -1
+
+
+def test_form_option():
+    """The default form is plain complex128; an unknown form is rejected."""
+    lib = binding.lib()
+    o = binding.mps_opts()
+    lib.mps_default_opts(C.byref(o))
+    assert o.form == binding.FORM_PLAIN_C128
+    o.form = 7
+    h = C.c_void_p()
+    occ = (C.c_int * 4)(1, 0, 1, 0)
+    assert lib.mps_create_product(4, 3, occ, C.byref(o), None, C.byref(h)) == -1
+    assert "form" in lib.mps_last_error().decode()

@@ -309,3 +309,57 @@ def test_serving_form_results_equal_each_request_alone(mps_cls):
         assert r.result["norm2"] == m.norm2() and r.result["discarded"] == disc, c["name"]
         assert r.result["bond_dims"] == m.bond_dims(), c["name"]
         m.close()
+
+
+# Precision form (split-BF16 charge-triple products).  Each real product is
+# hi*hi + hi*lo + lo*hi of the operands' two BF16 parts, so its error is at most
+# 3 * 2^-18 ~ 1.1e-5 of |a||b| (the dropped lo*lo term plus the split residuals);
+# a gate's Theta therefore carries ~1e-5 relative error and a circuit of G gates
+# up to ~G times that in the worst case (measured: ~2e-5 after 28 gates,
+# ~3-7e-5 after 100-300).  One layer is held to 5e-5, whole circuits to 2e-4.
+TOL_SPLIT_LAYER = 5e-5
+TOL_SPLIT_CIRCUIT = 2e-4
+
+
+def test_precision_form_one_layer_on_entangled_state(mps_cls):
+    from paper_2303_11409_amd.binding import FORM_PLAIN_C128, FORM_SPLIT_BF16X3
+    ch, gam, lam = circuits.synthetic_state(12, 6, 4, 40, seed=3)
+    states = [mps_cls.from_vidal(4, 6, ch, gam, lam, form=f) for f in (FORM_PLAIN_C128, FORM_SPLIT_BF16X3)]
+    lay = circuits.brickwork_layers(12, 2, 44)[1]
+    for m in states:
+        m.apply_layer([g.site for g in lay], [g.u for g in lay])
+    pats = circuits.sample_patterns(12, 6, 4, 256, 6)
+    ref, got = states[0].amplitudes(pats), states[1].amplitudes(pats)
+    close_amps(got, ref, TOL_SPLIT_LAYER)
+    # full-rank random sectors, no cap: the cut cannot depend on the noise
+    for b in range(13):
+        assert states[1].bond_sectors(b) == states[0].bond_sectors(b), b
+    assert abs(states[1].norm2() - states[0].norm2()) <= TOL_SPLIT_LAYER * states[0].norm2()
+    for m in states:
+        m.close()
+
+
+def test_precision_form_exact_circuit_vs_permanents(mps_cls):
+    from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
+    cfg = circuits.config_small_exact()
+    m = mps_cls(cfg["occupation"], 5, form=FORM_SPLIT_BF16X3)
+    for g in cfg["gates"]:
+        m.apply_gate(g.site, g.u)
+    pats = circuits.all_patterns(8, 4, 5)
+    exact = np.array([permanent.fock_amplitude(cfg["unitary"], cfg["occupation"], p) for p in pats])
+    close_amps(m.amplitudes(pats), exact, TOL_SPLIT_CIRCUIT)
+    assert abs(m.norm2() - 1.0) <= TOL_SPLIT_CIRCUIT
+    m.close()
+
+
+def test_precision_form_brickwork_vs_oracle(mps_cls):
+    from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
+    cfg = circuits.config_brickwork(12, 6, "first", 4, 12, 0, 1e-12, 7, "p")
+    m = mps_cls(cfg["occupation"], 4, chi_max=0, cutoff=1e-12, form=FORM_SPLIT_BF16X3)
+    for lay in cfg["layers"]:
+        m.apply_layer([g.site for g in lay], [g.u for g in lay])
+    ref = dense_mps.DenseMPS(cfg["occupation"], 4, chi_max=0, cutoff=1e-12).run(cfg["gates"])
+    pats = circuits.sample_patterns(12, 6, 4, 256, 8)
+    close_amps(m.amplitudes(pats), ref.amplitudes(pats), TOL_SPLIT_CIRCUIT)
+    assert abs(m.norm2() - ref.norm2()) <= TOL_SPLIT_CIRCUIT * ref.norm2()
+    m.close()

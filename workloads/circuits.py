@@ -328,3 +328,80 @@ def config_from_spec(spec: dict) -> dict:
 def config_serving_mix(n_requests: int, seed: int = 5, **kw) -> list:
     """The serving-form request mix as built circuits (see serving_mix_specs)."""
     return [config_from_spec(s) for s in serving_mix_specs(n_requests, seed, **kw)]
+
+
+def _fock_counts(sites: int, d: int, n_max: int) -> list:
+    cnt = [1] + [0] * n_max
+    for _ in range(sites):
+        nxt = [0] * (n_max + 1)
+        for n, c in enumerate(cnt):
+            if c:
+                for k in range(d):
+                    if n + k <= n_max:
+                        nxt[n + k] += c
+        cnt = nxt
+    return cnt
+
+
+def synthetic_state(L: int, N: int, d: int, chi: int, width: float = 3.0, lam_min: float = 1e-4,
+                    seed: int = 30):
+    """A random block-sparse U(1) MPS with saturated bonds, the stand-in for a
+    chi-saturated layer of the precision workload.  Bond k carries right
+    charges c in [max(0, N - k(d-1)), min(N, (L-k)(d-1))] with multiplicities
+    proportional to exp(-(c - c0)^2 / (2 width^2)), c0 = N (L - k) / L,
+    normalised to min(chi, Fock bound of the bond) and clipped per charge by
+    the number of left and right occupation strings; Gamma entries are complex
+    Gaussian on the blocks the charge rule allows (c_left - c_right in 0..d-1),
+    zero elsewhere; each bond's lambda decays exponentially from 1 to lam_min
+    (in a random order).  Returns (bond_charges, gammas, lambdas) as taken by
+    MPS.from_vidal; gammas[s] is (dim_s, dim_{s+1}) complex128."""
+    rng = np.random.default_rng(seed)
+    charges = []
+    for k in range(L + 1):
+        lo, hi = max(0, N - k * (d - 1)), min(N, (L - k) * (d - 1))
+        left, right = _fock_counts(k, d, N), _fock_counts(L - k, d, N)
+        cap = {c: min(left[N - c], right[c]) for c in range(lo, hi + 1)}
+        cap = {c: v for c, v in cap.items() if v > 0}
+        total = min(chi, sum(cap.values()))
+        c0 = N * (L - k) / L
+        w = {c: math.exp(-(c - c0) ** 2 / (2.0 * width ** 2)) for c in cap}
+        ws = sum(w.values())
+        cnt = {c: min(cap[c], int(total * w[c] / ws)) for c in cap}
+        left_over = total - sum(cnt.values())
+        for c in sorted(cap, key=lambda x: -w[x]):
+            if left_over <= 0:
+                break
+            add = min(cap[c] - cnt[c], left_over)
+            cnt[c] += add
+            left_over -= add
+        charges.append({c: v for c, v in cnt.items() if v > 0})
+    # drop, until none is left, every charge without an admissible partner on a
+    # neighbouring bond (c_left - c_right in 0..d-1), as the charge rule needs
+    changed = True
+    while changed:
+        changed = False
+        for k in range(L + 1):
+            keep = {}
+            for c, v in charges[k].items():
+                ok_l = k == 0 or any(c + a in charges[k - 1] for a in range(d))
+                ok_r = k == L or any(c - a in charges[k + 1] for a in range(d))
+                if ok_l and ok_r:
+                    keep[c] = v
+                else:
+                    changed = True
+            charges[k] = keep
+    charges = [[c for c in sorted(cnt) for _ in range(cnt[c])] for cnt in charges]
+    gammas = []
+    for s in range(L):
+        cl = np.array(charges[s])[:, None]
+        cr = np.array(charges[s + 1])[None, :]
+        allowed = (cl - cr >= 0) & (cl - cr <= d - 1)
+        g = (rng.standard_normal(allowed.shape) + 1j * rng.standard_normal(allowed.shape)) / math.sqrt(2.0)
+        g *= allowed
+        gammas.append(g.astype(np.complex128))
+    lambdas = []
+    for k in range(L + 1):
+        n = len(charges[k])
+        lam = np.exp(np.linspace(0.0, math.log(lam_min), n)) if n > 1 else np.ones(1)
+        lambdas.append(rng.permutation(lam))
+    return charges, gammas, lambdas
