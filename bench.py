@@ -173,6 +173,62 @@ def run_serving(args, rate, dev, circuits):
     }
 
 
+BF16_DENSE_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix-core peak
+
+
+def sector_gemm_chi2048(MPS, dev, circuits):
+    """Theta formation of one brickwork layer (32 gates) of a synthetic chi=2048
+    state in both forms: the plain complex128 kernel (products and gate mix
+    fused, FP64) and the split-BF16 products on the matrix cores (plus the
+    FP64 gate mix), with the whole layer's time and the forms' difference."""
+    import numpy as np
+    import torch
+    from paper_2303_11409_amd.binding import FORM_PLAIN_C128, FORM_SPLIT_BF16X3
+    ch, gam, lam = circuits.synthetic_state(64, 32, 4, 2048, seed=30)
+    lay = circuits.brickwork_layers(64, 1, 3)[0]
+    pats = circuits.sample_patterns(64, 32, 4, 256, 103)
+    res, amps = {}, {}
+    for form in (FORM_PLAIN_C128, FORM_SPLIT_BF16X3):
+        m = MPS.from_vidal(4, 32, ch, gam, lam, chi_max=2048, cutoff=1e-12, form=form, device=dev)
+        m.set_timing(True)
+        m.reset_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.apply_layer([g.site for g in lay], [g.u for g in lay])
+        m.sync()
+        el = time.perf_counter() - t0
+        res[form] = (m.stats(), el)
+        amps[form] = m.amplitudes(pats)
+        m.close()
+    sp, tp = res[FORM_PLAIN_C128]
+    ss, ts = res[FORM_SPLIT_BF16X3]
+    flops = sp["theta_flops"]
+    split_ms = ss["gemm_ms"] + ss["theta_ms"]
+    a, r = amps[FORM_SPLIT_BF16X3], amps[FORM_PLAIN_C128]
+    return {
+        "workload": "one brickwork layer (32 gates) of a synthetic chi=2048 state: L=64, N=32, d=4, bond k "
+                    "charges Gaussian (width 3) around N(L-k)/L normalised to 2048 and clipped by the Fock "
+                    "bound, complex Gaussian Gamma on the allowed blocks, lambda 1..1e-4 (seed 30)",
+        "algorithmic_flops": flops,
+        "plain": {"kernel": "theta_kernel (complex128 products and gate mix fused, FP64 FMA)",
+                  "ms": sp["theta_ms"], "tflops": flops / sp["theta_ms"] / 1e9,
+                  "frac_of_fp64_peak": flops / sp["theta_ms"] / 1e9 / FP64_VECTOR_PEAK_TFLOPS},
+        "split_bf16x3": {
+            "kernel": "split_gemm_kernel (v_mfma_f32_32x32x16_bf16, 3 products per real product, FP32 "
+                      "accumulation) + theta_mix_kernel (FP64 gate mix)",
+            "gemm_ms": ss["gemm_ms"], "mix_ms": ss["theta_ms"],
+            "tflops_algorithmic": flops / ss["gemm_ms"] / 1e9,
+            "mfma_executed_flops": ss["gemm_mfma_flops"],
+            "mfma_executed_tflops": ss["gemm_mfma_flops"] / ss["gemm_ms"] / 1e9,
+            "frac_of_bf16_peak": ss["gemm_mfma_flops"] / ss["gemm_ms"] / 1e9 / BF16_DENSE_PEAK_TFLOPS,
+            "theta_speedup_vs_plain": sp["theta_ms"] / split_ms},
+        "split_vs_plain_amplitude_rel_err": float(np.linalg.norm(a - r) / np.linalg.norm(r)),
+        "layer_seconds": {"plain": tp, "split_bf16x3": ts},
+        "layer_jacobi_ms": {"plain": sp["jacobi_ms"] + sp["jacobi_aux_ms"],
+                            "split_bf16x3": ss["jacobi_ms"] + ss["jacobi_aux_ms"]},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +240,8 @@ def main() -> int:
                     help="batching form: seeds of the same circuit run together (0 = skip)")
     ap.add_argument("--mix-circuits", type=int, default=64,
                     help="batching form: first circuits of the mixed-size workload run together (0 = skip)")
+    ap.add_argument("--no-chi2048", action="store_true",
+                    help="skip the sector-product measurement on a chi=2048 layer")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="serving form: length of each serving window (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serving form: arrivals per second")
@@ -304,6 +362,12 @@ def main() -> int:
                 "flops_per_launch": per_launch_flops, "launches": launches}
     props = torch.cuda.get_device_properties(0)
     value = args.steps * ngates / elapsed
+    if not args.no_chi2048:
+        log("sector products on a chi=2048 layer, plain and split-BF16 ...")
+        forms["sector_gemm_chi2048"] = sector_gemm_chi2048(MPS, dev, circuits)
+        g = forms["sector_gemm_chi2048"]
+        log(f"  plain {g['plain']['tflops']:.1f} TFLOP/s, split {g['split_bf16x3']['tflops_algorithmic']:.1f} "
+            f"(MFMA {100 * g['split_bf16x3']['frac_of_bf16_peak']:.1f}% of BF16 peak)")
     if args.serve_seconds > 0:
         log(f"serving form: {args.serve_seconds:.0f} s at {args.serve_rate:g} requests/s ...")
         forms["serving"] = run_serving(args, args.serve_rate, dev, circuits)

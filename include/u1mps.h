@@ -133,6 +133,8 @@ typedef struct {
                                /*   products execute, tile padding included    */
                                /*   (24 per complex multiply-add: 4 real       */
                                /*   products x 3 split terms x 2)              */
+  double split_ms;             /* split-BF16 form: splitting the site tensors  */
+                               /*   into BF16 planes before the products       */
 } mps_stats;
 
 /* Fill *o with the defaults: chi_max 0, cutoff 0, zero_tol 1e-13,

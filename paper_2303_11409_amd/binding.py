@@ -64,7 +64,7 @@ class mps_stats(C.Structure):
                 ("update_launches", C.c_longlong), ("polish_launches", C.c_longlong),
                 ("max_discarded", C.c_double), ("min_margin", C.c_double),
                 ("gemm_ms", C.c_double), ("gemm_launches", C.c_longlong),
-                ("gemm_mfma_flops", C.c_double)]
+                ("gemm_mfma_flops", C.c_double), ("split_ms", C.c_double)]
 
 
 EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_destroy", "mps_apply_gate",

@@ -69,17 +69,37 @@ struct ThetaTile {
   int pr0, pc0, ldp;
 };
 
-// Split-BF16 sector product (precision form): C (m x n, complex64, row-major,
-// ldc) = A (m x k) B (k x n), A and B complex128 row-major; each real product
-// runs as three BF16 products of the operands' high and low parts with FP32
-// accumulation.
-constexpr int kSgTile = 64;       // output tile edge
+// Split-BF16 form.  Before the products, each gate's two site tensors are
+// split into BF16 planes (re hi, re lo, im hi, im lo; x = hi + lo with
+// hi = bf16(x), lo = bf16(x - hi)) over a padded k axis (the middle bond,
+// every charge block starting at a multiple of 8, zeros between blocks):
+// A planes hold B[s] (rows = bond s), B planes hold B[s+1] transposed
+// (rows = bond s+2), so both operands have k contiguous.
+constexpr int kSgTile = 64;       // output tile edge of the products
 constexpr int kSgK = 32;          // k chunk staged per step
+constexpr int kSpTile = 32;       // tile edge of the split pass
 
+struct SplitPlanes {
+  const double2* src;     // the site frame
+  int ld;                 // its row stride
+  int rows;               // output rows (A: chi_s; B: chi_{s+2})
+  int trans;              // 0: out[i][kk] = src[i][k]; 1: out[j][kk] = src[k][j]
+  int ldk;                // padded k extent, a multiple of 8
+  long long kinv;         // offset in the batch's k table: source k of each padded kk, -1 = pad
+  long long out;          // offset (elements) of plane 0; plane p at out + p * rows * ldk
+  int tiles_k;            // ceil(ldk / kSpTile)
+  int tile_begin;
+};
+
+// One charge-triple product C (m x n, complex64, row-major, ldc) = A (m x k) B
+// (k x n) from the planes: a and b point at plane 0 of the operands' first
+// row and first k (k contiguous, row strides lda and ldb, multiples of 8),
+// plane strides pa and pb.
 struct SplitGemm {
-  const double2* a;
-  const double2* b;
+  const unsigned short* a;
+  const unsigned short* b;
   float2* c;
+  long long pa, pb;
   int m, n, k;
   int lda, ldb, ldc;
   int tiles_n;            // ceil(n / kSgTile)

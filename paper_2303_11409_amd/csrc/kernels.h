@@ -44,6 +44,8 @@ hipError_t launch_zero_fill(double2* const* ptrs, const long long* counts, int n
 hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_t st);
 // Precision form: split-BF16 charge-triple products into the complex64
 // scratch, then the gate mix into the Theta workspaces.
+hipError_t launch_split_planes(const SplitPlanes* plans, int nplan, int ntiles, const int* ktab,
+                               unsigned short* planes, hipStream_t st);
 hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, hipStream_t st);
 hipError_t launch_theta_mix(const GateWork* gates, const ThetaTile* tiles, int ntiles, const SectorWork* secs,
                             const double2* coef, const float2* pbuf, double2* raw, double2* scaled, hipStream_t st);

@@ -1127,65 +1127,108 @@ gather_vec_kernel(const double* __restrict__ src, double* __restrict__ dst,
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// x = h + l with h = bf16(x), l = bf16(x - h): |x - h - l| <= 2^-18 |x|
-// (after the float conversion of x, which adds 2^-24 |x|).
-__device__ __forceinline__ void split_bf16(double x, __bf16& h, __bf16& l) {
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi): |x - hi - lo| <= 2^-18 |x|
+// (after the float conversion of x, which adds 2^-24 |x|); BF16 bit patterns.
+__device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigned short& lo) {
   const float xf = (float)x;
-  h = (__bf16)xf;
-  l = (__bf16)(xf - (float)h);
+  const __bf16 h = (__bf16)xf;
+  const __bf16 l = (__bf16)(xf - (float)h);
+  hi = __builtin_bit_cast(unsigned short, h);
+  lo = __builtin_bit_cast(unsigned short, l);
 }
 
-// LDS planes of one k chunk: [plane][row or column][k], planes (re hi, re lo,
-// im hi, im lo); rows padded to 40 bf16 (80 bytes) so that every 8-element
-// operand read is one aligned 16-byte access.
+__device__ __forceinline__ void split_store(unsigned short* out, long long plane, long long idx, double2 v) {
+  unsigned short h, l;
+  split_bf16(v.x, h, l);
+  out[idx] = h;
+  out[plane + idx] = l;
+  split_bf16(v.y, h, l);
+  out[2 * plane + idx] = h;
+  out[3 * plane + idx] = l;
+}
+
+// The split pass: one 32 x 32 tile (rows x padded k) of one plan's planes per
+// workgroup.  Rows are read along the frame's contiguous axis: directly for
+// A planes, through an LDS transpose for the B planes.
+__global__ void __launch_bounds__(256)
+split_planes_kernel(const SplitPlanes* __restrict__ plans, int nplan, const int* __restrict__ ktab,
+                    unsigned short* __restrict__ planes) {
+  __shared__ double2 tile[kSpTile][kSpTile + 1];
+  int lo = 0, hi = nplan - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (plans[mid].tile_begin <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const SplitPlanes w = plans[lo];
+  const int local = blockIdx.x - w.tile_begin;
+  const int r0 = (local / w.tiles_k) * kSpTile, kk0 = (local % w.tiles_k) * kSpTile;
+  const int* kinv = ktab + w.kinv;
+  unsigned short* out = planes + w.out;
+  const long long plane = (long long)w.rows * w.ldk;
+  const int t = threadIdx.x;
+  if (!w.trans) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = r0 + (t >> 5) + 8 * q, kk = kk0 + (t & 31);
+      if (i < w.rows && kk < w.ldk) {
+        const int k = kinv[kk];
+        const double2 v = k >= 0 ? w.src[(size_t)i * w.ld + k] : make_double2(0.0, 0.0);
+        split_store(out, plane, (long long)i * w.ldk + kk, v);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kl = (t >> 5) + 8 * q, jl = t & 31;
+      const int kk = kk0 + kl, j = r0 + jl;
+      double2 v = make_double2(0.0, 0.0);
+      if (kk < w.ldk && j < w.rows) {
+        const int k = kinv[kk];
+        if (k >= 0) v = w.src[(size_t)k * w.ld + j];
+      }
+      tile[kl][jl] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jl = (t >> 5) + 8 * q, kl = t & 31;
+      const int j = r0 + jl, kk = kk0 + kl;
+      if (j < w.rows && kk < w.ldk) split_store(out, plane, (long long)j * w.ldk + kk, tile[kl][jl]);
+    }
+  }
+}
+
+// LDS rows of one k chunk: 32 BF16 plus 8 of padding (80 bytes), so every
+// 8-element operand read is one aligned 16-byte access.
 constexpr int kSgRow = kSgK + 8;
 
-// 8 consecutive complex elements per thread of a 64 x 32 chunk of A (row t/4,
-// columns 8 (t%4) ..) and of a 32 x 64 chunk of B (column t%64, rows
-// 8 (t/64) ..); out-of-range entries are 0 and issue no load.
-struct SgRegs {
-  double2 a[8], b[8];
-};
-
-__device__ __forceinline__ void sg_fetch(SgRegs& r, const SplitGemm& w, int row0, int col0, int k0) {
-  const int t = threadIdx.x;
-  const int ar = row0 + (t >> 2), ak = k0 + 8 * (t & 3);
-  const int bc = col0 + (t & 63), bk = k0 + 8 * (t >> 6);
+// 16-byte groups (8 k) of a 64-row x 32-k chunk of one operand's 4 planes:
+// 1024 groups, 4 per thread (group g = t + 256 q: plane g / 256, row
+// (g % 256) / 4, k 8 (g % 4)); rows past `rows` and groups starting past `k`
+// read as 0 (the planes are zero between charge blocks, so a group that
+// starts inside the range is exact).
+__device__ __forceinline__ void sg_fetch(uint4 (&r)[4], const unsigned short* __restrict__ base, long long pstride,
+                                         int ld, int rows, int k, int row0, int k0) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    r.a[e] = make_double2(0.0, 0.0);
-    r.b[e] = make_double2(0.0, 0.0);
-    if (ar < w.m && ak + e < w.k) r.a[e] = w.a[(size_t)ar * w.lda + ak + e];
-    if (bc < w.n && bk + e < w.k) r.b[e] = w.b[(size_t)(bk + e) * w.ldb + bc];
+  for (int q = 0; q < 4; ++q) {
+    const int g = threadIdx.x + 256 * q;
+    const int plane = g >> 8, row = (g & 255) >> 2, kg = 8 * (g & 3);
+    r[q] = make_uint4(0u, 0u, 0u, 0u);
+    if (row0 + row < rows && k0 + kg < k)
+      r[q] = *reinterpret_cast<const uint4*>(base + plane * pstride + (size_t)(row0 + row) * ld + k0 + kg);
   }
 }
 
-__device__ __forceinline__ void sg_stage(const SgRegs& r, __bf16 (*as)[kSgTile][kSgRow],
-                                         __bf16 (*bs)[kSgTile][kSgRow]) {
-  const int t = threadIdx.x;
-  bf16x8 p0, p1, p2, p3;
+__device__ __forceinline__ void sg_stage(const uint4 (&r)[4], unsigned short (*buf)[kSgTile][kSgRow]) {
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    __bf16 h, l;
-    split_bf16(r.a[e].x, h, l); p0[e] = h; p1[e] = l;
-    split_bf16(r.a[e].y, h, l); p2[e] = h; p3[e] = l;
+  for (int q = 0; q < 4; ++q) {
+    const int g = threadIdx.x + 256 * q;
+    *reinterpret_cast<uint4*>(&buf[g >> 8][(g & 255) >> 2][8 * (g & 3)]) = r[q];
   }
-  const int ar = t >> 2, ak = 8 * (t & 3);
-  *reinterpret_cast<bf16x8*>(&as[0][ar][ak]) = p0;
-  *reinterpret_cast<bf16x8*>(&as[1][ar][ak]) = p1;
-  *reinterpret_cast<bf16x8*>(&as[2][ar][ak]) = p2;
-  *reinterpret_cast<bf16x8*>(&as[3][ar][ak]) = p3;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    __bf16 h, l;
-    split_bf16(r.b[e].x, h, l); p0[e] = h; p1[e] = l;
-    split_bf16(r.b[e].y, h, l); p2[e] = h; p3[e] = l;
-  }
-  const int bc = t & 63, bk = 8 * (t >> 6);
-  *reinterpret_cast<bf16x8*>(&bs[0][bc][bk]) = p0;
-  *reinterpret_cast<bf16x8*>(&bs[1][bc][bk]) = p1;
-  *reinterpret_cast<bf16x8*>(&bs[2][bc][bk]) = p2;
-  *reinterpret_cast<bf16x8*>(&bs[3][bc][bk]) = p3;
+}
+
+__device__ __forceinline__ bf16x8 sg_op(const unsigned short (*buf)[kSgTile][kSgRow], int plane, int row, int k) {
+  return *reinterpret_cast<const bf16x8*>(&buf[plane][row][k]);
 }
 
 // One 64 x 64 output tile per workgroup; wave w computes the 32 x 32 quadrant
@@ -1193,11 +1236,14 @@ __device__ __forceinline__ void sg_stage(const SgRegs& r, __bf16 (*as)[kSgTile][
 // supplies A[i = l % 32][k = 8 (l / 32) + e] and B[k = 8 (l / 32) + e][j = l % 32]
 // (e = 0..7); its accumulator register r holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
 // Per k step: Re = Ar Br - Ai Bi and Im = Ar Bi + Ai Br, each real product as
-// hi*hi + hi*lo + lo*hi (the lo*lo term is below the split's error).
+// hi*hi + hi*lo + lo*hi (the lo*lo term is below the split's error).  The k
+// chunks go through two LDS buffers: the next chunk's loads are in flight
+// during the products and are staged into the other buffer, one barrier per
+// chunk.
 __global__ void __launch_bounds__(256)
 split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
-  __shared__ __align__(16) __bf16 as[4][kSgTile][kSgRow];
-  __shared__ __align__(16) __bf16 bs[4][kSgTile][kSgRow];
+  __shared__ __align__(16) unsigned short sa[2][4][kSgTile][kSgRow];
+  __shared__ __align__(16) unsigned short sb[2][4][kSgTile][kSgRow];
   int lo = 0, hi = nprob - 1;
   const int tile = blockIdx.x;
   while (lo < hi) {
@@ -1211,22 +1257,25 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
   const int R = 32 * (wave >> 1), Cq = 32 * (wave & 1);
   const int li = lane & 31, lk = 8 * (lane >> 5);
   f32x16 crp = {}, crn = {}, cim = {};
-  SgRegs rg;
-  sg_fetch(rg, w, row0, col0, 0);
+  uint4 ra[4], rb[4];
+  sg_fetch(ra, w.a, w.pa, w.lda, w.m, w.k, row0, 0);
+  sg_fetch(rb, w.b, w.pb, w.ldb, w.n, w.k, col0, 0);
+  sg_stage(ra, sa[0]);
+  sg_stage(rb, sb[0]);
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < w.k; k0 += kSgK) {
-    sg_stage(rg, as, bs);
-    __syncthreads();
-    if (k0 + kSgK < w.k) sg_fetch(rg, w, row0, col0, k0 + kSgK);   // in flight during the products
+    const bool more = k0 + kSgK < w.k;
+    if (more) {
+      sg_fetch(ra, w.a, w.pa, w.lda, w.m, w.k, row0, k0 + kSgK);
+      sg_fetch(rb, w.b, w.pb, w.ldb, w.n, w.k, col0, k0 + kSgK);
+    }
 #pragma unroll
     for (int ks = 0; ks < kSgK; ks += 16) {
-      const bf16x8 arh = *reinterpret_cast<const bf16x8*>(&as[0][R + li][ks + lk]);
-      const bf16x8 arl = *reinterpret_cast<const bf16x8*>(&as[1][R + li][ks + lk]);
-      const bf16x8 aih = *reinterpret_cast<const bf16x8*>(&as[2][R + li][ks + lk]);
-      const bf16x8 ail = *reinterpret_cast<const bf16x8*>(&as[3][R + li][ks + lk]);
-      const bf16x8 brh = *reinterpret_cast<const bf16x8*>(&bs[0][Cq + li][ks + lk]);
-      const bf16x8 brl = *reinterpret_cast<const bf16x8*>(&bs[1][Cq + li][ks + lk]);
-      const bf16x8 bih = *reinterpret_cast<const bf16x8*>(&bs[2][Cq + li][ks + lk]);
-      const bf16x8 bil = *reinterpret_cast<const bf16x8*>(&bs[3][Cq + li][ks + lk]);
+      const bf16x8 arh = sg_op(sa[buf], 0, R + li, ks + lk), arl = sg_op(sa[buf], 1, R + li, ks + lk);
+      const bf16x8 aih = sg_op(sa[buf], 2, R + li, ks + lk), ail = sg_op(sa[buf], 3, R + li, ks + lk);
+      const bf16x8 brh = sg_op(sb[buf], 0, Cq + li, ks + lk), brl = sg_op(sb[buf], 1, Cq + li, ks + lk);
+      const bf16x8 bih = sg_op(sb[buf], 2, Cq + li, ks + lk), bil = sg_op(sb[buf], 3, Cq + li, ks + lk);
       crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brh, crp, 0, 0, 0);
       crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, bih, crn, 0, 0, 0);
       cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bih, cim, 0, 0, 0);
@@ -1240,7 +1289,13 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
       cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brl, cim, 0, 0, 0);
       cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, brh, cim, 0, 0, 0);
     }
+    if (more) {
+      // the other buffer was last read before the previous barrier
+      sg_stage(ra, sa[buf ^ 1]);
+      sg_stage(rb, sb[buf ^ 1]);
+    }
     __syncthreads();
+    buf ^= 1;
   }
   const int j = col0 + Cq + li;
   if (j < w.n) {
@@ -1384,6 +1439,13 @@ hipError_t launch_zero_fill(double2* const* ptrs, const long long* counts, int n
 hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_t st) {
   if (nprob <= 0 || ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(zgemm_kernel, dim3(ntiles), dim3(256), 0, st, probs, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_planes(const SplitPlanes* plans, int nplan, int ntiles, const int* ktab,
+                               unsigned short* planes, hipStream_t st) {
+  if (nplan <= 0 || ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(split_planes_kernel, dim3(ntiles), dim3(256), 0, st, plans, nplan, ktab, planes);
   return hipGetLastError();
 }
 

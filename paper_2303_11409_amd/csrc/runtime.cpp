@@ -80,7 +80,7 @@ struct PinBuf {
   size_t cap = 0;
 };
 
-enum Kind { K_THETA = 0, K_SELECT, K_UPDATE, K_JACOBI, K_JACOBI_AUX, K_GEMM };
+enum Kind { K_THETA = 0, K_SELECT, K_UPDATE, K_JACOBI, K_JACOBI_AUX, K_GEMM, K_SPLIT };
 
 struct Pending {
   int kind;
@@ -107,7 +107,7 @@ struct mps_state {
   std::vector<double2*> site;    // per site, cap[s] * cap[s+1] complex
   // workspaces (grow-only)
   DevBuf th_raw, th_scaled, acc, sigma, order, jperm, jnorm, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc,
-      pbuf;
+      pbuf, planes;
   PinBuf stage_plan, stage_upd, stage_res, stage_misc, stage_flag;
   mps_stats stats{};
   bool timing = false;
@@ -237,6 +237,7 @@ mps_status drain_events(mps_state* h) {
       case K_JACOBI: h->stats.jacobi_ms += ms; break;
       case K_JACOBI_AUX: h->stats.jacobi_aux_ms += ms; break;
       case K_GEMM: h->stats.gemm_ms += ms; break;
+      case K_SPLIT: h->stats.split_ms += ms; break;
       default: h->stats.update_ms += ms; break;
     }
     h->pool.push_back(p.a);
@@ -337,9 +338,14 @@ struct BatchPlan {
   int sig_elems = 0;
   int maxw = 1;
   double theta_flops = 0.0;
-  // split-BF16 form: one product per charge triple into the complex64 scratch
+  // split-BF16 form: the BF16 planes of every gate's two site tensors, then
+  // one product per charge triple into the complex64 scratch
   bool split = false;
-  std::vector<SplitGemm> sg;              // c holds the scratch offset until upload
+  std::vector<SplitPlanes> spl;
+  std::vector<int> ktab;                  // padded k -> source k (-1 = pad), all gates
+  int spl_tiles = 0;
+  long long plane_elems = 0;
+  std::vector<SplitGemm> sg;              // a, b, c hold buffer offsets until upload
   int sg_tiles = 0;
   long long p_elems = 0;
   double sg_mfma_flops = 0.0;
@@ -419,6 +425,29 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
     P.maxP = std::max(P.maxP, Pp);
     P.sel_off.push_back(P.sel_scratch);
     P.sel_scratch += Pp;
+    // split-BF16 form: planes of B[s] and of B[s+1] transposed over the middle
+    // bond with every charge block padded to a multiple of 8
+    std::vector<int> pm(BM.charge.size() + 1, 0);
+    long long planeA = 0, planeB = 0;
+    int ldk = 0;
+    if (P.split) {
+      for (size_t i = 0; i < BM.charge.size(); ++i) pm[i + 1] = pm[i] + ((BM.count[i] + 7) & ~7);
+      ldk = pm.back();
+      const long long k0 = (long long)P.ktab.size();
+      for (size_t i = 0; i < BM.charge.size(); ++i)
+        for (int t = 0; t < pm[i + 1] - pm[i]; ++t) P.ktab.push_back(t < BM.count[i] ? BM.off[i] + t : -1);
+      const int tk = (ldk + kSpTile - 1) / kSpTile;
+      SplitPlanes pa{gw.bl, gw.ldl, BL.dim(), 0, ldk, k0, P.plane_elems, tk, P.spl_tiles};
+      planeA = P.plane_elems;
+      P.plane_elems += 4LL * BL.dim() * ldk;
+      P.spl_tiles += ((BL.dim() + kSpTile - 1) / kSpTile) * tk;
+      SplitPlanes pb{gw.br, gw.ldr, BR.dim(), 1, ldk, k0, P.plane_elems, tk, P.spl_tiles};
+      planeB = P.plane_elems;
+      P.plane_elems += 4LL * BR.dim() * ldk;
+      P.spl_tiles += ((BR.dim() + kSpTile - 1) / kSpTile) * tk;
+      P.spl.push_back(pa);
+      P.spl.push_back(pb);
+    }
     // tiles
     for (size_t a = 0; a < BL.charge.size(); ++a) {
       const int cL = BL.charge[a];
@@ -441,9 +470,11 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
           ++base.nout;
         }
         int ksum = 0;
+        int mid[kMaxD];
         for (int cM = wlo; cM <= whi; ++cM) {
           const int mi = BM.find(cM);
           if (mi < 0) continue;
+          mid[base.nin] = mi;
           base.k0[base.nin] = BM.off[mi];
           base.kn[base.nin] = BM.count[mi];
           base.a[base.nin] = cL - cM;
@@ -458,11 +489,16 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
           for (int j = 0; j < base.nin; ++j) {
             base.poff[j] = P.p_elems;
             SplitGemm sg{};
-            sg.a = gw.bl + (size_t)BL.off[a] * gw.ldl + base.k0[j];
-            sg.lda = gw.ldl;
-            sg.b = gw.br + (size_t)base.k0[j] * gw.ldr + BR.off[b];
-            sg.ldb = gw.ldr;
-            sg.c = reinterpret_cast<float2*>((uintptr_t)(P.p_elems * (long long)sizeof(float2)));
+            // offsets (elements) into the plane buffer and the scratch until upload
+            sg.a = reinterpret_cast<const unsigned short*>(
+                (uintptr_t)(planeA + (long long)BL.off[a] * ldk + pm[mid[j]]));
+            sg.pa = (long long)BL.dim() * ldk;
+            sg.lda = ldk;
+            sg.b = reinterpret_cast<const unsigned short*>(
+                (uintptr_t)(planeB + (long long)BR.off[b] * ldk + pm[mid[j]]));
+            sg.pb = (long long)BR.dim() * ldk;
+            sg.ldb = ldk;
+            sg.c = reinterpret_cast<float2*>((uintptr_t)P.p_elems);
             sg.ldc = nR;
             sg.m = nL;
             sg.n = nR;
@@ -546,8 +582,14 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   STCHK(ensure(h, h->jnorm, (size_t)P.sig_elems * sizeof(double)));
   if (P.split) {
     STCHK(ensure(h, h->pbuf, (size_t)std::max<long long>(P.p_elems, 1) * sizeof(float2)));
+    STCHK(ensure(h, h->planes, (size_t)std::max<long long>(P.plane_elems, 1) * sizeof(unsigned short)));
     float2* pb = static_cast<float2*>(h->pbuf.p);
-    for (SplitGemm& g : P.sg) g.c = pb + (reinterpret_cast<uintptr_t>(g.c) / sizeof(float2));
+    const unsigned short* pl = static_cast<const unsigned short*>(h->planes.p);
+    for (SplitGemm& g : P.sg) {
+      g.a = pl + reinterpret_cast<uintptr_t>(g.a);
+      g.b = pl + reinterpret_cast<uintptr_t>(g.b);
+      g.c = pb + reinterpret_cast<uintptr_t>(g.c);
+    }
   }
   if (P.maxP > 4096) {
     STCHK(ensure(h, h->sel_v, (size_t)P.sel_scratch * sizeof(double)));
@@ -563,6 +605,8 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   const size_t o_jblk = pk.add(P.jblocks.data(), P.jblocks.size() * sizeof(JacobiBlockWork));
   const size_t o_seloff = pk.add(P.sel_off.data(), P.sel_off.size() * sizeof(long long));
   const size_t o_sg = pk.add(P.sg.data(), P.sg.size() * sizeof(SplitGemm));
+  const size_t o_spl = pk.add(P.spl.data(), P.spl.size() * sizeof(SplitPlanes));
+  const size_t o_ktab = pk.add(P.ktab.data(), P.ktab.size() * sizeof(int));
   const size_t o_kept = pk.add(nullptr, (size_t)ns * sizeof(int));
   const size_t o_cut = pk.add(nullptr, (size_t)ng * sizeof(CutOut));
   const size_t o_jst = pk.add(nullptr, (size_t)ns * sizeof(JacobiOut));
@@ -581,6 +625,13 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   int* ord = static_cast<int*>(h->order.p);
 
   if (P.split) {
+    {
+      Timer tp(h, K_SPLIT);
+      STCHK(tp.start());
+      HIPCHK(launch_split_planes(at<SplitPlanes>(h->plan, o_spl), (int)P.spl.size(), P.spl_tiles,
+                                 at<int>(h->plan, o_ktab), static_cast<unsigned short*>(h->planes.p), h->st));
+      STCHK(tp.stop());
+    }
     {
       Timer tg(h, K_GEMM);
       STCHK(tg.start());
@@ -810,7 +861,8 @@ mps_status destroy_buffers(mps_state* h) {
   h->lam.clear();
   h->site.clear();
   DevBuf* bufs[] = {&h->th_raw, &h->th_scaled, &h->acc, &h->jperm, &h->jnorm, &h->sigma, &h->order, &h->plan, &h->upd,
-                    &h->norm_e0, &h->norm_e1, &h->norm_t, &h->sel_v, &h->sel_k, &h->misc, &h->pbuf};
+                    &h->norm_e0, &h->norm_e1, &h->norm_t, &h->sel_v, &h->sel_k, &h->misc, &h->pbuf,
+                    &h->planes};
   for (DevBuf* b : bufs) {
     dfree(h, b->p);
     b->p = nullptr;
