@@ -32,14 +32,15 @@ if ROOT not in sys.path:
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
 
 # HBM bytes per launch of jacobi_block_step on this workload, from two
-# rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline`
+# rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline
+# --batch-copies 0 --mix-circuits 0 --no-chi2048 --serve-seconds 0`
 # (FETCH_SIZE, WRITE_SIZE; mean over the launches) scaled by the same counters
 # on a plain 256 MiB copy (`bench.py --copy-probe`: FETCH_SIZE reads 131085.2
 # KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99982 and writes
-# by 1).  Valid only for the kernel source it was taken on.
+# by 1).  Valid only for the Jacobi source (csrc/jacobi.hip) it was taken on.
 MEASURED_TRAFFIC = {
-    "kernels_sha256": "891f9fd10b1e72786f253c0c0a11d5199d9652c78535f391823423c426ab1a59",
-    "fetch_kib": 21003.362, "write_kib": 35415.419,
+    "kernels_sha256": "60d88e3d9488717c40043df2fa82c35d2c6663215377ac3e2eadd45ff5a2ea67",
+    "fetch_kib": 20999.992, "write_kib": 35415.614,
     "fetch_scale": 262144.0 / 131085.208, "write_scale": 1.0,
 }
 
@@ -47,7 +48,7 @@ MEASURED_TRAFFIC = {
 def measured_traffic():
     """Bytes per launch from the counters, or None once the kernel source changed."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2303_11409_amd", "csrc", "kernels.hip")
+    src = os.path.join(ROOT, "paper_2303_11409_amd", "csrc", "jacobi.hip")
     try:
         with open(src, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()

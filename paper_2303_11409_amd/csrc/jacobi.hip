@@ -1,0 +1,694 @@
+// Per-sector SVD of the two-site update (Sec. II: the SVD of Theta split into
+// its middle-charge blocks): blocked one-sided (Hestenes) Jacobi in FP64 on
+// every Theta(m) of a batch, one launch per round-robin step.
+#include "device_util.h"
+#include "kernels.h"
+
+namespace u1mps {
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD of Theta(m), blocked.
+//
+// The SVD runs on the min(r, c) vectors of length max(r, c): the rows of
+// Theta when r <= c, else its columns (the theta kernel stores a tall sector
+// transposed).  A vector pair (x, y) with alpha = |x|^2, beta = |y|^2,
+// gamma = <x, y> is made orthogonal by the rotation
+//   zeta = (beta - alpha) / (2|gamma|), t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+//   c = 1/sqrt(1 + t^2), s = c t, w = s gamma/|gamma|,
+//   x' = c x - w y,  y' = conj(w) x + c y,
+// applied while |gamma| > tol sqrt(alpha beta) and |gamma| is above the
+// rounding floor of the sector.  Vectors are grouped in blocks of kJB; a
+// round-robin (circle method) schedule over the blocks pairs every two
+// blocks once per sweep.  For a block pair the workgroup forms the Gram
+// matrix G = X X^H of its 2 kJB vectors, applies the same rotations to G
+// (G <- U G U^H) until its off-diagonal is below tolerance, accumulating
+// W = prod U, and finally rotates the vectors, X <- W X.  Convergence is
+// always judged on a Gram matrix freshly formed from the vectors, so the
+// stopping rule is the same pairwise-cosine test as for the unblocked method.
+// With J the product of all rotations, J X = S Y with orthonormal rows Y:
+//   wide (X = Theta):    V^dagger = Y, the normalised vectors;
+//   tall (X = Theta^T):  V^dagger = conj(J), accumulated in A (c x c) from I.
+__device__ __forceinline__ void rr_pair(int step, int k, int np, int& i, int& j) {
+  const int q = np - 1;
+  if (k == 0) {
+    i = step % q;
+    j = q;
+  } else {
+    i = (step + k) % q;
+    j = (step - k + q) % q;
+  }
+}
+
+// a' = c a - w b ; b' = conj(w) a + c b, with w = wr + i wi
+__device__ __forceinline__ void rot_pair(double2& a, double2& b, double c, double wr, double wi) {
+  const double2 x = a, y = b;
+  a.x = c * x.x - (wr * y.x - wi * y.y);
+  a.y = c * x.y - (wr * y.y + wi * y.x);
+  b.x = (wr * x.x + wi * x.y) + c * y.x;
+  b.y = (wr * x.y - wi * x.x) + c * y.y;
+}
+
+__device__ __forceinline__ bool jac_rotation(double al, double be, double gr, double gi, double tol,
+                                             double floor_g, double& c, double& wr, double& wi) {
+  // test on squares: |gamma|^2 > tol^2 alpha beta and |gamma| > floor
+  const double g2 = gr * gr + gi * gi;
+  if (!(g2 > tol * tol * al * be) || !(g2 > floor_g * floor_g)) return false;
+  // with delta = beta - alpha, r = sqrt(delta^2 + 4|gamma|^2), D = |delta| + r:
+  // c = D / E, w = 2 sgn(delta) gamma / E with E^2 = D^2 + 4|gamma|^2 = 2 r D --
+  // the same rotation as t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+  // zeta = delta / (2|gamma|), c = 1/sqrt(1 + t^2), w = c t gamma/|gamma|
+  const double delta = be - al;
+  const double r = sqrt(delta * delta + 4.0 * g2);
+  const double D = fabs(delta) + r;
+  const double inv = rsqrt(2.0 * r * D);
+  const double sg = delta >= 0.0 ? 2.0 * inv : -2.0 * inv;
+  c = D * inv;
+  wr = sg * gr;
+  wi = sg * gi;
+  return true;
+}
+
+// Default threshold: (vector length) * eps, but never below 2 * kJP * eps,
+// the rounding level of the kJP-term combinations X <- W X that rotate a
+// block pair (short vectors would otherwise be held to a test they cannot
+// pass).
+__device__ __forceinline__ double jac_tol(double tol_opt, int len) {
+  return tol_opt > 0.0 ? tol_opt : (double)max(len, 2 * kJP) * DBL_EPSILON;
+}
+
+// One workgroup per sector: reset state, vector norms, identity order,
+// squared Frobenius norm, A = I.
+__global__ void __launch_bounds__(256)
+jacobi_init(const SectorWork* __restrict__ secs, const int* __restrict__ list,
+            const double2* __restrict__ theta, double2* __restrict__ accbuf,
+            JacobiOut* __restrict__ st, int* __restrict__ perm, double* __restrict__ norm2) {
+  __shared__ double wsum[4];
+  const int sid = list[blockIdx.x];
+  const SectorWork sw = secs[sid];
+  const bool tall = sw.tall != 0;
+  const int n = tall ? sw.c : sw.r;
+  const int len = tall ? sw.r : sw.c;
+  const double2* x = theta + sw.off;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (tall) {
+    double2* a = accbuf + sw.acc;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x)
+      a[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
+  }
+  double f = 0.0;
+  for (int i = wave; i < n; i += 4) {
+    const double2* xi = x + (size_t)i * len;
+    double ss = 0.0;
+    for (int col = lane; col < len; col += 64) {
+      const double2 v = xi[col];
+      ss = fma(v.x, v.x, fma(v.y, v.y, ss));
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) {
+      norm2[sw.sig + i] = ss;
+      perm[sw.sig + i] = i;
+    }
+    f += ss;
+  }
+  if (lane == 0) wsum[wave] = f;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    JacobiOut o;
+    o.sweeps = 0;
+    o.rotations = 0;
+    o.converged = n < 2 ? 1 : 0;
+    o.rot_this_sweep = 0;
+    o.gram_units = 0;
+    o.apply_units = 0;
+    o.fro2 = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    st[sid] = o;
+  }
+}
+
+// Column chunks of the kJP rows vrow[r] (-1 = absent) of a row-major matrix
+// with row length len.  A chunk is 32 columns; each of the 256 threads moves
+// kJChunkRegs of its elements (rows 8 k + tid / 32, column tid % 32), so a
+// wavefront reads two contiguous 512-byte row segments per load.  Absent
+// rows and columns past len read as 0 and issue no load.
+constexpr int kJChunkRegs = kJP * 32 / 256;
+
+__device__ __forceinline__ void jac_fetch(double2 (&v)[kJChunkRegs], const double2* __restrict__ x,
+                                          int len, int c0, const int* vrow) {
+  const int cc = threadIdx.x & 31, col = c0 + cc;
+#pragma unroll
+  for (int k = 0; k < kJChunkRegs; ++k) {
+    const int row = vrow[8 * k + (threadIdx.x >> 5)];
+    v[k] = make_double2(0.0, 0.0);
+    if (row >= 0 && col < len) v[k] = x[(size_t)row * len + col];
+  }
+}
+
+__device__ __forceinline__ void jac_stage(double2 (*xs)[33], const double2 (&v)[kJChunkRegs]) {
+  const int cc = threadIdx.x & 31;
+#pragma unroll
+  for (int k = 0; k < kJChunkRegs; ++k) xs[8 * k + (threadIdx.x >> 5)][cc] = v[k];
+}
+
+// Runs body(c0) for every chunk [c0, c0 + 32) of the rows, with the chunk
+// staged in xs.  Two chunks are in flight in registers while the body works
+// on the staged one, so the loads of chunk c0 + 64 overlap the body of c0.
+// The body may overwrite columns [c0, c0 + 32) of x (the loads in flight
+// are of later columns).
+template <class Body>
+__device__ __forceinline__ void jac_chunk_loop(double2 (*xs)[33], const double2* x, int len,
+                                               const int* vrow, Body&& body) {
+  double2 ra[kJChunkRegs], rb[kJChunkRegs];
+  jac_fetch(ra, x, len, 0, vrow);
+  jac_fetch(rb, x, len, 32, vrow);
+  for (int c0 = 0; c0 < len; c0 += 64) {
+    jac_stage(xs, ra);
+    __syncthreads();
+    jac_fetch(ra, x, len, c0 + 64, vrow);
+    body(c0);
+    __syncthreads();
+    if (c0 + 32 >= len) break;
+    jac_stage(xs, rb);
+    __syncthreads();
+    jac_fetch(rb, x, len, c0 + 96, vrow);
+    body(c0 + 32);
+    __syncthreads();
+  }
+}
+
+// X_IJ <- W X_IJ for one row-major matrix (rows of length len), in column
+// chunks of 32, on the matrix cores: wave w computes the 16 x 16 output
+// quadrant (rows 16 (w / 2), columns 16 (w % 2)) of each chunk as four real
+// products per k-step, Or = Wr Xr - Wi Xi and Oi = Wr Xi + Wi Xr.
+__device__ void jac_apply(double2 (*xs)[33], double2 (*ws)[kJP + 1], double2* __restrict__ x,
+                          int len, const int* vrow) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R = (wave >> 1) * 16, Cq = (wave & 1) * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  jac_chunk_loop(xs, x, len, vrow, [&](int c0) {
+    v4d orr = {0.0, 0.0, 0.0, 0.0}, oi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < kJP; k0 += 4) {
+      const double2 wv = ws[R + li][k0 + lk];      // A = W[R + i][k]
+      const double2 xv = xs[k0 + lk][Cq + li];     // B = X[k][C + j]
+      orr = mfma16x16x4(wv.x, xv.x, orr);
+      orr = mfma16x16x4(-wv.y, xv.y, orr);
+      oi = mfma16x16x4(wv.x, xv.y, oi);
+      oi = mfma16x16x4(wv.y, xv.x, oi);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int v = vrow[R + 4 * r + lk];
+      const int col = c0 + Cq + li;
+      if (v >= 0 && col < len) x[(size_t)v * len + col] = make_double2(orr[r], oi[r]);
+    }
+  });
+}
+
+// Gram matrix G = X X^H of the kJP rows into gs, on the matrix cores, with
+// three real products: Gr = Xr Xr^T + Xi Xi^T (symmetric) and Gi = M - M^T
+// with M = Xi Xr^T.  Waves 0, 1, 2 form the Gr quadrants (0,0), (0,16),
+// (16,16) and the same quadrants of M; wave 3 forms M's quadrant (16,0).
+// Gr's diagonal quadrants give both triangles with different rounding;
+// every decision must see one value per pair, so gs is made exactly
+// Hermitian from its upper triangle.  M passes through xs.
+__device__ void jac_gram(double2 (*xs)[33], double2 (*gs)[kJP + 1], const double2* x, int len,
+                         const int* vrow) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int P = wave >= 2 ? 16 : 0, Q = (wave == 1 || wave == 2) ? 16 : 0;
+  const int li = lane & 15, lk = lane >> 4;
+  const bool has_gr = wave < 3;
+  v4d gra = {0.0, 0.0, 0.0, 0.0}, grb = {0.0, 0.0, 0.0, 0.0}, mm = {0.0, 0.0, 0.0, 0.0};
+  jac_chunk_loop(xs, x, len, vrow, [&](int) {
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 4) {
+      const double2 av = xs[P + li][k0 + lk];     // A = X[P + i][k]
+      const double2 bv = xs[Q + li][k0 + lk];     // B = X[Q + j][k] (transposed)
+      if (has_gr) {
+        gra = mfma16x16x4(av.x, bv.x, gra);
+        grb = mfma16x16x4(av.y, bv.y, grb);
+      }
+      mm = mfma16x16x4(av.y, bv.x, mm);
+    }
+  });
+  // the loop ended on a barrier: xs is free
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (has_gr) gs[P + 4 * r + lk][Q + li] = make_double2(gra[r] + grb[r], 0.0);
+    xs[P + 4 * r + lk][Q + li] = make_double2(mm[r], 0.0);
+  }
+  __syncthreads();
+  for (int e = tid; e < kJP * kJP; e += blockDim.x) {
+    const int r = e / kJP, c = e % kJP;
+    if (r < c) {
+      const double2 g = make_double2(gs[r][c].x, xs[r][c].x - xs[c][r].x);
+      gs[r][c] = g;
+      gs[c][r] = cconj(g);
+    }
+  }
+}
+
+// Pair k of round-robin step s over the kJP rows of a block pair, as (p, q)
+// with p < q: the rotation always reads the upper-triangle entry.
+__device__ __forceinline__ void jac_pair_ordered(int s, int k, int& p, int& q) {
+  int i, j;
+  rr_pair(s, k, kJP, i, j);
+  p = min(i, j);
+  q = max(i, j);
+}
+
+// Pair k of round-robin step s over the kJP rows as (p, q), p < q: the pairs
+// of rr_pair(s, k, kJP), (s + k, s - k) mod (kJP - 1) and (s, kJP - 1) for
+// k = 0, computed with selects instead of divisions (s < kJP - 1, k < kJP / 2).
+__device__ __forceinline__ void jac_pair_fast(int s, int k, int& p, int& q) {
+  int i = s + k;
+  i = i >= kJP - 1 ? i - (kJP - 1) : i;
+  int j = s - k;
+  j = j < 0 ? j + (kJP - 1) : j;
+  j = k == 0 ? kJP - 1 : j;
+  p = min(i, j);
+  q = max(i, j);
+}
+
+// Workgroup-wide OR of a predicate with one barrier: lane 0 of each
+// wavefront publishes its wavefront's ballot in slot `parity` of flags, which
+// alternates between calls, so a slot is rewritten only after every thread
+// has passed the barrier of the call in between.  Every thread of the
+// workgroup must make the same sequence of calls.
+__device__ __forceinline__ bool block_any(int pred, int4* flags, int& parity) {
+  const bool w = __ballot(pred) != 0ull;
+  int* f = reinterpret_cast<int*>(flags + parity);
+  if ((threadIdx.x & 63) == 0) f[threadIdx.x >> 6] = w ? 1 : 0;
+  __syncthreads();
+  const int4 v = flags[parity];
+  parity ^= 1;
+  return (v.x | v.y | v.z | v.w) != 0;
+}
+
+// True if the pair (p, q) of a Gram matrix with diagonal alpha, beta and
+// off-diagonal gamma is above the rotation threshold (the test of
+// jac_rotation without computing the rotation).
+__device__ __forceinline__ bool jac_needs(double al, double be, double2 g, double tol, double floor_g) {
+  const double g2 = g.x * g.x + g.y * g.y;
+  return g2 > tol * tol * al * be && g2 > floor_g * floor_g;
+}
+
+// True if any off-diagonal pair of the Hermitian gs is above the threshold:
+// thread t checks the upper-triangle entries of its 2 x 2 block (rows
+// 2 (t / 16), columns 2 (t % 16)).  Uniform across the workgroup.
+__device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 1], double tol, double floor_g,
+                                              int4* anyf, int& parity) {
+  const int p0 = 2 * (threadIdx.x >> 4), q0 = 2 * (threadIdx.x & 15);
+  int f = 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int p = p0 + i, q = q0 + j;
+      if (p < q && jac_needs(gs[p][p].x, gs[q][q].x, gs[p][q], tol, floor_g)) f = 1;
+    }
+  return block_any(f, anyf, parity);
+}
+
+// Rotations of the Gram matrix gs (in LDS) until no pair exceeds the
+// threshold; W accumulates the product.  The caller has established that
+// some pair is above it.  A round-robin step rotates 16 disjoint pairs at
+// once, G <- U G U^H and W <- U W with U block diagonal over the pairs: 16
+// threads compute the pairs' rotations into rot[], then thread t = 16 A + B
+// updates the 2 x 2 blocks (rows of pair A) x (columns of pair B) of G and W
+// in place (each block is read and written by its owner only).  After each
+// sweep one parallel test over all pairs replaces the sweep that would find
+// nothing to rotate (it would leave G and W unchanged).
+__device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], double4* rot,
+                             double tol, double floor_g, int max_inner, int4* anyf, int& parity) {
+  const int tid = threadIdx.x;
+  const int A = tid >> 4, B = tid & 15;
+  for (int inner = 0; inner < max_inner; ++inner) {
+    for (int s2 = 0; s2 < kJP - 1; ++s2) {
+      // G and W change only in update phases, each closed by a barrier, so
+      // this thread's block is read before the rotations are published
+      int pa, qa, pb, qb;
+      jac_pair_fast(s2, A, pa, qa);
+      jac_pair_fast(s2, B, pb, qb);
+      double2 g00 = gs[pa][pb], g01 = gs[pa][qb], g10 = gs[qa][pb], g11 = gs[qa][qb];
+      double2 w00 = ws[pa][pb], w01 = ws[pa][qb], w10 = ws[qa][pb], w11 = ws[qa][qb];
+      int flag = 0;
+      if (tid < kJP / 2) {
+        int p, q;
+        jac_pair_fast(s2, tid, p, q);
+        double c = 1.0, wr = 0.0, wi = 0.0;
+        const double2 g = gs[p][q];
+        flag = jac_rotation(gs[p][p].x, gs[q][q].x, g.x, g.y, tol, floor_g, c, wr, wi) ? 1 : 0;
+        rot[tid] = make_double4(c, wr, wi, flag ? 1.0 : 0.0);
+      }
+      if (!block_any(flag, anyf, parity)) continue;
+      const double4 ra = rot[A], rb = rot[B];
+      if (ra.w != 0.0 || rb.w != 0.0) {
+        if (ra.w != 0.0) {        // rows pa, qa: U from the left, also on W
+          rot_pair(g00, g10, ra.x, ra.y, ra.z);
+          rot_pair(g01, g11, ra.x, ra.y, ra.z);
+          rot_pair(w00, w10, ra.x, ra.y, ra.z);
+          rot_pair(w01, w11, ra.x, ra.y, ra.z);
+          ws[pa][pb] = w00; ws[pa][qb] = w01; ws[qa][pb] = w10; ws[qa][qb] = w11;
+        }
+        if (rb.w != 0.0) {        // columns pb, qb: U^H from the right
+          rot_pair(g00, g01, rb.x, rb.y, -rb.z);
+          rot_pair(g10, g11, rb.x, rb.y, -rb.z);
+        }
+        gs[pa][pb] = g00; gs[pa][qb] = g01; gs[qa][pb] = g10; gs[qa][qb] = g11;
+      }
+      __syncthreads();
+    }
+    if (!jac_any_above(gs, tol, floor_g, anyf, parity)) break;
+  }
+  __syncthreads();
+}
+
+// One round-robin step for every active sector: one workgroup per block pair.
+//
+// A block pair that fails the convergence test is rotated in two passes.
+// Pass 0 diagonalises its Gram matrix only down to kJacLoose relative
+// off-diagonal or the Gram's own rounding level (kJacNoise * eps * max
+// diagonal): rotations of G itself carry errors of order eps * max|G|, which
+// would leave the smallest vectors of the pair with cosines of
+// eps * s_max^2 / (s_p s_q) if pursued further.  Pass 1 forms the Gram matrix
+// afresh from the rotated vectors; it is then nearly diagonal, its rotations
+// are small, their errors are relative to each vector's own norm, and it is
+// driven to the full tolerance.
+constexpr double kJacLoose = 1e-8;
+constexpr double kJacNoise = 64.0;
+
+__global__ void __launch_bounds__(256)
+jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __restrict__ jb,
+                  int njb, int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
+                  JacobiOut* __restrict__ st, const int* __restrict__ perm, double* __restrict__ norm2,
+                  double tol_opt, int max_inner) {
+  __shared__ double2 xs[kJP][33];
+  __shared__ double2 gs[kJP][kJP + 1];
+  __shared__ double2 ws[kJP][kJP + 1];
+  __shared__ double gmax;
+  __shared__ int vrow[kJP];
+  __shared__ double4 rot[kJP / 2];
+  __shared__ int4 anyf[2];
+  int parity = 0;
+  int lo = 0, hi = njb - 1;
+  const int pid = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jb[mid].pair_begin <= pid) lo = mid; else hi = mid - 1;
+  }
+  const JacobiBlockWork w = jb[lo];
+  if (step >= w.nb - 1) return;
+  const int sid = w.sector;
+  if (st[sid].converged) return;
+  const SectorWork sw = secs[sid];
+  const bool tall = sw.tall != 0;
+  const int n = tall ? sw.c : sw.r;
+  const int len = tall ? sw.r : sw.c;
+  double2* x = theta + sw.off;
+  const double tol = jac_tol(tol_opt, len);
+  const double floor_g = (double)len * DBL_EPSILON * DBL_EPSILON * st[sid].fro2;
+  int bi, bj;
+  rr_pair(step, pid - w.pair_begin, w.nb, bi, bj);
+  const int vI = bi * kJB, vJ = bj * kJB;
+  const int nI = max(0, min(kJB, n - vI)), nJ = max(0, min(kJB, n - vJ));
+  const int nv = nI + nJ;
+  const int tid = threadIdx.x;
+  // a block paired with the empty padding block still orthogonalises its own vectors
+  if (nv < 2) return;
+  // block I holds the vectors at sorted positions 16 I .. 16 I + 15
+  if (tid < kJP) {
+    const int pos = tid < kJB ? vI + tid : vJ + (tid - kJB);
+    const int lim = tid < kJB ? vI + nI : vJ + nJ;
+    vrow[tid] = pos < lim ? perm[sw.sig + pos] : -1;
+  }
+  __syncthreads();
+  bool fresh = false;          // gs holds the Gram matrix of the current vectors
+  for (int pass = 0; pass < 2; ++pass) {
+    if (!fresh) {
+      jac_gram(xs, gs, x, len, vrow);
+      if (tid == 0) atomicAdd(&st[sid].gram_units, (unsigned long long)nv * nv * len);
+    }
+    __syncthreads();
+    // ---- largest squared norm (for the coarse noise floor) and any pair
+    // above tolerance?  The barrier inside jac_any_above publishes gmax.
+    if (tid < 64) {
+      double m = tid < kJP ? gs[tid][tid].x : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+      if (tid == 0) gmax = m;
+    }
+    const bool need = jac_any_above(gs, tol, floor_g, anyf, parity);
+    if (!need) break;
+    if (pass == 0 && tid == 0) atomicAdd(&st[sid].rot_this_sweep, 1);
+    // ---- diagonalise G by rotations, W = accumulated product
+    for (int e = tid; e < kJP * kJP; e += blockDim.x) {
+      const int r = e / kJP, c = e % kJP;
+      ws[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    const double ptol = pass == 0 ? fmax(tol, kJacLoose) : tol;
+    const double pfloor = pass == 0 ? fmax(floor_g, kJacNoise * DBL_EPSILON * gmax) : floor_g;
+    if (pass == 0 && !jac_any_above(gs, ptol, pfloor, anyf, parity)) {
+      // nothing above the coarse thresholds: gs is still the Gram matrix of
+      // the unchanged vectors, go straight to the full-tolerance pass
+      fresh = true;
+      continue;
+    }
+    jac_gram_eig(gs, ws, rot, ptol, pfloor, max_inner, anyf, parity);
+    // ---- rotate the vectors (and the accumulator of a tall sector)
+    jac_apply(xs, ws, x, len, vrow);
+    if (tall) jac_apply(xs, ws, accbuf + sw.acc, n, vrow);
+    if (tid == 0) atomicAdd(&st[sid].apply_units, (unsigned long long)nv * nv * (len + (tall ? n : 0)));
+    fresh = false;
+    __syncthreads();
+  }
+  // latest squared norms of the pair's vectors (the Gram diagonal; after a
+  // rotation the rotated Gram's diagonal), for the next sweep's ordering
+  __syncthreads();
+  if (tid < kJP && vrow[tid] >= 0) norm2[sw.sig + vrow[tid]] = gs[tid][tid].x;
+}
+
+// Scalar one-sided Jacobi sweeps on the vectors themselves, for the rare
+// sector the blocked sweeps leave unconverged.  One workgroup per listed
+// sector; each wavefront takes whole vector pairs of a round-robin step,
+// forms alpha, beta, gamma with wave reductions and rotates both vectors (and
+// the accumulator rows of a tall sector).  A 2x2 rotation has only two-term
+// rounding, so it reaches cosines of order sqrt(len) eps, well inside the
+// tolerance.  Runs up to max_sweeps sweeps and marks the sector converged
+// when a sweep rotates nothing.
+__global__ void __launch_bounds__(256)
+jacobi_polish(const SectorWork* __restrict__ secs, const int* __restrict__ list,
+              double2* __restrict__ theta, double2* __restrict__ accbuf,
+              JacobiOut* __restrict__ st, double tol_opt, int max_sweeps) {
+  __shared__ int rotated;
+  const int sid = list[blockIdx.x];
+  if (st[sid].converged) return;
+  const SectorWork sw = secs[sid];
+  const bool tall = sw.tall != 0;
+  const int n = tall ? sw.c : sw.r;
+  const int len = tall ? sw.r : sw.c;
+  double2* x = theta + sw.off;
+  double2* acc = tall ? accbuf + sw.acc : nullptr;
+  const double tol = jac_tol(tol_opt, len);
+  const double floor_g = (double)len * DBL_EPSILON * DBL_EPSILON * st[sid].fro2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int np = n + (n & 1);
+  bool converged = false;
+  int sweeps = 0;
+  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+    __syncthreads();
+    if (threadIdx.x == 0) rotated = 0;
+    __syncthreads();
+    for (int step = 0; step < np - 1; ++step) {
+      for (int k = wave; k < np / 2; k += nwaves) {
+        int i, j;
+        rr_pair(step, k, np, i, j);
+        if (i >= n || j >= n) continue;
+        double2* xi = x + (size_t)i * len;
+        double2* xj = x + (size_t)j * len;
+        double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+        for (int col = lane; col < len; col += 64) {
+          const double2 a = xi[col], b = xj[col];
+          al = fma(a.x, a.x, fma(a.y, a.y, al));
+          be = fma(b.x, b.x, fma(b.y, b.y, be));
+          gr = fma(a.x, b.x, fma(a.y, b.y, gr));
+          gi = fma(a.y, b.x, fma(-a.x, b.y, gi));
+        }
+        al = wave_sum(al); be = wave_sum(be); gr = wave_sum(gr); gi = wave_sum(gi);
+        double c, wr, wi;
+        if (!jac_rotation(al, be, gr, gi, tol, floor_g, c, wr, wi)) continue;
+        for (int col = lane; col < len; col += 64) {
+          double2 a = xi[col], b = xj[col];
+          rot_pair(a, b, c, wr, wi);
+          xi[col] = a;
+          xj[col] = b;
+        }
+        if (tall) {
+          double2* ai = acc + (size_t)i * n;
+          double2* aj = acc + (size_t)j * n;
+          for (int col = lane; col < n; col += 64) {
+            double2 a = ai[col], b = aj[col];
+            rot_pair(a, b, c, wr, wi);
+            ai[col] = a;
+            aj[col] = b;
+          }
+        }
+        if (lane == 0) rotated = 1;
+      }
+      __syncthreads();
+    }
+    ++sweeps;
+    converged = rotated == 0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st[sid].sweeps += sweeps;
+    st[sid].converged = converged ? 1 : 0;
+  }
+}
+
+// After a sweep: a sector with no rotated block pair is converged.  One
+// workgroup; *active receives 1 if any sector still rotates.
+__global__ void __launch_bounds__(1024)
+jacobi_sweep_end(const int* __restrict__ list, int count, JacobiOut* __restrict__ st,
+                 int* __restrict__ active) {
+  __shared__ int act;
+  if (threadIdx.x == 0) act = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < count; i += blockDim.x) {
+    const int s = list[i];
+    JacobiOut o = st[s];
+    if (o.converged) continue;
+    o.sweeps += 1;
+    o.rotations += o.rot_this_sweep;
+    if (o.rot_this_sweep == 0) o.converged = 1;
+    else atomicOr(&act, 1);
+    o.rot_this_sweep = 0;
+    st[s] = o;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *active = act;
+}
+
+// Between sweeps: order every still-active sector's vectors by descending
+// norm (ties: lower index first), so that blocks hold vectors of similar
+// size.  One workgroup per sector.
+__global__ void __launch_bounds__(256)
+jacobi_sort(const SectorWork* __restrict__ secs, const int* __restrict__ list,
+            const JacobiOut* __restrict__ st, int* __restrict__ perm,
+            const double* __restrict__ norm2) {
+  const int sid = list[blockIdx.x];
+  if (st[sid].converged) return;
+  const SectorWork sw = secs[sid];
+  const int n = sw.tall ? sw.c : sw.r;
+  const double* nv = norm2 + sw.sig;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = nv[i];
+    int rank = 0;
+    for (int k = 0; k < n; ++k) {
+      const double w = nv[k];
+      rank += (w > v) || (w == v && k < i);
+    }
+    perm[sw.sig + rank] = i;
+  }
+}
+
+// One workgroup per sector: vector norms -> singular values, V^dagger rows
+// into the sector's slot (stride c), order by descending value.
+__global__ void __launch_bounds__(256)
+jacobi_finalize(const SectorWork* __restrict__ secs, const int* __restrict__ list,
+                double2* __restrict__ theta, const double2* __restrict__ accbuf,
+                double* __restrict__ sigma, int* __restrict__ order) {
+  extern __shared__ double jsm[];          // n doubles
+  const int sid = list[blockIdx.x];
+  const SectorWork sw = secs[sid];
+  const bool tall = sw.tall != 0;
+  const int n = tall ? sw.c : sw.r;
+  const int len = tall ? sw.r : sw.c;
+  double2* x = theta + sw.off;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  for (int i = wave; i < n; i += nwaves) {
+    double2* xi = x + (size_t)i * len;
+    double ss = 0.0;
+    for (int col = lane; col < len; col += 64) {
+      const double2 a = xi[col];
+      ss = fma(a.x, a.x, fma(a.y, a.y, ss));
+    }
+    ss = wave_sum(ss);
+    const double nr = sqrt(ss);
+    if (!tall && nr > 0.0) {
+      const double inv = 1.0 / nr;
+      for (int col = lane; col < len; col += 64) {
+        const double2 a = xi[col];
+        xi[col] = make_double2(a.x * inv, a.y * inv);
+      }
+    }
+    if (lane == 0) jsm[i] = nr;
+  }
+  __syncthreads();
+  if (tall) {
+    const double2* a = accbuf + sw.acc;
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) x[e] = cconj(a[e]);
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double v = jsm[i];
+    int rank = 0;
+    for (int k = 0; k < n; ++k) {
+      const double w = jsm[k];
+      rank += (w > v) || (w == v && k < i);
+    }
+    sigma[sw.sig + rank] = v;
+    order[sw.sig + rank] = i;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+
+hipError_t launch_jacobi_init(const SectorWork* secs, const int* list, int count,
+                              const double2* theta, double2* acc, JacobiOut* st, int* perm,
+                              double* norm2, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_init, dim3(count), dim3(256), 0, s, secs, list, theta, acc, st, perm, norm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count, const JacobiOut* st,
+                              int* perm, const double* norm2, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_sort, dim3(count), dim3(256), 0, s, secs, list, st, perm, norm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiBlockWork* jb, int njb, int npairs,
+                              int step, double2* theta, double2* acc, JacobiOut* st, const int* perm,
+                              double* norm2, double tol, int max_inner, hipStream_t s) {
+  if (npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_block_step, dim3(npairs), dim3(256), 0, s, secs, jb, njb, step, theta, acc,
+                     st, perm, norm2, tol, max_inner);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_sweep_end(const int* list, int count, JacobiOut* st, int* active, hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_sweep_end, dim3(1), dim3(1024), 0, s, list, count, st, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_polish(const SectorWork* secs, const int* list, int count, double2* theta,
+                                double2* acc, JacobiOut* st, double tol, int max_sweeps, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(jacobi_polish, dim3(count), dim3(256), 0, s, secs, list, theta, acc, st, tol, max_sweeps);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_finalize(const SectorWork* secs, const int* list, int count, int maxrows,
+                                  double2* theta, const double2* acc, double* sigma, int* order,
+                                  hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const size_t smem = (size_t)maxrows * sizeof(double);
+  hipLaunchKernelGGL(jacobi_finalize, dim3(count), dim3(256), smem, s, secs, list, theta, acc, sigma, order);
+  return hipGetLastError();
+}
+
+}  // namespace u1mps

@@ -1,0 +1,379 @@
+// Theta formation of the two-site update on sites (s, s+1) (Sec. II, the
+// two-site tensor of Eq. (E2) under a photon-number-conserving gate):
+//   theta_kernel        Theta~(cL, m, cR) = sum_cM G^(n)[(cL-m), (cL-cM)] B[s](cL,cM) B[s+1](cM,cR)
+//                       (charge-sector-matched products in complex128, the gate
+//                       mixed per n = cL - cR in the epilogue), plus
+//                       Theta = lambda_s * Theta~, the input of the SVD.
+//   split_planes_kernel, split_gemm_kernel, theta_mix_kernel
+//                       the same in the split-BF16 form: BF16 planes of the
+//                       site tensors, the charge-triple products on the matrix
+//                       cores (FP32 accumulation), the gate mix in FP64.
+#include "device_util.h"
+#include "kernels.h"
+
+namespace u1mps {
+
+// ---------------------------------------------------------------------------
+// Theta formation.  One workgroup (256 threads, 16 x 16) per 32 x 32 tile of
+// one (cL, cR) pair; each thread owns rows ty, ty+16 and columns tx, tx+16.
+template <int W>
+__global__ void __launch_bounds__(256)
+theta_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ tiles,
+             const SectorWork* __restrict__ secs, const double2* __restrict__ coef,
+             double2* __restrict__ th_raw, double2* __restrict__ th_scaled) {
+  __shared__ ThetaTile t;
+  __shared__ double2 as[kThetaTile][17];
+  __shared__ double2 bs[16][kThetaTile + 1];
+  if (threadIdx.x == 0) t = tiles[blockIdx.x];
+  __syncthreads();
+  const GateWork g = gates[t.gate];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+
+  double2 out[W][2][2];
+#pragma unroll
+  for (int i = 0; i < W; ++i)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) out[i][a][b] = make_double2(0.0, 0.0);
+
+  for (int j = 0; j < t.nin; ++j) {
+    double2 p[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) p[a][b] = make_double2(0.0, 0.0);
+    const int kb = t.k0[j], ke = t.k0[j] + t.kn[j];
+    for (int k0 = kb; k0 < ke; k0 += 16) {
+      // A tile: 32 rows x 16 k, two elements per thread
+      for (int e = threadIdx.x; e < kThetaTile * 16; e += 256) {
+        const int r = e >> 4, kk = e & 15;
+        const int k = k0 + kk;
+        double2 v = make_double2(0.0, 0.0);
+        if (r < t.nrow && k < ke) v = g.bl[(size_t)(t.row0 + r) * g.ldl + k];
+        as[r][kk] = v;
+      }
+      // B tile: 16 k x 32 columns
+      for (int e = threadIdx.x; e < 16 * kThetaTile; e += 256) {
+        const int kk = e >> 5, c = e & 31;
+        const int k = k0 + kk;
+        double2 v = make_double2(0.0, 0.0);
+        if (c < t.ncol && k < ke) v = g.br[(size_t)k * g.ldr + t.col0 + c];
+        bs[kk][c] = v;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < 16; ++kk) {
+        const double2 a0 = as[ty][kk], a1 = as[ty + 16][kk];
+        const double2 b0 = bs[kk][tx], b1 = bs[kk][tx + 16];
+        cfma(p[0][0], a0, b0);
+        cfma(p[0][1], a0, b1);
+        cfma(p[1][0], a1, b0);
+        cfma(p[1][1], a1, b1);
+      }
+      __syncthreads();
+    }
+    // gate mix: out_i += G^(n)[p_i][a_j] * P_j
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      if (i < t.nout) {
+        const double2 gc = coef[g.coef + (t.n * g.d + t.p[i]) * g.d + t.a[j]];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) cfma(out[i][a][b], gc, p[a][b]);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    if (i < t.nout) {
+      const SectorWork s = secs[t.sec[i]];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int r = ty + 16 * a;
+        if (r >= t.nrow) continue;
+        const double lam = g.lam_l[t.row0 + r];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int c = tx + 16 * b;
+          if (c >= t.ncol) continue;
+          const size_t rr = (size_t)(t.orow[i] + r), cc = (size_t)(t.ocol[i] + c);
+          const double2 v = out[i][a][b];
+          th_raw[(size_t)s.off + rr * s.c + cc] = v;
+          // the SVD input of a tall sector is stored transposed (its columns as rows)
+          const size_t si = s.tall ? (size_t)s.off + cc * s.r + rr : (size_t)s.off + rr * s.c + cc;
+          th_scaled[si] = make_double2(lam * v.x, lam * v.y);
+        }
+      }
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Precision form of Theta formation: the charge-triple products on the matrix
+// cores in split BF16, then the gate mix into the FP64 Theta workspaces.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi): |x - hi - lo| <= 2^-18 |x|
+// (after the float conversion of x, which adds 2^-24 |x|); BF16 bit patterns.
+__device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigned short& lo) {
+  const float xf = (float)x;
+  const __bf16 h = (__bf16)xf;
+  const __bf16 l = (__bf16)(xf - (float)h);
+  hi = __builtin_bit_cast(unsigned short, h);
+  lo = __builtin_bit_cast(unsigned short, l);
+}
+
+__device__ __forceinline__ void split_store(unsigned short* out, long long plane, long long idx, double2 v) {
+  unsigned short h, l;
+  split_bf16(v.x, h, l);
+  out[idx] = h;
+  out[plane + idx] = l;
+  split_bf16(v.y, h, l);
+  out[2 * plane + idx] = h;
+  out[3 * plane + idx] = l;
+}
+
+// The split pass: one 32 x 32 tile (rows x padded k) of one plan's planes per
+// workgroup.  Rows are read along the frame's contiguous axis: directly for
+// A planes, through an LDS transpose for the B planes.
+__global__ void __launch_bounds__(256)
+split_planes_kernel(const SplitPlanes* __restrict__ plans, int nplan, const int* __restrict__ ktab,
+                    unsigned short* __restrict__ planes) {
+  __shared__ double2 tile[kSpTile][kSpTile + 1];
+  int lo = 0, hi = nplan - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (plans[mid].tile_begin <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const SplitPlanes w = plans[lo];
+  const int local = blockIdx.x - w.tile_begin;
+  const int r0 = (local / w.tiles_k) * kSpTile, kk0 = (local % w.tiles_k) * kSpTile;
+  const int* kinv = ktab + w.kinv;
+  unsigned short* out = planes + w.out;
+  const long long plane = (long long)w.rows * w.ldk;
+  const int t = threadIdx.x;
+  if (!w.trans) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = r0 + (t >> 5) + 8 * q, kk = kk0 + (t & 31);
+      if (i < w.rows && kk < w.ldk) {
+        const int k = kinv[kk];
+        const double2 v = k >= 0 ? w.src[(size_t)i * w.ld + k] : make_double2(0.0, 0.0);
+        split_store(out, plane, (long long)i * w.ldk + kk, v);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kl = (t >> 5) + 8 * q, jl = t & 31;
+      const int kk = kk0 + kl, j = r0 + jl;
+      double2 v = make_double2(0.0, 0.0);
+      if (kk < w.ldk && j < w.rows) {
+        const int k = kinv[kk];
+        if (k >= 0) v = w.src[(size_t)k * w.ld + j];
+      }
+      tile[kl][jl] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int jl = (t >> 5) + 8 * q, kl = t & 31;
+      const int j = r0 + jl, kk = kk0 + kl;
+      if (j < w.rows && kk < w.ldk) split_store(out, plane, (long long)j * w.ldk + kk, tile[kl][jl]);
+    }
+  }
+}
+
+// LDS rows of one k chunk: 32 BF16 plus 8 of padding (80 bytes), so every
+// 8-element operand read is one aligned 16-byte access.
+constexpr int kSgRow = kSgK + 8;
+
+// 16-byte groups (8 k) of a 64-row x 32-k chunk of one operand's 4 planes:
+// 1024 groups, 4 per thread (group g = t + 256 q: plane g / 256, row
+// (g % 256) / 4, k 8 (g % 4)); rows past `rows` and groups starting past `k`
+// read as 0 (the planes are zero between charge blocks, so a group that
+// starts inside the range is exact).
+__device__ __forceinline__ void sg_fetch(uint4 (&r)[4], const unsigned short* __restrict__ base, long long pstride,
+                                         int ld, int rows, int k, int row0, int k0) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int g = threadIdx.x + 256 * q;
+    const int plane = g >> 8, row = (g & 255) >> 2, kg = 8 * (g & 3);
+    r[q] = make_uint4(0u, 0u, 0u, 0u);
+    if (row0 + row < rows && k0 + kg < k)
+      r[q] = *reinterpret_cast<const uint4*>(base + plane * pstride + (size_t)(row0 + row) * ld + k0 + kg);
+  }
+}
+
+__device__ __forceinline__ void sg_stage(const uint4 (&r)[4], unsigned short (*buf)[kSgTile][kSgRow]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int g = threadIdx.x + 256 * q;
+    *reinterpret_cast<uint4*>(&buf[g >> 8][(g & 255) >> 2][8 * (g & 3)]) = r[q];
+  }
+}
+
+__device__ __forceinline__ bf16x8 sg_op(const unsigned short (*buf)[kSgTile][kSgRow], int plane, int row, int k) {
+  return *reinterpret_cast<const bf16x8*>(&buf[plane][row][k]);
+}
+
+// One 64 x 64 output tile per workgroup; wave w computes the 32 x 32 quadrant
+// (rows 32 (w / 2), columns 32 (w % 2)) with v_mfma_f32_32x32x16_bf16.  Lane l
+// supplies A[i = l % 32][k = 8 (l / 32) + e] and B[k = 8 (l / 32) + e][j = l % 32]
+// (e = 0..7); its accumulator register r holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
+// Per k step: Re = Ar Br - Ai Bi and Im = Ar Bi + Ai Br, each real product as
+// hi*hi + hi*lo + lo*hi (the lo*lo term is below the split's error).  The k
+// chunks go through two LDS buffers: the next chunk's loads are in flight
+// during the products and are staged into the other buffer, one barrier per
+// chunk.
+__global__ void __launch_bounds__(256)
+split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
+  __shared__ __align__(16) unsigned short sa[2][4][kSgTile][kSgRow];
+  __shared__ __align__(16) unsigned short sb[2][4][kSgTile][kSgRow];
+  int lo = 0, hi = nprob - 1;
+  const int tile = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (probs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+  }
+  const SplitGemm w = probs[lo];
+  const int local = tile - w.tile_begin;
+  const int row0 = (local / w.tiles_n) * kSgTile, col0 = (local % w.tiles_n) * kSgTile;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int R = 32 * (wave >> 1), Cq = 32 * (wave & 1);
+  const int li = lane & 31, lk = 8 * (lane >> 5);
+  f32x16 crp = {}, crn = {}, cim = {};
+  uint4 ra[4], rb[4];
+  sg_fetch(ra, w.a, w.pa, w.lda, w.m, w.k, row0, 0);
+  sg_fetch(rb, w.b, w.pb, w.ldb, w.n, w.k, col0, 0);
+  sg_stage(ra, sa[0]);
+  sg_stage(rb, sb[0]);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < w.k; k0 += kSgK) {
+    const bool more = k0 + kSgK < w.k;
+    if (more) {
+      sg_fetch(ra, w.a, w.pa, w.lda, w.m, w.k, row0, k0 + kSgK);
+      sg_fetch(rb, w.b, w.pb, w.ldb, w.n, w.k, col0, k0 + kSgK);
+    }
+#pragma unroll
+    for (int ks = 0; ks < kSgK; ks += 16) {
+      const bf16x8 arh = sg_op(sa[buf], 0, R + li, ks + lk), arl = sg_op(sa[buf], 1, R + li, ks + lk);
+      const bf16x8 aih = sg_op(sa[buf], 2, R + li, ks + lk), ail = sg_op(sa[buf], 3, R + li, ks + lk);
+      const bf16x8 brh = sg_op(sb[buf], 0, Cq + li, ks + lk), brl = sg_op(sb[buf], 1, Cq + li, ks + lk);
+      const bf16x8 bih = sg_op(sb[buf], 2, Cq + li, ks + lk), bil = sg_op(sb[buf], 3, Cq + li, ks + lk);
+      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brh, crp, 0, 0, 0);
+      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, bih, crn, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bih, cim, 0, 0, 0);
+      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brl, crp, 0, 0, 0);
+      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, bil, crn, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bil, cim, 0, 0, 0);
+      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, brh, crp, 0, 0, 0);
+      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, bih, crn, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bih, cim, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brh, cim, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brl, cim, 0, 0, 0);
+      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, brh, cim, 0, 0, 0);
+    }
+    if (more) {
+      // the other buffer was last read before the previous barrier
+      sg_stage(ra, sa[buf ^ 1]);
+      sg_stage(rb, sb[buf ^ 1]);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  const int j = col0 + Cq + li;
+  if (j < w.n) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = row0 + R + 8 * (r >> 2) + (lane >> 5) * 4 + (r & 3);
+      if (i < w.m) w.c[(size_t)i * w.ldc + j] = make_float2(crp[r] - crn[r], cim[r]);
+    }
+  }
+}
+
+// Gate mix of the precision form: for the 32 x 32 tile of one charge pair,
+// Theta~(cL, m, cR) = sum_j G^(n)[cL - m][a_j] P_j with the products P_j from
+// the scratch (complex64, upcast), written like the plain kernel's epilogue.
+__global__ void __launch_bounds__(256)
+theta_mix_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ tiles,
+                 const SectorWork* __restrict__ secs, const double2* __restrict__ coef,
+                 const float2* __restrict__ pbuf, double2* __restrict__ th_raw,
+                 double2* __restrict__ th_scaled) {
+  const ThetaTile& t = tiles[blockIdx.x];
+  const GateWork g = gates[t.gate];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int nin = t.nin, nout = t.nout;
+  for (int a = 0; a < 2; ++a) {
+    const int r = ty + 16 * a;
+    if (r >= t.nrow) continue;
+    const double lam = g.lam_l[t.row0 + r];
+    for (int b = 0; b < 2; ++b) {
+      const int c = tx + 16 * b;
+      if (c >= t.ncol) continue;
+      double2 pv[kMaxD];
+#pragma unroll
+      for (int j = 0; j < kMaxD; ++j) {
+        pv[j] = make_double2(0.0, 0.0);
+        if (j < nin) {
+          const float2 f = pbuf[t.poff[j] + (size_t)(t.pr0 + r) * t.ldp + t.pc0 + c];
+          pv[j] = make_double2(f.x, f.y);
+        }
+      }
+      for (int i = 0; i < nout; ++i) {
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < kMaxD; ++j)
+          if (j < nin) cfma(v, coef[g.coef + (t.n * g.d + t.p[i]) * g.d + t.a[j]], pv[j]);
+        const SectorWork s = secs[t.sec[i]];
+        const size_t rr = (size_t)(t.orow[i] + r), cc = (size_t)(t.ocol[i] + c);
+        th_raw[(size_t)s.off + rr * s.c + cc] = v;
+        const size_t si = s.tall ? (size_t)s.off + cc * s.r + rr : (size_t)s.off + rr * s.c + cc;
+        th_scaled[si] = make_double2(lam * v.x, lam * v.y);
+      }
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Host launchers.
+
+hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntiles,
+                        const SectorWork* secs, const double2* coef, double2* raw,
+                        double2* scaled, int maxw, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (maxw <= 4)
+    hipLaunchKernelGGL(theta_kernel<4>, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, raw, scaled);
+  else
+    hipLaunchKernelGGL(theta_kernel<kMaxD>, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, raw, scaled);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_planes(const SplitPlanes* plans, int nplan, int ntiles, const int* ktab,
+                               unsigned short* planes, hipStream_t st) {
+  if (nplan <= 0 || ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(split_planes_kernel, dim3(ntiles), dim3(256), 0, st, plans, nplan, ktab, planes);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, hipStream_t st) {
+  if (nprob <= 0 || ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(split_gemm_kernel, dim3(ntiles), dim3(256), 0, st, probs, nprob);
+  return hipGetLastError();
+}
+
+hipError_t launch_theta_mix(const GateWork* gates, const ThetaTile* tiles, int ntiles, const SectorWork* secs,
+                            const double2* coef, const float2* pbuf, double2* raw, double2* scaled, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(theta_mix_kernel, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, pbuf, raw, scaled);
+  return hipGetLastError();
+}
+
+}  // namespace u1mps
