@@ -82,7 +82,7 @@ typedef struct {
  *   zero_tol   singular values <= zero_tol * s_max are dropped as numerical
  *              zeros (default 1e-13).
  *   max_sweeps Jacobi sweep limit per sector (default 40): blocked sweeps
- *              first (at most 24), then scalar sweeps on the vectors of any
+ *              first (at most 32), then scalar sweeps on the vectors of any
  *              sector still rotating.
  *   jacobi_tol rotate a vector pair while |<x,y>| > tol * |x| |y|; <= 0
  *              means max(vector length, 64) * 2^-52.  The SVD of an r x c

@@ -312,54 +312,54 @@ __device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 1], double tol
 // Rotations of the Gram matrix gs (in LDS) until no pair exceeds the
 // threshold; W accumulates the product.  The caller has established that
 // some pair is above it.  A round-robin step rotates 16 disjoint pairs at
-// once, G <- U G U^H and W <- U W with U block diagonal over the pairs: 16
-// threads compute the pairs' rotations into rot[], then thread t = 16 A + B
-// updates the 2 x 2 blocks (rows of pair A) x (columns of pair B) of G and W
-// in place (each block is read and written by its owner only).  After each
-// sweep one parallel test over all pairs replaces the sweep that would find
-// nothing to rotate (it would leave G and W unchanged).
-__device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*ws)[kJP + 1], double4* rot,
+// once, G <- U G U^H and W <- U W with U block diagonal over the pairs.
+// Thread t = 16 A + B owns the 2 x 2 blocks (rows of pair A) x (columns of
+// pair B): it computes the rotations of pairs A and B itself from the
+// current G, writes its rotated G block into the other buffer (g1, the
+// staging tile, idle during the eig) and updates its W block in place, so a
+// step needs one barrier and no exchange of rotations.  After each sweep one
+// parallel test over all pairs replaces the sweep that would find nothing to
+// rotate (it would leave G and W unchanged).  The final G is left in gs.
+__device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*g1)[kJP + 1], double2 (*ws)[kJP + 1],
                              double tol, double floor_g, int max_inner, int4* anyf, int& parity) {
   const int tid = threadIdx.x;
   const int A = tid >> 4, B = tid & 15;
+  double2 (*cur)[kJP + 1] = gs;
+  double2 (*nxt)[kJP + 1] = g1;
   for (int inner = 0; inner < max_inner; ++inner) {
     for (int s2 = 0; s2 < kJP - 1; ++s2) {
-      // G and W change only in update phases, each closed by a barrier, so
-      // this thread's block is read before the rotations are published
       int pa, qa, pb, qb;
       jac_pair_fast(s2, A, pa, qa);
       jac_pair_fast(s2, B, pb, qb);
-      double2 g00 = gs[pa][pb], g01 = gs[pa][qb], g10 = gs[qa][pb], g11 = gs[qa][qb];
-      double2 w00 = ws[pa][pb], w01 = ws[pa][qb], w10 = ws[qa][pb], w11 = ws[qa][qb];
-      int flag = 0;
-      if (tid < kJP / 2) {
-        int p, q;
-        jac_pair_fast(s2, tid, p, q);
-        double c = 1.0, wr = 0.0, wi = 0.0;
-        const double2 g = gs[p][q];
-        flag = jac_rotation(gs[p][p].x, gs[q][q].x, g.x, g.y, tol, floor_g, c, wr, wi) ? 1 : 0;
-        rot[tid] = make_double4(c, wr, wi, flag ? 1.0 : 0.0);
+      double ca = 1.0, wra = 0.0, wia = 0.0, cb = 1.0, wrb = 0.0, wib = 0.0;
+      const double2 ga = cur[pa][qa], gb = cur[pb][qb];
+      const bool fa = jac_rotation(cur[pa][pa].x, cur[qa][qa].x, ga.x, ga.y, tol, floor_g, ca, wra, wia);
+      const bool fb = jac_rotation(cur[pb][pb].x, cur[qb][qb].x, gb.x, gb.y, tol, floor_g, cb, wrb, wib);
+      double2 g00 = cur[pa][pb], g01 = cur[pa][qb], g10 = cur[qa][pb], g11 = cur[qa][qb];
+      if (fa) {                   // rows pa, qa: U from the left, also on W
+        double2 w00 = ws[pa][pb], w01 = ws[pa][qb], w10 = ws[qa][pb], w11 = ws[qa][qb];
+        rot_pair(g00, g10, ca, wra, wia);
+        rot_pair(g01, g11, ca, wra, wia);
+        rot_pair(w00, w10, ca, wra, wia);
+        rot_pair(w01, w11, ca, wra, wia);
+        ws[pa][pb] = w00; ws[pa][qb] = w01; ws[qa][pb] = w10; ws[qa][qb] = w11;
       }
-      if (!block_any(flag, anyf, parity)) continue;
-      const double4 ra = rot[A], rb = rot[B];
-      if (ra.w != 0.0 || rb.w != 0.0) {
-        if (ra.w != 0.0) {        // rows pa, qa: U from the left, also on W
-          rot_pair(g00, g10, ra.x, ra.y, ra.z);
-          rot_pair(g01, g11, ra.x, ra.y, ra.z);
-          rot_pair(w00, w10, ra.x, ra.y, ra.z);
-          rot_pair(w01, w11, ra.x, ra.y, ra.z);
-          ws[pa][pb] = w00; ws[pa][qb] = w01; ws[qa][pb] = w10; ws[qa][qb] = w11;
-        }
-        if (rb.w != 0.0) {        // columns pb, qb: U^H from the right
-          rot_pair(g00, g01, rb.x, rb.y, -rb.z);
-          rot_pair(g10, g11, rb.x, rb.y, -rb.z);
-        }
-        gs[pa][pb] = g00; gs[pa][qb] = g01; gs[qa][pb] = g10; gs[qa][qb] = g11;
+      if (fb) {                   // columns pb, qb: U^H from the right
+        rot_pair(g00, g01, cb, wrb, -wib);
+        rot_pair(g10, g11, cb, wrb, -wib);
       }
+      nxt[pa][pb] = g00; nxt[pa][qb] = g01; nxt[qa][pb] = g10; nxt[qa][qb] = g11;
+      // every read of cur in this step precedes the barrier, so the next step may overwrite it
       __syncthreads();
+      double2 (*t)[kJP + 1] = cur;
+      cur = nxt;
+      nxt = t;
     }
-    if (!jac_any_above(gs, tol, floor_g, anyf, parity)) break;
+    if (!jac_any_above(cur, tol, floor_g, anyf, parity)) break;
   }
+  // a sweep has an odd number of steps: an odd sweep count leaves G in g1
+  if (cur != gs)
+    for (int e = tid; e < kJP * kJP; e += blockDim.x) gs[e / kJP][e % kJP] = cur[e / kJP][e % kJP];
   __syncthreads();
 }
 
@@ -382,12 +382,12 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
                   int njb, int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
                   JacobiOut* __restrict__ st, const int* __restrict__ perm, double* __restrict__ norm2,
                   double tol_opt, int max_inner) {
+  // xs stages column chunks of the vectors; during the eig it is the second G buffer
   __shared__ double2 xs[kJP][33];
   __shared__ double2 gs[kJP][kJP + 1];
   __shared__ double2 ws[kJP][kJP + 1];
   __shared__ double gmax;
   __shared__ int vrow[kJP];
-  __shared__ double4 rot[kJP / 2];
   __shared__ int4 anyf[2];
   int parity = 0;
   int lo = 0, hi = njb - 1;
@@ -454,7 +454,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
       fresh = true;
       continue;
     }
-    jac_gram_eig(gs, ws, rot, ptol, pfloor, max_inner, anyf, parity);
+    jac_gram_eig(gs, xs, ws, ptol, pfloor, max_inner, anyf, parity);
     // ---- rotate the vectors (and the accumulator of a tall sector)
     jac_apply(xs, ws, x, len, vrow);
     if (tall) jac_apply(xs, ws, accbuf + sw.acc, n, vrow);

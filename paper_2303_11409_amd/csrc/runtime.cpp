@@ -92,7 +92,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // Rotation sweeps over a block pair's Gram matrix before the block is rotated.
 constexpr int kMaxInnerSweeps = 12;
 // Blocked sweeps before an unconverged sector is finished by scalar sweeps.
-constexpr int kBlockedSweeps = 24;
+constexpr int kBlockedSweeps = 32;
 
 }  // namespace
 
