@@ -533,8 +533,16 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
     P.gates[g] = gw;
     P.gp[g] = {s, gw.sec_begin, gw.sec_end};
   }
-  // blocked Jacobi schedule: min(r, c) vectors in blocks of kJB, block count even
-  for (size_t i = 0; i < P.secs.size(); ++i) {
+  // blocked Jacobi schedule: min(r, c) vectors in blocks of kJB, block count
+  // even.  Block pairs are numbered heaviest sector first (longest vectors):
+  // the dispatcher places workgroups in index order across the CUs, so the
+  // slow pairs get a CU of their own and the light ones share.
+  std::vector<int> jorder(P.secs.size());
+  for (size_t i = 0; i < jorder.size(); ++i) jorder[i] = (int)i;
+  std::stable_sort(jorder.begin(), jorder.end(), [&](int x, int y) {
+    return std::max(P.secs[x].r, P.secs[x].c) > std::max(P.secs[y].r, P.secs[y].c);
+  });
+  for (int i : jorder) {
     const SectorWork& sw = P.secs[i];
     const int nv = std::min(sw.r, sw.c);
     int nb = (nv + kJB - 1) / kJB;

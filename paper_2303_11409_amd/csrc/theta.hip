@@ -128,19 +128,27 @@ __device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigne
   lo = __builtin_bit_cast(unsigned short, l);
 }
 
-__device__ __forceinline__ void split_store(unsigned short* out, long long plane, long long idx, double2 v) {
-  unsigned short h, l;
-  split_bf16(v.x, h, l);
-  out[idx] = h;
-  out[plane + idx] = l;
-  split_bf16(v.y, h, l);
-  out[2 * plane + idx] = h;
-  out[3 * plane + idx] = l;
+// Four consecutive padded-k entries of one row into the four planes, one
+// 8-byte store per plane (idx is a multiple of 4).
+__device__ __forceinline__ void split_store4(unsigned short* out, long long plane, long long idx,
+                                             const double2 (&v)[4]) {
+  ushort4 rh, rl, ih, il;
+  split_bf16(v[0].x, rh.x, rl.x); split_bf16(v[0].y, ih.x, il.x);
+  split_bf16(v[1].x, rh.y, rl.y); split_bf16(v[1].y, ih.y, il.y);
+  split_bf16(v[2].x, rh.z, rl.z); split_bf16(v[2].y, ih.z, il.z);
+  split_bf16(v[3].x, rh.w, rl.w); split_bf16(v[3].y, ih.w, il.w);
+  *reinterpret_cast<ushort4*>(out + idx) = rh;
+  *reinterpret_cast<ushort4*>(out + plane + idx) = rl;
+  *reinterpret_cast<ushort4*>(out + 2 * plane + idx) = ih;
+  *reinterpret_cast<ushort4*>(out + 3 * plane + idx) = il;
 }
 
 // The split pass: one 32 x 32 tile (rows x padded k) of one plan's planes per
-// workgroup.  Rows are read along the frame's contiguous axis: directly for
-// A planes, through an LDS transpose for the B planes.
+// workgroup; thread t covers row t / 8 and the four padded k entries
+// 4 (t % 8) .. 4 (t % 8) + 3 (ldk is a multiple of 8, so such a group is
+// either inside the row or past its end).  Rows are read along the frame's
+// contiguous axis: directly for A planes, through an LDS transpose for the B
+// planes.
 __global__ void __launch_bounds__(256)
 split_planes_kernel(const SplitPlanes* __restrict__ plans, int nplan, const int* __restrict__ ktab,
                     unsigned short* __restrict__ planes) {
@@ -157,34 +165,34 @@ split_planes_kernel(const SplitPlanes* __restrict__ plans, int nplan, const int*
   unsigned short* out = planes + w.out;
   const long long plane = (long long)w.rows * w.ldk;
   const int t = threadIdx.x;
+  const int row = r0 + (t >> 3), kl = 4 * (t & 7), kk = kk0 + kl;
+  double2 v[4];
   if (!w.trans) {
+    if (row < w.rows && kk < w.ldk) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = r0 + (t >> 5) + 8 * q, kk = kk0 + (t & 31);
-      if (i < w.rows && kk < w.ldk) {
-        const int k = kinv[kk];
-        const double2 v = k >= 0 ? w.src[(size_t)i * w.ld + k] : make_double2(0.0, 0.0);
-        split_store(out, plane, (long long)i * w.ldk + kk, v);
+      for (int e = 0; e < 4; ++e) {
+        const int k = kinv[kk + e];
+        v[e] = k >= 0 ? w.src[(size_t)row * w.ld + k] : make_double2(0.0, 0.0);
       }
+      split_store4(out, plane, (long long)row * w.ldk + kk, v);
     }
   } else {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int kl = (t >> 5) + 8 * q, jl = t & 31;
-      const int kk = kk0 + kl, j = r0 + jl;
-      double2 v = make_double2(0.0, 0.0);
-      if (kk < w.ldk && j < w.rows) {
-        const int k = kinv[kk];
-        if (k >= 0) v = w.src[(size_t)k * w.ld + j];
+      const int tl = (t >> 5) + 8 * q, jl = t & 31;    // tile row = padded k, column = output row
+      const int kq = kk0 + tl, j = r0 + jl;
+      double2 x = make_double2(0.0, 0.0);
+      if (kq < w.ldk && j < w.rows) {
+        const int k = kinv[kq];
+        if (k >= 0) x = w.src[(size_t)k * w.ld + j];
       }
-      tile[kl][jl] = v;
+      tile[tl][jl] = x;
     }
     __syncthreads();
+    if (row < w.rows && kk < w.ldk) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int jl = (t >> 5) + 8 * q, kl = t & 31;
-      const int j = r0 + jl, kk = kk0 + kl;
-      if (j < w.rows && kk < w.ldk) split_store(out, plane, (long long)j * w.ldk + kk, tile[kl][jl]);
+      for (int e = 0; e < 4; ++e) v[e] = tile[kl + e][t >> 3];
+      split_store4(out, plane, (long long)row * w.ldk + kk, v);
     }
   }
 }
@@ -227,7 +235,8 @@ __device__ __forceinline__ bf16x8 sg_op(const unsigned short (*buf)[kSgTile][kSg
 // supplies A[i = l % 32][k = 8 (l / 32) + e] and B[k = 8 (l / 32) + e][j = l % 32]
 // (e = 0..7); its accumulator register r holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
 // Per k step: Re = Ar Br - Ai Bi and Im = Ar Bi + Ai Br, each real product as
-// hi*hi + hi*lo + lo*hi (the lo*lo term is below the split's error).  The k
+// hi*hi + hi*lo + lo*hi (the lo*lo term is below the split's error), in four
+// accumulators so that no two consecutive products depend.  The k
 // chunks go through two LDS buffers: the next chunk's loads are in flight
 // during the products and are staged into the other buffer, one barrier per
 // chunk.
@@ -247,7 +256,8 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R = 32 * (wave >> 1), Cq = 32 * (wave & 1);
   const int li = lane & 31, lk = 8 * (lane >> 5);
-  f32x16 crp = {}, crn = {}, cim = {};
+  // four independent accumulator chains: Re+ (Ar Br), Re- (Ai Bi), Im (Ar Bi), Im (Ai Br)
+  f32x16 crp = {}, crn = {}, cia = {}, cib = {};
   uint4 ra[4], rb[4];
   sg_fetch(ra, w.a, w.pa, w.lda, w.m, w.k, row0, 0);
   sg_fetch(rb, w.b, w.pb, w.ldb, w.n, w.k, col0, 0);
@@ -261,24 +271,30 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
       sg_fetch(ra, w.a, w.pa, w.lda, w.m, w.k, row0, k0 + kSgK);
       sg_fetch(rb, w.b, w.pb, w.ldb, w.n, w.k, col0, k0 + kSgK);
     }
+    // both k steps' operands first, then the 24 products round-robin over the chains
+    bf16x8 a[2][4], b[2][4];
 #pragma unroll
-    for (int ks = 0; ks < kSgK; ks += 16) {
-      const bf16x8 arh = sg_op(sa[buf], 0, R + li, ks + lk), arl = sg_op(sa[buf], 1, R + li, ks + lk);
-      const bf16x8 aih = sg_op(sa[buf], 2, R + li, ks + lk), ail = sg_op(sa[buf], 3, R + li, ks + lk);
-      const bf16x8 brh = sg_op(sb[buf], 0, Cq + li, ks + lk), brl = sg_op(sb[buf], 1, Cq + li, ks + lk);
-      const bf16x8 bih = sg_op(sb[buf], 2, Cq + li, ks + lk), bil = sg_op(sb[buf], 3, Cq + li, ks + lk);
-      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brh, crp, 0, 0, 0);
-      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, bih, crn, 0, 0, 0);
-      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bih, cim, 0, 0, 0);
-      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, brl, crp, 0, 0, 0);
-      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, bil, crn, 0, 0, 0);
-      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arh, bil, cim, 0, 0, 0);
-      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, brh, crp, 0, 0, 0);
-      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, bih, crn, 0, 0, 0);
-      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bih, cim, 0, 0, 0);
-      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brh, cim, 0, 0, 0);
-      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aih, brl, cim, 0, 0, 0);
-      cim = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, brh, cim, 0, 0, 0);
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        a[h][p] = sg_op(sa[buf], p, R + li, 16 * h + lk);
+        b[h][p] = sg_op(sb[buf], p, Cq + li, 16 * h + lk);
+      }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo
+      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][0], b[h][0], crp, 0, 0, 0);
+      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][2], b[h][2], crn, 0, 0, 0);
+      cia = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][0], b[h][2], cia, 0, 0, 0);
+      cib = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][2], b[h][0], cib, 0, 0, 0);
+      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][0], b[h][1], crp, 0, 0, 0);
+      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][2], b[h][3], crn, 0, 0, 0);
+      cia = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][0], b[h][3], cia, 0, 0, 0);
+      cib = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][2], b[h][1], cib, 0, 0, 0);
+      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][1], b[h][0], crp, 0, 0, 0);
+      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][3], b[h][2], crn, 0, 0, 0);
+      cia = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][1], b[h][2], cia, 0, 0, 0);
+      cib = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][3], b[h][0], cib, 0, 0, 0);
     }
     if (more) {
       // the other buffer was last read before the previous barrier
@@ -293,7 +309,7 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = row0 + R + 8 * (r >> 2) + (lane >> 5) * 4 + (r & 3);
-      if (i < w.m) w.c[(size_t)i * w.ldc + j] = make_float2(crp[r] - crn[r], cim[r]);
+      if (i < w.m) w.c[(size_t)i * w.ldc + j] = make_float2(crp[r] - crn[r], cia[r] + cib[r]);
     }
   }
 }
