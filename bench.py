@@ -154,7 +154,12 @@ def run_serving(args, rate, dev, circuits):
     n = int(rate * args.serve_seconds * 1.2) + 8
     specs = circuits.serving_mix_specs(n, seed=5)
     reqs = serving.poisson_requests(specs, rate=rate, seed=5, build=circuits.config_from_spec, n_patterns=16)
-    srv = serving.Server(int(args.serve_budget_gib * 2**30), max_active=args.serve_max_active, device=dev)
+    import torch
+    from paper_2303_11409_amd import TorchDevice
+    # two lanes: the large circuits (chi_max >= 1024) on one stream, the rest on another
+    devs = [TorchDevice(stream=torch.cuda.Stream()) for _ in range(2)]
+    srv = serving.Server(int(args.serve_budget_gib * 2**30), max_active=args.serve_max_active, devices=devs,
+                         lane_of=lambda sp: 0 if sp["chi_max"] >= 1024 else 1)
     rep = srv.run(reqs, until=args.serve_seconds)
     lat = rep.latencies()
     arrived = sum(1 for r in reqs if r.arrival < rep.seconds)
@@ -375,8 +380,9 @@ def main() -> int:
         forms["serving"]["workload"] = (
             "Poisson arrivals of the serving mix (95% batching-mix circuits, 5% L=64, 32 photons, "
             "chi_max=1024, depth 64; request j seed 5000+j, 16 sampled amplitudes each), admitted by "
-            f"an HBM budget of {args.serve_budget_gib:g} GiB and at most {args.serve_max_active} active, "
-            "one batch call per layer of all active requests; window without drain")
+            f"an HBM budget of {args.serve_budget_gib:g} GiB and at most {args.serve_max_active} active per "
+            "lane, two lanes (chi_max=1024 requests, the rest) each on its own stream and host thread, one "
+            "batch call per layer of all active requests of a lane; window without drain")
         log(f"  {forms['serving']['gate_applies_per_s']:.1f} gate applies/s, "
             f"{forms['serving']['completed']} completed")
         if args.serve_low_rate > 0:

@@ -6,6 +6,10 @@ resident on the device between layers.  Each iteration of the loop advances
 every active request by one brickwork layer, all of them together in one
 ``mps_apply_batch`` call (the batching form), so requests that arrive while
 others run join the next iteration and their work shares the same launches.
+Requests may be split into lanes (for instance large circuits apart from small
+ones): each lane runs this loop in its own host thread on its own stream, so
+an iteration of one lane does not wait for the slowest sector of another and
+the lanes' kernels fill the device together.
 A request whose last layer is done is retired: its result (norm, summed
 discarded weight, sampled amplitudes) is read out, its device memory returns to
 the budget and its latency (arrival to result) is recorded.
@@ -21,6 +25,7 @@ from __future__ import annotations
 
 import functools
 import math
+import threading
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional, Sequence
@@ -124,18 +129,26 @@ def finish(req: Request) -> dict:
 class Server:
     """Continuous-batching loop over a fixed list of requests with arrival times.
 
-    hbm_budget: bytes of device memory the admitted requests may hold together.
-    max_active: upper bound on simultaneously admitted requests.
+    hbm_budget: bytes of device memory the admitted requests may hold together
+    (shared by all lanes).
+    max_active: upper bound on simultaneously admitted requests per lane.
+    devices: one TorchDevice per lane (each with its own stream); None means one
+    lane on the default device.  Each lane is a host thread that runs the loop
+    on its own requests and stream, so the lanes' launches share the device.
+    lane_of: request spec -> lane index (default: lane 0).
     clock: returns seconds since the start (monotonic); tests may pass a
     simulated clock."""
 
     def __init__(self, hbm_budget: int, max_active: int = 1024, device=None,
-                 clock: Optional[Callable[[], float]] = None):
+                 clock: Optional[Callable[[], float]] = None, devices: Optional[Sequence] = None,
+                 lane_of: Optional[Callable[[dict], int]] = None):
         self.hbm_budget = int(hbm_budget)
         self.max_active = int(max_active)
-        self.device = device
+        self.devices = list(devices) if devices else [device]
+        self.lane_of = lane_of or (lambda spec: 0)
         self._t0 = None
         self._clock = clock
+        self._lock = threading.Lock()
 
     def now(self) -> float:
         if self._clock is not None:
@@ -143,38 +156,71 @@ class Server:
         return time.perf_counter() - self._t0
 
     def run(self, requests: Sequence[Request], until: Optional[float] = None) -> ServeReport:
-        """Serve the requests (sorted by arrival) until all are done or `until`
-        seconds have passed; returns the report."""
+        """Serve the requests until all are done or `until` seconds have passed;
+        returns the report."""
         self._t0 = time.perf_counter()
-        queue = sorted(requests, key=lambda r: r.arrival)
-        for r in queue:
+        nl = len(self.devices)
+        queues: List[List[Request]] = [[] for _ in range(nl)]
+        for r in sorted(requests, key=lambda r: r.arrival):
             sp = r.spec
             r.bytes = state_bytes(sp["L"], sp["n_photons"], sp["d"], sp["chi_max"])
             if r.bytes > self.hbm_budget:
                 raise ValueError(f"request {r.rid} needs {r.bytes} bytes, more than the budget")
+            lane = int(self.lane_of(sp))
+            if not 0 <= lane < nl:
+                raise ValueError(f"lane {lane} of request {r.rid} outside 0..{nl - 1}")
+            queues[lane].append(r)
+        self._used = 0
+        self._active_total = 0
         rep = ServeReport()
+        errors: List[BaseException] = []
+        pending = [0] * nl
+
+        def lane_loop(k: int) -> None:
+            try:
+                pending[k] = self._lane(k, queues[k], rep, until)
+            except BaseException as e:          # re-raised by run()
+                errors.append(e)
+
+        if nl == 1:
+            lane_loop(0)
+        else:
+            threads = [threading.Thread(target=lane_loop, args=(k,), daemon=True) for k in range(nl)]
+            for t in threads:
+                t.start()
+            for t in threads:
+                t.join()
+        if errors:
+            raise errors[0]
+        rep.pending = sum(pending)
+        rep.seconds = self.now()
+        return rep
+
+    def _lane(self, k: int, queue: List[Request], rep: ServeReport, until: Optional[float]) -> int:
         active: List[Request] = []
-        used = 0
         qi = 0
         try:
             while qi < len(queue) or active:
                 t = self.now()
                 if until is not None and t >= until:
                     break
-                # admit every arrived request that fits, in arrival order
-                while (qi < len(queue) and queue[qi].arrival <= t and len(active) < self.max_active
-                       and used + queue[qi].bytes <= self.hbm_budget):
+                # admit every arrived request of this lane that fits, in arrival order
+                while qi < len(queue) and queue[qi].arrival <= t and len(active) < self.max_active:
                     r = queue[qi]
+                    with self._lock:
+                        if self._used + r.bytes > self.hbm_budget:
+                            break
+                        self._used += r.bytes
+                        self._active_total += 1
+                        rep.peak_active = max(rep.peak_active, self._active_total)
+                        rep.peak_bytes = max(rep.peak_bytes, self._used)
                     r.materialize()
                     c = r.cfg
                     r.state = MPS(c["occupation"], c["d"], chi_max=c["chi_max"], cutoff=c["cutoff"],
-                                  device=self.device)
+                                  device=self.devices[k])
                     r.admitted_at = t
-                    used += r.bytes
                     active.append(r)
                     qi += 1
-                rep.peak_active = max(rep.peak_active, len(active))
-                rep.peak_bytes = max(rep.peak_bytes, used)
                 if not active:
                     # idle until the next arrival
                     if qi < len(queue):
@@ -182,15 +228,16 @@ class Server:
                         if wait > 0 and self._clock is None:
                             time.sleep(min(wait, 0.01))
                     continue
-                # one layer of every active request, together
+                # one layer of every active request of this lane, together
                 layers = []
+                ng = 0
                 for r in active:
                     lay = r.cfg["layers"][r.next_layer]
                     layers.append(([g.site for g in lay], [g.u for g in lay]))
-                    rep.gates += len(lay)
+                    ng += len(lay)
                 disc = apply_batch([r.state for r in active], layers)
-                rep.iterations += 1
                 still = []
+                done = []
                 for r, dsc in zip(active, disc):
                     r.discarded += float(np.sum(dsc))
                     r.next_layer += 1
@@ -199,19 +246,23 @@ class Server:
                         r.done_at = self.now()
                         r.state.close()
                         r.state = None
-                        used -= r.bytes
-                        rep.completed.append(r)
+                        done.append(r)
                     else:
                         still.append(r)
                 active = still
+                with self._lock:
+                    rep.gates += ng
+                    rep.iterations += 1
+                    for r in done:
+                        self._used -= r.bytes
+                        self._active_total -= 1
+                        rep.completed.append(r)
         finally:
             for r in active:
                 if r.state is not None:
                     r.state.close()
                     r.state = None
-        rep.pending = len(active) + sum(1 for r in queue[qi:] if until is None or r.arrival < until)
-        rep.seconds = self.now()
-        return rep
+        return len(active) + sum(1 for r in queue[qi:] if until is None or r.arrival < until)
 
 
 def poisson_requests(specs: Sequence[dict], rate: float, seed: int, build: Optional[Callable] = None,

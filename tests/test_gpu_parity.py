@@ -281,11 +281,15 @@ def test_batching_form_equals_each_state_alone(mps_cls):
         m.close()
 
 
-def test_serving_form_results_equal_each_request_alone(mps_cls):
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_serving_form_results_equal_each_request_alone(mps_cls, lanes):
     """Serving form: requests arriving at different times share batch calls with
-    whatever is running; each request's result (norm, discarded weight,
-    amplitudes, bond dimensions) is bitwise the same as the circuit run alone."""
-    from paper_2303_11409_amd import serving
+    whatever is running (with two lanes, the large requests run in their own
+    host thread on their own stream, concurrently with the rest); each request's
+    result (norm, discarded weight, amplitudes, bond dimensions) is bitwise the
+    same as the circuit run alone."""
+    import torch
+    from paper_2303_11409_amd import TorchDevice, serving
     cfgs = circuits.config_serving_mix(6, seed=21, l_range=(6, 12), chi_choices=(8, 16, 32),
                                        large_frac=0.2, large_L=14, large_chi=48)
     reqs = serving.poisson_requests(cfgs, rate=1.0, seed=2, n_patterns=16)
@@ -297,7 +301,12 @@ def test_serving_form_results_equal_each_request_alone(mps_cls):
         clock["t"] += 1.0
         return clock["t"]
 
-    rep = serving.Server(1 << 34, clock=tick).run(reqs)
+    if lanes == 1:
+        srv = serving.Server(1 << 34, clock=tick)
+    else:
+        devs = [TorchDevice(stream=torch.cuda.Stream()) for _ in range(2)]
+        srv = serving.Server(1 << 34, clock=tick, devices=devs, lane_of=lambda sp: 0 if sp["L"] >= 14 else 1)
+    rep = srv.run(reqs)
     assert len(rep.completed) == len(cfgs) and rep.iterations < sum(len(c["layers"]) for c in cfgs)
     for r in rep.completed:
         c = r.cfg

@@ -90,3 +90,35 @@ def test_scheduler_rejects_oversized_request(monkeypatch):
     reqs = serving.poisson_requests(cfgs, rate=1.0, seed=1)
     with pytest.raises(ValueError):
         serving.Server(1000).run(reqs)
+
+
+def test_scheduler_lanes(monkeypatch):
+    """Two lanes (threads): every request runs in its own lane, all complete, the
+    shared budget holds."""
+    lanes_seen = {}
+
+    class LaneState(FakeState):
+        def __init__(self, occ, d, chi_max=0, cutoff=0.0, device=None):
+            super().__init__(occ, d, chi_max, cutoff, device)
+            self.device = device
+
+    def fake_batch(states, layers):
+        devs = {id(s.device) for s in states}
+        assert len(devs) == 1                  # a batch never mixes lanes
+        for s in states:
+            lanes_seen[len(s.occ)] = s.device
+        return [np.zeros(len(s)) for s, _ in layers]
+
+    monkeypatch.setattr(serving, "MPS", LaneState)
+    monkeypatch.setattr(serving, "apply_batch", fake_batch)
+    cfgs = circuits.config_batch_mix(8, seed=3, l_range=(6, 12), chi_choices=(8, 16))
+    reqs = serving.poisson_requests(cfgs, rate=1e6, seed=1, n_patterns=4)
+    dev_small, dev_large = object(), object()
+    per = [serving.state_bytes(c["L"], sum(c["occupation"]), 4, c["chi_max"]) for c in cfgs]
+    srv = serving.Server(3 * max(per), devices=[dev_large, dev_small],
+                         lane_of=lambda sp: 0 if sp["L"] >= 10 else 1)
+    rep = srv.run(reqs)
+    assert len(rep.completed) == 8 and rep.pending == 0 and FakeState.live == 0
+    assert rep.peak_bytes <= 3 * max(per)
+    for L, dev in lanes_seen.items():
+        assert dev is (dev_large if L >= 10 else dev_small)
