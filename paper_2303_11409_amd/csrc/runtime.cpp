@@ -506,8 +506,9 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
             sg.tiles_n = (nR + kSgTile - 1) / kSgTile;
             sg.tile_begin = P.sg_tiles;
             P.sg_tiles += ((nL + kSgTile - 1) / kSgTile) * sg.tiles_n;
-            P.sg_mfma_flops += 24.0 * kSgTile * kSgTile * double(kSgK) *
-                               (((nL + kSgTile - 1) / kSgTile) * sg.tiles_n) * ((sg.k + kSgK - 1) / kSgK);
+            // executed: whole 64 x 64 tiles, k in steps of 16 (one MFMA k step)
+            P.sg_mfma_flops += 24.0 * kSgTile * kSgTile * 16.0 *
+                               (((nL + kSgTile - 1) / kSgTile) * sg.tiles_n) * ((sg.k + 15) / 16);
             P.sg.push_back(sg);
             P.p_elems += (long long)nL * nR;
           }

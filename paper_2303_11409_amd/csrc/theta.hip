@@ -280,8 +280,11 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
         a[h][p] = sg_op(sa[buf], p, R + li, 16 * h + lk);
         b[h][p] = sg_op(sb[buf], p, Cq + li, 16 * h + lk);
       }
+    // the second k step of a chunk that ends the segment early is all zero
+    const int nks = k0 + 16 < w.k ? 2 : 1;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
+      if (h >= nks) break;
       // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo
       crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][0], b[h][0], crp, 0, 0, 0);
       crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][2], b[h][2], crn, 0, 0, 0);

@@ -2,14 +2,15 @@
 
 Runs ONLY the CPU oracle (oracle/dense_mps.py) on the seeded workload from
 workloads/circuits.py and stores, as JSON text:
-  * the amplitudes of 1024 occupation patterns drawn uniformly (seed 102)
-    plus the input pattern,
+  * the amplitudes of 1024 occupation patterns drawn uniformly (seed 102 for
+    the 32-mode workload, 103 for the 64-mode one) plus the input pattern,
   * <psi|psi> by full contraction,
   * every bond's right-charge histogram from the oracle's charge audit,
   * every gate's discarded weight and cut margin,
   * the Schmidt values of the central bonds.
 
 Usage:  python tests/golden/make_golden.py L32_N16_d4_chi512
+        python tests/golden/make_golden.py L64_N32_d4_chi256
 """
 import json
 import os
@@ -25,12 +26,16 @@ from oracle import dense_mps  # noqa: E402
 from workloads import circuits  # noqa: E402
 
 WORKLOADS = {
-    "L32_N16_d4_chi512": lambda: circuits.config_plain_gpu(),
+    "L32_N16_d4_chi512": (lambda: circuits.config_plain_gpu(), 102),
+    # the precision-form circuit (64 modes, 32 photons in even modes, 64 layers)
+    # at a bond cap the oracle finishes in minutes
+    "L64_N32_d4_chi256": (lambda: circuits.config_precision(seed=3, chi_max=256), 103),
 }
 
 
 def main(name: str) -> None:
-    cfg = WORKLOADS[name]()
+    make, pattern_seed = WORKLOADS[name]
+    cfg = make()
     L, d = cfg["L"], cfg["d"]
     N = sum(cfg["occupation"])
     m = dense_mps.DenseMPS(cfg["occupation"], d, chi_max=cfg["chi_max"], cutoff=cfg["cutoff"])
@@ -40,7 +45,7 @@ def main(name: str) -> None:
             m.apply_gate(g.site, g.u)
         print(f"layer {li + 1}/{len(cfg['layers'])} chi {max(m.bond_dims())} "
               f"{time.time() - t0:.0f} s", flush=True)
-    pats = circuits.sample_patterns(L, N, d, 1024, 102)
+    pats = circuits.sample_patterns(L, N, d, 1024, pattern_seed)
     pats = np.vstack([pats, np.array(cfg["occupation"], dtype=np.int32)[None, :]])
     amp = m.amplitudes(pats)
     out = {
