@@ -39,8 +39,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/cl
 # KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99982 and writes
 # by 1).  Valid only for the Jacobi source (csrc/jacobi.hip) it was taken on.
 MEASURED_TRAFFIC = {
-    "kernels_sha256": "60d88e3d9488717c40043df2fa82c35d2c6663215377ac3e2eadd45ff5a2ea67",
-    "fetch_kib": 20999.992, "write_kib": 35415.614,
+    "kernels_sha256": "6556c859adf6bae95a0cc91634163fbeb8075a8315b937f87f7f057b8b25713d",
+    "fetch_kib": 21692.328, "write_kib": 35722.905,
     "fetch_scale": 262144.0 / 131085.208, "write_scale": 1.0,
 }
 
