@@ -177,29 +177,30 @@ __device__ __forceinline__ void jac_chunk_loop(double2 (*xs)[33], const double2*
 
 // X_IJ <- W X_IJ for one row-major matrix (rows of length len), in column
 // chunks of 32, on the matrix cores: wave w computes the 16 x 16 output
-// quadrant (rows 16 (w / 2), columns 16 (w % 2)) of each chunk as four real
-// products per k-step, Or = Wr Xr - Wi Xi and Oi = Wr Xi + Wi Xr.
+// quadrant (rows 16 (w / 2), columns 16 (w % 2)) of each chunk as three real
+// products per k-step (below).
 __device__ void jac_apply(double2 (*xs)[33], double2 (*ws)[kJP + 1], double2* __restrict__ x,
                           int len, const int* vrow) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R = (wave >> 1) * 16, Cq = (wave & 1) * 16;
   const int li = lane & 15, lk = lane >> 4;
   jac_chunk_loop(xs, x, len, vrow, [&](int c0) {
-    v4d orr = {0.0, 0.0, 0.0, 0.0}, oi = {0.0, 0.0, 0.0, 0.0};
+    // three real products (Gauss): P1 = Wr Xr, P2 = Wi Xi, P3 = (Wr + Wi)(Xr + Xi);
+    // Re = P1 - P2, Im = P3 - P1 - P2 -- three independent accumulator chains
+    v4d p1 = {0.0, 0.0, 0.0, 0.0}, p2 = {0.0, 0.0, 0.0, 0.0}, p3 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int k0 = 0; k0 < kJP; k0 += 4) {
       const double2 wv = ws[R + li][k0 + lk];      // A = W[R + i][k]
       const double2 xv = xs[k0 + lk][Cq + li];     // B = X[k][C + j]
-      orr = mfma16x16x4(wv.x, xv.x, orr);
-      orr = mfma16x16x4(-wv.y, xv.y, orr);
-      oi = mfma16x16x4(wv.x, xv.y, oi);
-      oi = mfma16x16x4(wv.y, xv.x, oi);
+      p1 = mfma16x16x4(wv.x, xv.x, p1);
+      p2 = mfma16x16x4(wv.y, xv.y, p2);
+      p3 = mfma16x16x4(wv.x + wv.y, xv.x + xv.y, p3);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int v = vrow[R + 4 * r + lk];
       const int col = c0 + Cq + li;
-      if (v >= 0 && col < len) x[(size_t)v * len + col] = make_double2(orr[r], oi[r]);
+      if (v >= 0 && col < len) x[(size_t)v * len + col] = make_double2(p1[r] - p2[r], p3[r] - p1[r] - p2[r]);
     }
   });
 }
