@@ -1,0 +1,49 @@
+"""Seeded input generators (CPU): the synthetic saturated state and the
+batching and serving mixes.  They hold no arithmetic of the method; these
+tests check that the inputs have the structure the method requires."""
+import numpy as np
+
+from workloads import circuits
+
+
+def test_synthetic_state_obeys_the_charge_rule():
+    L, N, d, chi = 12, 6, 4, 40
+    ch, gam, lam = circuits.synthetic_state(L, N, d, chi, seed=3)
+    assert len(ch) == L + 1 and len(gam) == L and len(lam) == L + 1
+    assert ch[0] == [N] and ch[L] == [0]                      # Eq. (E4) boundaries
+    for k in range(L + 1):
+        c = np.array(ch[k])
+        assert np.all(np.diff(c) >= 0)                          # sorted
+        assert np.all((c >= max(0, N - k * (d - 1))) & (c <= min(N, (L - k) * (d - 1))))
+        assert len(c) <= chi and len(lam[k]) == len(c)
+        assert np.all(lam[k] > 0) and np.max(lam[k]) <= 1.0
+    for s in range(L):
+        cl, cr = np.array(ch[s])[:, None], np.array(ch[s + 1])[None, :]
+        allowed = (cl - cr >= 0) & (cl - cr <= d - 1)
+        assert gam[s].shape == allowed.shape
+        assert np.all(gam[s][~allowed] == 0)                    # Eq. (E2): no entry off the charge rule
+        assert np.all(np.abs(gam[s][allowed]) > 0)
+        # every charge has a partner on both neighbouring bonds
+        assert np.all(allowed.any(axis=1)) and np.all(allowed.any(axis=0))
+
+
+def test_synthetic_state_saturates_the_cap():
+    ch, _, _ = circuits.synthetic_state(24, 12, 4, 256, seed=5)
+    dims = [len(c) for c in ch]
+    assert max(dims) == 256 and dims[12] == 256
+
+
+def test_mixes_are_seeded_and_shaped():
+    a = circuits.config_batch_mix(16, seed=4)
+    b = circuits.config_batch_mix(16, seed=4)
+    for x, y in zip(a, b):
+        assert x["L"] == y["L"] and x["chi_max"] == y["chi_max"]
+        assert all(np.array_equal(g.u, h.u) for g, h in zip(x["gates"], y["gates"]))
+        assert 16 <= x["L"] <= 48 and x["chi_max"] in (64, 128, 256, 512)
+        assert sum(x["occupation"]) == x["L"] // 2 and len(x["layers"]) == x["L"]
+    specs = circuits.serving_mix_specs(2000, seed=5)
+    large = [s for s in specs if s["L"] == 64]
+    assert 0.03 < len(large) / len(specs) < 0.07
+    assert all(s["chi_max"] == 1024 and s["depth"] == 64 and s["n_photons"] == 32 for s in large)
+    c = circuits.config_from_spec(specs[0])
+    assert len(c["layers"]) == specs[0]["depth"] and sum(c["occupation"]) == specs[0]["n_photons"]
