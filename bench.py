@@ -39,8 +39,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/cl
 # KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99982 and writes
 # by 1).  Valid only for the Jacobi source (csrc/jacobi.hip) it was taken on.
 MEASURED_TRAFFIC = {
-    "kernels_sha256": "6556c859adf6bae95a0cc91634163fbeb8075a8315b937f87f7f057b8b25713d",
-    "fetch_kib": 21692.328, "write_kib": 35722.905,
+    "kernels_sha256": "822a403be05d76fe4454846b3c50092334887d34b1bb599996fd3e18b69e21e3",
+    "fetch_kib": 21414.034, "write_kib": 35444.209,
     "fetch_scale": 262144.0 / 131085.208, "write_scale": 1.0,
 }
 
