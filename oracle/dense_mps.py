@@ -122,6 +122,12 @@ class DenseMPS:
 
     # ------------------------------------------------------------------ update
     def apply_gate(self, site: int, u: np.ndarray) -> GateRecord:
+        """Two-mode linear-optics gate of 2x2 mode unitary u (P_d G P_d)."""
+        return self.apply_dense(site, twomode.dense(np.asarray(u, dtype=np.complex128), self.d))
+
+    def apply_dense(self, site: int, g: np.ndarray) -> GateRecord:
+        """Any two-site gate as a d^2 x d^2 matrix, row p*d+q, column m*d+n
+        (a TEBD step of a Hamiltonian; the charge is not assumed here)."""
         s, d = site, self.d
         if not 0 <= s < self.L - 1:
             raise IndexError("gate site out of range")
@@ -133,7 +139,7 @@ class DenseMPS:
         else:
             th = np.einsum("xiy,y,yjz,z->xijz", a, self.lam[s + 1], b, self.lam[s + 2])
             lam_l = self.lam[s]
-        g4 = twomode.dense(np.asarray(u, dtype=np.complex128), d).reshape(d, d, d, d)
+        g4 = np.asarray(g, dtype=np.complex128).reshape(d, d, d, d)
         before = float(np.sum(np.abs(lam_l[:, None, None, None] * th) ** 2))
         th = np.einsum("pqmn,xmnz->xpqz", g4, th)
         theta = lam_l[:, None, None, None] * th
@@ -162,8 +168,12 @@ class DenseMPS:
         return rec
 
     def run(self, gates) -> "DenseMPS":
+        """Gates with .u (mode unitary) or .g4 (dense two-site matrix)."""
         for g in gates:
-            self.apply_gate(g.site, g.u)
+            if hasattr(g, "g4"):
+                self.apply_dense(g.site, g.g4)
+            else:
+                self.apply_gate(g.site, g.u)
         return self
 
     # ------------------------------------------------------------- read-outs

@@ -59,6 +59,30 @@ class FockState:
                 out[self.index[t2]] += cache[key] * amp
         self.psi = out
 
+    def apply_dense(self, site: int, g: np.ndarray) -> None:
+        """Any two-site gate as a d^2 x d^2 matrix (row p*d+q, column a*d+b).
+        Every element is visited: one that moves a basis string out of the
+        N-particle sector raises ValueError (the gate breaks the charge)."""
+        s, d = site, self.d
+        g = np.asarray(g, dtype=np.complex128).reshape(d * d, d * d)
+        out = np.zeros_like(self.psi)
+        for i, t in enumerate(self.basis):
+            amp = self.psi[i]
+            if amp == 0:
+                continue
+            col = t[s] * d + t[s + 1]
+            for p in range(d):
+                for q in range(d):
+                    el = g[p * d + q, col]
+                    if el == 0:
+                        continue
+                    t2 = t[:s] + (p, q) + t[s + 2:]
+                    j = self.index.get(t2)
+                    if j is None:
+                        raise ValueError(f"gate element ({p}{q},{t[s]}{t[s + 1]}) leaves the charge sector")
+                    out[j] += el * amp
+        self.psi = out
+
     def amplitude(self, occ: Sequence[int]) -> complex:
         t = tuple(int(x) for x in occ)
         i = self.index.get(t)
@@ -97,7 +121,11 @@ class FockState:
 
 
 def run(occupation: Sequence[int], d: int, gates) -> FockState:
+    """Gates with .u (mode unitary) or .g4 (dense two-site matrix)."""
     st = FockState(occupation, d)
     for g in gates:
-        st.apply(g.site, g.u)
+        if hasattr(g, "g4"):
+            st.apply_dense(g.site, g.g4)
+        else:
+            st.apply(g.site, g.u)
     return st

@@ -1,0 +1,196 @@
+"""Seeded inputs for Hamiltonian time evolution (TEBD) with a U(1) charge.
+
+Input generator shared by the tests, the oracle runs and the GPU runs; it holds
+none of the MPS update.  The paper names two lattice models whose
+Hamiltonians commute with a particle number (Sec. I and Sec. II: [H, N] = 0),
+besides linear optics:
+
+* the XXZ spin-1/2 chain,
+      H = J sum_i (Sx_i Sx_{i+1} + Sy_i Sy_{i+1} + Delta Sz_i Sz_{i+1}) - hz sum_i Sz_i,
+  with occupation n = 1 for spin up (Sz = n - 1/2) and d = 2, so the charge
+  is the number of up spins (the magnetisation plus L/2);
+  Sx Sx + Sy Sy = (S+ S- + S- S+) / 2;
+* the Bose-Hubbard chain,
+      H = -J sum_i (b_i^+ b_{i+1} + b_{i+1}^+ b_i) + U/2 sum_i n_i (n_i - 1) - mu sum_i n_i,
+  with occupations 0..d-1 per site (the MPS local cutoff d).
+
+Bond Hamiltonians h_i on sites (i, i+1) carry the bond's coupling plus the
+on-site terms shared between the two bonds of each site (half each; an end
+site's terms go fully to its only bond), so sum_i h_i = H.  Matrices are
+d^2 x d^2 with index p*d + q, p the occupation of the left site.
+
+A Trotter factor is exp(-i t h) (real time) or exp(-t h) (imaginary time),
+by scipy.linalg.expm.  A second-order step of length dt is: the even bonds
+(0-1, 2-3, ...) for dt/2, the odd bonds (1-2, 3-4, ...) for dt, the even
+bonds for dt/2 again; with `merge` the closing half step of one step and the
+opening half step of the next are one layer of length dt (exact, since the
+even bonds commute among themselves).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Sequence
+
+import numpy as np
+import scipy.linalg
+
+
+@dataclass
+class DenseGate:
+    site: int
+    g4: np.ndarray            # d^2 x d^2, row p*d+q (after), column a*d+b (before)
+
+
+def _lowering(d: int) -> np.ndarray:
+    b = np.zeros((d, d))
+    for n in range(1, d):
+        b[n - 1, n] = np.sqrt(n)
+    return b
+
+
+def xxz_bond(J: float, delta: float, hz: float = 0.0, w_left: float = 0.5, w_right: float = 0.5) -> np.ndarray:
+    """h for one bond of the XXZ chain (d = 2); w_left/w_right weight the field
+    on the two sites (1/2 inside the chain, 1 at an end)."""
+    sp = np.array([[0.0, 0.0], [1.0, 0.0]])        # S+ = |1><0|
+    sm = sp.T
+    sz = np.diag([-0.5, 0.5])
+    one = np.eye(2)
+    h = J * (0.5 * (np.kron(sp, sm) + np.kron(sm, sp)) + delta * np.kron(sz, sz))
+    h = h - hz * (w_left * np.kron(sz, one) + w_right * np.kron(one, sz))
+    return h.astype(np.complex128)
+
+
+def bose_hubbard_bond(d: int, J: float, U: float, mu: float = 0.0, w_left: float = 0.5,
+                      w_right: float = 0.5) -> np.ndarray:
+    """h for one bond of the Bose-Hubbard chain with occupations 0..d-1."""
+    b = _lowering(d)
+    bd = b.T
+    n = np.diag(np.arange(d, dtype=float))
+    one = np.eye(d)
+    onsite = 0.5 * U * n @ (n - one) - mu * n
+    h = -J * (np.kron(bd, b) + np.kron(b, bd))
+    h = h + w_left * np.kron(onsite, one) + w_right * np.kron(one, onsite)
+    return h.astype(np.complex128)
+
+
+def trotter_gate(h: np.ndarray, t: float, imaginary: bool = False) -> np.ndarray:
+    """exp(-i t h), or exp(-t h) with imaginary."""
+    return scipy.linalg.expm((-t if imaginary else -1j * t) * h)
+
+
+def bond_hamiltonians(model: str, L: int, d: int, **p) -> List[np.ndarray]:
+    """h_0 .. h_{L-2} of the chain (end sites' on-site terms on their one bond)."""
+    out = []
+    for i in range(L - 1):
+        wl = 1.0 if i == 0 else 0.5
+        wr = 1.0 if i == L - 2 else 0.5
+        if model == "xxz":
+            if d != 2:
+                raise ValueError("the XXZ chain has d = 2")
+            out.append(xxz_bond(p.get("J", 1.0), p.get("delta", 1.0), p.get("hz", 0.0), wl, wr))
+        elif model == "bose_hubbard":
+            out.append(bose_hubbard_bond(d, p.get("J", 1.0), p.get("U", 1.0), p.get("mu", 0.0), wl, wr))
+        else:
+            raise ValueError(model)
+    return out
+
+
+def hamiltonian_dense(hb: Sequence[np.ndarray], L: int, d: int) -> np.ndarray:
+    """H = sum_i h_i on the full d^L space (index sum_s occ_s d^(L-1-s)); small L only."""
+    dim = d ** L
+    H = np.zeros((dim, dim), dtype=np.complex128)
+    for i, h in enumerate(hb):
+        H += np.kron(np.kron(np.eye(d ** i), h), np.eye(d ** (L - i - 2)))
+    return H
+
+
+def trotter_layers(hb: Sequence[np.ndarray], dt: float, steps: int, order: int = 2, merge: bool = True,
+                   imaginary: bool = False) -> List[List[DenseGate]]:
+    """Layers of dense gates for `steps` Trotter steps of length dt."""
+    L = len(hb) + 1
+    even = list(range(0, L - 1, 2))
+    odd = list(range(1, L - 1, 2))
+
+    def layer(bonds, t):
+        return [DenseGate(i, trotter_gate(hb[i], t, imaginary)) for i in bonds]
+
+    if order == 1:
+        out = []
+        for _ in range(steps):
+            out += [layer(even, dt), layer(odd, dt)]
+        return [l for l in out if l]
+    if order != 2:
+        raise ValueError("order 1 or 2")
+    if steps <= 0:
+        return []
+    if not merge:
+        out = []
+        for _ in range(steps):
+            out += [layer(even, dt / 2), layer(odd, dt), layer(even, dt / 2)]
+        return [l for l in out if l]
+    out = [layer(even, dt / 2)]
+    for k in range(steps):
+        out.append(layer(odd, dt))
+        out.append(layer(even, dt if k < steps - 1 else dt / 2))
+    return [l for l in out if l]
+
+
+def neel(L: int) -> List[int]:
+    """|up, down, up, ...>: L//2 + L%2 up spins."""
+    return [1 - (i % 2) for i in range(L)]
+
+
+def config_tebd(model: str, L: int, d: int, occupation: Sequence[int], dt: float, steps: int,
+                chi_max: int, cutoff: float = 0.0, order: int = 2, imaginary: bool = False, **p) -> dict:
+    hb = bond_hamiltonians(model, L, d, **p)
+    occ = [int(x) for x in occupation]
+    if len(occ) != L or any(o < 0 or o >= d for o in occ):
+        raise ValueError("occupation must have L entries in 0..d-1")
+    layers = trotter_layers(hb, dt, steps, order=order, imaginary=imaginary)
+    return {"model": model, "L": L, "d": d, "occupation": occ, "n_photons": sum(occ), "dt": dt,
+            "steps": steps, "order": order, "imaginary": imaginary, "params": dict(p),
+            "chi_max": chi_max, "cutoff": cutoff, "layers": layers,
+            "gates": [g for lay in layers for g in lay]}
+
+
+def config_xxz(L: int = 64, steps: int = 40, dt: float = 0.05, chi_max: int = 256, delta: float = 1.0,
+               J: float = 1.0, hz: float = 0.0, cutoff: float = 0.0) -> dict:
+    """Quench of the Neel state under the XXZ chain (Delta = 1: Heisenberg)."""
+    return config_tebd("xxz", L, 2, neel(L), dt, steps, chi_max, cutoff, J=J, delta=delta, hz=hz)
+
+
+def config_bose_hubbard(L: int = 64, d: int = 4, steps: int = 40, dt: float = 0.05, chi_max: int = 256,
+                        J: float = 1.0, U: float = 2.0, mu: float = 0.0, cutoff: float = 0.0,
+                        filling: int = 1) -> dict:
+    """Quench of the Mott product state (filling bosons on every site)."""
+    return config_tebd("bose_hubbard", L, d, [filling] * L, dt, steps, chi_max, cutoff, J=J, U=U, mu=mu)
+
+
+def config_xxz_quench() -> dict:
+    """The measured XXZ workload: L = 64, Neel state (32 up spins), J = 1,
+    Delta = 0.5, 40 second-order steps of dt = 0.05 (T = 2), chi_max = 256,
+    cutoff 1e-12."""
+    return config_xxz(L=64, steps=40, dt=0.05, chi_max=256, delta=0.5, cutoff=1e-12)
+
+
+def config_bose_hubbard_quench() -> dict:
+    """The measured Bose-Hubbard workload: L = 64, unit filling (64 bosons),
+    d = 4, J = 1, U = 2, 20 second-order steps of dt = 0.05 (T = 1),
+    chi_max = 256, cutoff 1e-12."""
+    return config_bose_hubbard(L=64, d=4, steps=20, dt=0.05, chi_max=256, J=1.0, U=2.0, cutoff=1e-12)
+
+
+def random_charge_conserving(d: int, seed: int, unitary: bool = True) -> np.ndarray:
+    """A random d^2 x d^2 gate that conserves p + q: a Haar-random (or, with
+    unitary False, complex Gaussian) block for each local charge n."""
+    rng = np.random.default_rng(seed)
+    g = np.zeros((d * d, d * d), dtype=np.complex128)
+    for n in range(2 * d - 1):
+        idx = [p * d + (n - p) for p in range(max(0, n - d + 1), min(d - 1, n) + 1)]
+        k = len(idx)
+        z = (rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))) / np.sqrt(2)
+        if unitary:
+            q, r = np.linalg.qr(z)
+            z = q * (np.diag(r) / np.abs(np.diag(r)))
+        g[np.ix_(idx, idx)] = z
+    return g
