@@ -15,7 +15,9 @@ and the CPU oracle timed on a bounded prefix of the same circuit; under
 "forms", the batching form (several circuits per launch: copies of this
 circuit with other seeds, and the first circuits of the mixed-size workload)
 and the serving form (Poisson arrivals, continuous batching, p50/p99 latency
-from arrival to result).  Progress goes to stderr.
+from arrival to result); under "tebd", Hamiltonian time evolution with dense
+Trotter gates (an XXZ chain and a Bose-Hubbard chain, 64 sites each, quenched
+from product states).  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -100,6 +102,24 @@ def cpu_baseline(cfg, seconds: float):
             "sample": f"first {gates} of {sum(len(l) for l in cfg['layers'])} gates (layer order) of the same "
                       f"circuit, max bond dim reached {max(m.bond_dims())}; dense (chi*d)x(d*chi) complex128 "
                       f"SVD per gate; {el:.1f} s"}
+
+
+def run_tebd(MPS, dev, cfg):
+    """One Hamiltonian time evolution (dense Trotter gates, one layer per call)."""
+    layers = [([g.site for g in lay], [g.g4 for g in lay]) for lay in cfg["layers"]]
+    ng = sum(len(s) for s, _ in layers)
+    m = MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"], device=dev)
+    m.sync()
+    t0 = time.perf_counter()
+    disc = 0.0
+    for sites, gs in layers:
+        disc += float(sum(m.apply_layer_dense(sites, gs)))
+    m.sync()
+    el = time.perf_counter() - t0
+    out = {"gates": ng, "layers": len(layers), "seconds": el, "value": ng / el, "unit": "gate applies/s",
+           "norm_loss": 1.0 - m.norm2(), "discarded_total": disc, "max_bond_dim": max(m.bond_dims())}
+    m.close()
+    return out
 
 
 def copy_probe(torch) -> int:
@@ -261,6 +281,8 @@ def main() -> int:
                     help="serving form: a second window at this rate, within the device's capacity (0 = skip)")
     ap.add_argument("--serve-max-active", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=float, default=96.0)
+    ap.add_argument("--no-tebd", action="store_true",
+                    help="skip the Hamiltonian time-evolution workloads (XXZ, Bose-Hubbard)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the "
                          "reference kernel for scaling HBM byte counters)")
@@ -380,6 +402,17 @@ def main() -> int:
         g = forms["sector_gemm_chi2048"]
         log(f"  plain {g['plain']['tflops']:.1f} TFLOP/s, split {g['split_bf16x3']['tflops_algorithmic']:.1f} "
             f"(MFMA {100 * g['split_bf16x3']['frac_of_bf16_peak']:.1f}% of BF16 peak)")
+    tebd = {}
+    if not args.no_tebd:
+        from workloads import hamiltonians
+        for key, make in (("xxz", hamiltonians.config_xxz_quench),
+                          ("bose_hubbard", hamiltonians.config_bose_hubbard_quench)):
+            c = make()
+            log(f"Hamiltonian TEBD ({key}, L={c['L']}, d={c['d']}, chi_max={c['chi_max']}) ...")
+            r = run_tebd(MPS, dev, c)
+            r["workload"] = " ".join((make.__doc__ or "").split(":", 1)[-1].split())
+            tebd[key] = r
+            log(f"  {r['value']:.1f} gate applies/s, max bond dim {r['max_bond_dim']}")
     if args.serve_seconds > 0:
         log(f"serving form: {args.serve_seconds:.0f} s at {args.serve_rate:g} requests/s ...")
         forms["serving"] = run_serving(args, args.serve_rate, dev, circuits)
@@ -431,6 +464,7 @@ def main() -> int:
                    "lds_per_block": getattr(props, "shared_memory_per_block", None),
                    "lds_per_cu": getattr(props, "shared_memory_per_multiprocessor", None)},
         "forms": forms,
+        "tebd": tebd,
         "result": {"norm_loss": norm_loss, "max_bond_dim": max_chi,
                    "max_discarded": agg["max_discarded"], "min_cut_margin": agg["min_margin"]},
     }

@@ -187,6 +187,20 @@ mps_status mps_apply_gate(mps_t h, int site, const mps_z u2[4], double* discarde
 mps_status mps_apply_layer(mps_t h, int ngates, const int* sites,
                            const mps_z* u2s, double* discarded);
 
+/* The same layer for gates given as dense two-site matrices, such as the
+ * Trotter factors exp(-i dt h) of a Hamiltonian with [H, N] = 0 (Sec. II:
+ * Bose-Hubbard, XXZ with the magnetisation as the charge).  g4s holds
+ * ngates matrices of d^2 x d^2 complex elements back to back, each
+ * row-major with row index p*d + q (occupations of sites site and site+1
+ * after the gate) and column index a*d + b (before).  The library reads
+ * the blocks G^(n)[p][a] = g4[(p, n-p), (a, n-a)] and the rest of the
+ * update is that of mps_apply_layer.  Elements with p + q != a + b must
+ * vanish: those up to 1e-13 times the gate's largest element modulus are
+ * dropped, a larger one fails with MPS_E_CHARGE before any state changes.
+ * Errors: as mps_apply_layer; MPS_E_CHARGE as above. */
+mps_status mps_apply_layer_dense(mps_t h, int ngates, const int* sites,
+                                 const mps_z* g4s, double* discarded);
+
 /* Batching form: one layer of each of nh independent states (different
  * circuits, sizes and cut options, one local dimension d, one stream),
  * executed together -- the updates of all states share every launch, so

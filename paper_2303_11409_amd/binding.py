@@ -68,7 +68,7 @@ class mps_stats(C.Structure):
 
 
 EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_destroy", "mps_apply_gate",
-           "mps_apply_layer", "mps_apply_batch", "mps_truncate", "mps_amplitude", "mps_norm", "mps_bond_sectors",
+           "mps_apply_layer", "mps_apply_layer_dense", "mps_apply_batch", "mps_truncate", "mps_amplitude", "mps_norm", "mps_bond_sectors",
            "mps_bond_lambda", "mps_site_tensor", "mps_set_timing", "mps_get_stats",
            "mps_reset_stats", "mps_sync", "mps_last_error"]
 
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mps_destroy": (st, [h]),
         "mps_apply_gate": (st, [h, C.c_int, P(mps_z), P(C.c_double)]),
         "mps_apply_layer": (st, [h, C.c_int, P(C.c_int), P(mps_z), P(C.c_double)]),
+        "mps_apply_layer_dense": (st, [h, C.c_int, P(C.c_int), P(mps_z), P(C.c_double)]),
         "mps_apply_batch": (st, [C.c_int, P(h), P(C.c_int), P(C.c_int), P(mps_z), P(C.c_double)]),
         "mps_truncate": (st, [h, C.c_int, C.c_int, C.c_double, P(C.c_double)]),
         "mps_amplitude": (st, [h, C.c_int, P(C.c_int), P(mps_z)]),
@@ -265,6 +266,19 @@ class MPS:
         zu = np.ascontiguousarray(np.stack([np.asarray(u, dtype=np.complex128).reshape(2, 2) for u in us]))
         _check(self._lib.mps_apply_layer(self._h, n, c_sites, zu.ctypes.data_as(C.POINTER(mps_z)),
                                          disc.ctypes.data_as(C.POINTER(C.c_double))))
+        return disc
+
+    def apply_layer_dense(self, sites: Sequence[int], g4s: Sequence[np.ndarray]) -> np.ndarray:
+        """Dense two-site gates, each d^2 x d^2 with row p*d+q and column a*d+b."""
+        n = len(sites)
+        disc = np.zeros(n, dtype=np.float64)
+        if n == 0:
+            return disc
+        dd = self.d * self.d
+        c_sites = (C.c_int * n)(*[int(s) for s in sites])
+        zg = np.ascontiguousarray(np.stack([np.asarray(g, dtype=np.complex128).reshape(dd, dd) for g in g4s]))
+        _check(self._lib.mps_apply_layer_dense(self._h, n, c_sites, zg.ctypes.data_as(C.POINTER(mps_z)),
+                                               disc.ctypes.data_as(C.POINTER(C.c_double))))
         return disc
 
     def truncate(self, bond: int, chi_max: int, cutoff: float) -> float:

@@ -283,6 +283,20 @@ void gate_blocks(const mps_z u[4], int d, double2* out) {
   }
 }
 
+// G^(n)[p][a] of a gate given as a dense d^2 x d^2 matrix (row p*d+q, column
+// a*d+b): the element of row p*d+(n-p) and column a*d+(n-a).  Elements that
+// change the charge were checked to be negligible and are not read.
+void dense_blocks(const mps_z* g4, int d, double2* out) {
+  const int nb = 2 * d - 1, dd = d * d;
+  for (int i = 0; i < nb * d * d; ++i) out[i] = make_double2(0.0, 0.0);
+  for (int n = 0; n < nb; ++n)
+    for (int p = std::max(0, n - d + 1); p <= std::min(d - 1, n); ++p)
+      for (int a = std::max(0, n - d + 1); a <= std::min(d - 1, n); ++a) {
+        const mps_z v = g4[(size_t)(p * d + n - p) * dd + a * d + n - a];
+        out[(n * d + p) * d + a] = make_double2(v.re, v.im);
+      }
+}
+
 // ---- capacities ------------------------------------------------------------
 // Largest Schmidt rank a bond can reach: sum over charges c of
 // min(#left strings with N-c photons, #right strings with c photons),
@@ -351,12 +365,14 @@ struct BatchPlan {
   double sg_mfma_flops = 0.0;
 };
 
-// One two-site update of a batch: the state it acts on, its left site and its
-// 2x2 mode unitary.  A batch may mix states (of one local dimension d).
+// One two-site update of a batch: the state it acts on, its left site and
+// either its 2x2 mode unitary (u) or its dense d^2 x d^2 gate (g4, when u is
+// NULL).  A batch may mix states (of one local dimension d).
 struct GateRef {
   mps_state* h;
   int site;
   const mps_z* u;
+  const mps_z* g4;
 };
 
 mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
@@ -372,7 +388,11 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
     const Bond& BL = h->bonds[s];
     const Bond& BM = h->bonds[s + 1];
     const Bond& BR = h->bonds[s + 2];
-    gate_blocks(refs[g].u, d, P.coef.data() + (size_t)g * (2 * d - 1) * d * d);
+    double2* cg = P.coef.data() + (size_t)g * (2 * d - 1) * d * d;
+    if (refs[g].u)
+      gate_blocks(refs[g].u, d, cg);
+    else
+      dense_blocks(refs[g].g4, d, cg);
     GateWork gw{};
     gw.bl = h->site[s];
     gw.br = h->site[s + 1];
@@ -843,18 +863,35 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   return MPS_OK;
 }
 
-// Argument checks of one state's layer: sites in range, finite gates, disjoint pairs.
-mps_status check_layer(mps_t h, int ngates, const int* sites, const mps_z* u2s) {
+// A dense gate may carry charge-changing elements up to this fraction of its
+// largest element (rounding of a numerically built gate); they are dropped.
+constexpr double kDenseLeak = 1e-13;
+
+// Argument checks of one state's layer: sites in range, finite gates, disjoint
+// pairs.  Gates are 2x2 mode unitaries, or with dense set d^2 x d^2 matrices
+// that must conserve the local charge (p + q = a + b).
+mps_status check_layer(mps_t h, int ngates, const int* sites, const mps_z* gs, bool dense = false) {
   if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
   if (ngates < 0) return fail(MPS_E_ARG, "negative gate count");
   if (ngates == 0) return MPS_OK;
-  if (!sites || !u2s) return fail(MPS_E_ARG, "sites and u2s are required");
+  if (!sites || !gs) return fail(MPS_E_ARG, "sites and gates are required");
+  const int d = h->d, dd = d * d;
+  const size_t gsz = dense ? (size_t)dd * dd : 4;
   std::vector<int> order(ngates);
   for (int g = 0; g < ngates; ++g) {
     if (sites[g] < 0 || sites[g] > h->L - 2) return fail(MPS_E_ARG, "gate site %d outside 0..L-2", sites[g]);
-    for (int k = 0; k < 4; ++k)
-      if (!std::isfinite(u2s[4 * g + k].re) || !std::isfinite(u2s[4 * g + k].im))
-        return fail(MPS_E_ARG, "non-finite gate element");
+    const mps_z* e = gs + gsz * g;
+    double big = 0.0;
+    for (size_t k = 0; k < gsz; ++k) {
+      if (!std::isfinite(e[k].re) || !std::isfinite(e[k].im)) return fail(MPS_E_ARG, "non-finite gate element");
+      big = std::max(big, std::hypot(e[k].re, e[k].im));
+    }
+    if (dense)
+      for (int r = 0; r < dd; ++r)
+        for (int c = 0; c < dd; ++c)
+          if (r / d + r % d != c / d + c % d && std::hypot(e[r * dd + c].re, e[r * dd + c].im) > kDenseLeak * big)
+            return fail(MPS_E_CHARGE, "gate %d: element (%d,%d) changes the local charge %d -> %d", g, r, c,
+                        c / d + c % d, r / d + r % d);
     order[g] = sites[g];
   }
   std::sort(order.begin(), order.end());
@@ -1098,7 +1135,16 @@ mps_status mps_apply_layer(mps_t h, int ngates, const int* sites, const mps_z* u
   STCHK(check_layer(h, ngates, sites, u2s));
   if (ngates == 0) return MPS_OK;
   std::vector<GateRef> refs(ngates);
-  for (int g = 0; g < ngates; ++g) refs[g] = {h, sites[g], u2s + 4 * g};
+  for (int g = 0; g < ngates; ++g) refs[g] = {h, sites[g], u2s + 4 * g, nullptr};
+  return apply_batch(refs, discarded);
+}
+
+mps_status mps_apply_layer_dense(mps_t h, int ngates, const int* sites, const mps_z* g4s, double* discarded) {
+  STCHK(check_layer(h, ngates, sites, g4s, true));
+  if (ngates == 0) return MPS_OK;
+  const size_t gsz = (size_t)h->d * h->d * h->d * h->d;
+  std::vector<GateRef> refs(ngates);
+  for (int g = 0; g < ngates; ++g) refs[g] = {h, sites[g], nullptr, g4s + gsz * g};
   return apply_batch(refs, discarded);
 }
 
@@ -1124,7 +1170,7 @@ mps_status mps_apply_batch(int nh, const mps_t* hs, const int* ngates, const int
       if (h->st != h0->st) return fail(MPS_E_ARG, "states of one batch must share one stream");
       if (h->opts.form != h0->opts.form) return fail(MPS_E_ARG, "states of one batch must share the form");
     }
-    for (int g = 0; g < ngates[i]; ++g) refs.push_back({h, sites[off + g], u2s + 4 * (off + g)});
+    for (int g = 0; g < ngates[i]; ++g) refs.push_back({h, sites[off + g], u2s + 4 * (off + g), nullptr});
     off += ngates[i];
   }
   if (refs.empty()) return MPS_OK;

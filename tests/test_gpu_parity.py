@@ -372,3 +372,176 @@ def test_precision_form_brickwork_vs_oracle(mps_cls):
     close_amps(m.amplitudes(pats), ref.amplitudes(pats), TOL_SPLIT_CIRCUIT)
     assert abs(m.norm2() - ref.norm2()) <= TOL_SPLIT_CIRCUIT * ref.norm2()
     m.close()
+
+
+def test_precision_workload_chi256_vs_stored_oracle(mps_cls):
+    """The 64-mode precision circuit (32 photons in even modes, d=4, 64 layers =
+    2016 gates, seed 3) at chi_max = 256 against the oracle's stored results
+    (tests/golden, from oracle/ only): the plain form to the complex128 bar on
+    1025 amplitudes, every bond's charges, every gate's discarded weight and the
+    norm; the split-BF16 form to its accumulated bound.  Each gate is a
+    contraction (norm non-increasing) that adds at most ~3 * 2^-18 of the norm
+    through the split products, so 2016 gates stay within 2016 * 1.1e-5 = 2.2e-2
+    normwise; the cut binds at chi_max, so the split form's bookkeeping is only
+    compared where no stored cut margin is below the products' noise."""
+    import json
+    import os
+    from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
+    path = os.path.join(os.path.dirname(__file__), "golden", "L64_N32_d4_chi256.json")
+    ref = json.load(open(path))
+    cfg = circuits.config_precision(seed=3, chi_max=256)
+    pats = np.array(ref["patterns"], dtype=np.int32)
+    amp = np.array(ref["amp_re"]) + 1j * np.array(ref["amp_im"])
+    m, disc = run_gpu(mps_cls, cfg["occupation"], 4, None, chi_max=256, cutoff=1e-12, layered=True,
+                      layers=cfg["layers"])
+    assert np.max(np.abs(disc - np.array(ref["discarded"]))) <= 1e-12
+    # the closest cut of the stored run has margin 5.6e-10 of s_0, far above the
+    # ~1e-13 relative error of the FP64 singular values, so every cut agrees
+    assert min(x for x in ref["margin"] if x is not None) > 1e-10
+    for b in range(65):
+        exp = {int(k): v for k, v in ref["bond_charges"][b].items()}
+        assert m.bond_sectors(b) == exp, b
+    close_amps(m.amplitudes(pats), amp)
+    assert abs(m.norm2() - ref["norm2"]) <= 1e-9 * ref["norm2"]
+    m.close()
+    s = mps_cls(cfg["occupation"], 4, chi_max=256, cutoff=1e-12, form=FORM_SPLIT_BF16X3)
+    for lay in cfg["layers"]:
+        s.apply_layer([g.site for g in lay], [g.u for g in lay])
+    got = s.amplitudes(pats)
+    err = float(np.linalg.norm(got - amp) / np.linalg.norm(amp))
+    assert err <= 2016 * 1.1e-5, err
+    assert abs(s.norm2() - ref["norm2"]) <= 2016 * 1.1e-5 * ref["norm2"]
+    margins = [x for x in ref["margin"] if x is not None]
+    if min(margins) > 1e-4:
+        for b in range(65):
+            assert s.bond_sectors(b) == {int(k): v for k, v in ref["bond_charges"][b].items()}, b
+    s.close()
+
+
+def test_batch_rejects_mixed_forms_and_duplicates(mps_cls):
+    """mps_apply_batch refuses states of different forms or a state listed twice,
+    before touching any state."""
+    from paper_2303_11409_amd import MPSError, apply_batch
+    from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
+    occ = [1, 1, 0, 0]
+    a = mps_cls(occ, 3)
+    b = mps_cls(occ, 3, form=FORM_SPLIT_BF16X3)
+    u = circuits.beam_splitter(0.3, 0.2)
+    before = a.amplitudes(np.array([[1, 1, 0, 0]]))
+    with pytest.raises(MPSError):
+        apply_batch([a, b], [([0], [u]), ([0], [u])])
+    with pytest.raises(MPSError):
+        apply_batch([a, a], [([0], [u]), ([2], [u])])
+    assert np.array_equal(a.amplitudes(np.array([[1, 1, 0, 0]])), before)
+    a.close()
+    b.close()
+
+
+# ------------------------------------------------------------ Hamiltonian TEBD
+def run_dense(MPS, cfg):
+    m = MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"])
+    disc = []
+    for lay in cfg["layers"]:
+        disc.extend(m.apply_layer_dense([g.site for g in lay], [g.g4 for g in lay]))
+    return m, np.array(disc)
+
+
+@pytest.mark.parametrize("model", ["xxz", "bose_hubbard"])
+def test_tebd_dense_gates_vs_oracle(mps_cls, model):
+    """Second-order Trotter evolution (dense two-site gates exp(-i dt h)) with
+    truncation: per-gate discarded weight, Schmidt values, bond charges and
+    amplitudes against the dense oracle at the same cut."""
+    from workloads import hamiltonians as ham
+    if model == "xxz":
+        cfg = ham.config_tebd("xxz", 24, 2, ham.neel(24), 0.2, 10, 20, 1e-12, J=1.0, delta=1.3, hz=0.07)
+    else:
+        cfg = ham.config_tebd("bose_hubbard", 10, 4, [1, 2] * 5, 0.15, 5, 20, 1e-12, J=1.0, U=1.5, mu=0.1)
+    m, disc = run_dense(mps_cls, cfg)
+    ref = dense_mps.DenseMPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"])
+    ref.run(cfg["gates"])
+    assert min(r.margin for r in ref.records) > 1e-9
+    odisc = np.array([r.discarded for r in ref.records])
+    assert odisc.max() > 1e-10                      # the cut is active
+    assert np.max(np.abs(disc - odisc)) <= 1e-12
+    pats = circuits.sample_patterns(cfg["L"], cfg["n_photons"], cfg["d"], 300, 8)
+    close_amps(m.amplitudes(pats), ref.amplitudes(pats))
+    assert abs(m.norm2() - ref.norm2()) <= TOL
+    check_bookkeeping(m, ref)
+    check_lambdas(m, ref)
+    m.close()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_dense_random_charge_conserving_gates_vs_brute_force(mps_cls, seed):
+    """Random block-diagonal gates (unitary, and non-unitary complex Gaussian
+    blocks) without truncation against the Fock-space brute force."""
+    from workloads import hamiltonians as ham
+    rng = np.random.default_rng(900 + seed)
+    L = int(rng.integers(3, 7))
+    d = int(rng.integers(2, 5))
+    occ = [int(x) for x in rng.integers(0, d, size=L)]
+    if sum(occ) == 0:
+        occ[0] = 1
+    gates = [ham.DenseGate(int(rng.integers(0, L - 1)),
+                           ham.random_charge_conserving(d, int(rng.integers(1 << 30)), unitary=bool(seed % 2 == 0)))
+             for _ in range(3 * L)]
+    m = mps_cls(occ, d)
+    for g in gates:
+        m.apply_layer_dense([g.site], [g.g4])
+    st = fock.run(occ, d, gates)
+    pats = circuits.all_patterns(L, sum(occ), d)
+    ref = np.array([st.amplitude(p) for p in pats])
+    got = m.amplitudes(pats)
+    scale = float(np.max(np.abs(ref)))
+    assert np.max(np.abs(got - ref)) <= 1e-12 * max(scale, 1.0)
+    assert abs(m.norm2() - st.norm2()) <= 1e-12 * max(st.norm2(), 1.0)
+    m.close()
+
+
+def test_dense_layer_equals_mode_unitary_layer(mps_cls):
+    """A beam splitter given as its dense Fock matrix gives the result of the
+    mode-unitary entry point (the coefficients agree to rounding)."""
+    from oracle import twomode
+    cfg = circuits.config_brickwork(12, 6, "first", 3, 8, 12, 1e-12, 41, "t")
+    a, da = run_gpu(mps_cls, cfg["occupation"], 3, None, chi_max=12, cutoff=1e-12, layered=True,
+                    layers=cfg["layers"])
+    b = mps_cls(cfg["occupation"], 3, chi_max=12, cutoff=1e-12)
+    db = []
+    for lay in cfg["layers"]:
+        db.extend(b.apply_layer_dense([g.site for g in lay], [twomode.dense(g.u, 3) for g in lay]))
+    pats = circuits.sample_patterns(12, 6, 3, 200, 6)
+    close_amps(b.amplitudes(pats), a.amplitudes(pats))
+    assert np.max(np.abs(np.array(db) - da)) <= 1e-13
+    for k in range(13):
+        assert a.bond_sectors(k) == b.bond_sectors(k)
+    a.close()
+    b.close()
+
+
+def test_dense_gate_charge_check(mps_cls):
+    """A gate that changes the local charge is refused before the state
+    changes; rounding-level leakage (below 1e-13 of the largest element) is
+    accepted and dropped."""
+    from paper_2303_11409_amd import MPSError
+    from workloads import hamiltonians as ham
+    occ = [1, 0, 1, 0, 1, 0]
+    m = mps_cls(occ, 2)
+    pats = circuits.all_patterns(6, 3, 2)
+    g = ham.trotter_gate(ham.xxz_bond(1.0, 0.5), 0.3)
+    m.apply_layer_dense([0, 2], [g, g])
+    before = m.amplitudes(pats)
+    bad = g.copy()
+    bad[1, 0] = 1e-6                                   # |00> -> |01>
+    with pytest.raises(MPSError) as e:
+        m.apply_layer_dense([1, 3], [g, bad])
+    assert e.value.status == -2                        # MPS_E_CHARGE
+    assert np.array_equal(m.amplitudes(pats), before)
+    tiny = g.copy()
+    tiny[1, 0] = 1e-15
+    ref = mps_cls(occ, 2)
+    ref.apply_layer_dense([0, 2], [g, g])
+    ref.apply_layer_dense([1, 3], [g, g])
+    m.apply_layer_dense([1, 3], [g, tiny])
+    assert np.array_equal(m.amplitudes(pats), ref.amplitudes(pats))
+    m.close()
+    ref.close()
