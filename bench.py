@@ -281,6 +281,8 @@ def main() -> int:
                     help="serving form: a second window at this rate, within the device's capacity (0 = skip)")
     ap.add_argument("--serve-max-active", type=int, default=64)
     ap.add_argument("--serve-budget-gib", type=float, default=96.0)
+    ap.add_argument("--samples", type=int, default=4096,
+                    help="exact output samples drawn from the final state (0 = skip)")
     ap.add_argument("--no-tebd", action="store_true",
                     help="skip the Hamiltonian time-evolution workloads (XXZ, Bose-Hubbard)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -351,6 +353,21 @@ def main() -> int:
                     agg[k] = max(agg[k], v)
                 else:
                     agg[k] += v
+    sampling = None
+    if args.samples > 0:
+        log(f"sampling {args.samples} output patterns from the final state ...")
+        us = np.random.default_rng(7).random((args.samples, cfg["L"]))
+        states[0].sample(us[:8])                      # workspaces
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        spats, sprob = states[0].sample(us)
+        sel = time.perf_counter() - ts
+        sampling = {"workload": f"{args.samples} exact samples (chain rule over the left environments, "
+                                "uniforms seed 7) of the final state of one step, host-to-host",
+                    "samples": args.samples, "seconds": sel, "value": args.samples / sel, "unit": "samples/s",
+                    "distinct_patterns": int(len({tuple(p) for p in spats.tolist()})),
+                    "max_prob": float(sprob.max())}
+        log(f"  {args.samples / sel:.0f} samples/s")
     norm_loss = 1.0 - states[0].norm2()
     max_chi = max(states[0].bond_dims())
     probe = circuits.sample_patterns(32, 16, 4, 64, 102)
@@ -465,6 +482,7 @@ def main() -> int:
                    "lds_per_cu": getattr(props, "shared_memory_per_multiprocessor", None)},
         "forms": forms,
         "tebd": tebd,
+        "sampling": sampling,
         "result": {"norm_loss": norm_loss, "max_bond_dim": max_chi,
                    "max_discarded": agg["max_discarded"], "min_cut_margin": agg["min_margin"]},
     }

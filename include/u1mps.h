@@ -232,6 +232,21 @@ mps_status mps_amplitude(mps_t h, int count, const int* occ, mps_z* out);
 /* <psi|psi> by full contraction of the transfer matrices (not sum lambda^2). */
 mps_status mps_norm(mps_t h, double* norm2);
 
+/* Exact samples of output patterns (the read-out of a boson-sampling
+ * circuit, Sec. I): pattern i is drawn with probability |c_i|^2 / <psi|psi>,
+ * c_i as in Eq. (E2), by the chain rule from mode L-1 down to mode 0.  Mode
+ * k of sample j takes the smallest occupation whose cumulative conditional
+ * probability exceeds uniforms[j*L + k] (caller-supplied, each in [0, 1);
+ * the library draws no random numbers).
+ *   occ    out, count*L row-major occupations;
+ *   prob   out, may be NULL: |c_i|^2 / <psi|psi> of each drawn pattern.
+ * The left environments of every bond are held in device memory during the
+ * call (as many complex entries as the squared bond dimensions, summed).
+ * Errors: MPS_E_ARG (a uniform outside [0, 1), a charge block above 2048),
+ * MPS_E_NUMERIC (a vanished or non-finite marginal), MPS_E_NOMEM,
+ * MPS_E_DEVICE. */
+mps_status mps_sample(mps_t h, int count, const double* uniforms, int* occ, double* prob);
+
 /* Bookkeeping of bond `bond` (0..L): its distinct charges in ascending
  * order and their multiplicities.  cap is the capacity of charge[] and
  * count[]; *nsec receives the number of sectors (MPS_E_ARG if > cap). */

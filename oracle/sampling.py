@@ -75,14 +75,23 @@ def left_environments(mps) -> List[np.ndarray]:
     return E
 
 
-def mps_samples(mps, uniforms: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+def decision_margin(p: np.ndarray, u: float) -> float:
+    """Distance of u * sum(p) from the nearest cumulative boundary, over sum(p)."""
+    tot = float(np.sum(p))
+    return float(np.min(np.abs(u * tot - np.cumsum(p)))) / tot
+
+
+def mps_samples(mps, uniforms: np.ndarray, margins: bool = False):
     """Chain-rule samples from the dense oracle MPS, modes L-1 down to 0.
-    Returns (patterns [count, L], probabilities |c_i|^2 / <psi|psi> [count])."""
+    Returns (patterns [count, L], probabilities |c_i|^2 / <psi|psi> [count])
+    and, with margins, each sample's smallest decision margin (a draw whose
+    margin is at rounding level may go either way in another precision)."""
     E = left_environments(mps)
     u = np.asarray(uniforms, dtype=np.float64)
     L, d = mps.L, mps.d
     out = np.zeros((u.shape[0], L), dtype=np.int32)
     prob = np.ones(u.shape[0])
+    marg = np.full(u.shape[0], np.inf)
     for j in range(u.shape[0]):
         v = np.ones(1, dtype=np.complex128)            # contraction of the chosen suffix
         for k in range(L - 1, -1, -1):
@@ -91,7 +100,10 @@ def mps_samples(mps, uniforms: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
             p = np.array([float(np.real(np.vdot(w, E[k] @ w))) for w in ws])
             p = np.maximum(p, 0.0)
             i = _pick(p, u[j, k])
+            marg[j] = min(marg[j], decision_margin(p, u[j, k]))
             prob[j] *= p[i] / float(np.sum(p))
             out[j, k] = i
             v = ws[i] / np.sqrt(p[i])
+    if margins:
+        return out, prob, marg
     return out, prob

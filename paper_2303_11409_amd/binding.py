@@ -68,7 +68,7 @@ class mps_stats(C.Structure):
 
 
 EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_destroy", "mps_apply_gate",
-           "mps_apply_layer", "mps_apply_layer_dense", "mps_apply_batch", "mps_truncate", "mps_amplitude", "mps_norm", "mps_bond_sectors",
+           "mps_apply_layer", "mps_apply_layer_dense", "mps_apply_batch", "mps_truncate", "mps_amplitude", "mps_norm", "mps_sample", "mps_bond_sectors",
            "mps_bond_lambda", "mps_site_tensor", "mps_set_timing", "mps_get_stats",
            "mps_reset_stats", "mps_sync", "mps_last_error"]
 
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mps_truncate": (st, [h, C.c_int, C.c_int, C.c_double, P(C.c_double)]),
         "mps_amplitude": (st, [h, C.c_int, P(C.c_int), P(mps_z)]),
         "mps_norm": (st, [h, P(C.c_double)]),
+        "mps_sample": (st, [h, C.c_int, P(C.c_double), P(C.c_int), P(C.c_double)]),
         "mps_bond_sectors": (st, [h, C.c_int, C.c_int, P(C.c_int), P(C.c_int), P(C.c_int)]),
         "mps_bond_lambda": (st, [h, C.c_int, C.c_int, P(C.c_int), P(C.c_double)]),
         "mps_site_tensor": (st, [h, C.c_int, C.c_size_t, P(C.c_int), P(C.c_int), P(mps_z)]),
@@ -299,6 +300,19 @@ class MPS:
         v = C.c_double(0.0)
         _check(self._lib.mps_norm(self._h, C.byref(v)))
         return v.value
+
+    def sample(self, uniforms: np.ndarray):
+        """Exact samples: uniforms [count, L] in [0, 1) -> (patterns [count, L]
+        int32, probabilities [count])."""
+        u = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64).reshape(-1, self.L))
+        n = u.shape[0]
+        occ = np.zeros((n, self.L), dtype=np.int32)
+        prob = np.zeros(n, dtype=np.float64)
+        if n:
+            _check(self._lib.mps_sample(self._h, n, u.ctypes.data_as(C.POINTER(C.c_double)),
+                                        occ.ctypes.data_as(C.POINTER(C.c_int)),
+                                        prob.ctypes.data_as(C.POINTER(C.c_double))))
+        return occ, prob
 
     def bond_sectors(self, bond: int) -> Dict[int, int]:
         cap = self.N + 1

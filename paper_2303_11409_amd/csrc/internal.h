@@ -19,6 +19,7 @@ namespace u1mps {
 constexpr int kMaxD = 8;          // local dimension limit (occupations 0..7)
 constexpr int kThetaTile = 32;    // Theta output tile edge
 constexpr int kGemmTile = 32;     // generic ZGEMM tile edge
+constexpr size_t kSampleLds = 64 * 1024;   // sampler: LDS for its two vectors
 
 // One two-site update inside a batch.
 struct GateWork {

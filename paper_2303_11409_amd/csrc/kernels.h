@@ -54,6 +54,14 @@ hipError_t launch_amplitude(const double2* const* sites, const int* ld, const in
                             const int* occ, double2* out, int count, int L, int d, int N,
                             int maxdim, hipStream_t st);
 
+// Chain-rule sampling of `count` patterns (sample.hip): sites[s] (ldb[s]) and
+// the left environments envs[s] (lde[s]) of every site, bondmap[(b, c)] =
+// (offset, count) of charge c on bond b, uniforms[count * L]; writes occ and
+// prob (-1 where a marginal vanished or was not finite).
+hipError_t launch_sample(const double2* const* sites, const int* ldb, const double2* const* envs,
+                         const int* lde, const int2* bondmap, const double* uniforms, int* occ,
+                         double* prob, int count, int L, int d, int N, int maxblk, hipStream_t st);
+
 hipError_t launch_gather_cols(const double2* src, int lds, double2* dst, int ldd, int rows,
                               const int* map, int ncols, hipStream_t st);
 hipError_t launch_gather_rows(const double2* src, int lds, double2* dst, int ldd, const int* map,

@@ -107,7 +107,7 @@ struct mps_state {
   std::vector<double2*> site;    // per site, cap[s] * cap[s+1] complex
   // workspaces (grow-only)
   DevBuf th_raw, th_scaled, acc, sigma, order, jperm, jnorm, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc,
-      pbuf, planes;
+      pbuf, planes, envs, samp;
   PinBuf stage_plan, stage_upd, stage_res, stage_misc, stage_flag;
   mps_stats stats{};
   bool timing = false;
@@ -908,7 +908,7 @@ mps_status destroy_buffers(mps_state* h) {
   h->site.clear();
   DevBuf* bufs[] = {&h->th_raw, &h->th_scaled, &h->acc, &h->jperm, &h->jnorm, &h->sigma, &h->order, &h->plan, &h->upd,
                     &h->norm_e0, &h->norm_e1, &h->norm_t, &h->sel_v, &h->sel_k, &h->misc, &h->pbuf,
-                    &h->planes};
+                    &h->planes, &h->envs, &h->samp};
   for (DevBuf* b : bufs) {
     dfree(h, b->p);
     b->p = nullptr;
@@ -1311,17 +1311,18 @@ mps_status mps_amplitude(mps_t h, int count, const int* occ, mps_z* out) {
   return MPS_OK;
 }
 
-mps_status mps_norm(mps_t h, double* norm2) {
-  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
-  if (!norm2) return fail(MPS_E_ARG, "norm2 is NULL");
+// Left environments E_0 .. E_L into the frames eb[b] (dim_b x dim_b, row-major):
+// E_0 = 1 and E_{s+1}[c', c'] = sum_w B[w, c']^dagger E_s[w, w] B[w, c'], w the
+// rows of bond s whose charges c' .. c'+d-1 reach charge c' of bond s+1, so
+// every E is block-diagonal by charge.  eb[s] and eb[s+2] may be one frame.
+// The plan goes through misc/stage_misc; stage_misc keeps `extra` bytes past
+// it (*tail is their offset) for the caller.
+mps_status left_envs(mps_state* h, const std::vector<double2*>& eb, size_t extra, size_t* tail) {
   const int L = h->L, d = h->d;
   int maxdim = 1;
   for (int b = 0; b <= L; ++b) maxdim = std::max(maxdim, h->bonds[b].dim());
   const size_t esz = (size_t)maxdim * maxdim;
-  STCHK(ensure(h, h->norm_e0, esz * sizeof(double2)));
-  STCHK(ensure(h, h->norm_e1, esz * sizeof(double2)));
   STCHK(ensure(h, h->norm_t, (size_t)d * esz * sizeof(double2)));
-  double2* e[2] = {static_cast<double2*>(h->norm_e0.p), static_cast<double2*>(h->norm_e1.p)};
   double2* tbuf = static_cast<double2*>(h->norm_t.p);
   // per site: problems T_c' = E[w, w] B[w, c'] and E'[c', c'] = B[w, c']^dagger T_c'
   std::vector<std::vector<GemmWork>> p1(L), p2(L);
@@ -1332,8 +1333,8 @@ mps_status mps_norm(mps_t h, double* norm2) {
     const Bond& B0 = h->bonds[s];
     const Bond& B1 = h->bonds[s + 1];
     const int ld0 = B0.dim(), ld1 = B1.dim();
-    double2* ein = e[s & 1];
-    double2* eout = e[(s + 1) & 1];
+    double2* ein = eb[s];
+    double2* eout = eb[s + 1];
     fptr[s] = eout;
     fcnt[s] = (long long)ld1 * ld1;
     size_t toff = 0;
@@ -1373,7 +1374,7 @@ mps_status mps_norm(mps_t h, double* norm2) {
       p2[s].push_back(b);
       toff += (size_t)kw * nn;
     }
-    if (toff > (size_t)d * esz) return fail(MPS_E_ARG, "internal: norm scratch too small");
+    if (toff > (size_t)d * esz) return fail(MPS_E_ARG, "internal: environment scratch too small");
   }
   Packer pk;
   std::vector<size_t> o1(L), o2(L);
@@ -1387,19 +1388,104 @@ mps_status mps_norm(mps_t h, double* norm2) {
   const size_t o_one = pk.add(&one, sizeof one);
   HIPCHK(hipStreamSynchronize(h->st));
   STCHK(ensure(h, h->misc, pk.total));
-  STCHK(ensure_pin(h->stage_misc, pk.total + sizeof(double2)));
+  STCHK(ensure_pin(h->stage_misc, pk.total + extra));
   pk.write(h->stage_misc.p);
   HIPCHK(hipMemcpyAsync(h->misc.p, h->stage_misc.p, pk.total, hipMemcpyHostToDevice, h->st));
-  HIPCHK(hipMemcpyAsync(e[0], at<double2>(h->misc, o_one), sizeof(double2), hipMemcpyDeviceToDevice, h->st));
+  HIPCHK(hipMemcpyAsync(eb[0], at<double2>(h->misc, o_one), sizeof(double2), hipMemcpyDeviceToDevice, h->st));
   for (int s = 0; s < L; ++s) {
     HIPCHK(launch_zero_fill(at<double2*>(h->misc, o_fp) + s, at<long long>(h->misc, o_fc) + s, 1, fcnt[s], h->st));
     HIPCHK(launch_zgemm(at<GemmWork>(h->misc, o1[s]), (int)p1[s].size(), nt1[s], h->st));
     HIPCHK(launch_zgemm(at<GemmWork>(h->misc, o2[s]), (int)p2[s].size(), nt2[s], h->st));
   }
-  double2* res = reinterpret_cast<double2*>(static_cast<char*>(h->stage_misc.p) + pk.total);
-  HIPCHK(hipMemcpyAsync(res, e[L & 1], sizeof(double2), hipMemcpyDeviceToHost, h->st));
+  *tail = pk.total;
+  return MPS_OK;
+}
+
+mps_status mps_norm(mps_t h, double* norm2) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (!norm2) return fail(MPS_E_ARG, "norm2 is NULL");
+  const int L = h->L;
+  int maxdim = 1;
+  for (int b = 0; b <= L; ++b) maxdim = std::max(maxdim, h->bonds[b].dim());
+  const size_t esz = (size_t)maxdim * maxdim;
+  STCHK(ensure(h, h->norm_e0, esz * sizeof(double2)));
+  STCHK(ensure(h, h->norm_e1, esz * sizeof(double2)));
+  std::vector<double2*> eb(L + 1);
+  for (int b = 0; b <= L; ++b)
+    eb[b] = static_cast<double2*>((b & 1) ? h->norm_e1.p : h->norm_e0.p);
+  size_t tail = 0;
+  STCHK(left_envs(h, eb, sizeof(double2), &tail));
+  double2* res = reinterpret_cast<double2*>(static_cast<char*>(h->stage_misc.p) + tail);
+  HIPCHK(hipMemcpyAsync(res, eb[L], sizeof(double2), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
   *norm2 = res->x;
+  return MPS_OK;
+}
+
+mps_status mps_sample(mps_t h, int count, const double* uniforms, int* occ, double* prob) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (count < 0) return fail(MPS_E_ARG, "negative count");
+  if (count == 0) return MPS_OK;
+  if (!uniforms || !occ) return fail(MPS_E_ARG, "uniforms and occ are required");
+  const int L = h->L, N = h->N;
+  for (size_t k = 0; k < (size_t)count * L; ++k)
+    if (!(uniforms[k] >= 0.0 && uniforms[k] < 1.0)) return fail(MPS_E_ARG, "uniform %zu outside [0, 1)", k);
+  std::vector<int2> bmap((size_t)(L + 1) * (N + 1), make_int2(0, 0));
+  int maxblk = 1;
+  size_t etot = 0;
+  std::vector<size_t> eoff(L + 1);
+  for (int b = 0; b <= L; ++b) {
+    const Bond& B = h->bonds[b];
+    for (size_t i = 0; i < B.charge.size(); ++i) {
+      bmap[(size_t)b * (N + 1) + B.charge[i]] = make_int2(B.off[i], B.count[i]);
+      maxblk = std::max(maxblk, B.count[i]);
+    }
+    eoff[b] = etot;
+    etot += (size_t)B.dim() * B.dim();
+  }
+  if ((size_t)2 * maxblk * sizeof(double2) > kSampleLds)
+    return fail(MPS_E_ARG, "a charge block of %d exceeds the sampler's limit of %zu", maxblk,
+                kSampleLds / (2 * sizeof(double2)));
+  STCHK(ensure(h, h->envs, etot * sizeof(double2)));
+  std::vector<double2*> eb(L + 1);
+  for (int b = 0; b <= L; ++b) eb[b] = static_cast<double2*>(h->envs.p) + eoff[b];
+  size_t tail = 0;
+  STCHK(left_envs(h, eb, 0, &tail));
+  std::vector<int> ldb(L), lde(L);
+  std::vector<const double2*> sp(L), ep(L);
+  for (int s = 0; s < L; ++s) {
+    ldb[s] = h->bonds[s + 1].dim();
+    lde[s] = h->bonds[s].dim();
+    sp[s] = h->site[s];
+    ep[s] = eb[s];
+  }
+  Packer pk;
+  const size_t o_sp = pk.add(sp.data(), sp.size() * sizeof(double2*));
+  const size_t o_ep = pk.add(ep.data(), ep.size() * sizeof(double2*));
+  const size_t o_lb = pk.add(ldb.data(), ldb.size() * sizeof(int));
+  const size_t o_le = pk.add(lde.data(), lde.size() * sizeof(int));
+  const size_t o_bm = pk.add(bmap.data(), bmap.size() * sizeof(int2));
+  const size_t o_u = pk.add(uniforms, (size_t)count * L * sizeof(double));
+  const size_t o_occ = pk.add(nullptr, (size_t)count * L * sizeof(int));
+  const size_t o_pr = pk.add(nullptr, (size_t)count * sizeof(double));
+  STCHK(ensure(h, h->samp, pk.total));
+  // the environments' plan is still being copied from stage_misc
+  HIPCHK(hipStreamSynchronize(h->st));
+  STCHK(ensure_pin(h->stage_misc, pk.total));
+  pk.write(h->stage_misc.p);
+  HIPCHK(hipMemcpyAsync(h->samp.p, h->stage_misc.p, o_occ, hipMemcpyHostToDevice, h->st));
+  HIPCHK(launch_sample(at<const double2*>(h->samp, o_sp), at<int>(h->samp, o_lb), at<const double2*>(h->samp, o_ep),
+                       at<int>(h->samp, o_le), at<int2>(h->samp, o_bm), at<double>(h->samp, o_u),
+                       at<int>(h->samp, o_occ), at<double>(h->samp, o_pr), count, L, h->d, N, maxblk, h->st));
+  HIPCHK(hipMemcpyAsync(static_cast<char*>(h->stage_misc.p) + o_occ, at<char>(h->samp, o_occ), pk.total - o_occ,
+                        hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  const char* res = static_cast<const char*>(h->stage_misc.p);
+  const double* pr = reinterpret_cast<const double*>(res + o_pr);
+  for (int j = 0; j < count; ++j)
+    if (!(pr[j] >= 0.0)) return fail(MPS_E_NUMERIC, "sample %d met a vanished or non-finite marginal", j);
+  std::memcpy(occ, res + o_occ, (size_t)count * L * sizeof(int));
+  if (prob) std::memcpy(prob, pr, (size_t)count * sizeof(double));
   return MPS_OK;
 }
 

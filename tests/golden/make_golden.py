@@ -1,9 +1,10 @@
 """Writes the stored oracle results used by the full-size GPU parity test.
 
 Runs ONLY the CPU oracle (oracle/dense_mps.py) on the seeded workload from
-workloads/circuits.py and stores, as JSON text:
+workloads/circuits.py or workloads/hamiltonians.py and stores, as JSON text:
   * the amplitudes of 1024 occupation patterns drawn uniformly (seed 102 for
-    the 32-mode workload, 103 for the 64-mode one) plus the input pattern,
+    the 32-mode circuit, 103 for the 64-mode one, 104 and 105 for the XXZ and
+    Bose-Hubbard quenches) plus the input pattern,
   * <psi|psi> by full contraction,
   * every bond's right-charge histogram from the oracle's charge audit,
   * every gate's discarded weight and cut margin,
@@ -11,6 +12,8 @@ workloads/circuits.py and stores, as JSON text:
 
 Usage:  python tests/golden/make_golden.py L32_N16_d4_chi512
         python tests/golden/make_golden.py L64_N32_d4_chi256
+        python tests/golden/make_golden.py XXZ_L64_chi256_T10
+        python tests/golden/make_golden.py BH_L64_d4_chi256_T3
 """
 import json
 import os
@@ -23,13 +26,16 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 from oracle import dense_mps  # noqa: E402
-from workloads import circuits  # noqa: E402
+from workloads import circuits, hamiltonians  # noqa: E402
 
 WORKLOADS = {
     "L32_N16_d4_chi512": (lambda: circuits.config_plain_gpu(), 102),
     # the precision-form circuit (64 modes, 32 photons in even modes, 64 layers)
     # at a bond cap the oracle finishes in minutes
     "L64_N32_d4_chi256": (lambda: circuits.config_precision(seed=3, chi_max=256), 103),
+    # Hamiltonian time evolution (dense Trotter gates), the measured quenches
+    "XXZ_L64_chi256_T10": (hamiltonians.config_xxz_quench, 104),
+    "BH_L64_d4_chi256_T3": (hamiltonians.config_bose_hubbard_quench, 105),
 }
 
 
@@ -41,8 +47,7 @@ def main(name: str) -> None:
     m = dense_mps.DenseMPS(cfg["occupation"], d, chi_max=cfg["chi_max"], cutoff=cfg["cutoff"])
     t0 = time.time()
     for li, lay in enumerate(cfg["layers"]):
-        for g in lay:
-            m.apply_gate(g.site, g.u)
+        m.run(lay)
         print(f"layer {li + 1}/{len(cfg['layers'])} chi {max(m.bond_dims())} "
               f"{time.time() - t0:.0f} s", flush=True)
     pats = circuits.sample_patterns(L, N, d, 1024, pattern_seed)

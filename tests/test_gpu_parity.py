@@ -545,3 +545,100 @@ def test_dense_gate_charge_check(mps_cls):
     assert np.array_equal(m.amplitudes(pats), ref.amplitudes(pats))
     m.close()
     ref.close()
+
+
+# ------------------------------------------------------------------ sampling
+SAMPLE_MARGIN = 1e-9     # draws closer than this to a cumulative boundary may go either way
+
+
+def check_samples(m, ref_mps, u, norm_ref):
+    """GPU samples against the oracle's for the same uniforms: identical patterns
+    wherever the oracle's decision margins exceed SAMPLE_MARGIN, probabilities to
+    1e-10 relative, and every pattern valid with prob = |amplitude|^2 / norm."""
+    from oracle import sampling
+    pats, prob = m.sample(u)
+    rp, rprob, marg = sampling.mps_samples(ref_mps, u, margins=True)
+    clear = marg > SAMPLE_MARGIN
+    assert clear.mean() > 0.95
+    assert np.array_equal(pats[clear], rp[clear])
+    assert np.max(np.abs(prob[clear] - rprob[clear]) / rprob[clear]) <= 1e-10
+    assert (pats.sum(axis=1) == m.N).all() and pats.min() >= 0 and pats.max() < m.d
+    amp = m.amplitudes(pats)
+    assert np.max(np.abs(np.abs(amp) ** 2 / norm_ref - prob) / prob) <= 1e-10
+    return pats, prob
+
+
+def test_sample_exact_circuit_vs_oracle_and_permanents(mps_cls):
+    cfg = circuits.config_small_exact()
+    m, _ = run_gpu(mps_cls, cfg["occupation"], 5, cfg["gates"])
+    ref = dense_mps.DenseMPS(cfg["occupation"], 5).run(cfg["gates"])
+    u = np.random.default_rng(70).random((512, 8))
+    pats, prob = check_samples(m, ref, u, 1.0)
+    perm = np.array([abs(permanent.fock_amplitude(cfg["unitary"], cfg["occupation"], p)) ** 2 for p in pats])
+    assert np.max(np.abs(prob - perm)) <= 1e-12
+    m.close()
+
+
+def test_sample_truncated_and_tebd_states_vs_oracle(mps_cls):
+    from workloads import hamiltonians as ham
+    cfg = circuits.config_brickwork(12, 6, "first", 3, 12, 10, 1e-12, 21, "t")
+    m, _ = run_gpu(mps_cls, cfg["occupation"], 3, cfg["gates"], chi_max=10, cutoff=1e-12)
+    ref = dense_mps.DenseMPS(cfg["occupation"], 3, chi_max=10, cutoff=1e-12).run(cfg["gates"])
+    check_samples(m, ref, np.random.default_rng(71).random((400, 12)), ref.norm2())
+    m.close()
+    c = ham.config_tebd("bose_hubbard", 10, 4, [1, 2] * 5, 0.15, 5, 20, 1e-12, J=1.0, U=1.5, mu=0.1)
+    m, _ = run_dense(mps_cls, c)
+    ref = dense_mps.DenseMPS(c["occupation"], 4, chi_max=20, cutoff=1e-12).run(c["gates"])
+    check_samples(m, ref, np.random.default_rng(72).random((400, 10)), ref.norm2())
+    m.close()
+
+
+def test_sample_frequencies_on_gpu(mps_cls):
+    """20000 GPU draws from a 4-mode state follow |c|^2 / norm (chi-square)."""
+    rng = np.random.default_rng(3)
+    gates = [circuits.Gate(int(rng.integers(0, 3)), circuits.haar_unitary(2, int(rng.integers(1 << 30))))
+             for _ in range(10)]
+    m, _ = run_gpu(mps_cls, [1, 1, 1, 0], 4, gates)
+    pats = circuits.all_patterns(4, 3, 4)
+    st = fock.run([1, 1, 1, 0], 4, gates)
+    p_exact = np.array([abs(st.amplitude(p)) ** 2 for p in pats]) / st.norm2()
+    n = 20000
+    got, _ = m.sample(np.random.default_rng(5).random((n, 4)))
+    index = {tuple(int(x) for x in p): k for k, p in enumerate(pats)}
+    counts = np.bincount([index[tuple(int(x) for x in g)] for g in got], minlength=len(pats))
+    keep = p_exact * n >= 5
+    chi2 = float(np.sum((counts[keep] - n * p_exact[keep]) ** 2 / (n * p_exact[keep])))
+    dof = int(keep.sum()) - 1
+    assert chi2 < dof + 4.5 * np.sqrt(2 * dof) + 10, (chi2, dof)
+    m.close()
+
+
+def test_sample_full_32_mode_circuit_properties(mps_cls):
+    """At the bench size (L=32, chi_max=512) the oracle cannot run per draw: every
+    drawn pattern is valid and its probability equals |amplitude|^2 / norm from
+    the amplitude path, and the same uniforms give the same draws."""
+    cfg = circuits.config_plain_gpu()
+    m, _ = run_gpu(mps_cls, cfg["occupation"], 4, None, chi_max=512, cutoff=1e-12, layered=True,
+                   layers=cfg["layers"])
+    nrm = m.norm2()
+    u = np.random.default_rng(73).random((256, 32))
+    pats, prob = m.sample(u)
+    assert (pats.sum(axis=1) == 16).all() and pats.min() >= 0 and pats.max() < 4
+    amp = m.amplitudes(pats)
+    assert np.max(np.abs(np.abs(amp) ** 2 / nrm - prob) / prob) <= 1e-9
+    # the same uniforms give the same draws
+    again, prob2 = m.sample(u)
+    assert np.array_equal(again, pats) and np.array_equal(prob2, prob)
+    m.close()
+
+
+def test_sample_argument_errors(mps_cls):
+    from paper_2303_11409_amd import MPSError
+    m = mps_cls([1, 0, 1], 2)
+    with pytest.raises(MPSError):
+        m.sample(np.array([[0.1, 1.0, 0.2]]))
+    with pytest.raises(MPSError):
+        m.sample(np.array([[0.1, -0.1, 0.2]]))
+    pats, prob = m.sample(np.zeros((2, 3)))
+    assert pats.tolist() == [[1, 0, 1], [1, 0, 1]] and np.allclose(prob, 1.0)
+    m.close()

@@ -168,16 +168,17 @@ def config_bose_hubbard(L: int = 64, d: int = 4, steps: int = 40, dt: float = 0.
 
 def config_xxz_quench() -> dict:
     """The measured XXZ workload: L = 64, Neel state (32 up spins), J = 1,
-    Delta = 0.5, 40 second-order steps of dt = 0.05 (T = 2), chi_max = 256,
-    cutoff 1e-12."""
-    return config_xxz(L=64, steps=40, dt=0.05, chi_max=256, delta=0.5, cutoff=1e-12)
+    Delta = 0.5, 200 second-order steps of dt = 0.05 (T = 10; 12632 gates in
+    401 layers), chi_max = 256 (reached near T = 7), cutoff 1e-12."""
+    return config_xxz(L=64, steps=200, dt=0.05, chi_max=256, delta=0.5, cutoff=1e-12)
 
 
 def config_bose_hubbard_quench() -> dict:
-    """The measured Bose-Hubbard workload: L = 64, unit filling (64 bosons),
-    d = 4, J = 1, U = 2, 20 second-order steps of dt = 0.05 (T = 1),
-    chi_max = 256, cutoff 1e-12."""
-    return config_bose_hubbard(L=64, d=4, steps=20, dt=0.05, chi_max=256, J=1.0, U=2.0, cutoff=1e-12)
+    """The measured Bose-Hubbard workload: L = 64, density wave |2,0,2,0,...>
+    (64 bosons), d = 4, J = 1, U = 2, 60 second-order steps of dt = 0.05
+    (T = 3; 3812 gates in 121 layers), chi_max = 256 (reached near T = 1.5),
+    cutoff 1e-12."""
+    return config_tebd("bose_hubbard", 64, 4, [2, 0] * 32, 0.05, 60, 256, 1e-12, J=1.0, U=2.0)
 
 
 def random_charge_conserving(d: int, seed: int, unitary: bool = True) -> np.ndarray:
