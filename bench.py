@@ -35,29 +35,36 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/cl
 
 # HBM bytes per launch of jacobi_block_step on this workload, from two
 # rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline
-# --batch-copies 0 --mix-circuits 0 --no-chi2048 --serve-seconds 0`
+# --batch-copies 0 --mix-circuits 0 --no-chi2048 --serve-seconds 0 --samples 0
+# --no-tebd`
 # (FETCH_SIZE, WRITE_SIZE; mean over the launches) scaled by the same counters
 # on a plain 256 MiB copy (`bench.py --copy-probe`: FETCH_SIZE reads 131085.2
 # KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99982 and writes
-# by 1).  Valid only for the Jacobi source (csrc/jacobi.hip) it was taken on.
+# by 1).  Valid only for the Jacobi source (csrc/jacobi.hip) and the inner
+# sweep count per visit (kMaxInnerSweeps in csrc/runtime.cpp) it was taken on.
 MEASURED_TRAFFIC = {
     "kernels_sha256": "822a403be05d76fe4454846b3c50092334887d34b1bb599996fd3e18b69e21e3",
-    "fetch_kib": 21414.034, "write_kib": 35444.209,
+    "max_inner": 1,
+    "fetch_kib": 25474.587, "write_kib": 37976.814,
     "fetch_scale": 262144.0 / 131085.208, "write_scale": 1.0,
 }
 
 
 def measured_traffic():
-    """Bytes per launch from the counters, or None once the kernel source changed."""
+    """Bytes per launch from the counters, or None once the kernel source or its
+    inner sweep count changed."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2303_11409_amd", "csrc", "jacobi.hip")
+    import re
+    csrc = os.path.join(ROOT, "paper_2303_11409_amd", "csrc")
     try:
-        with open(src, "rb") as f:
+        with open(os.path.join(csrc, "jacobi.hip"), "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()
+        with open(os.path.join(csrc, "runtime.cpp")) as f:
+            inner = re.search(r"kMaxInnerSweeps = (\d+);", f.read())
     except OSError:
         return None
     t = MEASURED_TRAFFIC
-    if sha != t["kernels_sha256"]:
+    if sha != t["kernels_sha256"] or inner is None or int(inner.group(1)) != t["max_inner"]:
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 METRIC = "gate applies/s + sector-GEMM TFLOP/s at χ=2048 vs plain; p50/p99 latency"
