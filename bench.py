@@ -43,9 +43,9 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/cl
 # by 1).  Valid only for the Jacobi source (csrc/jacobi.hip) and the inner
 # sweep count per visit (kMaxInnerSweeps in csrc/runtime.cpp) it was taken on.
 MEASURED_TRAFFIC = {
-    "kernels_sha256": "822a403be05d76fe4454846b3c50092334887d34b1bb599996fd3e18b69e21e3",
+    "kernels_sha256": "6416f5c5774462e1be2ce3334c18593b029039258c518194238463efb8d0be71",
     "max_inner": 1,
-    "fetch_kib": 25474.587, "write_kib": 37976.814,
+    "fetch_kib": 16572.336, "write_kib": 21338.777,
     "fetch_scale": 262144.0 / 131085.208, "write_scale": 1.0,
 }
 

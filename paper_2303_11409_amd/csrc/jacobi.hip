@@ -20,11 +20,12 @@ namespace u1mps {
 // rounding floor of the sector.  Vectors are grouped in blocks of kJB; a
 // round-robin (circle method) schedule over the blocks pairs every two
 // blocks once per sweep.  For a block pair the workgroup forms the Gram
-// matrix G = X X^H of its 2 kJB vectors, applies the same rotations to G
-// (G <- U G U^H) until its off-diagonal is below tolerance, accumulating
-// W = prod U, and finally rotates the vectors, X <- W X.  Convergence is
-// always judged on a Gram matrix freshly formed from the vectors, so the
-// stopping rule is the same pairwise-cosine test as for the unblocked method.
+// matrix G = X X^H of its 2 kJB vectors, applies rotations to G
+// (G <- U G U^H; a bounded number of sweeps over its pairs, not necessarily
+// to tolerance), accumulating W = prod U, and rotates the vectors, X <- W X.
+// Convergence is always judged on a Gram matrix freshly formed from the
+// vectors, so the stopping rule is the same pairwise-cosine test as for the
+// unblocked method; the outer sweeps carry the iteration to it.
 // With J the product of all rotations, J X = S Y with orthonormal rows Y:
 //   wide (X = Theta):    V^dagger = Y, the normalised vectors;
 //   tall (X = Theta^T):  V^dagger = conj(J), accumulated in A (c x c) from I.
@@ -310,9 +311,9 @@ __device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 1], double tol
   return block_any(f, anyf, parity);
 }
 
-// Rotations of the Gram matrix gs (in LDS) until no pair exceeds the
-// threshold; W accumulates the product.  The caller has established that
-// some pair is above it.  A round-robin step rotates 16 disjoint pairs at
+// Rotations of the Gram matrix gs (in LDS): up to max_inner sweeps, fewer if
+// no pair exceeds the threshold any more; W accumulates the product.  The
+// caller has established that some pair is above it.  A round-robin step rotates 16 disjoint pairs at
 // once, G <- U G U^H and W <- U W with U block diagonal over the pairs.
 // Thread t = 16 A + B owns the 2 x 2 blocks (rows of pair A) x (columns of
 // pair B): it computes the rotations of pairs A and B itself from the
@@ -320,7 +321,8 @@ __device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 1], double tol
 // staging tile, idle during the eig) and updates its W block in place, so a
 // step needs one barrier and no exchange of rotations.  After each sweep one
 // parallel test over all pairs replaces the sweep that would find nothing to
-// rotate (it would leave G and W unchanged).  The final G is left in gs.
+// rotate (it would leave G and W unchanged); after the last allowed sweep the
+// test is skipped.  The final G is left in gs.
 __device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*g1)[kJP + 1], double2 (*ws)[kJP + 1],
                              double tol, double floor_g, int max_inner, int4* anyf, int& parity) {
   const int tid = threadIdx.x;
@@ -356,7 +358,7 @@ __device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*g1)[kJP + 1], dou
       cur = nxt;
       nxt = t;
     }
-    if (!jac_any_above(cur, tol, floor_g, anyf, parity)) break;
+    if (inner + 1 < max_inner && !jac_any_above(cur, tol, floor_g, anyf, parity)) break;
   }
   // a sweep has an odd number of steps: an odd sweep count leaves G in g1
   if (cur != gs)
@@ -366,15 +368,17 @@ __device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*g1)[kJP + 1], dou
 
 // One round-robin step for every active sector: one workgroup per block pair.
 //
-// A block pair that fails the convergence test is rotated in two passes.
-// Pass 0 diagonalises its Gram matrix only down to kJacLoose relative
-// off-diagonal or the Gram's own rounding level (kJacNoise * eps * max
-// diagonal): rotations of G itself carry errors of order eps * max|G|, which
+// A block pair that fails the convergence test is rotated once per visit,
+// with one of two thresholds.  While some pair of its Gram matrix is above
+// kJacLoose relative off-diagonal (and above the Gram's own rounding level,
+// kJacNoise * eps * max diagonal), the rotations of G use those coarse
+// thresholds: rotations of G itself carry errors of order eps * max|G|, which
 // would leave the smallest vectors of the pair with cosines of
-// eps * s_max^2 / (s_p s_q) if pursued further.  Pass 1 forms the Gram matrix
-// afresh from the rotated vectors; it is then nearly diagonal, its rotations
-// are small, their errors are relative to each vector's own norm, and it is
-// driven to the full tolerance.
+// eps * s_max^2 / (s_p s_q) if pursued further.  Only a Gram matrix with
+// nothing above the coarse thresholds is rotated to the full tolerance; it is
+// then nearly diagonal, its rotations are small and their errors are relative
+// to each vector's own norm.  A visit that rotated at the coarse thresholds
+// ends there: the next sweep forms the Gram matrix afresh.
 constexpr double kJacLoose = 1e-8;
 constexpr double kJacNoise = 64.0;
 
@@ -441,7 +445,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
     const bool need = jac_any_above(gs, tol, floor_g, anyf, parity);
     if (!need) break;
     if (pass == 0 && tid == 0) atomicAdd(&st[sid].rot_this_sweep, 1);
-    // ---- diagonalise G by rotations, W = accumulated product
+    // ---- rotate G (at most max_inner sweeps), W = accumulated product
     for (int e = tid; e < kJP * kJP; e += blockDim.x) {
       const int r = e / kJP, c = e % kJP;
       ws[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
@@ -462,6 +466,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
     if (tid == 0) atomicAdd(&st[sid].apply_units, (unsigned long long)nv * nv * (len + (tall ? n : 0)));
     fresh = false;
     __syncthreads();
+    if (pass == 0) break;
   }
   // latest squared norms of the pair's vectors (the Gram diagonal; after a
   // rotation the rotated Gram's diagonal), for the next sweep's ordering
