@@ -642,3 +642,51 @@ def test_sample_argument_errors(mps_cls):
     pats, prob = m.sample(np.zeros((2, 3)))
     assert pats.tolist() == [[1, 0, 1], [1, 0, 1]] and np.allclose(prob, 1.0)
     m.close()
+
+
+def _tebd_vs_stored(mps_cls, name, make):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle results {name}.json not present")
+    ref = json.load(open(path))
+    cfg = make()
+    m, disc = run_dense(mps_cls, cfg)
+    margins = [x for x in ref["margin"] if x is not None]
+    odisc = np.array(ref["discarded"])
+    assert disc.shape == odisc.shape
+    assert np.max(np.abs(disc - odisc)) <= 1e-12
+    # FP64 singular values carry errors of order 1e-13 of s_0: a stored margin
+    # above 1e-11 cannot flip a cut
+    if min(margins) > 1e-11:
+        for b in range(cfg["L"] + 1):
+            exp = {int(k): v for k, v in ref["bond_charges"][b].items()}
+            assert m.bond_sectors(b) == exp, b
+    pats = np.array(ref["patterns"], dtype=np.int32)
+    amp = np.array(ref["amp_re"]) + 1j * np.array(ref["amp_im"])
+    close_amps(m.amplitudes(pats), amp)
+    assert abs(m.norm2() - ref["norm2"]) <= 1e-9 * ref["norm2"]
+    for b, lam in ref["lambda_center"].items():
+        got = np.sort(m.bond_lambda(int(b)))[::-1]
+        lam = np.array(lam)
+        assert got.shape == lam.shape and np.max(np.abs(got - lam)) <= TOL * lam[0], b
+    m.close()
+    return min(margins)
+
+
+def test_tebd_xxz_quench_vs_stored_oracle(mps_cls):
+    """The measured XXZ quench (L=64, chi_max=256, 12632 dense gates, the launch
+    configuration the bench times) against the oracle's stored results: every
+    gate's discarded weight, every bond's charges (the closest stored cut margin
+    is far above FP64 rounding), 1025 amplitudes, the norm and the central
+    Schmidt values."""
+    from workloads import hamiltonians as ham
+    _tebd_vs_stored(mps_cls, "XXZ_L64_chi256_T10", ham.config_xxz_quench)
+
+
+def test_tebd_bose_hubbard_quench_vs_stored_oracle(mps_cls):
+    """The measured Bose-Hubbard quench (L=64, d=4, chi_max=256, 3812 dense gates)
+    against the oracle's stored results, as for the XXZ quench."""
+    from workloads import hamiltonians as ham
+    _tebd_vs_stored(mps_cls, "BH_L64_d4_chi256_T3", ham.config_bose_hubbard_quench)
