@@ -111,6 +111,25 @@ def cpu_baseline(cfg, seconds: float):
                       f"SVD per gate; {el:.1f} s"}
 
 
+def sample_flops(m, pats):
+    """Algorithmic flops of sample_kernel for the drawn patterns (see the JSON note)."""
+    L, d = m.L, m.d
+    blocks = [m.bond_sectors(b) for b in range(L + 1)]
+    tot = 0
+    for p in pats.tolist():
+        c = 0
+        for s in range(L - 1, -1, -1):
+            nc = blocks[s + 1].get(c, 0)
+            for i in range(d):
+                nr = blocks[s].get(c + i, 0)
+                if nr:
+                    tot += 8 * nr * nc + 8 * nr * nr
+            nr = blocks[s].get(c + p[s], 0)
+            tot += 8 * nr * nc
+            c += p[s]
+    return float(tot)
+
+
 def run_tebd(MPS, dev, cfg):
     """One Hamiltonian time evolution (dense Trotter gates, one layer per call)."""
     layers = [([g.site for g in lay], [g.g4 for g in lay]) for lay in cfg["layers"]]
@@ -369,11 +388,16 @@ def main() -> int:
         ts = time.perf_counter()
         spats, sprob = states[0].sample(us)
         sel = time.perf_counter() - ts
+        sflops = sample_flops(states[0], spats)
         sampling = {"workload": f"{args.samples} exact samples (chain rule over the left environments, "
                                 "uniforms seed 7) of the final state of one step, host-to-host",
                     "samples": args.samples, "seconds": sel, "value": args.samples / sel, "unit": "samples/s",
                     "distinct_patterns": int(len({tuple(p) for p in spats.tolist()})),
-                    "max_prob": float(sprob.max())}
+                    "max_prob": float(sprob.max()),
+                    "kernel_flops": sflops,
+                    "kernel_flops_note": "sample_kernel's algorithmic work: per sample and mode, 8 n_r n_c "
+                                         "(w = B v) + 8 n_r^2 (w^H E w) per admissible occupation, plus one more "
+                                         "B v for the drawn one; n = charge-block sizes along the drawn path"}
         log(f"  {args.samples / sel:.0f} samples/s")
     norm_loss = 1.0 - states[0].norm2()
     max_chi = max(states[0].bond_dims())

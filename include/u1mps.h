@@ -241,7 +241,8 @@ mps_status mps_norm(mps_t h, double* norm2);
  *   occ    out, count*L row-major occupations;
  *   prob   out, may be NULL: |c_i|^2 / <psi|psi> of each drawn pattern.
  * The left environments of every bond are held in device memory during the
- * call (as many complex entries as the squared bond dimensions, summed).
+ * call only (as many complex entries as the squared bond dimensions, summed:
+ * about the size of the state) and released before it returns.
  * Errors: MPS_E_ARG (a uniform outside [0, 1), a charge block above 2048),
  * MPS_E_NUMERIC (a vanished or non-finite marginal), MPS_E_NOMEM,
  * MPS_E_DEVICE. */

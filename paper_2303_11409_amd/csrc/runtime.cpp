@@ -1484,6 +1484,10 @@ mps_status mps_sample(mps_t h, int count, const double* uniforms, int* occ, doub
   HIPCHK(hipMemcpyAsync(static_cast<char*>(h->stage_misc.p) + o_occ, at<char>(h->samp, o_occ), pk.total - o_occ,
                         hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
+  // the environments are as large as the state: give them back after each call
+  dfree(h, h->envs.p);
+  h->envs.p = nullptr;
+  h->envs.cap = 0;
   const char* res = static_cast<const char*>(h->stage_misc.p);
   const double* pr = reinterpret_cast<const double*>(res + o_pr);
   for (int j = 0; j < count; ++j)

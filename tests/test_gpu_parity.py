@@ -690,3 +690,34 @@ def test_tebd_bose_hubbard_quench_vs_stored_oracle(mps_cls):
     against the oracle's stored results, as for the XXZ quench."""
     from workloads import hamiltonians as ham
     _tebd_vs_stored(mps_cls, "BH_L64_d4_chi256_T3", ham.config_bose_hubbard_quench)
+
+
+def test_dense_and_sampling_edges(mps_cls):
+    """Edges: an empty dense layer, a two-site chain, the vacuum, a zero-count
+    sample, a fully occupied d = 2 chain (one pattern) and draws at u -> 1."""
+    from workloads import hamiltonians as ham
+    g = ham.trotter_gate(ham.xxz_bond(1.0, 0.4, 0.0, 1.0, 1.0), 0.7)
+    m = mps_cls([1, 0], 2)
+    assert m.apply_layer_dense([], []).shape == (0,)
+    m.apply_layer_dense([0], [g])
+    st = fock.FockState([1, 0], 2)
+    st.apply_dense(0, g)
+    pats = np.array([[1, 0], [0, 1]])
+    assert np.max(np.abs(m.amplitudes(pats) - np.array([st.amplitude(p) for p in pats]))) < 1e-14
+    occ, prob = m.sample(np.zeros((0, 2)))
+    assert occ.shape == (0, 2) and prob.shape == (0,)
+    occ, prob = m.sample(np.array([[0.0, 0.0], [0.0, np.nextafter(1.0, 0.0)]]))
+    p10 = abs(st.amplitude([1, 0])) ** 2
+    # mode 1 is drawn first: occupation 0 (pattern (1,0)) below u = P(1,0), else 1
+    assert occ.tolist() == [[1, 0], [0, 1]]
+    assert abs(prob[0] - p10) < 1e-14 and abs(prob[1] - (1 - p10)) < 1e-14
+    m.close()
+    v = mps_cls([0, 0, 0], 3)
+    occ, prob = v.sample(np.random.default_rng(0).random((4, 3)))
+    assert (occ == 0).all() and np.allclose(prob, 1.0)
+    v.close()
+    full = mps_cls([1, 1, 1, 1], 2)
+    full.apply_layer_dense([0, 2], [g, g])
+    occ, prob = full.sample(np.random.default_rng(1).random((3, 4)))
+    assert (occ == 1).all() and np.allclose(prob, 1.0, atol=1e-14)
+    full.close()
