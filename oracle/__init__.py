@@ -24,7 +24,9 @@ fock       -- brute-force state vector in the N-photon, occupation<d sector.
 dense_mps  -- dense (no-symmetry) MPS TEBD with the same truncation rule as
               the GPU path, amplitudes (E1), full-contraction norm, and an
               independent charge audit of every bond; gates given as mode
-              unitaries or as dense two-site matrices (Hamiltonian TEBD).
+              unitaries or as dense two-site matrices (Hamiltonian TEBD); with a
+              modulus n the charge is the particle number mod n (Z_n) and the
+              audit tracks the unitary omega^Q instead of Q.
 sampling   -- exact chain-rule sampling of output patterns, by brute force
               over a probability table and from the dense MPS's environments.
 """

@@ -101,13 +101,17 @@ class DenseMPS:
     """Dense MPS of L modes with local dimension d, started in a Fock product state."""
 
     def __init__(self, occupation: Sequence[int], d: int, chi_max: int = 0,
-                 cutoff: float = 0.0, zero_tol: float = 1e-13, form: str = "hastings"):
+                 cutoff: float = 0.0, zero_tol: float = 1e-13, form: str = "hastings",
+                 modulus: int = 0):
         occ = [int(x) for x in occupation]
         if any(o < 0 or o >= d for o in occ):
             raise ValueError("occupation outside 0..d-1")
         if form not in ("hastings", "vidal"):
             raise ValueError(form)
         self.L, self.d, self.N = len(occ), d, sum(occ)
+        # modulus 0: the charge is the particle number (U(1)); n >= 2: the
+        # particle number mod n (Z_n), audited through the unitary omega^Q
+        self.modulus = int(modulus)
         self.chi_max, self.cutoff, self.zero_tol, self.form = chi_max, cutoff, zero_tol, form
         self.t: List[np.ndarray] = []          # B (hastings) or Gamma (vidal)
         for o in occ:
@@ -116,8 +120,12 @@ class DenseMPS:
             self.t.append(a)
         self.lam: List[np.ndarray] = [np.ones(1) for _ in range(self.L + 1)]
         left = np.concatenate([[0], np.cumsum(occ)])
-        self.q: List[np.ndarray] = [np.array([[float(left[b])]], dtype=np.complex128)
-                                    for b in range(self.L + 1)]
+        if self.modulus:
+            w = np.exp(2j * np.pi / self.modulus)
+            self.q: List[np.ndarray] = [np.array([[w ** int(left[b])]], dtype=np.complex128)
+                                        for b in range(self.L + 1)]
+        else:
+            self.q = [np.array([[float(left[b])]], dtype=np.complex128) for b in range(self.L + 1)]
         self.records: List[GateRecord] = []
 
     # ------------------------------------------------------------------ update
@@ -157,11 +165,14 @@ class DenseMPS:
             self.t[s + 1] = (vk.reshape(k, d, chr_) / self.lam[s + 2][None, None, :])
         self.lam[s + 1] = sv[:k].copy()
         # charge audit of the new bond s+1
-        qrow = np.kron(self.q[s], np.eye(d)) + np.kron(np.eye(chl), np.diag(np.arange(d)))
         uk = uu[:, :k]
+        if self.modulus:
+            w = np.exp(2j * np.pi / self.modulus)
+            qrow = np.kron(self.q[s], np.diag(w ** np.arange(d)))
+        else:
+            qrow = np.kron(self.q[s], np.eye(d)) + np.kron(np.eye(chl), np.diag(np.arange(d)))
         self.q[s + 1] = uk.conj().T @ qrow @ uk
-        ev = np.linalg.eigvalsh(self.q[s + 1])
-        ok = bool(np.all(np.abs(ev - np.round(ev)) <= 1e-6))
+        ok = self.audit_clean(s + 1)
         rec = GateRecord(site=s, kept=k, discarded=cut.discarded, margin=cut.margin,
                          leak=before - after, audit_ok=ok)
         self.records.append(rec)
@@ -221,15 +232,29 @@ class DenseMPS:
     def bond_dims(self) -> List[int]:
         return [self.lam[b].size for b in range(self.L + 1)]
 
+    def _left_charges(self, bond: int) -> np.ndarray:
+        """Left charges of the Schmidt vectors of a bond as real numbers (integers
+        when the audit is clean): eigenvalues of the left particle number, or
+        for Z_n the phases of omega^Q times n / (2 pi), taken in [0, n)."""
+        if self.modulus:
+            ev = np.linalg.eigvals(self.q[bond])
+            return np.mod(np.angle(ev) * self.modulus / (2 * np.pi), self.modulus)
+        return np.linalg.eigvalsh(self.q[bond])
+
     def bond_charges(self, bond: int) -> Dict[int, int]:
-        """Right-charge histogram of a bond from the charge audit (Eq. (E3))."""
-        ev = np.linalg.eigvalsh(self.q[bond])
+        """Right-charge histogram of a bond from the charge audit (Eq. (E3));
+        for Z_n the right charge is taken mod n."""
         hist: Dict[int, int] = {}
-        for e in ev:
+        for e in self._left_charges(bond):
             c = self.N - int(round(float(e)))
+            if self.modulus:
+                c %= self.modulus
             hist[c] = hist.get(c, 0) + 1
         return dict(sorted(hist.items()))
 
     def audit_clean(self, bond: int, tol: float = 1e-6) -> bool:
-        ev = np.linalg.eigvalsh(self.q[bond])
-        return bool(np.all(np.abs(ev - np.round(ev)) <= tol))
+        ev = self._left_charges(bond)
+        dev = np.abs(ev - np.round(ev))
+        if self.modulus:
+            dev = np.minimum(dev, np.abs(ev - self.modulus))
+        return bool(np.all(dev <= tol))

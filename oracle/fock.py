@@ -10,6 +10,7 @@ cutoff P_d G P_d).  No tensor network is involved.
 """
 from __future__ import annotations
 
+import itertools
 from typing import Dict, List, Sequence, Tuple
 
 import numpy as np
@@ -18,14 +19,24 @@ from . import twomode
 
 
 class FockState:
-    def __init__(self, occupation: Sequence[int], d: int):
+    """modulus 0: the basis holds every string with the input's particle number;
+    n >= 2: every string whose particle number equals the input's mod n (a
+    Z_n charge)."""
+
+    def __init__(self, occupation: Sequence[int], d: int, modulus: int = 0):
         self.L = len(occupation)
         self.d = d
         self.N = int(sum(occupation))
+        self.modulus = int(modulus)
         if max(occupation) >= d:
             raise ValueError("input occupation exceeds the local cutoff")
         self.basis: List[Tuple[int, ...]] = []
-        self._enumerate([], 0, self.N)
+        if self.modulus:
+            for t in itertools.product(range(d), repeat=self.L):
+                if sum(t) % self.modulus == self.N % self.modulus:
+                    self.basis.append(tuple(t))
+        else:
+            self._enumerate([], 0, self.N)
         self.index: Dict[Tuple[int, ...], int] = {t: i for i, t in enumerate(self.basis)}
         self.psi = np.zeros(len(self.basis), dtype=np.complex128)
         self.psi[self.index[tuple(int(x) for x in occupation)]] = 1.0
@@ -96,7 +107,7 @@ class FockState:
         of the state matrix psi[(left string), (right string)] with that c."""
         blocks: Dict[int, Dict[Tuple[int, ...], Dict[Tuple[int, ...], complex]]] = {}
         for i, t in enumerate(self.basis):
-            c = sum(t[bond:])
+            c = sum(t[bond:]) % self.modulus if self.modulus else sum(t[bond:])
             blocks.setdefault(c, {}).setdefault(t[:bond], {})[t[bond:]] = self.psi[i]
         ranks: Dict[int, int] = {}
         smax = 0.0
@@ -120,9 +131,9 @@ class FockState:
         return ranks
 
 
-def run(occupation: Sequence[int], d: int, gates) -> FockState:
+def run(occupation: Sequence[int], d: int, gates, modulus: int = 0) -> FockState:
     """Gates with .u (mode unitary) or .g4 (dense two-site matrix)."""
-    st = FockState(occupation, d)
+    st = FockState(occupation, d, modulus)
     for g in gates:
         if hasattr(g, "g4"):
             st.apply_dense(g.site, g.g4)

@@ -721,3 +721,25 @@ def test_dense_and_sampling_edges(mps_cls):
     occ, prob = full.sample(np.random.default_rng(1).random((3, 4)))
     assert (occ == 1).all() and np.allclose(prob, 1.0, atol=1e-14)
     full.close()
+
+
+def test_precision_form_with_dense_gates(mps_cls):
+    """The split-BF16 form takes dense Trotter gates like mode unitaries: a
+    Bose-Hubbard evolution with an active cut stays within the accumulated
+    product bound of the plain form's amplitudes, and both agree with the
+    oracle's norm to that bound."""
+    from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
+    from workloads import hamiltonians as ham
+    cfg = ham.config_tebd("bose_hubbard", 10, 4, [1, 2] * 5, 0.15, 5, 20, 1e-12, J=1.0, U=1.5, mu=0.1)
+    p, _ = run_dense(mps_cls, cfg)
+    s = mps_cls(cfg["occupation"], 4, chi_max=20, cutoff=1e-12, form=FORM_SPLIT_BF16X3)
+    for lay in cfg["layers"]:
+        s.apply_layer_dense([g.site for g in lay], [g.g4 for g in lay])
+    pats = circuits.sample_patterns(10, 15, 4, 300, 8)
+    a, b = p.amplitudes(pats), s.amplitudes(pats)
+    ng = len(cfg["gates"])
+    err = float(np.linalg.norm(a - b) / np.linalg.norm(a))
+    assert err <= ng * 1.1e-5, err
+    assert abs(s.norm2() - p.norm2()) <= ng * 1.1e-5 * p.norm2()
+    p.close()
+    s.close()

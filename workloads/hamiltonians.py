@@ -14,6 +14,17 @@ besides linear optics:
       H = -J sum_i (b_i^+ b_{i+1} + b_{i+1}^+ b_i) + U/2 sum_i n_i (n_i - 1) - mu sum_i n_i,
   with occupations 0..d-1 per site (the MPS local cutoff d).
 
+Two models with a discrete Abelian charge (Z_n, the particle number mod n;
+the paper's general Abelian symmetries, Sec. I) and local dimension d = n:
+
+* the transverse-field Ising chain, H = -J sum_i X_i X_{i+1} - h sum_i Z_i,
+  Z = diag(1, -1) on occupations (0, 1): X X changes the occupation count by
+  0 or 2, so its parity (Z_2) is conserved;
+* the Z_n clock chain in its charge basis, tau = diag(omega^p) (omega =
+  exp(2 pi i / n)) and sigma the shift |p> -> |p + 1 mod n>:
+  H = -J sum_i (sigma_i sigma_{i+1}^dagger + h.c.) - f sum_i (tau_i + tau_i^dagger),
+  which conserves sum_i p_i mod n.
+
 Bond Hamiltonians h_i on sites (i, i+1) carry the bond's coupling plus the
 on-site terms shared between the two bonds of each site (half each; an end
 site's terms go fully to its only bond), so sum_i h_i = H.  Matrices are
@@ -73,6 +84,27 @@ def bose_hubbard_bond(d: int, J: float, U: float, mu: float = 0.0, w_left: float
     return h.astype(np.complex128)
 
 
+def ising_bond(J: float, h: float, w_left: float = 0.5, w_right: float = 0.5) -> np.ndarray:
+    """h for one bond of the transverse-field Ising chain (d = 2)."""
+    x = np.array([[0.0, 1.0], [1.0, 0.0]])
+    z = np.diag([1.0, -1.0])
+    one = np.eye(2)
+    return (-J * np.kron(x, x) - h * (w_left * np.kron(z, one) + w_right * np.kron(one, z))).astype(np.complex128)
+
+
+def clock_bond(n: int, J: float, f: float, w_left: float = 0.5, w_right: float = 0.5) -> np.ndarray:
+    """h for one bond of the Z_n clock chain in the charge basis (d = n)."""
+    w = np.exp(2j * np.pi / n)
+    sig = np.zeros((n, n), dtype=np.complex128)
+    for p in range(n):
+        sig[(p + 1) % n, p] = 1.0
+    tau = np.diag(w ** np.arange(n))
+    one = np.eye(n)
+    hop = np.kron(sig, sig.conj().T)
+    field = tau + tau.conj().T
+    return -J * (hop + hop.conj().T) - f * (w_left * np.kron(field, one) + w_right * np.kron(one, field))
+
+
 def trotter_gate(h: np.ndarray, t: float, imaginary: bool = False) -> np.ndarray:
     """exp(-i t h), or exp(-t h) with imaginary."""
     return scipy.linalg.expm((-t if imaginary else -1j * t) * h)
@@ -90,6 +122,12 @@ def bond_hamiltonians(model: str, L: int, d: int, **p) -> List[np.ndarray]:
             out.append(xxz_bond(p.get("J", 1.0), p.get("delta", 1.0), p.get("hz", 0.0), wl, wr))
         elif model == "bose_hubbard":
             out.append(bose_hubbard_bond(d, p.get("J", 1.0), p.get("U", 1.0), p.get("mu", 0.0), wl, wr))
+        elif model == "ising":
+            if d != 2:
+                raise ValueError("the Ising chain has d = 2")
+            out.append(ising_bond(p.get("J", 1.0), p.get("h", 1.0), wl, wr))
+        elif model == "clock":
+            out.append(clock_bond(d, p.get("J", 1.0), p.get("f", 1.0), wl, wr))
         else:
             raise ValueError(model)
     return out
@@ -147,7 +185,8 @@ def config_tebd(model: str, L: int, d: int, occupation: Sequence[int], dt: float
     if len(occ) != L or any(o < 0 or o >= d for o in occ):
         raise ValueError("occupation must have L entries in 0..d-1")
     layers = trotter_layers(hb, dt, steps, order=order, imaginary=imaginary)
-    return {"model": model, "L": L, "d": d, "occupation": occ, "n_photons": sum(occ), "dt": dt,
+    modulus = d if model in ("ising", "clock") else 0
+    return {"model": model, "L": L, "d": d, "occupation": occ, "n_photons": sum(occ), "modulus": modulus, "dt": dt,
             "steps": steps, "order": order, "imaginary": imaginary, "params": dict(p),
             "chi_max": chi_max, "cutoff": cutoff, "layers": layers,
             "gates": [g for lay in layers for g in lay]}
@@ -179,6 +218,20 @@ def config_bose_hubbard_quench() -> dict:
     (T = 3; 3812 gates in 121 layers), chi_max = 256 (reached near T = 1.5),
     cutoff 1e-12."""
     return config_tebd("bose_hubbard", 64, 4, [2, 0] * 32, 0.05, 60, 256, 1e-12, J=1.0, U=2.0)
+
+
+def config_ising_quench() -> dict:
+    """The measured Z_2 workload: transverse-field Ising chain, L = 64, all
+    spins in occupation 0, J = 1, h = 0.5, 200 second-order steps of dt = 0.05
+    (T = 10; 12632 gates), chi_max = 256, cutoff 1e-12."""
+    return config_tebd("ising", 64, 2, [0] * 64, 0.05, 200, 256, 1e-12, J=1.0, h=0.5)
+
+
+def config_clock_quench() -> dict:
+    """The measured Z_3 workload: Z_3 clock chain, L = 64, all sites in charge
+    0, J = 1, f = 0.3, 60 second-order steps of dt = 0.05 (T = 3; 3812 gates),
+    chi_max = 256, cutoff 1e-12."""
+    return config_tebd("clock", 64, 3, [0] * 64, 0.05, 60, 256, 1e-12, J=1.0, f=0.3)
 
 
 def random_charge_conserving(d: int, seed: int, unitary: bool = True) -> np.ndarray:
