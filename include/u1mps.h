@@ -94,6 +94,14 @@ typedef struct {
  *              accumulated in FP32 (relative error of order 1e-5 per
  *              product); the gate mix, the Jacobi SVD, the cut and the update
  *              stay FP64.
+ *   modulus    0 (default): U(1), the charge of Eqs. (E2)-(E4) is the particle
+ *              number.  n >= 2: a discrete Abelian charge Z_n (the paper's
+ *              general Abelian symmetries, Sec. I), the particle number mod n,
+ *              with d == n: every local occupation is a distinct charge, bond
+ *              charges lie in 0..n-1, the charge balance of Eq. (E4) holds mod
+ *              n (bond 0 carries n_photons mod n), and every left/right charge
+ *              pair of a site is allowed with occupation (cL - cR) mod n.  A
+ *              Z_n state takes dense gates only (mps_apply_layer_dense).
  * The kept count is K = max(1, min(chi_max, K_eps, K_zero)). */
 typedef enum { MPS_FORM_PLAIN_C128 = 0, MPS_FORM_SPLIT_BF16X3 = 1 } mps_form;
 
@@ -104,6 +112,9 @@ typedef struct {
   int max_sweeps;
   double jacobi_tol;
   int form;                    /* mps_form */
+  int modulus;                 /* 0: U(1), the charge is the particle number;
+                                  n >= 2: Z_n, the particle number mod n
+                                  (requires d == n; bond charges 0..n-1) */
 } mps_opts;
 
 /* Per-handle counters, accumulated since creation or mps_reset_stats.
@@ -138,7 +149,7 @@ typedef struct {
 } mps_stats;
 
 /* Fill *o with the defaults: chi_max 0, cutoff 0, zero_tol 1e-13,
- * max_sweeps 40, jacobi_tol 0. */
+ * max_sweeps 40, jacobi_tol 0, plain form, modulus 0. */
 void mps_default_opts(mps_opts* o);
 
 /* Create a state of L sites with local dimension d (occupations 0..d-1,
@@ -195,8 +206,10 @@ mps_status mps_apply_layer(mps_t h, int ngates, const int* sites,
  * after the gate) and column index a*d + b (before).  The library reads
  * the blocks G^(n)[p][a] = g4[(p, n-p), (a, n-a)] and the rest of the
  * update is that of mps_apply_layer.  Elements with p + q != a + b must
- * vanish: those up to 1e-13 times the gate's largest element modulus are
- * dropped, a larger one fails with MPS_E_CHARGE before any state changes.
+ * vanish (for a Z_n state: p + q != a + b mod n, and the blocks are indexed
+ * by the total mod n): those up to 1e-13 times the gate's largest element
+ * modulus are dropped, a larger one fails with MPS_E_CHARGE before any state
+ * changes.
  * Errors: as mps_apply_layer; MPS_E_CHARGE as above. */
 mps_status mps_apply_layer_dense(mps_t h, int ngates, const int* sites,
                                  const mps_z* g4s, double* discarded);

@@ -50,7 +50,8 @@ FORM_SPLIT_BF16X3 = 1        # Theta's charge-triple products in split BF16 on t
 
 class mps_opts(C.Structure):
     _fields_ = [("chi_max", C.c_int), ("cutoff", C.c_double), ("zero_tol", C.c_double),
-                ("max_sweeps", C.c_int), ("jacobi_tol", C.c_double), ("form", C.c_int)]
+                ("max_sweeps", C.c_int), ("jacobi_tol", C.c_double), ("form", C.c_int),
+                ("modulus", C.c_int)]
 
 
 class mps_stats(C.Structure):
@@ -184,18 +185,21 @@ def _close_all() -> None:
 
 
 class MPS:
-    """A U(1)-symmetric MPS on the GPU, created as a Fock product state."""
+    """A U(1)-symmetric MPS on the GPU, created as a Fock product state.
+    modulus n >= 2 (with d == n) makes the charge the particle number mod n."""
 
     def __init__(self, occupation: Sequence[int], d: int, chi_max: int = 0, cutoff: float = 0.0,
                  zero_tol: float = 1e-13, max_sweeps: int = 40, jacobi_tol: float = 0.0,
-                 device: Optional[TorchDevice] = None, form: int = FORM_PLAIN_C128, _handle=None):
+                 device: Optional[TorchDevice] = None, form: int = FORM_PLAIN_C128, modulus: int = 0,
+                 _handle=None):
         self._lib = lib()
         self.L = len(occupation)
         self.d = d
         self.N = int(sum(occupation))
+        self.modulus = int(modulus)
         self._dev = device if device is not None else TorchDevice()
         self._dev_struct = self._dev.struct()
-        self._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form))
+        self._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus))
         self._h = C.c_void_p()
         if _handle is not None:
             self._h = _handle
@@ -210,15 +214,16 @@ class MPS:
                    gammas: List[np.ndarray], lambdas: List[np.ndarray], chi_max: int = 0,
                    cutoff: float = 0.0, zero_tol: float = 1e-13, max_sweeps: int = 40,
                    jacobi_tol: float = 0.0, device: Optional[TorchDevice] = None,
-                   form: int = FORM_PLAIN_C128) -> "MPS":
+                   form: int = FORM_PLAIN_C128, modulus: int = 0) -> "MPS":
         L = len(gammas)
         dims = [len(c) for c in bond_charges]
         obj = cls.__new__(cls)
         obj._lib = lib()
         obj.L, obj.d, obj.N = L, d, n_photons
+        obj.modulus = int(modulus)
         obj._dev = device if device is not None else TorchDevice()
         obj._dev_struct = obj._dev.struct()
-        obj._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form))
+        obj._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus))
         obj._h = C.c_void_p()
         c_dims = (C.c_int * (L + 1))(*dims)
         flat = [int(c) for b in bond_charges for c in b]
@@ -315,7 +320,7 @@ class MPS:
         return occ, prob
 
     def bond_sectors(self, bond: int) -> Dict[int, int]:
-        cap = self.N + 1
+        cap = max(self.N + 1, self.modulus)
         n = C.c_int(0)
         ch = (C.c_int * cap)()
         cnt = (C.c_int * cap)()

@@ -271,12 +271,14 @@ zgemm_kernel(const GemmWork* __restrict__ probs, int nprob) {
 
 // ---------------------------------------------------------------------------
 // Amplitudes: one workgroup per pattern.  The charge path c_{s+1} = c_s - occ_s
-// selects one block of every site tensor (Eq. (E2)); the amplitude is the
-// product of those blocks.  Any missing charge gives exactly zero.
+// (mod n for a Z_n charge) selects one block of every site tensor (Eq. (E2));
+// the amplitude is the product of those blocks.  Any missing charge gives
+// exactly zero.  bondmap has nc = (mod ? mod : N + 1) entries per bond.
 __global__ void __launch_bounds__(256)
 amplitude_kernel(const double2* const* __restrict__ sites, const int* __restrict__ ld,
                  const int2* __restrict__ bondmap, const int* __restrict__ occ,
-                 double2* __restrict__ out, int L, int d, int N, int maxdim) {
+                 double2* __restrict__ out, int L, int d, int N, int mod, int maxdim) {
+  const int nc = mod ? mod : N + 1;
   extern __shared__ double2 vsm[];
   double2* v0 = vsm;
   double2* v1 = vsm + maxdim;
@@ -288,9 +290,9 @@ amplitude_kernel(const double2* const* __restrict__ sites, const int* __restrict
     for (int s = 0; s < L; ++s) {
       const int x = o[s];
       if (x < 0 || x >= d) { good = 0; break; }
-      c -= x;
+      c = mod ? (c - x + mod) % mod : c - x;
       if (c < 0) { good = 0; break; }
-      if (bondmap[(size_t)(s + 1) * (N + 1) + c].y == 0) { good = 0; break; }
+      if (bondmap[(size_t)(s + 1) * nc + c].y == 0) { good = 0; break; }
     }
     if (c != 0) good = 0;
     ok = good;
@@ -304,8 +306,8 @@ amplitude_kernel(const double2* const* __restrict__ sites, const int* __restrict
   int c = N;
   int n0 = 1, off0 = bondmap[c].x;   // bond 0 holds only charge N
   for (int s = 0; s < L; ++s) {
-    const int c1 = c - o[s];
-    const int2 b1 = bondmap[(size_t)(s + 1) * (N + 1) + c1];
+    const int c1 = mod ? (c - o[s] + mod) % mod : c - o[s];
+    const int2 b1 = bondmap[(size_t)(s + 1) * nc + c1];
     const double2* B = sites[s];
     const int lds = ld[s];
     for (int j = threadIdx.x; j < b1.y; j += blockDim.x) {
@@ -393,11 +395,12 @@ hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_
 }
 
 hipError_t launch_amplitude(const double2* const* sites, const int* ld, const int2* bondmap,
-                            const int* occ, double2* out, int count, int L, int d, int N,
+                            const int* occ, double2* out, int count, int L, int d, int N, int mod,
                             int maxdim, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const size_t smem = (size_t)2 * maxdim * sizeof(double2);
-  hipLaunchKernelGGL(amplitude_kernel, dim3(count), dim3(256), smem, st, sites, ld, bondmap, occ, out, L, d, N, maxdim);
+  hipLaunchKernelGGL(amplitude_kernel, dim3(count), dim3(256), smem, st, sites, ld, bondmap, occ, out, L, d, N, mod,
+                     maxdim);
   return hipGetLastError();
 }
 

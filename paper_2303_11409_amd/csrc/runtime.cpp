@@ -70,6 +70,15 @@ struct Bond {
   }
 };
 
+// Charge arithmetic: U(1) (mod 0) or Z_n (mod n, charges in 0..n-1).
+inline int cwrap(int mod, int c) { return mod ? ((c % mod) + mod) % mod : c; }
+// Is a site entry between left charge ci and right charge cj allowed (Eq. (E2)),
+// i.e. is ci - cj a local occupation 0..d-1 (mod n for Z_n)?
+inline bool step_ok(int mod, int d, int ci, int cj) {
+  const int p = cwrap(mod, ci - cj);
+  return p >= 0 && p <= d - 1;
+}
+
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
@@ -102,6 +111,7 @@ constexpr int kBlockedSweeps = 32;
 
 struct mps_state {
   int L = 0, d = 0, N = 0;
+  int mod = 0;                   // 0: U(1) particle number; n: particle number mod n (d == n)
   mps_opts opts{};
   mps_device dev{};
   hipStream_t st = nullptr;
@@ -290,9 +300,20 @@ void gate_blocks(const mps_z u[4], int d, double2* out) {
 // G^(n)[p][a] of a gate given as a dense d^2 x d^2 matrix (row p*d+q, column
 // a*d+b): the element of row p*d+(n-p) and column a*d+(n-a).  Elements that
 // change the charge were checked to be negligible and are not read.
-void dense_blocks(const mps_z* g4, int d, double2* out) {
+// For a Z_n charge (mod = n = d) the blocks are indexed by the total mod n and
+// the second site's occupation is (n - p) mod n.
+void dense_blocks(const mps_z* g4, int d, int mod, double2* out) {
   const int nb = 2 * d - 1, dd = d * d;
   for (int i = 0; i < nb * d * d; ++i) out[i] = make_double2(0.0, 0.0);
+  if (mod) {
+    for (int n = 0; n < mod; ++n)
+      for (int p = 0; p < d; ++p)
+        for (int a = 0; a < d; ++a) {
+          const mps_z v = g4[(size_t)(p * d + cwrap(mod, n - p)) * dd + a * d + cwrap(mod, n - a)];
+          out[(n * d + p) * d + a] = make_double2(v.re, v.im);
+        }
+    return;
+  }
   for (int n = 0; n < nb; ++n)
     for (int p = std::max(0, n - d + 1); p <= std::min(d - 1, n); ++p)
       for (int a = std::max(0, n - d + 1); a <= std::min(d - 1, n); ++a) {
@@ -317,13 +338,32 @@ std::vector<double> strings_count(int sites, int d, int N) {
   return cnt;
 }
 
+// Strings over `sites` sites with occupations < d, counted by their sum mod n.
+std::vector<double> strings_count_mod(int sites, int d, int mod) {
+  std::vector<double> cnt(mod, 0.0), nx(mod);
+  cnt[0] = 1.0;
+  for (int s = 0; s < sites; ++s) {
+    std::fill(nx.begin(), nx.end(), 0.0);
+    for (int c = 0; c < mod; ++c)
+      for (int a = 0; a < d; ++a) nx[(c + a) % mod] += cnt[c];
+    cnt.swap(nx);
+  }
+  return cnt;
+}
+
 mps_status compute_caps(mps_state* h) {
   h->cap.assign(h->L + 1, 1);
   for (int b = 0; b <= h->L; ++b) {
-    const std::vector<double> left = strings_count(b, h->d, h->N);
-    const std::vector<double> right = strings_count(h->L - b, h->d, h->N);
     double tot = 0.0;
-    for (int c = 0; c <= h->N; ++c) tot += std::min(left[h->N - c], right[c]);
+    if (h->mod) {
+      const std::vector<double> left = strings_count_mod(b, h->d, h->mod);
+      const std::vector<double> right = strings_count_mod(h->L - b, h->d, h->mod);
+      for (int c = 0; c < h->mod; ++c) tot += std::min(left[cwrap(h->mod, h->N - c)], right[c]);
+    } else {
+      const std::vector<double> left = strings_count(b, h->d, h->N);
+      const std::vector<double> right = strings_count(h->L - b, h->d, h->N);
+      for (int c = 0; c <= h->N; ++c) tot += std::min(left[h->N - c], right[c]);
+    }
     if (h->opts.chi_max > 0) tot = std::min(tot, double(h->opts.chi_max));
     tot = std::max(tot, double(h->bonds[b].dim()));
     if (tot > 65536.0)
@@ -396,7 +436,7 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
     if (refs[g].u)
       gate_blocks(refs[g].u, d, cg);
     else
-      dense_blocks(refs[g].g4, d, cg);
+      dense_blocks(refs[g].g4, d, h->mod, cg);
     GateWork gw{};
     gw.bl = h->site[s];
     gw.br = h->site[s + 1];
@@ -411,14 +451,16 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
     gw.cutoff = h->opts.cutoff;
     gw.zero_tol = h->opts.zero_tol;
     // sectors: every middle charge m with rows (cL in [m, m+d-1]) and
-    // columns (cR in [m-d+1, m]) present
-    const int mlo = std::max(BL.charge.front() - (d - 1), BR.charge.front());
-    const int mhi = std::min(BL.charge.back(), BR.charge.back() + (d - 1));
+    // columns (cR in [m-d+1, m]) present.  For a Z_n charge with d = n every
+    // row and every column belongs to every m (the occupation is cL - m mod n).
+    const int zn = h->mod;
+    const int mlo = zn ? 0 : std::max(BL.charge.front() - (d - 1), BR.charge.front());
+    const int mhi = zn ? zn - 1 : std::min(BL.charge.back(), BR.charge.back() + (d - 1));
     std::vector<int> secmap(std::max(0, mhi - mlo + 1), -1);
     int T = 0;
     for (int m = mlo; m <= mhi; ++m) {
-      const int i0 = BL.lower(m), i1 = BL.lower(m + d);
-      const int j0 = BR.lower(m - d + 1), j1 = BR.lower(m + 1);
+      const int i0 = zn ? 0 : BL.lower(m), i1 = zn ? (int)BL.charge.size() : BL.lower(m + d);
+      const int j0 = zn ? 0 : BR.lower(m - d + 1), j1 = zn ? (int)BR.charge.size() : BR.lower(m + 1);
       const int r = BL.off[i1] - BL.off[i0];
       const int c = BR.off[j1] - BR.off[j0];
       if (r <= 0 || c <= 0) continue;
@@ -477,18 +519,23 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
       const int cL = BL.charge[a];
       for (size_t b = 0; b < BR.charge.size(); ++b) {
         const int cR = BR.charge[b];
-        const int n = cL - cR;
-        if (n < 0 || n > 2 * d - 2) continue;
-        const int wlo = std::max(cR, cL - d + 1), whi = std::min(cL, cR + d - 1);
+        const int n = cwrap(zn, cL - cR);
+        if (!zn && (n < 0 || n > 2 * d - 2)) continue;
+        // window of middle charges (old bond) and new sectors: U(1) the
+        // integers between max(cR, cL-d+1) and min(cL, cR+d-1); Z_n all of them
+        const int wlo = zn ? 0 : std::max(cR, cL - d + 1), whi = zn ? zn - 1 : std::min(cL, cR + d - 1);
         ThetaTile base{};
         base.gate = g;
         base.n = n;
         for (int m = wlo; m <= whi; ++m) {
           const int si = (m >= mlo && m <= mhi) ? secmap[m - mlo] : -1;
-          if (si < 0) return fail(MPS_E_CHARGE, "internal: sector %d missing at site %d", m, s);
+          if (si < 0) {
+            if (zn) continue;
+            return fail(MPS_E_CHARGE, "internal: sector %d missing at site %d", m, s);
+          }
           const SectorWork& sw = P.secs[si];
           base.sec[base.nout] = si;
-          base.p[base.nout] = cL - m;
+          base.p[base.nout] = cwrap(zn, cL - m);
           base.orow[base.nout] = BL.off[a] - sw.rlo;
           base.ocol[base.nout] = BR.off[b] - sw.clo;
           ++base.nout;
@@ -501,7 +548,7 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
           mid[base.nin] = mi;
           base.k0[base.nin] = BM.off[mi];
           base.kn[base.nin] = BM.count[mi];
-          base.a[base.nin] = cL - cM;
+          base.a[base.nin] = cwrap(zn, cL - cM);
           ksum += BM.count[mi];
           ++base.nin;
         }
@@ -881,6 +928,7 @@ mps_status check_layer(mps_t h, int ngates, const int* sites, const mps_z* gs, b
   if (!sites || !gs) return fail(MPS_E_ARG, "sites and gates are required");
   const int d = h->d, dd = d * d;
   const size_t gsz = dense ? (size_t)dd * dd : 4;
+  if (!dense && h->mod) return fail(MPS_E_ARG, "a Z_n state takes dense gates (mps_apply_layer_dense)");
   std::vector<int> order(ngates);
   for (int g = 0; g < ngates; ++g) {
     if (sites[g] < 0 || sites[g] > h->L - 2) return fail(MPS_E_ARG, "gate site %d outside 0..L-2", sites[g]);
@@ -893,7 +941,8 @@ mps_status check_layer(mps_t h, int ngates, const int* sites, const mps_z* gs, b
     if (dense)
       for (int r = 0; r < dd; ++r)
         for (int c = 0; c < dd; ++c)
-          if (r / d + r % d != c / d + c % d && std::hypot(e[r * dd + c].re, e[r * dd + c].im) > kDenseLeak * big)
+          if (cwrap(h->mod, r / d + r % d - c / d - c % d) != 0 &&
+              std::hypot(e[r * dd + c].re, e[r * dd + c].im) > kDenseLeak * big)
             return fail(MPS_E_CHARGE, "gate %d: element (%d,%d) changes the local charge %d -> %d", g, r, c,
                         c / d + c % d, r / d + r % d);
     order[g] = sites[g];
@@ -947,6 +996,7 @@ void mps_default_opts(mps_opts* o) {
   o->max_sweeps = 40;
   o->jacobi_tol = 0.0;
   o->form = MPS_FORM_PLAIN_C128;
+  o->modulus = 0;
 }
 
 const char* mps_last_error(void) { return g_err.c_str(); }
@@ -972,6 +1022,10 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
   if (o.max_sweeps <= 0) return fail(MPS_E_ARG, "max_sweeps must be positive");
   if (!(o.cutoff >= 0.0) || !(o.zero_tol >= 0.0)) return fail(MPS_E_ARG, "cutoff and zero_tol must be >= 0");
   if (o.form != MPS_FORM_PLAIN_C128 && o.form != MPS_FORM_SPLIT_BF16X3) return fail(MPS_E_ARG, "unknown form %d", o.form);
+  if (o.modulus != 0 && o.modulus != d)
+    return fail(MPS_E_ARG, "a Z_n charge needs n equal to the local dimension (modulus %d, d %d)", o.modulus, d);
+  const int zn = o.modulus;
+  const int nq = zn ? n_photons % zn : n_photons;     // charge of bond 0
 
   // charge tables with a stable sort of every bond by charge
   std::vector<Bond> bonds(L + 1);
@@ -982,7 +1036,8 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
     std::vector<int> ch(bond_charge + pos, bond_charge + pos + n);
     pos += n;
     for (int c : ch)
-      if (c < 0 || c > n_photons) return fail(MPS_E_CHARGE, "bond %d has charge %d outside 0..N", b, c);
+      if (c < 0 || c > (zn ? zn - 1 : n_photons))
+        return fail(MPS_E_CHARGE, "bond %d has charge %d outside 0..%d", b, c, zn ? zn - 1 : n_photons);
     std::vector<int> idx(n);
     for (int i = 0; i < n; ++i) idx[i] = i;
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) { return ch[a] < ch[c]; });
@@ -998,14 +1053,14 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
     }
     B.finish();
   }
-  if (bonds[0].charge[0] != n_photons) return fail(MPS_E_CHARGE, "bond 0 must carry charge N (Eq. E4)");
+  if (bonds[0].charge[0] != nq) return fail(MPS_E_CHARGE, "bond 0 must carry charge N (Eq. E4)");
   if (bonds[L].charge[0] != 0) return fail(MPS_E_CHARGE, "bond L must carry charge 0 (Eq. E4)");
   // every left charge must connect to some right charge with 0 <= cL - cR <= d-1
   for (int s = 0; s < L; ++s) {
     for (int c : bonds[s].charge) {
       bool ok = false;
       for (int c2 : bonds[s + 1].charge)
-        if (c - c2 >= 0 && c - c2 <= d - 1) ok = true;
+        if (step_ok(zn, d, c, c2)) ok = true;
       if (!ok) return fail(MPS_E_CHARGE, "charge %d on bond %d has no admissible partner on bond %d", c, s, s + 1);
     }
   }
@@ -1037,12 +1092,12 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
         if (gamma) {
           const mps_z z = gamma[s][(size_t)perm[s][i] * cdim + perm[s + 1][j]];
           v = make_double2(z.re * hlam[s + 1][j], z.im * hlam[s + 1][j]);
-          const bool allowed = (ci - cj >= 0 && ci - cj <= d - 1);
+          const bool allowed = step_ok(zn, d, ci, cj);
           if (!allowed && (z.re != 0.0 || z.im != 0.0))
             return fail(MPS_E_CHARGE, "site %d entry (%d,%d) violates the charge rule (Eq. E2)", s, i, j);
           if (!std::isfinite(z.re) || !std::isfinite(z.im)) return fail(MPS_E_ARG, "non-finite gamma");
         } else {
-          v = (ci - cj >= 0 && ci - cj <= d - 1) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+          v = step_ok(zn, d, ci, cj) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
         }
         hsite[s][(size_t)i * cdim + j] = v;
       }
@@ -1053,7 +1108,8 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
   if (!h) return fail(MPS_E_NOMEM, "handle allocation failed");
   h->L = L;
   h->d = d;
-  h->N = n_photons;
+  h->N = nq;
+  h->mod = zn;
   h->opts = o;
   if (dev) h->dev = *dev;
   h->st = static_cast<hipStream_t>(h->dev.stream);
@@ -1120,9 +1176,10 @@ mps_status mps_create_product(int L, int d, const int* occupation, const mps_opt
       return fail(MPS_E_ARG, "occupation %d of mode %d outside 0..d-1", occupation[i], i);
     N += occupation[i];
   }
+  const int zn = opts ? opts->modulus : 0;
   int c = N;
   for (int b = 0; b <= L; ++b) {
-    ch[b] = c;
+    ch[b] = (zn > 0) ? c % zn : c;
     if (b < L) c -= occupation[b];
   }
   return mps_create(L, d, N, dims.data(), ch.data(), nullptr, nullptr, opts, dev, out);
@@ -1279,12 +1336,13 @@ mps_status mps_amplitude(mps_t h, int count, const int* occ, mps_z* out) {
   if (count == 0) return MPS_OK;
   if (!occ || !out) return fail(MPS_E_ARG, "occ and out are required");
   const int L = h->L, N = h->N;
-  std::vector<int2> bmap((size_t)(L + 1) * (N + 1), make_int2(0, 0));
+  const int ncb = h->mod ? h->mod : N + 1;          // bondmap entries per bond
+  std::vector<int2> bmap((size_t)(L + 1) * ncb, make_int2(0, 0));
   int maxdim = 1;
   for (int b = 0; b <= L; ++b) {
     const Bond& B = h->bonds[b];
     for (size_t i = 0; i < B.charge.size(); ++i)
-      bmap[(size_t)b * (N + 1) + B.charge[i]] = make_int2(B.off[i], B.count[i]);
+      bmap[(size_t)b * ncb + B.charge[i]] = make_int2(B.off[i], B.count[i]);
     maxdim = std::max(maxdim, B.dim());
   }
   std::vector<int> ld(L);
@@ -1306,8 +1364,8 @@ mps_status mps_amplitude(mps_t h, int count, const int* occ, mps_z* out) {
   pk.write(h->stage_misc.p);
   HIPCHK(hipMemcpyAsync(h->misc.p, h->stage_misc.p, o_out, hipMemcpyHostToDevice, h->st));
   HIPCHK(launch_amplitude(at<const double2*>(h->misc, o_sp), at<int>(h->misc, o_ld), at<int2>(h->misc, o_bm),
-                          at<int>(h->misc, o_occ), at<double2>(h->misc, o_out), count, L, h->d, N, maxdim,
-                          h->st));
+                          at<int>(h->misc, o_occ), at<double2>(h->misc, o_out), count, L, h->d, N, h->mod,
+                          maxdim, h->st));
   HIPCHK(hipMemcpyAsync(static_cast<char*>(h->stage_misc.p) + o_out, at<char>(h->misc, o_out),
                         (size_t)count * sizeof(double2), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
@@ -1344,7 +1402,8 @@ mps_status left_envs(mps_state* h, const std::vector<double2*>& eb, size_t extra
     size_t toff = 0;
     for (size_t i = 0; i < B1.charge.size(); ++i) {
       const int cp = B1.charge[i];
-      const int w0 = B0.off[B0.lower(cp)], w1 = B0.off[B0.lower(cp + d)];
+      // rows of bond s reaching charge cp: charges cp..cp+d-1 (Z_n with d = n: all)
+      const int w0 = h->mod ? 0 : B0.off[B0.lower(cp)], w1 = h->mod ? B0.dim() : B0.off[B0.lower(cp + d)];
       if (w1 <= w0) continue;
       const int nn = B1.count[i], o1 = B1.off[i], kw = w1 - w0;
       GemmWork a{};
@@ -1434,14 +1493,15 @@ mps_status mps_sample(mps_t h, int count, const double* uniforms, int* occ, doub
   const int L = h->L, N = h->N;
   for (size_t k = 0; k < (size_t)count * L; ++k)
     if (!(uniforms[k] >= 0.0 && uniforms[k] < 1.0)) return fail(MPS_E_ARG, "uniform %zu outside [0, 1)", k);
-  std::vector<int2> bmap((size_t)(L + 1) * (N + 1), make_int2(0, 0));
+  const int ncb = h->mod ? h->mod : N + 1;          // bondmap entries per bond
+  std::vector<int2> bmap((size_t)(L + 1) * ncb, make_int2(0, 0));
   int maxblk = 1;
   size_t etot = 0;
   std::vector<size_t> eoff(L + 1);
   for (int b = 0; b <= L; ++b) {
     const Bond& B = h->bonds[b];
     for (size_t i = 0; i < B.charge.size(); ++i) {
-      bmap[(size_t)b * (N + 1) + B.charge[i]] = make_int2(B.off[i], B.count[i]);
+      bmap[(size_t)b * ncb + B.charge[i]] = make_int2(B.off[i], B.count[i]);
       maxblk = std::max(maxblk, B.count[i]);
     }
     eoff[b] = etot;
@@ -1480,7 +1540,8 @@ mps_status mps_sample(mps_t h, int count, const double* uniforms, int* occ, doub
   HIPCHK(hipMemcpyAsync(h->samp.p, h->stage_misc.p, o_occ, hipMemcpyHostToDevice, h->st));
   HIPCHK(launch_sample(at<const double2*>(h->samp, o_sp), at<int>(h->samp, o_lb), at<const double2*>(h->samp, o_ep),
                        at<int>(h->samp, o_le), at<int2>(h->samp, o_bm), at<double>(h->samp, o_u),
-                       at<int>(h->samp, o_occ), at<double>(h->samp, o_pr), count, L, h->d, N, maxblk, h->st));
+                       at<int>(h->samp, o_occ), at<double>(h->samp, o_pr), count, L, h->d, N, h->mod, maxblk,
+                       h->st));
   HIPCHK(hipMemcpyAsync(static_cast<char*>(h->stage_misc.p) + o_occ, at<char>(h->samp, o_occ), pk.total - o_occ,
                         hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));

@@ -9,6 +9,7 @@
 // E_s the left environment of bond s (block-diagonal by charge, built by the
 // norm's contraction).  The occupation is the smallest i whose cumulative
 // p exceeds u * sum(p) for the caller's uniform u; v becomes w_i / sqrt(p_i).
+// With a Z_n charge (mod = n) the charges add mod n.
 //
 // One workgroup (four waves) per sample.  Each matrix-vector product gives
 // every row of the block to a group of g lanes, g the power of two covering
@@ -73,7 +74,8 @@ __global__ void __launch_bounds__(256)
 sample_kernel(const double2* const* __restrict__ sites, const int* __restrict__ ldb,
               const double2* const* __restrict__ envs, const int* __restrict__ lde,
               const int2* __restrict__ bondmap, const double* __restrict__ uni, int* __restrict__ occ,
-              double* __restrict__ prob, int L, int d, int N, int maxblk) {
+              double* __restrict__ prob, int L, int d, int N, int mod, int maxblk) {
+  const int ncb = mod ? mod : N + 1;             // bondmap entries per bond
   extern __shared__ double2 smem[];
   double2* v = smem;
   double2* w = smem + maxblk;
@@ -84,7 +86,7 @@ sample_kernel(const double2* const* __restrict__ sites, const int* __restrict__ 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (tid == 0) v[0] = make_double2(1.0, 0.0);
   int c = 0;                                   // charge of bond s+1; bond L holds only 0
-  int nc = 1, offc = bondmap[(size_t)L * (N + 1)].x;
+  int nc = 1, offc = bondmap[(size_t)L * ncb].x;
   double pr = 1.0;
   __syncthreads();
   for (int s = L - 1; s >= 0; --s) {
@@ -93,8 +95,8 @@ sample_kernel(const double2* const* __restrict__ sites, const int* __restrict__ 
     const double2* E = envs[s];
     const int le = lde[s];
     for (int i = 0; i < d; ++i) {
-      const int c2 = c + i;
-      const int2 bm = c2 <= N ? bondmap[(size_t)s * (N + 1) + c2] : make_int2(0, 0);
+      const int c2 = mod ? (c + i) % mod : c + i;
+      const int2 bm = c2 < ncb ? bondmap[(size_t)s * ncb + c2] : make_int2(0, 0);
       double q = 0.0;
       if (bm.y > 0) {
         block_matvec(B + (size_t)bm.x * lb + offc, lb, bm.y, nc, v, w);
@@ -140,13 +142,14 @@ sample_kernel(const double2* const* __restrict__ sites, const int* __restrict__ 
       if (tid == 0) prob[j] = -1.0;
       return;
     }
-    const int2 bm = bondmap[(size_t)s * (N + 1) + c + i];
+    const int cn = mod ? (c + i) % mod : c + i;
+    const int2 bm = bondmap[(size_t)s * ncb + cn];
     block_matvec(B + (size_t)bm.x * lb + offc, lb, bm.y, nc, v, w);
     __syncthreads();
     const double sc = 1.0 / sqrt(pv[i]);
     for (int r = tid; r < bm.y; r += blockDim.x) v[r] = make_double2(w[r].x * sc, w[r].y * sc);
     if (tid == 0) occ[(size_t)j * L + s] = i;
-    c += i;
+    c = cn;
     nc = bm.y;
     offc = bm.x;
     __syncthreads();
@@ -156,11 +159,11 @@ sample_kernel(const double2* const* __restrict__ sites, const int* __restrict__ 
 
 hipError_t launch_sample(const double2* const* sites, const int* ldb, const double2* const* envs,
                          const int* lde, const int2* bondmap, const double* uniforms, int* occ,
-                         double* prob, int count, int L, int d, int N, int maxblk, hipStream_t st) {
+                         double* prob, int count, int L, int d, int N, int mod, int maxblk, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   if (d > kMaxD || (size_t)2 * maxblk * sizeof(double2) > kSampleLds) return hipErrorInvalidValue;
   hipLaunchKernelGGL(sample_kernel, dim3(count), dim3(256), 2 * maxblk * sizeof(double2), st, sites, ldb,
-                     envs, lde, bondmap, uniforms, occ, prob, L, d, N, maxblk);
+                     envs, lde, bondmap, uniforms, occ, prob, L, d, N, mod, maxblk);
   return hipGetLastError();
 }
 

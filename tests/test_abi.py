@@ -102,3 +102,24 @@ def test_form_option():
     occ = (C.c_int * 4)(1, 0, 1, 0)
     assert lib.mps_create_product(4, 3, occ, C.byref(o), None, C.byref(h)) == -1
     assert "form" in lib.mps_last_error().decode()
+
+
+def test_modulus_option():
+    """The default charge is U(1) (modulus 0); a Z_n charge needs n == d, and its
+    bond charges must lie in 0..n-1 -- both refused before any device work."""
+    lib = binding.lib()
+    o = binding.mps_opts()
+    lib.mps_default_opts(C.byref(o))
+    assert o.modulus == 0
+    h = C.c_void_p()
+    occ = (C.c_int * 4)(1, 0, 1, 0)
+    o.modulus = 3
+    assert lib.mps_create_product(4, 2, occ, C.byref(o), None, C.byref(h)) == -1
+    assert "Z_n" in lib.mps_last_error().decode()
+    o.modulus = 2
+    cd = (C.c_int * 4)(1, 1, 1, 1)
+    cc = (C.c_int * 4)(0, 2, 1, 0)
+    assert lib.mps_create(3, 2, 2, cd, cc, None, None, C.byref(o), None, C.byref(h)) == -2
+    cc = (C.c_int * 4)(1, 1, 1, 0)                 # bond 0 must carry N mod 2 = 0
+    assert lib.mps_create(3, 2, 2, cd, cc, None, None, C.byref(o), None, C.byref(h)) == -2
+    assert "bond 0" in lib.mps_last_error().decode()

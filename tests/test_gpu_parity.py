@@ -743,3 +743,116 @@ def test_precision_form_with_dense_gates(mps_cls):
     assert abs(s.norm2() - p.norm2()) <= ng * 1.1e-5 * p.norm2()
     p.close()
     s.close()
+
+
+# -------------------------------------------------------------- Z_n charges
+def _zn_case(model):
+    from workloads import hamiltonians as ham
+    if model == "ising":
+        return ham.config_tebd("ising", 16, 2, [1, 0, 0, 1, 1, 0, 1, 0, 0, 0, 1, 1, 0, 1, 0, 0], 0.2, 8, 10, 1e-12,
+                               J=1.0, h=0.7)
+    return ham.config_tebd("clock", 10, 3, [0, 1, 2, 2, 0, 1, 0, 2, 1, 0], 0.15, 5, 12, 1e-12, J=1.0, f=0.4)
+
+
+def run_zn(MPS, cfg, form=None):
+    kw = {} if form is None else {"form": form}
+    m = MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"], modulus=cfg["modulus"], **kw)
+    disc = []
+    for lay in cfg["layers"]:
+        disc.extend(m.apply_layer_dense([g.site for g in lay], [g.g4 for g in lay]))
+    return m, np.array(disc)
+
+
+@pytest.mark.parametrize("model", ["ising", "clock"])
+def test_zn_tebd_vs_oracle(mps_cls, model):
+    """Z_2 (transverse-field Ising) and Z_3 (clock) Trotter evolutions with the
+    bond cap binding: discarded weights, Schmidt values, per-bond Z_n charges and
+    amplitudes against the oracle (charge audited through omega^Q); strings of
+    another charge give exactly zero."""
+    from workloads import hamiltonians as ham
+    cfg = _zn_case(model)
+    n = cfg["modulus"]
+    m, disc = run_zn(mps_cls, cfg)
+    ref = dense_mps.DenseMPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"],
+                             modulus=n).run(cfg["gates"])
+    assert min(r.margin for r in ref.records) > 1e-9
+    odisc = np.array([r.discarded for r in ref.records])
+    assert odisc.max() > 1e-11
+    assert np.max(np.abs(disc - odisc)) <= 1e-12
+    pats = ham.zn_patterns(cfg["L"], cfg["d"], sum(cfg["occupation"]), 300, 4)
+    close_amps(m.amplitudes(pats), ref.amplitudes(pats))
+    other = ham.zn_patterns(cfg["L"], cfg["d"], sum(cfg["occupation"]) + 1, 50, 5)
+    assert np.all(m.amplitudes(other) == 0)
+    assert abs(m.norm2() - ref.norm2()) <= TOL
+    check_bookkeeping(m, ref)
+    check_lambdas(m, ref)
+    # exact samples of the Z_n state, as the oracle draws them
+    from oracle import sampling
+    u = np.random.default_rng(74).random((200, cfg["L"]))
+    sp, sprob = m.sample(u)
+    rp, rprob, marg = sampling.mps_samples(ref, u, margins=True)
+    clear = marg > SAMPLE_MARGIN
+    assert np.array_equal(sp[clear], rp[clear])
+    assert np.max(np.abs(sprob - rprob) / rprob) <= 1e-10
+    assert np.all(sp.sum(axis=1) % n == sum(cfg["occupation"]) % n)
+    m.close()
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_zn_random_gates_vs_brute_force(mps_cls, d):
+    """Random Z_d-conserving gates without truncation against the Fock-space
+    brute force over the charge sector (every amplitude)."""
+    import itertools
+    from workloads import hamiltonians as ham
+    rng = np.random.default_rng(40 + d)
+    L = 5
+    occ = [int(x) for x in rng.integers(0, d, size=L)]
+    gates = [ham.DenseGate(int(rng.integers(0, L - 1)), ham.random_zn_gate(d, int(rng.integers(1 << 30))))
+             for _ in range(12)]
+    m = mps_cls(occ, d, modulus=d)
+    for g in gates:
+        m.apply_layer_dense([g.site], [g.g4])
+    st = fock.run(occ, d, gates, modulus=d)
+    pats = np.array(st.basis, dtype=np.int32)
+    got = m.amplitudes(pats)
+    assert np.max(np.abs(got - st.psi)) < 1e-12
+    assert abs(m.norm2() - 1.0) < 1e-12
+    for b in range(L + 1):
+        assert m.bond_sectors(b) == st.schmidt_ranks(b), b
+    m.close()
+
+
+def test_zn_rules(mps_cls):
+    """A Z_n state refuses mode unitaries and gates that change the charge mod
+    n, and accepts gates that change the particle number by n."""
+    from paper_2303_11409_amd import MPSError
+    from workloads import hamiltonians as ham
+    m = mps_cls([0, 0, 0, 0], 2, modulus=2)
+    with pytest.raises(MPSError):
+        m.apply_layer([0], [circuits.beam_splitter(0.3, 0.1)])
+    bad = np.eye(4, dtype=np.complex128)
+    bad[1, 0] = 0.2                                     # |00> -> |01>: parity changes
+    with pytest.raises(MPSError) as e:
+        m.apply_layer_dense([0], [bad])
+    assert e.value.status == -2
+    g = ham.trotter_gate(ham.ising_bond(1.0, 0.0, 1.0, 1.0), 0.5)   # |00> -> |11>
+    m.apply_layer_dense([1], [g])
+    amp = m.amplitudes(np.array([[0, 1, 1, 0], [0, 0, 0, 0]]))
+    assert abs(abs(amp[0]) - abs(np.sin(0.5))) < 1e-14 and abs(abs(amp[1]) - np.cos(0.5)) < 1e-14
+    m.close()
+
+
+def test_zn_precision_form(mps_cls):
+    """The split-BF16 form on a Z_3 state stays within the accumulated product
+    bound of the plain form."""
+    from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
+    from workloads import hamiltonians as ham
+    cfg = _zn_case("clock")
+    p, _ = run_zn(mps_cls, cfg)
+    s, _ = run_zn(mps_cls, cfg, form=FORM_SPLIT_BF16X3)
+    pats = ham.zn_patterns(cfg["L"], 3, sum(cfg["occupation"]), 300, 6)
+    a, b = p.amplitudes(pats), s.amplitudes(pats)
+    ng = len(cfg["gates"])
+    assert float(np.linalg.norm(a - b) / np.linalg.norm(a)) <= ng * 1.1e-5
+    p.close()
+    s.close()

@@ -234,6 +234,33 @@ def config_clock_quench() -> dict:
     return config_tebd("clock", 64, 3, [0] * 64, 0.05, 60, 256, 1e-12, J=1.0, f=0.3)
 
 
+def zn_patterns(L: int, d: int, charge: int, count: int, seed: int) -> np.ndarray:
+    """count uniform occupation strings (occupations < d) whose particle number
+    is `charge` mod d (rejection sampling, numpy.random.default_rng(seed))."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        t = rng.integers(0, d, size=L)
+        if int(t.sum()) % d == charge % d:
+            out.append(t)
+    return np.array(out, dtype=np.int32)
+
+
+def random_zn_gate(d: int, seed: int, unitary: bool = True) -> np.ndarray:
+    """A random d^2 x d^2 gate that conserves p + q mod d (a Z_d charge): a
+    Haar-random (or complex Gaussian) block for each total mod d."""
+    rng = np.random.default_rng(seed)
+    g = np.zeros((d * d, d * d), dtype=np.complex128)
+    for n in range(d):
+        idx = [p * d + (n - p) % d for p in range(d)]
+        z = (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))) / np.sqrt(2)
+        if unitary:
+            q, r = np.linalg.qr(z)
+            z = q * (np.diag(r) / np.abs(np.diag(r)))
+        g[np.ix_(idx, idx)] = z
+    return g
+
+
 def random_charge_conserving(d: int, seed: int, unitary: bool = True) -> np.ndarray:
     """A random d^2 x d^2 gate that conserves p + q: a Haar-random (or, with
     unitary False, complex Gaussian) block for each local charge n."""
