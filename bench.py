@@ -16,8 +16,9 @@ and the CPU oracle timed on a bounded prefix of the same circuit; under
 circuit with other seeds, and the first circuits of the mixed-size workload)
 and the serving form (Poisson arrivals, continuous batching, p50/p99 latency
 from arrival to result); under "tebd", Hamiltonian time evolution with dense
-Trotter gates (an XXZ chain and a Bose-Hubbard chain, 64 sites each, quenched
-from product states).  Progress goes to stderr.
+Trotter gates (an XXZ chain and a Bose-Hubbard chain with the particle number
+as the charge, a transverse-field Ising chain with Z_2 and a clock chain with
+Z_3 charges; 64 sites each, quenched from product states).  Progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -134,7 +135,8 @@ def run_tebd(MPS, dev, cfg):
     """One Hamiltonian time evolution (dense Trotter gates, one layer per call)."""
     layers = [([g.site for g in lay], [g.g4 for g in lay]) for lay in cfg["layers"]]
     ng = sum(len(s) for s, _ in layers)
-    m = MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"], device=dev)
+    m = MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"], device=dev,
+            modulus=cfg.get("modulus", 0))
     m.sync()
     t0 = time.perf_counter()
     disc = 0.0
@@ -454,7 +456,9 @@ def main() -> int:
     if not args.no_tebd:
         from workloads import hamiltonians
         for key, make in (("xxz", hamiltonians.config_xxz_quench),
-                          ("bose_hubbard", hamiltonians.config_bose_hubbard_quench)):
+                          ("bose_hubbard", hamiltonians.config_bose_hubbard_quench),
+                          ("ising_z2", hamiltonians.config_ising_quench),
+                          ("clock_z3", hamiltonians.config_clock_quench)):
             c = make()
             log(f"Hamiltonian TEBD ({key}, L={c['L']}, d={c['d']}, chi_max={c['chi_max']}) ...")
             r = run_tebd(MPS, dev, c)
