@@ -3,8 +3,9 @@
 Runs ONLY the CPU oracle (oracle/dense_mps.py) on the seeded workload from
 workloads/circuits.py or workloads/hamiltonians.py and stores, as JSON text:
   * the amplitudes of 1024 occupation patterns drawn uniformly (seed 102 for
-    the 32-mode circuit, 103 for the 64-mode one, 104 and 105 for the XXZ and
-    Bose-Hubbard quenches) plus the input pattern,
+    the 32-mode circuit, 103 for the 64-mode one, 104, 105 and 106 for the
+    XXZ, Bose-Hubbard and Ising quenches; for the Ising quench among strings
+    of the input's charge mod 2) plus the input pattern,
   * <psi|psi> by full contraction,
   * every bond's right-charge histogram from the oracle's charge audit,
   * every gate's discarded weight and cut margin,
@@ -14,6 +15,7 @@ Usage:  python tests/golden/make_golden.py L32_N16_d4_chi512
         python tests/golden/make_golden.py L64_N32_d4_chi256
         python tests/golden/make_golden.py XXZ_L64_chi256_T10
         python tests/golden/make_golden.py BH_L64_d4_chi256_T3
+        python tests/golden/make_golden.py ISING_L64_chi256_T10
 """
 import json
 import os
@@ -36,6 +38,8 @@ WORKLOADS = {
     # Hamiltonian time evolution (dense Trotter gates), the measured quenches
     "XXZ_L64_chi256_T10": (hamiltonians.config_xxz_quench, 104),
     "BH_L64_d4_chi256_T3": (hamiltonians.config_bose_hubbard_quench, 105),
+    # the Z_2 (transverse-field Ising) quench: charge = occupation count mod 2
+    "ISING_L64_chi256_T10": (hamiltonians.config_ising_quench, 106),
 }
 
 
@@ -44,19 +48,23 @@ def main(name: str) -> None:
     cfg = make()
     L, d = cfg["L"], cfg["d"]
     N = sum(cfg["occupation"])
-    m = dense_mps.DenseMPS(cfg["occupation"], d, chi_max=cfg["chi_max"], cutoff=cfg["cutoff"])
+    mod = cfg.get("modulus", 0)
+    m = dense_mps.DenseMPS(cfg["occupation"], d, chi_max=cfg["chi_max"], cutoff=cfg["cutoff"], modulus=mod)
     t0 = time.time()
     for li, lay in enumerate(cfg["layers"]):
         m.run(lay)
         print(f"layer {li + 1}/{len(cfg['layers'])} chi {max(m.bond_dims())} "
               f"{time.time() - t0:.0f} s", flush=True)
-    pats = circuits.sample_patterns(L, N, d, 1024, pattern_seed)
+    if mod:
+        pats = hamiltonians.zn_patterns(L, d, N, 1024, pattern_seed)
+    else:
+        pats = circuits.sample_patterns(L, N, d, 1024, pattern_seed)
     pats = np.vstack([pats, np.array(cfg["occupation"], dtype=np.int32)[None, :]])
     amp = m.amplitudes(pats)
     out = {
         "workload": name,
         "generator": "tests/golden/make_golden.py (oracle/dense_mps.py only)",
-        "L": L, "d": d, "N": N, "chi_max": cfg["chi_max"], "cutoff": cfg["cutoff"],
+        "L": L, "d": d, "N": N, "modulus": mod, "chi_max": cfg["chi_max"], "cutoff": cfg["cutoff"],
         "patterns": pats.tolist(),
         "amp_re": amp.real.tolist(), "amp_im": amp.imag.tolist(),
         "norm2": m.norm2(),

@@ -439,7 +439,8 @@ def test_batch_rejects_mixed_forms_and_duplicates(mps_cls):
 
 # ------------------------------------------------------------ Hamiltonian TEBD
 def run_dense(MPS, cfg):
-    m = MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"])
+    m = MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"],
+            modulus=cfg.get("modulus", 0))
     disc = []
     for lay in cfg["layers"]:
         disc.extend(m.apply_layer_dense([g.site for g in lay], [g.g4 for g in lay]))
@@ -683,6 +684,13 @@ def test_tebd_xxz_quench_vs_stored_oracle(mps_cls):
     Schmidt values."""
     from workloads import hamiltonians as ham
     _tebd_vs_stored(mps_cls, "XXZ_L64_chi256_T10", ham.config_xxz_quench)
+
+
+def test_tebd_ising_quench_vs_stored_oracle(mps_cls):
+    """The measured Z_2 Ising quench (L=64, chi_max=256, 12632 dense gates)
+    against the oracle's stored results, as for the XXZ quench."""
+    from workloads import hamiltonians as ham
+    _tebd_vs_stored(mps_cls, "ISING_L64_chi256_T10", ham.config_ising_quench)
 
 
 def test_tebd_bose_hubbard_quench_vs_stored_oracle(mps_cls):
