@@ -255,3 +255,17 @@ def test_brute_force_rejects_charge_breaking_gate():
     st.apply_dense(1, np.eye(4))
     with pytest.raises(ValueError):
         fock.FockState([0, 0, 1], 2).apply_dense(0, g)
+
+
+def test_site_dependent_potential_sums_to_hamiltonian():
+    """With a chemical potential per site the bond Hamiltonians still sum to
+    H = -J sum (b^+ b + h.c.) + U/2 sum n(n-1) - sum_i mu_i n_i."""
+    L, d, J, U = 5, 3, 0.8, 1.3
+    mu = [0.3, -0.2, 0.45, 0.0, -0.35]
+    hb = ham.bond_hamiltonians("bose_hubbard", L, d, J=J, U=U, mu_sites=mu)
+    b = np.diag(np.sqrt(np.arange(1, d)), 1)
+    n = np.diag(np.arange(d, dtype=float))
+    H = -J * sum(_site_op(b.T, i, L) @ _site_op(b, i + 1, L) + _site_op(b, i, L) @ _site_op(b.T, i + 1, L)
+                 for i in range(L - 1))
+    H = H + sum(_site_op(0.5 * U * n @ (n - np.eye(d)) - mu[i] * n, i, L) for i in range(L))
+    assert np.max(np.abs(ham.hamiltonian_dense(hb, L, d) - H)) < 1e-13

@@ -72,15 +72,18 @@ def xxz_bond(J: float, delta: float, hz: float = 0.0, w_left: float = 0.5, w_rig
 
 
 def bose_hubbard_bond(d: int, J: float, U: float, mu: float = 0.0, w_left: float = 0.5,
-                      w_right: float = 0.5) -> np.ndarray:
-    """h for one bond of the Bose-Hubbard chain with occupations 0..d-1."""
+                      w_right: float = 0.5, mu_right: float = None) -> np.ndarray:
+    """h for one bond of the Bose-Hubbard chain with occupations 0..d-1; the
+    chemical potential of the right site is mu_right (default mu)."""
     b = _lowering(d)
     bd = b.T
     n = np.diag(np.arange(d, dtype=float))
     one = np.eye(d)
-    onsite = 0.5 * U * n @ (n - one) - mu * n
+    mr = mu if mu_right is None else mu_right
+    onsite_l = 0.5 * U * n @ (n - one) - mu * n
+    onsite_r = 0.5 * U * n @ (n - one) - mr * n
     h = -J * (np.kron(bd, b) + np.kron(b, bd))
-    h = h + w_left * np.kron(onsite, one) + w_right * np.kron(one, onsite)
+    h = h + w_left * np.kron(onsite_l, one) + w_right * np.kron(one, onsite_r)
     return h.astype(np.complex128)
 
 
@@ -121,7 +124,11 @@ def bond_hamiltonians(model: str, L: int, d: int, **p) -> List[np.ndarray]:
                 raise ValueError("the XXZ chain has d = 2")
             out.append(xxz_bond(p.get("J", 1.0), p.get("delta", 1.0), p.get("hz", 0.0), wl, wr))
         elif model == "bose_hubbard":
-            out.append(bose_hubbard_bond(d, p.get("J", 1.0), p.get("U", 1.0), p.get("mu", 0.0), wl, wr))
+            # mu_sites: a site-dependent chemical potential (overrides mu)
+            ms = p.get("mu_sites")
+            ml = ms[i] if ms is not None else p.get("mu", 0.0)
+            mr = ms[i + 1] if ms is not None else p.get("mu", 0.0)
+            out.append(bose_hubbard_bond(d, p.get("J", 1.0), p.get("U", 1.0), ml, wl, wr, mr))
         elif model == "ising":
             if d != 2:
                 raise ValueError("the Ising chain has d = 2")
@@ -214,10 +221,11 @@ def config_xxz_quench() -> dict:
 
 def config_bose_hubbard_quench() -> dict:
     """The measured Bose-Hubbard workload: L = 64, density wave |2,0,2,0,...>
-    (64 bosons), d = 4, J = 1, U = 2, 60 second-order steps of dt = 0.05
-    (T = 3; 3812 gates in 121 layers), chi_max = 256 (reached near T = 1.5),
-    cutoff 1e-12."""
-    return config_tebd("bose_hubbard", 64, 4, [2, 0] * 32, 0.05, 60, 256, 1e-12, J=1.0, U=2.0)
+    (64 bosons), d = 4, J = 1, U = 2, weak disorder mu_i ~ U[-0.5, 0.5]
+    (numpy.random.default_rng(7)), 60 second-order steps of dt = 0.05 (T = 3;
+    3812 gates in 121 layers), chi_max = 256, cutoff 1e-12."""
+    mu = [float(x) for x in np.random.default_rng(7).uniform(-0.5, 0.5, size=64)]
+    return config_tebd("bose_hubbard", 64, 4, [2, 0] * 32, 0.05, 60, 256, 1e-12, J=1.0, U=2.0, mu_sites=mu)
 
 
 def config_ising_quench() -> dict:
