@@ -47,3 +47,20 @@ def test_mixes_are_seeded_and_shaped():
     assert all(s["chi_max"] == 1024 and s["depth"] == 64 and s["n_photons"] == 32 for s in large)
     c = circuits.config_from_spec(specs[0])
     assert len(c["layers"]) == specs[0]["depth"] and sum(c["occupation"]) == specs[0]["n_photons"]
+
+
+def test_zn_input_generators():
+    """Z_n patterns lie in the requested charge class and cover it; random Z_n
+    gates are unitary and conserve the local charge mod n exactly."""
+    from workloads import hamiltonians as ham
+    pats = ham.zn_patterns(6, 3, 4, 400, 1)
+    assert pats.shape == (400, 6) and pats.min() >= 0 and pats.max() < 3
+    assert np.all(pats.sum(axis=1) % 3 == 1)
+    assert len({tuple(p) for p in pats.tolist()}) > 150          # 243 strings in the class
+    for d in (2, 3, 4):
+        g = ham.random_zn_gate(d, 5)
+        assert np.max(np.abs(g.conj().T @ g - np.eye(d * d))) < 1e-13
+        for r in range(d * d):
+            for c in range(d * d):
+                if (r // d + r % d - c // d - c % d) % d:
+                    assert g[r, c] == 0
