@@ -26,7 +26,9 @@ dense_mps  -- dense (no-symmetry) MPS TEBD with the same truncation rule as
               independent charge audit of every bond; gates given as mode
               unitaries or as dense two-site matrices (Hamiltonian TEBD); with a
               modulus n the charge is the particle number mod n (Z_n) and the
-              audit tracks the unitary omega^Q instead of Q.
+              audit tracks the unitary omega^Q instead of Q; with a charge map
+              (d x K) the state carries K independent U(1) charges, each
+              audited by its own operator.
 sampling   -- exact chain-rule sampling of output patterns, by brute force
               over a probability table and from the dense MPS's environments.
 """

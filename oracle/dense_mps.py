@@ -102,7 +102,7 @@ class DenseMPS:
 
     def __init__(self, occupation: Sequence[int], d: int, chi_max: int = 0,
                  cutoff: float = 0.0, zero_tol: float = 1e-13, form: str = "hastings",
-                 modulus: int = 0):
+                 modulus: int = 0, charge_map=None):
         occ = [int(x) for x in occupation]
         if any(o < 0 or o >= d for o in occ):
             raise ValueError("occupation outside 0..d-1")
@@ -112,6 +112,9 @@ class DenseMPS:
         # modulus 0: the charge is the particle number (U(1)); n >= 2: the
         # particle number mod n (Z_n), audited through the unitary omega^Q
         self.modulus = int(modulus)
+        # charge_map (d x K integers): K independent U(1) charges, local state p
+        # carrying charge_map[p]; each component is audited by its own operator
+        self.cmap = None if charge_map is None else np.asarray(charge_map, dtype=np.int64).reshape(d, -1)
         self.chi_max, self.cutoff, self.zero_tol, self.form = chi_max, cutoff, zero_tol, form
         self.t: List[np.ndarray] = []          # B (hastings) or Gamma (vidal)
         for o in occ:
@@ -120,7 +123,14 @@ class DenseMPS:
             self.t.append(a)
         self.lam: List[np.ndarray] = [np.ones(1) for _ in range(self.L + 1)]
         left = np.concatenate([[0], np.cumsum(occ)])
-        if self.modulus:
+        if self.cmap is not None:
+            K = self.cmap.shape[1]
+            lk = np.concatenate([np.zeros((1, K), dtype=np.int64), np.cumsum(self.cmap[occ], axis=0)])
+            self.total = tuple(int(x) for x in lk[-1])
+            self.qk = [[np.array([[float(lk[b, k])]], dtype=np.complex128) for b in range(self.L + 1)]
+                       for k in range(K)]
+            self.q = self.qk[0]
+        elif self.modulus:
             w = np.exp(2j * np.pi / self.modulus)
             self.q: List[np.ndarray] = [np.array([[w ** int(left[b])]], dtype=np.complex128)
                                         for b in range(self.L + 1)]
@@ -166,12 +176,18 @@ class DenseMPS:
         self.lam[s + 1] = sv[:k].copy()
         # charge audit of the new bond s+1
         uk = uu[:, :k]
-        if self.modulus:
+        if self.cmap is not None:
+            for comp, qb in enumerate(self.qk):
+                row = np.kron(qb[s], np.eye(d)) + np.kron(np.eye(chl), np.diag(self.cmap[:, comp].astype(float)))
+                qb[s + 1] = uk.conj().T @ row @ uk
+            qrow = None
+        elif self.modulus:
             w = np.exp(2j * np.pi / self.modulus)
             qrow = np.kron(self.q[s], np.diag(w ** np.arange(d)))
         else:
             qrow = np.kron(self.q[s], np.eye(d)) + np.kron(np.eye(chl), np.diag(np.arange(d)))
-        self.q[s + 1] = uk.conj().T @ qrow @ uk
+        if qrow is not None:
+            self.q[s + 1] = uk.conj().T @ qrow @ uk
         ok = self.audit_clean(s + 1)
         rec = GateRecord(site=s, kept=k, discarded=cut.discarded, margin=cut.margin,
                          leak=before - after, audit_ok=ok)
@@ -241,9 +257,25 @@ class DenseMPS:
             return np.mod(np.angle(ev) * self.modulus / (2 * np.pi), self.modulus)
         return np.linalg.eigvalsh(self.q[bond])
 
-    def bond_charges(self, bond: int) -> Dict[int, int]:
+    def _joint_left_charges(self, bond: int) -> np.ndarray:
+        """K components' left charges of a bond's Schmidt vectors (rows): the
+        commuting operators are diagonalised together through a generic
+        combination, and each one's value read off on the common eigenvectors."""
+        ops = [qb[bond] for qb in self.qk]
+        weights = [1.0, 0.6180339887498949, 0.41421356237309515, 0.7320508075688772][:len(ops)]
+        _, v = np.linalg.eigh(sum(w * o for w, o in zip(weights, ops)))
+        return np.stack([np.real(np.einsum("ij,ik,kj->j", v.conj(), o, v)) for o in ops], axis=1)
+
+    def bond_charges(self, bond: int) -> Dict:
         """Right-charge histogram of a bond from the charge audit (Eq. (E3));
-        for Z_n the right charge is taken mod n."""
+        for Z_n the right charge is taken mod n; with a charge map the keys
+        are tuples of the K components."""
+        if self.cmap is not None:
+            hist_t: Dict = {}
+            for row in self._joint_left_charges(bond):
+                c = tuple(t - int(round(float(x))) for t, x in zip(self.total, row))
+                hist_t[c] = hist_t.get(c, 0) + 1
+            return dict(sorted(hist_t.items()))
         hist: Dict[int, int] = {}
         for e in self._left_charges(bond):
             c = self.N - int(round(float(e)))
@@ -253,6 +285,9 @@ class DenseMPS:
         return dict(sorted(hist.items()))
 
     def audit_clean(self, bond: int, tol: float = 1e-6) -> bool:
+        if self.cmap is not None:
+            ev = self._joint_left_charges(bond)
+            return bool(np.all(np.abs(ev - np.round(ev)) <= tol))
         ev = self._left_charges(bond)
         dev = np.abs(ev - np.round(ev))
         if self.modulus:

@@ -23,15 +23,23 @@ class FockState:
     n >= 2: every string whose particle number equals the input's mod n (a
     Z_n charge)."""
 
-    def __init__(self, occupation: Sequence[int], d: int, modulus: int = 0):
+    def __init__(self, occupation: Sequence[int], d: int, modulus: int = 0, charge_map=None):
         self.L = len(occupation)
         self.d = d
         self.N = int(sum(occupation))
         self.modulus = int(modulus)
+        # charge_map (d x K): K U(1) charges; the basis holds every string with
+        # the input's charge vector
+        self.cmap = None if charge_map is None else np.asarray(charge_map, dtype=np.int64).reshape(d, -1)
         if max(occupation) >= d:
             raise ValueError("input occupation exceeds the local cutoff")
         self.basis: List[Tuple[int, ...]] = []
-        if self.modulus:
+        if self.cmap is not None:
+            total = self.cmap[list(occupation)].sum(axis=0)
+            for t in itertools.product(range(d), repeat=self.L):
+                if np.array_equal(self.cmap[list(t)].sum(axis=0), total):
+                    self.basis.append(tuple(t))
+        elif self.modulus:
             for t in itertools.product(range(d), repeat=self.L):
                 if sum(t) % self.modulus == self.N % self.modulus:
                     self.basis.append(tuple(t))
@@ -107,7 +115,11 @@ class FockState:
         of the state matrix psi[(left string), (right string)] with that c."""
         blocks: Dict[int, Dict[Tuple[int, ...], Dict[Tuple[int, ...], complex]]] = {}
         for i, t in enumerate(self.basis):
-            c = sum(t[bond:]) % self.modulus if self.modulus else sum(t[bond:])
+            if self.cmap is not None:
+                c = tuple(int(x) for x in self.cmap[list(t[bond:])].sum(axis=0)) if bond < self.L else \
+                    tuple([0] * self.cmap.shape[1])
+            else:
+                c = sum(t[bond:]) % self.modulus if self.modulus else sum(t[bond:])
             blocks.setdefault(c, {}).setdefault(t[:bond], {})[t[bond:]] = self.psi[i]
         ranks: Dict[int, int] = {}
         smax = 0.0
@@ -131,9 +143,9 @@ class FockState:
         return ranks
 
 
-def run(occupation: Sequence[int], d: int, gates, modulus: int = 0) -> FockState:
+def run(occupation: Sequence[int], d: int, gates, modulus: int = 0, charge_map=None) -> FockState:
     """Gates with .u (mode unitary) or .g4 (dense two-site matrix)."""
-    st = FockState(occupation, d, modulus)
+    st = FockState(occupation, d, modulus, charge_map)
     for g in gates:
         if hasattr(g, "g4"):
             st.apply_dense(g.site, g.g4)

@@ -108,6 +108,27 @@ def clock_bond(n: int, J: float, f: float, w_left: float = 0.5, w_right: float =
     return -J * (hop + hop.conj().T) - f * (w_left * np.kron(field, one) + w_right * np.kron(one, field))
 
 
+# Two species of hard-core bosons on one site: p = 2 a + b with a, b in {0, 1}
+# the occupations of species up and down; each species' number is a U(1)
+# charge of its own (U(1) x U(1)).
+TWO_SPECIES_CHARGES = np.array([[p // 2, p % 2] for p in range(4)])
+
+
+def two_species_bond(J: float, U: float, w_left: float = 0.5, w_right: float = 0.5) -> np.ndarray:
+    """h for one bond of the two-species hard-core boson chain (d = 4):
+    -J sum_sigma (b+_{i,sigma} b_{i+1,sigma} + h.c.) + U n_up n_down on each site."""
+    low = np.array([[0.0, 1.0], [0.0, 0.0]])          # |1> -> |0>
+    one2 = np.eye(2)
+    b_up, b_dn = np.kron(low, one2), np.kron(one2, low)
+    one = np.eye(4)
+    h = np.zeros((16, 16))
+    for b in (b_up, b_dn):
+        h = h - J * (np.kron(b.T, b) + np.kron(b, b.T))
+    nn = (b_up.T @ b_up) @ (b_dn.T @ b_dn)
+    h = h + U * (w_left * np.kron(nn, one) + w_right * np.kron(one, nn))
+    return h.astype(np.complex128)
+
+
 def trotter_gate(h: np.ndarray, t: float, imaginary: bool = False) -> np.ndarray:
     """exp(-i t h), or exp(-t h) with imaginary."""
     return scipy.linalg.expm((-t if imaginary else -1j * t) * h)
@@ -135,6 +156,10 @@ def bond_hamiltonians(model: str, L: int, d: int, **p) -> List[np.ndarray]:
             out.append(ising_bond(p.get("J", 1.0), p.get("h", 1.0), wl, wr))
         elif model == "clock":
             out.append(clock_bond(d, p.get("J", 1.0), p.get("f", 1.0), wl, wr))
+        elif model == "two_species":
+            if d != 4:
+                raise ValueError("the two-species chain has d = 4")
+            out.append(two_species_bond(p.get("J", 1.0), p.get("U", 1.0), wl, wr))
         else:
             raise ValueError(model)
     return out
@@ -193,7 +218,9 @@ def config_tebd(model: str, L: int, d: int, occupation: Sequence[int], dt: float
         raise ValueError("occupation must have L entries in 0..d-1")
     layers = trotter_layers(hb, dt, steps, order=order, imaginary=imaginary)
     modulus = d if model in ("ising", "clock") else 0
-    return {"model": model, "L": L, "d": d, "occupation": occ, "n_photons": sum(occ), "modulus": modulus, "dt": dt,
+    cmap = TWO_SPECIES_CHARGES if model == "two_species" else None
+    return {"model": model, "L": L, "d": d, "occupation": occ, "n_photons": sum(occ), "modulus": modulus,
+            "charge_map": cmap, "dt": dt,
             "steps": steps, "order": order, "imaginary": imaginary, "params": dict(p),
             "chi_max": chi_max, "cutoff": cutoff, "layers": layers,
             "gates": [g for lay in layers for g in lay]}
