@@ -80,7 +80,12 @@ def truncation(s: np.ndarray, chi_max: int, cutoff: float, zero_tol: float) -> C
     return CutResult(kept=k, discarded=float(tail[k]), total=total, margin=margin)
 
 
-def _svd(m: np.ndarray):
+def _svd(m: np.ndarray, driver: str = "gesdd"):
+    """LAPACK SVD.  gesdd (divide and conquer) by default, falling back to
+    gesvd (QR iteration) if it fails; driver="gesvd" takes QR iteration
+    throughout -- a second, independently rounded FP64 SVD of the same matrix."""
+    if driver == "gesvd":
+        return scipy.linalg.svd(m, full_matrices=False, lapack_driver="gesvd")
     try:
         return scipy.linalg.svd(m, full_matrices=False, lapack_driver="gesdd")
     except np.linalg.LinAlgError:
@@ -102,12 +107,15 @@ class DenseMPS:
 
     def __init__(self, occupation: Sequence[int], d: int, chi_max: int = 0,
                  cutoff: float = 0.0, zero_tol: float = 1e-13, form: str = "hastings",
-                 modulus: int = 0, charge_map=None):
+                 modulus: int = 0, charge_map=None, svd_driver: str = "gesdd"):
         occ = [int(x) for x in occupation]
         if any(o < 0 or o >= d for o in occ):
             raise ValueError("occupation outside 0..d-1")
         if form not in ("hastings", "vidal"):
             raise ValueError(form)
+        if svd_driver not in ("gesdd", "gesvd"):
+            raise ValueError(svd_driver)
+        self.svd_driver = svd_driver
         self.L, self.d, self.N = len(occ), d, sum(occ)
         # modulus 0: the charge is the particle number (U(1)); n >= 2: the
         # particle number mod n (Z_n), audited through the unitary omega^Q
@@ -138,6 +146,47 @@ class DenseMPS:
             self.q = [np.array([[float(left[b])]], dtype=np.complex128) for b in range(self.L + 1)]
         self.records: List[GateRecord] = []
 
+    @classmethod
+    def from_vidal(cls, d: int, n_photons: int, bond_charges: Sequence[Sequence[int]],
+                   gammas: Sequence[np.ndarray], lambdas: Sequence[np.ndarray], chi_max: int = 0,
+                   cutoff: float = 0.0, zero_tol: float = 1e-13, form: str = "hastings",
+                   svd_driver: str = "gesdd") -> "DenseMPS":
+        """A U(1) state given in the charge-labelled Vidal form of Eq. (E2):
+        bond b's indices carry right-charges bond_charges[b] (Eq. (E3); bond 0
+        is {N}, bond L is {0}, Eq. (E4)), gammas[s] is the chi_s x chi_{s+1}
+        matrix Gamma[s] with no physical index, and lambdas[b] the bond's
+        values.  The Kronecker delta of (E2) puts entry (a, b) of gammas[s] on
+        physical index i = c_s(a) - c_{s+1}(b); an entry with i outside
+        0..d-1 must be zero (ValueError otherwise).  The dense tensor is
+        Gamma[s][a, i, b] = delta(i, c_s(a) - c_{s+1}(b)) gammas[s][a, b],
+        stored as B = Gamma lambda[s+1] in the Hastings form.  The charge audit
+        starts from the given labels: Q[b] = diag(N - c_b), the photons left of
+        the bond."""
+        L = len(gammas)
+        if len(bond_charges) != L + 1 or len(lambdas) != L + 1:
+            raise ValueError("need L+1 bonds of charges and of lambdas")
+        ch = [np.asarray(c, dtype=np.int64).reshape(-1) for c in bond_charges]
+        if ch[0].tolist() != [n_photons] or ch[L].tolist() != [0]:
+            raise ValueError("bond 0 must carry {N} and bond L {0} (Eq. (E4))")
+        obj = cls([0] * L, d, chi_max=chi_max, cutoff=cutoff, zero_tol=zero_tol, form=form,
+                  svd_driver=svd_driver)
+        obj.N = int(n_photons)
+        obj.lam = [np.asarray(l, dtype=np.float64).reshape(-1).copy() for l in lambdas]
+        obj.t = []
+        for s in range(L):
+            g = np.asarray(gammas[s], dtype=np.complex128)
+            if g.shape != (ch[s].size, ch[s + 1].size) or obj.lam[s + 1].size != ch[s + 1].size:
+                raise ValueError(f"site {s}: shapes do not match the bond dimensions")
+            phys = ch[s][:, None] - ch[s + 1][None, :]
+            if np.any(g[(phys < 0) | (phys >= d)] != 0):
+                raise ValueError(f"site {s}: an entry violates the charge rule of Eq. (E2)")
+            gam = np.zeros((ch[s].size, d, ch[s + 1].size), dtype=np.complex128)
+            for i in range(d):
+                gam[:, i, :] = np.where(phys == i, g, 0.0)
+            obj.t.append(gam * obj.lam[s + 1][None, None, :] if form == "hastings" else gam)
+        obj.q = [np.diag((obj.N - c).astype(np.complex128)) for c in ch]
+        return obj
+
     # ------------------------------------------------------------------ update
     def apply_gate(self, site: int, u: np.ndarray) -> GateRecord:
         """Two-mode linear-optics gate of 2x2 mode unitary u (P_d G P_d)."""
@@ -151,19 +200,22 @@ class DenseMPS:
             raise IndexError("gate site out of range")
         a, b = self.t[s], self.t[s + 1]
         chl, chr_ = a.shape[0], b.shape[2]
+        # theta~[x, i, j, z] = sum_y a[x, i, y] b[y, j, z] (a matrix product over
+        # the middle bond; in the Vidal form with lambda on the middle and right bonds)
         if self.form == "hastings":
-            th = np.einsum("xiy,yjz->xijz", a, b)
-            lam_l = self.lam[s]
+            th = np.tensordot(a, b, axes=([2], [0]))
         else:
-            th = np.einsum("xiy,y,yjz,z->xijz", a, self.lam[s + 1], b, self.lam[s + 2])
-            lam_l = self.lam[s]
+            th = np.tensordot(a * self.lam[s + 1][None, None, :], b * self.lam[s + 2][None, None, :],
+                              axes=([2], [0]))
+        lam_l = self.lam[s]
         g4 = np.asarray(g, dtype=np.complex128).reshape(d, d, d, d)
         before = float(np.sum(np.abs(lam_l[:, None, None, None] * th) ** 2))
-        th = np.einsum("pqmn,xmnz->xpqz", g4, th)
+        # the gate on the two physical indices: th'[x, p, q, z] = sum_mn g4[p, q, m, n] th[x, m, n, z]
+        th = np.ascontiguousarray(np.tensordot(g4, th, axes=([2, 3], [1, 2])).transpose(2, 0, 1, 3))
         theta = lam_l[:, None, None, None] * th
         after = float(np.sum(np.abs(theta) ** 2))
         mat = theta.reshape(chl * d, d * chr_)
-        uu, sv, vh = _svd(mat)
+        uu, sv, vh = _svd(mat, self.svd_driver)
         cut = truncation(sv, self.chi_max, self.cutoff, self.zero_tol)
         k = cut.kept
         vk = vh[:k]
@@ -224,17 +276,22 @@ class DenseMPS:
         return complex(v[0])
 
     def amplitudes(self, patterns: np.ndarray) -> np.ndarray:
+        """(E1) for many patterns; patterns go through in groups small enough
+        that the gathered blocks stay near 256 MiB."""
         pats = np.asarray(patterns, dtype=np.int64)
         bs = self.site_matrices()
         out = np.zeros(pats.shape[0], dtype=np.complex128)
         valid = np.all((pats >= 0) & (pats < self.d), axis=1)
         idx = np.nonzero(valid)[0]
-        if idx.size:
-            v = np.ones((idx.size, 1), dtype=np.complex128)
+        chi = max(self.bond_dims())
+        group = max(1, int((1 << 28) // (16 * chi * chi)))
+        for g0 in range(0, idx.size, group):
+            sel = idx[g0:g0 + group]
+            v = np.ones((sel.size, 1), dtype=np.complex128)
             for s in range(self.L):
-                blk = bs[s][:, pats[idx, s], :]          # (chi_s, n, chi_{s+1})
+                blk = bs[s][:, pats[sel, s], :]          # (chi_s, n, chi_{s+1})
                 v = np.einsum("nx,xny->ny", v, blk)
-            out[idx] = v[:, 0]
+            out[sel] = v[:, 0]
         return out
 
     def norm2(self) -> float:

@@ -208,6 +208,41 @@ def sample_patterns(n_modes: int, n_photons: int, d: int, count: int, seed: int)
     return out
 
 
+def charge_path_patterns(bond_charges: Sequence[Sequence[int]], d: int, count: int, seed: int) -> np.ndarray:
+    """``count`` occupation strings drawn uniformly from the strings whose
+    right-charge path c_0 = N, c_{k+1} = c_k - occ_k visits only charges
+    present on every bond (so none of them is structurally zero in a state
+    with these bond charges); occupations < d."""
+    L = len(bond_charges) - 1
+    present = [set(int(c) for c in b) for b in bond_charges]
+    # paths[k][c] = admissible strings over modes k..L-1 starting at charge c on bond k
+    paths: List[dict] = [dict() for _ in range(L + 1)]
+    paths[L] = {0: 1} if 0 in present[L] else {}
+    for k in range(L - 1, -1, -1):
+        for c in present[k]:
+            n = sum(paths[k + 1].get(c - a, 0) for a in range(d))
+            if n:
+                paths[k][c] = n
+    n0 = next(iter(present[0]))
+    if paths[0].get(n0, 0) == 0:
+        raise ValueError("no admissible charge path")
+    rng = np.random.default_rng(seed)
+    out = np.zeros((count, L), dtype=np.int32)
+    for t in range(count):
+        c = n0
+        for k in range(L):
+            weights = [paths[k + 1].get(c - a, 0) for a in range(d)]
+            total = sum(weights)
+            x = int(rng.integers(0, total)) if total < 2 ** 62 else _big_randint(rng, total)
+            a = 0
+            while x >= weights[a]:
+                x -= weights[a]
+                a += 1
+            out[t, k] = a
+            c -= a
+    return out
+
+
 def _big_randint(rng, total: int) -> int:
     nbits = total.bit_length() + 64
     while True:
