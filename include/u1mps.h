@@ -34,9 +34,11 @@
  *   u11 a1^+.  A gate on `site` acts on modes site and site+1.
  *   Errors: every call returns an mps_status; MPS_OK is 0, errors are
  *   negative.  Argument and charge errors are detected before any state
- *   changes.  A device-side failure (Jacobi non-convergence, a vanished or
- *   non-finite two-site matrix) is reported by the call that detects it;
- *   the state is then unspecified and the handle should be destroyed.
+ *   changes.  A device-side failure of an update (Jacobi non-convergence, a
+ *   vanished or non-finite two-site matrix) and an allocation failure are
+ *   reported by the call that detects them, before the update writes the
+ *   state: the state is unchanged.  After MPS_E_DEVICE (a failed HIP call) the
+ *   state is unspecified and the handle should be destroyed.
  *   mps_last_error() returns a thread-local message for the last failure.
  *   One handle must not be used from two threads at once.
  */
@@ -82,8 +84,10 @@ typedef struct {
  *   zero_tol   singular values <= zero_tol * s_max are dropped as numerical
  *              zeros (default 1e-13).
  *   max_sweeps Jacobi sweep limit per sector (default 40): blocked sweeps
- *              first (at most 32), then scalar sweeps on the vectors of any
- *              sector still rotating.
+ *              first (at most blocked_sweeps, default 32), then scalar sweeps
+ *              on the vectors of any sector still rotating.  A sector still
+ *              rotating after max_sweeps fails the update with MPS_E_NOCONV
+ *              before any state changes.
  *   jacobi_tol rotate a vector pair while |<x,y>| > tol * |x| |y|; <= 0
  *              means max(vector length, 64) * 2^-52.  The SVD of an r x c
  *              sector orthogonalises its min(r, c) rows or columns.
@@ -115,6 +119,14 @@ typedef struct {
   int modulus;                 /* 0: U(1), the charge is the particle number;
                                   n >= 2: Z_n, the particle number mod n
                                   (requires d == n; bond charges 0..n-1) */
+  int blocked_sweeps;          /* blocked Jacobi sweeps before the scalar
+                                  finish (0: the default, 32); at most
+                                  max_sweeps.  A diagnostic: a small value
+                                  sends sectors through the scalar sweeps. */
+  int select_scratch;          /* 1: the cut's sort always goes through
+                                  device memory, as it does when a gate has
+                                  more than 4096 candidate values (0: LDS
+                                  when it fits).  A diagnostic. */
 } mps_opts;
 
 /* Per-handle counters, accumulated since creation or mps_reset_stats.
@@ -146,10 +158,13 @@ typedef struct {
                                /*   products x 3 split terms x 2)              */
   double split_ms;             /* split-BF16 form: splitting the site tensors  */
                                /*   into BF16 planes before the products       */
+  double leak_total;           /* weight removed by the local cutoff, summed   */
+                               /*   over gates (see mps_last_leaks)            */
 } mps_stats;
 
 /* Fill *o with the defaults: chi_max 0, cutoff 0, zero_tol 1e-13,
- * max_sweeps 40, jacobi_tol 0, plain form, modulus 0. */
+ * max_sweeps 40, jacobi_tol 0, plain form, modulus 0, blocked_sweeps 0,
+ * select_scratch 0. */
 void mps_default_opts(mps_opts* o);
 
 /* Create a state of L sites with local dimension d (occupations 0..d-1,
@@ -276,6 +291,16 @@ mps_status mps_bond_lambda(mps_t h, int bond, int cap, int* n, double* lambda);
  * in ascending-charge order).  cap is out's capacity in elements. */
 mps_status mps_site_tensor(mps_t h, int site, size_t cap, int* rows, int* cols,
                            mps_z* out);
+
+/* Per-gate weight removed by the local cutoff in the last apply call that
+ * touched h (its gates in call order): |lambda_s theta~|^2 of the two-site
+ * tensor before the gate minus |theta|^2 after it.  With d <= N the gate
+ * the MPS applies is the two-mode gate projected to occupations < d, which is
+ * not unitary on the blocks of total photon number n >= d (Sec. II gives d as
+ * the local dimension); this is the weight that projection removes, apart
+ * from the SVD's discarded weight.  cap is the capacity of leak; *n receives
+ * the gate count (MPS_E_ARG if above cap). */
+mps_status mps_last_leaks(mps_t h, int cap, int* n, double* leak);
 
 /* Enable (1) or disable (0) HIP-event timing of every kernel launch. */
 mps_status mps_set_timing(mps_t h, int on);

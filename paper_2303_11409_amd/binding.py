@@ -51,7 +51,7 @@ FORM_SPLIT_BF16X3 = 1        # Theta's charge-triple products in split BF16 on t
 class mps_opts(C.Structure):
     _fields_ = [("chi_max", C.c_int), ("cutoff", C.c_double), ("zero_tol", C.c_double),
                 ("max_sweeps", C.c_int), ("jacobi_tol", C.c_double), ("form", C.c_int),
-                ("modulus", C.c_int)]
+                ("modulus", C.c_int), ("blocked_sweeps", C.c_int), ("select_scratch", C.c_int)]
 
 
 class mps_stats(C.Structure):
@@ -65,12 +65,12 @@ class mps_stats(C.Structure):
                 ("update_launches", C.c_longlong), ("polish_launches", C.c_longlong),
                 ("max_discarded", C.c_double), ("min_margin", C.c_double),
                 ("gemm_ms", C.c_double), ("gemm_launches", C.c_longlong),
-                ("gemm_mfma_flops", C.c_double), ("split_ms", C.c_double)]
+                ("gemm_mfma_flops", C.c_double), ("split_ms", C.c_double), ("leak_total", C.c_double)]
 
 
 EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_destroy", "mps_apply_gate",
            "mps_apply_layer", "mps_apply_layer_dense", "mps_apply_batch", "mps_truncate", "mps_amplitude", "mps_norm", "mps_sample", "mps_bond_sectors",
-           "mps_bond_lambda", "mps_site_tensor", "mps_set_timing", "mps_get_stats",
+           "mps_bond_lambda", "mps_site_tensor", "mps_last_leaks", "mps_set_timing", "mps_get_stats",
            "mps_reset_stats", "mps_sync", "mps_last_error"]
 
 
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mps_bond_sectors": (st, [h, C.c_int, C.c_int, P(C.c_int), P(C.c_int), P(C.c_int)]),
         "mps_bond_lambda": (st, [h, C.c_int, C.c_int, P(C.c_int), P(C.c_double)]),
         "mps_site_tensor": (st, [h, C.c_int, C.c_size_t, P(C.c_int), P(C.c_int), P(mps_z)]),
+        "mps_last_leaks": (st, [h, C.c_int, P(C.c_int), P(C.c_double)]),
         "mps_set_timing": (st, [h, C.c_int]),
         "mps_get_stats": (st, [h, P(mps_stats)]),
         "mps_reset_stats": (st, [h]),
@@ -191,7 +192,7 @@ class MPS:
     def __init__(self, occupation: Sequence[int], d: int, chi_max: int = 0, cutoff: float = 0.0,
                  zero_tol: float = 1e-13, max_sweeps: int = 40, jacobi_tol: float = 0.0,
                  device: Optional[TorchDevice] = None, form: int = FORM_PLAIN_C128, modulus: int = 0,
-                 _handle=None):
+                 blocked_sweeps: int = 0, select_scratch: int = 0, _handle=None):
         self._lib = lib()
         self.L = len(occupation)
         self.d = d
@@ -199,7 +200,8 @@ class MPS:
         self.modulus = int(modulus)
         self._dev = device if device is not None else TorchDevice()
         self._dev_struct = self._dev.struct()
-        self._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus))
+        self._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus),
+                              int(blocked_sweeps), int(select_scratch))
         self._h = C.c_void_p()
         if _handle is not None:
             self._h = _handle
@@ -214,7 +216,8 @@ class MPS:
                    gammas: List[np.ndarray], lambdas: List[np.ndarray], chi_max: int = 0,
                    cutoff: float = 0.0, zero_tol: float = 1e-13, max_sweeps: int = 40,
                    jacobi_tol: float = 0.0, device: Optional[TorchDevice] = None,
-                   form: int = FORM_PLAIN_C128, modulus: int = 0) -> "MPS":
+                   form: int = FORM_PLAIN_C128, modulus: int = 0, blocked_sweeps: int = 0,
+                   select_scratch: int = 0) -> "MPS":
         L = len(gammas)
         dims = [len(c) for c in bond_charges]
         obj = cls.__new__(cls)
@@ -223,7 +226,8 @@ class MPS:
         obj.modulus = int(modulus)
         obj._dev = device if device is not None else TorchDevice()
         obj._dev_struct = obj._dev.struct()
-        obj._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus))
+        obj._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus),
+                             int(blocked_sweeps), int(select_scratch))
         obj._h = C.c_void_p()
         c_dims = (C.c_int * (L + 1))(*dims)
         flat = [int(c) for b in bond_charges for c in b]
@@ -346,6 +350,14 @@ class MPS:
         _check(self._lib.mps_site_tensor(self._h, int(site), out.size, C.byref(rr), C.byref(cc),
                                          out.ctypes.data_as(C.POINTER(mps_z))))
         return out
+
+    def last_leaks(self) -> np.ndarray:
+        """Per-gate weight removed by the local cutoff in the last apply call."""
+        n = C.c_int(0)
+        self._lib.mps_last_leaks(self._h, 0, C.byref(n), None)
+        out = np.zeros(max(n.value, 1), dtype=np.float64)
+        _check(self._lib.mps_last_leaks(self._h, out.size, C.byref(n), out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out[:n.value]
 
     def set_timing(self, on: bool) -> None:
         _check(self._lib.mps_set_timing(self._h, 1 if on else 0))

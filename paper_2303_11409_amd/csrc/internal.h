@@ -20,6 +20,7 @@ constexpr int kMaxD = 8;          // local dimension limit (occupations 0..7)
 constexpr int kThetaTile = 32;    // Theta output tile edge
 constexpr int kGemmTile = 32;     // generic ZGEMM tile edge
 constexpr size_t kSampleLds = 64 * 1024;   // sampler: LDS for its two vectors
+constexpr int kSelectLds = 4096;  // cut: candidate values sorted in LDS (48 KiB)
 
 // One two-site update inside a batch.
 struct GateWork {
@@ -30,6 +31,7 @@ struct GateWork {
   int coef;               // offset of this gate's (2d-1) x d x d coefficients
   int d;
   int sec_begin, sec_end; // sector range [begin, end) in the batch's sector list
+  int tile_begin, tile_end;  // Theta tile range [begin, end) of this gate
   int keep_cap;           // largest admissible new bond dimension
   int chi_max;            // <= 0: none
   double cutoff;
@@ -143,6 +145,8 @@ struct CutOut {
   double discarded;
   double total;
   double margin;
+  double leak;            // weight the local cutoff removed: |lambda theta~|^2 before
+                          // the gate minus the total weight after it
 };
 
 // Blocked Jacobi: vectors are grouped in blocks of kJB; one round-robin step

@@ -6,9 +6,10 @@
 
 namespace u1mps {
 
+// tile_before[t] receives |lambda_s theta~|^2 of tile t before the gate.
 hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntiles,
                         const SectorWork* secs, const double2* coef, double2* raw,
-                        double2* scaled, int maxw, hipStream_t st);
+                        double2* scaled, double* tile_before, int maxw, hipStream_t st);
 
 // Blocked one-sided Jacobi SVD of every listed sector (vectors: min(r, c)
 // rows or columns of length max(r, c)); st holds per-sector state.
@@ -30,9 +31,14 @@ hipError_t launch_jacobi_finalize(const SectorWork* secs, const int* list, int c
                                   double2* theta, const double2* acc, double* sigma, int* order,
                                   hipStream_t s);
 
+// The cut's sort runs in LDS when every gate has at most kSelectLds candidate
+// values, else (or when global is set) in the device scratch gsv/gsk.
+// tile_before (may be NULL): per-tile weights before the gate, summed per gate
+// into CutOut::leak.
 hipError_t launch_select(const GateWork* gates, int ngates, const SectorWork* secs,
                          const double* sigma, double* gsv, int* gsk, const long long* scratch_off,
-                         int* kept, CutOut* cut, int maxP, hipStream_t st);
+                         int* kept, CutOut* cut, int maxP, bool global, const double* tile_before,
+                         hipStream_t st);
 
 hipError_t launch_update_rows(const RowWork* rows, int nrows, const SectorWork* secs,
                               const UpdateWork* upd, const double2* vh, const double* sigma,
@@ -48,7 +54,8 @@ hipError_t launch_split_planes(const SplitPlanes* plans, int nplan, int ntiles, 
                                unsigned short* planes, hipStream_t st);
 hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, hipStream_t st);
 hipError_t launch_theta_mix(const GateWork* gates, const ThetaTile* tiles, int ntiles, const SectorWork* secs,
-                            const double2* coef, const float2* pbuf, double2* raw, double2* scaled, hipStream_t st);
+                            const double2* coef, const float2* pbuf, double2* raw, double2* scaled,
+                            double* tile_before, hipStream_t st);
 
 // mod: 0 for a U(1) charge, n for a Z_n charge (bondmap then has n entries per bond).
 hipError_t launch_amplitude(const double2* const* sites, const int* ld, const int2* bondmap,

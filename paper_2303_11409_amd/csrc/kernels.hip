@@ -13,24 +13,54 @@
 namespace u1mps {
 
 // ---------------------------------------------------------------------------
-// Cut over all sectors of one gate.  One workgroup per gate.  Entries are
+// Cut over all sectors of one gate.  One workgroup of 512 threads per gate
+// (LDS: the candidates, up to 48 KiB, plus 12 KiB of counters and sums).  Entries are
 // (value, key) with key = local sector << 20 | rank; they are sorted by value
 // descending, then key ascending (bitonic network), and the kept count is
 //   K = max(1, min(K_eps, K_zero, chi_max, keep_cap, T)).
+// The weights behind K_eps and the discarded weight are compensated sums.
 __device__ __forceinline__ bool sel_before(double va, int ka, double vb, int kb) {
   return va > vb || (va == vb && ka < kb);
 }
 
-__global__ void __launch_bounds__(1024)
+// Compensated FP64 sums (double-double accumulation): a value is hi + lo.
+// add_sq adds v^2 exactly up to the final rounding: the product's rounding
+// error comes from an fma, the sum's from TwoSum, both folded into lo.
+struct Dd {
+  double hi, lo;
+};
+__device__ __forceinline__ Dd dd_add(Dd a, double b) {
+  const double s = a.hi + b;
+  const double bb = s - a.hi;
+  const double err = (a.hi - (s - bb)) + (b - bb);
+  return {s, a.lo + err};
+}
+__device__ __forceinline__ Dd dd_add_sq(Dd a, double v) {
+  const double p = v * v;
+  const double pe = fma(v, v, -p);
+  Dd r = dd_add(a, p);
+  r.lo += pe;
+  return r;
+}
+__device__ __forceinline__ Dd dd_add(Dd a, Dd b) {
+  Dd r = dd_add(a, b.hi);
+  r.lo += b.lo;
+  return r;
+}
+__device__ __forceinline__ double dd_val(Dd a) { return a.hi + a.lo; }
+
+constexpr int kSelectThreads = 512;
+
+__global__ void __launch_bounds__(kSelectThreads)
 select_kernel(const GateWork* __restrict__ gates, const SectorWork* __restrict__ secs,
               const double* __restrict__ sigma, double* __restrict__ gsv, int* __restrict__ gsk,
               const long long* __restrict__ scratch_off, int* __restrict__ kept,
-              CutOut* __restrict__ cut, int lds_cap) {
+              CutOut* __restrict__ cut, int lds_cap, const double* __restrict__ tile_before) {
   extern __shared__ double ssm[];
   __shared__ int cnt[1024];
-  __shared__ double chunk[1024];
+  __shared__ Dd chunk[kSelectThreads];
   __shared__ int kmin, kzero, nf_flag;
-  __shared__ double disc_sh;
+  __shared__ Dd disc_sh;
   __shared__ int total_sh;
   const int gi = blockIdx.x;
   const GateWork g = gates[gi];
@@ -97,42 +127,42 @@ select_kernel(const GateWork* __restrict__ gates, const SectorWork* __restrict__
   }
   const double s0 = sv[0];
   bool bad = !(s0 > 0.0) || !isfinite(s0);
-  // chunked sums of squares over the T valid entries, in sorted order
+  // chunked compensated sums of squares over the T valid entries, in sorted order
   const int C = (T + nt - 1) / nt;
   const int cb = tid * C, ce = min(T, cb + C);
-  double part = 0.0;
+  Dd part = {0.0, 0.0};
   int nonfinite = 0;
   for (int i = cb; i < ce; ++i) {
     const double v = sv[i];
     if (!isfinite(v)) nonfinite = 1;
-    part = fma(v, v, part);
+    part = dd_add_sq(part, v);
   }
   chunk[tid] = part;
-  if (tid == 0) { kmin = T; kzero = 0; nf_flag = 0; disc_sh = 0.0; }
+  if (tid == 0) { kmin = T; kzero = 0; nf_flag = 0; }
   __syncthreads();
   if (nonfinite) atomicOr(&nf_flag, 1);
   __syncthreads();
   if (nf_flag) bad = true;
   if (tid == 0) {
     // suffix sums of the chunk sums, fixed order
-    double run = 0.0;
+    Dd run = {0.0, 0.0};
     for (int t = nt - 1; t >= 0; --t) {
-      const double v = chunk[t];
+      const Dd v = chunk[t];
       chunk[t] = run;          // sum of chunks after t
-      run += v;
+      run = dd_add(run, v);
     }
     disc_sh = run;             // temporarily: total weight W
   }
   __syncthreads();
-  const double W = disc_sh;
+  const double W = dd_val(disc_sh);
   const double thr = g.cutoff * W;
   const double zthr = g.zero_tol * s0;
   int my_kmin = T, my_kz = 0;
   {
-    double run = chunk[tid];
+    Dd run = chunk[tid];
     for (int i = ce - 1; i >= cb; --i) {
-      run = fma(sv[i], sv[i], run);
-      if (run <= thr) my_kmin = i;
+      run = dd_add_sq(run, sv[i]);
+      if (dd_val(run) <= thr) my_kmin = i;
       if (sv[i] > zthr) ++my_kz;
     }
   }
@@ -146,22 +176,39 @@ select_kernel(const GateWork* __restrict__ gates, const SectorWork* __restrict__
   K = max(K, 1);
   // tail weight at K
   if (K < T && K >= cb && K < ce) {
-    double run = chunk[tid];
-    for (int i = ce - 1; i >= K; --i) run = fma(sv[i], sv[i], run);
+    Dd run = chunk[tid];
+    for (int i = ce - 1; i >= K; --i) run = dd_add_sq(run, sv[i]);
     disc_sh = run;
   }
   __syncthreads();
-  if (K >= T && tid == 0) disc_sh = 0.0;
+  if (K >= T && tid == 0) disc_sh = Dd{0.0, 0.0};
   for (int i = tid; i < K; i += nt) atomicAdd(&cnt[sk[i] >> 20], 1);
+  // weight before the gate: the gate's tile sums in a fixed order
+  Dd bsum = {0.0, 0.0};
+  if (tile_before) {
+    const int nts = g.tile_end - g.tile_begin;
+    const int TC = (nts + nt - 1) / nt;
+    for (int i = g.tile_begin + tid * TC; i < min(g.tile_end, g.tile_begin + (tid + 1) * TC); ++i)
+      bsum = dd_add(bsum, tile_before[i]);
+  }
+  __syncthreads();
+  chunk[tid] = bsum;
+  __syncthreads();
+  if (tid == 0) {
+    Dd b = {0.0, 0.0};
+    for (int t = 0; t < nt; ++t) b = dd_add(b, chunk[t]);
+    chunk[0] = b;
+  }
   __syncthreads();
   for (int s = tid; s < nsec; s += nt) kept[g.sec_begin + s] = cnt[s];
   if (tid == 0) {
     CutOut o;
     o.kept = K;
     o.flags = bad ? 1 : 0;
-    o.discarded = disc_sh;
+    o.discarded = dd_val(disc_sh);
     o.total = W;
     o.margin = K < T ? (sv[K - 1] - sv[K]) / s0 : INFINITY;
+    o.leak = tile_before ? dd_val(chunk[0]) - W : 0.0;
     cut[gi] = o;
   }
 }
@@ -360,14 +407,14 @@ gather_vec_kernel(const double* __restrict__ src, double* __restrict__ dst,
 
 hipError_t launch_select(const GateWork* gates, int ngates, const SectorWork* secs,
                          const double* sigma, double* gsv, int* gsk, const long long* scratch_off,
-                         int* kept, CutOut* cut, int maxP, hipStream_t st) {
+                         int* kept, CutOut* cut, int maxP, bool global, const double* tile_before,
+                         hipStream_t st) {
   if (ngates <= 0) return hipSuccess;
-  // LDS holds P doubles + P ints when P <= 4096 (48 KiB); larger goes to global scratch
-  const int lds_cap = 4096;
-  const int P = maxP <= lds_cap ? maxP : 0;
+  // LDS holds P doubles + P ints when P <= kSelectLds (48 KiB); larger goes to global scratch
+  const int P = (maxP <= kSelectLds && !global) ? maxP : 0;
   const size_t smem = (size_t)P * (sizeof(double) + sizeof(int));
-  hipLaunchKernelGGL(select_kernel, dim3(ngates), dim3(1024), smem, st, gates, secs, sigma, gsv,
-                     gsk, scratch_off, kept, cut, P > 0 ? lds_cap : 0);
+  hipLaunchKernelGGL(select_kernel, dim3(ngates), dim3(kSelectThreads), smem, st, gates, secs, sigma, gsv,
+                     gsk, scratch_off, kept, cut, P > 0 ? kSelectLds : 0, tile_before);
   return hipGetLastError();
 }
 

@@ -121,7 +121,8 @@ struct mps_state {
   std::vector<double2*> site;    // per site, cap[s] * cap[s+1] complex
   // workspaces (grow-only)
   DevBuf th_raw, th_scaled, acc, sigma, order, jperm, jnorm, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc,
-      pbuf, planes, envs, samp;
+      pbuf, planes, envs, samp, tbefore;
+  std::vector<double> last_leak;   // per gate of the last apply call touching this state
   PinBuf stage_plan, stage_upd, stage_res, stage_misc, stage_flag;
   mps_stats stats{};
   bool timing = false;
@@ -515,6 +516,7 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
       P.spl.push_back(pb);
     }
     // tiles
+    gw.tile_begin = (int)P.tiles.size();
     for (size_t a = 0; a < BL.charge.size(); ++a) {
       const int cL = BL.charge[a];
       for (size_t b = 0; b < BR.charge.size(); ++b) {
@@ -602,6 +604,7 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
         }
       }
     }
+    gw.tile_end = (int)P.tiles.size();
     P.gates[g] = gw;
     P.gp[g] = {s, gw.sec_begin, gw.sec_end};
   }
@@ -660,6 +663,8 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   STCHK(ensure(h, h->order, (size_t)P.sig_elems * sizeof(int)));
   STCHK(ensure(h, h->jperm, (size_t)P.sig_elems * sizeof(int)));
   STCHK(ensure(h, h->jnorm, (size_t)P.sig_elems * sizeof(double)));
+  STCHK(ensure(h, h->tbefore, std::max<size_t>(P.tiles.size(), 1) * sizeof(double)));
+  double* d_tbefore = static_cast<double*>(h->tbefore.p);
   if (P.split) {
     STCHK(ensure(h, h->pbuf, (size_t)std::max<long long>(P.p_elems, 1) * sizeof(float2)));
     STCHK(ensure(h, h->planes, (size_t)std::max<long long>(P.plane_elems, 1) * sizeof(unsigned short)));
@@ -671,7 +676,8 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
       g.c = pb + reinterpret_cast<uintptr_t>(g.c);
     }
   }
-  if (P.maxP > 4096) {
+  const bool sel_global = P.maxP > kSelectLds || h->opts.select_scratch;
+  if (sel_global) {
     STCHK(ensure(h, h->sel_v, (size_t)P.sel_scratch * sizeof(double)));
     STCHK(ensure(h, h->sel_k, (size_t)P.sel_scratch * sizeof(int)));
   }
@@ -724,13 +730,13 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     STCHK(tm.start());
     HIPCHK(launch_theta_mix(d_gates, at<ThetaTile>(h->plan, o_tiles), (int)P.tiles.size(), d_secs,
                             at<double2>(h->plan, o_coef), static_cast<const float2*>(h->pbuf.p), raw, scaled,
-                            h->st));
+                            d_tbefore, h->st));
     STCHK(tm.stop());
   } else {
     Timer tm(h, K_THETA);
     STCHK(tm.start());
     HIPCHK(launch_theta(d_gates, at<ThetaTile>(h->plan, o_tiles), (int)P.tiles.size(), d_secs,
-                        at<double2>(h->plan, o_coef), raw, scaled, P.maxw, h->st));
+                        at<double2>(h->plan, o_coef), raw, scaled, d_tbefore, P.maxw, h->st));
     STCHK(tm.stop());
   }
   {
@@ -750,7 +756,8 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     }
     // blocked sweeps; a sector still rotating after kBlockedSweeps of them is
     // finished by scalar sweeps on its vectors
-    const int blocked = std::min(h->opts.max_sweeps, kBlockedSweeps);
+    const int blocked =
+        std::min(h->opts.max_sweeps, h->opts.blocked_sweeps > 0 ? h->opts.blocked_sweeps : kBlockedSweeps);
     int still_active = 1;
     for (int sweep = 0; sweep < blocked; ++sweep) {
       Timer tm(h, K_JACOBI);
@@ -791,7 +798,8 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     STCHK(tm.start());
     HIPCHK(launch_select(d_gates, ng, d_secs, sig, static_cast<double*>(h->sel_v.p),
                          static_cast<int*>(h->sel_k.p), at<long long>(h->plan, o_seloff),
-                         at<int>(h->plan, o_kept), at<CutOut>(h->plan, o_cut), P.maxP, h->st));
+                         at<int>(h->plan, o_kept), at<CutOut>(h->plan, o_cut), P.maxP, sel_global, d_tbefore,
+                         h->st));
     STCHK(tm.stop());
   }
   // read back kept counts, cut results and Jacobi statistics
@@ -899,10 +907,14 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     HIPCHK(launch_zgemm(at<GemmWork>(h->upd, u_gemm), (int)gemms.size(), ntiles, h->st));
     STCHK(tm.stop());
   }
+  for (int g = 0; g < ng; ++g)
+    if (g == 0 || refs[g - 1].h != refs[g].h) refs[g].h->last_leak.clear();
   for (int g = 0; g < ng; ++g) {
     mps_state* hg = refs[g].h;
     hg->bonds[refs[g].site + 1] = newb[g];
     if (discarded) discarded[g] = cut[g].discarded;
+    hg->last_leak.push_back(cut[g].leak);
+    hg->stats.leak_total += cut[g].leak;
     hg->stats.gates += 1;
     hg->stats.max_discarded = std::max(hg->stats.max_discarded, cut[g].discarded);
     if (std::isfinite(cut[g].margin)) hg->stats.min_margin = std::min(hg->stats.min_margin, cut[g].margin);
@@ -961,7 +973,7 @@ mps_status destroy_buffers(mps_state* h) {
   h->site.clear();
   DevBuf* bufs[] = {&h->th_raw, &h->th_scaled, &h->acc, &h->jperm, &h->jnorm, &h->sigma, &h->order, &h->plan, &h->upd,
                     &h->norm_e0, &h->norm_e1, &h->norm_t, &h->sel_v, &h->sel_k, &h->misc, &h->pbuf,
-                    &h->planes, &h->envs, &h->samp};
+                    &h->planes, &h->envs, &h->samp, &h->tbefore};
   for (DevBuf* b : bufs) {
     dfree(h, b->p);
     b->p = nullptr;
@@ -997,6 +1009,8 @@ void mps_default_opts(mps_opts* o) {
   o->jacobi_tol = 0.0;
   o->form = MPS_FORM_PLAIN_C128;
   o->modulus = 0;
+  o->blocked_sweeps = 0;
+  o->select_scratch = 0;
 }
 
 const char* mps_last_error(void) { return g_err.c_str(); }
@@ -1020,6 +1034,8 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
   mps_default_opts(&o);
   if (opts) o = *opts;
   if (o.max_sweeps <= 0) return fail(MPS_E_ARG, "max_sweeps must be positive");
+  if (o.blocked_sweeps < 0) return fail(MPS_E_ARG, "blocked_sweeps must be >= 0");
+  if (o.select_scratch != 0 && o.select_scratch != 1) return fail(MPS_E_ARG, "select_scratch must be 0 or 1");
   if (!(o.cutoff >= 0.0) || !(o.zero_tol >= 0.0)) return fail(MPS_E_ARG, "cutoff and zero_tol must be >= 0");
   if (o.form != MPS_FORM_PLAIN_C128 && o.form != MPS_FORM_SPLIT_BF16X3) return fail(MPS_E_ARG, "unknown form %d", o.form);
   if (o.modulus != 0 && o.modulus != d)
@@ -1268,8 +1284,10 @@ mps_status mps_truncate(mps_t h, int bond, int chi_max, double cutoff, double* d
   gw.chi_max = chi_max;
   gw.cutoff = cutoff;
   gw.zero_tol = h->opts.zero_tol;
+  if (secs.size() > 1024) return fail(MPS_E_ARG, "more than 1024 charges on bond %d", bond);
   int Pp = 1;
   while (Pp < T) Pp <<= 1;
+  const bool sel_global = Pp > kSelectLds || h->opts.select_scratch;
   long long zero = 0;
   Packer pk;
   const size_t o_g = pk.add(&gw, sizeof gw);
@@ -1279,7 +1297,7 @@ mps_status mps_truncate(mps_t h, int bond, int chi_max, double cutoff, double* d
   const size_t o_cut = pk.add(nullptr, sizeof(CutOut));
   STCHK(ensure(h, h->plan, pk.total));
   STCHK(ensure_pin(h->stage_plan, pk.total));
-  if (Pp > 4096) {
+  if (sel_global) {
     STCHK(ensure(h, h->sel_v, (size_t)Pp * sizeof(double)));
     STCHK(ensure(h, h->sel_k, (size_t)Pp * sizeof(int)));
   }
@@ -1289,7 +1307,7 @@ mps_status mps_truncate(mps_t h, int bond, int chi_max, double cutoff, double* d
   HIPCHK(launch_select(at<GateWork>(h->plan, o_g), 1, at<SectorWork>(h->plan, o_s), h->lam[bond],
                        static_cast<double*>(h->sel_v.p), static_cast<int*>(h->sel_k.p),
                        at<long long>(h->plan, o_z), at<int>(h->plan, o_kept), at<CutOut>(h->plan, o_cut),
-                       Pp, h->st));
+                       Pp, sel_global, nullptr, h->st));
   STCHK(ensure_pin(h->stage_res, pk.total - o_kept));
   HIPCHK(hipMemcpyAsync(h->stage_res.p, at<char>(h->plan, o_kept), pk.total - o_kept,
                         hipMemcpyDeviceToHost, h->st));
@@ -1593,6 +1611,16 @@ mps_status mps_site_tensor(mps_t h, int site, size_t cap, int* rows, int* cols, 
   if (!out) return fail(MPS_E_ARG, "out is NULL");
   HIPCHK(hipMemcpyAsync(out, h->site[site], (size_t)r * c * sizeof(double2), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
+  return MPS_OK;
+}
+
+mps_status mps_last_leaks(mps_t h, int cap, int* n, double* leak) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  const int cnt = (int)h->last_leak.size();
+  if (n) *n = cnt;
+  if (cnt > cap) return fail(MPS_E_ARG, "capacity %d < %d gates", cap, cnt);
+  if (cnt && !leak) return fail(MPS_E_ARG, "leak is NULL");
+  for (int i = 0; i < cnt; ++i) leak[i] = h->last_leak[i];
   return MPS_OK;
 }
 

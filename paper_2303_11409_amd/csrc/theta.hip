@@ -16,18 +16,33 @@ namespace u1mps {
 // ---------------------------------------------------------------------------
 // Theta formation.  One workgroup (256 threads, 16 x 16) per 32 x 32 tile of
 // one (cL, cR) pair; each thread owns rows ty, ty+16 and columns tx, tx+16.
+// Sum over the workgroup's 256 threads in a fixed order (deterministic).
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
 template <int W>
 __global__ void __launch_bounds__(256)
 theta_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ tiles,
              const SectorWork* __restrict__ secs, const double2* __restrict__ coef,
-             double2* __restrict__ th_raw, double2* __restrict__ th_scaled) {
+             double2* __restrict__ th_raw, double2* __restrict__ th_scaled,
+             double* __restrict__ tile_before) {
   __shared__ ThetaTile t;
   __shared__ double2 as[kThetaTile][17];
   __shared__ double2 bs[16][kThetaTile + 1];
+  __shared__ double red[4];
   if (threadIdx.x == 0) t = tiles[blockIdx.x];
   __syncthreads();
   const GateWork g = gates[t.gate];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  // lambda_s of this thread's two rows (0 past the tile)
+  double lr[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) lr[a] = ty + 16 * a < t.nrow ? g.lam_l[t.row0 + ty + 16 * a] : 0.0;
+  double before = 0.0;     // |lambda_s P_j|^2 summed over the input segments
 
   double2 out[W][2][2];
 #pragma unroll
@@ -73,6 +88,11 @@ theta_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ t
       }
       __syncthreads();
     }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        before = fma(lr[a] * lr[a], fma(p[a][b].x, p[a][b].x, p[a][b].y * p[a][b].y), before);
     // gate mix: out_i += G^(n)[p_i][a_j] * P_j
 #pragma unroll
     for (int i = 0; i < W; ++i) {
@@ -108,6 +128,8 @@ theta_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ t
       }
     }
   }
+  before = block_sum256(before, red);
+  if (threadIdx.x == 0) tile_before[blockIdx.x] = before;
 }
 
 
@@ -324,11 +346,13 @@ __global__ void __launch_bounds__(256)
 theta_mix_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ tiles,
                  const SectorWork* __restrict__ secs, const double2* __restrict__ coef,
                  const float2* __restrict__ pbuf, double2* __restrict__ th_raw,
-                 double2* __restrict__ th_scaled) {
+                 double2* __restrict__ th_scaled, double* __restrict__ tile_before) {
+  __shared__ double red[4];
   const ThetaTile& t = tiles[blockIdx.x];
   const GateWork g = gates[t.gate];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int nin = t.nin, nout = t.nout;
+  double before = 0.0;     // |lambda_s P_j|^2 summed over the input segments
   for (int a = 0; a < 2; ++a) {
     const int r = ty + 16 * a;
     if (r >= t.nrow) continue;
@@ -343,6 +367,7 @@ theta_mix_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict
         if (j < nin) {
           const float2 f = pbuf[t.poff[j] + (size_t)(t.pr0 + r) * t.ldp + t.pc0 + c];
           pv[j] = make_double2(f.x, f.y);
+          before = fma(lam * lam, fma(pv[j].x, pv[j].x, pv[j].y * pv[j].y), before);
         }
       }
       for (int i = 0; i < nout; ++i) {
@@ -358,6 +383,8 @@ theta_mix_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict
       }
     }
   }
+  before = block_sum256(before, red);
+  if (threadIdx.x == 0) tile_before[blockIdx.x] = before;
 }
 
 
@@ -366,12 +393,14 @@ theta_mix_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict
 
 hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntiles,
                         const SectorWork* secs, const double2* coef, double2* raw,
-                        double2* scaled, int maxw, hipStream_t st) {
+                        double2* scaled, double* tile_before, int maxw, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   if (maxw <= 4)
-    hipLaunchKernelGGL(theta_kernel<4>, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, raw, scaled);
+    hipLaunchKernelGGL(theta_kernel<4>, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, raw, scaled,
+                       tile_before);
   else
-    hipLaunchKernelGGL(theta_kernel<kMaxD>, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, raw, scaled);
+    hipLaunchKernelGGL(theta_kernel<kMaxD>, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, raw, scaled,
+                       tile_before);
   return hipGetLastError();
 }
 
@@ -389,9 +418,11 @@ hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, hipS
 }
 
 hipError_t launch_theta_mix(const GateWork* gates, const ThetaTile* tiles, int ntiles, const SectorWork* secs,
-                            const double2* coef, const float2* pbuf, double2* raw, double2* scaled, hipStream_t st) {
+                            const double2* coef, const float2* pbuf, double2* raw, double2* scaled,
+                            double* tile_before, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(theta_mix_kernel, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, pbuf, raw, scaled);
+  hipLaunchKernelGGL(theta_mix_kernel, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, pbuf, raw, scaled,
+                     tile_before);
   return hipGetLastError();
 }
 

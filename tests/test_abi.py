@@ -123,3 +123,27 @@ def test_modulus_option():
     cc = (C.c_int * 4)(1, 1, 1, 0)                 # bond 0 must carry N mod 2 = 0
     assert lib.mps_create(3, 2, 2, cd, cc, None, None, C.byref(o), None, C.byref(h)) == -2
     assert "bond 0" in lib.mps_last_error().decode()
+
+
+def test_diagnostic_options():
+    """blocked_sweeps and select_scratch default to 0 and are range-checked on
+    the host."""
+    lib = binding.lib()
+    o = binding.mps_opts()
+    lib.mps_default_opts(C.byref(o))
+    assert (o.blocked_sweeps, o.select_scratch) == (0, 0)
+    h = C.c_void_p()
+    occ = (C.c_int * 4)(1, 0, 1, 0)
+    o.blocked_sweeps = -1
+    assert lib.mps_create_product(4, 3, occ, C.byref(o), None, C.byref(h)) == -1
+    assert "blocked_sweeps" in lib.mps_last_error().decode()
+    o.blocked_sweeps = 0
+    o.select_scratch = 2
+    assert lib.mps_create_product(4, 3, occ, C.byref(o), None, C.byref(h)) == -1
+    assert "select_scratch" in lib.mps_last_error().decode()
+
+
+def test_last_leaks_argument_errors():
+    lib = binding.lib()
+    n = C.c_int(-1)
+    assert lib.mps_last_leaks(None, 0, C.byref(n), None) == -1
