@@ -65,7 +65,7 @@ struct ThetaTile {
   int sec[kMaxD], p[kMaxD];                // output sector, cL - m
   int orow[kMaxD], ocol[kMaxD];            // tile origin inside Theta(m)
   // split-BF16 form only: the products P_j = B[s](cL, segment j) B[s+1](., cR)
-  // of the tile's charge pair sit in the complex64 scratch at poff[j], row-major
+  // of the tile's charge pair sit in the complex128 scratch at poff[j], row-major
   // with row length ldp (= the pair's column count); the tile starts at
   // row pr0, column pc0 of them
   long long poff[kMaxD];
@@ -73,14 +73,16 @@ struct ThetaTile {
 };
 
 // Split-BF16 form.  Before the products, each gate's two site tensors are
-// split into BF16 planes (re hi, re lo, im hi, im lo; x = hi + lo with
-// hi = bf16(x), lo = bf16(x - hi)) over a padded k axis (the middle bond,
+// split into kSgPlanes BF16 planes (re hi, re mid, re lo, im hi, im mid,
+// im lo; x = hi + mid + lo with hi = bf16(x), mid = bf16(x - hi),
+// lo = bf16(x - hi - mid)) over a padded k axis (the middle bond,
 // every charge block starting at a multiple of 8, zeros between blocks):
 // A planes hold B[s] (rows = bond s), B planes hold B[s+1] transposed
 // (rows = bond s+2), so both operands have k contiguous.
 constexpr int kSgTile = 64;       // output tile edge of the products
 constexpr int kSgK = 32;          // k chunk staged per step
 constexpr int kSpTile = 32;       // tile edge of the split pass
+constexpr int kSgPlanes = 6;      // BF16 planes per operand: 3 parts x (re, im)
 
 struct SplitPlanes {
   const double2* src;     // the site frame
@@ -94,14 +96,14 @@ struct SplitPlanes {
   int tile_begin;
 };
 
-// One charge-triple product C (m x n, complex64, row-major, ldc) = A (m x k) B
+// One charge-triple product C (m x n, complex128, row-major, ldc) = A (m x k) B
 // (k x n) from the planes: a and b point at plane 0 of the operands' first
 // row and first k (k contiguous, row strides lda and ldb, multiples of 8),
 // plane strides pa and pb.
 struct SplitGemm {
   const unsigned short* a;
   const unsigned short* b;
-  float2* c;
+  double2* c;
   long long pa, pb;
   int m, n, k;
   int lda, ldb, ldc;

@@ -54,7 +54,7 @@ hipError_t launch_split_planes(const SplitPlanes* plans, int nplan, int ntiles, 
                                unsigned short* planes, hipStream_t st);
 hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, hipStream_t st);
 hipError_t launch_theta_mix(const GateWork* gates, const ThetaTile* tiles, int ntiles, const SectorWork* secs,
-                            const double2* coef, const float2* pbuf, double2* raw, double2* scaled,
+                            const double2* coef, const double2* pbuf, double2* raw, double2* scaled,
                             double* tile_before, hipStream_t st);
 
 // mod: 0 for a U(1) charge, n for a Z_n charge (bondmap then has n entries per bond).

@@ -398,7 +398,7 @@ struct BatchPlan {
   int maxw = 1;
   double theta_flops = 0.0;
   // split-BF16 form: the BF16 planes of every gate's two site tensors, then
-  // one product per charge triple into the complex64 scratch
+  // one product per charge triple into the complex128 scratch
   bool split = false;
   std::vector<SplitPlanes> spl;
   std::vector<int> ktab;                  // padded k -> source k (-1 = pad), all gates
@@ -506,11 +506,11 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
       const int tk = (ldk + kSpTile - 1) / kSpTile;
       SplitPlanes pa{gw.bl, gw.ldl, BL.dim(), 0, ldk, k0, P.plane_elems, tk, P.spl_tiles};
       planeA = P.plane_elems;
-      P.plane_elems += 4LL * BL.dim() * ldk;
+      P.plane_elems += (long long)kSgPlanes * BL.dim() * ldk;
       P.spl_tiles += ((BL.dim() + kSpTile - 1) / kSpTile) * tk;
       SplitPlanes pb{gw.br, gw.ldr, BR.dim(), 1, ldk, k0, P.plane_elems, tk, P.spl_tiles};
       planeB = P.plane_elems;
-      P.plane_elems += 4LL * BR.dim() * ldk;
+      P.plane_elems += (long long)kSgPlanes * BR.dim() * ldk;
       P.spl_tiles += ((BR.dim() + kSpTile - 1) / kSpTile) * tk;
       P.spl.push_back(pa);
       P.spl.push_back(pb);
@@ -571,7 +571,7 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
                 (uintptr_t)(planeB + (long long)BR.off[b] * ldk + pm[mid[j]]));
             sg.pb = (long long)BR.dim() * ldk;
             sg.ldb = ldk;
-            sg.c = reinterpret_cast<float2*>((uintptr_t)P.p_elems);
+            sg.c = reinterpret_cast<double2*>((uintptr_t)P.p_elems);
             sg.ldc = nR;
             sg.m = nL;
             sg.n = nR;
@@ -580,7 +580,7 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
             sg.tile_begin = P.sg_tiles;
             P.sg_tiles += ((nL + kSgTile - 1) / kSgTile) * sg.tiles_n;
             // executed: whole 64 x 64 tiles, k in steps of 16 (one MFMA k step)
-            P.sg_mfma_flops += 24.0 * kSgTile * kSgTile * 16.0 *
+            P.sg_mfma_flops += 48.0 * kSgTile * kSgTile * 16.0 *
                                (((nL + kSgTile - 1) / kSgTile) * sg.tiles_n) * ((sg.k + 15) / 16);
             P.sg.push_back(sg);
             P.p_elems += (long long)nL * nR;
@@ -666,9 +666,9 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   STCHK(ensure(h, h->tbefore, std::max<size_t>(P.tiles.size(), 1) * sizeof(double)));
   double* d_tbefore = static_cast<double*>(h->tbefore.p);
   if (P.split) {
-    STCHK(ensure(h, h->pbuf, (size_t)std::max<long long>(P.p_elems, 1) * sizeof(float2)));
+    STCHK(ensure(h, h->pbuf, (size_t)std::max<long long>(P.p_elems, 1) * sizeof(double2)));
     STCHK(ensure(h, h->planes, (size_t)std::max<long long>(P.plane_elems, 1) * sizeof(unsigned short)));
-    float2* pb = static_cast<float2*>(h->pbuf.p);
+    double2* pb = static_cast<double2*>(h->pbuf.p);
     const unsigned short* pl = static_cast<const unsigned short*>(h->planes.p);
     for (SplitGemm& g : P.sg) {
       g.a = pl + reinterpret_cast<uintptr_t>(g.a);
@@ -729,7 +729,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     Timer tm(h, K_THETA);
     STCHK(tm.start());
     HIPCHK(launch_theta_mix(d_gates, at<ThetaTile>(h->plan, o_tiles), (int)P.tiles.size(), d_secs,
-                            at<double2>(h->plan, o_coef), static_cast<const float2*>(h->pbuf.p), raw, scaled,
+                            at<double2>(h->plan, o_coef), static_cast<const double2*>(h->pbuf.p), raw, scaled,
                             d_tbefore, h->st));
     STCHK(tm.stop());
   } else {

@@ -140,29 +140,36 @@ theta_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ t
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// x = hi + lo with hi = bf16(x), lo = bf16(x - hi): |x - hi - lo| <= 2^-18 |x|
-// (after the float conversion of x, which adds 2^-24 |x|); BF16 bit patterns.
-__device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigned short& lo) {
+// x = hi + mid + lo in BF16 (8 significant bits each), taken from the float
+// conversion of x (relative error 2^-24): hi = bf16(x), mid = bf16(x - hi),
+// lo = bf16(x - hi - mid).  Each difference is exact in float and each
+// rounding keeps the next 8 bits, so |x - hi| <= 2^-8 |x|, |x - hi - mid| <=
+// 2^-16 |x| and |x - hi - mid - lo| <= 2^-24 |x|: with the conversion the
+// three parts represent x to 2^-23 relative.
+__device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigned short& mid,
+                                           unsigned short& lo) {
   const float xf = (float)x;
   const __bf16 h = (__bf16)xf;
-  const __bf16 l = (__bf16)(xf - (float)h);
+  const float r1 = xf - (float)h;
+  const __bf16 m = (__bf16)r1;
+  const __bf16 l = (__bf16)(r1 - (float)m);
   hi = __builtin_bit_cast(unsigned short, h);
+  mid = __builtin_bit_cast(unsigned short, m);
   lo = __builtin_bit_cast(unsigned short, l);
 }
 
-// Four consecutive padded-k entries of one row into the four planes, one
-// 8-byte store per plane (idx is a multiple of 4).
+// Four consecutive padded-k entries of one row into the six planes (re hi,
+// re mid, re lo, im hi, im mid, im lo), one 8-byte store per plane (idx is a
+// multiple of 4).
 __device__ __forceinline__ void split_store4(unsigned short* out, long long plane, long long idx,
                                              const double2 (&v)[4]) {
-  ushort4 rh, rl, ih, il;
-  split_bf16(v[0].x, rh.x, rl.x); split_bf16(v[0].y, ih.x, il.x);
-  split_bf16(v[1].x, rh.y, rl.y); split_bf16(v[1].y, ih.y, il.y);
-  split_bf16(v[2].x, rh.z, rl.z); split_bf16(v[2].y, ih.z, il.z);
-  split_bf16(v[3].x, rh.w, rl.w); split_bf16(v[3].y, ih.w, il.w);
-  *reinterpret_cast<ushort4*>(out + idx) = rh;
-  *reinterpret_cast<ushort4*>(out + plane + idx) = rl;
-  *reinterpret_cast<ushort4*>(out + 2 * plane + idx) = ih;
-  *reinterpret_cast<ushort4*>(out + 3 * plane + idx) = il;
+  ushort4 p[kSgPlanes];
+  split_bf16(v[0].x, p[0].x, p[1].x, p[2].x); split_bf16(v[0].y, p[3].x, p[4].x, p[5].x);
+  split_bf16(v[1].x, p[0].y, p[1].y, p[2].y); split_bf16(v[1].y, p[3].y, p[4].y, p[5].y);
+  split_bf16(v[2].x, p[0].z, p[1].z, p[2].z); split_bf16(v[2].y, p[3].z, p[4].z, p[5].z);
+  split_bf16(v[3].x, p[0].w, p[1].w, p[2].w); split_bf16(v[3].y, p[3].w, p[4].w, p[5].w);
+#pragma unroll
+  for (int q = 0; q < kSgPlanes; ++q) *reinterpret_cast<ushort4*>(out + q * plane + idx) = p[q];
 }
 
 // The split pass: one 32 x 32 tile (rows x padded k) of one plan's planes per
@@ -220,18 +227,19 @@ split_planes_kernel(const SplitPlanes* __restrict__ plans, int nplan, const int*
 }
 
 // LDS rows of one k chunk: 32 BF16 plus 8 of padding (80 bytes), so every
-// 8-element operand read is one aligned 16-byte access.
+// 8-element operand read is one aligned 16-byte access.  Two buffers of six
+// planes of 64 rows per operand: 120 KiB of LDS per workgroup.
 constexpr int kSgRow = kSgK + 8;
 
-// 16-byte groups (8 k) of a 64-row x 32-k chunk of one operand's 4 planes:
-// 1024 groups, 4 per thread (group g = t + 256 q: plane g / 256, row
-// (g % 256) / 4, k 8 (g % 4)); rows past `rows` and groups starting past `k`
-// read as 0 (the planes are zero between charge blocks, so a group that
+// 16-byte groups (8 k) of a 64-row x 32-k chunk of one operand's six
+// planes: 1536 groups, six per thread (group g = t + 256 q: plane g / 256,
+// row (g % 256) / 4, k 8 (g % 4)); rows past `rows` and groups starting past
+// `k` read as 0 (the planes are zero between charge blocks, so a group that
 // starts inside the range is exact).
-__device__ __forceinline__ void sg_fetch(uint4 (&r)[4], const unsigned short* __restrict__ base, long long pstride,
-                                         int ld, int rows, int k, int row0, int k0) {
+__device__ __forceinline__ void sg_fetch(uint4 (&r)[kSgPlanes], const unsigned short* __restrict__ base,
+                                         long long pstride, int ld, int rows, int k, int row0, int k0) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < kSgPlanes; ++q) {
     const int g = threadIdx.x + 256 * q;
     const int plane = g >> 8, row = (g & 255) >> 2, kg = 8 * (g & 3);
     r[q] = make_uint4(0u, 0u, 0u, 0u);
@@ -240,9 +248,9 @@ __device__ __forceinline__ void sg_fetch(uint4 (&r)[4], const unsigned short* __
   }
 }
 
-__device__ __forceinline__ void sg_stage(const uint4 (&r)[4], unsigned short (*buf)[kSgTile][kSgRow]) {
+__device__ __forceinline__ void sg_stage(const uint4 (&r)[kSgPlanes], unsigned short (*buf)[kSgTile][kSgRow]) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < kSgPlanes; ++q) {
     const int g = threadIdx.x + 256 * q;
     *reinterpret_cast<uint4*>(&buf[g >> 8][(g & 255) >> 2][8 * (g & 3)]) = r[q];
   }
@@ -252,20 +260,35 @@ __device__ __forceinline__ bf16x8 sg_op(const unsigned short (*buf)[kSgTile][kSg
   return *reinterpret_cast<const bf16x8*>(&buf[plane][row][k]);
 }
 
+// Accumulates the six split products of one real product whose parts are
+// x[0..2] (hi, mid, lo) and y[0..2]: the terms x_i y_j with i + j <= 2.  The
+// dropped terms (mid lo, lo mid, lo lo) are below 2^-23 of |x| |y|.
+__device__ __forceinline__ f32x16 sg_real6(const bf16x8* x, const bf16x8* y, f32x16 c) {
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[0], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[1], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[0], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[2], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[2], y[0], c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[1], c, 0, 0, 0);
+  return c;
+}
+
 // One 64 x 64 output tile per workgroup; wave w computes the 32 x 32 quadrant
 // (rows 32 (w / 2), columns 32 (w % 2)) with v_mfma_f32_32x32x16_bf16.  Lane l
 // supplies A[i = l % 32][k = 8 (l / 32) + e] and B[k = 8 (l / 32) + e][j = l % 32]
 // (e = 0..7); its accumulator register r holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
 // Per k step: Re = Ar Br - Ai Bi and Im = Ar Bi + Ai Br, each real product as
-// hi*hi + hi*lo + lo*hi (the lo*lo term is below the split's error), in four
-// accumulators so that no two consecutive products depend.  The k
-// chunks go through two LDS buffers: the next chunk's loads are in flight
-// during the products and are staged into the other buffer, one barrier per
-// chunk.
+// the six split terms of sg_real6, in four accumulators (Ar Br, Ai Bi, Ar Bi,
+// Ai Br) whose chains interleave.  Products of BF16 values are exact in FP32;
+// the matrix cores accumulate one 32-wide k chunk in FP32, and the chunk sums
+// are added in FP64 (so FP32 rounding grows with the chunk, not with k), and
+// the product is stored in complex128.  The k chunks go through two LDS
+// buffers: the next chunk's loads are in flight during the products and are
+// staged into the other buffer, one barrier per chunk.
 __global__ void __launch_bounds__(256)
 split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
-  __shared__ __align__(16) unsigned short sa[2][4][kSgTile][kSgRow];
-  __shared__ __align__(16) unsigned short sb[2][4][kSgTile][kSgRow];
+  __shared__ __align__(16) unsigned short sa[2][kSgPlanes][kSgTile][kSgRow];
+  __shared__ __align__(16) unsigned short sb[2][kSgPlanes][kSgTile][kSgRow];
   int lo = 0, hi = nprob - 1;
   const int tile = blockIdx.x;
   while (lo < hi) {
@@ -278,9 +301,10 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R = 32 * (wave >> 1), Cq = 32 * (wave & 1);
   const int li = lane & 31, lk = 8 * (lane >> 5);
-  // four independent accumulator chains: Re+ (Ar Br), Re- (Ai Bi), Im (Ar Bi), Im (Ai Br)
-  f32x16 crp = {}, crn = {}, cia = {}, cib = {};
-  uint4 ra[4], rb[4];
+  double dre[16], dim[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) dre[r] = dim[r] = 0.0;
+  uint4 ra[kSgPlanes], rb[kSgPlanes];
   sg_fetch(ra, w.a, w.pa, w.lda, w.m, w.k, row0, 0);
   sg_fetch(rb, w.b, w.pb, w.ldb, w.n, w.k, col0, 0);
   sg_stage(ra, sa[0]);
@@ -293,33 +317,28 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
       sg_fetch(ra, w.a, w.pa, w.lda, w.m, w.k, row0, k0 + kSgK);
       sg_fetch(rb, w.b, w.pb, w.ldb, w.n, w.k, col0, k0 + kSgK);
     }
-    // both k steps' operands first, then the 24 products round-robin over the chains
-    bf16x8 a[2][4], b[2][4];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        a[h][p] = sg_op(sa[buf], p, R + li, 16 * h + lk);
-        b[h][p] = sg_op(sb[buf], p, Cq + li, 16 * h + lk);
-      }
     // the second k step of a chunk that ends the segment early is all zero
     const int nks = k0 + 16 < w.k ? 2 : 1;
+    f32x16 crp = {}, crn = {}, cia = {}, cib = {};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (h >= nks) break;
-      // planes: 0 re hi, 1 re lo, 2 im hi, 3 im lo
-      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][0], b[h][0], crp, 0, 0, 0);
-      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][2], b[h][2], crn, 0, 0, 0);
-      cia = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][0], b[h][2], cia, 0, 0, 0);
-      cib = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][2], b[h][0], cib, 0, 0, 0);
-      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][0], b[h][1], crp, 0, 0, 0);
-      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][2], b[h][3], crn, 0, 0, 0);
-      cia = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][0], b[h][3], cia, 0, 0, 0);
-      cib = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][2], b[h][1], cib, 0, 0, 0);
-      crp = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][1], b[h][0], crp, 0, 0, 0);
-      crn = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][3], b[h][2], crn, 0, 0, 0);
-      cia = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][1], b[h][2], cia, 0, 0, 0);
-      cib = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[h][3], b[h][0], cib, 0, 0, 0);
+      // planes 0..2: re hi, mid, lo; 3..5: im hi, mid, lo
+      bf16x8 a[kSgPlanes], b[kSgPlanes];
+#pragma unroll
+      for (int p = 0; p < kSgPlanes; ++p) {
+        a[p] = sg_op(sa[buf], p, R + li, 16 * h + lk);
+        b[p] = sg_op(sb[buf], p, Cq + li, 16 * h + lk);
+      }
+      crp = sg_real6(a, b, crp);
+      crn = sg_real6(a + 3, b + 3, crn);
+      cia = sg_real6(a, b + 3, cia);
+      cib = sg_real6(a + 3, b, cib);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      dre[r] += (double)crp[r] - (double)crn[r];
+      dim[r] += (double)cia[r] + (double)cib[r];
     }
     if (more) {
       // the other buffer was last read before the previous barrier
@@ -334,18 +353,18 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = row0 + R + 8 * (r >> 2) + (lane >> 5) * 4 + (r & 3);
-      if (i < w.m) w.c[(size_t)i * w.ldc + j] = make_float2(crp[r] - crn[r], cia[r] + cib[r]);
+      if (i < w.m) w.c[(size_t)i * w.ldc + j] = make_double2(dre[r], dim[r]);
     }
   }
 }
 
 // Gate mix of the precision form: for the 32 x 32 tile of one charge pair,
 // Theta~(cL, m, cR) = sum_j G^(n)[cL - m][a_j] P_j with the products P_j from
-// the scratch (complex64, upcast), written like the plain kernel's epilogue.
+// the complex128 scratch, written like the plain kernel's epilogue.
 __global__ void __launch_bounds__(256)
 theta_mix_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ tiles,
                  const SectorWork* __restrict__ secs, const double2* __restrict__ coef,
-                 const float2* __restrict__ pbuf, double2* __restrict__ th_raw,
+                 const double2* __restrict__ pbuf, double2* __restrict__ th_raw,
                  double2* __restrict__ th_scaled, double* __restrict__ tile_before) {
   __shared__ double red[4];
   const ThetaTile& t = tiles[blockIdx.x];
@@ -365,8 +384,7 @@ theta_mix_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict
       for (int j = 0; j < kMaxD; ++j) {
         pv[j] = make_double2(0.0, 0.0);
         if (j < nin) {
-          const float2 f = pbuf[t.poff[j] + (size_t)(t.pr0 + r) * t.ldp + t.pc0 + c];
-          pv[j] = make_double2(f.x, f.y);
+          pv[j] = pbuf[t.poff[j] + (size_t)(t.pr0 + r) * t.ldp + t.pc0 + c];
           before = fma(lam * lam, fma(pv[j].x, pv[j].x, pv[j].y * pv[j].y), before);
         }
       }
@@ -418,7 +436,7 @@ hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, hipS
 }
 
 hipError_t launch_theta_mix(const GateWork* gates, const ThetaTile* tiles, int ntiles, const SectorWork* secs,
-                            const double2* coef, const float2* pbuf, double2* raw, double2* scaled,
+                            const double2* coef, const double2* pbuf, double2* raw, double2* scaled,
                             double* tile_before, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(theta_mix_kernel, dim3(ntiles), dim3(256), 0, st, gates, tiles, secs, coef, pbuf, raw, scaled,

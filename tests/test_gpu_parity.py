@@ -320,14 +320,16 @@ def test_serving_form_results_equal_each_request_alone(mps_cls, lanes):
         m.close()
 
 
-# Precision form (split-BF16 charge-triple products).  Each real product is
-# hi*hi + hi*lo + lo*hi of the operands' two BF16 parts, so its error is at most
-# 3 * 2^-18 ~ 1.1e-5 of |a||b| (the dropped lo*lo term plus the split residuals);
-# a gate's Theta therefore carries ~1e-5 relative error and a circuit of G gates
-# up to ~G times that in the worst case (measured: ~2e-5 after 28 gates,
-# ~3-7e-5 after 100-300).  One layer is held to 5e-5, whole circuits to 2e-4.
-TOL_SPLIT_LAYER = 5e-5
-TOL_SPLIT_CIRCUIT = 2e-4
+# Precision form (split-BF16 charge-triple products).  Every operand entry is
+# split into three BF16 parts (hi + mid + lo: 2^-23 relative, the FP32
+# conversion included) and each real product keeps the six part products of
+# total order <= 2, so one product is off by at most ~3 * 2^-23 of |a||b|; the
+# matrix cores sum 32-wide k chunks in FP32 (at most 32 * 2^-24 of the chunk's
+# sum of |a||b|, about sqrt(32) * 2^-24 typically) and the chunks are added in
+# FP64.  A gate's Theta is thus within a few 1e-7 of its FP64 value; the stated
+# bar for the FP32-accuracy forms, 1e-5 relative, holds with margin for a
+# layer and for circuits of hundreds of gates (measured 2e-7 to 6e-7).
+TOL_SPLIT = 1e-5
 
 
 def test_precision_form_one_layer_on_entangled_state(mps_cls):
@@ -339,11 +341,11 @@ def test_precision_form_one_layer_on_entangled_state(mps_cls):
         m.apply_layer([g.site for g in lay], [g.u for g in lay])
     pats = circuits.sample_patterns(12, 6, 4, 256, 6)
     ref, got = states[0].amplitudes(pats), states[1].amplitudes(pats)
-    close_amps(got, ref, TOL_SPLIT_LAYER)
+    close_amps(got, ref, TOL_SPLIT)
     # full-rank random sectors, no cap: the cut cannot depend on the noise
     for b in range(13):
         assert states[1].bond_sectors(b) == states[0].bond_sectors(b), b
-    assert abs(states[1].norm2() - states[0].norm2()) <= TOL_SPLIT_LAYER * states[0].norm2()
+    assert abs(states[1].norm2() - states[0].norm2()) <= TOL_SPLIT * states[0].norm2()
     for m in states:
         m.close()
 
@@ -356,8 +358,8 @@ def test_precision_form_exact_circuit_vs_permanents(mps_cls):
         m.apply_gate(g.site, g.u)
     pats = circuits.all_patterns(8, 4, 5)
     exact = np.array([permanent.fock_amplitude(cfg["unitary"], cfg["occupation"], p) for p in pats])
-    close_amps(m.amplitudes(pats), exact, TOL_SPLIT_CIRCUIT)
-    assert abs(m.norm2() - 1.0) <= TOL_SPLIT_CIRCUIT
+    close_amps(m.amplitudes(pats), exact, TOL_SPLIT)
+    assert abs(m.norm2() - 1.0) <= TOL_SPLIT
     m.close()
 
 
@@ -369,8 +371,8 @@ def test_precision_form_brickwork_vs_oracle(mps_cls):
         m.apply_layer([g.site for g in lay], [g.u for g in lay])
     ref = dense_mps.DenseMPS(cfg["occupation"], 4, chi_max=0, cutoff=1e-12).run(cfg["gates"])
     pats = circuits.sample_patterns(12, 6, 4, 256, 8)
-    close_amps(m.amplitudes(pats), ref.amplitudes(pats), TOL_SPLIT_CIRCUIT)
-    assert abs(m.norm2() - ref.norm2()) <= TOL_SPLIT_CIRCUIT * ref.norm2()
+    close_amps(m.amplitudes(pats), ref.amplitudes(pats), TOL_SPLIT)
+    assert abs(m.norm2() - ref.norm2()) <= TOL_SPLIT * ref.norm2()
     m.close()
 
 
@@ -379,11 +381,13 @@ def test_precision_workload_chi256_vs_stored_oracle(mps_cls):
     2016 gates, seed 3) at chi_max = 256 against the oracle's stored results
     (tests/golden, from oracle/ only): the plain form to the complex128 bar on
     1025 amplitudes, every bond's charges, every gate's discarded weight and the
-    norm; the split-BF16 form to its accumulated bound.  Each gate is a
-    contraction (norm non-increasing) that adds at most ~3 * 2^-18 of the norm
-    through the split products, so 2016 gates stay within 2016 * 1.1e-5 = 2.2e-2
-    normwise; the cut binds at chi_max, so the split form's bookkeeping is only
-    compared where no stored cut margin is below the products' noise."""
+    norm; the split-BF16 form to the 1e-5 bar of the FP32-accuracy forms on the
+    same amplitudes and the norm.  The split form's Schmidt values carry noise
+    of order 1e-6 of the bond's largest, so its cut decisions are fixed where
+    the stored cut margin is above 1e-5: its bookkeeping must equal the plain
+    form's, bond by bond after every layer, while every gate so far had such a
+    margin; after the first gate below it, mismatching bonds are counted and
+    reported, and every gate's discarded weight is held to 1e-5 of the norm."""
     import json
     import os
     from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
@@ -392,9 +396,23 @@ def test_precision_workload_chi256_vs_stored_oracle(mps_cls):
     cfg = circuits.config_precision(seed=3, chi_max=256)
     pats = np.array(ref["patterns"], dtype=np.int32)
     amp = np.array(ref["amp_re"]) + 1j * np.array(ref["amp_im"])
-    m, disc = run_gpu(mps_cls, cfg["occupation"], 4, None, chi_max=256, cutoff=1e-12, layered=True,
-                      layers=cfg["layers"])
-    assert np.max(np.abs(disc - np.array(ref["discarded"]))) <= 1e-12
+    m = mps_cls(cfg["occupation"], 4, chi_max=256, cutoff=1e-12)
+    s = mps_cls(cfg["occupation"], 4, chi_max=256, cutoff=1e-12, form=FORM_SPLIT_BF16X3)
+    margin = np.array([x if x is not None else np.inf for x in ref["margin"]])
+    disc, sdisc, g0, mismatched = [], [], 0, 0
+    for lay in cfg["layers"]:
+        sites, us = [g.site for g in lay], [g.u for g in lay]
+        disc.extend(m.apply_layer(sites, us))
+        sdisc.extend(s.apply_layer(sites, us))
+        g0 += len(lay)
+        decided = bool(np.all(margin[:g0] > 1e-5))
+        for b in range(65):
+            if s.bond_sectors(b) != m.bond_sectors(b):
+                assert not decided, (g0, b)
+                mismatched += 1
+    print(f"split form: first cut margin below 1e-5 at gate {int(np.argmax(margin <= 1e-5))}, "
+          f"{mismatched} bond/layer bookkeeping mismatches after it")
+    assert np.max(np.abs(np.array(disc) - np.array(ref["discarded"]))) <= 1e-12
     # the closest cut of the stored run has margin 5.6e-10 of s_0, far above the
     # ~1e-13 relative error of the FP64 singular values, so every cut agrees
     assert min(x for x in ref["margin"] if x is not None) > 1e-10
@@ -403,18 +421,13 @@ def test_precision_workload_chi256_vs_stored_oracle(mps_cls):
         assert m.bond_sectors(b) == exp, b
     close_amps(m.amplitudes(pats), amp)
     assert abs(m.norm2() - ref["norm2"]) <= 1e-9 * ref["norm2"]
-    m.close()
-    s = mps_cls(cfg["occupation"], 4, chi_max=256, cutoff=1e-12, form=FORM_SPLIT_BF16X3)
-    for lay in cfg["layers"]:
-        s.apply_layer([g.site for g in lay], [g.u for g in lay])
+    assert np.max(np.abs(np.array(sdisc) - np.array(ref["discarded"]))) <= TOL_SPLIT
     got = s.amplitudes(pats)
     err = float(np.linalg.norm(got - amp) / np.linalg.norm(amp))
-    assert err <= 2016 * 1.1e-5, err
-    assert abs(s.norm2() - ref["norm2"]) <= 2016 * 1.1e-5 * ref["norm2"]
-    margins = [x for x in ref["margin"] if x is not None]
-    if min(margins) > 1e-4:
-        for b in range(65):
-            assert s.bond_sectors(b) == {int(k): v for k, v in ref["bond_charges"][b].items()}, b
+    print(f"split form after 2016 gates: amplitudes {err:.3e} normwise")
+    close_amps(got, amp, TOL_SPLIT)
+    assert abs(s.norm2() - ref["norm2"]) <= TOL_SPLIT * ref["norm2"]
+    m.close()
     s.close()
 
 
@@ -762,9 +775,8 @@ def test_dense_and_sampling_edges(mps_cls):
 
 def test_precision_form_with_dense_gates(mps_cls):
     """The split-BF16 form takes dense Trotter gates like mode unitaries: a
-    Bose-Hubbard evolution with an active cut stays within the accumulated
-    product bound of the plain form's amplitudes, and both agree with the
-    oracle's norm to that bound."""
+    Bose-Hubbard evolution with an active cut (50 gates) stays within the 1e-5
+    bar of the plain form's amplitudes and norm."""
     from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
     from workloads import hamiltonians as ham
     cfg = ham.config_tebd("bose_hubbard", 10, 4, [1, 2] * 5, 0.15, 5, 20, 1e-12, J=1.0, U=1.5, mu=0.1)
@@ -774,10 +786,8 @@ def test_precision_form_with_dense_gates(mps_cls):
         s.apply_layer_dense([g.site for g in lay], [g.g4 for g in lay])
     pats = circuits.sample_patterns(10, 15, 4, 300, 8)
     a, b = p.amplitudes(pats), s.amplitudes(pats)
-    ng = len(cfg["gates"])
-    err = float(np.linalg.norm(a - b) / np.linalg.norm(a))
-    assert err <= ng * 1.1e-5, err
-    assert abs(s.norm2() - p.norm2()) <= ng * 1.1e-5 * p.norm2()
+    close_amps(b, a, TOL_SPLIT)
+    assert abs(s.norm2() - p.norm2()) <= TOL_SPLIT * p.norm2()
     p.close()
     s.close()
 
@@ -880,8 +890,8 @@ def test_zn_rules(mps_cls):
 
 
 def test_zn_precision_form(mps_cls):
-    """The split-BF16 form on a Z_3 state stays within the accumulated product
-    bound of the plain form."""
+    """The split-BF16 form on a Z_3 state stays within the 1e-5 bar of the
+    plain form."""
     from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
     from workloads import hamiltonians as ham
     cfg = _zn_case("clock")
@@ -889,7 +899,6 @@ def test_zn_precision_form(mps_cls):
     s, _ = run_zn(mps_cls, cfg, form=FORM_SPLIT_BF16X3)
     pats = ham.zn_patterns(cfg["L"], 3, sum(cfg["occupation"]), 300, 6)
     a, b = p.amplitudes(pats), s.amplitudes(pats)
-    ng = len(cfg["gates"])
-    assert float(np.linalg.norm(a - b) / np.linalg.norm(a)) <= ng * 1.1e-5
+    close_amps(b, a, TOL_SPLIT)
     p.close()
     s.close()
