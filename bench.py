@@ -11,7 +11,8 @@ region (inputs resident in HBM).
 
 Printed: one JSON line (stdout) with gate applies/s, the roofline of the
 dominant kernel (HIP events on the library's stream over the timed region)
-and the CPU oracle timed on a bounded prefix of the same circuit; under
+and the CPU oracle timed on saturated gates of the same shape (the whole
+circuit's oracle time estimated from them); under
 "forms", the batching form (several circuits per launch: copies of this
 circuit with other seeds, and the first circuits of the mixed-size workload)
 and the serving form (Poisson arrivals, continuous batching, p50/p99 latency
@@ -84,32 +85,100 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(cfg, seconds: float):
-    """The oracle (dense TEBD, NumPy/LAPACK) on the first layers of the same circuit."""
-    from oracle import dense_mps
+def cpu_info() -> dict:
+    """Host CPU model, the cores this process may run on and the BLAS threads."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        blas = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
-        threads = os.cpu_count() or 1
-    m = dense_mps.DenseMPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"])
-    t0 = time.perf_counter()
-    gates = 0
-    done = False
-    for lay in cfg["layers"]:
-        for g in lay:
-            m.apply_gate(g.site, g.u)
-            gates += 1
-            if time.perf_counter() - t0 >= seconds:
-                done = True
-                break
-        if done:
+        blas = affinity
+    return {"cpu_model": model, "affinity_cores": affinity, "blas_threads": int(blas)}
+
+
+def cpu_baseline(cfg, shapes, budget: float = 60.0):
+    """The oracle (dense TEBD, NumPy/LAPACK, complex128) timed per gate on
+    saturated states of the same shape as the benchmark circuit's bonds, and
+    the whole circuit's oracle time estimated from them.
+
+    A gate of the oracle costs one dense (chi_s d) x (d chi_{s+2}) SVD plus
+    BLAS-3 products; its time is measured on a synthetic saturated state
+    (L=32, N=16, d=4; circuits.synthetic_state at chi = 64, 128, 256, 512,
+    imported by Eq. (E2)) at the central gate of the circuit's first layer.
+    ``shapes`` lists the (chi_s, chi_{s+2}) of every gate of the circuit (from
+    the GPU run); each gate is charged the measured time of the sample with
+    the nearest m n min(m, n) (m, n the dense matrix's sides), scaled by that
+    product.  A sample predicted to exceed ``budget`` seconds is skipped (the
+    largest one measured then stands for the larger gates).  Also reported: the
+    saturated rate at the largest sample alone, and one chi=128 gate on one
+    thread beside the same gate on all BLAS threads."""
+    import numpy as np
+    from oracle import dense_mps
+    from workloads import circuits
+    info = cpu_info()
+    L, N, d = cfg["L"], sum(cfg["occupation"]), cfg["d"]
+    gate = {g.site: g for g in circuits.brickwork_layers(L, 1, 2)[0]}[L // 2 - 2]
+    samples = []
+    t_all = time.perf_counter()
+    for chi in (64, 128, 256, 512):
+        # a doubling of chi costs about 8x: stop before a sample would overrun the budget
+        if samples and samples[-1]["seconds"] * 8.0 > budget:
             break
-    el = time.perf_counter() - t0
-    return {"value": gates / el, "unit": "gate applies/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {gates} of {sum(len(l) for l in cfg['layers'])} gates (layer order) of the same "
-                      f"circuit, max bond dim reached {max(m.bond_dims())}; dense (chi*d)x(d*chi) complex128 "
-                      f"SVD per gate; {el:.1f} s"}
+        ch, gam, lam = circuits.synthetic_state(L, N, d, chi, seed=31)
+        m = dense_mps.DenseMPS.from_vidal(d, N, ch, gam, lam, chi_max=chi, cutoff=cfg["cutoff"])
+        del gam
+        s = gate.site
+        dm, dn = m.t[s].shape[0] * d, d * m.t[s + 1].shape[2]
+        t0 = time.perf_counter()
+        m.apply_gate(s, gate.u)
+        samples.append({"chi": chi, "m": dm, "n": dn, "seconds": time.perf_counter() - t0})
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        ch, gam, lam = circuits.synthetic_state(L, N, d, 128, seed=31)
+        m = dense_mps.DenseMPS.from_vidal(d, N, ch, gam, lam, chi_max=128, cutoff=cfg["cutoff"])
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            m.apply_gate(gate.site, gate.u)
+            t1 = time.perf_counter() - t0
+        single = {"chi": 128, "seconds_one_thread": t1,
+                  "seconds_all_threads": next(x["seconds"] for x in samples if x["chi"] == 128)}
+    except Exception:
+        pass
+    sampled = time.perf_counter() - t_all
+
+    def work(m_, n_):
+        return float(m_) * n_ * min(m_, n_)
+
+    logw = np.array([np.log(work(x["m"], x["n"])) for x in samples])
+    est = 0.0
+    for cl, cr in shapes:
+        w = work(cl * d, d * cr)
+        k = int(np.argmin(np.abs(logw - np.log(w))))
+        est += samples[k]["seconds"] * w / work(samples[k]["m"], samples[k]["n"])
+    sat = samples[-1]
+    return {"value": len(shapes) / est, "unit": "gate applies/s", "cores": info["blas_threads"],
+            "kind": "oracle",
+            "sample": f"one gate (central site, layer 1, seed 2) on each saturated synthetic state of the "
+                      f"benchmark's shape (L=32, N=16, d=4; chi = {', '.join(str(x['chi']) for x in samples)}): dense (chi d) x (d chi) "
+                      f"complex128 SVD per gate, {sampled:.1f} s in total; the circuit's {len(shapes)} gates "
+                      f"charged by their (chi_s d) x (d chi_s+2) shapes from the GPU run, nearest sample "
+                      f"scaled by m n min(m, n): estimated {est:.0f} s for the whole circuit",
+            "circuit_seconds_estimate": est,
+            "saturated_gate_applies_per_s": {"chi": sat["chi"], "value": 1.0 / sat["seconds"]},
+            "samples": samples, "single_thread": single, **info}
 
 
 def sample_flops(m, pats):
@@ -196,12 +265,13 @@ def run_batched(cfgs, MPS, apply_batch, dev, keep_first=False):
     return gates, el, first
 
 
-def run_serving(args, rate, dev, circuits):
+def run_serving(args, rate, window, circuits):
     """One serving window: Poisson arrivals at `rate` of the serving mix, continuous
-    batching, results read out at completion; no drain after the window."""
+    batching, results read out at completion; no drain after the window (requests
+    unfinished at its end are reported as censored)."""
     import numpy as np
     from paper_2303_11409_amd import serving
-    n = int(rate * args.serve_seconds * 1.2) + 8
+    n = int(rate * window * 1.2) + 8
     specs = circuits.serving_mix_specs(n, seed=5)
     reqs = serving.poisson_requests(specs, rate=rate, seed=5, build=circuits.config_from_spec, n_patterns=16)
     import torch
@@ -210,22 +280,34 @@ def run_serving(args, rate, dev, circuits):
     devs = [TorchDevice(stream=torch.cuda.Stream()) for _ in range(2)]
     srv = serving.Server(int(args.serve_budget_gib * 2**30), max_active=args.serve_max_active, devices=devs,
                          lane_of=lambda sp: 0 if sp["chi_max"] >= 1024 else 1)
-    rep = srv.run(reqs, until=args.serve_seconds)
+    rep = srv.run(reqs, until=window)
     lat = rep.latencies()
+    cens = rep.censored_latencies()
     arrived = sum(1 for r in reqs if r.arrival < rep.seconds)
     done_gates = sum(len(r.cfg["gates"]) for r in rep.completed)
-    mean_gates = float(np.mean([sp["depth"] * (sp["L"] // 2) - (sp["depth"] // 2) * (1 - sp["L"] % 2)
-                                for sp in specs]))
+
+    def gates_of(sp):
+        return sp["depth"] * (sp["L"] // 2) - (sp["depth"] // 2) * (1 - sp["L"] % 2)
+
+    mean_gates = float(np.mean([gates_of(sp) for sp in specs]))
+    executed = rep.gates / rep.seconds
     return {
         "arrival_rate": rate, "window_s": rep.seconds, "arrived": arrived, "completed": len(rep.completed),
-        "pending": rep.pending, "iterations": rep.iterations, "peak_active": rep.peak_active,
-        "peak_admitted_gib": rep.peak_bytes / 2**30,
-        "gate_applies_per_s": rep.gates / rep.seconds,
+        "completed_over_arrived": len(rep.completed) / max(arrived, 1),
+        "pending": rep.pending, "refused": len(rep.refused), "iterations": rep.iterations,
+        "peak_active": rep.peak_active, "peak_admitted_gib": rep.peak_bytes / 2**30,
+        "gate_applies_per_s": executed,
         "completed_gate_applies_per_s": done_gates / rep.seconds,
         "requests_per_s": len(rep.completed) / rep.seconds,
-        "latency_s": {"p50": percentile(list(lat), 50), "p99": percentile(list(lat), 99),
-                      "max": float(lat.max()) if lat.size else None},
+        # every arrival: unfinished requests count as censored at the window's end
+        # (arrival to end), so these percentiles are lower bounds over all arrivals
+        "latency_all_arrivals_censored_s": {"p50": percentile(list(cens), 50), "p99": percentile(list(cens), 99),
+                                            "censored": rep.pending},
+        "latency_completed_s": {"p50": percentile(list(lat), 50), "p99": percentile(list(lat), 99),
+                                "max": float(lat.max()) if lat.size else None},
         "offered_gate_applies_per_s": rate * mean_gates,
+        # arrivals per second the measured gate rate could sustain for this mix
+        "sustainable_arrival_rate": executed / mean_gates,
     }
 
 
@@ -295,7 +377,6 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-copies", type=int, default=8,
                     help="batching form: seeds of the same circuit run together (0 = skip)")
@@ -303,8 +384,10 @@ def main() -> int:
                     help="batching form: first circuits of the mixed-size workload run together (0 = skip)")
     ap.add_argument("--no-chi2048", action="store_true",
                     help="skip the sector-product measurement on a chi=2048 layer")
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
-                    help="serving form: length of each serving window (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="serving form: length of the serving window at --serve-rate (0 = skip)")
+    ap.add_argument("--serve-low-seconds", type=float, default=20.0,
+                    help="serving form: length of the window at --serve-low-rate")
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serving form: arrivals per second")
     ap.add_argument("--serve-low-rate", type=float, default=0.5,
                     help="serving form: a second window at this rate, within the device's capacity (0 = skip)")
@@ -347,12 +430,26 @@ def main() -> int:
             m.apply_layer(sites, us)
         m.sync()
 
-    for w in range(args.warmup):
+    def run_shapes(m):
+        """The circuit once, recording each gate's outer bond dimensions."""
+        shapes = []
+        for sites, us in layers:
+            dims = m.bond_dims()
+            shapes.extend((dims[s], dims[s + 2]) for s in sites)
+            m.apply_layer(sites, us)
+        m.sync()
+        return shapes
+
+    shapes = None
+    for w in range(max(args.warmup, 1)):
         t = time.perf_counter()
         m = new_state()
-        run(m)
+        if shapes is None:
+            shapes = run_shapes(m)
+        else:
+            run(m)
         m.close()
-        log(f"warmup {w + 1}/{args.warmup}: {time.perf_counter() - t:.2f} s")
+        log(f"untimed run {w + 1}: {time.perf_counter() - t:.2f} s")
 
     states = [new_state() for _ in range(args.steps)]
     for m in states:
@@ -468,18 +565,19 @@ def main() -> int:
             log(f"  {r['value']:.1f} gate applies/s, max bond dim {r['max_bond_dim']}")
     if args.serve_seconds > 0:
         log(f"serving form: {args.serve_seconds:.0f} s at {args.serve_rate:g} requests/s ...")
-        forms["serving"] = run_serving(args, args.serve_rate, dev, circuits)
+        forms["serving"] = run_serving(args, args.serve_rate, args.serve_seconds, circuits)
         forms["serving"]["workload"] = (
             "Poisson arrivals of the serving mix (95% batching-mix circuits, 5% L=64, 32 photons, "
             "chi_max=1024, depth 64; request j seed 5000+j, 16 sampled amplitudes each), admitted by "
             f"an HBM budget of {args.serve_budget_gib:g} GiB and at most {args.serve_max_active} active per "
             "lane, two lanes (chi_max=1024 requests, the rest) each on its own stream and host thread, one "
-            "batch call per layer of all active requests of a lane; window without drain")
+            "batch call per layer of all active requests of a lane; window without drain, unfinished "
+            "requests reported as censored")
         log(f"  {forms['serving']['gate_applies_per_s']:.1f} gate applies/s, "
             f"{forms['serving']['completed']} completed")
-        if args.serve_low_rate > 0:
-            log(f"serving form: {args.serve_seconds:.0f} s at {args.serve_low_rate:g} requests/s ...")
-            low = run_serving(args, args.serve_low_rate, dev, circuits)
+        if args.serve_low_rate > 0 and args.serve_low_seconds > 0:
+            log(f"serving form: {args.serve_low_seconds:.0f} s at {args.serve_low_rate:g} requests/s ...")
+            low = run_serving(args, args.serve_low_rate, args.serve_low_seconds, circuits)
             low["note"] = "same mix at an arrival rate within the device's capacity"
             forms["serving_low_rate"] = low
             log(f"  {low['gate_applies_per_s']:.1f} gate applies/s, {low['completed']} completed")
@@ -523,8 +621,9 @@ def main() -> int:
                    "max_discarded": agg["max_discarded"], "min_cut_margin": agg["min_margin"]},
     }
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded prefix ...")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        log("timing the CPU oracle on saturated gates of the benchmark's shape ...")
+        out["cpu_baseline"] = cpu_baseline(cfg, shapes)
+        log(f"  {out['cpu_baseline']['value']:.3f} gate applies/s (whole-circuit estimate)")
     print(json.dumps(out), flush=True)
     return 0
 

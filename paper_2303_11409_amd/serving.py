@@ -12,7 +12,9 @@ an iteration of one lane does not wait for the slowest sector of another and
 the lanes' kernels fill the device together.
 A request whose last layer is done is retired: its result (norm, summed
 discarded weight, sampled amplitudes) is read out, its device memory returns to
-the budget and its latency (arrival to result) is recorded.
+the budget and its latency (arrival to result) is recorded.  A request whose
+footprint alone exceeds the budget can never be admitted: it is refused (it
+gets an error result at once) and the loop goes on with the others.
 
 The per-request device footprint used for admission is the state's allocation
 bound: site tensors of cap[s] x cap[s+1] complex128 and Schmidt vectors of
@@ -96,6 +98,7 @@ class Request:
     admitted_at: float = math.nan
     done_at: float = math.nan
     result: Optional[dict] = None
+    refused: Optional[str] = None      # why the request was refused admission
 
     def materialize(self) -> None:
         from workloads import circuits as _c  # circuit and pattern generators (inputs only)
@@ -109,7 +112,9 @@ class Request:
 @dataclass
 class ServeReport:
     completed: List[Request] = field(default_factory=list)
-    pending: int = 0                   # arrived but not finished when the run ended
+    refused: List[Request] = field(default_factory=list)
+    unfinished: List[Request] = field(default_factory=list)   # arrived, not done when the run ended
+    pending: int = 0                   # len(unfinished)
     iterations: int = 0
     gates: int = 0
     seconds: float = 0.0
@@ -117,7 +122,17 @@ class ServeReport:
     peak_bytes: int = 0
 
     def latencies(self) -> np.ndarray:
+        """Arrival to result of the completed requests."""
         return np.array([r.done_at - r.arrival for r in self.completed])
+
+    def censored_latencies(self) -> np.ndarray:
+        """Every arrived, admissible request: the completed ones' latencies and,
+        for a request still waiting or running when the run ended, the time from
+        its arrival to the end (a lower bound of its latency).  Percentiles of
+        this set are lower bounds of the percentiles over all arrivals."""
+        done = [r.done_at - r.arrival for r in self.completed]
+        cut = [max(0.0, self.seconds - r.arrival) for r in self.unfinished]
+        return np.array(done + cut)
 
 
 def finish(req: Request) -> dict:
@@ -161,20 +176,18 @@ class Server:
         self._t0 = time.perf_counter()
         nl = len(self.devices)
         queues: List[List[Request]] = [[] for _ in range(nl)]
+        rep = ServeReport()
         for r in sorted(requests, key=lambda r: r.arrival):
             sp = r.spec
             r.bytes = state_bytes(sp["L"], sp["n_photons"], sp["d"], sp["chi_max"])
-            if r.bytes > self.hbm_budget:
-                raise ValueError(f"request {r.rid} needs {r.bytes} bytes, more than the budget")
             lane = int(self.lane_of(sp))
             if not 0 <= lane < nl:
                 raise ValueError(f"lane {lane} of request {r.rid} outside 0..{nl - 1}")
             queues[lane].append(r)
         self._used = 0
         self._active_total = 0
-        rep = ServeReport()
         errors: List[BaseException] = []
-        pending = [0] * nl
+        pending: List[List[Request]] = [[] for _ in range(nl)]
 
         def lane_loop(k: int) -> None:
             try:
@@ -192,11 +205,13 @@ class Server:
                 t.join()
         if errors:
             raise errors[0]
-        rep.pending = sum(pending)
         rep.seconds = self.now()
+        rep.unfinished = sorted((r for p in pending for r in p), key=lambda r: r.arrival)
+        rep.pending = len(rep.unfinished)
+        rep.refused.sort(key=lambda r: r.arrival)
         return rep
 
-    def _lane(self, k: int, queue: List[Request], rep: ServeReport, until: Optional[float]) -> int:
+    def _lane(self, k: int, queue: List[Request], rep: ServeReport, until: Optional[float]) -> List[Request]:
         active: List[Request] = []
         qi = 0
         try:
@@ -207,6 +222,15 @@ class Server:
                 # admit every arrived request of this lane that fits, in arrival order
                 while qi < len(queue) and queue[qi].arrival <= t and len(active) < self.max_active:
                     r = queue[qi]
+                    if r.bytes > self.hbm_budget:
+                        # can never fit: refuse it and serve the others
+                        r.refused = f"needs {r.bytes} bytes of device memory, more than the budget"
+                        r.result = {"error": r.refused}
+                        r.done_at = t
+                        with self._lock:
+                            rep.refused.append(r)
+                        qi += 1
+                        continue
                     with self._lock:
                         if self._used + r.bytes > self.hbm_budget:
                             break
@@ -262,7 +286,8 @@ class Server:
                 if r.state is not None:
                     r.state.close()
                     r.state = None
-        return len(active) + sum(1 for r in queue[qi:] if until is None or r.arrival < until)
+        end = self.now()
+        return active + [r for r in queue[qi:] if r.arrival < end and r.bytes <= self.hbm_budget]
 
 
 def poisson_requests(specs: Sequence[dict], rate: float, seed: int, build: Optional[Callable] = None,

@@ -84,12 +84,65 @@ def test_scheduler_continuous_batching_and_budget(monkeypatch):
         assert r.result["amplitudes"].shape == (4,)
 
 
-def test_scheduler_rejects_oversized_request(monkeypatch):
+def test_scheduler_refuses_oversized_request_and_keeps_serving(monkeypatch):
+    """A request whose footprint exceeds the whole budget is refused at its
+    arrival (error result, no state created) while the others are served."""
+    def fake_batch(states, layers):
+        return [np.zeros(len(s)) for s, _ in layers]
+
     monkeypatch.setattr(serving, "MPS", FakeState)
-    cfgs = circuits.config_batch_mix(1, seed=3, l_range=(8, 8), chi_choices=(16,))
-    reqs = serving.poisson_requests(cfgs, rate=1.0, seed=1)
-    with pytest.raises(ValueError):
-        serving.Server(1000).run(reqs)
+    monkeypatch.setattr(serving, "apply_batch", fake_batch)
+    small = circuits.config_batch_mix(3, seed=3, l_range=(6, 8), chi_choices=(8,))
+    big = circuits.config_batch_mix(1, seed=5, l_range=(12, 12), chi_choices=(64,))
+    cfgs = [small[0], big[0], small[1], small[2]]
+    reqs = serving.poisson_requests(cfgs, rate=1.0, seed=1, n_patterns=4)
+    for i, r in enumerate(reqs):
+        r.arrival = [0, 1, 2, 3][i]
+    clock = {"t": -1.0}
+
+    def tick():
+        clock["t"] += 1.0
+        return clock["t"]
+
+    per = [serving.state_bytes(c["L"], sum(c["occupation"]), 4, c["chi_max"]) for c in cfgs]
+    budget = 2 * max(per[0], per[2], per[3])
+    assert per[1] > budget
+    rep = serving.Server(budget, clock=tick).run(reqs)
+    assert [r.rid for r in rep.refused] == [1]
+    assert "error" in rep.refused[0].result and rep.refused[0].state is None
+    assert sorted(r.rid for r in rep.completed) == [0, 2, 3]
+    assert rep.pending == 0 and FakeState.live == 0
+
+
+def test_scheduler_reports_unfinished_requests_as_censored(monkeypatch):
+    """A window that ends while requests wait or run reports them: pending
+    counts them, and the censored latencies (arrival to the window's end) join
+    the completed ones, so percentiles over all arrivals are not computed over
+    the survivors only."""
+    def fake_batch(states, layers):
+        return [np.zeros(len(s)) for s, _ in layers]
+
+    monkeypatch.setattr(serving, "MPS", FakeState)
+    monkeypatch.setattr(serving, "apply_batch", fake_batch)
+    cfgs = circuits.config_batch_mix(5, seed=3, l_range=(6, 8), chi_choices=(8,))
+    reqs = serving.poisson_requests(cfgs, rate=1.0, seed=1, n_patterns=4)
+    for i, r in enumerate(reqs):
+        r.arrival = [0, 0, 0, 0, 0][i]
+    clock = {"t": -1.0}
+
+    def tick():
+        clock["t"] += 1.0
+        return clock["t"]
+
+    per = [serving.state_bytes(c["L"], sum(c["occupation"]), 4, c["chi_max"]) for c in cfgs]
+    rep = serving.Server(sum(per), max_active=1, clock=tick).run(reqs, until=12.0)
+    assert 0 < len(rep.completed) < 5
+    assert rep.pending == 5 - len(rep.completed) == len(rep.unfinished)
+    cens = rep.censored_latencies()
+    assert cens.size == 5
+    assert np.all(cens[len(rep.completed):] >= 0.0)
+    assert cens.max() >= rep.latencies().max()
+    assert FakeState.live == 0
 
 
 def test_scheduler_lanes(monkeypatch):
