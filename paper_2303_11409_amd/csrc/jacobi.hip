@@ -53,20 +53,28 @@ __device__ __forceinline__ bool jac_rotation(double al, double be, double gr, do
                                              double floor_g, double& c, double& wr, double& wi) {
   // test on squares: |gamma|^2 > tol^2 alpha beta and |gamma| > floor
   const double g2 = gr * gr + gi * gi;
-  if (!(g2 > tol * tol * al * be) || !(g2 > floor_g * floor_g)) return false;
+  const bool rot = (g2 > tol * tol * al * be) && (g2 > floor_g * floor_g);
   // with delta = beta - alpha, r = sqrt(delta^2 + 4|gamma|^2), D = |delta| + r:
-  // c = D / E, w = 2 sgn(delta) gamma / E with E^2 = D^2 + 4|gamma|^2 = 2 r D --
-  // the same rotation as t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
-  // zeta = delta / (2|gamma|), c = 1/sqrt(1 + t^2), w = c t gamma/|gamma|
+  // c = D / E, w = 2 sgn(delta) gamma / E with E^2 = D^2 + 4|gamma|^2 (= 2 r D)
+  // -- the rotation t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)),
+  // zeta = delta / (2|gamma|), c = 1/sqrt(1 + t^2), w = c t gamma/|gamma|.
+  // Only the angle depends on r, so r is taken from the hardware reciprocal
+  // square root without refinement (relative error far below what a sweep
+  // needs: the pair is left with a cosine of that order instead of 0); E is
+  // formed from the D actually used and inverted to full precision, so
+  // c^2 + |w|^2 = 1 to rounding.  Computed without branches (the identity is
+  // selected when the pair is below the thresholds), so that the rotations of
+  // several pairs interleave.
   const double delta = be - al;
-  const double r = sqrt(delta * delta + 4.0 * g2);
+  const double x = fma(delta, delta, 4.0 * g2);
+  const double r = x * __builtin_amdgcn_rsq(x);
   const double D = fabs(delta) + r;
-  const double inv = rsqrt(2.0 * r * D);
+  const double inv = rsqrt(fma(D, D, 4.0 * g2));
   const double sg = delta >= 0.0 ? 2.0 * inv : -2.0 * inv;
-  c = D * inv;
-  wr = sg * gr;
-  wi = sg * gi;
-  return true;
+  c = rot ? D * inv : 1.0;
+  wr = rot ? sg * gr : 0.0;
+  wi = rot ? sg * gi : 0.0;
+  return rot;
 }
 
 // Default threshold: (vector length) * eps, but never below 2 * kJP * eps,
@@ -334,23 +342,23 @@ __device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*g1)[kJP + 1], dou
       int pa, qa, pb, qb;
       jac_pair_fast(s2, A, pa, qa);
       jac_pair_fast(s2, B, pb, qb);
-      double ca = 1.0, wra = 0.0, wia = 0.0, cb = 1.0, wrb = 0.0, wib = 0.0;
+      // every LDS read of the step first, so that their latencies overlap
       const double2 ga = cur[pa][qa], gb = cur[pb][qb];
-      const bool fa = jac_rotation(cur[pa][pa].x, cur[qa][qa].x, ga.x, ga.y, tol, floor_g, ca, wra, wia);
-      const bool fb = jac_rotation(cur[pb][pb].x, cur[qb][qb].x, gb.x, gb.y, tol, floor_g, cb, wrb, wib);
+      const double apa = cur[pa][pa].x, aqa = cur[qa][qa].x, apb = cur[pb][pb].x, aqb = cur[qb][qb].x;
       double2 g00 = cur[pa][pb], g01 = cur[pa][qb], g10 = cur[qa][pb], g11 = cur[qa][qb];
-      if (fa) {                   // rows pa, qa: U from the left, also on W
-        double2 w00 = ws[pa][pb], w01 = ws[pa][qb], w10 = ws[qa][pb], w11 = ws[qa][qb];
-        rot_pair(g00, g10, ca, wra, wia);
-        rot_pair(g01, g11, ca, wra, wia);
-        rot_pair(w00, w10, ca, wra, wia);
-        rot_pair(w01, w11, ca, wra, wia);
-        ws[pa][pb] = w00; ws[pa][qb] = w01; ws[qa][pb] = w10; ws[qa][qb] = w11;
-      }
-      if (fb) {                   // columns pb, qb: U^H from the right
-        rot_pair(g00, g01, cb, wrb, -wib);
-        rot_pair(g10, g11, cb, wrb, -wib);
-      }
+      double2 w00 = ws[pa][pb], w01 = ws[pa][qb], w10 = ws[qa][pb], w11 = ws[qa][qb];
+      double ca, wra, wia, cb, wrb, wib;
+      jac_rotation(apa, aqa, ga.x, ga.y, tol, floor_g, ca, wra, wia);
+      jac_rotation(apb, aqb, gb.x, gb.y, tol, floor_g, cb, wrb, wib);
+      // rows pa, qa: U from the left, also on W; columns pb, qb: U^H from the
+      // right (an identity rotation leaves a block exactly as it was)
+      rot_pair(g00, g10, ca, wra, wia);
+      rot_pair(g01, g11, ca, wra, wia);
+      rot_pair(w00, w10, ca, wra, wia);
+      rot_pair(w01, w11, ca, wra, wia);
+      rot_pair(g00, g01, cb, wrb, -wib);
+      rot_pair(g10, g11, cb, wrb, -wib);
+      ws[pa][pb] = w00; ws[pa][qb] = w01; ws[qa][pb] = w10; ws[qa][qb] = w11;
       nxt[pa][pb] = g00; nxt[pa][qb] = g01; nxt[qa][pb] = g10; nxt[qa][qb] = g11;
       // every read of cur in this step precedes the barrier, so the next step may overwrite it
       __syncthreads();
