@@ -129,6 +129,12 @@ typedef struct {
                                   device memory, as it does when a gate has
                                   more than 4096 candidate values (0: LDS
                                   when it fits).  A diagnostic. */
+  int sweep_graph;             /* 1: the step launches of a Jacobi sweep are
+                                  captured once per update call into a HIP
+                                  graph (on the handle's stream, thread-local
+                                  capture) and the graph is launched once per
+                                  sweep; 0 (default): launched one by one.
+                                  Results are identical either way. */
 } mps_opts;
 
 /* Per-handle counters, accumulated since creation or mps_reset_stats.
@@ -162,11 +168,16 @@ typedef struct {
                                /*   into BF16 planes before the products       */
   double leak_total;           /* weight removed by the local cutoff, summed   */
                                /*   over gates (see mps_last_leaks)            */
+  long long graph_launches;    /* sweeps launched as a captured graph          */
+  double host_plan_ms;         /* host wall time spent planning updates (the   */
+                               /*   charge-sector work lists, uploads packed,  */
+                               /*   update lists from the kept counts); always */
+                               /*   measured                                   */
 } mps_stats;
 
 /* Fill *o with the defaults: chi_max 0, cutoff 0, zero_tol 1e-13,
  * max_sweeps 40, jacobi_tol 0, plain form, modulus 0, blocked_sweeps 0,
- * select_scratch 0. */
+ * select_scratch 0, sweep_graph 0. */
 void mps_default_opts(mps_opts* o);
 
 /* Create a state of L sites with local dimension d (occupations 0..d-1,

@@ -51,7 +51,8 @@ FORM_SPLIT_BF16X3 = 1        # Theta's charge-triple products in split BF16 on t
 class mps_opts(C.Structure):
     _fields_ = [("chi_max", C.c_int), ("cutoff", C.c_double), ("zero_tol", C.c_double),
                 ("max_sweeps", C.c_int), ("jacobi_tol", C.c_double), ("form", C.c_int),
-                ("modulus", C.c_int), ("blocked_sweeps", C.c_int), ("select_scratch", C.c_int)]
+                ("modulus", C.c_int), ("blocked_sweeps", C.c_int), ("select_scratch", C.c_int),
+                ("sweep_graph", C.c_int)]
 
 
 class mps_stats(C.Structure):
@@ -65,7 +66,8 @@ class mps_stats(C.Structure):
                 ("update_launches", C.c_longlong), ("polish_launches", C.c_longlong),
                 ("max_discarded", C.c_double), ("min_margin", C.c_double),
                 ("gemm_ms", C.c_double), ("gemm_launches", C.c_longlong),
-                ("gemm_mfma_flops", C.c_double), ("split_ms", C.c_double), ("leak_total", C.c_double)]
+                ("gemm_mfma_flops", C.c_double), ("split_ms", C.c_double), ("leak_total", C.c_double),
+                ("graph_launches", C.c_longlong), ("host_plan_ms", C.c_double)]
 
 
 EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_destroy", "mps_apply_gate",
@@ -192,7 +194,7 @@ class MPS:
     def __init__(self, occupation: Sequence[int], d: int, chi_max: int = 0, cutoff: float = 0.0,
                  zero_tol: float = 1e-13, max_sweeps: int = 40, jacobi_tol: float = 0.0,
                  device: Optional[TorchDevice] = None, form: int = FORM_PLAIN_C128, modulus: int = 0,
-                 blocked_sweeps: int = 0, select_scratch: int = 0, _handle=None):
+                 blocked_sweeps: int = 0, select_scratch: int = 0, sweep_graph: int = 0, _handle=None):
         self._lib = lib()
         self.L = len(occupation)
         self.d = d
@@ -201,7 +203,7 @@ class MPS:
         self._dev = device if device is not None else TorchDevice()
         self._dev_struct = self._dev.struct()
         self._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus),
-                              int(blocked_sweeps), int(select_scratch))
+                              int(blocked_sweeps), int(select_scratch), int(sweep_graph))
         self._h = C.c_void_p()
         if _handle is not None:
             self._h = _handle
@@ -217,7 +219,7 @@ class MPS:
                    cutoff: float = 0.0, zero_tol: float = 1e-13, max_sweeps: int = 40,
                    jacobi_tol: float = 0.0, device: Optional[TorchDevice] = None,
                    form: int = FORM_PLAIN_C128, modulus: int = 0, blocked_sweeps: int = 0,
-                   select_scratch: int = 0) -> "MPS":
+                   select_scratch: int = 0, sweep_graph: int = 0) -> "MPS":
         L = len(gammas)
         dims = [len(c) for c in bond_charges]
         obj = cls.__new__(cls)
@@ -227,7 +229,7 @@ class MPS:
         obj._dev = device if device is not None else TorchDevice()
         obj._dev_struct = obj._dev.struct()
         obj._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus),
-                             int(blocked_sweeps), int(select_scratch))
+                             int(blocked_sweeps), int(select_scratch), int(sweep_graph))
         obj._h = C.c_void_p()
         c_dims = (C.c_int * (L + 1))(*dims)
         flat = [int(c) for b in bond_charges for c in b]

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
@@ -115,6 +116,7 @@ struct mps_state {
   mps_opts opts{};
   mps_device dev{};
   hipStream_t st = nullptr;
+  hipStream_t cap_st = nullptr;  // private stream for graph capture (the handle's may be the null stream)
   std::vector<Bond> bonds;       // L + 1
   std::vector<int> cap;          // per bond: largest admissible dimension
   std::vector<double*> lam;      // per bond, cap[b] doubles
@@ -650,6 +652,11 @@ mps_status check_device_limits(mps_state* h, const BatchPlan& P) {
 mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   mps_state* h = refs[0].h;
   const int ng = (int)refs.size();
+  using clock = std::chrono::steady_clock;
+  auto plan_t0 = clock::now();
+  auto plan_add = [&]() {
+    h->stats.host_plan_ms += std::chrono::duration<double, std::milli>(clock::now() - plan_t0).count();
+  };
   BatchPlan P;
   STCHK(plan_batch(refs, P));
   STCHK(check_device_limits(h, P));
@@ -702,6 +709,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   STCHK(ensure_pin(h->stage_plan, upload));
   pk.write(h->stage_plan.p);
   HIPCHK(hipMemcpyAsync(h->plan.p, h->stage_plan.p, upload, hipMemcpyHostToDevice, h->st));
+  plan_add();
 
   const GateWork* d_gates = at<GateWork>(h->plan, o_gates);
   const SectorWork* d_secs = at<SectorWork>(h->plan, o_secs);
@@ -746,7 +754,9 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     int* d_perm = static_cast<int*>(h->jperm.p);
     double* d_norm = static_cast<double*>(h->jnorm.p);
     int* d_active = at<int>(h->plan, o_active);
-    STCHK(ensure_pin(h->stage_flag, sizeof(int)));
+    // two pinned slots for the per-sweep "still rotating" flag (see below)
+    STCHK(ensure_pin(h->stage_flag, 2 * sizeof(int)));
+    volatile int* flag = static_cast<volatile int*>(h->stage_flag.p);
     {
       Timer tm(h, K_JACOBI_AUX);
       STCHK(tm.start());
@@ -758,13 +768,51 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     // finished by scalar sweeps on its vectors
     const int blocked =
         std::min(h->opts.max_sweeps, h->opts.blocked_sweeps > 0 ? h->opts.blocked_sweeps : kBlockedSweeps);
+    // The step launches of a sweep are the same every sweep: with sweep_graph
+    // they are captured once per update into a HIP graph and replayed on the
+    // handle's stream.  Capture runs on a private stream (the null stream
+    // cannot be captured); capturing executes nothing.
+    struct GraphExec {
+      hipGraphExec_t g = nullptr;
+      ~GraphExec() {
+        if (g) (void)hipGraphExecDestroy(g);
+      }
+    } gholder;
+    hipGraphExec_t& gexec = gholder.g;
+    if (h->opts.sweep_graph && P.jmaxnb > 1) {
+      hipGraph_t graph = nullptr;
+      if (!h->cap_st) HIPCHK(hipStreamCreateWithFlags(&h->cap_st, hipStreamNonBlocking));
+      HIPCHK(hipStreamBeginCapture(h->cap_st, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = hipSuccess;
+      for (int step = 0; step < P.jmaxnb - 1 && ce == hipSuccess; ++step)
+        ce = launch_jacobi_step(d_secs, at<JacobiBlockWork>(h->plan, o_jblk), ns, P.jpairs, step, scaled, d_acc,
+                                d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, h->cap_st);
+      const hipError_t ee = hipStreamEndCapture(h->cap_st, &graph);
+      if (ce == hipSuccess) ce = ee;
+      if (ce == hipSuccess) ce = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (ce != hipSuccess) return fail(MPS_E_DEVICE, "capture of the sweep graph failed: %s", hipGetErrorString(ce));
+    }
+    // The host never idles the device between sweeps: sweep k's flag is copied
+    // into pinned slot k % 2 behind it, and the host reads it only once sweep
+    // k + 1 is enqueued.  A sweep enqueued after convergence finds every
+    // sector converged and returns at once, so it changes nothing.
+    hipEvent_t fev[2] = {nullptr, nullptr};
+    STCHK(ev_get(h, &fev[0]));
+    STCHK(ev_get(h, &fev[1]));
     int still_active = 1;
+    int issued = 0;
     for (int sweep = 0; sweep < blocked; ++sweep) {
       Timer tm(h, K_JACOBI);
       STCHK(tm.start());
-      for (int step = 0; step < P.jmaxnb - 1; ++step)
-        HIPCHK(launch_jacobi_step(d_secs, at<JacobiBlockWork>(h->plan, o_jblk), ns, P.jpairs, step, scaled,
-                                  d_acc, d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, h->st));
+      if (gexec) {
+        HIPCHK(hipGraphLaunch(gexec, h->st));
+        h->stats.graph_launches += 1;
+      } else {
+        for (int step = 0; step < P.jmaxnb - 1; ++step)
+          HIPCHK(launch_jacobi_step(d_secs, at<JacobiBlockWork>(h->plan, o_jblk), ns, P.jpairs, step, scaled,
+                                    d_acc, d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, h->st));
+      }
       STCHK(tm.stop());
       h->stats.jacobi_launches += P.jmaxnb - 1;
       Timer ta(h, K_JACOBI_AUX);
@@ -773,11 +821,24 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
       HIPCHK(launch_jacobi_sort(d_secs, d_jlist, ns, d_jst, d_perm, d_norm, h->st));
       STCHK(ta.stop());
       h->stats.jacobi_aux_launches += 2;
-      HIPCHK(hipMemcpyAsync(h->stage_flag.p, d_active, sizeof(int), hipMemcpyDeviceToHost, h->st));
-      HIPCHK(hipStreamSynchronize(h->st));
-      still_active = *static_cast<volatile int*>(h->stage_flag.p);
-      if (!still_active) break;
+      HIPCHK(hipMemcpyAsync(const_cast<int*>(flag) + (sweep & 1), d_active, sizeof(int), hipMemcpyDeviceToHost,
+                            h->st));
+      HIPCHK(hipEventRecord(fev[sweep & 1], h->st));
+      issued = sweep + 1;
+      if (sweep >= 1) {
+        HIPCHK(hipEventSynchronize(fev[(sweep - 1) & 1]));
+        if (!flag[(sweep - 1) & 1]) {
+          still_active = 0;
+          break;
+        }
+      }
     }
+    if (still_active && issued > 0) {
+      HIPCHK(hipEventSynchronize(fev[(issued - 1) & 1]));
+      still_active = flag[(issued - 1) & 1];
+    }
+    h->pool.push_back(fev[0]);
+    h->pool.push_back(fev[1]);
     if (still_active && h->opts.max_sweeps > blocked) {
       Timer tp(h, K_JACOBI_AUX);
       STCHK(tp.start());
@@ -832,6 +893,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   h->stats.theta_flops += P.theta_flops;
 
   // new bond tables and update lists
+  plan_t0 = clock::now();
   std::vector<RowWork> rows;
   std::vector<UpdateWork> upds(ng);
   std::vector<double2*> fill_ptr(ng);
@@ -898,6 +960,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   STCHK(ensure_pin(h->stage_upd, pu.total));
   pu.write(h->stage_upd.p);
   HIPCHK(hipMemcpyAsync(h->upd.p, h->stage_upd.p, pu.total, hipMemcpyHostToDevice, h->st));
+  plan_add();
   {
     Timer tm(h, K_UPDATE);
     STCHK(tm.start());
@@ -967,6 +1030,10 @@ mps_status check_layer(mps_t h, int ngates, const int* sites, const mps_z* gs, b
 
 mps_status destroy_buffers(mps_state* h) {
   if (h->st) (void)hipStreamSynchronize(h->st);
+  if (h->cap_st) {
+    (void)hipStreamDestroy(h->cap_st);
+    h->cap_st = nullptr;
+  }
   for (double* p : h->lam) dfree(h, p);
   for (double2* p : h->site) dfree(h, p);
   h->lam.clear();
@@ -1011,6 +1078,7 @@ void mps_default_opts(mps_opts* o) {
   o->modulus = 0;
   o->blocked_sweeps = 0;
   o->select_scratch = 0;
+  o->sweep_graph = 0;
 }
 
 const char* mps_last_error(void) { return g_err.c_str(); }
@@ -1036,6 +1104,7 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
   if (o.max_sweeps <= 0) return fail(MPS_E_ARG, "max_sweeps must be positive");
   if (o.blocked_sweeps < 0) return fail(MPS_E_ARG, "blocked_sweeps must be >= 0");
   if (o.select_scratch != 0 && o.select_scratch != 1) return fail(MPS_E_ARG, "select_scratch must be 0 or 1");
+  if (o.sweep_graph != 0 && o.sweep_graph != 1) return fail(MPS_E_ARG, "sweep_graph must be 0 or 1");
   if (!(o.cutoff >= 0.0) || !(o.zero_tol >= 0.0)) return fail(MPS_E_ARG, "cutoff and zero_tol must be >= 0");
   if (o.form != MPS_FORM_PLAIN_C128 && o.form != MPS_FORM_SPLIT_BF16X3) return fail(MPS_E_ARG, "unknown form %d", o.form);
   if (o.modulus != 0 && o.modulus != d)

@@ -152,12 +152,15 @@ class Server:
     on its own requests and stream, so the lanes' launches share the device.
     lane_of: request spec -> lane index (default: lane 0).
     clock: returns seconds since the start (monotonic); tests may pass a
-    simulated clock."""
+    simulated clock.
+    state_opts: extra keyword options of every request's MPS (for instance
+    sweep_graph=1)."""
 
     def __init__(self, hbm_budget: int, max_active: int = 1024, device=None,
                  clock: Optional[Callable[[], float]] = None, devices: Optional[Sequence] = None,
-                 lane_of: Optional[Callable[[dict], int]] = None):
+                 lane_of: Optional[Callable[[dict], int]] = None, state_opts: Optional[dict] = None):
         self.hbm_budget = int(hbm_budget)
+        self.state_opts = dict(state_opts or {})
         self.max_active = int(max_active)
         self.devices = list(devices) if devices else [device]
         self.lane_of = lane_of or (lambda spec: 0)
@@ -241,7 +244,7 @@ class Server:
                     r.materialize()
                     c = r.cfg
                     r.state = MPS(c["occupation"], c["d"], chi_max=c["chi_max"], cutoff=c["cutoff"],
-                                  device=self.devices[k])
+                                  device=self.devices[k], **self.state_opts)
                     r.admitted_at = t
                     active.append(r)
                     qi += 1
