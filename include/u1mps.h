@@ -273,6 +273,22 @@ mps_status mps_amplitude(mps_t h, int count, const int* occ, mps_z* out);
 /* <psi|psi> by full contraction of the transfer matrices (not sum lambda^2). */
 mps_status mps_norm(mps_t h, double* norm2);
 
+/* mps_norm for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same contraction and kernels, with the environment buffers and the work
+ * lists in a fixed device array of the library (64 MiB per GPU, held until the
+ * process ends) instead of the handle's growable workspaces.  Allocates no
+ * device or pinned memory.  The result equals mps_norm's.
+ * Limit: (2 + d) * chi^2 * 16 bytes plus the work lists must fit in 64 MiB,
+ * chi the largest bond dimension (d = 4: chi up to about 830); a larger state
+ * fails with MPS_E_ARG before any device work.  Runs on the GPU current when
+ * the handle was created and on its stream, and returns after its device work
+ * has finished.  All calls share one array per GPU (its contents are those of
+ * the last call); calls are serialised by a lock inside the library, so calls
+ * from several host threads do not overlap on the device.
+ * Errors: MPS_E_ARG, MPS_E_DEVICE. */
+mps_status mps_norm_noalloc(mps_t h, double* norm2);
+
 /* Exact samples of output patterns (the read-out of a boson-sampling
  * circuit, Sec. I): pattern i is drawn with probability |c_i|^2 / <psi|psi>,
  * c_i as in Eq. (E2), by the chain rule from mode L-1 down to mode 0.  Mode

@@ -71,7 +71,7 @@ class mps_stats(C.Structure):
 
 
 EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_destroy", "mps_apply_gate",
-           "mps_apply_layer", "mps_apply_layer_dense", "mps_apply_batch", "mps_truncate", "mps_amplitude", "mps_norm", "mps_sample", "mps_bond_sectors",
+           "mps_apply_layer", "mps_apply_layer_dense", "mps_apply_batch", "mps_truncate", "mps_amplitude", "mps_norm", "mps_norm_noalloc", "mps_sample", "mps_bond_sectors",
            "mps_bond_lambda", "mps_site_tensor", "mps_last_leaks", "mps_set_timing", "mps_get_stats",
            "mps_reset_stats", "mps_sync", "mps_last_error"]
 
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mps_truncate": (st, [h, C.c_int, C.c_int, C.c_double, P(C.c_double)]),
         "mps_amplitude": (st, [h, C.c_int, P(C.c_int), P(mps_z)]),
         "mps_norm": (st, [h, P(C.c_double)]),
+        "mps_norm_noalloc": (st, [h, P(C.c_double)]),
         "mps_sample": (st, [h, C.c_int, P(C.c_double), P(C.c_int), P(C.c_double)]),
         "mps_bond_sectors": (st, [h, C.c_int, C.c_int, P(C.c_int), P(C.c_int), P(C.c_int)]),
         "mps_bond_lambda": (st, [h, C.c_int, C.c_int, P(C.c_int), P(C.c_double)]),
@@ -310,6 +311,12 @@ class MPS:
     def norm2(self) -> float:
         v = C.c_double(0.0)
         _check(self._lib.mps_norm(self._h, C.byref(v)))
+        return v.value
+
+    def norm2_noalloc(self) -> float:
+        """<psi|psi> through mps_norm_noalloc (no device allocation)."""
+        v = C.c_double(0.0)
+        _check(self._lib.mps_norm_noalloc(self._h, C.byref(v)))
         return v.value
 
     def sample(self, uniforms: np.ndarray):

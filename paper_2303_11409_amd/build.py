@@ -6,7 +6,8 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["csrc/theta.hip", "csrc/jacobi.hip", "csrc/kernels.hip", "csrc/sample.hip", "csrc/runtime.cpp"]
+SOURCES = ["csrc/theta.hip", "csrc/jacobi.hip", "csrc/kernels.hip", "csrc/sample.hip", "csrc/noalloc.hip",
+           "csrc/runtime.cpp"]
 OUTPUT = os.path.join(HERE, "libu1mps.so")
 
 HIPCC_FLAGS = [

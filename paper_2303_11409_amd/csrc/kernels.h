@@ -2,6 +2,8 @@
 // device pointer; every launch goes to the given stream.
 #pragma once
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace u1mps {
@@ -75,5 +77,14 @@ hipError_t launch_gather_cols(const double2* src, int lds, double2* dst, int ldd
 hipError_t launch_gather_rows(const double2* src, int lds, double2* dst, int ldd, const int* map,
                               int nrows, int cols, hipStream_t st);
 hipError_t launch_gather_vec(const double* src, double* dst, const int* map, int n, hipStream_t st);
+
+// Fixed device scratch of the entry point that allocates nothing
+// (noalloc.hip): kScratchBytes per GPU.  scratch_region returns the array's
+// device address on `device` (looked up once per device, with that device
+// current); the caller holds scratch_lock() while it looks the address up
+// and while its device work on the array runs.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+std::unique_lock<std::mutex> scratch_lock();
+hipError_t scratch_region(int device, void** ptr, size_t* bytes);
 
 }  // namespace u1mps

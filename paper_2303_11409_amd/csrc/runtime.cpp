@@ -113,6 +113,7 @@ constexpr int kBlockedSweeps = 32;
 struct mps_state {
   int L = 0, d = 0, N = 0;
   int mod = 0;                   // 0: U(1) particle number; n: particle number mod n (d == n)
+  int device = 0;                // the GPU current when the handle was created
   mps_opts opts{};
   mps_device dev{};
   hipStream_t st = nullptr;
@@ -1198,6 +1199,7 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
   h->opts = o;
   if (dev) h->dev = *dev;
   h->st = static_cast<hipStream_t>(h->dev.stream);
+  if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
   h->bonds = bonds;
   h->stats.min_margin = INFINITY;
   mps_status s = compute_caps(h);
@@ -1464,28 +1466,50 @@ mps_status mps_amplitude(mps_t h, int count, const int* occ, mps_z* out) {
 // E_0 = 1 and E_{s+1}[c', c'] = sum_w B[w, c']^dagger E_s[w, w] B[w, c'], w the
 // rows of bond s whose charges c' .. c'+d-1 reach charge c' of bond s+1, so
 // every E is block-diagonal by charge.  eb[s] and eb[s+2] may be one frame.
-// The plan goes through misc/stage_misc; stage_misc keeps `extra` bytes past
-// it (*tail is their offset) for the caller.
-mps_status left_envs(mps_state* h, const std::vector<double2*>& eb, size_t extra, size_t* tail) {
-  const int L = h->L, d = h->d;
+//
+// Work lists of the left-environment contraction (the norm's and the
+// sampler's): per site s, T_c' = E_s[w, w] B[s][w, c'] into tbuf, then
+// E_{s+1}[c', c'] = B[s][w, c']^dagger T_c', block by block over the charges
+// c' of bond s+1 (w: the rows of bond s that reach c').  The packed lists stay
+// valid while the EnvPlan lives (the packer keeps pointers into it).
+struct EnvPlan {
+  std::vector<std::vector<GemmWork>> p1, p2;
+  std::vector<int> nt1, nt2;
+  std::vector<double2*> fptr;
+  std::vector<long long> fcnt;
+  std::vector<size_t> o1, o2;
+  size_t o_fp = 0, o_fc = 0, o_one = 0;
+  double2 one = make_double2(1.0, 0.0);
+  Packer pk;
+  EnvPlan() = default;
+  EnvPlan(const EnvPlan&) = delete;
+  EnvPlan& operator=(const EnvPlan&) = delete;
+};
+
+// The largest bond dimension of the state and T's size in elements (d * that^2).
+size_t env_tbuf_elems(const mps_state* h, int* maxdim_out) {
   int maxdim = 1;
-  for (int b = 0; b <= L; ++b) maxdim = std::max(maxdim, h->bonds[b].dim());
-  const size_t esz = (size_t)maxdim * maxdim;
-  STCHK(ensure(h, h->norm_t, (size_t)d * esz * sizeof(double2)));
-  double2* tbuf = static_cast<double2*>(h->norm_t.p);
-  // per site: problems T_c' = E[w, w] B[w, c'] and E'[c', c'] = B[w, c']^dagger T_c'
-  std::vector<std::vector<GemmWork>> p1(L), p2(L);
-  std::vector<int> nt1(L, 0), nt2(L, 0);
-  std::vector<double2*> fptr(L);
-  std::vector<long long> fcnt(L);
+  for (int b = 0; b <= h->L; ++b) maxdim = std::max(maxdim, h->bonds[b].dim());
+  if (maxdim_out) *maxdim_out = maxdim;
+  return (size_t)h->d * maxdim * maxdim;
+}
+
+mps_status plan_envs(mps_state* h, const std::vector<double2*>& eb, double2* tbuf, size_t tcap, EnvPlan& E) {
+  const int L = h->L, d = h->d;
+  E.p1.assign(L, {});
+  E.p2.assign(L, {});
+  E.nt1.assign(L, 0);
+  E.nt2.assign(L, 0);
+  E.fptr.assign(L, nullptr);
+  E.fcnt.assign(L, 0);
   for (int s = 0; s < L; ++s) {
     const Bond& B0 = h->bonds[s];
     const Bond& B1 = h->bonds[s + 1];
     const int ld0 = B0.dim(), ld1 = B1.dim();
     double2* ein = eb[s];
     double2* eout = eb[s + 1];
-    fptr[s] = eout;
-    fcnt[s] = (long long)ld1 * ld1;
+    E.fptr[s] = eout;
+    E.fcnt[s] = (long long)ld1 * ld1;
     size_t toff = 0;
     for (size_t i = 0; i < B1.charge.size(); ++i) {
       const int cp = B1.charge[i];
@@ -1504,9 +1528,9 @@ mps_status left_envs(mps_state* h, const std::vector<double2*>& eb, size_t extra
       a.n = nn;
       a.k = kw;
       a.tiles_n = (nn + kGemmTile - 1) / kGemmTile;
-      a.tile_begin = nt1[s];
-      nt1[s] += ((kw + kGemmTile - 1) / kGemmTile) * a.tiles_n;
-      p1[s].push_back(a);
+      a.tile_begin = E.nt1[s];
+      E.nt1[s] += ((kw + kGemmTile - 1) / kGemmTile) * a.tiles_n;
+      E.p1[s].push_back(a);
       GemmWork b{};
       b.a = h->site[s] + (size_t)w0 * ld1 + o1;
       b.lda = ld1;
@@ -1519,35 +1543,55 @@ mps_status left_envs(mps_state* h, const std::vector<double2*>& eb, size_t extra
       b.n = nn;
       b.k = kw;
       b.tiles_n = (nn + kGemmTile - 1) / kGemmTile;
-      b.tile_begin = nt2[s];
-      nt2[s] += ((nn + kGemmTile - 1) / kGemmTile) * b.tiles_n;
-      p2[s].push_back(b);
+      b.tile_begin = E.nt2[s];
+      E.nt2[s] += ((nn + kGemmTile - 1) / kGemmTile) * b.tiles_n;
+      E.p2[s].push_back(b);
       toff += (size_t)kw * nn;
     }
-    if (toff > (size_t)d * esz) return fail(MPS_E_ARG, "internal: environment scratch too small");
+    if (toff > tcap) return fail(MPS_E_ARG, "internal: environment scratch too small");
   }
-  Packer pk;
-  std::vector<size_t> o1(L), o2(L);
+  E.o1.assign(L, 0);
+  E.o2.assign(L, 0);
   for (int s = 0; s < L; ++s) {
-    o1[s] = pk.add(p1[s].data(), p1[s].size() * sizeof(GemmWork));
-    o2[s] = pk.add(p2[s].data(), p2[s].size() * sizeof(GemmWork));
+    E.o1[s] = E.pk.add(E.p1[s].data(), E.p1[s].size() * sizeof(GemmWork));
+    E.o2[s] = E.pk.add(E.p2[s].data(), E.p2[s].size() * sizeof(GemmWork));
   }
-  const size_t o_fp = pk.add(fptr.data(), fptr.size() * sizeof(double2*));
-  const size_t o_fc = pk.add(fcnt.data(), fcnt.size() * sizeof(long long));
-  const double2 one = make_double2(1.0, 0.0);
-  const size_t o_one = pk.add(&one, sizeof one);
+  E.o_fp = E.pk.add(E.fptr.data(), E.fptr.size() * sizeof(double2*));
+  E.o_fc = E.pk.add(E.fcnt.data(), E.fcnt.size() * sizeof(long long));
+  E.o_one = E.pk.add(&E.one, sizeof E.one);
+  return MPS_OK;
+}
+
+// The contraction's launches, with the packed lists already at `list` on the
+// device: E_0 = 1, then per site a zero fill of E_{s+1} and the two products.
+mps_status launch_envs(mps_state* h, const std::vector<double2*>& eb, const EnvPlan& E, char* list) {
+  auto on = [&](size_t off) { return list + off; };
+  HIPCHK(hipMemcpyAsync(eb[0], on(E.o_one), sizeof(double2), hipMemcpyDeviceToDevice, h->st));
+  for (int s = 0; s < h->L; ++s) {
+    HIPCHK(launch_zero_fill(reinterpret_cast<double2**>(on(E.o_fp)) + s,
+                            reinterpret_cast<long long*>(on(E.o_fc)) + s, 1, E.fcnt[s], h->st));
+    HIPCHK(launch_zgemm(reinterpret_cast<const GemmWork*>(on(E.o1[s])), (int)E.p1[s].size(), E.nt1[s], h->st));
+    HIPCHK(launch_zgemm(reinterpret_cast<const GemmWork*>(on(E.o2[s])), (int)E.p2[s].size(), E.nt2[s], h->st));
+  }
+  return MPS_OK;
+}
+
+// The environments E_0..E_L into eb (device buffers of dim_b^2), through the
+// handle's workspaces (misc, stage_misc); `extra` bytes of pinned staging are
+// reserved after the uploaded lists, at offset *tail of stage_misc, for the
+// caller.
+mps_status left_envs(mps_state* h, const std::vector<double2*>& eb, size_t extra, size_t* tail) {
+  const size_t tel = env_tbuf_elems(h, nullptr);
+  STCHK(ensure(h, h->norm_t, tel * sizeof(double2)));
+  EnvPlan E;
+  STCHK(plan_envs(h, eb, static_cast<double2*>(h->norm_t.p), tel, E));
   HIPCHK(hipStreamSynchronize(h->st));
-  STCHK(ensure(h, h->misc, pk.total));
-  STCHK(ensure_pin(h->stage_misc, pk.total + extra));
-  pk.write(h->stage_misc.p);
-  HIPCHK(hipMemcpyAsync(h->misc.p, h->stage_misc.p, pk.total, hipMemcpyHostToDevice, h->st));
-  HIPCHK(hipMemcpyAsync(eb[0], at<double2>(h->misc, o_one), sizeof(double2), hipMemcpyDeviceToDevice, h->st));
-  for (int s = 0; s < L; ++s) {
-    HIPCHK(launch_zero_fill(at<double2*>(h->misc, o_fp) + s, at<long long>(h->misc, o_fc) + s, 1, fcnt[s], h->st));
-    HIPCHK(launch_zgemm(at<GemmWork>(h->misc, o1[s]), (int)p1[s].size(), nt1[s], h->st));
-    HIPCHK(launch_zgemm(at<GemmWork>(h->misc, o2[s]), (int)p2[s].size(), nt2[s], h->st));
-  }
-  *tail = pk.total;
+  STCHK(ensure(h, h->misc, E.pk.total));
+  STCHK(ensure_pin(h->stage_misc, E.pk.total + extra));
+  E.pk.write(h->stage_misc.p);
+  HIPCHK(hipMemcpyAsync(h->misc.p, h->stage_misc.p, E.pk.total, hipMemcpyHostToDevice, h->st));
+  STCHK(launch_envs(h, eb, E, static_cast<char*>(h->misc.p)));
+  *tail = E.pk.total;
   return MPS_OK;
 }
 
@@ -1569,6 +1613,50 @@ mps_status mps_norm(mps_t h, double* norm2) {
   HIPCHK(hipMemcpyAsync(res, eb[L], sizeof(double2), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
   *norm2 = res->x;
+  return MPS_OK;
+}
+
+mps_status mps_norm_noalloc(mps_t h, double* norm2) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (!norm2) return fail(MPS_E_ARG, "norm2 is NULL");
+  const int L = h->L;
+  int maxdim = 1;
+  const size_t tel = env_tbuf_elems(h, &maxdim);
+  const size_t esz = (size_t)maxdim * maxdim;
+  // scratch layout: E (even bonds) | E (odd bonds) | T | packed work lists
+  const size_t o_e1 = align256(esz * sizeof(double2));
+  const size_t o_t = o_e1 + align256(esz * sizeof(double2));
+  const size_t o_list = o_t + align256(tel * sizeof(double2));
+  int cur = 0;
+  HIPCHK(hipGetDevice(&cur));
+  struct DeviceGuard {
+    int prev, want;
+    ~DeviceGuard() {
+      if (prev != want) (void)hipSetDevice(prev);
+    }
+  } guard{cur, h->device};
+  if (cur != h->device) HIPCHK(hipSetDevice(h->device));
+  auto lock = scratch_lock();
+  void* base = nullptr;
+  size_t cap = 0;
+  HIPCHK(scratch_region(h->device, &base, &cap));
+  char* sc = static_cast<char*>(base);
+  std::vector<double2*> eb(L + 1);
+  for (int b = 0; b <= L; ++b) eb[b] = reinterpret_cast<double2*>(sc + ((b & 1) ? o_e1 : 0));
+  EnvPlan E;
+  STCHK(plan_envs(h, eb, reinterpret_cast<double2*>(sc + o_t), tel, E));
+  if (o_list + E.pk.total > cap)
+    return fail(MPS_E_ARG, "mps_norm_noalloc: bond dimension %d needs %zu bytes of scratch, the limit is %zu",
+                maxdim, o_list + E.pk.total, cap);
+  // pageable staging on the host: the copy completes before the call returns
+  std::vector<char> stage(E.pk.total);
+  E.pk.write(stage.data());
+  HIPCHK(hipMemcpyAsync(sc + o_list, stage.data(), E.pk.total, hipMemcpyHostToDevice, h->st));
+  STCHK(launch_envs(h, eb, E, sc + o_list));
+  double2 res = make_double2(0.0, 0.0);
+  HIPCHK(hipMemcpyAsync(&res, eb[L], sizeof(double2), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  *norm2 = res.x;
   return MPS_OK;
 }
 
