@@ -12,11 +12,13 @@ region (inputs resident in HBM).
 Printed: one JSON line (stdout) with gate applies/s, the roofline of the
 dominant kernel (HIP events on the library's stream over the timed region)
 and the CPU oracle timed on saturated gates of the same shape (the whole
-circuit's oracle time estimated from them); under
-"forms", the batching form (several circuits per launch: copies of this
-circuit with other seeds, and the first circuits of the mixed-size workload)
-and the serving form (Poisson arrivals, continuous batching, p50/p99 latency
-from arrival to result); under "tebd", Hamiltonian time evolution with dense
+circuit's oracle time estimated from them); under "forms", the precision form
+against the plain one on a saturated chi=2048 state (sector products on the
+matrix cores, gate applies/s, their difference), the batching form (several
+circuits per launch: copies of this circuit with other seeds, and the 512
+circuits of the mixed-size workload) and the serving form (Poisson arrivals,
+continuous batching, p50/p99 latency from arrival to result, unfinished
+requests censored); under "tebd", Hamiltonian time evolution with dense
 Trotter gates (an XXZ chain and a Bose-Hubbard chain with the particle number
 as the charge, a transverse-field Ising chain with Z_2 and a clock chain with
 Z_3 charges; 64 sites each, quenched from product states).  Progress goes to stderr.
@@ -37,7 +39,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/cl
 
 # HBM bytes per launch of jacobi_block_step on this workload, from two
 # rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline
-# --batch-copies 0 --mix-circuits 0 --no-chi2048 --serve-seconds 0 --samples 0
+# --batch-copies 0 --mix-circuits 0 --chi2048-layers 0 --serve-seconds 0 --samples 0
 # --no-tebd`
 # (FETCH_SIZE, WRITE_SIZE; mean over the launches) scaled by the same counters
 # on a plain 256 MiB copy (`bench.py --copy-probe`: FETCH_SIZE reads 131085.2
@@ -236,12 +238,14 @@ def copy_probe(torch) -> int:
     return 0 if ok else 1
 
 
-def run_batched(cfgs, MPS, apply_batch, dev, keep_first=False):
-    """The batching form: layer k of every circuit in one mps_apply_batch call.
+def run_batched(cfgs, MPS, apply_batch, dev, keep_first=False, sweep_graph=1):
+    """The batching form: layer k of every circuit in one mps_apply_batch call,
+    each Jacobi sweep's step launches replayed from a captured HIP graph.
     States are created before the timed region.  Returns (gates, seconds, first
-    state if keep_first)."""
+    state if keep_first, host planning seconds)."""
     import torch
-    states = [MPS(c["occupation"], c["d"], chi_max=c["chi_max"], cutoff=c["cutoff"], device=dev) for c in cfgs]
+    states = [MPS(c["occupation"], c["d"], chi_max=c["chi_max"], cutoff=c["cutoff"], device=dev,
+                  sweep_graph=sweep_graph) for c in cfgs]
     lays = []
     depth = max(len(c["layers"]) for c in cfgs)
     for k in range(depth):
@@ -259,10 +263,11 @@ def run_batched(cfgs, MPS, apply_batch, dev, keep_first=False):
         m.sync()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    plan_s = sum(m.stats()["host_plan_ms"] for m in states) / 1e3
     first = states[0] if keep_first else None
     for m in states[1 if keep_first else 0:]:
         m.close()
-    return gates, el, first
+    return gates, el, first, plan_s
 
 
 def run_serving(args, rate, window, circuits):
@@ -278,8 +283,9 @@ def run_serving(args, rate, window, circuits):
     from paper_2303_11409_amd import TorchDevice
     # two lanes: the large circuits (chi_max >= 1024) on one stream, the rest on another
     devs = [TorchDevice(stream=torch.cuda.Stream()) for _ in range(2)]
-    srv = serving.Server(int(args.serve_budget_gib * 2**30), max_active=args.serve_max_active, devices=devs,
-                         lane_of=lambda sp: 0 if sp["chi_max"] >= 1024 else 1)
+    srv = serving.Server(int(args.serve_budget_gib * 2**30), max_active=[args.serve_max_large, args.serve_max_active],
+                         devices=devs,
+                         lane_of=lambda sp: 0 if sp["chi_max"] >= 1024 else 1, state_opts={"sweep_graph": 1})
     rep = srv.run(reqs, until=window)
     lat = rep.latencies()
     cens = rep.censored_latencies()
@@ -314,17 +320,24 @@ def run_serving(args, rate, window, circuits):
 BF16_DENSE_PEAK_TFLOPS = 2500.0    # MI355X dense BF16 matrix-core peak
 
 
-def sector_gemm_chi2048(MPS, dev, circuits):
-    """Theta formation of one brickwork layer (32 gates) of a synthetic chi=2048
-    state in both forms: the plain complex128 kernel (products and gate mix
-    fused, FP64) and the split-BF16 products on the matrix cores (plus the
-    FP64 gate mix), with the whole layer's time and the forms' difference."""
+def precision_chi2048(MPS, dev, circuits, layers: int):
+    """The precision workload's saturated regime in both forms: a synthetic
+    chi=2048 state (L=64, N=32, d=4; bond charges Gaussian around N(L-k)/L,
+    normalised to 2048 and clipped by the Fock bound; complex Gaussian Gamma on
+    the allowed blocks; lambda 1..1e-4; seed 30) through `layers` brickwork
+    layers of the 64-mode circuit's angles (seed 3), chi_max = 2048, cutoff
+    1e-12, once in the plain complex128 form and once with the split-BF16
+    sector products.  Reports gate applies/s per form, the sector products
+    (plain FP64 against split BF16 on the matrix cores), the Jacobi's rate
+    against the FP64 peak, and the forms' difference on 1024 amplitudes drawn
+    along the state's charge paths (seed 107)."""
     import numpy as np
     import torch
     from paper_2303_11409_amd.binding import FORM_PLAIN_C128, FORM_SPLIT_BF16X3
     ch, gam, lam = circuits.synthetic_state(64, 32, 4, 2048, seed=30)
-    lay = circuits.brickwork_layers(64, 1, 3)[0]
-    pats = circuits.sample_patterns(64, 32, 4, 256, 103)
+    lays = circuits.brickwork_layers(64, layers, 3)
+    pats = circuits.charge_path_patterns(ch, 4, 1024, 107)
+    ngates = sum(len(l) for l in lays)
     res, amps = {}, {}
     for form in (FORM_PLAIN_C128, FORM_SPLIT_BF16X3):
         m = MPS.from_vidal(4, 32, ch, gam, lam, chi_max=2048, cutoff=1e-12, form=form, device=dev)
@@ -332,7 +345,8 @@ def sector_gemm_chi2048(MPS, dev, circuits):
         m.reset_stats()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        m.apply_layer([g.site for g in lay], [g.u for g in lay])
+        for lay in lays:
+            m.apply_layer([g.site for g in lay], [g.u for g in lay])
         m.sync()
         el = time.perf_counter() - t0
         res[form] = (m.stats(), el)
@@ -343,10 +357,22 @@ def sector_gemm_chi2048(MPS, dev, circuits):
     flops = sp["theta_flops"]
     split_ms = ss["split_ms"] + ss["gemm_ms"] + ss["theta_ms"]
     a, r = amps[FORM_SPLIT_BF16X3], amps[FORM_PLAIN_C128]
+    jac = {}
+    for key, (st, _) in (("plain", res[FORM_PLAIN_C128]), ("split_bf16x3", res[FORM_SPLIT_BF16X3])):
+        jl = max(st["jacobi_launches"], 1)
+        jac[key] = {"ms": st["jacobi_ms"], "aux_ms": st["jacobi_aux_ms"],
+                    "tflops": st["jacobi_flops"] / max(st["jacobi_ms"], 1e-9) / 1e9,
+                    "frac_of_fp64_peak": st["jacobi_flops"] / max(st["jacobi_ms"], 1e-9) / 1e9
+                    / FP64_VECTOR_PEAK_TFLOPS,
+                    "launches": jl, "sweeps_per_sector": st["sweeps"] / max(st["sectors"], 1)}
     return {
-        "workload": "one brickwork layer (32 gates) of a synthetic chi=2048 state: L=64, N=32, d=4, bond k "
-                    "charges Gaussian (width 3) around N(L-k)/L normalised to 2048 and clipped by the Fock "
-                    "bound, complex Gaussian Gamma on the allowed blocks, lambda 1..1e-4 (seed 30)",
+        "workload": f"{layers} brickwork layers ({ngates} gates; circuit seed 3) of the 64-mode precision circuit "
+                    "applied to a synthetic saturated chi=2048 state: L=64, N=32, d=4, bond k charges Gaussian "
+                    "(width 3) around N(L-k)/L normalised to 2048 and clipped by the Fock bound, complex Gaussian "
+                    "Gamma on the allowed blocks, lambda 1..1e-4 (seed 30); chi_max=2048, cutoff 1e-12",
+        "gates": ngates,
+        "gate_applies_per_s": {"plain": ngates / tp, "split_bf16x3": ngates / ts},
+        "seconds": {"plain": tp, "split_bf16x3": ts},
         "algorithmic_flops": flops,
         "plain": {"kernel": "theta_kernel (complex128 products and gate mix fused, FP64 FMA)",
                   "ms": sp["theta_ms"], "tflops": flops / sp["theta_ms"] / 1e9,
@@ -365,11 +391,45 @@ def sector_gemm_chi2048(MPS, dev, circuits):
             "frac_of_bf16_peak_useful": 6.0 * flops / ss["gemm_ms"] / 1e9 / BF16_DENSE_PEAK_TFLOPS,
             "split_ms": ss["split_ms"],
             "theta_speedup_vs_plain": sp["theta_ms"] / split_ms},
+        "jacobi": jac,
         "split_vs_plain_amplitude_rel_err": float(np.linalg.norm(a - r) / np.linalg.norm(r)),
-        "layer_seconds": {"plain": tp, "split_bf16x3": ts},
-        "layer_jacobi_ms": {"plain": sp["jacobi_ms"] + sp["jacobi_aux_ms"],
-                            "split_bf16x3": ss["jacobi_ms"] + ss["jacobi_aux_ms"]},
+        "split_vs_plain_amplitude_max_err": float(np.max(np.abs(a - r)) / np.max(np.abs(r))),
+        "amplitudes": "1024 patterns along the state's charge paths (seed 107)",
     }
+
+
+def precision_full(MPS, dev, circuits):
+    """The whole precision circuit (L=64, 32 photons in even modes, d=4, 64
+    layers = 2016 gates, seed 3, chi_max=2048, cutoff 1e-12) from the Fock
+    state, in both forms; 1024 uniform patterns (seed 103)."""
+    import numpy as np
+    import torch
+    from paper_2303_11409_amd.binding import FORM_PLAIN_C128, FORM_SPLIT_BF16X3
+    cfg = circuits.config_precision(seed=3, chi_max=2048)
+    pats = circuits.sample_patterns(64, 32, 4, 1024, 103)
+    out, amps = {}, {}
+    for key, form in (("plain", FORM_PLAIN_C128), ("split_bf16x3", FORM_SPLIT_BF16X3)):
+        m = MPS(cfg["occupation"], 4, chi_max=2048, cutoff=1e-12, form=form, device=dev)
+        m.set_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for lay in cfg["layers"]:
+            m.apply_layer([g.site for g in lay], [g.u for g in lay])
+        m.sync()
+        el = time.perf_counter() - t0
+        st = m.stats()
+        amps[key] = m.amplitudes(pats)
+        out[key] = {"seconds": el, "gate_applies_per_s": len(cfg["gates"]) / el, "norm2": m.norm2(),
+                    "max_bond_dim": max(m.bond_dims()), "jacobi_ms": st["jacobi_ms"],
+                    "theta_ms": st["theta_ms"] + st["gemm_ms"] + st["split_ms"],
+                    "min_cut_margin": st["min_margin"]}
+        m.close()
+        log(f"  {key}: {el:.1f} s")
+    a, r = amps["split_bf16x3"], amps["plain"]
+    out["split_vs_plain_amplitude_rel_err"] = float(np.linalg.norm(a - r) / np.linalg.norm(r))
+    out["workload"] = ("L=64, 32 photons in even modes, d=4, 64 brickwork layers (2016 gates, seed 3), "
+                       "chi_max=2048, cutoff 1e-12; 1024 uniform patterns (seed 103)")
+    return out
 
 
 def main() -> int:
@@ -380,10 +440,14 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-copies", type=int, default=8,
                     help="batching form: seeds of the same circuit run together (0 = skip)")
-    ap.add_argument("--mix-circuits", type=int, default=64,
-                    help="batching form: first circuits of the mixed-size workload run together (0 = skip)")
-    ap.add_argument("--no-chi2048", action="store_true",
-                    help="skip the sector-product measurement on a chi=2048 layer")
+    ap.add_argument("--mix-circuits", type=int, default=512,
+                    help="batching form: circuits of the mixed-size workload run together (0 = skip)")
+    ap.add_argument("--chi2048-layers", type=int, default=4,
+                    help="precision form: brickwork layers applied to the saturated chi=2048 state in both "
+                         "forms (0 = skip)")
+    ap.add_argument("--precision-full", action="store_true",
+                    help="also run the whole 2016-gate chi_max=2048 precision circuit in both forms "
+                         "(several minutes)")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="serving form: length of the serving window at --serve-rate (0 = skip)")
     ap.add_argument("--serve-low-seconds", type=float, default=20.0,
@@ -391,7 +455,10 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serving form: arrivals per second")
     ap.add_argument("--serve-low-rate", type=float, default=0.5,
                     help="serving form: a second window at this rate, within the device's capacity (0 = skip)")
-    ap.add_argument("--serve-max-active", type=int, default=64)
+    ap.add_argument("--serve-max-active", type=int, default=512,
+                    help="serving form: most requests active at once in the lane of the batching-mix circuits")
+    ap.add_argument("--serve-max-large", type=int, default=16,
+                    help="serving form: most requests active at once in the lane of the chi_max=1024 circuits")
     ap.add_argument("--serve-budget-gib", type=float, default=96.0)
     ap.add_argument("--samples", type=int, default=4096,
                     help="exact output samples drawn from the final state (0 = skip)")
@@ -511,26 +578,28 @@ def main() -> int:
         B = args.batch_copies
         log(f"batching form: {B} seeds of the same circuit ...")
         cfgs = [circuits.config_plain_gpu(seed=2 + i) for i in range(B)]
-        g, el, first = run_batched(cfgs, MPS, apply_batch, dev, keep_first=True)
+        g, el, first, plan_s = run_batched(cfgs, MPS, apply_batch, dev, keep_first=True)
         same = bool(np.array_equal(first.amplitudes(probe), plain_amps))
         first.close()
         forms["batching_same_circuit"] = {
             "workload": f"{B} circuits: the plain workload with circuit seeds 2..{B + 1}, "
                         "each layer of all circuits in one mps_apply_batch call",
             "circuits": B, "gates": g, "seconds": el, "value": g / el, "unit": "gate applies/s",
-            "vs_plain": (g / el) / (args.steps * ngates / elapsed),
+            "vs_plain": (g / el) / (args.steps * ngates / elapsed), "host_plan_s": plan_s,
             "seed2_bitwise_equal_to_plain": same}
         log(f"  {g / el:.1f} gate applies/s")
     if args.mix_circuits > 0:
         n = args.mix_circuits
-        log(f"batching form: first {n} circuits of the mixed workload ...")
+        log(f"batching form: {n} circuits of the mixed workload ...")
         cfgs = circuits.config_batch_mix(512)[:n]
-        g, el, _ = run_batched(cfgs, MPS, apply_batch, dev)
+        g, el, _, plan_s = run_batched(cfgs, MPS, apply_batch, dev)
         forms["batching_mix"] = {
-            "workload": f"first {n} of 512 mixed circuits (circuit i: L ~ U{{16..48}}, floor(L/2) photons "
+            "workload": f"{n} of the 512 mixed circuits (circuit i: L ~ U{{16..48}}, floor(L/2) photons "
                         "in the first modes, d=4, depth L, chi_max ~ U{64,128,256,512}, cutoff 1e-12, "
-                        "seed 4000+i; mix seed 4), complex128, layer k of all circuits in one call",
-            "circuits": n, "gates": g, "seconds": el, "value": g / el, "unit": "gate applies/s"}
+                        "seed 4000+i; mix seed 4), complex128, layer k of all circuits in one "
+                        "mps_apply_batch call, Jacobi sweeps replayed from captured HIP graphs",
+            "circuits": n, "gates": g, "seconds": el, "value": g / el, "unit": "gate applies/s",
+            "vs_plain": (g / el) / (args.steps * ngates / elapsed), "host_plan_s": plan_s}
         log(f"  {g / el:.1f} gate applies/s")
 
     # dominant kernel: the blocked Jacobi step (one launch per round-robin step)
@@ -544,12 +613,17 @@ def main() -> int:
                 "flops_per_launch": per_launch_flops, "launches": launches}
     props = torch.cuda.get_device_properties(0)
     value = args.steps * ngates / elapsed
-    if not args.no_chi2048:
-        log("sector products on a chi=2048 layer, plain and split-BF16 ...")
-        forms["sector_gemm_chi2048"] = sector_gemm_chi2048(MPS, dev, circuits)
-        g = forms["sector_gemm_chi2048"]
-        log(f"  plain {g['plain']['tflops']:.1f} TFLOP/s, split {g['split_bf16x3']['tflops_algorithmic']:.1f} "
-            f"(MFMA {100 * g['split_bf16x3']['frac_of_bf16_peak']:.1f}% of BF16 peak)")
+    if args.chi2048_layers > 0:
+        log(f"precision form: {args.chi2048_layers} layers of a saturated chi=2048 state, plain and split ...")
+        forms["precision_chi2048"] = precision_chi2048(MPS, dev, circuits, args.chi2048_layers)
+        g = forms["precision_chi2048"]
+        log(f"  products: plain {g['plain']['tflops']:.1f} TFLOP/s, split "
+            f"{g['split_bf16x3']['tflops_algorithmic']:.1f} (MFMA {100 * g['split_bf16x3']['frac_of_bf16_peak']:.1f}% "
+            f"of BF16 peak); {g['gate_applies_per_s']['plain']:.1f} / {g['gate_applies_per_s']['split_bf16x3']:.1f} "
+            f"gate applies/s; split vs plain {g['split_vs_plain_amplitude_rel_err']:.2e}")
+    if args.precision_full:
+        log("precision form: the whole 2016-gate chi_max=2048 circuit, plain and split ...")
+        forms["precision_full_circuit"] = precision_full(MPS, dev, circuits)
     tebd = {}
     if not args.no_tebd:
         from workloads import hamiltonians
@@ -569,8 +643,9 @@ def main() -> int:
         forms["serving"]["workload"] = (
             "Poisson arrivals of the serving mix (95% batching-mix circuits, 5% L=64, 32 photons, "
             "chi_max=1024, depth 64; request j seed 5000+j, 16 sampled amplitudes each), admitted by "
-            f"an HBM budget of {args.serve_budget_gib:g} GiB and at most {args.serve_max_active} active per "
-            "lane, two lanes (chi_max=1024 requests, the rest) each on its own stream and host thread, one "
+            f"an HBM budget of {args.serve_budget_gib:g} GiB, two lanes (chi_max=1024 requests, at most "
+            f"{args.serve_max_large} active; the rest, at most {args.serve_max_active} active) each on its own "
+            "stream and host thread, one "
             "batch call per layer of all active requests of a lane; window without drain, unfinished "
             "requests reported as censored")
         log(f"  {forms['serving']['gate_applies_per_s']:.1f} gate applies/s, "

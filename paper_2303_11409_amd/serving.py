@@ -146,7 +146,8 @@ class Server:
 
     hbm_budget: bytes of device memory the admitted requests may hold together
     (shared by all lanes).
-    max_active: upper bound on simultaneously admitted requests per lane.
+    max_active: upper bound on simultaneously admitted requests per lane (an
+    int for every lane, or one value per lane).
     devices: one TorchDevice per lane (each with its own stream); None means one
     lane on the default device.  Each lane is a host thread that runs the loop
     on its own requests and stream, so the lanes' launches share the device.
@@ -156,13 +157,17 @@ class Server:
     state_opts: extra keyword options of every request's MPS (for instance
     sweep_graph=1)."""
 
-    def __init__(self, hbm_budget: int, max_active: int = 1024, device=None,
+    def __init__(self, hbm_budget: int, max_active=1024, device=None,
                  clock: Optional[Callable[[], float]] = None, devices: Optional[Sequence] = None,
                  lane_of: Optional[Callable[[dict], int]] = None, state_opts: Optional[dict] = None):
         self.hbm_budget = int(hbm_budget)
         self.state_opts = dict(state_opts or {})
-        self.max_active = int(max_active)
         self.devices = list(devices) if devices else [device]
+        nl = len(self.devices)
+        ma = list(max_active) if isinstance(max_active, (list, tuple)) else [max_active] * nl
+        if len(ma) != nl:
+            raise ValueError("one max_active per lane")
+        self.max_active = [int(x) for x in ma]
         self.lane_of = lane_of or (lambda spec: 0)
         self._t0 = None
         self._clock = clock
@@ -223,7 +228,7 @@ class Server:
                 if until is not None and t >= until:
                     break
                 # admit every arrived request of this lane that fits, in arrival order
-                while qi < len(queue) and queue[qi].arrival <= t and len(active) < self.max_active:
+                while qi < len(queue) and queue[qi].arrival <= t and len(active) < self.max_active[k]:
                     r = queue[qi]
                     if r.bytes > self.hbm_budget:
                         # can never fit: refuse it and serve the others
