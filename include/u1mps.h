@@ -206,6 +206,29 @@ mps_status mps_create_product(int L, int d, const int* occupation,
                               const mps_opts* opts, const mps_device* dev,
                               mps_t* out);
 
+/* A product state whose local states carry one or two independent U(1)
+ * charges (the paper's general Abelian symmetries, Sec. I; for example two
+ * species of hard-core bosons, local state p = 2 a + b carrying the pair of
+ * species numbers (a, b)).  charge_map[p * ncomp + k] (0..64) is component k
+ * of the charge of local state p; ncomp is 1 or 2, the rows must be distinct,
+ * and the modulus option must be 0.  The right-charges of Eq. (E3) are then
+ * sums of these (pairs for ncomp = 2), the rule of Eq. (E2) allows an entry
+ * on local state p between left charge cL and right charge cR when
+ * cL - cR = charge_map[p], and a gate must conserve the charge of the pair
+ * of sites: such a state takes dense gates only (mps_apply_layer_dense, which
+ * refuses a charge-changing element).  Amplitudes, norms, sampling and the
+ * cut are those of the U(1) case; mps_bond_charges reads the bookkeeping as
+ * components, mps_bond_sectors as internal integer keys.
+ * Errors: MPS_E_ARG, MPS_E_NOMEM, MPS_E_DEVICE. */
+mps_status mps_create_product_charges(int L, int d, const int* occupation, int ncomp,
+                                      const int* charge_map, const mps_opts* opts,
+                                      const mps_device* dev, mps_t* out);
+
+/* Number of charge components of the state (1 for U(1) and Z_n states, 1 or
+ * 2 for mps_create_product_charges). */
+mps_status mps_charge_components(mps_t h, int* ncomp);
+
+
 /* Release every resource of the handle (NULL is accepted). */
 mps_status mps_destroy(mps_t h);
 
@@ -310,6 +333,12 @@ mps_status mps_sample(mps_t h, int count, const double* uniforms, int* occ, doub
  * count[]; *nsec receives the number of sectors (MPS_E_ARG if > cap). */
 mps_status mps_bond_sectors(mps_t h, int bond, int cap, int* nsec,
                             int* charge, int* count);
+
+/* Bookkeeping of bond `bond` with the charges as components: sector i has
+ * charge comps[i * ncomp .. i * ncomp + ncomp - 1] (ncomp from
+ * mps_charge_components; sectors in lexicographic order) and multiplicity
+ * count[i].  cap is the number of sectors comps[] and count[] can hold. */
+mps_status mps_bond_charges(mps_t h, int bond, int cap, int* nsec, int* comps, int* count);
 
 /* Schmidt values of bond `bond`, ordered by ascending charge and, within a
  * charge, descending value.  *n receives the bond dimension. */

@@ -70,7 +70,8 @@ class mps_stats(C.Structure):
                 ("graph_launches", C.c_longlong), ("host_plan_ms", C.c_double)]
 
 
-EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_destroy", "mps_apply_gate",
+EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_create_product_charges",
+           "mps_charge_components", "mps_bond_charges", "mps_destroy", "mps_apply_gate",
            "mps_apply_layer", "mps_apply_layer_dense", "mps_apply_batch", "mps_truncate", "mps_amplitude", "mps_norm", "mps_norm_noalloc", "mps_sample", "mps_bond_sectors",
            "mps_bond_lambda", "mps_site_tensor", "mps_last_leaks", "mps_set_timing", "mps_get_stats",
            "mps_reset_stats", "mps_sync", "mps_last_error"]
@@ -93,6 +94,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
         "mps_create": (st, [C.c_int, C.c_int, C.c_int, P(C.c_int), P(C.c_int), P(P(mps_z)),
                             P(P(C.c_double)), P(mps_opts), P(mps_device), P(h)]),
         "mps_create_product": (st, [C.c_int, C.c_int, P(C.c_int), P(mps_opts), P(mps_device), P(h)]),
+        "mps_create_product_charges": (st, [C.c_int, C.c_int, P(C.c_int), C.c_int, P(C.c_int), P(mps_opts),
+                                            P(mps_device), P(h)]),
+        "mps_charge_components": (st, [h, P(C.c_int)]),
+        "mps_bond_charges": (st, [h, C.c_int, C.c_int, P(C.c_int), P(C.c_int), P(C.c_int)]),
         "mps_destroy": (st, [h]),
         "mps_apply_gate": (st, [h, C.c_int, P(mps_z), P(C.c_double)]),
         "mps_apply_layer": (st, [h, C.c_int, P(C.c_int), P(mps_z), P(C.c_double)]),
@@ -190,17 +195,22 @@ def _close_all() -> None:
 
 class MPS:
     """A U(1)-symmetric MPS on the GPU, created as a Fock product state.
-    modulus n >= 2 (with d == n) makes the charge the particle number mod n."""
+    modulus n >= 2 (with d == n) makes the charge the particle number mod n;
+    charge_map (d x K integers, K = 1 or 2) gives every local state its own
+    charge with K independent U(1) components (mps_create_product_charges)."""
 
     def __init__(self, occupation: Sequence[int], d: int, chi_max: int = 0, cutoff: float = 0.0,
                  zero_tol: float = 1e-13, max_sweeps: int = 40, jacobi_tol: float = 0.0,
                  device: Optional[TorchDevice] = None, form: int = FORM_PLAIN_C128, modulus: int = 0,
-                 blocked_sweeps: int = 0, select_scratch: int = 0, sweep_graph: int = 0, _handle=None):
+                 blocked_sweeps: int = 0, select_scratch: int = 0, sweep_graph: int = 0, charge_map=None,
+                 _handle=None):
         self._lib = lib()
         self.L = len(occupation)
         self.d = d
         self.N = int(sum(occupation))
         self.modulus = int(modulus)
+        self.ncomp = 1
+        self._cap = max(self.N + 1, self.modulus)
         self._dev = device if device is not None else TorchDevice()
         self._dev_struct = self._dev.struct()
         self._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus),
@@ -210,8 +220,19 @@ class MPS:
             self._h = _handle
             return
         occ = (C.c_int * self.L)(*[int(x) for x in occupation])
-        _check(self._lib.mps_create_product(self.L, d, occ, C.byref(self._opts),
-                                            C.byref(self._dev_struct), C.byref(self._h)))
+        if charge_map is None:
+            _check(self._lib.mps_create_product(self.L, d, occ, C.byref(self._opts),
+                                                C.byref(self._dev_struct), C.byref(self._h)))
+        else:
+            cm = np.asarray(charge_map, dtype=np.int64).reshape(d, -1)
+            self.ncomp = int(cm.shape[1])
+            flat = (C.c_int * cm.size)(*[int(x) for x in cm.reshape(-1)])
+            _check(self._lib.mps_create_product_charges(self.L, d, occ, self.ncomp, flat, C.byref(self._opts),
+                                                        C.byref(self._dev_struct), C.byref(self._h)))
+            # sectors per bond: at most the number of distinct component tuples
+            tot = cm[[int(x) for x in occupation]].sum(axis=0)
+            self._cap = int(np.prod(tot + 1))
+            self.total = tuple(int(x) for x in tot)
         _OPEN.add(self)
 
     @classmethod
@@ -227,6 +248,8 @@ class MPS:
         obj._lib = lib()
         obj.L, obj.d, obj.N = L, d, n_photons
         obj.modulus = int(modulus)
+        obj.ncomp = 1
+        obj._cap = max(n_photons + 1, obj.modulus)
         obj._dev = device if device is not None else TorchDevice()
         obj._dev_struct = obj._dev.struct()
         obj._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus),
@@ -332,11 +355,17 @@ class MPS:
                                         prob.ctypes.data_as(C.POINTER(C.c_double))))
         return occ, prob
 
-    def bond_sectors(self, bond: int) -> Dict[int, int]:
-        cap = max(self.N + 1, self.modulus)
+    def bond_sectors(self, bond: int) -> Dict:
+        """Charge -> multiplicity of a bond; with a two-component charge map the
+        charges are (c1, c2) tuples."""
+        cap = self._cap
         n = C.c_int(0)
-        ch = (C.c_int * cap)()
         cnt = (C.c_int * cap)()
+        if self.ncomp == 2:
+            ch = (C.c_int * (2 * cap))()
+            _check(self._lib.mps_bond_charges(self._h, int(bond), cap, C.byref(n), ch, cnt))
+            return {(int(ch[2 * i]), int(ch[2 * i + 1])): int(cnt[i]) for i in range(n.value)}
+        ch = (C.c_int * cap)()
         _check(self._lib.mps_bond_sectors(self._h, int(bond), cap, C.byref(n), ch, cnt))
         return {int(ch[i]): int(cnt[i]) for i in range(n.value)}
 

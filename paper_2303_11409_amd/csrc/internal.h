@@ -38,17 +38,31 @@ struct GateWork {
   double zero_tol;
 };
 
+// The charge of every local state (an entry of a site tensor on local state p
+// joins a left charge cL to the right charge cL - s[p]); U(1) and Z_n: s[p] = p.
+struct Steps {
+  int s[kMaxD];
+};
+
 // One middle-charge sector Theta(m) of one gate.
 struct SectorWork {
   int gate;               // index into the batch's GateWork list
   int m;                  // middle charge
   int r, c;               // Theta(m) is r x c
-  int rlo, clo;           // first row (bond s index) / column (bond s+2 index)
+  int rlo, clo;           // first row (bond s index) / column (bond s+2 index) of the first block
   long long off;          // element offset of Theta(m) in the theta workspaces
   int sig;                // offset of this sector's r singular values / row order
   int kmax;               // min(r, c): at most this many values enter the cut
   int tall;               // r > c: the SVD orthogonalises the c columns instead
   long long acc;          // tall only: element offset of the c x c rotation accumulator
+  // the rows of Theta(m) are row blocks of the bond-s frame and its columns
+  // column blocks of the bond-(s+2) frame, packed in ascending charge order:
+  // block k covers frame rows rb_off[k] .. rb_off[k] + rb_n[k] - 1 at rows
+  // rb_pos[k] .. of Theta(m) (likewise cb_* for columns).  U(1) and Z_n
+  // sectors are one block each way; two U(1) components give several.
+  int nrb, ncb;
+  int rb_off[kMaxD], rb_n[kMaxD], rb_pos[kMaxD];
+  int cb_off[kMaxD], cb_n[kMaxD], cb_pos[kMaxD];
 };
 
 // One 32x32 output tile of one (cL, cR) charge pair of one gate.  The tile

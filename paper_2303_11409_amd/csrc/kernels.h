@@ -62,7 +62,7 @@ hipError_t launch_theta_mix(const GateWork* gates, const ThetaTile* tiles, int n
 // mod: 0 for a U(1) charge, n for a Z_n charge (bondmap then has n entries per bond).
 hipError_t launch_amplitude(const double2* const* sites, const int* ld, const int2* bondmap,
                             const int* occ, double2* out, int count, int L, int d, int N, int mod,
-                            int maxdim, hipStream_t st);
+                            int maxdim, Steps steps, hipStream_t st);
 
 // Chain-rule sampling of `count` patterns (sample.hip): sites[s] (ldb[s]) and
 // the left environments envs[s] (lde[s]) of every site, bondmap[(b, c)] =
@@ -70,7 +70,8 @@ hipError_t launch_amplitude(const double2* const* sites, const int* ld, const in
 // prob (-1 where a marginal vanished or was not finite).
 hipError_t launch_sample(const double2* const* sites, const int* ldb, const double2* const* envs,
                          const int* lde, const int2* bondmap, const double* uniforms, int* occ,
-                         double* prob, int count, int L, int d, int N, int mod, int maxblk, hipStream_t st);
+                         double* prob, int count, int L, int d, int N, int mod, int maxblk, Steps steps,
+                         hipStream_t st);
 
 hipError_t launch_gather_cols(const double2* src, int lds, double2* dst, int ldd, int rows,
                               const int* map, int ncols, hipStream_t st);

@@ -226,8 +226,11 @@ update_rows_kernel(const RowWork* __restrict__ rows, const SectorWork* __restric
   const double2* xr = vh + s.off + (size_t)src * s.c;
   double2* dst = u.br_new + (size_t)rw.row * u.ldr;
   for (int col = threadIdx.x; col < u.ldr; col += blockDim.x) {
-    const int cc = col - s.clo;
-    dst[col] = (cc >= 0 && cc < s.c) ? xr[cc] : make_double2(0.0, 0.0);
+    // the sector's columns are its column blocks of the frame; zero elsewhere
+    int cc = -1;
+    for (int k = 0; k < s.ncb; ++k)
+      if (col >= s.cb_off[k] && col < s.cb_off[k] + s.cb_n[k]) cc = s.cb_pos[k] + col - s.cb_off[k];
+    dst[col] = cc >= 0 ? xr[cc] : make_double2(0.0, 0.0);
   }
   if (threadIdx.x == 0) u.lam_new[rw.row] = sigma[s.sig + rw.j];
 }
@@ -317,14 +320,15 @@ zgemm_kernel(const GemmWork* __restrict__ probs, int nprob) {
 }
 
 // ---------------------------------------------------------------------------
-// Amplitudes: one workgroup per pattern.  The charge path c_{s+1} = c_s - occ_s
-// (mod n for a Z_n charge) selects one block of every site tensor (Eq. (E2));
-// the amplitude is the product of those blocks.  Any missing charge gives
-// exactly zero.  bondmap has nc = (mod ? mod : N + 1) entries per bond.
+// Amplitudes: one workgroup per pattern.  The charge path c_{s+1} = c_s -
+// step[occ_s] (mod n for a Z_n charge) selects one block of every site tensor
+// (Eq. (E2)); the amplitude is the product of those blocks.  Any missing
+// charge gives exactly zero.  bondmap has nc = (mod ? mod : N + 1) entries per
+// bond (N: the charge of bond 0, the largest of all).
 __global__ void __launch_bounds__(256)
 amplitude_kernel(const double2* const* __restrict__ sites, const int* __restrict__ ld,
                  const int2* __restrict__ bondmap, const int* __restrict__ occ,
-                 double2* __restrict__ out, int L, int d, int N, int mod, int maxdim) {
+                 double2* __restrict__ out, int L, int d, int N, int mod, int maxdim, Steps st) {
   const int nc = mod ? mod : N + 1;
   extern __shared__ double2 vsm[];
   double2* v0 = vsm;
@@ -337,8 +341,8 @@ amplitude_kernel(const double2* const* __restrict__ sites, const int* __restrict
     for (int s = 0; s < L; ++s) {
       const int x = o[s];
       if (x < 0 || x >= d) { good = 0; break; }
-      c = mod ? (c - x + mod) % mod : c - x;
-      if (c < 0) { good = 0; break; }
+      c = mod ? (c - x + mod) % mod : c - st.s[x];
+      if (c < 0 || c >= nc) { good = 0; break; }
       if (bondmap[(size_t)(s + 1) * nc + c].y == 0) { good = 0; break; }
     }
     if (c != 0) good = 0;
@@ -353,7 +357,7 @@ amplitude_kernel(const double2* const* __restrict__ sites, const int* __restrict
   int c = N;
   int n0 = 1, off0 = bondmap[c].x;   // bond 0 holds only charge N
   for (int s = 0; s < L; ++s) {
-    const int c1 = mod ? (c - o[s] + mod) % mod : c - o[s];
+    const int c1 = mod ? (c - o[s] + mod) % mod : c - st.s[o[s]];
     const int2 b1 = bondmap[(size_t)(s + 1) * nc + c1];
     const double2* B = sites[s];
     const int lds = ld[s];
@@ -443,11 +447,11 @@ hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_
 
 hipError_t launch_amplitude(const double2* const* sites, const int* ld, const int2* bondmap,
                             const int* occ, double2* out, int count, int L, int d, int N, int mod,
-                            int maxdim, hipStream_t st) {
+                            int maxdim, Steps steps, hipStream_t st) {
   if (count <= 0) return hipSuccess;
   const size_t smem = (size_t)2 * maxdim * sizeof(double2);
   hipLaunchKernelGGL(amplitude_kernel, dim3(count), dim3(256), smem, st, sites, ld, bondmap, occ, out, L, d, N, mod,
-                     maxdim);
+                     maxdim, steps);
   return hipGetLastError();
 }
 

@@ -73,12 +73,55 @@ struct Bond {
 
 // Charge arithmetic: U(1) (mod 0) or Z_n (mod n, charges in 0..n-1).
 inline int cwrap(int mod, int c) { return mod ? ((c % mod) + mod) % mod : c; }
-// Is a site entry between left charge ci and right charge cj allowed (Eq. (E2)),
-// i.e. is ci - cj a local occupation 0..d-1 (mod n for Z_n)?
-inline bool step_ok(int mod, int d, int ci, int cj) {
-  const int p = cwrap(mod, ci - cj);
-  return p >= 0 && p <= d - 1;
-}
+
+// The charge rule of a state.  Local state p carries the charge step[p]; an
+// entry of a site tensor between left charge cL and right charge cR is allowed
+// when cL - cR is some step[p] (mod n for Z_n), and then p is its local state:
+// Eq. (E2), with the occupation in the Kronecker delta replaced by the local
+// state's charge.  U(1) photon number: step[p] = p.  Z_n (d = n): the same
+// steps, charges mod n.  Two U(1) charges (the general Abelian case): a charge
+// (c1, c2) is the integer key c1 * radix + c2 with radix above twice every
+// second component, so keys add like the pairs, a difference of keys fixes
+// the difference of pairs, and ascending keys are the pairs in lexicographic
+// order; step[p] is the key of local state p's pair.
+struct ChargeRule {
+  int mod = 0;
+  std::vector<int> step;      // d entries, distinct, >= 0
+  std::vector<int> sums;      // distinct two-site totals step[p] + step[q] (mod n), ascending
+  int minstep = 0, maxstep = 0;
+  bool photon = true;         // U(1) with step[p] = p (beam splitters apply)
+  void init(int m, const std::vector<int>& st) {
+    mod = m;
+    step = st;
+    const int d = (int)st.size();
+    photon = !m;
+    for (int p = 0; p < d; ++p) photon = photon && st[p] == p;
+    minstep = *std::min_element(st.begin(), st.end());
+    maxstep = *std::max_element(st.begin(), st.end());
+    sums.clear();
+    for (int p = 0; p < d; ++p)
+      for (int q = 0; q < d; ++q) sums.push_back(cwrap(m, st[p] + st[q]));
+    std::sort(sums.begin(), sums.end());
+    sums.erase(std::unique(sums.begin(), sums.end()), sums.end());
+  }
+  // the local state p with step[p] == diff (mod n), or -1
+  int local(int diff) const {
+    if (mod) diff = cwrap(mod, diff);
+    for (size_t p = 0; p < step.size(); ++p)
+      if (step[p] == diff) return (int)p;
+    return -1;
+  }
+  bool ok(int ci, int cj) const { return local(ci - cj) >= 0; }
+  int sum_index(int total) const {
+    if (mod) total = cwrap(mod, total);
+    auto it = std::lower_bound(sums.begin(), sums.end(), total);
+    return (it != sums.end() && *it == total) ? int(it - sums.begin()) : -1;
+  }
+  // does a two-site element (p, q) <- (a, b) keep the charge?
+  bool conserves(int p, int q, int a, int b) const {
+    return cwrap(mod, step[p] + step[q] - step[a] - step[b]) == 0;
+  }
+};
 
 struct DevBuf {
   void* p = nullptr;
@@ -114,6 +157,9 @@ struct mps_state {
   int L = 0, d = 0, N = 0;
   int mod = 0;                   // 0: U(1) particle number; n: particle number mod n (d == n)
   int device = 0;                // the GPU current when the handle was created
+  ChargeRule rule;               // charges of the local states (U(1), Z_n, or two U(1) components)
+  int ncomp = 1;                 // charge components packed into one key (1 or 2)
+  int radix = 0;                 // ncomp == 2: key = c1 * radix + c2
   mps_opts opts{};
   mps_device dev{};
   hipStream_t st = nullptr;
@@ -302,54 +348,46 @@ void gate_blocks(const mps_z u[4], int d, double2* out) {
 }
 
 // G^(n)[p][a] of a gate given as a dense d^2 x d^2 matrix (row p*d+q, column
-// a*d+b): the element of row p*d+(n-p) and column a*d+(n-a).  Elements that
-// change the charge were checked to be negligible and are not read.
-// For a Z_n charge (mod = n = d) the blocks are indexed by the total mod n and
-// the second site's occupation is (n - p) mod n.
-void dense_blocks(const mps_z* g4, int d, int mod, double2* out) {
-  const int nb = 2 * d - 1, dd = d * d;
+// a*d+b): for the n-th two-site total S of the rule, the element of row
+// p*d+q and column a*d+b with step[p] + step[q] = step[a] + step[b] = S (mod n
+// for Z_n).  Elements that change the charge were checked to be negligible
+// and are not read.
+void dense_blocks(const mps_z* g4, int d, const ChargeRule& R, double2* out) {
+  const int nb = (int)R.sums.size(), dd = d * d;
   for (int i = 0; i < nb * d * d; ++i) out[i] = make_double2(0.0, 0.0);
-  if (mod) {
-    for (int n = 0; n < mod; ++n)
-      for (int p = 0; p < d; ++p)
-        for (int a = 0; a < d; ++a) {
-          const mps_z v = g4[(size_t)(p * d + cwrap(mod, n - p)) * dd + a * d + cwrap(mod, n - a)];
-          out[(n * d + p) * d + a] = make_double2(v.re, v.im);
-        }
-    return;
-  }
-  for (int n = 0; n < nb; ++n)
-    for (int p = std::max(0, n - d + 1); p <= std::min(d - 1, n); ++p)
-      for (int a = std::max(0, n - d + 1); a <= std::min(d - 1, n); ++a) {
-        const mps_z v = g4[(size_t)(p * d + n - p) * dd + a * d + n - a];
+  for (int n = 0; n < nb; ++n) {
+    const int S = R.sums[n];
+    for (int p = 0; p < d; ++p) {
+      const int q = R.local(S - R.step[p]);
+      if (q < 0) continue;
+      for (int a = 0; a < d; ++a) {
+        const int b = R.local(S - R.step[a]);
+        if (b < 0) continue;
+        const mps_z v = g4[(size_t)(p * d + q) * dd + a * d + b];
         out[(n * d + p) * d + a] = make_double2(v.re, v.im);
       }
+    }
+  }
 }
 
 // ---- capacities ------------------------------------------------------------
 // Largest Schmidt rank a bond can reach: sum over charges c of
-// min(#left strings with N-c photons, #right strings with c photons),
-// strings over the sites of each side with occupations < d.
-std::vector<double> strings_count(int sites, int d, int N) {
-  std::vector<double> cnt(N + 1, 0.0), nx(N + 1);
+// min(#left strings of total charge N - c, #right strings of total charge c),
+// strings over the sites of each side with local states 0..d-1 (charges as
+// keys 0..N, or mod n).
+std::vector<double> strings_by_charge(int sites, const ChargeRule& R, int N) {
+  const int n = R.mod ? R.mod : N + 1;
+  std::vector<double> cnt(n, 0.0), nx(n);
   cnt[0] = 1.0;
   for (int s = 0; s < sites; ++s) {
     std::fill(nx.begin(), nx.end(), 0.0);
-    for (int n = 0; n <= N; ++n)
-      for (int a = 0; a < d && a <= n; ++a) nx[n] += cnt[n - a];
-    cnt.swap(nx);
-  }
-  return cnt;
-}
-
-// Strings over `sites` sites with occupations < d, counted by their sum mod n.
-std::vector<double> strings_count_mod(int sites, int d, int mod) {
-  std::vector<double> cnt(mod, 0.0), nx(mod);
-  cnt[0] = 1.0;
-  for (int s = 0; s < sites; ++s) {
-    std::fill(nx.begin(), nx.end(), 0.0);
-    for (int c = 0; c < mod; ++c)
-      for (int a = 0; a < d; ++a) nx[(c + a) % mod] += cnt[c];
+    for (int c = 0; c < n; ++c) {
+      if (cnt[c] == 0.0) continue;
+      for (int st : R.step) {
+        const int c2 = R.mod ? (c + st) % R.mod : c + st;
+        if (c2 < n) nx[c2] += cnt[c];
+      }
+    }
     cnt.swap(nx);
   }
   return cnt;
@@ -357,16 +395,14 @@ std::vector<double> strings_count_mod(int sites, int d, int mod) {
 
 mps_status compute_caps(mps_state* h) {
   h->cap.assign(h->L + 1, 1);
+  const int n = h->mod ? h->mod : h->N + 1;
   for (int b = 0; b <= h->L; ++b) {
     double tot = 0.0;
-    if (h->mod) {
-      const std::vector<double> left = strings_count_mod(b, h->d, h->mod);
-      const std::vector<double> right = strings_count_mod(h->L - b, h->d, h->mod);
-      for (int c = 0; c < h->mod; ++c) tot += std::min(left[cwrap(h->mod, h->N - c)], right[c]);
-    } else {
-      const std::vector<double> left = strings_count(b, h->d, h->N);
-      const std::vector<double> right = strings_count(h->L - b, h->d, h->N);
-      for (int c = 0; c <= h->N; ++c) tot += std::min(left[h->N - c], right[c]);
+    const std::vector<double> left = strings_by_charge(b, h->rule, h->N);
+    const std::vector<double> right = strings_by_charge(h->L - b, h->rule, h->N);
+    for (int c = 0; c < n; ++c) {
+      const int lc = h->mod ? cwrap(h->mod, h->N - c) : h->N - c;
+      tot += std::min(left[lc], right[c]);
     }
     if (h->opts.chi_max > 0) tot = std::min(tot, double(h->opts.chi_max));
     tot = std::max(tot, double(h->bonds[b].dim()));
@@ -429,64 +465,111 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
   P.split = refs[0].h->opts.form == MPS_FORM_SPLIT_BF16X3;
   P.gates.resize(ng);
   P.gp.resize(ng);
-  P.coef.assign((size_t)ng * (2 * d - 1) * d * d, make_double2(0.0, 0.0));
+  P.coef.clear();
   for (int g = 0; g < ng; ++g) {
     mps_state* h = refs[g].h;
+    const ChargeRule& R = h->rule;
     const int s = refs[g].site;
     const Bond& BL = h->bonds[s];
     const Bond& BM = h->bonds[s + 1];
     const Bond& BR = h->bonds[s + 2];
-    double2* cg = P.coef.data() + (size_t)g * (2 * d - 1) * d * d;
+    // gate blocks G^(n) for the rule's two-site totals (U(1): n = 0..2d-2)
+    const size_t coef0 = P.coef.size();
+    P.coef.resize(coef0 + R.sums.size() * d * d, make_double2(0.0, 0.0));
+    double2* cg = P.coef.data() + coef0;
     if (refs[g].u)
       gate_blocks(refs[g].u, d, cg);
     else
-      dense_blocks(refs[g].g4, d, h->mod, cg);
+      dense_blocks(refs[g].g4, d, R, cg);
     GateWork gw{};
     gw.bl = h->site[s];
     gw.br = h->site[s + 1];
     gw.lam_l = h->lam[s];
     gw.ldl = BM.dim();
     gw.ldr = BR.dim();
-    gw.coef = g * (2 * d - 1) * d * d;
+    gw.coef = (int)coef0;
     gw.d = d;
     gw.sec_begin = (int)P.secs.size();
     gw.keep_cap = h->cap[s + 1];
     gw.chi_max = h->opts.chi_max;
     gw.cutoff = h->opts.cutoff;
     gw.zero_tol = h->opts.zero_tol;
-    // sectors: every middle charge m with rows (cL in [m, m+d-1]) and
-    // columns (cR in [m-d+1, m]) present.  For a Z_n charge with d = n every
-    // row and every column belongs to every m (the occupation is cL - m mod n).
+    // sectors: every middle charge m with rows (charges cL of bond s with
+    // cL - m a local charge) and columns (charges cR of bond s+2 with m - cR a
+    // local charge).  U(1): cL in [m, m+d-1], cR in [m-d+1, m]; Z_n (d = n):
+    // every row and every column belongs to every m.  The rows of Theta(m)
+    // are its row blocks in ascending charge order, packed; blocks adjacent
+    // in the frame are merged (so a U(1) or Z_n sector is one row block and
+    // one column block).
     const int zn = h->mod;
-    const int mlo = zn ? 0 : std::max(BL.charge.front() - (d - 1), BR.charge.front());
-    const int mhi = zn ? zn - 1 : std::min(BL.charge.back(), BR.charge.back() + (d - 1));
-    std::vector<int> secmap(std::max(0, mhi - mlo + 1), -1);
+    std::vector<int> cand;
+    if (zn) {
+      for (int m = 0; m < zn; ++m) cand.push_back(m);
+    } else {
+      for (int cL : BL.charge)
+        for (int st : R.step) cand.push_back(cL - st);
+      std::sort(cand.begin(), cand.end());
+      cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    }
+    std::vector<int> secm;          // middle charge of every sector of this gate, ascending
     int T = 0;
-    for (int m = mlo; m <= mhi; ++m) {
-      const int i0 = zn ? 0 : BL.lower(m), i1 = zn ? (int)BL.charge.size() : BL.lower(m + d);
-      const int j0 = zn ? 0 : BR.lower(m - d + 1), j1 = zn ? (int)BR.charge.size() : BR.lower(m + 1);
-      const int r = BL.off[i1] - BL.off[i0];
-      const int c = BR.off[j1] - BR.off[j0];
-      if (r <= 0 || c <= 0) continue;
+    auto add_block = [](int& nb, int* off, int* n, int* pos, int fo, int fn, int total) {
+      if (nb > 0 && off[nb - 1] + n[nb - 1] == fo) {
+        n[nb - 1] += fn;
+      } else {
+        off[nb] = fo;
+        n[nb] = fn;
+        pos[nb] = total;
+        ++nb;
+      }
+    };
+    for (int m : cand) {
       SectorWork sw{};
+      int r = 0, c = 0;
+      for (size_t i = 0; i < BL.charge.size(); ++i)
+        if (R.ok(BL.charge[i], m)) {
+          add_block(sw.nrb, sw.rb_off, sw.rb_n, sw.rb_pos, BL.off[i], BL.count[i], r);
+          r += BL.count[i];
+        }
+      for (size_t j = 0; j < BR.charge.size(); ++j)
+        if (R.ok(m, BR.charge[j])) {
+          add_block(sw.ncb, sw.cb_off, sw.cb_n, sw.cb_pos, BR.off[j], BR.count[j], c);
+          c += BR.count[j];
+        }
+      if (r <= 0 || c <= 0) continue;
       sw.gate = g;
       sw.m = m;
       sw.r = r;
       sw.c = c;
-      sw.rlo = BL.off[i0];
-      sw.clo = BR.off[j0];
+      sw.rlo = sw.rb_off[0];
+      sw.clo = sw.cb_off[0];
       sw.off = P.th_elems;
       sw.sig = P.sig_elems;
       sw.kmax = std::min(r, c);
       sw.tall = r > c ? 1 : 0;
       sw.acc = P.acc_elems;
       if (sw.tall) P.acc_elems += (long long)c * c;
-      secmap[m - mlo] = (int)P.secs.size();
+      secm.push_back(m);
       P.secs.push_back(sw);
       P.th_elems += (long long)r * c;
       P.sig_elems += r;
       T += sw.kmax;
     }
+    auto sector_of = [&](int m) {
+      auto it = std::lower_bound(secm.begin(), secm.end(), m);
+      return (it != secm.end() && *it == m) ? gw.sec_begin + int(it - secm.begin()) : -1;
+    };
+    // position inside Theta(m) of frame row fr (resp. column fc)
+    auto row_pos = [](const SectorWork& w, int fr) {
+      for (int k = 0; k < w.nrb; ++k)
+        if (fr >= w.rb_off[k] && fr < w.rb_off[k] + w.rb_n[k]) return w.rb_pos[k] + fr - w.rb_off[k];
+      return -1;
+    };
+    auto col_pos = [](const SectorWork& w, int fc) {
+      for (int k = 0; k < w.ncb; ++k)
+        if (fc >= w.cb_off[k] && fc < w.cb_off[k] + w.cb_n[k]) return w.cb_pos[k] + fc - w.cb_off[k];
+      return -1;
+    };
     gw.sec_end = (int)P.secs.size();
     if (gw.sec_end == gw.sec_begin) return fail(MPS_E_CHARGE, "gate at site %d has no charge sector", s);
     if (gw.sec_end - gw.sec_begin > 1024) return fail(MPS_E_ARG, "more than 1024 sectors in one update");
@@ -524,36 +607,41 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
       const int cL = BL.charge[a];
       for (size_t b = 0; b < BR.charge.size(); ++b) {
         const int cR = BR.charge[b];
-        const int n = cwrap(zn, cL - cR);
-        if (!zn && (n < 0 || n > 2 * d - 2)) continue;
-        // window of middle charges (old bond) and new sectors: U(1) the
-        // integers between max(cR, cL-d+1) and min(cL, cR+d-1); Z_n all of them
-        const int wlo = zn ? 0 : std::max(cR, cL - d + 1), whi = zn ? zn - 1 : std::min(cL, cR + d - 1);
+        const int n = R.sum_index(cL - cR);
+        if (n < 0) continue;
+        // the new sectors m (cL - m and m - cR local charges) and the old
+        // middle charges cM (likewise), each in ascending charge order
+        std::vector<std::pair<int, int>> outs, ins;
+        for (int p = 0; p < d; ++p) {
+          const int m = cwrap(zn, cL - R.step[p]);
+          if (R.ok(m, cR)) outs.push_back({m, p});
+        }
+        std::sort(outs.begin(), outs.end());
+        for (const auto& mp : outs) ins.push_back(mp);
         ThetaTile base{};
         base.gate = g;
         base.n = n;
-        for (int m = wlo; m <= whi; ++m) {
-          const int si = (m >= mlo && m <= mhi) ? secmap[m - mlo] : -1;
-          if (si < 0) {
-            if (zn) continue;
-            return fail(MPS_E_CHARGE, "internal: sector %d missing at site %d", m, s);
-          }
+        for (const auto& mp : outs) {
+          const int si = sector_of(mp.first);
+          if (si < 0) return fail(MPS_E_CHARGE, "internal: sector %d missing at site %d", mp.first, s);
           const SectorWork& sw = P.secs[si];
           base.sec[base.nout] = si;
-          base.p[base.nout] = cwrap(zn, cL - m);
-          base.orow[base.nout] = BL.off[a] - sw.rlo;
-          base.ocol[base.nout] = BR.off[b] - sw.clo;
+          base.p[base.nout] = mp.second;
+          base.orow[base.nout] = row_pos(sw, BL.off[a]);
+          base.ocol[base.nout] = col_pos(sw, BR.off[b]);
+          if (base.orow[base.nout] < 0 || base.ocol[base.nout] < 0)
+            return fail(MPS_E_CHARGE, "internal: block outside sector %d at site %d", mp.first, s);
           ++base.nout;
         }
         int ksum = 0;
         int mid[kMaxD];
-        for (int cM = wlo; cM <= whi; ++cM) {
-          const int mi = BM.find(cM);
+        for (const auto& mp : ins) {
+          const int mi = BM.find(mp.first);
           if (mi < 0) continue;
           mid[base.nin] = mi;
           base.k0[base.nin] = BM.off[mi];
           base.kn[base.nin] = BM.count[mi];
-          base.a[base.nin] = cwrap(zn, cL - cM);
+          base.a[base.nin] = mp.second;
           ksum += BM.count[mi];
           ++base.nin;
         }
@@ -636,6 +724,12 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
 }
 
 bool valid_handle(mps_t h) { return h != nullptr && h->L > 0; }
+
+Steps steps_of(const mps_state* h) {
+  Steps st{};
+  for (int p = 0; p < h->d; ++p) st.s[p] = h->rule.step[p];
+  return st;
+}
 
 mps_status check_device_limits(mps_state* h, const BatchPlan& P) {
   if ((size_t)P.jmaxrows * sizeof(double) > 64 * 1024)
@@ -899,9 +993,9 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   std::vector<UpdateWork> upds(ng);
   std::vector<double2*> fill_ptr(ng);
   std::vector<long long> fill_cnt(ng);
-  std::vector<GemmWork> gemms;
+  std::vector<std::vector<GemmWork>> gemms(1);   // per column block of the sectors
   long long maxfill = 0;
-  int ntiles = 0;
+  std::vector<int> ntiles(1, 0);
   std::vector<Bond> newb(ng);
   for (int g = 0; g < ng; ++g) {
     mps_state* hg = refs[g].h;
@@ -930,23 +1024,33 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
       const SectorWork& sw = P.secs[i];
       const int o = nb.off[k];
       for (int j = 0; j < kept[i]; ++j) rows.push_back({g, i, j, o + j});
-      GemmWork gw{};
-      gw.a = raw + sw.off;
-      gw.lda = sw.c;
-      gw.b = hg->site[s + 1] + (size_t)o * chir + sw.clo;
-      gw.ldb = chir;
-      gw.c = hg->site[s] + (size_t)sw.rlo * chin + o;
-      gw.ldc = chin;
-      gw.m = sw.r;
-      gw.n = kept[i];
-      gw.k = sw.c;
-      gw.opa = 0;
-      gw.opb = 1;
-      gw.beta_one = 0;
-      gw.tiles_n = (gw.n + kGemmTile - 1) / kGemmTile;
-      gw.tile_begin = ntiles;
-      ntiles += ((gw.m + kGemmTile - 1) / kGemmTile) * gw.tiles_n;
-      gemms.push_back(gw);
+      // new B[s](row block, kept) = sum over column blocks of
+      // Theta~(row block, column block) V^dagger(kept, column block)^dagger,
+      // column block kc in launch kc (accumulating after the first)
+      for (int kc = 0; kc < sw.ncb; ++kc)
+        for (int kr = 0; kr < sw.nrb; ++kr) {
+          GemmWork gw{};
+          gw.a = raw + sw.off + (size_t)sw.rb_pos[kr] * sw.c + sw.cb_pos[kc];
+          gw.lda = sw.c;
+          gw.b = hg->site[s + 1] + (size_t)o * chir + sw.cb_off[kc];
+          gw.ldb = chir;
+          gw.c = hg->site[s] + (size_t)sw.rb_off[kr] * chin + o;
+          gw.ldc = chin;
+          gw.m = sw.rb_n[kr];
+          gw.n = kept[i];
+          gw.k = sw.cb_n[kc];
+          gw.opa = 0;
+          gw.opb = 1;
+          gw.beta_one = kc > 0 ? 1 : 0;
+          gw.tiles_n = (gw.n + kGemmTile - 1) / kGemmTile;
+          if ((int)gemms.size() <= kc) {
+            gemms.resize(kc + 1);
+            ntiles.resize(kc + 1, 0);
+          }
+          gw.tile_begin = ntiles[kc];
+          ntiles[kc] += ((gw.m + kGemmTile - 1) / kGemmTile) * gw.tiles_n;
+          gemms[kc].push_back(gw);
+        }
       hg->stats.update_flops += 8.0 * sw.r * double(sw.c) * kept[i];
       ++k;
     }
@@ -956,7 +1060,9 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   const size_t u_upd = pu.add(upds.data(), upds.size() * sizeof(UpdateWork));
   const size_t u_fp = pu.add(fill_ptr.data(), fill_ptr.size() * sizeof(double2*));
   const size_t u_fc = pu.add(fill_cnt.data(), fill_cnt.size() * sizeof(long long));
-  const size_t u_gemm = pu.add(gemms.data(), gemms.size() * sizeof(GemmWork));
+  std::vector<size_t> u_gemm(gemms.size());
+  for (size_t kc = 0; kc < gemms.size(); ++kc)
+    u_gemm[kc] = pu.add(gemms[kc].data(), gemms[kc].size() * sizeof(GemmWork));
   STCHK(ensure(h, h->upd, pu.total));
   STCHK(ensure_pin(h->stage_upd, pu.total));
   pu.write(h->stage_upd.p);
@@ -968,7 +1074,8 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     HIPCHK(launch_update_rows(at<RowWork>(h->upd, u_rows), (int)rows.size(), d_secs,
                               at<UpdateWork>(h->upd, u_upd), scaled, sig, ord, h->st));
     HIPCHK(launch_zero_fill(at<double2*>(h->upd, u_fp), at<long long>(h->upd, u_fc), ng, maxfill, h->st));
-    HIPCHK(launch_zgemm(at<GemmWork>(h->upd, u_gemm), (int)gemms.size(), ntiles, h->st));
+    for (size_t kc = 0; kc < gemms.size(); ++kc)
+      HIPCHK(launch_zgemm(at<GemmWork>(h->upd, u_gemm[kc]), (int)gemms[kc].size(), ntiles[kc], h->st));
     STCHK(tm.stop());
   }
   for (int g = 0; g < ng; ++g)
@@ -1004,7 +1111,8 @@ mps_status check_layer(mps_t h, int ngates, const int* sites, const mps_z* gs, b
   if (!sites || !gs) return fail(MPS_E_ARG, "sites and gates are required");
   const int d = h->d, dd = d * d;
   const size_t gsz = dense ? (size_t)dd * dd : 4;
-  if (!dense && h->mod) return fail(MPS_E_ARG, "a Z_n state takes dense gates (mps_apply_layer_dense)");
+  if (!dense && !h->rule.photon)
+    return fail(MPS_E_ARG, "only a U(1) photon-number state takes mode unitaries; use mps_apply_layer_dense");
   std::vector<int> order(ngates);
   for (int g = 0; g < ngates; ++g) {
     if (sites[g] < 0 || sites[g] > h->L - 2) return fail(MPS_E_ARG, "gate site %d outside 0..L-2", sites[g]);
@@ -1017,10 +1125,10 @@ mps_status check_layer(mps_t h, int ngates, const int* sites, const mps_z* gs, b
     if (dense)
       for (int r = 0; r < dd; ++r)
         for (int c = 0; c < dd; ++c)
-          if (cwrap(h->mod, r / d + r % d - c / d - c % d) != 0 &&
+          if (!h->rule.conserves(r / d, r % d, c / d, c % d) &&
               std::hypot(e[r * dd + c].re, e[r * dd + c].im) > kDenseLeak * big)
             return fail(MPS_E_CHARGE, "gate %d: element (%d,%d) changes the local charge %d -> %d", g, r, c,
-                        c / d + c % d, r / d + r % d);
+                        h->rule.step[c / d] + h->rule.step[c % d], h->rule.step[r / d] + h->rule.step[r % d]);
     order[g] = sites[g];
   }
   std::sort(order.begin(), order.end());
@@ -1084,9 +1192,17 @@ void mps_default_opts(mps_opts* o) {
 
 const char* mps_last_error(void) { return g_err.c_str(); }
 
-mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const int* bond_charge,
-                      const mps_z* const* gamma, const double* const* lambda, const mps_opts* opts,
-                      const mps_device* dev, mps_t* out) {
+}  // extern "C"
+
+namespace {
+
+// mps_create for a given charge rule: `charges` of the rule's keys, n_photons
+// the key of bond 0 (U(1) and Z_n: the photon number; the rule's steps then
+// the identity).
+mps_status create_impl(int L, int d, int n_photons, const int* bond_dim, const int* bond_charge,
+                       const mps_z* const* gamma, const double* const* lambda, const mps_opts* opts,
+                       const mps_device* dev, const std::vector<int>* steps, int ncomp, int radix,
+                       mps_t* out) {
   if (!out) return fail(MPS_E_ARG, "out is NULL");
   *out = nullptr;
   if (L < 2) return fail(MPS_E_ARG, "L must be at least 2");
@@ -1112,6 +1228,13 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
     return fail(MPS_E_ARG, "a Z_n charge needs n equal to the local dimension (modulus %d, d %d)", o.modulus, d);
   const int zn = o.modulus;
   const int nq = zn ? n_photons % zn : n_photons;     // charge of bond 0
+  ChargeRule R;
+  {
+    std::vector<int> ident(d);
+    for (int p = 0; p < d; ++p) ident[p] = p;
+    if (steps && zn) return fail(MPS_E_ARG, "a Z_n charge takes the occupations as its charges");
+    R.init(zn, steps ? *steps : ident);
+  }
 
   // charge tables with a stable sort of every bond by charge
   std::vector<Bond> bonds(L + 1);
@@ -1146,7 +1269,7 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
     for (int c : bonds[s].charge) {
       bool ok = false;
       for (int c2 : bonds[s + 1].charge)
-        if (step_ok(zn, d, c, c2)) ok = true;
+        if (R.ok(c, c2)) ok = true;
       if (!ok) return fail(MPS_E_CHARGE, "charge %d on bond %d has no admissible partner on bond %d", c, s, s + 1);
     }
   }
@@ -1178,12 +1301,12 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
         if (gamma) {
           const mps_z z = gamma[s][(size_t)perm[s][i] * cdim + perm[s + 1][j]];
           v = make_double2(z.re * hlam[s + 1][j], z.im * hlam[s + 1][j]);
-          const bool allowed = step_ok(zn, d, ci, cj);
+          const bool allowed = R.ok(ci, cj);
           if (!allowed && (z.re != 0.0 || z.im != 0.0))
             return fail(MPS_E_CHARGE, "site %d entry (%d,%d) violates the charge rule (Eq. E2)", s, i, j);
           if (!std::isfinite(z.re) || !std::isfinite(z.im)) return fail(MPS_E_ARG, "non-finite gamma");
         } else {
-          v = step_ok(zn, d, ci, cj) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
+          v = R.ok(ci, cj) ? make_double2(1.0, 0.0) : make_double2(0.0, 0.0);
         }
         hsite[s][(size_t)i * cdim + j] = v;
       }
@@ -1196,6 +1319,9 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
   h->d = d;
   h->N = nq;
   h->mod = zn;
+  h->rule = R;
+  h->ncomp = ncomp;
+  h->radix = radix;
   h->opts = o;
   if (dev) h->dev = *dev;
   h->st = static_cast<hipStream_t>(h->dev.stream);
@@ -1249,6 +1375,86 @@ mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const in
     return s;
   }
   *out = h;
+  return MPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mps_status mps_create(int L, int d, int n_photons, const int* bond_dim, const int* bond_charge,
+                      const mps_z* const* gamma, const double* const* lambda, const mps_opts* opts,
+                      const mps_device* dev, mps_t* out) {
+  return create_impl(L, d, n_photons, bond_dim, bond_charge, gamma, lambda, opts, dev, nullptr, 1, 0, out);
+}
+
+mps_status mps_create_product_charges(int L, int d, const int* occupation, int ncomp, const int* charge_map,
+                                      const mps_opts* opts, const mps_device* dev, mps_t* out) {
+  if (!out) return fail(MPS_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!occupation || !charge_map) return fail(MPS_E_ARG, "occupation and charge_map are required");
+  if (L < 2) return fail(MPS_E_ARG, "L must be at least 2");
+  if (d < 2 || d > kMaxD) return fail(MPS_E_ARG, "d must lie in 2..%d", kMaxD);
+  if (ncomp != 1 && ncomp != 2) return fail(MPS_E_ARG, "ncomp must be 1 or 2");
+  if (opts && opts->modulus != 0) return fail(MPS_E_ARG, "charge_map takes U(1) components (modulus 0)");
+  for (int i = 0; i < L; ++i)
+    if (occupation[i] < 0 || occupation[i] >= d)
+      return fail(MPS_E_ARG, "local state %d of mode %d outside 0..d-1", occupation[i], i);
+  std::vector<long long> tot(ncomp, 0), mx(ncomp, 0);
+  for (int p = 0; p < d; ++p)
+    for (int k = 0; k < ncomp; ++k) {
+      const int v = charge_map[p * ncomp + k];
+      if (v < 0 || v > 64) return fail(MPS_E_ARG, "charge_map entry %d outside 0..64", v);
+      mx[k] = std::max<long long>(mx[k], v);
+    }
+  for (int i = 0; i < L; ++i)
+    for (int k = 0; k < ncomp; ++k) tot[k] += charge_map[occupation[i] * ncomp + k];
+  // keys: radix above twice the second components a bond difference or a
+  // two-site total can carry
+  const long long radix = ncomp == 2 ? 2 * (tot[1] + mx[1]) + 2 : 0;
+  if (ncomp == 2 && (tot[0] + 1) * radix > (1LL << 24)) return fail(MPS_E_ARG, "charges too large to pack");
+  std::vector<int> steps(d);
+  for (int p = 0; p < d; ++p)
+    steps[p] = ncomp == 2 ? int(charge_map[2 * p] * radix + charge_map[2 * p + 1]) : charge_map[p];
+  for (int p = 0; p < d; ++p)
+    for (int q = 0; q < p; ++q)
+      if (steps[p] == steps[q]) return fail(MPS_E_ARG, "local states %d and %d carry the same charge", q, p);
+  std::vector<int> dims(L + 1, 1), ch(L + 1, 0);
+  long long c = 0;
+  for (int i = 0; i < L; ++i) c += steps[occupation[i]];
+  const int total = int(c);
+  for (int b = 0; b <= L; ++b) {
+    ch[b] = int(c);
+    if (b < L) c -= steps[occupation[b]];
+  }
+  return create_impl(L, d, total, dims.data(), ch.data(), nullptr, nullptr, opts, dev, &steps, ncomp, int(radix),
+                     out);
+}
+
+mps_status mps_bond_charges(mps_t h, int bond, int cap, int* nsec, int* comps, int* count) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (bond < 0 || bond > h->L) return fail(MPS_E_ARG, "bond %d outside 0..L", bond);
+  const Bond& B = h->bonds[bond];
+  if (nsec) *nsec = (int)B.charge.size();
+  if ((int)B.charge.size() > cap) return fail(MPS_E_ARG, "capacity %d < %zu sectors", cap, B.charge.size());
+  for (size_t i = 0; i < B.charge.size(); ++i) {
+    if (comps) {
+      if (h->ncomp == 2) {
+        comps[2 * i] = B.charge[i] / h->radix;
+        comps[2 * i + 1] = B.charge[i] % h->radix;
+      } else {
+        comps[i] = B.charge[i];
+      }
+    }
+    if (count) count[i] = B.count[i];
+  }
+  return MPS_OK;
+}
+
+mps_status mps_charge_components(mps_t h, int* ncomp) {
+  if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
+  if (!ncomp) return fail(MPS_E_ARG, "ncomp is NULL");
+  *ncomp = h->ncomp;
   return MPS_OK;
 }
 
@@ -1454,7 +1660,7 @@ mps_status mps_amplitude(mps_t h, int count, const int* occ, mps_z* out) {
   HIPCHK(hipMemcpyAsync(h->misc.p, h->stage_misc.p, o_out, hipMemcpyHostToDevice, h->st));
   HIPCHK(launch_amplitude(at<const double2*>(h->misc, o_sp), at<int>(h->misc, o_ld), at<int2>(h->misc, o_bm),
                           at<int>(h->misc, o_occ), at<double2>(h->misc, o_out), count, L, h->d, N, h->mod,
-                          maxdim, h->st));
+                          maxdim, steps_of(h), h->st));
   HIPCHK(hipMemcpyAsync(static_cast<char*>(h->stage_misc.p) + o_out, at<char>(h->misc, o_out),
                         (size_t)count * sizeof(double2), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
@@ -1495,7 +1701,7 @@ size_t env_tbuf_elems(const mps_state* h, int* maxdim_out) {
 }
 
 mps_status plan_envs(mps_state* h, const std::vector<double2*>& eb, double2* tbuf, size_t tcap, EnvPlan& E) {
-  const int L = h->L, d = h->d;
+  const int L = h->L;
   E.p1.assign(L, {});
   E.p2.assign(L, {});
   E.nt1.assign(L, 0);
@@ -1513,8 +1719,12 @@ mps_status plan_envs(mps_state* h, const std::vector<double2*>& eb, double2* tbu
     size_t toff = 0;
     for (size_t i = 0; i < B1.charge.size(); ++i) {
       const int cp = B1.charge[i];
-      // rows of bond s reaching charge cp: charges cp..cp+d-1 (Z_n with d = n: all)
-      const int w0 = h->mod ? 0 : B0.off[B0.lower(cp)], w1 = h->mod ? B0.dim() : B0.off[B0.lower(cp + d)];
+      // rows of bond s reaching charge cp: charges cp + step[p] (Z_n with d = n:
+      // all).  The range from the smallest to the largest such charge may hold
+      // other charges too; their entries of B[s] are structural zeros, so they
+      // add nothing (U(1): exactly the charges cp..cp+d-1)
+      const int w0 = h->mod ? 0 : B0.off[B0.lower(cp + h->rule.minstep)];
+      const int w1 = h->mod ? B0.dim() : B0.off[B0.lower(cp + h->rule.maxstep + 1)];
       if (w1 <= w0) continue;
       const int nn = B1.count[i], o1 = B1.off[i], kw = w1 - w0;
       GemmWork a{};
@@ -1716,6 +1926,7 @@ mps_status mps_sample(mps_t h, int count, const double* uniforms, int* occ, doub
   HIPCHK(launch_sample(at<const double2*>(h->samp, o_sp), at<int>(h->samp, o_lb), at<const double2*>(h->samp, o_ep),
                        at<int>(h->samp, o_le), at<int2>(h->samp, o_bm), at<double>(h->samp, o_u),
                        at<int>(h->samp, o_occ), at<double>(h->samp, o_pr), count, L, h->d, N, h->mod, maxblk,
+                       steps_of(h),
                        h->st));
   HIPCHK(hipMemcpyAsync(static_cast<char*>(h->stage_misc.p) + o_occ, at<char>(h->samp, o_occ), pk.total - o_occ,
                         hipMemcpyDeviceToHost, h->st));

@@ -5,11 +5,12 @@
 // with v the contraction B_{s+1} .. B_{L-1} of the occupations already drawn
 // (a vector on one charge block of bond s+1), occupation i of mode s has the
 // unnormalised conditional probability
-//     p_i = w_i^dagger E_s w_i,   w_i = B_s[charge c + i, charge c] v,
+//     p_i = w_i^dagger E_s w_i,   w_i = B_s[charge c + step_i, charge c] v,
 // E_s the left environment of bond s (block-diagonal by charge, built by the
-// norm's contraction).  The occupation is the smallest i whose cumulative
-// p exceeds u * sum(p) for the caller's uniform u; v becomes w_i / sqrt(p_i).
-// With a Z_n charge (mod = n) the charges add mod n.
+// norm's contraction), step_i the charge of local state i (U(1): i).  The
+// occupation is the smallest i whose cumulative p exceeds u * sum(p) for the
+// caller's uniform u; v becomes w_i / sqrt(p_i).  With a Z_n charge (mod = n)
+// the charges add mod n.
 //
 // One workgroup (four waves) per sample.  Each matrix-vector product gives
 // every row of the block to a group of g lanes, g the power of two covering
@@ -74,7 +75,7 @@ __global__ void __launch_bounds__(256)
 sample_kernel(const double2* const* __restrict__ sites, const int* __restrict__ ldb,
               const double2* const* __restrict__ envs, const int* __restrict__ lde,
               const int2* __restrict__ bondmap, const double* __restrict__ uni, int* __restrict__ occ,
-              double* __restrict__ prob, int L, int d, int N, int mod, int maxblk) {
+              double* __restrict__ prob, int L, int d, int N, int mod, int maxblk, Steps st) {
   const int ncb = mod ? mod : N + 1;             // bondmap entries per bond
   extern __shared__ double2 smem[];
   double2* v = smem;
@@ -95,7 +96,7 @@ sample_kernel(const double2* const* __restrict__ sites, const int* __restrict__ 
     const double2* E = envs[s];
     const int le = lde[s];
     for (int i = 0; i < d; ++i) {
-      const int c2 = mod ? (c + i) % mod : c + i;
+      const int c2 = mod ? (c + i) % mod : c + st.s[i];
       const int2 bm = c2 < ncb ? bondmap[(size_t)s * ncb + c2] : make_int2(0, 0);
       double q = 0.0;
       if (bm.y > 0) {
@@ -142,7 +143,7 @@ sample_kernel(const double2* const* __restrict__ sites, const int* __restrict__ 
       if (tid == 0) prob[j] = -1.0;
       return;
     }
-    const int cn = mod ? (c + i) % mod : c + i;
+    const int cn = mod ? (c + i) % mod : c + st.s[i];
     const int2 bm = bondmap[(size_t)s * ncb + cn];
     block_matvec(B + (size_t)bm.x * lb + offc, lb, bm.y, nc, v, w);
     __syncthreads();
@@ -159,11 +160,12 @@ sample_kernel(const double2* const* __restrict__ sites, const int* __restrict__ 
 
 hipError_t launch_sample(const double2* const* sites, const int* ldb, const double2* const* envs,
                          const int* lde, const int2* bondmap, const double* uniforms, int* occ,
-                         double* prob, int count, int L, int d, int N, int mod, int maxblk, hipStream_t st) {
+                         double* prob, int count, int L, int d, int N, int mod, int maxblk, Steps steps,
+                         hipStream_t st) {
   if (count <= 0) return hipSuccess;
   if (d > kMaxD || (size_t)2 * maxblk * sizeof(double2) > kSampleLds) return hipErrorInvalidValue;
   hipLaunchKernelGGL(sample_kernel, dim3(count), dim3(256), 2 * maxblk * sizeof(double2), st, sites, ldb,
-                     envs, lde, bondmap, uniforms, occ, prob, L, d, N, mod, maxblk);
+                     envs, lde, bondmap, uniforms, occ, prob, L, d, N, mod, maxblk, steps);
   return hipGetLastError();
 }
 

@@ -147,3 +147,20 @@ def test_last_leaks_argument_errors():
     lib = binding.lib()
     n = C.c_int(-1)
     assert lib.mps_last_leaks(None, 0, C.byref(n), None) == -1
+
+
+def test_charge_map_argument_errors():
+    """mps_create_product_charges refuses bad maps before touching the device."""
+    lib = binding.lib()
+    h = C.c_void_p()
+    occ = (C.c_int * 4)(1, 2, 0, 3)
+    o = binding.mps_opts()
+    lib.mps_default_opts(C.byref(o))
+    good = (C.c_int * 8)(0, 0, 0, 1, 1, 0, 1, 1)
+    dup = (C.c_int * 8)(0, 0, 0, 1, 0, 1, 1, 1)
+    assert lib.mps_create_product_charges(4, 4, occ, 3, good, C.byref(o), None, C.byref(h)) == -1
+    assert lib.mps_create_product_charges(4, 4, occ, 2, dup, C.byref(o), None, C.byref(h)) == -1
+    assert "same charge" in lib.mps_last_error().decode()
+    o.modulus = 4
+    assert lib.mps_create_product_charges(4, 4, occ, 2, good, C.byref(o), None, C.byref(h)) == -1
+    assert not h.value

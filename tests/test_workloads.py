@@ -64,3 +64,19 @@ def test_zn_input_generators():
             for c in range(d * d):
                 if (r // d + r % d - c // d - c % d) % d:
                     assert g[r, c] == 0
+
+
+def test_charge_map_patterns_uniform_over_the_sector():
+    """Strings drawn for a pair of species numbers carry exactly that pair and
+    cover the sector uniformly (chi-square against the exact count)."""
+    import collections
+    import math
+
+    import scipy.stats
+    from workloads import hamiltonians as ham
+    cm = ham.TWO_SPECIES_CHARGES
+    pats = ham.charge_map_patterns(6, cm, (3, 2), 20000, 2)
+    assert all(tuple(cm[list(p)].sum(axis=0)) == (3, 2) for p in pats)
+    cnt = collections.Counter(map(tuple, pats.tolist()))
+    assert len(cnt) == math.comb(6, 3) * math.comb(6, 2)     # hard-core species on 6 sites
+    assert scipy.stats.chisquare(np.array(list(cnt.values()))).pvalue > 1e-3

@@ -281,6 +281,44 @@ def zn_patterns(L: int, d: int, charge: int, count: int, seed: int) -> np.ndarra
     return np.array(out, dtype=np.int32)
 
 
+def charge_map_patterns(L: int, charge_map, total, count: int, seed: int) -> np.ndarray:
+    """count occupation strings drawn uniformly from the strings of L local
+    states whose charges charge_map[p] (tuples) sum to `total`: exact suffix
+    counts per partial charge, then a chain of draws
+    (numpy.random.default_rng(seed))."""
+    cm = [tuple(int(x) for x in row) for row in np.asarray(charge_map).reshape(len(charge_map), -1)]
+    total = tuple(int(x) for x in total)
+    d = len(cm)
+    # ways[k][c] = strings over sites k..L-1 whose charges sum to c
+    ways = [dict() for _ in range(L + 1)]
+    ways[L] = {tuple(0 for _ in total): 1}
+    for k in range(L - 1, -1, -1):
+        w = {}
+        for c, n in ways[k + 1].items():
+            for q in cm:
+                c2 = tuple(a + b for a, b in zip(c, q))
+                if all(a <= t for a, t in zip(c2, total)):
+                    w[c2] = w.get(c2, 0) + n
+        ways[k] = w
+    if ways[0].get(total, 0) == 0:
+        raise ValueError("no string carries that charge")
+    rng = np.random.default_rng(seed)
+    out = np.zeros((count, L), dtype=np.int32)
+    for t in range(count):
+        rem = total
+        for k in range(L):
+            opts = [(p, tuple(a - b for a, b in zip(rem, cm[p]))) for p in range(d)]
+            wts = [ways[k + 1].get(r, 0) if all(x >= 0 for x in r) else 0 for _, r in opts]
+            x = int(rng.integers(0, sum(wts)))
+            p = 0
+            while x >= wts[p]:
+                x -= wts[p]
+                p += 1
+            out[t, k] = p
+            rem = opts[p][1]
+    return out
+
+
 def random_zn_gate(d: int, seed: int, unitary: bool = True) -> np.ndarray:
     """A random d^2 x d^2 gate that conserves p + q mod d (a Z_d charge): a
     Haar-random (or complex Gaussian) block for each total mod d."""
