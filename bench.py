@@ -357,6 +357,19 @@ def precision_chi2048(MPS, dev, circuits, layers: int):
     flops = sp["theta_flops"]
     split_ms = ss["split_ms"] + ss["gemm_ms"] + ss["theta_ms"]
     a, r = amps[FORM_SPLIT_BF16X3], amps[FORM_PLAIN_C128]
+    # every output tile shape of the products forced in turn on the first layer
+    shapes = {}
+    lay0 = lays[0]
+    for v, name in enumerate(("64x64", "32x64", "64x32", "32x32")):
+        m = MPS.from_vidal(4, 32, ch, gam, lam, chi_max=2048, cutoff=1e-12, form=FORM_SPLIT_BF16X3, device=dev,
+                           tile_tuning=2 + v)
+        m.set_timing(True)
+        m.apply_layer([g.site for g in lay0], [g.u for g in lay0])
+        m.sync()
+        st = m.stats()
+        shapes[name] = {"gemm_ms": st["gemm_ms"], "mfma_executed_flops": st["gemm_mfma_flops"],
+                        "frac_of_bf16_peak": st["gemm_mfma_flops"] / st["gemm_ms"] / 1e9 / BF16_DENSE_PEAK_TFLOPS}
+        m.close()
     jac = {}
     for key, (st, _) in (("plain", res[FORM_PLAIN_C128]), ("split_bf16x3", res[FORM_SPLIT_BF16X3])):
         jl = max(st["jacobi_launches"], 1)
@@ -390,7 +403,10 @@ def precision_chi2048(MPS, dev, circuits, layers: int):
             "mfma_useful_tflops": 6.0 * flops / ss["gemm_ms"] / 1e9,
             "frac_of_bf16_peak_useful": 6.0 * flops / ss["gemm_ms"] / 1e9 / BF16_DENSE_PEAK_TFLOPS,
             "split_ms": ss["split_ms"],
-            "theta_speedup_vs_plain": sp["theta_ms"] / split_ms},
+            "theta_speedup_vs_plain": sp["theta_ms"] / split_ms,
+            "tile_chosen": ("64x64", "32x64", "64x32", "32x32")[ss["gemm_variant"]],
+            "tile_tunings": ss["tile_tunings"],
+            "tile_shapes_first_layer": shapes},
         "jacobi": jac,
         "split_vs_plain_amplitude_rel_err": float(np.linalg.norm(a - r) / np.linalg.norm(r)),
         "split_vs_plain_amplitude_max_err": float(np.max(np.abs(a - r)) / np.max(np.abs(r))),

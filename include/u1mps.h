@@ -135,6 +135,15 @@ typedef struct {
                                   capture) and the graph is launched once per
                                   sweep; 0 (default): launched one by one.
                                   Results are identical either way. */
+  int tile_tuning;             /* split-BF16 form: 1 (default): the output tile
+                                  of the sector products is chosen per batch by
+                                  a tuner keyed on the histogram of charge-block
+                                  sizes (the first batch with a key times every
+                                  shape once; the choice is kept for the
+                                  process); 0: always 64 x 64; 2..5: always
+                                  shape 0..3 (64x64, 32x64, 64x32, 32x32; a
+                                  diagnostic).  The products are bitwise the
+                                  same for every shape. */
 } mps_opts;
 
 /* Per-handle counters, accumulated since creation or mps_reset_stats.
@@ -173,11 +182,15 @@ typedef struct {
                                /*   charge-sector work lists, uploads packed,  */
                                /*   update lists from the kept counts); always */
                                /*   measured                                   */
+  long long tile_tunings;      /* split form: batches that timed every tile    */
+                               /*   shape of the products (new histogram key)  */
+  int gemm_variant;            /* split form: tile shape of the last products  */
+                               /*   launch: 0 64x64, 1 32x64, 2 64x32, 3 32x32 */
 } mps_stats;
 
 /* Fill *o with the defaults: chi_max 0, cutoff 0, zero_tol 1e-13,
  * max_sweeps 40, jacobi_tol 0, plain form, modulus 0, blocked_sweeps 0,
- * select_scratch 0, sweep_graph 0. */
+ * select_scratch 0, sweep_graph 0, tile_tuning 1. */
 void mps_default_opts(mps_opts* o);
 
 /* Create a state of L sites with local dimension d (occupations 0..d-1,

@@ -93,7 +93,9 @@ struct ThetaTile {
 // every charge block starting at a multiple of 8, zeros between blocks):
 // A planes hold B[s] (rows = bond s), B planes hold B[s+1] transposed
 // (rows = bond s+2), so both operands have k contiguous.
-constexpr int kSgTile = 64;       // output tile edge of the products
+constexpr int kSgVariants = 4;    // output tiles of the products: 64x64, 32x64, 64x32, 32x32
+constexpr int kSgTileR[kSgVariants] = {64, 32, 64, 32};
+constexpr int kSgTileC[kSgVariants] = {64, 64, 32, 32};
 constexpr int kSgK = 32;          // k chunk staged per step
 constexpr int kSpTile = 32;       // tile edge of the split pass
 constexpr int kSgPlanes = 6;      // BF16 planes per operand: 3 parts x (re, im)
@@ -121,8 +123,8 @@ struct SplitGemm {
   long long pa, pb;
   int m, n, k;
   int lda, ldb, ldc;
-  int tiles_n;            // ceil(n / kSgTile)
-  int tile_begin;         // first flattened tile of this problem
+  int tiles_n[kSgVariants];     // per tile shape: ceil(n / tile columns)
+  int tile_begin[kSgVariants];  // per tile shape: first flattened tile of this problem
 };
 
 // A generic complex GEMM problem C = op(A) op(B) (+ C when beta_one).

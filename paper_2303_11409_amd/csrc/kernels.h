@@ -54,7 +54,8 @@ hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_
 // scratch, then the gate mix into the Theta workspaces.
 hipError_t launch_split_planes(const SplitPlanes* plans, int nplan, int ntiles, const int* ktab,
                                unsigned short* planes, hipStream_t st);
-hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, hipStream_t st);
+// variant: the output tile shape, 0..kSgVariants-1 (kSgTileR x kSgTileC)
+hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, int variant, hipStream_t st);
 hipError_t launch_theta_mix(const GateWork* gates, const ThetaTile* tiles, int ntiles, const SectorWork* secs,
                             const double2* coef, const double2* pbuf, double2* raw, double2* scaled,
                             double* tile_before, hipStream_t st);

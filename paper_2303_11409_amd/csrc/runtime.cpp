@@ -20,6 +20,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -444,9 +446,9 @@ struct BatchPlan {
   int spl_tiles = 0;
   long long plane_elems = 0;
   std::vector<SplitGemm> sg;              // a, b, c hold buffer offsets until upload
-  int sg_tiles = 0;
+  int sg_tiles[kSgVariants] = {0, 0, 0, 0};
   long long p_elems = 0;
-  double sg_mfma_flops = 0.0;
+  double sg_mfma_flops[kSgVariants] = {0.0, 0.0, 0.0, 0.0};
 };
 
 // One two-site update of a batch: the state it acts on, its left site and
@@ -667,12 +669,15 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
             sg.m = nL;
             sg.n = nR;
             sg.k = base.kn[j];
-            sg.tiles_n = (nR + kSgTile - 1) / kSgTile;
-            sg.tile_begin = P.sg_tiles;
-            P.sg_tiles += ((nL + kSgTile - 1) / kSgTile) * sg.tiles_n;
-            // executed: whole 64 x 64 tiles, k in steps of 16 (one MFMA k step)
-            P.sg_mfma_flops += 48.0 * kSgTile * kSgTile * 16.0 *
-                               (((nL + kSgTile - 1) / kSgTile) * sg.tiles_n) * ((sg.k + 15) / 16);
+            for (int v = 0; v < kSgVariants; ++v) {
+              const int tr = kSgTileR[v], tc = kSgTileC[v];
+              sg.tiles_n[v] = (nR + tc - 1) / tc;
+              sg.tile_begin[v] = P.sg_tiles[v];
+              P.sg_tiles[v] += ((nL + tr - 1) / tr) * sg.tiles_n[v];
+              // executed: whole tiles, k in steps of 16 (one MFMA k step)
+              P.sg_mfma_flops[v] += 48.0 * tr * tc * 16.0 * (((nL + tr - 1) / tr) * sg.tiles_n[v]) *
+                                    ((sg.k + 15) / 16);
+            }
             P.sg.push_back(sg);
             P.p_elems += (long long)nL * nR;
           }
@@ -736,6 +741,42 @@ mps_status check_device_limits(mps_state* h, const BatchPlan& P) {
     return fail(MPS_E_ARG, "sector with %d vectors exceeds the Jacobi finalize LDS budget", P.jmaxrows);
   (void)h;
   return MPS_OK;
+}
+
+// ---- tile-shape tuner of the split-BF16 products ----------------------------
+// The best output tile of the products depends on the charge-block sizes: the
+// key of a batch is its histogram of products by the class of their row and
+// column counts (up to 32, up to 64, more), each class weighted by its
+// algorithmic flops and quantised to eighths.  The first batch with a key runs
+// every tile shape once and keeps the fastest for that key for the rest of the
+// process (all shapes give bitwise the same products).
+std::mutex g_tile_mu;
+std::map<std::string, int> g_tile_best;
+
+std::string tile_key(const BatchPlan& P) {
+  double w[9] = {0.0}, tot = 0.0;
+  auto cls = [](int x) { return x <= 32 ? 0 : (x <= 64 ? 1 : 2); };
+  for (const SplitGemm& g : P.sg) {
+    const double f = double(g.m) * g.n * g.k;
+    w[3 * cls(g.m) + cls(g.n)] += f;
+    tot += f;
+  }
+  std::string key(9, '0');
+  for (int i = 0; i < 9; ++i) key[i] = char('0' + (tot > 0.0 ? int(std::lround(8.0 * w[i] / tot)) : 0));
+  return key;
+}
+
+bool tuned_variant(const std::string& key, int* v) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  auto it = g_tile_best.find(key);
+  if (it == g_tile_best.end()) return false;
+  *v = it->second;
+  return true;
+}
+
+void remember_variant(const std::string& key, int v) {
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tile_best[key] = v;
 }
 
 // ---- the batched two-site update ------------------------------------------
@@ -822,12 +863,45 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
       STCHK(tp.stop());
     }
     {
+      const SplitGemm* d_sg = at<SplitGemm>(h->plan, o_sg);
+      int variant = h->opts.tile_tuning >= 2 ? h->opts.tile_tuning - 2 : 0;
+      bool have = h->opts.tile_tuning != 1;
+      std::string key;
+      if (!have) {
+        key = tile_key(P);
+        have = tuned_variant(key, &variant);
+      }
+      if (!have) {
+        // first batch with this histogram: every tile shape once, timed; the
+        // products are bitwise the same, so the last run's are kept
+        hipEvent_t e0, e1;
+        STCHK(ev_get(h, &e0));
+        STCHK(ev_get(h, &e1));
+        float best = 0.f;
+        for (int v = 0; v < kSgVariants; ++v) {
+          HIPCHK(hipEventRecord(e0, h->st));
+          HIPCHK(launch_split_gemm(d_sg, (int)P.sg.size(), P.sg_tiles[v], v, h->st));
+          HIPCHK(hipEventRecord(e1, h->st));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          if (v == 0 || ms < best) {
+            best = ms;
+            variant = v;
+          }
+        }
+        h->pool.push_back(e0);
+        h->pool.push_back(e1);
+        remember_variant(key, variant);
+        h->stats.tile_tunings += 1;
+      }
       Timer tg(h, K_GEMM);
       STCHK(tg.start());
-      HIPCHK(launch_split_gemm(at<SplitGemm>(h->plan, o_sg), (int)P.sg.size(), P.sg_tiles, h->st));
+      HIPCHK(launch_split_gemm(d_sg, (int)P.sg.size(), P.sg_tiles[variant], variant, h->st));
       STCHK(tg.stop());
       h->stats.gemm_launches += 1;
-      h->stats.gemm_mfma_flops += P.sg_mfma_flops;
+      h->stats.gemm_mfma_flops += P.sg_mfma_flops[variant];
+      h->stats.gemm_variant = variant;
     }
     Timer tm(h, K_THETA);
     STCHK(tm.start());
@@ -1188,6 +1262,7 @@ void mps_default_opts(mps_opts* o) {
   o->blocked_sweeps = 0;
   o->select_scratch = 0;
   o->sweep_graph = 0;
+  o->tile_tuning = 1;
 }
 
 const char* mps_last_error(void) { return g_err.c_str(); }
@@ -1222,6 +1297,8 @@ mps_status create_impl(int L, int d, int n_photons, const int* bond_dim, const i
   if (o.blocked_sweeps < 0) return fail(MPS_E_ARG, "blocked_sweeps must be >= 0");
   if (o.select_scratch != 0 && o.select_scratch != 1) return fail(MPS_E_ARG, "select_scratch must be 0 or 1");
   if (o.sweep_graph != 0 && o.sweep_graph != 1) return fail(MPS_E_ARG, "sweep_graph must be 0 or 1");
+  if (o.tile_tuning < 0 || o.tile_tuning > 1 + kSgVariants)
+    return fail(MPS_E_ARG, "tile_tuning must lie in 0..%d", 1 + kSgVariants);
   if (!(o.cutoff >= 0.0) || !(o.zero_tol >= 0.0)) return fail(MPS_E_ARG, "cutoff and zero_tol must be >= 0");
   if (o.form != MPS_FORM_PLAIN_C128 && o.form != MPS_FORM_SPLIT_BF16X3) return fail(MPS_E_ARG, "unknown form %d", o.form);
   if (o.modulus != 0 && o.modulus != d)

@@ -228,35 +228,42 @@ split_planes_kernel(const SplitPlanes* __restrict__ plans, int nplan, const int*
 
 // LDS rows of one k chunk: 32 BF16 plus 8 of padding (80 bytes), so every
 // 8-element operand read is one aligned 16-byte access.  Two buffers of six
-// planes of 64 rows per operand: 120 KiB of LDS per workgroup.
+// planes per operand: 120 KiB of LDS per workgroup for a 64 x 64 tile.
 constexpr int kSgRow = kSgK + 8;
 
-// 16-byte groups (8 k) of a 64-row x 32-k chunk of one operand's six
-// planes: 1536 groups, six per thread (group g = t + 256 q: plane g / 256,
-// row (g % 256) / 4, k 8 (g % 4)); rows past `rows` and groups starting past
-// `k` read as 0 (the planes are zero between charge blocks, so a group that
-// starts inside the range is exact).
-__device__ __forceinline__ void sg_fetch(uint4 (&r)[kSgPlanes], const unsigned short* __restrict__ base,
-                                         long long pstride, int ld, int rows, int k, int row0, int k0) {
+// 16-byte groups (8 k) of a ROWS-row x 32-k chunk of one operand's six
+// planes: 6 * 4 * ROWS groups over the NT threads of the workgroup (group g:
+// plane g / (4 ROWS), row (g % (4 ROWS)) / 4, k 8 (g % 4)); rows past `rows`
+// and groups starting past `k` read as 0 (the planes are zero between charge
+// blocks, so a group that starts inside the range is exact).
+template <int ROWS, int NT>
+struct SgLoad {
+  static constexpr int kGroups = kSgPlanes * 4 * ROWS;
+  static constexpr int kPer = (kGroups + NT - 1) / NT;
+  uint4 r[kPer];
+  __device__ __forceinline__ void fetch(const unsigned short* __restrict__ base, long long pstride, int ld,
+                                        int rows, int k, int row0, int k0) {
 #pragma unroll
-  for (int q = 0; q < kSgPlanes; ++q) {
-    const int g = threadIdx.x + 256 * q;
-    const int plane = g >> 8, row = (g & 255) >> 2, kg = 8 * (g & 3);
-    r[q] = make_uint4(0u, 0u, 0u, 0u);
-    if (row0 + row < rows && k0 + kg < k)
-      r[q] = *reinterpret_cast<const uint4*>(base + plane * pstride + (size_t)(row0 + row) * ld + k0 + kg);
+    for (int q = 0; q < kPer; ++q) {
+      const int g = threadIdx.x + NT * q;
+      const int plane = g / (4 * ROWS), row = (g % (4 * ROWS)) >> 2, kg = 8 * (g & 3);
+      r[q] = make_uint4(0u, 0u, 0u, 0u);
+      if (g < kGroups && row0 + row < rows && k0 + kg < k)
+        r[q] = *reinterpret_cast<const uint4*>(base + plane * pstride + (size_t)(row0 + row) * ld + k0 + kg);
+    }
   }
-}
-
-__device__ __forceinline__ void sg_stage(const uint4 (&r)[kSgPlanes], unsigned short (*buf)[kSgTile][kSgRow]) {
+  __device__ __forceinline__ void stage(unsigned short (*buf)[ROWS][kSgRow]) const {
 #pragma unroll
-  for (int q = 0; q < kSgPlanes; ++q) {
-    const int g = threadIdx.x + 256 * q;
-    *reinterpret_cast<uint4*>(&buf[g >> 8][(g & 255) >> 2][8 * (g & 3)]) = r[q];
+    for (int q = 0; q < kPer; ++q) {
+      const int g = threadIdx.x + NT * q;
+      if (g < kGroups)
+        *reinterpret_cast<uint4*>(&buf[g / (4 * ROWS)][(g % (4 * ROWS)) >> 2][8 * (g & 3)]) = r[q];
+    }
   }
-}
+};
 
-__device__ __forceinline__ bf16x8 sg_op(const unsigned short (*buf)[kSgTile][kSgRow], int plane, int row, int k) {
+template <int ROWS>
+__device__ __forceinline__ bf16x8 sg_op(const unsigned short (*buf)[ROWS][kSgRow], int plane, int row, int k) {
   return *reinterpret_cast<const bf16x8*>(&buf[plane][row][k]);
 }
 
@@ -273,49 +280,56 @@ __device__ __forceinline__ f32x16 sg_real6(const bf16x8* x, const bf16x8* y, f32
   return c;
 }
 
-// One 64 x 64 output tile per workgroup; wave w computes the 32 x 32 quadrant
-// (rows 32 (w / 2), columns 32 (w % 2)) with v_mfma_f32_32x32x16_bf16.  Lane l
-// supplies A[i = l % 32][k = 8 (l / 32) + e] and B[k = 8 (l / 32) + e][j = l % 32]
-// (e = 0..7); its accumulator register r holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].
-// Per k step: Re = Ar Br - Ai Bi and Im = Ar Bi + Ai Br, each real product as
-// the six split terms of sg_real6, in four accumulators (Ar Br, Ai Bi, Ar Bi,
-// Ai Br) whose chains interleave.  Products of BF16 values are exact in FP32;
-// the matrix cores accumulate one 32-wide k chunk in FP32, and the chunk sums
-// are added in FP64 (so FP32 rounding grows with the chunk, not with k), and
-// the product is stored in complex128.  The k chunks go through two LDS
-// buffers: the next chunk's loads are in flight during the products and are
-// staged into the other buffer, one barrier per chunk.
-__global__ void __launch_bounds__(256)
-split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
-  __shared__ __align__(16) unsigned short sa[2][kSgPlanes][kSgTile][kSgRow];
-  __shared__ __align__(16) unsigned short sb[2][kSgPlanes][kSgTile][kSgRow];
+// One (32 WR) x (32 WC) output tile per workgroup of WR x WC waves; wave w
+// computes the 32 x 32 quadrant (rows 32 (w / WC), columns 32 (w % WC)) with
+// v_mfma_f32_32x32x16_bf16.  Lane l supplies A[i = l % 32][k = 8 (l / 32) + e]
+// and B[k = 8 (l / 32) + e][j = l % 32] (e = 0..7); its accumulator register r
+// holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].  Per k step: Re = Ar Br -
+// Ai Bi and Im = Ar Bi + Ai Br, each real product as the six split terms of
+// sg_real6, in four accumulators (Ar Br, Ai Bi, Ar Bi, Ai Br) whose chains
+// interleave.  Products of BF16 values are exact in FP32; the matrix cores
+// accumulate one 32-wide k chunk in FP32, and the chunk sums are added in
+// FP64 (so FP32 rounding grows with the chunk, not with k), and the product is
+// stored in complex128.  Every output element sees the same sequence of
+// matrix-core operations whatever the tile shape, so the shapes give bitwise
+// the same products (the tuner picks one by speed alone).  The k chunks go
+// through two LDS buffers: the next chunk's loads are in flight during the
+// products and are staged into the other buffer, one barrier per chunk.
+template <int WR, int WC>
+__global__ void __launch_bounds__(64 * WR * WC)
+split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob, int variant) {
+  constexpr int NT = 64 * WR * WC, TR = 32 * WR, TC = 32 * WC;
+  __shared__ __align__(16) unsigned short sa[2][kSgPlanes][TR][kSgRow];
+  __shared__ __align__(16) unsigned short sb[2][kSgPlanes][TC][kSgRow];
   int lo = 0, hi = nprob - 1;
   const int tile = blockIdx.x;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (probs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+    if (probs[mid].tile_begin[variant] <= tile) lo = mid; else hi = mid - 1;
   }
   const SplitGemm w = probs[lo];
-  const int local = tile - w.tile_begin;
-  const int row0 = (local / w.tiles_n) * kSgTile, col0 = (local % w.tiles_n) * kSgTile;
+  const int tn = w.tiles_n[variant];
+  const int local = tile - w.tile_begin[variant];
+  const int row0 = (local / tn) * TR, col0 = (local % tn) * TC;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int R = 32 * (wave >> 1), Cq = 32 * (wave & 1);
+  const int R = 32 * (wave / WC), Cq = 32 * (wave % WC);
   const int li = lane & 31, lk = 8 * (lane >> 5);
   double dre[16], dim[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) dre[r] = dim[r] = 0.0;
-  uint4 ra[kSgPlanes], rb[kSgPlanes];
-  sg_fetch(ra, w.a, w.pa, w.lda, w.m, w.k, row0, 0);
-  sg_fetch(rb, w.b, w.pb, w.ldb, w.n, w.k, col0, 0);
-  sg_stage(ra, sa[0]);
-  sg_stage(rb, sb[0]);
+  SgLoad<TR, NT> la;
+  SgLoad<TC, NT> lb;
+  la.fetch(w.a, w.pa, w.lda, w.m, w.k, row0, 0);
+  lb.fetch(w.b, w.pb, w.ldb, w.n, w.k, col0, 0);
+  la.stage(sa[0]);
+  lb.stage(sb[0]);
   __syncthreads();
   int buf = 0;
   for (int k0 = 0; k0 < w.k; k0 += kSgK) {
     const bool more = k0 + kSgK < w.k;
     if (more) {
-      sg_fetch(ra, w.a, w.pa, w.lda, w.m, w.k, row0, k0 + kSgK);
-      sg_fetch(rb, w.b, w.pb, w.ldb, w.n, w.k, col0, k0 + kSgK);
+      la.fetch(w.a, w.pa, w.lda, w.m, w.k, row0, k0 + kSgK);
+      lb.fetch(w.b, w.pb, w.ldb, w.n, w.k, col0, k0 + kSgK);
     }
     // the second k step of a chunk that ends the segment early is all zero
     const int nks = k0 + 16 < w.k ? 2 : 1;
@@ -327,8 +341,8 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
       bf16x8 a[kSgPlanes], b[kSgPlanes];
 #pragma unroll
       for (int p = 0; p < kSgPlanes; ++p) {
-        a[p] = sg_op(sa[buf], p, R + li, 16 * h + lk);
-        b[p] = sg_op(sb[buf], p, Cq + li, 16 * h + lk);
+        a[p] = sg_op<TR>(sa[buf], p, R + li, 16 * h + lk);
+        b[p] = sg_op<TC>(sb[buf], p, Cq + li, 16 * h + lk);
       }
       crp = sg_real6(a, b, crp);
       crn = sg_real6(a + 3, b + 3, crn);
@@ -342,8 +356,8 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob) {
     }
     if (more) {
       // the other buffer was last read before the previous barrier
-      sg_stage(ra, sa[buf ^ 1]);
-      sg_stage(rb, sb[buf ^ 1]);
+      la.stage(sa[buf ^ 1]);
+      lb.stage(sb[buf ^ 1]);
     }
     __syncthreads();
     buf ^= 1;
@@ -429,9 +443,24 @@ hipError_t launch_split_planes(const SplitPlanes* plans, int nplan, int ntiles, 
   return hipGetLastError();
 }
 
-hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, hipStream_t st) {
+hipError_t launch_split_gemm(const SplitGemm* probs, int nprob, int ntiles, int variant, hipStream_t st) {
   if (nprob <= 0 || ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(split_gemm_kernel, dim3(ntiles), dim3(256), 0, st, probs, nprob);
+  switch (variant) {
+    case 0:
+      hipLaunchKernelGGL((split_gemm_kernel<2, 2>), dim3(ntiles), dim3(256), 0, st, probs, nprob, variant);
+      break;
+    case 1:
+      hipLaunchKernelGGL((split_gemm_kernel<1, 2>), dim3(ntiles), dim3(128), 0, st, probs, nprob, variant);
+      break;
+    case 2:
+      hipLaunchKernelGGL((split_gemm_kernel<2, 1>), dim3(ntiles), dim3(128), 0, st, probs, nprob, variant);
+      break;
+    case 3:
+      hipLaunchKernelGGL((split_gemm_kernel<1, 1>), dim3(ntiles), dim3(64), 0, st, probs, nprob, variant);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -350,6 +350,26 @@ def test_precision_form_one_layer_on_entangled_state(mps_cls):
         m.close()
 
 
+def test_precision_tile_shapes_are_bitwise_equal(mps_cls):
+    """Every output tile shape of the split products (forced one by one) and
+    the tuner's choice give bitwise the same state after a layer: each element
+    sees the same matrix-core operations whatever the tile."""
+    from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
+    ch, gam, lam = circuits.synthetic_state(16, 8, 4, 120, seed=9)
+    lay = circuits.brickwork_layers(16, 2, 45)[0]
+    pats = circuits.charge_path_patterns(ch, 4, 256, 12)
+    amps, variants = [], []
+    for tt in (2, 3, 4, 5, 1):
+        m = mps_cls.from_vidal(4, 8, ch, gam, lam, form=FORM_SPLIT_BF16X3, tile_tuning=tt)
+        m.apply_layer([g.site for g in lay], [g.u for g in lay])
+        amps.append(m.amplitudes(pats))
+        variants.append(m.stats()["gemm_variant"])
+        m.close()
+    assert variants[:4] == [0, 1, 2, 3] and 0 <= variants[4] <= 3
+    for a in amps[1:]:
+        assert np.array_equal(a, amps[0])
+
+
 def test_precision_form_exact_circuit_vs_permanents(mps_cls):
     from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
     cfg = circuits.config_small_exact()
