@@ -184,7 +184,7 @@ def cpu_baseline(cfg, shapes, budget: float = 60.0):
 
 
 def sample_flops(m, pats):
-    """Algorithmic flops of sample_kernel for the drawn patterns (see the JSON note)."""
+    """Algorithmic flops of the sampler for the drawn patterns (see the JSON note)."""
     L, d = m.L, m.d
     blocks = [m.bond_sectors(b) for b in range(L + 1)]
     tot = 0
@@ -578,9 +578,11 @@ def main() -> int:
                     "distinct_patterns": int(len({tuple(p) for p in spats.tolist()})),
                     "max_prob": float(sprob.max()),
                     "kernel_flops": sflops,
-                    "kernel_flops_note": "sample_kernel's algorithmic work: per sample and mode, 8 n_r n_c "
+                    "kernel_flops_note": "the sampler's algorithmic work: per sample and mode, 8 n_r n_c "
                                          "(w = B v) + 8 n_r^2 (w^H E w) per admissible occupation, plus one more "
-                                         "B v for the drawn one; n = charge-block sizes along the drawn path"}
+                                         "B v for the drawn one; n = charge-block sizes along the drawn path "
+                                         "(the grouped rounds reuse the drawn w, so they do the first two "
+                                         "terms only)"}
         log(f"  {args.samples / sel:.0f} samples/s")
     norm_loss = 1.0 - states[0].norm2()
     max_chi = max(states[0].bond_dims())

@@ -333,12 +333,14 @@ mps_status mps_norm_noalloc(mps_t h, double* norm2);
  * the library draws no random numbers).
  *   occ    out, count*L row-major occupations;
  *   prob   out, may be NULL: |c_i|^2 / <psi|psi> of each drawn pattern.
- * The left environments of every bond are held in device memory during the
- * call only (as many complex entries as the squared bond dimensions, summed:
- * about the size of the state) and released before it returns.
- * Errors: MPS_E_ARG (a uniform outside [0, 1), a charge block above 2048),
- * MPS_E_NUMERIC (a vanished or non-finite marginal), MPS_E_NOMEM,
- * MPS_E_DEVICE. */
+ * All samples advance together, one mode per round; the samples on one
+ * charge share the products with that charge's blocks.  The left
+ * environments of every bond (as many complex entries as the squared bond
+ * dimensions, summed: about the size of the state) and the rounds' buffers
+ * (about 10 vectors of the largest charge block per sample, at most 8192
+ * samples at a time) are held in device memory during the call only.
+ * Errors: MPS_E_ARG (a uniform outside [0, 1)), MPS_E_NUMERIC (a vanished or
+ * non-finite marginal), MPS_E_NOMEM, MPS_E_DEVICE. */
 mps_status mps_sample(mps_t h, int count, const double* uniforms, int* occ, double* prob);
 
 /* Bookkeeping of bond `bond` (0..L): its distinct charges in ascending

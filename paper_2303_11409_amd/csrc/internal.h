@@ -19,7 +19,6 @@ namespace u1mps {
 constexpr int kMaxD = 8;          // local dimension limit (occupations 0..7)
 constexpr int kThetaTile = 32;    // Theta output tile edge
 constexpr int kGemmTile = 32;     // generic ZGEMM tile edge
-constexpr size_t kSampleLds = 64 * 1024;   // sampler: LDS for its two vectors
 constexpr int kSelectLds = 4096;  // cut: candidate values sorted in LDS (48 KiB)
 
 // One two-site update inside a batch.
@@ -139,6 +138,18 @@ struct GemmWork {
   int beta_one;
   int tiles_n;            // ceil(n / kGemmTile)
   int tile_begin;         // first flattened tile of this problem
+};
+
+// One group of the sampler's round for mode s: the samples standing on one
+// charge c of bond s+1 (ids[id0 .. id0 + ng - 1]), their vectors gathered
+// into V (nc x ng, row-major) at voff; for each candidate local state loc[k]
+// with a block of charge c + step on bond s (nr[k] rows), W_k = B_s[.] V and
+// X_k = E_s[.] W_k (nr[k] x ng, row-major) at woff[k] of their buffers.
+struct SampleGroup {
+  int nc, ng, id0, nout;
+  long long voff;
+  int loc[kMaxD], nr[kMaxD];
+  long long woff[kMaxD];
 };
 
 // New-row descriptor for the update of B[s+1] and lambda[s+1].

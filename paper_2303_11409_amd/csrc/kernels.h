@@ -69,10 +69,14 @@ hipError_t launch_amplitude(const double2* const* sites, const int* ld, const in
 // the left environments envs[s] (lde[s]) of every site, bondmap[(b, c)] =
 // (offset, count) of charge c on bond b, uniforms[count * L]; writes occ and
 // prob (-1 where a marginal vanished or was not finite).
-hipError_t launch_sample(const double2* const* sites, const int* ldb, const double2* const* envs,
-                         const int* lde, const int2* bondmap, const double* uniforms, int* occ,
-                         double* prob, int count, int L, int d, int N, int mod, int maxblk, Steps steps,
-                         hipStream_t st);
+// The sampler's round for one mode (sample.hip): gather of every group's
+// vectors from the per-sample slots (column j of the maxblk x ld_slot slot
+// matrix), then, after the two products, the draw of every sample.
+hipError_t launch_sample_gather(const SampleGroup* groups, int ngroups, long long maxelems, const int* ids,
+                                const double2* slots, int ld_slot, double2* vbuf, hipStream_t st);
+hipError_t launch_sample_pick(const SampleGroup* groups, int ngroups, const int* ids, int total,
+                              const double2* wbuf, const double2* xbuf, const double* uni, int L, int s,
+                              double2* slots, int ld_slot, int* occ, double* prob, int* pick_out, hipStream_t st);
 
 hipError_t launch_gather_cols(const double2* src, int lds, double2* dst, int ldd, int rows,
                               const int* map, int ncols, hipStream_t st);

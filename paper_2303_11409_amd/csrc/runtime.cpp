@@ -1947,77 +1947,204 @@ mps_status mps_norm_noalloc(mps_t h, double* norm2) {
   return MPS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Samples per round of the sampler (bounds its buffers: about 10 vectors of
+// the largest charge block per sample).
+constexpr int kSampleChunk = 8192;
+
+// `cnt` samples with the environments eb already built: one round per mode,
+// from the last to the first (see sample.hip).
+mps_status sample_chunk(mps_state* h, const std::vector<double2*>& eb, int cnt, const double* uniforms,
+                        int* occ, double* prob) {
+  const int L = h->L, d = h->d, zn = h->mod;
+  int maxblk = 1, maxsec = 1;
+  for (int b = 0; b <= L; ++b) {
+    for (int c : h->bonds[b].count) maxblk = std::max(maxblk, c);
+    maxsec = std::max(maxsec, (int)h->bonds[b].charge.size());
+  }
+  const size_t vec = (size_t)maxblk * cnt;        // one vector of the largest block per sample
+  Packer pk;
+  const size_t o_u = pk.add(uniforms, (size_t)cnt * L * sizeof(double));
+  const size_t o_occ = pk.add(nullptr, (size_t)cnt * L * sizeof(int));
+  const size_t o_pr = pk.add(nullptr, (size_t)cnt * sizeof(double));
+  const size_t o_pick = pk.add(nullptr, (size_t)cnt * sizeof(int));
+  const size_t o_slot = pk.add(nullptr, vec * sizeof(double2));
+  const size_t o_v = pk.add(nullptr, vec * sizeof(double2));
+  const size_t o_w = pk.add(nullptr, (size_t)d * vec * sizeof(double2));
+  const size_t o_x = pk.add(nullptr, (size_t)d * vec * sizeof(double2));
+  const size_t o_ids = pk.add(nullptr, (size_t)cnt * sizeof(int));
+  const size_t o_grp = pk.add(nullptr, (size_t)maxsec * sizeof(SampleGroup));
+  const size_t o_g1 = pk.add(nullptr, (size_t)maxsec * d * sizeof(GemmWork));
+  const size_t o_g2 = pk.add(nullptr, (size_t)maxsec * d * sizeof(GemmWork));
+  STCHK(ensure(h, h->samp, pk.total));
+  // the previous staging use (the environments' lists) may still be in flight
+  HIPCHK(hipStreamSynchronize(h->st));
+  const size_t stage_list = (size_t)cnt * sizeof(int) + align256((size_t)maxsec * sizeof(SampleGroup)) +
+                            2 * align256((size_t)maxsec * d * sizeof(GemmWork)) + 1024;
+  const size_t stage_init = (size_t)cnt * L * sizeof(double) + 2 * (size_t)cnt * sizeof(double2) + 1024;
+  STCHK(ensure_pin(h->stage_misc, std::max(stage_list, stage_init) + (size_t)cnt * L * sizeof(int) +
+                                      (size_t)cnt * sizeof(double) + 1024));
+  char* stg = static_cast<char*>(h->stage_misc.p);
+  char* dev = static_cast<char*>(h->samp.p);
+  double2* slots = reinterpret_cast<double2*>(dev + o_slot);
+  // initial state: the vector 1 on the single charge of bond L, probability 1
+  {
+    std::memcpy(stg, uniforms, (size_t)cnt * L * sizeof(double));
+    double2* one = reinterpret_cast<double2*>(stg + align256((size_t)cnt * L * sizeof(double)));
+    double* pones = reinterpret_cast<double*>(one + cnt);
+    for (int j = 0; j < cnt; ++j) {
+      one[j] = make_double2(1.0, 0.0);
+      pones[j] = 1.0;
+    }
+    HIPCHK(hipMemcpyAsync(dev + o_u, stg, (size_t)cnt * L * sizeof(double), hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipMemcpyAsync(slots, one, (size_t)cnt * sizeof(double2), hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipMemcpyAsync(dev + o_pr, pones, (size_t)cnt * sizeof(double), hipMemcpyHostToDevice, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+  }
+  std::vector<int> cur(cnt, 0);                    // charge of bond s+1 of every sample (bond L: 0)
+  std::vector<int> picks(cnt);
+  for (int s = L - 1; s >= 0; --s) {
+    const Bond& B0 = h->bonds[s];
+    const Bond& B1 = h->bonds[s + 1];
+    const int ldb = B1.dim(), lde = B0.dim();
+    // groups by charge, ascending; sample ids ascending inside a group
+    std::vector<int> order(cnt);
+    for (int j = 0; j < cnt; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cur[x] < cur[y]; });
+    std::vector<SampleGroup> groups;
+    std::vector<GemmWork> g1, g2;
+    int nt1 = 0, nt2 = 0;
+    long long voff = 0, woff = 0;
+    long long maxelems = 0;
+    for (int t = 0; t < cnt;) {
+      const int c = cur[order[t]];
+      int e = t;
+      while (e < cnt && cur[order[e]] == c) ++e;
+      const int bi = B1.find(c);
+      if (bi < 0) return fail(MPS_E_ARG, "internal: sample charge %d missing on bond %d", c, s + 1);
+      SampleGroup g{};
+      g.nc = B1.count[bi];
+      g.ng = e - t;
+      g.id0 = t;
+      g.voff = voff;
+      for (int i = 0; i < d; ++i) {
+        const int c2 = zn ? (c + i) % zn : c + h->rule.step[i];
+        const int ri = B0.find(c2);
+        if (ri < 0) continue;
+        const int nr = B0.count[ri], offr = B0.off[ri];
+        g.loc[g.nout] = i;
+        g.nr[g.nout] = nr;
+        g.woff[g.nout] = woff;
+        GemmWork a{};
+        a.a = h->site[s] + (size_t)offr * ldb + B1.off[bi];
+        a.lda = ldb;
+        a.b = reinterpret_cast<double2*>(dev + o_v) + voff;
+        a.ldb = g.ng;
+        a.c = reinterpret_cast<double2*>(dev + o_w) + woff;
+        a.ldc = g.ng;
+        a.m = nr;
+        a.n = g.ng;
+        a.k = g.nc;
+        a.tiles_n = (g.ng + kGemmTile - 1) / kGemmTile;
+        a.tile_begin = nt1;
+        nt1 += ((nr + kGemmTile - 1) / kGemmTile) * a.tiles_n;
+        g1.push_back(a);
+        GemmWork x{};
+        x.a = eb[s] + (size_t)offr * lde + offr;
+        x.lda = lde;
+        x.b = reinterpret_cast<double2*>(dev + o_w) + woff;
+        x.ldb = g.ng;
+        x.c = reinterpret_cast<double2*>(dev + o_x) + woff;
+        x.ldc = g.ng;
+        x.m = nr;
+        x.n = g.ng;
+        x.k = nr;
+        x.tiles_n = a.tiles_n;
+        x.tile_begin = nt2;
+        nt2 += ((nr + kGemmTile - 1) / kGemmTile) * x.tiles_n;
+        g2.push_back(x);
+        woff += (long long)nr * g.ng;
+        ++g.nout;
+      }
+      voff += (long long)g.nc * g.ng;
+      maxelems = std::max(maxelems, (long long)g.nc * g.ng);
+      groups.push_back(g);
+      t = e;
+    }
+    // lists up, then gather, the two products and the draw
+    Packer pl;
+    const size_t l_ids = pl.add(order.data(), order.size() * sizeof(int));
+    const size_t l_grp = pl.add(groups.data(), groups.size() * sizeof(SampleGroup));
+    const size_t l_g1 = pl.add(g1.data(), g1.size() * sizeof(GemmWork));
+    const size_t l_g2 = pl.add(g2.data(), g2.size() * sizeof(GemmWork));
+    pl.write(stg);
+    // the list region [o_ids, o_g2 + ...) holds the same layout as pl
+    HIPCHK(hipMemcpyAsync(dev + o_ids, stg, pl.total, hipMemcpyHostToDevice, h->st));
+    const int* d_ids = reinterpret_cast<const int*>(dev + o_ids + l_ids);
+    const SampleGroup* d_grp = reinterpret_cast<const SampleGroup*>(dev + o_ids + l_grp);
+    HIPCHK(launch_sample_gather(d_grp, (int)groups.size(), maxelems, d_ids, slots, cnt,
+                                reinterpret_cast<double2*>(dev + o_v), h->st));
+    HIPCHK(launch_zgemm(reinterpret_cast<const GemmWork*>(dev + o_ids + l_g1), (int)g1.size(), nt1, h->st));
+    HIPCHK(launch_zgemm(reinterpret_cast<const GemmWork*>(dev + o_ids + l_g2), (int)g2.size(), nt2, h->st));
+    HIPCHK(launch_sample_pick(d_grp, (int)groups.size(), d_ids, cnt, reinterpret_cast<const double2*>(dev + o_w),
+                              reinterpret_cast<const double2*>(dev + o_x), reinterpret_cast<const double*>(dev + o_u),
+                              L, s, slots, cnt, reinterpret_cast<int*>(dev + o_occ),
+                              reinterpret_cast<double*>(dev + o_pr), reinterpret_cast<int*>(dev + o_pick), h->st));
+    HIPCHK(hipMemcpyAsync(picks.data(), dev + o_pick, (size_t)cnt * sizeof(int), hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    for (int j = 0; j < cnt; ++j) {
+      if (picks[j] < 0) return fail(MPS_E_NUMERIC, "sample %d met a vanished or non-finite marginal", j);
+      cur[j] = zn ? (cur[j] + picks[j]) % zn : cur[j] + h->rule.step[picks[j]];
+    }
+  }
+  HIPCHK(hipMemcpyAsync(occ, dev + o_occ, (size_t)cnt * L * sizeof(int), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipMemcpyAsync(prob, dev + o_pr, (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipStreamSynchronize(h->st));
+  return MPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 mps_status mps_sample(mps_t h, int count, const double* uniforms, int* occ, double* prob) {
   if (!valid_handle(h)) return fail(MPS_E_ARG, "invalid handle");
   if (count < 0) return fail(MPS_E_ARG, "negative count");
   if (count == 0) return MPS_OK;
   if (!uniforms || !occ) return fail(MPS_E_ARG, "uniforms and occ are required");
-  const int L = h->L, N = h->N;
+  const int L = h->L;
   for (size_t k = 0; k < (size_t)count * L; ++k)
     if (!(uniforms[k] >= 0.0 && uniforms[k] < 1.0)) return fail(MPS_E_ARG, "uniform %zu outside [0, 1)", k);
-  const int ncb = h->mod ? h->mod : N + 1;          // bondmap entries per bond
-  std::vector<int2> bmap((size_t)(L + 1) * ncb, make_int2(0, 0));
-  int maxblk = 1;
   size_t etot = 0;
   std::vector<size_t> eoff(L + 1);
   for (int b = 0; b <= L; ++b) {
-    const Bond& B = h->bonds[b];
-    for (size_t i = 0; i < B.charge.size(); ++i) {
-      bmap[(size_t)b * ncb + B.charge[i]] = make_int2(B.off[i], B.count[i]);
-      maxblk = std::max(maxblk, B.count[i]);
-    }
     eoff[b] = etot;
-    etot += (size_t)B.dim() * B.dim();
+    etot += (size_t)h->bonds[b].dim() * h->bonds[b].dim();
   }
-  if ((size_t)2 * maxblk * sizeof(double2) > kSampleLds)
-    return fail(MPS_E_ARG, "a charge block of %d exceeds the sampler's limit of %zu", maxblk,
-                kSampleLds / (2 * sizeof(double2)));
   STCHK(ensure(h, h->envs, etot * sizeof(double2)));
   std::vector<double2*> eb(L + 1);
   for (int b = 0; b <= L; ++b) eb[b] = static_cast<double2*>(h->envs.p) + eoff[b];
   size_t tail = 0;
   STCHK(left_envs(h, eb, 0, &tail));
-  std::vector<int> ldb(L), lde(L);
-  std::vector<const double2*> sp(L), ep(L);
-  for (int s = 0; s < L; ++s) {
-    ldb[s] = h->bonds[s + 1].dim();
-    lde[s] = h->bonds[s].dim();
-    sp[s] = h->site[s];
-    ep[s] = eb[s];
+  std::vector<double> pr(count);
+  mps_status st = MPS_OK;
+  for (int c0 = 0; c0 < count && st == MPS_OK; c0 += kSampleChunk) {
+    const int cnt = std::min(kSampleChunk, count - c0);
+    st = sample_chunk(h, eb, cnt, uniforms + (size_t)c0 * L, occ + (size_t)c0 * L, pr.data() + c0);
   }
-  Packer pk;
-  const size_t o_sp = pk.add(sp.data(), sp.size() * sizeof(double2*));
-  const size_t o_ep = pk.add(ep.data(), ep.size() * sizeof(double2*));
-  const size_t o_lb = pk.add(ldb.data(), ldb.size() * sizeof(int));
-  const size_t o_le = pk.add(lde.data(), lde.size() * sizeof(int));
-  const size_t o_bm = pk.add(bmap.data(), bmap.size() * sizeof(int2));
-  const size_t o_u = pk.add(uniforms, (size_t)count * L * sizeof(double));
-  const size_t o_occ = pk.add(nullptr, (size_t)count * L * sizeof(int));
-  const size_t o_pr = pk.add(nullptr, (size_t)count * sizeof(double));
-  STCHK(ensure(h, h->samp, pk.total));
-  // the environments' plan is still being copied from stage_misc
-  HIPCHK(hipStreamSynchronize(h->st));
-  STCHK(ensure_pin(h->stage_misc, pk.total));
-  pk.write(h->stage_misc.p);
-  HIPCHK(hipMemcpyAsync(h->samp.p, h->stage_misc.p, o_occ, hipMemcpyHostToDevice, h->st));
-  HIPCHK(launch_sample(at<const double2*>(h->samp, o_sp), at<int>(h->samp, o_lb), at<const double2*>(h->samp, o_ep),
-                       at<int>(h->samp, o_le), at<int2>(h->samp, o_bm), at<double>(h->samp, o_u),
-                       at<int>(h->samp, o_occ), at<double>(h->samp, o_pr), count, L, h->d, N, h->mod, maxblk,
-                       steps_of(h),
-                       h->st));
-  HIPCHK(hipMemcpyAsync(static_cast<char*>(h->stage_misc.p) + o_occ, at<char>(h->samp, o_occ), pk.total - o_occ,
-                        hipMemcpyDeviceToHost, h->st));
-  HIPCHK(hipStreamSynchronize(h->st));
-  // the environments are as large as the state: give them back after each call
+  // the environments and the round buffers are as large as the state: give them back
+  (void)hipStreamSynchronize(h->st);
   dfree(h, h->envs.p);
   h->envs.p = nullptr;
   h->envs.cap = 0;
-  const char* res = static_cast<const char*>(h->stage_misc.p);
-  const double* pr = reinterpret_cast<const double*>(res + o_pr);
-  for (int j = 0; j < count; ++j)
-    if (!(pr[j] >= 0.0)) return fail(MPS_E_NUMERIC, "sample %d met a vanished or non-finite marginal", j);
-  std::memcpy(occ, res + o_occ, (size_t)count * L * sizeof(int));
-  if (prob) std::memcpy(prob, pr, (size_t)count * sizeof(double));
+  dfree(h, h->samp.p);
+  h->samp.p = nullptr;
+  h->samp.cap = 0;
+  if (st != MPS_OK) return st;
+  if (prob) std::memcpy(prob, pr.data(), (size_t)count * sizeof(double));
   return MPS_OK;
 }
 

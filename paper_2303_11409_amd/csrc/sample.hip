@@ -12,160 +12,113 @@
 // caller's uniform u; v becomes w_i / sqrt(p_i).  With a Z_n charge (mod = n)
 // the charges add mod n.
 //
-// One workgroup (four waves) per sample.  Each matrix-vector product gives
-// every row of the block to a group of g lanes, g the power of two covering
-// the vector (at most 64), so short blocks keep the wave busy with several
-// rows; the groups read their row contiguously.
+// All samples advance together, one mode per round.  The samples that stand
+// on the same charge c of bond s+1 form a group: their vectors are gathered
+// into the columns of one matrix V (sample_gather_kernel), so that W_i =
+// B_s[c + step_i, c] V and X_i = E_s[c + step_i] W_i are two products with
+// many right-hand sides (the generic complex GEMM) and every block of B_s and
+// E_s is read once per group instead of once per sample; sample_pick_kernel
+// then forms p_i = Re(W_i^dagger X_i) column by column, draws, and writes the
+// sample's new vector into its slot.  The host regroups the samples between
+// rounds from the drawn occupations.
 #include "device_util.h"
 #include "kernels.h"
 
 namespace u1mps {
 
-__device__ __forceinline__ int group_width(int n) {
-  int g = 1;
-  while (g < n && g < 64) g <<= 1;
-  return g;
-}
-
-__device__ __forceinline__ double group_sum(double v, int g) {
-  for (int o = g >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// y[r] = sum_k A[r * lda + k] x[k] for r < nr, k < nk (x and y in LDS).
-__device__ void block_matvec(const double2* __restrict__ A, int lda, int nr, int nk,
-                             const double2* x, double2* y) {
-  const int g = group_width(nk);
-  const int lane = threadIdx.x & 63;
-  const int sub = lane & (g - 1);
-  const int row0 = (threadIdx.x >> 6) * (64 / g) + lane / g;
-  const int step = (blockDim.x >> 6) * (64 / g);
-  for (int rb = 0; rb < nr; rb += step) {
-    const int r = rb + row0;
-    double2 acc = make_double2(0.0, 0.0);
-    if (r < nr)
-      for (int k = sub; k < nk; k += g) cfma(acc, A[(size_t)r * lda + k], x[k]);
-    acc.x = group_sum(acc.x, g);
-    acc.y = group_sum(acc.y, g);
-    if (r < nr && sub == 0) y[r] = acc;
-  }
-}
-
-// This thread's share of Re sum_r conj(x[r]) sum_k A[r * lda + k] x[k].
-__device__ double block_quad(const double2* __restrict__ A, int lda, int n, const double2* x) {
-  const int g = group_width(n);
-  const int lane = threadIdx.x & 63;
-  const int sub = lane & (g - 1);
-  const int row0 = (threadIdx.x >> 6) * (64 / g) + lane / g;
-  const int step = (blockDim.x >> 6) * (64 / g);
-  double q = 0.0;
-  for (int rb = 0; rb < n; rb += step) {
-    const int r = rb + row0;
-    double2 acc = make_double2(0.0, 0.0);
-    if (r < n)
-      for (int k = sub; k < n; k += g) cfma(acc, A[(size_t)r * lda + k], x[k]);
-    acc.x = group_sum(acc.x, g);
-    acc.y = group_sum(acc.y, g);
-    if (r < n && sub == 0) q += x[r].x * acc.x + x[r].y * acc.y;
-  }
-  return q;
-}
-
+// V_g[k][jj] = slots[k][ids[id0 + jj]] for every group (blockIdx.y), k < nc.
 __global__ void __launch_bounds__(256)
-sample_kernel(const double2* const* __restrict__ sites, const int* __restrict__ ldb,
-              const double2* const* __restrict__ envs, const int* __restrict__ lde,
-              const int2* __restrict__ bondmap, const double* __restrict__ uni, int* __restrict__ occ,
-              double* __restrict__ prob, int L, int d, int N, int mod, int maxblk, Steps st) {
-  const int ncb = mod ? mod : N + 1;             // bondmap entries per bond
-  extern __shared__ double2 smem[];
-  double2* v = smem;
-  double2* w = smem + maxblk;
-  __shared__ double part[4];
-  __shared__ double pv[kMaxD];
-  __shared__ int pick_sh;
-  const int j = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (tid == 0) v[0] = make_double2(1.0, 0.0);
-  int c = 0;                                   // charge of bond s+1; bond L holds only 0
-  int nc = 1, offc = bondmap[(size_t)L * ncb].x;
-  double pr = 1.0;
-  __syncthreads();
-  for (int s = L - 1; s >= 0; --s) {
-    const double2* B = sites[s];
-    const int lb = ldb[s];
-    const double2* E = envs[s];
-    const int le = lde[s];
-    for (int i = 0; i < d; ++i) {
-      const int c2 = mod ? (c + i) % mod : c + st.s[i];
-      const int2 bm = c2 < ncb ? bondmap[(size_t)s * ncb + c2] : make_int2(0, 0);
-      double q = 0.0;
-      if (bm.y > 0) {
-        block_matvec(B + (size_t)bm.x * lb + offc, lb, bm.y, nc, v, w);
-        __syncthreads();
-        q = block_quad(E + (size_t)bm.x * le + bm.x, le, bm.y, w);
-      }
-      q = wave_sum(q);
-      if (lane == 0) part[wv] = q;
-      __syncthreads();
-      if (tid == 0) {
-        const double t = part[0] + part[1] + part[2] + part[3];
-        pv[i] = (t > 0.0 || t != t) ? t : 0.0;   // rounding below zero -> 0; NaN kept
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      double tot = 0.0;
-      for (int i = 0; i < d; ++i) tot += pv[i];
-      int pick = -1;
-      if (tot > 0.0 && tot <= DBL_MAX) {
-        const double ut = uni[(size_t)j * L + s] * tot;
-        double acc = 0.0;
-        for (int i = 0; i < d; ++i) {
-          acc += pv[i];
-          if (ut < acc) {
-            pick = i;
-            break;
-          }
-        }
-        if (pick < 0)
-          for (int i = d - 1; i >= 0; --i)
-            if (pv[i] > 0.0) {
-              pick = i;
-              break;
-            }
-        pr *= pv[pick] / tot;
-      }
-      pick_sh = pick;
-    }
-    __syncthreads();
-    const int i = pick_sh;
-    if (i < 0) {                                // the whole workgroup leaves together
-      if (tid == 0) prob[j] = -1.0;
-      return;
-    }
-    const int cn = mod ? (c + i) % mod : c + st.s[i];
-    const int2 bm = bondmap[(size_t)s * ncb + cn];
-    block_matvec(B + (size_t)bm.x * lb + offc, lb, bm.y, nc, v, w);
-    __syncthreads();
-    const double sc = 1.0 / sqrt(pv[i]);
-    for (int r = tid; r < bm.y; r += blockDim.x) v[r] = make_double2(w[r].x * sc, w[r].y * sc);
-    if (tid == 0) occ[(size_t)j * L + s] = i;
-    c = cn;
-    nc = bm.y;
-    offc = bm.x;
-    __syncthreads();
+sample_gather_kernel(const SampleGroup* __restrict__ groups, const int* __restrict__ ids,
+                     const double2* __restrict__ slots, int ld_slot, double2* __restrict__ vbuf) {
+  const SampleGroup g = groups[blockIdx.y];
+  const long long n = (long long)g.nc * g.ng;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = (int)(e / g.ng), jj = (int)(e % g.ng);
+    vbuf[g.voff + e] = slots[(size_t)k * ld_slot + ids[g.id0 + jj]];
   }
-  if (tid == 0) prob[j] = pr;
 }
 
-hipError_t launch_sample(const double2* const* sites, const int* ldb, const double2* const* envs,
-                         const int* lde, const int2* bondmap, const double* uniforms, int* occ,
-                         double* prob, int count, int L, int d, int N, int mod, int maxblk, Steps steps,
-                         hipStream_t st) {
-  if (count <= 0) return hipSuccess;
-  if (d > kMaxD || (size_t)2 * maxblk * sizeof(double2) > kSampleLds) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(sample_kernel, dim3(count), dim3(256), 2 * maxblk * sizeof(double2), st, sites, ldb,
-                     envs, lde, bondmap, uniforms, occ, prob, L, d, N, mod, maxblk, steps);
+// One thread per sample (position t of the grouped id list): the candidate
+// probabilities p_k = Re sum_r conj(W_k[r][jj]) X_k[r][jj] of its column jj,
+// the draw (NaN or a non-positive total leaves pick -1), the running
+// probability and the new vector W_pick[:, jj] / sqrt(p_pick) in its slot.
+__global__ void __launch_bounds__(256)
+sample_pick_kernel(const SampleGroup* __restrict__ groups, int ngroups, const int* __restrict__ ids, int total,
+                   const double2* __restrict__ wbuf, const double2* __restrict__ xbuf,
+                   const double* __restrict__ uni, int L, int s, double2* __restrict__ slots, int ld_slot,
+                   int* __restrict__ occ, double* __restrict__ prob, int* __restrict__ pick_out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  int lo = 0, hi = ngroups - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (groups[mid].id0 <= t) lo = mid; else hi = mid - 1;
+  }
+  const SampleGroup g = groups[lo];
+  const int jj = t - g.id0, j = ids[t];
+  double pv[kMaxD];
+  double tot = 0.0;
+  for (int k = 0; k < g.nout; ++k) {
+    const double2* w = wbuf + g.woff[k] + jj;
+    const double2* x = xbuf + g.woff[k] + jj;
+    double q = 0.0;
+    for (int r = 0; r < g.nr[k]; ++r) {
+      const double2 a = w[(size_t)r * g.ng], b = x[(size_t)r * g.ng];
+      q = fma(a.x, b.x, fma(a.y, b.y, q));
+    }
+    pv[k] = (q > 0.0 || q != q) ? q : 0.0;      // rounding below zero -> 0; NaN kept
+    tot += pv[k];
+  }
+  int pick = -1;
+  if (tot > 0.0 && tot <= DBL_MAX) {
+    const double ut = uni[(size_t)j * L + s] * tot;
+    double acc = 0.0;
+    for (int k = 0; k < g.nout; ++k) {
+      acc += pv[k];
+      if (ut < acc) {
+        pick = k;
+        break;
+      }
+    }
+    if (pick < 0)
+      for (int k = g.nout - 1; k >= 0; --k)
+        if (pv[k] > 0.0) {
+          pick = k;
+          break;
+        }
+  }
+  if (pick < 0) {
+    pick_out[j] = -1;
+    return;
+  }
+  prob[j] *= pv[pick] / tot;
+  occ[(size_t)j * L + s] = g.loc[pick];
+  pick_out[j] = g.loc[pick];
+  const double sc = 1.0 / sqrt(pv[pick]);
+  const double2* w = wbuf + g.woff[pick] + jj;
+  for (int r = 0; r < g.nr[pick]; ++r) {
+    const double2 a = w[(size_t)r * g.ng];
+    slots[(size_t)r * ld_slot + j] = make_double2(a.x * sc, a.y * sc);
+  }
+}
+
+hipError_t launch_sample_gather(const SampleGroup* groups, int ngroups, long long maxelems, const int* ids,
+                                const double2* slots, int ld_slot, double2* vbuf, hipStream_t st) {
+  if (ngroups <= 0 || maxelems <= 0) return hipSuccess;
+  long long bx = (maxelems + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(sample_gather_kernel, dim3((unsigned)bx, (unsigned)ngroups), dim3(256), 0, st, groups, ids,
+                     slots, ld_slot, vbuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_pick(const SampleGroup* groups, int ngroups, const int* ids, int total,
+                              const double2* wbuf, const double2* xbuf, const double* uni, int L, int s,
+                              double2* slots, int ld_slot, int* occ, double* prob, int* pick_out, hipStream_t st) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sample_pick_kernel, dim3((total + 255) / 256), dim3(256), 0, st, groups, ngroups, ids, total,
+                     wbuf, xbuf, uni, L, s, slots, ld_slot, occ, prob, pick_out);
   return hipGetLastError();
 }
 
