@@ -147,6 +147,7 @@ struct GemmWork {
 // X_k = E_s[.] W_k (nr[k] x ng, row-major) at woff[k] of their buffers.
 struct SampleGroup {
   int nc, ng, id0, nout;
+  int tile0;              // first workgroup of the group in the draw kernel (16 samples each)
   long long voff;
   int loc[kMaxD], nr[kMaxD];
   long long woff[kMaxD];

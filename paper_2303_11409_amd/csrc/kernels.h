@@ -74,7 +74,8 @@ hipError_t launch_amplitude(const double2* const* sites, const int* ld, const in
 // matrix), then, after the two products, the draw of every sample.
 hipError_t launch_sample_gather(const SampleGroup* groups, int ngroups, long long maxelems, const int* ids,
                                 const double2* slots, int ld_slot, double2* vbuf, hipStream_t st);
-hipError_t launch_sample_pick(const SampleGroup* groups, int ngroups, const int* ids, int total,
+// ntiles: sum over groups of ceil(ng / 16) (tile0 of each group: its first).
+hipError_t launch_sample_pick(const SampleGroup* groups, int ngroups, int ntiles, const int* ids,
                               const double2* wbuf, const double2* xbuf, const double* uni, int L, int s,
                               double2* slots, int ld_slot, int* occ, double* prob, int* pick_out, hipStream_t st);
 

@@ -220,17 +220,19 @@ update_rows_kernel(const RowWork* __restrict__ rows, const SectorWork* __restric
                    const UpdateWork* __restrict__ upd, const double2* __restrict__ vh,
                    const double* __restrict__ sigma, const int* __restrict__ order) {
   const RowWork rw = rows[blockIdx.x];
-  const SectorWork s = secs[rw.sector];
+  const SectorWork& s = secs[rw.sector];
   const UpdateWork u = upd[rw.gate];
   const int src = order[s.sig + rw.j];
   const double2* xr = vh + s.off + (size_t)src * s.c;
   double2* dst = u.br_new + (size_t)rw.row * u.ldr;
-  for (int col = threadIdx.x; col < u.ldr; col += blockDim.x) {
-    // the sector's columns are its column blocks of the frame; zero elsewhere
-    int cc = -1;
-    for (int k = 0; k < s.ncb; ++k)
-      if (col >= s.cb_off[k] && col < s.cb_off[k] + s.cb_n[k]) cc = s.cb_pos[k] + col - s.cb_off[k];
-    dst[col] = cc >= 0 ? xr[cc] : make_double2(0.0, 0.0);
+  // the sector's columns are its column blocks of the frame; zero elsewhere
+  const int ncb = s.ncb;
+  for (int col = threadIdx.x; col < u.ldr; col += blockDim.x) dst[col] = make_double2(0.0, 0.0);
+  // the zeros land before the blocks overwrite their columns (workgroup-scope fence)
+  __syncthreads();
+  for (int k = 0; k < ncb; ++k) {
+    const int off = s.cb_off[k], n = s.cb_n[k], pos = s.cb_pos[k];
+    for (int c = threadIdx.x; c < n; c += blockDim.x) dst[off + c] = xr[pos + c];
   }
   if (threadIdx.x == 0) u.lam_new[rw.row] = sigma[s.sig + rw.j];
 }

@@ -2016,7 +2016,7 @@ mps_status sample_chunk(mps_state* h, const std::vector<double2*>& eb, int cnt, 
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cur[x] < cur[y]; });
     std::vector<SampleGroup> groups;
     std::vector<GemmWork> g1, g2;
-    int nt1 = 0, nt2 = 0;
+    int nt1 = 0, nt2 = 0, ptiles = 0;
     long long voff = 0, woff = 0;
     long long maxelems = 0;
     for (int t = 0; t < cnt;) {
@@ -2030,6 +2030,8 @@ mps_status sample_chunk(mps_state* h, const std::vector<double2*>& eb, int cnt, 
       g.ng = e - t;
       g.id0 = t;
       g.voff = voff;
+      g.tile0 = ptiles;
+      ptiles += (g.ng + 15) / 16;
       for (int i = 0; i < d; ++i) {
         const int c2 = zn ? (c + i) % zn : c + h->rule.step[i];
         const int ri = B0.find(c2);
@@ -2089,7 +2091,7 @@ mps_status sample_chunk(mps_state* h, const std::vector<double2*>& eb, int cnt, 
                                 reinterpret_cast<double2*>(dev + o_v), h->st));
     HIPCHK(launch_zgemm(reinterpret_cast<const GemmWork*>(dev + o_ids + l_g1), (int)g1.size(), nt1, h->st));
     HIPCHK(launch_zgemm(reinterpret_cast<const GemmWork*>(dev + o_ids + l_g2), (int)g2.size(), nt2, h->st));
-    HIPCHK(launch_sample_pick(d_grp, (int)groups.size(), d_ids, cnt, reinterpret_cast<const double2*>(dev + o_w),
+    HIPCHK(launch_sample_pick(d_grp, (int)groups.size(), ptiles, d_ids, reinterpret_cast<const double2*>(dev + o_w),
                               reinterpret_cast<const double2*>(dev + o_x), reinterpret_cast<const double*>(dev + o_u),
                               L, s, slots, cnt, reinterpret_cast<int*>(dev + o_occ),
                               reinterpret_cast<double*>(dev + o_pr), reinterpret_cast<int*>(dev + o_pick), h->st));

@@ -39,66 +39,97 @@ sample_gather_kernel(const SampleGroup* __restrict__ groups, const int* __restri
   }
 }
 
-// One thread per sample (position t of the grouped id list): the candidate
-// probabilities p_k = Re sum_r conj(W_k[r][jj]) X_k[r][jj] of its column jj,
-// the draw (NaN or a non-positive total leaves pick -1), the running
-// probability and the new vector W_pick[:, jj] / sqrt(p_pick) in its slot.
+// One workgroup per kPickS consecutive samples of one group (columns jj0 ..
+// jj0 + kPickS - 1): thread t takes sample column jj0 + t % kPickS and every
+// kPickRows-th row starting at t / kPickS, so each row's kPickS columns are
+// one contiguous load.  The candidate probabilities p_k = Re sum_r
+// conj(W_k[r][jj]) X_k[r][jj] are summed over the row slices in LDS (fixed
+// order); the first slice draws (NaN or a non-positive total leaves pick -1)
+// and updates the running probability; every slice then writes its rows of
+// the new vector W_pick[:, jj] / sqrt(p_pick) into the sample's slot.
+constexpr int kPickS = 16;
+constexpr int kPickRows = 256 / kPickS;
+
 __global__ void __launch_bounds__(256)
-sample_pick_kernel(const SampleGroup* __restrict__ groups, int ngroups, const int* __restrict__ ids, int total,
+sample_pick_kernel(const SampleGroup* __restrict__ groups, int ngroups, const int* __restrict__ ids,
                    const double2* __restrict__ wbuf, const double2* __restrict__ xbuf,
                    const double* __restrict__ uni, int L, int s, double2* __restrict__ slots, int ld_slot,
                    int* __restrict__ occ, double* __restrict__ prob, int* __restrict__ pick_out) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
+  __shared__ double part[kPickRows][kMaxD][kPickS];
+  __shared__ int pick_sh[kPickS];
+  __shared__ double scale_sh[kPickS];
   int lo = 0, hi = ngroups - 1;
+  const int b = blockIdx.x;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (groups[mid].id0 <= t) lo = mid; else hi = mid - 1;
+    if (groups[mid].tile0 <= b) lo = mid; else hi = mid - 1;
   }
-  const SampleGroup g = groups[lo];
-  const int jj = t - g.id0, j = ids[t];
-  double pv[kMaxD];
-  double tot = 0.0;
-  for (int k = 0; k < g.nout; ++k) {
-    const double2* w = wbuf + g.woff[k] + jj;
-    const double2* x = xbuf + g.woff[k] + jj;
+  const SampleGroup& g = groups[lo];
+  const int col = threadIdx.x % kPickS, slice = threadIdx.x / kPickS;
+  const int jj = (b - g.tile0) * kPickS + col;
+  const bool live = jj < g.ng;
+  const int nout = g.nout, ng = g.ng;
+  for (int k = 0; k < nout; ++k) {
     double q = 0.0;
-    for (int r = 0; r < g.nr[k]; ++r) {
-      const double2 a = w[(size_t)r * g.ng], b = x[(size_t)r * g.ng];
-      q = fma(a.x, b.x, fma(a.y, b.y, q));
-    }
-    pv[k] = (q > 0.0 || q != q) ? q : 0.0;      // rounding below zero -> 0; NaN kept
-    tot += pv[k];
-  }
-  int pick = -1;
-  if (tot > 0.0 && tot <= DBL_MAX) {
-    const double ut = uni[(size_t)j * L + s] * tot;
-    double acc = 0.0;
-    for (int k = 0; k < g.nout; ++k) {
-      acc += pv[k];
-      if (ut < acc) {
-        pick = k;
-        break;
+    if (live) {
+      const double2* w = wbuf + g.woff[k] + jj;
+      const double2* x = xbuf + g.woff[k] + jj;
+      for (int r = slice; r < g.nr[k]; r += kPickRows) {
+        const double2 a = w[(size_t)r * ng], c = x[(size_t)r * ng];
+        q = fma(a.x, c.x, fma(a.y, c.y, q));
       }
     }
-    if (pick < 0)
-      for (int k = g.nout - 1; k >= 0; --k)
-        if (pv[k] > 0.0) {
-          pick = k;
-          break;
+    part[slice][k][col] = q;
+  }
+  __syncthreads();
+  if (slice == 0) {
+    int pick = -1;
+    double sc = 0.0;
+    if (live) {
+      const int j = ids[g.id0 + jj];
+      double pv[kMaxD];
+      double tot = 0.0;
+      for (int k = 0; k < nout; ++k) {
+        double q = 0.0;
+        for (int r = 0; r < kPickRows; ++r) q += part[r][k][col];
+        pv[k] = (q > 0.0 || q != q) ? q : 0.0;     // rounding below zero -> 0; NaN kept
+        tot += pv[k];
+      }
+      if (tot > 0.0 && tot <= DBL_MAX) {
+        const double ut = uni[(size_t)j * L + s] * tot;
+        double acc = 0.0;
+        for (int k = 0; k < nout; ++k) {
+          acc += pv[k];
+          if (ut < acc) {
+            pick = k;
+            break;
+          }
         }
+        if (pick < 0)
+          for (int k = nout - 1; k >= 0; --k)
+            if (pv[k] > 0.0) {
+              pick = k;
+              break;
+            }
+      }
+      if (pick >= 0) {
+        prob[j] *= pv[pick] / tot;
+        occ[(size_t)j * L + s] = g.loc[pick];
+        sc = 1.0 / sqrt(pv[pick]);
+      }
+      pick_out[j] = pick >= 0 ? g.loc[pick] : -1;
+    }
+    pick_sh[col] = pick;
+    scale_sh[col] = sc;
   }
-  if (pick < 0) {
-    pick_out[j] = -1;
-    return;
-  }
-  prob[j] *= pv[pick] / tot;
-  occ[(size_t)j * L + s] = g.loc[pick];
-  pick_out[j] = g.loc[pick];
-  const double sc = 1.0 / sqrt(pv[pick]);
+  __syncthreads();
+  const int pick = pick_sh[col];
+  if (!live || pick < 0) return;
+  const int j = ids[g.id0 + jj];
+  const double sc = scale_sh[col];
   const double2* w = wbuf + g.woff[pick] + jj;
-  for (int r = 0; r < g.nr[pick]; ++r) {
-    const double2 a = w[(size_t)r * g.ng];
+  for (int r = slice; r < g.nr[pick]; r += kPickRows) {
+    const double2 a = w[(size_t)r * ng];
     slots[(size_t)r * ld_slot + j] = make_double2(a.x * sc, a.y * sc);
   }
 }
@@ -113,12 +144,12 @@ hipError_t launch_sample_gather(const SampleGroup* groups, int ngroups, long lon
   return hipGetLastError();
 }
 
-hipError_t launch_sample_pick(const SampleGroup* groups, int ngroups, const int* ids, int total,
+hipError_t launch_sample_pick(const SampleGroup* groups, int ngroups, int ntiles, const int* ids,
                               const double2* wbuf, const double2* xbuf, const double* uni, int L, int s,
                               double2* slots, int ld_slot, int* occ, double* prob, int* pick_out, hipStream_t st) {
-  if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sample_pick_kernel, dim3((total + 255) / 256), dim3(256), 0, st, groups, ngroups, ids, total,
-                     wbuf, xbuf, uni, L, s, slots, ld_slot, occ, prob, pick_out);
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sample_pick_kernel, dim3(ntiles), dim3(256), 0, st, groups, ngroups, ids, wbuf, xbuf, uni, L,
+                     s, slots, ld_slot, occ, prob, pick_out);
   return hipGetLastError();
 }
 

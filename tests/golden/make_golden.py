@@ -11,6 +11,10 @@ workloads/circuits.py or workloads/hamiltonians.py and stores, as JSON text:
   * every gate's discarded weight and cut margin,
   * the Schmidt values of the central bonds.
 
+A name in PREFIXES stores the first layers of a workload only (every bond's
+Schmidt values too): BH_L64_d4_chi256_T3_L53 is the Bose-Hubbard quench up to
+its first near-tie at the cut.
+
 A name ending in _gesvd repeats its workload with LAPACK's QR-iteration SVD
 (gesvd) in place of divide and conquer (gesdd): a second correct FP64 run of
 the same algorithm whose rounding differs, which measures how far two such
@@ -31,6 +35,7 @@ Usage:  python tests/golden/make_golden.py L32_N16_d4_chi512
         python tests/golden/make_golden.py ISING_L64_chi256_T10
         python tests/golden/make_golden.py ISING_L64_chi256_T10_gesvd
         python tests/golden/make_golden.py BH_L64_d4_chi256_T3_gesvd
+        python tests/golden/make_golden.py BH_L64_d4_chi256_T3_L53
         python tests/golden/make_golden.py SYN_L64_chi2048_4gates
 """
 import json
@@ -56,6 +61,14 @@ WORKLOADS = {
     "BH_L64_d4_chi256_T3": (hamiltonians.config_bose_hubbard_quench, 105),
     # the Z_2 (transverse-field Ising) quench: charge = occupation count mod 2
     "ISING_L64_chi256_T10": (hamiltonians.config_ising_quench, 106),
+}
+
+
+# prefixes: (workload, layers) -- the part of an evolution that FP64 determines
+# (the disordered Bose-Hubbard quench's first stored cut margin below 1e-11 of
+# s_0 is at gate 1686, in layer 53; its first 53 layers hold 1670 gates)
+PREFIXES = {
+    "BH_L64_d4_chi256_T3_L53": ("BH_L64_d4_chi256_T3", 53),
 }
 
 
@@ -119,8 +132,15 @@ def main(name: str) -> None:
     driver = "gesdd"
     if name.endswith("_gesvd"):
         driver = "gesvd"
-    make, pattern_seed = WORKLOADS[name[:-len("_gesvd")] if driver == "gesvd" else name]
+    base = name[:-len("_gesvd")] if driver == "gesvd" else name
+    nlayers = None
+    if base in PREFIXES:
+        base, nlayers = PREFIXES[base]
+    make, pattern_seed = WORKLOADS[base]
     cfg = make()
+    if nlayers is not None:
+        cfg["layers"] = cfg["layers"][:nlayers]
+        cfg["gates"] = [g for lay in cfg["layers"] for g in lay]
     L, d = cfg["L"], cfg["d"]
     N = sum(cfg["occupation"])
     mod = cfg.get("modulus", 0)
@@ -150,6 +170,8 @@ def main(name: str) -> None:
         "discarded": [r.discarded for r in m.records],
         "margin": [r.margin if np.isfinite(r.margin) else None for r in m.records],
         "lambda_center": {str(b): m.lam[b].tolist() for b in (L // 2 - 1, L // 2, L // 2 + 1)},
+        "layers": len(cfg["layers"]),
+        "lambda_all": ({str(b): m.lam[b].tolist() for b in range(L + 1)} if nlayers is not None else None),
         "oracle_seconds": time.time() - t0,
     }
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}.json")

@@ -719,17 +719,46 @@ def test_tebd_xxz_quench_vs_stored_oracle(mps_cls):
     _tebd_vs_stored(mps_cls, "XXZ_L64_chi256_T10", ham.config_xxz_quench)
 
 
+def oracle_spread(name):
+    """How far two correct FP64 runs of the oracle drift apart on a stored
+    workload: the gesdd run against the gesvd rerun (tests/golden, both from
+    oracle/ only), as (amplitudes, per entry relative to the largest;
+    discarded weights, largest absolute; central Schmidt values, relative to
+    each bond's largest)."""
+    import json
+    import os
+    g = os.path.join(os.path.dirname(__file__), "golden")
+    a = json.load(open(os.path.join(g, f"{name}.json")))
+    b = json.load(open(os.path.join(g, f"{name}_gesvd.json")))
+    A = np.array(a["amp_re"]) + 1j * np.array(a["amp_im"])
+    B = np.array(b["amp_re"]) + 1j * np.array(b["amp_im"])
+    amp = float(np.max(np.abs(A - B)) / np.max(np.abs(A)))
+    disc = float(np.max(np.abs(np.array(a["discarded"]) - np.array(b["discarded"]))))
+    lam = max(float(np.max(np.abs(np.array(a["lambda_center"][k]) - np.array(b["lambda_center"][k])))
+                    / a["lambda_center"][k][0]) for k in a["lambda_center"])
+    assert a["bond_charges"] == b["bond_charges"]
+    return amp, disc, lam
+
+
 def test_tebd_ising_quench_vs_stored_oracle(mps_cls):
     """The measured Z_2 Ising quench (L=64, chi_max=256, 12632 dense gates)
-    against the oracle's stored results.  Charges must match exactly; the
-    values carry the two SVDs' rounding differences (the Jacobi stops at
-    orthogonality ~1e-13, LAPACK is backward stable at ~1e-16), which each
-    truncating gate passes on and near-ties at later cuts enlarge: measured
-    2.6e-11 on the worst discarded weight (gate 12542) and 3.1e-9 on the
-    amplitudes after 12632 gates.  Bars for this length of evolution: 1e-10
-    per discarded weight, 1e-8 relative on amplitudes and Schmidt values."""
+    against the oracle's stored results.  Charges must match exactly.  The
+    values of a long truncated evolution carry the rounding of every SVD,
+    which each later cut passes on: two correct FP64 runs of the oracle, with
+    LAPACK's divide-and-conquer and QR-iteration SVDs, end 3.3e-9 apart on
+    the amplitudes and 2.5e-11 on the worst discarded weight (stored as the
+    _gesvd rerun).  The GPU is held to four times that spread (and never
+    tighter than the complex128 bars): its difference from the oracle must
+    look like the oracle's difference from itself."""
+    import os
     from workloads import hamiltonians as ham
-    _tebd_vs_stored(mps_cls, "ISING_L64_chi256_T10", ham.config_ising_quench, amp_tol=1e-8, disc_tol=1e-10)
+    name = "ISING_L64_chi256_T10"
+    if not os.path.exists(os.path.join(os.path.dirname(__file__), "golden", f"{name}_gesvd.json")):
+        pytest.skip("the oracle's gesvd rerun of the Ising quench is not stored")
+    amp_s, disc_s, lam_s = oracle_spread(name)
+    assert 1e-10 < amp_s < 1e-8 and disc_s < 1e-10
+    _tebd_vs_stored(mps_cls, name, ham.config_ising_quench, amp_tol=max(TOL, 4 * max(amp_s, lam_s)),
+                    disc_tol=max(1e-12, 4 * disc_s))
 
 
 def test_tebd_bose_hubbard_quench_vs_stored_oracle(mps_cls):
@@ -759,6 +788,43 @@ def test_tebd_bose_hubbard_quench_vs_stored_oracle(mps_cls):
     tie = int(np.argmax(margins < 1e-11)) if np.any(margins < 1e-11) else len(margins)
     assert tie > 1000
     assert np.max(np.abs(disc[:tie] - odisc[:tie])) <= 1e-12
+    m.close()
+
+
+def test_tebd_bose_hubbard_prefix_vs_stored_oracle(mps_cls):
+    """The disordered Bose-Hubbard quench up to its first near-tie at the cut
+    (53 layers, 1670 gates; every stored cut margin above 4e-11 of s_0, far
+    above the FP64 rounding of the Schmidt values) against the oracle's stored
+    state at that point: every gate's discarded weight, 1025 amplitudes, the
+    norm, every bond's Schmidt values at the complex128 bars, and the charges
+    of every bond whose audit is clean."""
+    import json
+    import os
+    from workloads import hamiltonians as ham
+    path = os.path.join(os.path.dirname(__file__), "golden", "BH_L64_d4_chi256_T3_L53.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle results BH_L64_d4_chi256_T3_L53.json not present")
+    ref = json.load(open(path))
+    cfg = ham.config_bose_hubbard_quench()
+    cfg["layers"] = cfg["layers"][:ref["layers"]]
+    m, disc = run_dense(mps_cls, cfg)
+    odisc = np.array(ref["discarded"])
+    assert disc.shape == odisc.shape == (1670,)
+    assert min(x for x in ref["margin"] if x is not None) > 1e-11
+    assert np.max(np.abs(disc - odisc)) <= 1e-12
+    pats = np.array(ref["patterns"], dtype=np.int32)
+    amp = np.array(ref["amp_re"]) + 1j * np.array(ref["amp_im"])
+    close_amps(m.amplitudes(pats), amp)
+    assert abs(m.norm2() - ref["norm2"]) <= TOL * ref["norm2"]
+    clean = 0
+    for b in range(cfg["L"] + 1):
+        lam = np.array(ref["lambda_all"][str(b)])
+        got = np.sort(m.bond_lambda(b))[::-1]
+        assert got.shape == lam.shape and np.max(np.abs(got - lam)) <= TOL * lam[0], b
+        if ref["audit_clean"][b]:
+            clean += 1
+            assert m.bond_sectors(b) == {int(k): v for k, v in ref["bond_charges"][b].items()}, b
+    print(f"Bose-Hubbard prefix: charges compared on {clean} of {cfg['L'] + 1} bonds (clean audit)")
     m.close()
 
 
