@@ -675,7 +675,7 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
               sg.tile_begin[v] = P.sg_tiles[v];
               P.sg_tiles[v] += ((nL + tr - 1) / tr) * sg.tiles_n[v];
               // executed: whole tiles, k in steps of 16 (one MFMA k step)
-              P.sg_mfma_flops[v] += 48.0 * tr * tc * 16.0 * (((nL + tr - 1) / tr) * sg.tiles_n[v]) *
+              P.sg_mfma_flops[v] += 64.0 * tr * tc * 16.0 * (((nL + tr - 1) / tr) * sg.tiles_n[v]) *
                                     ((sg.k + 15) / 16);
             }
             P.sg.push_back(sg);

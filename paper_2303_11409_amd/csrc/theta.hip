@@ -140,19 +140,19 @@ theta_kernel(const GateWork* __restrict__ gates, const ThetaTile* __restrict__ t
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// x = hi + mid + lo in BF16 (8 significant bits each), taken from the float
-// conversion of x (relative error 2^-24): hi = bf16(x), mid = bf16(x - hi),
-// lo = bf16(x - hi - mid).  Each difference is exact in float and each
-// rounding keeps the next 8 bits, so |x - hi| <= 2^-8 |x|, |x - hi - mid| <=
-// 2^-16 |x| and |x - hi - mid - lo| <= 2^-24 |x|: with the conversion the
-// three parts represent x to 2^-23 relative.
+// x = hi + mid + lo in BF16 (8 significant bits each): hi = bf16(x),
+// mid = bf16(x - hi), lo = bf16(x - hi - mid), the differences taken in FP64
+// (exact: each part agrees with what remains to its leading bits) and each
+// part rounded through FP32.  Every rounding keeps the next 8 bits of what
+// remains, so |x - hi| <= 2^-8 |x|, |x - hi - mid| <= 2^-16 |x| and
+// |x - hi - mid - lo| <= 2^-24 |x| (up to the FP32 step, 2^-24 of each part).
 __device__ __forceinline__ void split_bf16(double x, unsigned short& hi, unsigned short& mid,
                                            unsigned short& lo) {
-  const float xf = (float)x;
-  const __bf16 h = (__bf16)xf;
-  const float r1 = xf - (float)h;
-  const __bf16 m = (__bf16)r1;
-  const __bf16 l = (__bf16)(r1 - (float)m);
+  const __bf16 h = (__bf16)(float)x;
+  const double r1 = x - (double)(float)h;
+  const __bf16 m = (__bf16)(float)r1;
+  const double r2 = r1 - (double)(float)m;
+  const __bf16 l = (__bf16)(float)r2;
   hi = __builtin_bit_cast(unsigned short, h);
   mid = __builtin_bit_cast(unsigned short, m);
   lo = __builtin_bit_cast(unsigned short, l);
@@ -267,30 +267,45 @@ __device__ __forceinline__ bf16x8 sg_op(const unsigned short (*buf)[ROWS][kSgRow
   return *reinterpret_cast<const bf16x8*>(&buf[plane][row][k]);
 }
 
-// Accumulates the six split products of one real product whose parts are
-// x[0..2] (hi, mid, lo) and y[0..2]: the terms x_i y_j with i + j <= 2.  The
-// dropped terms (mid lo, lo mid, lo lo) are below 2^-23 of |x| |y|.
-__device__ __forceinline__ f32x16 sg_real6(const bf16x8* x, const bf16x8* y, f32x16 c) {
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[0], c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[1], c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[0], c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[2], c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[2], y[0], c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[1], c, 0, 0, 0);
-  return c;
+// The split products of one real product x y, x = x[0] + x[1] + x[2] and
+// y = y[0] + y[1] + y[2] (hi, mid, lo): the leading term x0 y0 into `big`,
+// the seven terms x_i y_j with 0 < i + j <= 3 into `small` (only lo lo, below
+// 2^-32 of |x||y|, is dropped).  Keeping the corrections apart from the
+// leading term means the FP32 rounding of their sum is relative to the
+// corrections, 2^-8 of the product, not to the product.
+__device__ __forceinline__ void sg_real8(const bf16x8* x, const bf16x8* y, f32x16& big, f32x16& small) {
+  big = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[0], big, 0, 0, 0);
+  small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[1], small, 0, 0, 0);
+  small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[0], small, 0, 0, 0);
+  small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[0], y[2], small, 0, 0, 0);
+  small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[2], y[0], small, 0, 0, 0);
+  small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[1], small, 0, 0, 0);
+  small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[1], y[2], small, 0, 0, 0);
+  small = __builtin_amdgcn_mfma_f32_32x32x16_bf16(x[2], y[1], small, 0, 0, 0);
+}
+
+// The parts with their signs flipped (bit 15 of every BF16).
+__device__ __forceinline__ void sg_negate3(const bf16x8* x, bf16x8* out) {
+#pragma unroll
+  for (int p = 0; p < 3; ++p) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 v = __builtin_bit_cast(u32x4, x[p]);
+    v ^= 0x80008000u;
+    out[p] = __builtin_bit_cast(bf16x8, v);
+  }
 }
 
 // One (32 WR) x (32 WC) output tile per workgroup of WR x WC waves; wave w
 // computes the 32 x 32 quadrant (rows 32 (w / WC), columns 32 (w % WC)) with
 // v_mfma_f32_32x32x16_bf16.  Lane l supplies A[i = l % 32][k = 8 (l / 32) + e]
 // and B[k = 8 (l / 32) + e][j = l % 32] (e = 0..7); its accumulator register r
-// holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].  Per k step: Re = Ar Br -
-// Ai Bi and Im = Ar Bi + Ai Br, each real product as the six split terms of
-// sg_real6, in four accumulators (Ar Br, Ai Bi, Ar Bi, Ai Br) whose chains
-// interleave.  Products of BF16 values are exact in FP32; the matrix cores
-// accumulate one 32-wide k chunk in FP32, and the chunk sums are added in
-// FP64 (so FP32 rounding grows with the chunk, not with k), and the product is
-// stored in complex128.  Every output element sees the same sequence of
+// holds D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32].  Per k step: Re = Ar Br +
+// Ai (-Bi) and Im = Ar Bi + Ai Br, each real product as the split terms of
+// sg_real8, into four accumulators (Re and Im, leading terms and corrections)
+// whose chains interleave.  Products of BF16 values are exact in FP32; the
+// matrix cores accumulate one 32-wide k chunk in FP32, the chunk sums are
+// added in FP64 (so FP32 rounding grows with the chunk, not with k), and the
+// product is stored in complex128.  Every output element sees the same sequence of
 // matrix-core operations whatever the tile shape, so the shapes give bitwise
 // the same products (the tuner picks one by speed alone).  The k chunks go
 // through two LDS buffers: the next chunk's loads are in flight during the
@@ -333,26 +348,27 @@ split_gemm_kernel(const SplitGemm* __restrict__ probs, int nprob, int variant) {
     }
     // the second k step of a chunk that ends the segment early is all zero
     const int nks = k0 + 16 < w.k ? 2 : 1;
-    f32x16 crp = {}, crn = {}, cia = {}, cib = {};
+    f32x16 reb = {}, res = {}, imb = {}, ims = {};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (h >= nks) break;
       // planes 0..2: re hi, mid, lo; 3..5: im hi, mid, lo
-      bf16x8 a[kSgPlanes], b[kSgPlanes];
+      bf16x8 a[kSgPlanes], b[kSgPlanes], bin[3];
 #pragma unroll
       for (int p = 0; p < kSgPlanes; ++p) {
         a[p] = sg_op<TR>(sa[buf], p, R + li, 16 * h + lk);
         b[p] = sg_op<TC>(sb[buf], p, Cq + li, 16 * h + lk);
       }
-      crp = sg_real6(a, b, crp);
-      crn = sg_real6(a + 3, b + 3, crn);
-      cia = sg_real6(a, b + 3, cia);
-      cib = sg_real6(a + 3, b, cib);
+      sg_negate3(b + 3, bin);
+      sg_real8(a, b, reb, res);
+      sg_real8(a + 3, bin, reb, res);
+      sg_real8(a, b + 3, imb, ims);
+      sg_real8(a + 3, b, imb, ims);
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      dre[r] += (double)crp[r] - (double)crn[r];
-      dim[r] += (double)cia[r] + (double)cib[r];
+      dre[r] += (double)reb[r] + (double)res[r];
+      dim[r] += (double)imb[r] + (double)ims[r];
     }
     if (more) {
       // the other buffer was last read before the previous barrier
