@@ -94,10 +94,12 @@ typedef struct {
  *   form       MPS_FORM_PLAIN_C128 (default): every step in complex128.
  *              MPS_FORM_SPLIT_BF16X3: the charge-triple products of Theta
  *              formation run on the matrix cores with each operand split into
- *              three BF16 parts (x = hi + mid + lo, 2^-23 relative) and the
- *              six BF16 products of total order <= 2 per real product,
- *              accumulated in FP32 (FP32 accuracy: a few 2^-23 per product
- *              plus the FP32 rounding of the sums); the gate mix, the Jacobi
+ *              three BF16 parts (x = hi + mid + lo, 2^-24 relative) and the
+ *              eight BF16 part products other than lo*lo per real product,
+ *              the leading one and the corrections accumulated apart in FP32
+ *              within 32-wide k chunks, the chunks summed in FP64 (FP32
+ *              accuracy: about 2^-24 per product plus the FP32 rounding of
+ *              the chunk sums); the gate mix, the Jacobi
  *              SVD, the cut and the update stay FP64, and the site tensors
  *              are stored in complex128.
  *   modulus    0 (default): U(1), the charge of Eqs. (E2)-(E4) is the particle
@@ -171,8 +173,8 @@ typedef struct {
   long long gemm_launches;     /*   (theta_ms then covers the gate mix)        */
   double gemm_mfma_flops;      /* split-BF16 form: flops the BF16 matrix-core  */
                                /*   products execute, tile padding included    */
-                               /*   (48 per complex multiply-add: 4 real       */
-                               /*   products x 6 split terms x 2)              */
+                               /*   (64 per complex multiply-add: 4 real       */
+                               /*   products x 8 split terms x 2)              */
   double split_ms;             /* split-BF16 form: splitting the site tensors  */
                                /*   into BF16 planes before the products       */
   double leak_total;           /* weight removed by the local cutoff, summed   */

@@ -321,14 +321,14 @@ def test_serving_form_results_equal_each_request_alone(mps_cls, lanes):
 
 
 # Precision form (split-BF16 charge-triple products).  Every operand entry is
-# split into three BF16 parts (hi + mid + lo: 2^-23 relative, the FP32
-# conversion included) and each real product keeps the six part products of
-# total order <= 2, so one product is off by at most ~3 * 2^-23 of |a||b|; the
-# matrix cores sum 32-wide k chunks in FP32 (at most 32 * 2^-24 of the chunk's
-# sum of |a||b|, about sqrt(32) * 2^-24 typically) and the chunks are added in
-# FP64.  A gate's Theta is thus within a few 1e-7 of its FP64 value; the stated
-# bar for the FP32-accuracy forms, 1e-5 relative, holds with margin for a
-# layer and for circuits of hundreds of gates (measured 2e-7 to 6e-7).
+# split into three BF16 parts (hi + mid + lo, residuals taken in FP64: 2^-24
+# relative) and each real product keeps the eight part products other than
+# lo*lo, the leading one and the corrections in separate FP32 accumulators
+# over 32-wide k chunks, the chunks summed in FP64: about 2^-24 of |a||b| per
+# product plus the FP32 rounding of the chunk sums.  A gate's Theta is thus
+# within a few 1e-8 to 1e-7 of its FP64 value; the stated bar for the
+# FP32-accuracy forms, 1e-5 relative, holds with margin for a layer (measured
+# 1e-7 to 3e-7) and for the 2016-gate 64-mode circuit (3.9e-6).
 TOL_SPLIT = 1e-5
 
 
