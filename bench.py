@@ -39,18 +39,19 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/cl
 
 # HBM bytes per launch of jacobi_block_step on this workload, from two
 # rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline
-# --batch-copies 0 --mix-circuits 0 --chi2048-layers 0 --serve-seconds 0 --samples 0
-# --no-tebd`
-# (FETCH_SIZE, WRITE_SIZE; mean over the launches) scaled by the same counters
-# on a plain 256 MiB copy (`bench.py --copy-probe`: FETCH_SIZE reads 131085.2
-# KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99982 and writes
-# by 1).  Valid only for the Jacobi source (csrc/jacobi.hip) and the inner
-# sweep count per visit (kMaxInnerSweeps in csrc/runtime.cpp) it was taken on.
+# --batch-copies 0 --mix-circuits 0 --chi2048-layers 0 --serve-seconds 0
+# --samples 4096 --no-tebd`
+# (FETCH_SIZE, WRITE_SIZE; mean over the 20988 launches) scaled by the same
+# counters on a plain 256 MiB copy (`bench.py --copy-probe`: FETCH_SIZE reads
+# 131085.2 KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99980
+# and writes by 1).  Valid only for the Jacobi source (csrc/jacobi.hip) and the
+# inner sweep count per visit (kMaxInnerSweeps in csrc/runtime.cpp) it was
+# taken on.
 MEASURED_TRAFFIC = {
-    "kernels_sha256": "6416f5c5774462e1be2ce3334c18593b029039258c518194238463efb8d0be71",
+    "kernels_sha256": "558b22d3ccbe4b8ba15a38d9b96ed87765332668e867b033aaeee704b95bcb81",
     "max_inner": 1,
-    "fetch_kib": 16572.336, "write_kib": 21338.777,
-    "fetch_scale": 262144.0 / 131085.208, "write_scale": 1.0,
+    "fetch_kib": 15566.3, "write_kib": 19929.3,
+    "fetch_scale": 262144.0 / 131085.2, "write_scale": 1.0,
 }
 
 
