@@ -50,14 +50,15 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/cl
 MEASURED_TRAFFIC = {
     "kernels_sha256": "558b22d3ccbe4b8ba15a38d9b96ed87765332668e867b033aaeee704b95bcb81",
     "max_inner": 1,
+    "jacobi_block": 16,
     "fetch_kib": 15566.3, "write_kib": 19929.3,
     "fetch_scale": 262144.0 / 131085.2, "write_scale": 1.0,
 }
 
 
-def measured_traffic():
-    """Bytes per launch from the counters, or None once the kernel source or its
-    inner sweep count changed."""
+def measured_traffic(block: int):
+    """Bytes per launch from the counters, or None once the kernel source, its
+    inner sweep count or the Jacobi block size differs from the counted run."""
     import hashlib
     import re
     csrc = os.path.join(ROOT, "paper_2303_11409_amd", "csrc")
@@ -71,7 +72,11 @@ def measured_traffic():
     t = MEASURED_TRAFFIC
     if sha != t["kernels_sha256"] or inner is None or int(inner.group(1)) != t["max_inner"]:
         return None
+    if block != t["jacobi_block"]:
+        return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
+# vectors per Jacobi block when mps_opts.jacobi_block is 0
+JACOBI_BLOCK_DEFAULT = 16
 METRIC = "gate applies/s + sector-GEMM TFLOP/s at χ=2048 vs plain; p50/p99 latency"
 
 
@@ -481,6 +486,8 @@ def main() -> int:
                     help="exact output samples drawn from the final state (0 = skip)")
     ap.add_argument("--no-tebd", action="store_true",
                     help="skip the Hamiltonian time-evolution workloads (XXZ, Bose-Hubbard)")
+    ap.add_argument("--jacobi-block", type=int, default=0,
+                    help="vectors per Jacobi block of the headline circuit (0: the library default, 8; or 16)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the "
                          "reference kernel for scaling HBM byte counters)")
@@ -507,7 +514,8 @@ def main() -> int:
     dev = TorchDevice()
 
     def new_state():
-        return MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"], device=dev)
+        return MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"], device=dev,
+                   jacobi_block=args.jacobi_block)
 
     def run(m):
         for sites, us in layers:
@@ -626,9 +634,11 @@ def main() -> int:
     per_launch_flops = agg["jacobi_flops"] / launches
     avg_ms = agg["jacobi_ms"] / launches
     achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
+    jblock = args.jacobi_block or JACOBI_BLOCK_DEFAULT
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
-                "kernel": "jacobi_block_step", "avg_launch_ms": avg_ms,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(jblock),
+                "kernel": "jacobi_block_step8" if jblock == 8 else "jacobi_block_step", "jacobi_block": jblock,
+                "avg_launch_ms": avg_ms,
                 "flops_per_launch": per_launch_flops, "launches": launches}
     props = torch.cuda.get_device_properties(0)
     value = args.steps * ngates / elapsed

@@ -146,6 +146,13 @@ typedef struct {
                                   shape 0..3 (64x64, 32x64, 64x32, 32x32; a
                                   diagnostic).  The products are bitwise the
                                   same for every shape. */
+  int jacobi_block;            /* vectors per block of the blocked Jacobi SVD:
+                                  0 (default) = 16, or 8 or 16.  A block pair
+                                  of 2b vectors is orthogonalised per visit
+                                  through its 2b x 2b Gram matrix; smaller
+                                  blocks make shorter visits and more of them.
+                                  In a batch the first state's value serves
+                                  every state. */
 } mps_opts;
 
 /* Per-handle counters, accumulated since creation or mps_reset_stats.
@@ -192,7 +199,7 @@ typedef struct {
 
 /* Fill *o with the defaults: chi_max 0, cutoff 0, zero_tol 1e-13,
  * max_sweeps 40, jacobi_tol 0, plain form, modulus 0, blocked_sweeps 0,
- * select_scratch 0, sweep_graph 0, tile_tuning 1. */
+ * select_scratch 0, sweep_graph 0, tile_tuning 1, jacobi_block 0. */
 void mps_default_opts(mps_opts* o);
 
 /* Create a state of L sites with local dimension d (occupations 0..d-1,

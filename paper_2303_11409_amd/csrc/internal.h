@@ -179,11 +179,13 @@ struct CutOut {
                           // the gate minus the total weight after it
 };
 
-// Blocked Jacobi: vectors are grouped in blocks of kJB; one round-robin step
-// pairs the nb blocks of a sector into nb/2 block pairs, each handled by one
-// workgroup.
+// Blocked Jacobi: vectors are grouped in blocks of kJB8 = 8 or kJB = 16
+// (mps_opts.jacobi_block); one round-robin step pairs the nb blocks of a
+// sector into nb/2 block pairs, each handled by one workgroup.
 constexpr int kJB = 16;
 constexpr int kJP = 2 * kJB;
+constexpr int kJB8 = 8;
+constexpr int kJacobiBlockDefault = kJB;
 
 struct JacobiBlockWork {
   int sector;             // SectorWork index

@@ -482,6 +482,302 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
   if (tid < kJP && vrow[tid] >= 0) norm2[sw.sig + vrow[tid]] = gs[tid][tid].x;
 }
 
+// ---------------------------------------------------------------------------
+// The same visit with blocks of kJB8 = 8 vectors (block pairs of 16).
+//
+// A 16-vector pair carries a quarter of the Gram and rotation work of a
+// 32-vector pair and its eig takes 15 round-robin steps instead of 31, so a
+// visit is several times shorter; a sweep has twice the steps and a launch
+// twice the workgroups.  The work is laid out for that size: each of the four
+// wavefronts takes every fourth 32-column chunk of the vectors through a
+// staging tile of its own (no workgroup barrier in the chunk loops), the
+// Gram matrix is summed from the four partial products in a fixed order, and
+// the eig runs on one wavefront, which owns the whole 16 x 16 problem, with
+// the matrices updated in place in LDS (within a wavefront, LDS operations
+// complete in issue order, and every read of a step is issued before its
+// first write).
+constexpr int kJP8 = 2 * kJB8;
+constexpr int kJ8Regs = kJP8 * 32 / 64;   // elements of a 16 x 32 chunk per lane
+
+// LDS ordering point within one wavefront: the compiler keeps LDS accesses on
+// their side, and this lane's LDS operations have completed.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);       // lgkmcnt(0), other counters unconstrained
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pair k of round-robin step s over the 16 rows, (p, q) with p < q (the
+// schedule of rr_pair(s, k, 16) with selects instead of divisions).
+__device__ __forceinline__ void jac8_pair(int s, int k, int& p, int& q) {
+  int i = s + k;
+  i = i >= kJP8 - 1 ? i - (kJP8 - 1) : i;
+  int j = s - k;
+  j = j < 0 ? j + (kJP8 - 1) : j;
+  j = k == 0 ? kJP8 - 1 : j;
+  p = min(i, j);
+  q = max(i, j);
+}
+
+// Lane's share of the chunk [c0, c0 + 32) of the 16 rows: element e = lane +
+// 64 j is row e / 32, column e % 32, so 32 lanes read one row's 512 bytes.
+// rowp[j] is that row's base pointer (null: absent row, reads as 0).
+__device__ __forceinline__ void jac8_fetch(double2 (&v)[kJ8Regs], const double2* const (&rowp)[kJ8Regs],
+                                           int len, int c0) {
+  const int col = c0 + (threadIdx.x & 31);
+#pragma unroll
+  for (int j = 0; j < kJ8Regs; ++j) {
+    v[j] = make_double2(0.0, 0.0);
+    if (rowp[j] && col < len) v[j] = rowp[j][col];
+  }
+}
+
+// Runs body(c0, tile) for the chunks c0 = 32 (w + 4 i) < len of wavefront w,
+// each staged in the wavefront's tile; the next chunk's loads are in flight
+// while the body works.  The body may overwrite its own chunk's columns.
+template <class Body>
+__device__ __forceinline__ void jac8_chunks(double2 (*xt)[33], const double2* x, int len, const int* vrow,
+                                            Body&& body) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double2* rowp[kJ8Regs];
+#pragma unroll
+  for (int j = 0; j < kJ8Regs; ++j) {
+    const int r = vrow[(lane >> 5) + 2 * j];
+    rowp[j] = r >= 0 ? x + (size_t)r * len : nullptr;
+  }
+  const int nch = (len + 31) >> 5;
+  double2 ra[kJ8Regs];
+  int ch = wave;
+  if (ch < nch) jac8_fetch(ra, rowp, len, ch * 32);
+  while (ch < nch) {
+    wave_lds_sync();                        // the previous body's tile reads are done
+#pragma unroll
+    for (int j = 0; j < kJ8Regs; ++j) xt[(lane >> 5) + 2 * j][lane & 31] = ra[j];
+    wave_lds_sync();
+    const int nx = ch + 4;
+    if (nx < nch) jac8_fetch(ra, rowp, len, nx * 32);
+    body(ch * 32);
+    ch = nx;
+  }
+  wave_lds_sync();
+}
+
+// G = X X^H of the 16 rows into gs (exactly Hermitian, from the upper
+// triangle).  Each wavefront forms Gr = Xr Xr^T + Xi Xi^T and M = Xi Xr^T over
+// its chunks on the matrix cores (lane l supplies X[l % 16][k0 + l / 16] as
+// both operands); the partials meet in the staging tiles and are summed in
+// wavefront order; Gi = M - M^T.
+__device__ void jac8_gram(double2 (*xt)[kJP8][33], double2 (*gs)[kJP8 + 1], const double2* x, int len,
+                          const int* vrow) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  double2 (*t)[33] = xt[wave];
+  v4d gra = {0.0, 0.0, 0.0, 0.0}, grb = {0.0, 0.0, 0.0, 0.0}, mm = {0.0, 0.0, 0.0, 0.0};
+  jac8_chunks(t, x, len, vrow, [&](int) {
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 4) {
+      const double2 av = t[li][k0 + lk];
+      gra = mfma16x16x4(av.x, av.x, gra);
+      grb = mfma16x16x4(av.y, av.y, grb);
+      mm = mfma16x16x4(av.y, av.x, mm);
+    }
+  });
+  double* part = reinterpret_cast<double*>(&t[0][0]);     // [2][16][16]
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    part[(4 * r + lk) * 16 + li] = gra[r] + grb[r];
+    part[256 + (4 * r + lk) * 16 + li] = mm[r];
+  }
+  __syncthreads();
+  {
+    const int r = tid >> 4, c = tid & 15;
+    if (r <= c) {
+      double gr = 0.0, mrc = 0.0, mcr = 0.0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const double* pw = reinterpret_cast<const double*>(&xt[w][0][0]);
+        gr += pw[r * 16 + c];
+        mrc += pw[256 + r * 16 + c];
+        mcr += pw[256 + c * 16 + r];
+      }
+      const double2 g = make_double2(gr, r == c ? 0.0 : mrc - mcr);
+      gs[r][c] = g;
+      gs[c][r] = cconj(g);
+    }
+  }
+  __syncthreads();
+}
+
+// X <- W X for the 16 rows of a row-major matrix (rows of length len): per
+// chunk, two 16 x 16 output tiles, three real products per k-step (Gauss).
+__device__ void jac8_apply(double2 (*xt)[kJP8][33], double2 (*ws)[kJP8 + 1], double2* __restrict__ x, int len,
+                           const int* vrow) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  double2 (*t)[33] = xt[wave];
+  int orow[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) orow[r] = vrow[4 * r + lk];
+  jac8_chunks(t, x, len, vrow, [&](int c0) {
+#pragma unroll
+    for (int jt = 0; jt < 32; jt += 16) {
+      v4d p1 = {0.0, 0.0, 0.0, 0.0}, p2 = {0.0, 0.0, 0.0, 0.0}, p3 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k0 = 0; k0 < kJP8; k0 += 4) {
+        const double2 wv = ws[li][k0 + lk];          // A = W[i][k]
+        const double2 xv = t[k0 + lk][jt + li];      // B = X[k][jt + j]
+        p1 = mfma16x16x4(wv.x, xv.x, p1);
+        p2 = mfma16x16x4(wv.y, xv.y, p2);
+        p3 = mfma16x16x4(wv.x + wv.y, xv.x + xv.y, p3);
+      }
+      const int col = c0 + jt + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (orow[r] >= 0 && col < len)
+          x[(size_t)orow[r] * len + col] = make_double2(p1[r] - p2[r], p3[r] - p1[r] - p2[r]);
+    }
+  });
+}
+
+// True (uniform) if any off-diagonal pair of the 16 x 16 gs is above the
+// threshold: thread t checks entry (t / 16, t % 16).
+__device__ __forceinline__ bool jac8_any_above(double2 (*gs)[kJP8 + 1], double tol, double floor_g, int4* anyf,
+                                               int& parity) {
+  const int p = threadIdx.x >> 4, q = threadIdx.x & 15;
+  const int f = p < q && jac_needs(gs[p][p].x, gs[q][q].x, gs[p][q], tol, floor_g) ? 1 : 0;
+  return block_any(f, anyf, parity);
+}
+
+// Rotations of the 16 x 16 gs by wavefront 0, in place: lane 8 A + B owns
+// the 2 x 2 blocks (rows of pair A) x (columns of pair B) of G and W, as in
+// jac_gram_eig; up to max_inner sweeps of 15 steps.
+__device__ void jac8_gram_eig(double2 (*gs)[kJP8 + 1], double2 (*ws)[kJP8 + 1], double tol, double floor_g,
+                              int max_inner) {
+  const int lane = threadIdx.x & 63;
+  const int A = lane >> 3, B = lane & 7;
+  for (int inner = 0; inner < max_inner; ++inner) {
+    for (int s2 = 0; s2 < kJP8 - 1; ++s2) {
+      int pa, qa, pb, qb;
+      jac8_pair(s2, A, pa, qa);
+      jac8_pair(s2, B, pb, qb);
+      const double2 ga = gs[pa][qa], gb = gs[pb][qb];
+      const double apa = gs[pa][pa].x, aqa = gs[qa][qa].x, apb = gs[pb][pb].x, aqb = gs[qb][qb].x;
+      double2 g00 = gs[pa][pb], g01 = gs[pa][qb], g10 = gs[qa][pb], g11 = gs[qa][qb];
+      double2 w00 = ws[pa][pb], w01 = ws[pa][qb], w10 = ws[qa][pb], w11 = ws[qa][qb];
+      double ca, wra, wia, cb, wrb, wib;
+      jac_rotation(apa, aqa, ga.x, ga.y, tol, floor_g, ca, wra, wia);
+      jac_rotation(apb, aqb, gb.x, gb.y, tol, floor_g, cb, wrb, wib);
+      rot_pair(g00, g10, ca, wra, wia);
+      rot_pair(g01, g11, ca, wra, wia);
+      rot_pair(w00, w10, ca, wra, wia);
+      rot_pair(w01, w11, ca, wra, wia);
+      rot_pair(g00, g01, cb, wrb, -wib);
+      rot_pair(g10, g11, cb, wrb, -wib);
+      // every read of this step is issued before the first write
+      wave_lds_sync();
+      ws[pa][pb] = w00; ws[pa][qb] = w01; ws[qa][pb] = w10; ws[qa][qb] = w11;
+      gs[pa][pb] = g00; gs[pa][qb] = g01; gs[qa][pb] = g10; gs[qa][qb] = g11;
+      wave_lds_sync();
+    }
+    if (inner + 1 < max_inner) {
+      int f = 0;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int p = 2 * A + i, q = 2 * B + j;
+          if (p < q && jac_needs(gs[p][p].x, gs[q][q].x, gs[p][q], tol, floor_g)) f = 1;
+        }
+      if (__ballot(f) == 0ull) break;
+    }
+  }
+}
+
+// One round-robin step over blocks of 8 for every active sector: one
+// workgroup of 256 threads per block pair.  Visit rule, thresholds and
+// bookkeeping as in jacobi_block_step.
+__global__ void __launch_bounds__(256)
+jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiBlockWork* __restrict__ jb,
+                   int njb, int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
+                   JacobiOut* __restrict__ st, const int* __restrict__ perm, double* __restrict__ norm2,
+                   double tol_opt, int max_inner) {
+  __shared__ double2 xt[4][kJP8][33];
+  __shared__ double2 gs[kJP8][kJP8 + 1];
+  __shared__ double2 ws[kJP8][kJP8 + 1];
+  __shared__ double gmax;
+  __shared__ int vrow[kJP8];
+  __shared__ int4 anyf[2];
+  int parity = 0;
+  int lo = 0, hi = njb - 1;
+  const int pid = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jb[mid].pair_begin <= pid) lo = mid; else hi = mid - 1;
+  }
+  const JacobiBlockWork w = jb[lo];
+  if (step >= w.nb - 1) return;
+  const int sid = w.sector;
+  if (st[sid].converged) return;
+  const SectorWork sw = secs[sid];
+  const bool tall = sw.tall != 0;
+  const int n = tall ? sw.c : sw.r;
+  const int len = tall ? sw.r : sw.c;
+  double2* x = theta + sw.off;
+  const double tol = jac_tol(tol_opt, len);
+  const double floor_g = (double)len * DBL_EPSILON * DBL_EPSILON * st[sid].fro2;
+  int bi, bj;
+  rr_pair(step, pid - w.pair_begin, w.nb, bi, bj);
+  const int vI = bi * kJB8, vJ = bj * kJB8;
+  const int nI = max(0, min(kJB8, n - vI)), nJ = max(0, min(kJB8, n - vJ));
+  const int nv = nI + nJ;
+  const int tid = threadIdx.x;
+  if (nv < 2) return;
+  if (tid < kJP8) {
+    const int pos = tid < kJB8 ? vI + tid : vJ + (tid - kJB8);
+    const int lim = tid < kJB8 ? vI + nI : vJ + nJ;
+    vrow[tid] = pos < lim ? perm[sw.sig + pos] : -1;
+  }
+  __syncthreads();
+  bool fresh = false;
+  for (int pass = 0; pass < 2; ++pass) {
+    if (!fresh) {
+      jac8_gram(xt, gs, x, len, vrow);
+      if (tid == 0) atomicAdd(&st[sid].gram_units, (unsigned long long)nv * nv * len);
+    }
+    if (tid < 64) {
+      double m = tid < kJP8 ? gs[tid][tid].x : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+      if (tid == 0) gmax = m;
+    }
+    const bool need = jac8_any_above(gs, tol, floor_g, anyf, parity);
+    if (!need) break;
+    if (pass == 0 && tid == 0) atomicAdd(&st[sid].rot_this_sweep, 1);
+    {
+      const int r = tid >> 4, c = tid & 15;
+      ws[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+    const double ptol = pass == 0 ? fmax(tol, kJacLoose) : tol;
+    const double pfloor = pass == 0 ? fmax(floor_g, kJacNoise * DBL_EPSILON * gmax) : floor_g;
+    if (pass == 0 && !jac8_any_above(gs, ptol, pfloor, anyf, parity)) {
+      fresh = true;
+      continue;
+    }
+    if (tid < 64) jac8_gram_eig(gs, ws, ptol, pfloor, max_inner);
+    __syncthreads();
+    jac8_apply(xt, ws, x, len, vrow);
+    if (tall) jac8_apply(xt, ws, accbuf + sw.acc, n, vrow);
+    if (tid == 0) atomicAdd(&st[sid].apply_units, (unsigned long long)nv * nv * (len + (tall ? n : 0)));
+    fresh = false;
+    __syncthreads();
+    if (pass == 0) break;
+  }
+  __syncthreads();
+  if (tid < kJP8 && vrow[tid] >= 0) norm2[sw.sig + vrow[tid]] = gs[tid][tid].x;
+}
+
 // Scalar one-sided Jacobi sweeps on the vectors themselves, for the rare
 // sector the blocked sweeps leave unconverged.  One workgroup per listed
 // sector; each wavefront takes whole vector pairs of a round-robin step,
@@ -677,10 +973,16 @@ hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count
 
 hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiBlockWork* jb, int njb, int npairs,
                               int step, double2* theta, double2* acc, JacobiOut* st, const int* perm,
-                              double* norm2, double tol, int max_inner, hipStream_t s) {
+                              double* norm2, double tol, int max_inner, int block, hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_block_step, dim3(npairs), dim3(256), 0, s, secs, jb, njb, step, theta, acc,
-                     st, perm, norm2, tol, max_inner);
+  if (block == kJB8)
+    hipLaunchKernelGGL(jacobi_block_step8, dim3(npairs), dim3(256), 0, s, secs, jb, njb, step, theta, acc,
+                       st, perm, norm2, tol, max_inner);
+  else if (block == kJB)
+    hipLaunchKernelGGL(jacobi_block_step, dim3(npairs), dim3(256), 0, s, secs, jb, njb, step, theta, acc,
+                       st, perm, norm2, tol, max_inner);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ hipError_t launch_jacobi_init(const SectorWork* secs, const int* list, int count
                               double* norm2, hipStream_t s);
 hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiBlockWork* jb, int njb, int npairs,
                               int step, double2* theta, double2* acc, JacobiOut* st, const int* perm,
-                              double* norm2, double tol, int max_inner, hipStream_t s);
+                              double* norm2, double tol, int max_inner, int block, hipStream_t s);
 hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count, const JacobiOut* st,
                               int* perm, const double* norm2, hipStream_t s);
 hipError_t launch_jacobi_sweep_end(const int* list, int count, JacobiOut* st, int* active, hipStream_t s);

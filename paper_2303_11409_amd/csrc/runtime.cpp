@@ -430,6 +430,7 @@ struct BatchPlan {
   std::vector<int> jlist;                 // every sector id
   std::vector<JacobiBlockWork> jblocks;   // block schedule per sector
   int jpairs = 0, jmaxnb = 2, jmaxrows = 1;
+  int jblock = kJB8;                      // vectors per Jacobi block (8 or 16)
   std::vector<long long> sel_off;         // global sort scratch offsets
   long long sel_scratch = 0;
   int maxP = 1;
@@ -465,6 +466,7 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
   const int ng = (int)refs.size();
   const int d = refs[0].h->d;
   P.split = refs[0].h->opts.form == MPS_FORM_SPLIT_BF16X3;
+  P.jblock = refs[0].h->opts.jacobi_block == 0 ? kJacobiBlockDefault : refs[0].h->opts.jacobi_block;
   P.gates.resize(ng);
   P.gp.resize(ng);
   P.coef.clear();
@@ -704,8 +706,8 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
     P.gates[g] = gw;
     P.gp[g] = {s, gw.sec_begin, gw.sec_end};
   }
-  // blocked Jacobi schedule: min(r, c) vectors in blocks of kJB, block count
-  // even.  Block pairs are numbered heaviest sector first (longest vectors):
+  // blocked Jacobi schedule: min(r, c) vectors in blocks of P.jblock, block
+  // count even.  Block pairs are numbered heaviest sector first (longest vectors):
   // the dispatcher places workgroups in index order across the CUs, so the
   // slow pairs get a CU of their own and the light ones share.
   std::vector<int> jorder(P.secs.size());
@@ -716,7 +718,7 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
   for (int i : jorder) {
     const SectorWork& sw = P.secs[i];
     const int nv = std::min(sw.r, sw.c);
-    int nb = (nv + kJB - 1) / kJB;
+    int nb = (nv + P.jblock - 1) / P.jblock;
     nb += nb & 1;
     nb = std::max(nb, 2);
     P.jlist.push_back((int)i);
@@ -955,7 +957,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
       hipError_t ce = hipSuccess;
       for (int step = 0; step < P.jmaxnb - 1 && ce == hipSuccess; ++step)
         ce = launch_jacobi_step(d_secs, at<JacobiBlockWork>(h->plan, o_jblk), ns, P.jpairs, step, scaled, d_acc,
-                                d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, h->cap_st);
+                                d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, P.jblock, h->cap_st);
       const hipError_t ee = hipStreamEndCapture(h->cap_st, &graph);
       if (ce == hipSuccess) ce = ee;
       if (ce == hipSuccess) ce = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
@@ -980,7 +982,8 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
       } else {
         for (int step = 0; step < P.jmaxnb - 1; ++step)
           HIPCHK(launch_jacobi_step(d_secs, at<JacobiBlockWork>(h->plan, o_jblk), ns, P.jpairs, step, scaled,
-                                    d_acc, d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, h->st));
+                                    d_acc, d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, P.jblock,
+                                    h->st));
       }
       STCHK(tm.stop());
       h->stats.jacobi_launches += P.jmaxnb - 1;
@@ -1263,6 +1266,7 @@ void mps_default_opts(mps_opts* o) {
   o->select_scratch = 0;
   o->sweep_graph = 0;
   o->tile_tuning = 1;
+  o->jacobi_block = 0;
 }
 
 const char* mps_last_error(void) { return g_err.c_str(); }
@@ -1299,6 +1303,8 @@ mps_status create_impl(int L, int d, int n_photons, const int* bond_dim, const i
   if (o.sweep_graph != 0 && o.sweep_graph != 1) return fail(MPS_E_ARG, "sweep_graph must be 0 or 1");
   if (o.tile_tuning < 0 || o.tile_tuning > 1 + kSgVariants)
     return fail(MPS_E_ARG, "tile_tuning must lie in 0..%d", 1 + kSgVariants);
+  if (o.jacobi_block != 0 && o.jacobi_block != kJB8 && o.jacobi_block != kJB)
+    return fail(MPS_E_ARG, "jacobi_block must be 0, %d or %d", kJB8, kJB);
   if (!(o.cutoff >= 0.0) || !(o.zero_tol >= 0.0)) return fail(MPS_E_ARG, "cutoff and zero_tol must be >= 0");
   if (o.form != MPS_FORM_PLAIN_C128 && o.form != MPS_FORM_SPLIT_BF16X3) return fail(MPS_E_ARG, "unknown form %d", o.form);
   if (o.modulus != 0 && o.modulus != d)

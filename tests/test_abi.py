@@ -143,6 +143,22 @@ def test_diagnostic_options():
     assert "select_scratch" in lib.mps_last_error().decode()
 
 
+def test_jacobi_block_option():
+    """jacobi_block defaults to 0 (blocks of 16); only 0, 8 and 16 are accepted,
+    checked on the host."""
+    lib = binding.lib()
+    o = binding.mps_opts()
+    lib.mps_default_opts(C.byref(o))
+    assert o.jacobi_block == 0
+    h = C.c_void_p()
+    occ = (C.c_int * 4)(1, 0, 1, 0)
+    for bad in (-1, 4, 12, 32):
+        o.jacobi_block = bad
+        assert lib.mps_create_product(4, 3, occ, C.byref(o), None, C.byref(h)) == -1
+        assert "jacobi_block" in lib.mps_last_error().decode()
+    assert not h.value
+
+
 def test_last_leaks_argument_errors():
     lib = binding.lib()
     n = C.c_int(-1)

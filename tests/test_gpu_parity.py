@@ -36,8 +36,8 @@ def close_amps(got, ref, tol=TOL):
     return per
 
 
-def run_gpu(MPS, occ, d, gates, chi_max=0, cutoff=0.0, layered=False, layers=None):
-    m = MPS(occ, d, chi_max=chi_max, cutoff=cutoff)
+def run_gpu(MPS, occ, d, gates, chi_max=0, cutoff=0.0, layered=False, layers=None, jacobi_block=0):
+    m = MPS(occ, d, chi_max=chi_max, cutoff=cutoff, jacobi_block=jacobi_block)
     disc = []
     if layered:
         for lay in layers:
@@ -97,9 +97,11 @@ def test_random_small_circuits_vs_brute_force(mps_cls, seed):
     m.close()
 
 
-def test_truncated_brickwork_vs_oracle(mps_cls):
+@pytest.mark.parametrize("jacobi_block", [8, 16])
+def test_truncated_brickwork_vs_oracle(mps_cls, jacobi_block):
     cfg = circuits.config_brickwork(12, 6, "first", 3, 12, 10, 1e-12, 21, "t")
-    m, disc = run_gpu(mps_cls, cfg["occupation"], 3, cfg["gates"], chi_max=10, cutoff=1e-12)
+    m, disc = run_gpu(mps_cls, cfg["occupation"], 3, cfg["gates"], chi_max=10, cutoff=1e-12,
+                      jacobi_block=jacobi_block)
     ref = dense_mps.DenseMPS(cfg["occupation"], 3, chi_max=10, cutoff=1e-12).run(cfg["gates"])
     odisc = np.array([r.discarded for r in ref.records])
     assert min(r.margin for r in ref.records) > 1e-9
@@ -212,18 +214,20 @@ def test_vacuum_and_edges(mps_cls):
     m.close()
 
 
-def test_full_32_mode_circuit_vs_stored_oracle(mps_cls):
+@pytest.mark.parametrize("jacobi_block", [8, 16])
+def test_full_32_mode_circuit_vs_stored_oracle(mps_cls, jacobi_block):
     """The whole L=32, N=16, d=4, chi_max=512 circuit (496 gates, the benchmark
     workload) against the oracle's stored results (tests/golden, written by
     make_golden.py from oracle/ only): 1025 amplitudes, norm, every bond's charge
-    multiplicities, every gate's discarded weight, central Schmidt values."""
+    multiplicities, every gate's discarded weight, central Schmidt values; with
+    Jacobi blocks of 8 and of 16 vectors."""
     import json
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "L32_N16_d4_chi512.json")
     ref = json.load(open(path))
     cfg = circuits.config_plain_gpu()
     m, disc = run_gpu(mps_cls, cfg["occupation"], 4, None, chi_max=512, cutoff=1e-12, layered=True,
-                      layers=cfg["layers"])
+                      layers=cfg["layers"], jacobi_block=jacobi_block)
     # gates in layer order == stored order (the stored run applied them layer by layer)
     assert np.max(np.abs(disc - np.array(ref["discarded"]))) <= 1e-12
     for b in range(33):
