@@ -75,8 +75,6 @@ def measured_traffic(block: int):
     if block != t["jacobi_block"]:
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
-# vectors per Jacobi block when mps_opts.jacobi_block is 0
-JACOBI_BLOCK_DEFAULT = 16
 METRIC = "gate applies/s + sector-GEMM TFLOP/s at χ=2048 vs plain; p50/p99 latency"
 
 
@@ -477,7 +475,7 @@ def main() -> int:
     ap.add_argument("--serve-rate", type=float, default=200.0, help="serving form: arrivals per second")
     ap.add_argument("--serve-low-rate", type=float, default=0.5,
                     help="serving form: a second window at this rate, within the device's capacity (0 = skip)")
-    ap.add_argument("--serve-max-active", type=int, default=512,
+    ap.add_argument("--serve-max-active", type=int, default=64,
                     help="serving form: most requests active at once in the lane of the batching-mix circuits")
     ap.add_argument("--serve-max-large", type=int, default=16,
                     help="serving form: most requests active at once in the lane of the chi_max=1024 circuits")
@@ -487,7 +485,9 @@ def main() -> int:
     ap.add_argument("--no-tebd", action="store_true",
                     help="skip the Hamiltonian time-evolution workloads (XXZ, Bose-Hubbard)")
     ap.add_argument("--jacobi-block", type=int, default=0,
-                    help="vectors per Jacobi block of the headline circuit (0: the library default, 8; or 16)")
+                    help="vectors per Jacobi block of the headline circuit (0: chosen per update by the library; 8 or 16)")
+    ap.add_argument("--sweep-graph", type=int, default=0,
+                    help="headline circuit: 1 replays each Jacobi sweep from a captured HIP graph")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 256 MiB device-to-device copy three times (the "
                          "reference kernel for scaling HBM byte counters)")
@@ -515,7 +515,7 @@ def main() -> int:
 
     def new_state():
         return MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"], device=dev,
-                   jacobi_block=args.jacobi_block)
+                   jacobi_block=args.jacobi_block, sweep_graph=args.sweep_graph)
 
     def run(m):
         for sites, us in layers:
@@ -569,6 +569,8 @@ def main() -> int:
                     agg[k] = min(agg[k], v)
                 elif k == "max_discarded":
                     agg[k] = max(agg[k], v)
+                elif k in ("jacobi_block", "gemm_variant"):
+                    agg[k] = v
                 else:
                     agg[k] += v
     sampling = None
@@ -629,17 +631,26 @@ def main() -> int:
             "vs_plain": (g / el) / (args.steps * ngates / elapsed), "host_plan_s": plan_s}
         log(f"  {g / el:.1f} gate applies/s")
 
-    # dominant kernel: the blocked Jacobi step (one launch per round-robin step)
-    launches = max(agg["jacobi_launches"], 1)
-    per_launch_flops = agg["jacobi_flops"] / launches
-    avg_ms = agg["jacobi_ms"] / launches
+    # dominant kernel: the blocked Jacobi step (one launch per round-robin step);
+    # updates take blocks of 8 (jacobi_block_step8) or 16 (jacobi_block_step)
+    j8 = {"ms": agg["jacobi8_ms"], "launches": agg["jacobi8_launches"], "flops": agg["jacobi8_flops"]}
+    j16 = {"ms": agg["jacobi_ms"] - j8["ms"], "launches": agg["jacobi_launches"] - j8["launches"],
+           "flops": agg["jacobi_flops"] - j8["flops"]}
+    jblock = 8 if j8["ms"] >= j16["ms"] else 16
+    dom, other = (j8, j16) if jblock == 8 else (j16, j8)
+    launches = max(dom["launches"], 1)
+    per_launch_flops = dom["flops"] / launches
+    avg_ms = dom["ms"] / launches
     achieved = per_launch_flops / (avg_ms * 1e-3) / 1e12
-    jblock = args.jacobi_block or JACOBI_BLOCK_DEFAULT
+    kname = {8: "jacobi_block_step8", 16: "jacobi_block_step"}
     roofline = {"bound": "alu", "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(jblock),
-                "kernel": "jacobi_block_step8" if jblock == 8 else "jacobi_block_step", "jacobi_block": jblock,
+                "kernel": kname[jblock], "jacobi_block": jblock,
                 "avg_launch_ms": avg_ms,
-                "flops_per_launch": per_launch_flops, "launches": launches}
+                "flops_per_launch": per_launch_flops, "launches": launches,
+                "other_block_size": {"kernel": kname[24 - jblock], "launches": other["launches"],
+                                     "ms": other["ms"],
+                                     "tflops": other["flops"] / max(other["ms"], 1e-9) / 1e9}}
     props = torch.cuda.get_device_properties(0)
     value = args.steps * ngates / elapsed
     if args.chi2048_layers > 0:

@@ -147,12 +147,15 @@ typedef struct {
                                   diagnostic).  The products are bitwise the
                                   same for every shape. */
   int jacobi_block;            /* vectors per block of the blocked Jacobi SVD:
-                                  0 (default) = 16, or 8 or 16.  A block pair
-                                  of 2b vectors is orthogonalised per visit
-                                  through its 2b x 2b Gram matrix; smaller
-                                  blocks make shorter visits and more of them.
-                                  In a batch the first state's value serves
-                                  every state. */
+                                  8 or 16, or 0 (default): chosen per update
+                                  call, 8 when the longest vector has 320 or
+                                  more elements and the call has fewer pairs
+                                  of 16-vector blocks than twice the GPU's
+                                  compute units, else 16.  A block pair of 2b
+                                  vectors is orthogonalised per visit through
+                                  its 2b x 2b Gram matrix; smaller blocks make
+                                  shorter visits and more of them.  In a batch
+                                  the first state's value serves every state. */
 } mps_opts;
 
 /* Per-handle counters, accumulated since creation or mps_reset_stats.
@@ -195,6 +198,11 @@ typedef struct {
                                /*   shape of the products (new histogram key)  */
   int gemm_variant;            /* split form: tile shape of the last products  */
                                /*   launch: 0 64x64, 1 32x64, 2 64x32, 3 32x32 */
+  int jacobi_block;            /* vectors per Jacobi block of the last update  */
+                               /*   (8 or 16; see mps_opts.jacobi_block)       */
+  double jacobi8_ms, jacobi8_flops;  /* the share of jacobi_ms, jacobi_flops */
+  long long jacobi8_launches;  /*   and jacobi_launches from updates that used */
+                               /*   blocks of 8 (jacobi_block_step8)           */
 } mps_stats;
 
 /* Fill *o with the defaults: chi_max 0, cutoff 0, zero_tol 1e-13,

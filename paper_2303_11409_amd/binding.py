@@ -68,7 +68,8 @@ class mps_stats(C.Structure):
                 ("gemm_ms", C.c_double), ("gemm_launches", C.c_longlong),
                 ("gemm_mfma_flops", C.c_double), ("split_ms", C.c_double), ("leak_total", C.c_double),
                 ("graph_launches", C.c_longlong), ("host_plan_ms", C.c_double),
-                ("tile_tunings", C.c_longlong), ("gemm_variant", C.c_int)]
+                ("tile_tunings", C.c_longlong), ("gemm_variant", C.c_int), ("jacobi_block", C.c_int),
+                ("jacobi8_ms", C.c_double), ("jacobi8_flops", C.c_double), ("jacobi8_launches", C.c_longlong)]
 
 
 EXPORTS = ["mps_default_opts", "mps_create", "mps_create_product", "mps_create_product_charges",

@@ -185,7 +185,6 @@ struct CutOut {
 constexpr int kJB = 16;
 constexpr int kJP = 2 * kJB;
 constexpr int kJB8 = 8;
-constexpr int kJacobiBlockDefault = kJB;
 
 struct JacobiBlockWork {
   int sector;             // SectorWork index

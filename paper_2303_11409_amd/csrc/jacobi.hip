@@ -152,7 +152,7 @@ __device__ __forceinline__ void jac_fetch(double2 (&v)[kJChunkRegs], const doubl
   }
 }
 
-__device__ __forceinline__ void jac_stage(double2 (*xs)[33], const double2 (&v)[kJChunkRegs]) {
+__device__ __forceinline__ void jac_stage(double2 (*xs)[kJP + 2], const double2 (&v)[kJChunkRegs]) {
   const int cc = threadIdx.x & 31;
 #pragma unroll
   for (int k = 0; k < kJChunkRegs; ++k) xs[8 * k + (threadIdx.x >> 5)][cc] = v[k];
@@ -164,7 +164,7 @@ __device__ __forceinline__ void jac_stage(double2 (*xs)[33], const double2 (&v)[
 // The body may overwrite columns [c0, c0 + 32) of x (the loads in flight
 // are of later columns).
 template <class Body>
-__device__ __forceinline__ void jac_chunk_loop(double2 (*xs)[33], const double2* x, int len,
+__device__ __forceinline__ void jac_chunk_loop(double2 (*xs)[kJP + 2], const double2* x, int len,
                                                const int* vrow, Body&& body) {
   double2 ra[kJChunkRegs], rb[kJChunkRegs];
   jac_fetch(ra, x, len, 0, vrow);
@@ -188,7 +188,7 @@ __device__ __forceinline__ void jac_chunk_loop(double2 (*xs)[33], const double2*
 // chunks of 32, on the matrix cores: wave w computes the 16 x 16 output
 // quadrant (rows 16 (w / 2), columns 16 (w % 2)) of each chunk as three real
 // products per k-step (below).
-__device__ void jac_apply(double2 (*xs)[33], double2 (*ws)[kJP + 1], double2* __restrict__ x,
+__device__ void jac_apply(double2 (*xs)[kJP + 2], double2 (*ws)[kJP + 2], double2* __restrict__ x,
                           int len, const int* vrow) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int R = (wave >> 1) * 16, Cq = (wave & 1) * 16;
@@ -221,7 +221,7 @@ __device__ void jac_apply(double2 (*xs)[33], double2 (*ws)[kJP + 1], double2* __
 // Gr's diagonal quadrants give both triangles with different rounding;
 // every decision must see one value per pair, so gs is made exactly
 // Hermitian from its upper triangle.  M passes through xs.
-__device__ void jac_gram(double2 (*xs)[33], double2 (*gs)[kJP + 1], const double2* x, int len,
+__device__ void jac_gram(double2 (*xs)[kJP + 2], double2 (*gs)[kJP + 2], const double2* x, int len,
                          const int* vrow) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int P = wave >= 2 ? 16 : 0, Q = (wave == 1 || wave == 2) ? 16 : 0;
@@ -305,7 +305,7 @@ __device__ __forceinline__ bool jac_needs(double al, double be, double2 g, doubl
 // True if any off-diagonal pair of the Hermitian gs is above the threshold:
 // thread t checks the upper-triangle entries of its 2 x 2 block (rows
 // 2 (t / 16), columns 2 (t % 16)).  Uniform across the workgroup.
-__device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 1], double tol, double floor_g,
+__device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 2], double tol, double floor_g,
                                               int4* anyf, int& parity) {
   const int p0 = 2 * (threadIdx.x >> 4), q0 = 2 * (threadIdx.x & 15);
   int f = 0;
@@ -331,12 +331,12 @@ __device__ __forceinline__ bool jac_any_above(double2 (*gs)[kJP + 1], double tol
 // parallel test over all pairs replaces the sweep that would find nothing to
 // rotate (it would leave G and W unchanged); after the last allowed sweep the
 // test is skipped.  The final G is left in gs.
-__device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*g1)[kJP + 1], double2 (*ws)[kJP + 1],
+__device__ void jac_gram_eig(double2 (*gs)[kJP + 2], double2 (*g1)[kJP + 2], double2 (*ws)[kJP + 2],
                              double tol, double floor_g, int max_inner, int4* anyf, int& parity) {
   const int tid = threadIdx.x;
   const int A = tid >> 4, B = tid & 15;
-  double2 (*cur)[kJP + 1] = gs;
-  double2 (*nxt)[kJP + 1] = g1;
+  double2 (*cur)[kJP + 2] = gs;
+  double2 (*nxt)[kJP + 2] = g1;
   for (int inner = 0; inner < max_inner; ++inner) {
     for (int s2 = 0; s2 < kJP - 1; ++s2) {
       int pa, qa, pb, qb;
@@ -362,7 +362,7 @@ __device__ void jac_gram_eig(double2 (*gs)[kJP + 1], double2 (*g1)[kJP + 1], dou
       nxt[pa][pb] = g00; nxt[pa][qb] = g01; nxt[qa][pb] = g10; nxt[qa][qb] = g11;
       // every read of cur in this step precedes the barrier, so the next step may overwrite it
       __syncthreads();
-      double2 (*t)[kJP + 1] = cur;
+      double2 (*t)[kJP + 2] = cur;
       cur = nxt;
       nxt = t;
     }
@@ -395,10 +395,14 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
                   int njb, int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
                   JacobiOut* __restrict__ st, const int* __restrict__ perm, double* __restrict__ norm2,
                   double tol_opt, int max_inner) {
-  // xs stages column chunks of the vectors; during the eig it is the second G buffer
-  __shared__ double2 xs[kJP][33];
-  __shared__ double2 gs[kJP][kJP + 1];
-  __shared__ double2 ws[kJP][kJP + 1];
+  // xs stages column chunks of the vectors; during the eig it is the second G
+  // buffer.  Rows are padded by two elements: with a stride of kJP + 2 the
+  // entries one round-robin step reads fall on more distinct LDS banks than
+  // with kJP + 1 (whose pair entries (p, q), p + q fixed by the step, share
+  // few banks).
+  __shared__ double2 xs[kJP][kJP + 2];
+  __shared__ double2 gs[kJP][kJP + 2];
+  __shared__ double2 ws[kJP][kJP + 2];
   __shared__ double gmax;
   __shared__ int vrow[kJP];
   __shared__ int4 anyf[2];

@@ -135,7 +135,7 @@ struct PinBuf {
   size_t cap = 0;
 };
 
-enum Kind { K_THETA = 0, K_SELECT, K_UPDATE, K_JACOBI, K_JACOBI_AUX, K_GEMM, K_SPLIT };
+enum Kind { K_THETA = 0, K_SELECT, K_UPDATE, K_JACOBI, K_JACOBI8, K_JACOBI_AUX, K_GEMM, K_SPLIT };
 
 struct Pending {
   int kind;
@@ -159,6 +159,7 @@ struct mps_state {
   int L = 0, d = 0, N = 0;
   int mod = 0;                   // 0: U(1) particle number; n: particle number mod n (d == n)
   int device = 0;                // the GPU current when the handle was created
+  int cus = 256;                 // compute units of that GPU
   ChargeRule rule;               // charges of the local states (U(1), Z_n, or two U(1) components)
   int ncomp = 1;                 // charge components packed into one key (1 or 2)
   int radix = 0;                 // ncomp == 2: key = c1 * radix + c2
@@ -301,6 +302,10 @@ mps_status drain_events(mps_state* h) {
       case K_THETA: h->stats.theta_ms += ms; break;
       case K_SELECT: h->stats.select_ms += ms; break;
       case K_JACOBI: h->stats.jacobi_ms += ms; break;
+      case K_JACOBI8:
+        h->stats.jacobi_ms += ms;
+        h->stats.jacobi8_ms += ms;
+        break;
       case K_JACOBI_AUX: h->stats.jacobi_aux_ms += ms; break;
       case K_GEMM: h->stats.gemm_ms += ms; break;
       case K_SPLIT: h->stats.split_ms += ms; break;
@@ -462,11 +467,33 @@ struct GateRef {
   const mps_z* g4;
 };
 
+// Vectors per Jacobi block when the options leave it open.  A round-robin
+// step lasts as long as its slowest block-pair visit, and a visit of 16
+// vectors has about a quarter of the Gram and rotation work of a visit of 32
+// and an eig of 15 steps instead of 31; but blocks of 8 double the steps of a
+// sweep and the passes over the vectors.  Measured: blocks of 8 pay when the
+// longest vectors are long (the 32-mode chi = 512 circuit, up to ~430
+// elements: 0.755 s against 0.792 s) and the batch leaves room on the chip
+// (fewer 32-vector block pairs than two per compute unit); with vectors of
+// 256 (the Z_2 quench at chi = 256) or a full chip (batches of circuits, the
+// chi = 2048 layer) blocks of 16 are faster.
+int auto_jacobi_block(const std::vector<SectorWork>& secs, int cus) {
+  long long pairs = 0;
+  int maxlen = 0;
+  for (const SectorWork& sw : secs) {
+    int nb = (std::min(sw.r, sw.c) + kJB - 1) / kJB;
+    nb += nb & 1;
+    pairs += std::max(nb, 2) / 2;
+    maxlen = std::max(maxlen, std::max(sw.r, sw.c));
+  }
+  return (maxlen >= 320 && pairs < 2LL * cus) ? kJB8 : kJB;
+}
+
 mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
   const int ng = (int)refs.size();
   const int d = refs[0].h->d;
   P.split = refs[0].h->opts.form == MPS_FORM_SPLIT_BF16X3;
-  P.jblock = refs[0].h->opts.jacobi_block == 0 ? kJacobiBlockDefault : refs[0].h->opts.jacobi_block;
+  P.jblock = refs[0].h->opts.jacobi_block;
   P.gates.resize(ng);
   P.gp.resize(ng);
   P.coef.clear();
@@ -710,6 +737,7 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
   // count even.  Block pairs are numbered heaviest sector first (longest vectors):
   // the dispatcher places workgroups in index order across the CUs, so the
   // slow pairs get a CU of their own and the light ones share.
+  if (P.jblock == 0) P.jblock = auto_jacobi_block(P.secs, refs[0].h->cus);
   std::vector<int> jorder(P.secs.size());
   for (size_t i = 0; i < jorder.size(); ++i) jorder[i] = (int)i;
   std::stable_sort(jorder.begin(), jorder.end(), [&](int x, int y) {
@@ -798,6 +826,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   BatchPlan P;
   STCHK(plan_batch(refs, P));
   STCHK(check_device_limits(h, P));
+  for (const GateRef& r : refs) r.h->stats.jacobi_block = P.jblock;
   const int ns = (int)P.secs.size();
 
   // workspaces
@@ -974,7 +1003,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     int still_active = 1;
     int issued = 0;
     for (int sweep = 0; sweep < blocked; ++sweep) {
-      Timer tm(h, K_JACOBI);
+      Timer tm(h, P.jblock == kJB8 ? K_JACOBI8 : K_JACOBI);
       STCHK(tm.start());
       if (gexec) {
         HIPCHK(hipGraphLaunch(gexec, h->st));
@@ -987,6 +1016,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
       }
       STCHK(tm.stop());
       h->stats.jacobi_launches += P.jmaxnb - 1;
+      if (P.jblock == kJB8) h->stats.jacobi8_launches += P.jmaxnb - 1;
       Timer ta(h, K_JACOBI_AUX);
       STCHK(ta.start());
       HIPCHK(launch_jacobi_sweep_end(d_jlist, ns, d_jst, d_active, h->st));
@@ -1060,7 +1090,9 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     gs.sectors += 1;
     gs.sweeps += jst[s].sweeps;
     gs.rotations += jst[s].rotations;
-    gs.jacobi_flops += 8.0 * double(jst[s].gram_units) + 8.0 * double(jst[s].apply_units);
+    const double jf = 8.0 * double(jst[s].gram_units) + 8.0 * double(jst[s].apply_units);
+    gs.jacobi_flops += jf;
+    if (P.jblock == kJB8) gs.jacobi8_flops += jf;
   }
   h->stats.theta_flops += P.theta_flops;
 
@@ -1409,6 +1441,8 @@ mps_status create_impl(int L, int d, int n_photons, const int* bond_dim, const i
   if (dev) h->dev = *dev;
   h->st = static_cast<hipStream_t>(h->dev.stream);
   if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+  if (hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || h->cus < 1)
+    h->cus = 256;
   h->bonds = bonds;
   h->stats.min_margin = INFINITY;
   mps_status s = compute_caps(h);

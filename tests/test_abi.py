@@ -144,7 +144,7 @@ def test_diagnostic_options():
 
 
 def test_jacobi_block_option():
-    """jacobi_block defaults to 0 (blocks of 16); only 0, 8 and 16 are accepted,
+    """jacobi_block defaults to 0 (chosen per update); only 0, 8 and 16 are accepted,
     checked on the host."""
     lib = binding.lib()
     o = binding.mps_opts()
