@@ -37,21 +37,22 @@ if ROOT not in sys.path:
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/clk
 
-# HBM bytes per launch of jacobi_block_step on this workload, from two
+# HBM bytes per launch of the dominant Jacobi step kernel on this workload
+# (jacobi_block_step8: the circuit's updates take blocks of 8), from two
 # rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline
 # --batch-copies 0 --mix-circuits 0 --chi2048-layers 0 --serve-seconds 0
 # --samples 4096 --no-tebd`
-# (FETCH_SIZE, WRITE_SIZE; mean over the 20988 launches) scaled by the same
+# (FETCH_SIZE, WRITE_SIZE; mean over the 43146 launches) scaled by the same
 # counters on a plain 256 MiB copy (`bench.py --copy-probe`: FETCH_SIZE reads
 # 131085.2 KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99980
-# and writes by 1).  Valid only for the Jacobi source (csrc/jacobi.hip) and the
-# inner sweep count per visit (kMaxInnerSweeps in csrc/runtime.cpp) it was
-# taken on.
+# and writes by 1).  Valid only for the Jacobi source (csrc/jacobi.hip), the
+# inner sweep count per visit (kMaxInnerSweeps in csrc/runtime.cpp) and the
+# block size it was taken on.
 MEASURED_TRAFFIC = {
-    "kernels_sha256": "558b22d3ccbe4b8ba15a38d9b96ed87765332668e867b033aaeee704b95bcb81",
+    "kernels_sha256": "8a09b0b35d436542976c32865a146013f6c7c119e0c2dfb4ce48f41c7f26da81",
     "max_inner": 1,
-    "jacobi_block": 16,
-    "fetch_kib": 15566.3, "write_kib": 19929.3,
+    "jacobi_block": 8,
+    "fetch_kib": 15295.7, "write_kib": 20491.8,
     "fetch_scale": 262144.0 / 131085.2, "write_scale": 1.0,
 }
 

@@ -2025,7 +2025,7 @@ mps_status sample_chunk(mps_state* h, const std::vector<double2*>& eb, int cnt, 
   const size_t stage_list = (size_t)cnt * sizeof(int) + align256((size_t)maxsec * sizeof(SampleGroup)) +
                             2 * align256((size_t)maxsec * d * sizeof(GemmWork)) + 1024;
   const size_t stage_init = (size_t)cnt * L * sizeof(double) + 2 * (size_t)cnt * sizeof(double2) + 1024;
-  STCHK(ensure_pin(h->stage_misc, std::max(stage_list, stage_init) + (size_t)cnt * L * sizeof(int) +
+  STCHK(ensure_pin(h->stage_misc, align256(std::max(stage_list, stage_init)) + (size_t)cnt * L * sizeof(int) +
                                       (size_t)cnt * sizeof(double) + 1024));
   char* stg = static_cast<char*>(h->stage_misc.p);
   char* dev = static_cast<char*>(h->samp.p);
@@ -2050,10 +2050,20 @@ mps_status sample_chunk(mps_state* h, const std::vector<double2*>& eb, int cnt, 
     const Bond& B0 = h->bonds[s];
     const Bond& B1 = h->bonds[s + 1];
     const int ldb = B1.dim(), lde = B0.dim();
-    // groups by charge, ascending; sample ids ascending inside a group
+    // groups by charge, ascending; sample ids ascending inside a group (a
+    // counting sort over the bond's charge positions)
     std::vector<int> order(cnt);
-    for (int j = 0; j < cnt; ++j) order[j] = j;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cur[x] < cur[y]; });
+    {
+      const int nq = (int)B1.charge.size();
+      std::vector<int> pos(cnt), start(nq + 1, 0);
+      for (int j = 0; j < cnt; ++j) {
+        pos[j] = B1.find(cur[j]);
+        if (pos[j] < 0) return fail(MPS_E_ARG, "internal: sample charge %d missing on bond %d", cur[j], s + 1);
+        ++start[pos[j] + 1];
+      }
+      for (int q = 0; q < nq; ++q) start[q + 1] += start[q];
+      for (int j = 0; j < cnt; ++j) order[start[pos[j]]++] = j;
+    }
     std::vector<SampleGroup> groups;
     std::vector<GemmWork> g1, g2;
     int nt1 = 0, nt2 = 0, ptiles = 0;
@@ -2135,8 +2145,11 @@ mps_status sample_chunk(mps_state* h, const std::vector<double2*>& eb, int cnt, 
                               reinterpret_cast<const double2*>(dev + o_x), reinterpret_cast<const double*>(dev + o_u),
                               L, s, slots, cnt, reinterpret_cast<int*>(dev + o_occ),
                               reinterpret_cast<double*>(dev + o_pr), reinterpret_cast<int*>(dev + o_pick), h->st));
-    HIPCHK(hipMemcpyAsync(picks.data(), dev + o_pick, (size_t)cnt * sizeof(int), hipMemcpyDeviceToHost, h->st));
+    // the draws come back through pinned memory past the list region
+    int* pk_host = reinterpret_cast<int*>(stg + align256(stage_list));
+    HIPCHK(hipMemcpyAsync(pk_host, dev + o_pick, (size_t)cnt * sizeof(int), hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
+    std::memcpy(picks.data(), pk_host, (size_t)cnt * sizeof(int));
     for (int j = 0; j < cnt; ++j) {
       if (picks[j] < 0) return fail(MPS_E_NUMERIC, "sample %d met a vanished or non-finite marginal", j);
       cur[j] = zn ? (cur[j] + picks[j]) % zn : cur[j] + h->rule.step[picks[j]];
