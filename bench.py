@@ -434,8 +434,10 @@ def precision_full(MPS, dev, circuits):
         m.set_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for lay in cfg["layers"]:
+        for li, lay in enumerate(cfg["layers"]):
             m.apply_layer([g.site for g in lay], [g.u for g in lay])
+            if li % 16 == 15:
+                log(f"  {key}: layer {li + 1}/{len(cfg['layers'])}, {time.perf_counter() - t0:.1f} s")
         m.sync()
         el = time.perf_counter() - t0
         st = m.stats()
