@@ -351,13 +351,16 @@ mps_status mps_norm_noalloc(mps_t h, double* norm2);
  *   occ    out, count*L row-major occupations;
  *   prob   out, may be NULL: |c_i|^2 / <psi|psi> of each drawn pattern.
  * All samples advance together, one mode per round; the samples on one
- * charge share the products with that charge's blocks.  The left
+ * charge share the products with that charge's blocks, and each round is
+ * planned on the device (the host waits once per call).  Bonds may carry at
+ * most 1024 charges.  The left
  * environments of every bond (as many complex entries as the squared bond
  * dimensions, summed: about the size of the state) and the rounds' buffers
  * (about 10 vectors of the largest charge block per sample, at most 8192
  * samples at a time) are held in device memory during the call only.
- * Errors: MPS_E_ARG (a uniform outside [0, 1)), MPS_E_NUMERIC (a vanished or
- * non-finite marginal), MPS_E_NOMEM, MPS_E_DEVICE. */
+ * Errors: MPS_E_ARG (a uniform outside [0, 1), more than 1024 charges on a
+ * bond), MPS_E_NUMERIC (a vanished or non-finite marginal; occ and prob are
+ * then undefined), MPS_E_NOMEM, MPS_E_DEVICE. */
 mps_status mps_sample(mps_t h, int count, const double* uniforms, int* occ, double* prob);
 
 /* Bookkeeping of bond `bond` (0..L): its distinct charges in ascending

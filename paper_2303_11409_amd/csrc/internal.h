@@ -150,7 +150,27 @@ struct SampleGroup {
   int tile0;              // first workgroup of the group in the draw kernel (16 samples each)
   long long voff;
   int loc[kMaxD], nr[kMaxD];
+  int pos[kMaxD];         // charge position on bond s of candidate k's block
   long long woff[kMaxD];
+};
+
+// The fixed part of a group, per charge position q of bond s+1 (the sampler
+// plans each round on the device from these and the samples' positions):
+// the block of q (nc rows, frame offset off1 on bond s+1) and, for every
+// local state with a block on bond s, that block's position, rows and frame
+// offset on bond s.
+struct SampleCand {
+  int nc, off1, nout;
+  int loc[kMaxD], pos[kMaxD], nr[kMaxD], off0[kMaxD];
+};
+
+// Charge positions per bond the sampler's device plan handles (LDS counters).
+constexpr int kMaxSampleCharges = 1024;
+
+// Per-round totals the device plan writes for the launches that follow
+// (whose grids are host-side upper bounds), and a sticky failure flag.
+struct SampleCounts {
+  int nt1, nt2, ptiles, failed;
 };
 
 // New-row descriptor for the update of B[s+1] and lambda[s+1].

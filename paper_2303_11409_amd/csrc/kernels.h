@@ -49,7 +49,9 @@ hipError_t launch_update_rows(const RowWork* rows, int nrows, const SectorWork* 
 hipError_t launch_zero_fill(double2* const* ptrs, const long long* counts, int nranges,
                             long long maxcount, hipStream_t st);
 
-hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_t st);
+// total (optional): a device count of the tiles to run, for lists planned on
+// the device (ntiles is then an upper bound).
+hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_t st, const int* total = nullptr);
 // Precision form: split-BF16 charge-triple products into the complex64
 // scratch, then the gate mix into the Theta workspaces.
 hipError_t launch_split_planes(const SplitPlanes* plans, int nplan, int ntiles, const int* ktab,
@@ -72,12 +74,20 @@ hipError_t launch_amplitude(const double2* const* sites, const int* ld, const in
 // The sampler's round for one mode (sample.hip): gather of every group's
 // vectors from the per-sample slots (column j of the maxblk x ld_slot slot
 // matrix), then, after the two products, the draw of every sample.
+// One round's plan on the device (one workgroup; nq <= kMaxSampleCharges):
+// groups, product lists (nq * kMaxD entries each) and counts from the
+// samples' charge positions on bond s+1.
+hipError_t launch_sample_plan(const SampleCand* cand, int nq, const int* pos, int cnt, const double2* site, int ldb,
+                              const double2* env, int lde, double2* vbuf, double2* wbuf, double2* xbuf, int* ids,
+                              SampleGroup* groups, GemmWork* g1, GemmWork* g2, SampleCounts* counts, hipStream_t st);
 hipError_t launch_sample_gather(const SampleGroup* groups, int ngroups, long long maxelems, const int* ids,
                                 const double2* slots, int ld_slot, double2* vbuf, hipStream_t st);
-// ntiles: sum over groups of ceil(ng / 16) (tile0 of each group: its first).
+// ntiles: an upper bound of sum over groups of ceil(ng / 16); the true count
+// is counts->ptiles.  Writes every sample's new charge position into pos.
 hipError_t launch_sample_pick(const SampleGroup* groups, int ngroups, int ntiles, const int* ids,
                               const double2* wbuf, const double2* xbuf, const double* uni, int L, int s,
-                              double2* slots, int ld_slot, int* occ, double* prob, int* pick_out, hipStream_t st);
+                              double2* slots, int ld_slot, int* occ, double* prob, int* pos, SampleCounts* counts,
+                              hipStream_t st);
 
 hipError_t launch_gather_cols(const double2* src, int lds, double2* dst, int ldd, int rows,
                               const int* map, int ncols, hipStream_t st);

@@ -252,12 +252,15 @@ zero_fill_kernel(double2* const* __restrict__ ptrs, const long long* __restrict_
 // ---------------------------------------------------------------------------
 // Generic batched complex GEMM, 32 x 32 tiles, k-chunks of 16 through LDS.
 __global__ void __launch_bounds__(256)
-zgemm_kernel(const GemmWork* __restrict__ probs, int nprob) {
+zgemm_kernel(const GemmWork* __restrict__ probs, int nprob, const int* __restrict__ total) {
   __shared__ double2 as[kGemmTile][17];
   __shared__ double2 bs[16][kGemmTile + 1];
-  // locate the problem of this tile
-  int lo = 0, hi = nprob - 1;
   const int tile = blockIdx.x;
+  // a list planned on the device: the grid is an upper bound, *total the tiles
+  if (total && tile >= *total) return;
+  // locate the problem of this tile (problems without tiles are never found:
+  // the last problem whose first tile is <= tile has it)
+  int lo = 0, hi = nprob - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (probs[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
@@ -441,9 +444,9 @@ hipError_t launch_zero_fill(double2* const* ptrs, const long long* counts, int n
   return hipGetLastError();
 }
 
-hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_t st) {
+hipError_t launch_zgemm(const GemmWork* probs, int nprob, int ntiles, hipStream_t st, const int* total) {
   if (nprob <= 0 || ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(zgemm_kernel, dim3(ntiles), dim3(256), 0, st, probs, nprob);
+  hipLaunchKernelGGL(zgemm_kernel, dim3(ntiles), dim3(256), 0, st, probs, nprob, total);
   return hipGetLastError();
 }
 

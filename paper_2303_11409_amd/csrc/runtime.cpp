@@ -1996,168 +1996,134 @@ namespace {
 constexpr int kSampleChunk = 8192;
 
 // `cnt` samples with the environments eb already built: one round per mode,
-// from the last to the first (see sample.hip).
+// from the last to the first (see sample.hip).  Each round is planned on the
+// device from the samples' charge positions, so all rounds are enqueued
+// without waiting and the host synchronises once at the end.
 mps_status sample_chunk(mps_state* h, const std::vector<double2*>& eb, int cnt, const double* uniforms,
                         int* occ, double* prob) {
   const int L = h->L, d = h->d, zn = h->mod;
-  int maxblk = 1, maxsec = 1;
+  // fixed candidate tables of every round and upper bounds of its grids
+  int maxblk = 1, maxq = 1;
   for (int b = 0; b <= L; ++b) {
     for (int c : h->bonds[b].count) maxblk = std::max(maxblk, c);
-    maxsec = std::max(maxsec, (int)h->bonds[b].charge.size());
+    maxq = std::max(maxq, (int)h->bonds[b].charge.size());
+  }
+  if (maxq > kMaxSampleCharges) return fail(MPS_E_ARG, "more than %d charges on a bond", kMaxSampleCharges);
+  std::vector<SampleCand> cand;
+  std::vector<size_t> cand_off(L);
+  std::vector<int> ub_gemm(L), ub_pick(L);
+  std::vector<long long> ub_elems(L);
+  const long long ctiles = (cnt + kGemmTile - 1) / kGemmTile;
+  for (int s = 0; s < L; ++s) {
+    const Bond& B0 = h->bonds[s];
+    const Bond& B1 = h->bonds[s + 1];
+    cand_off[s] = cand.size();
+    long long maxrt = 0, sumrt = 0;
+    int maxnc = 1;
+    for (size_t q = 0; q < B1.charge.size(); ++q) {
+      const int c = B1.charge[q];
+      SampleCand sc{};
+      sc.nc = B1.count[q];
+      sc.off1 = B1.off[q];
+      long long rt = 0;
+      for (int i = 0; i < d; ++i) {
+        const int c2 = zn ? (c + i) % zn : c + h->rule.step[i];
+        const int ri = B0.find(c2);
+        if (ri < 0) continue;
+        sc.loc[sc.nout] = i;
+        sc.pos[sc.nout] = ri;
+        sc.nr[sc.nout] = B0.count[ri];
+        sc.off0[sc.nout] = B0.off[ri];
+        rt += (B0.count[ri] + kGemmTile - 1) / kGemmTile;
+        ++sc.nout;
+      }
+      maxrt = std::max(maxrt, rt);
+      sumrt += rt;
+      maxnc = std::max(maxnc, sc.nc);
+      cand.push_back(sc);
+    }
+    // sum_q rt_q ceil(ng_q / T) <= max_q rt_q ceil(cnt / T) + sum_q rt_q
+    const long long ub = maxrt * ctiles + sumrt;
+    if (ub > INT_MAX) return fail(MPS_E_ARG, "sampling round %d too large", s);
+    ub_gemm[s] = (int)ub;
+    ub_pick[s] = (cnt + 15) / 16 + (int)B1.charge.size();
+    ub_elems[s] = (long long)maxnc * cnt;
   }
   const size_t vec = (size_t)maxblk * cnt;        // one vector of the largest block per sample
   Packer pk;
-  const size_t o_u = pk.add(uniforms, (size_t)cnt * L * sizeof(double));
+  const size_t o_u = pk.add(nullptr, (size_t)cnt * L * sizeof(double));
   const size_t o_occ = pk.add(nullptr, (size_t)cnt * L * sizeof(int));
   const size_t o_pr = pk.add(nullptr, (size_t)cnt * sizeof(double));
-  const size_t o_pick = pk.add(nullptr, (size_t)cnt * sizeof(int));
+  const size_t o_pos = pk.add(nullptr, (size_t)cnt * sizeof(int));
+  const size_t o_cnt = pk.add(nullptr, sizeof(SampleCounts));
+  const size_t o_cand = pk.add(nullptr, cand.size() * sizeof(SampleCand));
   const size_t o_slot = pk.add(nullptr, vec * sizeof(double2));
   const size_t o_v = pk.add(nullptr, vec * sizeof(double2));
   const size_t o_w = pk.add(nullptr, (size_t)d * vec * sizeof(double2));
   const size_t o_x = pk.add(nullptr, (size_t)d * vec * sizeof(double2));
   const size_t o_ids = pk.add(nullptr, (size_t)cnt * sizeof(int));
-  const size_t o_grp = pk.add(nullptr, (size_t)maxsec * sizeof(SampleGroup));
-  const size_t o_g1 = pk.add(nullptr, (size_t)maxsec * d * sizeof(GemmWork));
-  const size_t o_g2 = pk.add(nullptr, (size_t)maxsec * d * sizeof(GemmWork));
+  const size_t o_grp = pk.add(nullptr, (size_t)maxq * sizeof(SampleGroup));
+  const size_t o_g1 = pk.add(nullptr, (size_t)maxq * kMaxD * sizeof(GemmWork));
+  const size_t o_g2 = pk.add(nullptr, (size_t)maxq * kMaxD * sizeof(GemmWork));
   STCHK(ensure(h, h->samp, pk.total));
   // the previous staging use (the environments' lists) may still be in flight
   HIPCHK(hipStreamSynchronize(h->st));
-  const size_t stage_list = (size_t)cnt * sizeof(int) + align256((size_t)maxsec * sizeof(SampleGroup)) +
-                            2 * align256((size_t)maxsec * d * sizeof(GemmWork)) + 1024;
-  const size_t stage_init = (size_t)cnt * L * sizeof(double) + 2 * (size_t)cnt * sizeof(double2) + 1024;
-  STCHK(ensure_pin(h->stage_misc, align256(std::max(stage_list, stage_init)) + (size_t)cnt * L * sizeof(int) +
-                                      (size_t)cnt * sizeof(double) + 1024));
+  // inputs, laid out as on the device from o_u to o_slot (the initial vector 1
+  // of every sample, on the single charge of bond L, goes to row 0 of the slots)
+  const size_t head = o_slot + (size_t)cnt * sizeof(double2);
+  const size_t tail_out =
+      align256((size_t)cnt * L * sizeof(int)) + align256((size_t)cnt * sizeof(double)) + sizeof(SampleCounts);
+  STCHK(ensure_pin(h->stage_misc, std::max(head, tail_out)));
   char* stg = static_cast<char*>(h->stage_misc.p);
-  char* dev = static_cast<char*>(h->samp.p);
-  double2* slots = reinterpret_cast<double2*>(dev + o_slot);
-  // initial state: the vector 1 on the single charge of bond L, probability 1
-  {
-    std::memcpy(stg, uniforms, (size_t)cnt * L * sizeof(double));
-    double2* one = reinterpret_cast<double2*>(stg + align256((size_t)cnt * L * sizeof(double)));
-    double* pones = reinterpret_cast<double*>(one + cnt);
-    for (int j = 0; j < cnt; ++j) {
-      one[j] = make_double2(1.0, 0.0);
-      pones[j] = 1.0;
-    }
-    HIPCHK(hipMemcpyAsync(dev + o_u, stg, (size_t)cnt * L * sizeof(double), hipMemcpyHostToDevice, h->st));
-    HIPCHK(hipMemcpyAsync(slots, one, (size_t)cnt * sizeof(double2), hipMemcpyHostToDevice, h->st));
-    HIPCHK(hipMemcpyAsync(dev + o_pr, pones, (size_t)cnt * sizeof(double), hipMemcpyHostToDevice, h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
+  std::memset(stg, 0, head);
+  std::memcpy(stg + o_u, uniforms, (size_t)cnt * L * sizeof(double));
+  double* pones = reinterpret_cast<double*>(stg + o_pr);
+  double2* vones = reinterpret_cast<double2*>(stg + o_slot);
+  for (int j = 0; j < cnt; ++j) {
+    pones[j] = 1.0;
+    vones[j] = make_double2(1.0, 0.0);
   }
-  std::vector<int> cur(cnt, 0);                    // charge of bond s+1 of every sample (bond L: 0)
-  std::vector<int> picks(cnt);
+  std::memcpy(stg + o_cand, cand.data(), cand.size() * sizeof(SampleCand));
+  char* dev = static_cast<char*>(h->samp.p);
+  HIPCHK(hipMemcpyAsync(dev, stg, head, hipMemcpyHostToDevice, h->st));
+  int* d_pos = reinterpret_cast<int*>(dev + o_pos);
+  SampleCounts* d_cnt = reinterpret_cast<SampleCounts*>(dev + o_cnt);
+  double2* slots = reinterpret_cast<double2*>(dev + o_slot);
+  double2* vbuf = reinterpret_cast<double2*>(dev + o_v);
+  double2* wbuf = reinterpret_cast<double2*>(dev + o_w);
+  double2* xbuf = reinterpret_cast<double2*>(dev + o_x);
+  int* d_ids = reinterpret_cast<int*>(dev + o_ids);
+  SampleGroup* d_grp = reinterpret_cast<SampleGroup*>(dev + o_grp);
+  GemmWork* d_g1 = reinterpret_cast<GemmWork*>(dev + o_g1);
+  GemmWork* d_g2 = reinterpret_cast<GemmWork*>(dev + o_g2);
+  const SampleCand* d_cand = reinterpret_cast<const SampleCand*>(dev + o_cand);
   for (int s = L - 1; s >= 0; --s) {
     const Bond& B0 = h->bonds[s];
     const Bond& B1 = h->bonds[s + 1];
-    const int ldb = B1.dim(), lde = B0.dim();
-    // groups by charge, ascending; sample ids ascending inside a group (a
-    // counting sort over the bond's charge positions)
-    std::vector<int> order(cnt);
-    {
-      const int nq = (int)B1.charge.size();
-      std::vector<int> pos(cnt), start(nq + 1, 0);
-      for (int j = 0; j < cnt; ++j) {
-        pos[j] = B1.find(cur[j]);
-        if (pos[j] < 0) return fail(MPS_E_ARG, "internal: sample charge %d missing on bond %d", cur[j], s + 1);
-        ++start[pos[j] + 1];
-      }
-      for (int q = 0; q < nq; ++q) start[q + 1] += start[q];
-      for (int j = 0; j < cnt; ++j) order[start[pos[j]]++] = j;
-    }
-    std::vector<SampleGroup> groups;
-    std::vector<GemmWork> g1, g2;
-    int nt1 = 0, nt2 = 0, ptiles = 0;
-    long long voff = 0, woff = 0;
-    long long maxelems = 0;
-    for (int t = 0; t < cnt;) {
-      const int c = cur[order[t]];
-      int e = t;
-      while (e < cnt && cur[order[e]] == c) ++e;
-      const int bi = B1.find(c);
-      if (bi < 0) return fail(MPS_E_ARG, "internal: sample charge %d missing on bond %d", c, s + 1);
-      SampleGroup g{};
-      g.nc = B1.count[bi];
-      g.ng = e - t;
-      g.id0 = t;
-      g.voff = voff;
-      g.tile0 = ptiles;
-      ptiles += (g.ng + 15) / 16;
-      for (int i = 0; i < d; ++i) {
-        const int c2 = zn ? (c + i) % zn : c + h->rule.step[i];
-        const int ri = B0.find(c2);
-        if (ri < 0) continue;
-        const int nr = B0.count[ri], offr = B0.off[ri];
-        g.loc[g.nout] = i;
-        g.nr[g.nout] = nr;
-        g.woff[g.nout] = woff;
-        GemmWork a{};
-        a.a = h->site[s] + (size_t)offr * ldb + B1.off[bi];
-        a.lda = ldb;
-        a.b = reinterpret_cast<double2*>(dev + o_v) + voff;
-        a.ldb = g.ng;
-        a.c = reinterpret_cast<double2*>(dev + o_w) + woff;
-        a.ldc = g.ng;
-        a.m = nr;
-        a.n = g.ng;
-        a.k = g.nc;
-        a.tiles_n = (g.ng + kGemmTile - 1) / kGemmTile;
-        a.tile_begin = nt1;
-        nt1 += ((nr + kGemmTile - 1) / kGemmTile) * a.tiles_n;
-        g1.push_back(a);
-        GemmWork x{};
-        x.a = eb[s] + (size_t)offr * lde + offr;
-        x.lda = lde;
-        x.b = reinterpret_cast<double2*>(dev + o_w) + woff;
-        x.ldb = g.ng;
-        x.c = reinterpret_cast<double2*>(dev + o_x) + woff;
-        x.ldc = g.ng;
-        x.m = nr;
-        x.n = g.ng;
-        x.k = nr;
-        x.tiles_n = a.tiles_n;
-        x.tile_begin = nt2;
-        nt2 += ((nr + kGemmTile - 1) / kGemmTile) * x.tiles_n;
-        g2.push_back(x);
-        woff += (long long)nr * g.ng;
-        ++g.nout;
-      }
-      voff += (long long)g.nc * g.ng;
-      maxelems = std::max(maxelems, (long long)g.nc * g.ng);
-      groups.push_back(g);
-      t = e;
-    }
-    // lists up, then gather, the two products and the draw
-    Packer pl;
-    const size_t l_ids = pl.add(order.data(), order.size() * sizeof(int));
-    const size_t l_grp = pl.add(groups.data(), groups.size() * sizeof(SampleGroup));
-    const size_t l_g1 = pl.add(g1.data(), g1.size() * sizeof(GemmWork));
-    const size_t l_g2 = pl.add(g2.data(), g2.size() * sizeof(GemmWork));
-    pl.write(stg);
-    // the list region [o_ids, o_g2 + ...) holds the same layout as pl
-    HIPCHK(hipMemcpyAsync(dev + o_ids, stg, pl.total, hipMemcpyHostToDevice, h->st));
-    const int* d_ids = reinterpret_cast<const int*>(dev + o_ids + l_ids);
-    const SampleGroup* d_grp = reinterpret_cast<const SampleGroup*>(dev + o_ids + l_grp);
-    HIPCHK(launch_sample_gather(d_grp, (int)groups.size(), maxelems, d_ids, slots, cnt,
-                                reinterpret_cast<double2*>(dev + o_v), h->st));
-    HIPCHK(launch_zgemm(reinterpret_cast<const GemmWork*>(dev + o_ids + l_g1), (int)g1.size(), nt1, h->st));
-    HIPCHK(launch_zgemm(reinterpret_cast<const GemmWork*>(dev + o_ids + l_g2), (int)g2.size(), nt2, h->st));
-    HIPCHK(launch_sample_pick(d_grp, (int)groups.size(), ptiles, d_ids, reinterpret_cast<const double2*>(dev + o_w),
-                              reinterpret_cast<const double2*>(dev + o_x), reinterpret_cast<const double*>(dev + o_u),
-                              L, s, slots, cnt, reinterpret_cast<int*>(dev + o_occ),
-                              reinterpret_cast<double*>(dev + o_pr), reinterpret_cast<int*>(dev + o_pick), h->st));
-    // the draws come back through pinned memory past the list region
-    int* pk_host = reinterpret_cast<int*>(stg + align256(stage_list));
-    HIPCHK(hipMemcpyAsync(pk_host, dev + o_pick, (size_t)cnt * sizeof(int), hipMemcpyDeviceToHost, h->st));
-    HIPCHK(hipStreamSynchronize(h->st));
-    std::memcpy(picks.data(), pk_host, (size_t)cnt * sizeof(int));
-    for (int j = 0; j < cnt; ++j) {
-      if (picks[j] < 0) return fail(MPS_E_NUMERIC, "sample %d met a vanished or non-finite marginal", j);
-      cur[j] = zn ? (cur[j] + picks[j]) % zn : cur[j] + h->rule.step[picks[j]];
-    }
+    const int nq = (int)B1.charge.size();
+    HIPCHK(launch_sample_plan(d_cand + cand_off[s], nq, d_pos, cnt, h->site[s], B1.dim(), eb[s], B0.dim(), vbuf,
+                              wbuf, xbuf, d_ids, d_grp, d_g1, d_g2, d_cnt, h->st));
+    HIPCHK(launch_sample_gather(d_grp, nq, ub_elems[s], d_ids, slots, cnt, vbuf, h->st));
+    HIPCHK(launch_zgemm(d_g1, nq * kMaxD, ub_gemm[s], h->st, &d_cnt->nt1));
+    HIPCHK(launch_zgemm(d_g2, nq * kMaxD, ub_gemm[s], h->st, &d_cnt->nt2));
+    HIPCHK(launch_sample_pick(d_grp, nq, ub_pick[s], d_ids, wbuf, xbuf, reinterpret_cast<const double*>(dev + o_u), L,
+                              s, slots, cnt, reinterpret_cast<int*>(dev + o_occ), reinterpret_cast<double*>(dev + o_pr),
+                              d_pos, d_cnt, h->st));
   }
-  HIPCHK(hipMemcpyAsync(occ, dev + o_occ, (size_t)cnt * L * sizeof(int), hipMemcpyDeviceToHost, h->st));
-  HIPCHK(hipMemcpyAsync(prob, dev + o_pr, (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  // results back through pinned memory (the staging buffer, sized for them
+  // above; the copies are ordered after the upload on the stream):
+  // occupations, probabilities, the flag
+  int* h_occ = reinterpret_cast<int*>(stg);
+  double* h_pr = reinterpret_cast<double*>(stg + align256((size_t)cnt * L * sizeof(int)));
+  SampleCounts* h_cnt = reinterpret_cast<SampleCounts*>(stg + align256((size_t)cnt * L * sizeof(int)) +
+                                                         align256((size_t)cnt * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(h_occ, dev + o_occ, (size_t)cnt * L * sizeof(int), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipMemcpyAsync(h_pr, dev + o_pr, (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost, h->st));
+  HIPCHK(hipMemcpyAsync(h_cnt, d_cnt, sizeof(SampleCounts), hipMemcpyDeviceToHost, h->st));
   HIPCHK(hipStreamSynchronize(h->st));
+  if (h_cnt->failed) return fail(MPS_E_NUMERIC, "a sample met a vanished or non-finite marginal");
+  std::memcpy(occ, h_occ, (size_t)cnt * L * sizeof(int));
+  std::memcpy(prob, h_pr, (size_t)cnt * sizeof(double));
   return MPS_OK;
 }
 

@@ -19,12 +19,116 @@
 // many right-hand sides (the generic complex GEMM) and every block of B_s and
 // E_s is read once per group instead of once per sample; sample_pick_kernel
 // then forms p_i = Re(W_i^dagger X_i) column by column, draws, and writes the
-// sample's new vector into its slot.  The host regroups the samples between
-// rounds from the drawn occupations.
+// sample's new vector into its slot and its new charge position.  The rounds
+// are planned on the device (sample_plan_kernel: the groups and the product
+// lists from the samples' charge positions), so the host enqueues all of them
+// without waiting; the product and draw launches take host-side upper bounds
+// on their grids and the true totals from the plan.
 #include "device_util.h"
 #include "kernels.h"
 
 namespace u1mps {
+
+constexpr int kPickS = 16;
+constexpr int kPickRows = 256 / kPickS;
+
+// Plan of one round (one workgroup): the samples' charge positions on bond
+// s+1 are counted per position in LDS; thread 0 lays out the groups in
+// position order (V, W and X offsets, the draw kernel's tiles) and the two
+// product lists, W_k = B_s[block k, block q] V and X_k = E_s[block k] W_k per
+// group q and candidate k (unused entries hold no tiles, so the lists keep a
+// fixed length of nq * kMaxD); then every sample takes a slot in its group.
+// The order of the samples inside a group is arbitrary: every sample's
+// column of the products, its draw and its new vector depend on its own
+// column only.
+__global__ void __launch_bounds__(1024)
+sample_plan_kernel(const SampleCand* __restrict__ cand, int nq, const int* __restrict__ pos, int cnt,
+                   const double2* __restrict__ site, int ldb, const double2* __restrict__ env, int lde,
+                   double2* vbuf, double2* wbuf, double2* xbuf, int* __restrict__ ids,
+                   SampleGroup* __restrict__ groups, GemmWork* __restrict__ g1, GemmWork* __restrict__ g2,
+                   SampleCounts* __restrict__ counts) {
+  __shared__ int hist[kMaxSampleCharges];
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) hist[q] = 0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < cnt; j += blockDim.x) atomicAdd(&hist[pos[j]], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int id0 = 0, tile0 = 0, t1 = 0, t2 = 0;
+    long long voff = 0, woff = 0;
+    for (int q = 0; q < nq; ++q) {
+      const SampleCand& c = cand[q];
+      const int ng = hist[q];
+      const int tn = (ng + kGemmTile - 1) / kGemmTile;
+      SampleGroup g;
+      g.nc = c.nc;
+      g.ng = ng;
+      g.id0 = id0;
+      g.nout = c.nout;
+      g.tile0 = tile0;
+      g.voff = voff;
+      for (int k = 0; k < kMaxD; ++k) {
+        GemmWork a, b;
+        a.opa = a.opb = b.opa = b.opb = 0;
+        a.beta_one = b.beta_one = 0;
+        a.a = b.a = nullptr;
+        a.b = b.b = nullptr;
+        a.c = b.c = nullptr;
+        a.m = a.n = a.k = b.m = b.n = b.k = 0;
+        a.lda = a.ldb = a.ldc = b.lda = b.ldb = b.ldc = 0;
+        a.tiles_n = b.tiles_n = 0;
+        g.loc[k] = g.nr[k] = g.pos[k] = 0;
+        g.woff[k] = 0;
+        if (k < c.nout) {
+          const int nr = c.nr[k], tm = (nr + kGemmTile - 1) / kGemmTile;
+          g.loc[k] = c.loc[k];
+          g.nr[k] = nr;
+          g.pos[k] = c.pos[k];
+          g.woff[k] = woff;
+          a.a = site + (size_t)c.off0[k] * ldb + c.off1;
+          a.lda = ldb;
+          a.b = vbuf + voff;
+          a.ldb = ng;
+          a.c = wbuf + woff;
+          a.ldc = ng;
+          a.m = nr;
+          a.n = ng;
+          a.k = c.nc;
+          a.tiles_n = tn;
+          b.a = env + (size_t)c.off0[k] * lde + c.off0[k];
+          b.lda = lde;
+          b.b = wbuf + woff;
+          b.ldb = ng;
+          b.c = xbuf + woff;
+          b.ldc = ng;
+          b.m = nr;
+          b.n = ng;
+          b.k = nr;
+          b.tiles_n = tn;
+          a.tile_begin = t1;
+          b.tile_begin = t2;
+          t1 += tm * tn;
+          t2 += tm * tn;
+          woff += (long long)nr * ng;
+        } else {
+          a.tile_begin = t1;
+          b.tile_begin = t2;
+        }
+        g1[q * kMaxD + k] = a;
+        g2[q * kMaxD + k] = b;
+      }
+      groups[q] = g;
+      hist[q] = id0;                        // from here on: the group's next free slot
+      voff += (long long)c.nc * ng;
+      id0 += ng;
+      tile0 += (ng + kPickS - 1) / kPickS;
+    }
+    counts->nt1 = t1;
+    counts->nt2 = t2;
+    counts->ptiles = tile0;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < cnt; j += blockDim.x) ids[atomicAdd(&hist[pos[j]], 1)] = j;
+}
 
 // V_g[k][jj] = slots[k][ids[id0 + jj]] for every group (blockIdx.y), k < nc.
 __global__ void __launch_bounds__(256)
@@ -47,19 +151,18 @@ sample_gather_kernel(const SampleGroup* __restrict__ groups, const int* __restri
 // order); the first slice draws (NaN or a non-positive total leaves pick -1)
 // and updates the running probability; every slice then writes its rows of
 // the new vector W_pick[:, jj] / sqrt(p_pick) into the sample's slot.
-constexpr int kPickS = 16;
-constexpr int kPickRows = 256 / kPickS;
-
 __global__ void __launch_bounds__(256)
 sample_pick_kernel(const SampleGroup* __restrict__ groups, int ngroups, const int* __restrict__ ids,
                    const double2* __restrict__ wbuf, const double2* __restrict__ xbuf,
                    const double* __restrict__ uni, int L, int s, double2* __restrict__ slots, int ld_slot,
-                   int* __restrict__ occ, double* __restrict__ prob, int* __restrict__ pick_out) {
+                   int* __restrict__ occ, double* __restrict__ prob, int* __restrict__ pos,
+                   SampleCounts* __restrict__ counts) {
   __shared__ double part[kPickRows][kMaxD][kPickS];
   __shared__ int pick_sh[kPickS];
   __shared__ double scale_sh[kPickS];
-  int lo = 0, hi = ngroups - 1;
   const int b = blockIdx.x;
+  if (b >= counts->ptiles) return;          // the grid is an upper bound
+  int lo = 0, hi = ngroups - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (groups[mid].tile0 <= b) lo = mid; else hi = mid - 1;
@@ -117,7 +220,10 @@ sample_pick_kernel(const SampleGroup* __restrict__ groups, int ngroups, const in
         occ[(size_t)j * L + s] = g.loc[pick];
         sc = 1.0 / sqrt(pv[pick]);
       }
-      pick_out[j] = pick >= 0 ? g.loc[pick] : -1;
+      // a vanished or non-finite marginal fails the call; the sample keeps a
+      // valid position so that the later rounds stay in bounds
+      pos[j] = pick >= 0 ? g.pos[pick] : 0;
+      if (pick < 0) atomicOr(&counts->failed, 1);
     }
     pick_sh[col] = pick;
     scale_sh[col] = sc;
@@ -134,6 +240,15 @@ sample_pick_kernel(const SampleGroup* __restrict__ groups, int ngroups, const in
   }
 }
 
+hipError_t launch_sample_plan(const SampleCand* cand, int nq, const int* pos, int cnt, const double2* site, int ldb,
+                              const double2* env, int lde, double2* vbuf, double2* wbuf, double2* xbuf, int* ids,
+                              SampleGroup* groups, GemmWork* g1, GemmWork* g2, SampleCounts* counts, hipStream_t st) {
+  if (nq <= 0 || nq > kMaxSampleCharges) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sample_plan_kernel, dim3(1), dim3(1024), 0, st, cand, nq, pos, cnt, site, ldb, env, lde, vbuf,
+                     wbuf, xbuf, ids, groups, g1, g2, counts);
+  return hipGetLastError();
+}
+
 hipError_t launch_sample_gather(const SampleGroup* groups, int ngroups, long long maxelems, const int* ids,
                                 const double2* slots, int ld_slot, double2* vbuf, hipStream_t st) {
   if (ngroups <= 0 || maxelems <= 0) return hipSuccess;
@@ -146,10 +261,11 @@ hipError_t launch_sample_gather(const SampleGroup* groups, int ngroups, long lon
 
 hipError_t launch_sample_pick(const SampleGroup* groups, int ngroups, int ntiles, const int* ids,
                               const double2* wbuf, const double2* xbuf, const double* uni, int L, int s,
-                              double2* slots, int ld_slot, int* occ, double* prob, int* pick_out, hipStream_t st) {
+                              double2* slots, int ld_slot, int* occ, double* prob, int* pos, SampleCounts* counts,
+                              hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
   hipLaunchKernelGGL(sample_pick_kernel, dim3(ntiles), dim3(256), 0, st, groups, ngroups, ids, wbuf, xbuf, uni, L,
-                     s, slots, ld_slot, occ, prob, pick_out);
+                     s, slots, ld_slot, occ, prob, pos, counts);
   return hipGetLastError();
 }
 
