@@ -175,7 +175,7 @@ struct mps_state {
   DevBuf th_raw, th_scaled, acc, sigma, order, jperm, jnorm, plan, upd, norm_e0, norm_e1, norm_t, sel_v, sel_k, misc,
       pbuf, planes, envs, samp, tbefore;
   std::vector<double> last_leak;   // per gate of the last apply call touching this state
-  PinBuf stage_plan, stage_upd, stage_res, stage_misc, stage_flag;
+  PinBuf stage_plan, stage_upd, stage_res, stage_misc, stage_flag, stage_samp;
   mps_stats stats{};
   bool timing = false;
   std::vector<Pending> pending;
@@ -1264,7 +1264,7 @@ mps_status destroy_buffers(mps_state* h) {
     b->p = nullptr;
     b->cap = 0;
   }
-  PinBuf* pins[] = {&h->stage_plan, &h->stage_upd, &h->stage_res, &h->stage_misc, &h->stage_flag};
+  PinBuf* pins[] = {&h->stage_plan, &h->stage_upd, &h->stage_res, &h->stage_misc, &h->stage_flag, &h->stage_samp};
   for (PinBuf* b : pins) {
     if (b->p) (void)hipHostFree(b->p);
     b->p = nullptr;
@@ -2066,15 +2066,15 @@ mps_status sample_chunk(mps_state* h, const std::vector<double2*>& eb, int cnt, 
   const size_t o_g1 = pk.add(nullptr, (size_t)maxq * kMaxD * sizeof(GemmWork));
   const size_t o_g2 = pk.add(nullptr, (size_t)maxq * kMaxD * sizeof(GemmWork));
   STCHK(ensure(h, h->samp, pk.total));
-  // the previous staging use (the environments' lists) may still be in flight
-  HIPCHK(hipStreamSynchronize(h->st));
   // inputs, laid out as on the device from o_u to o_slot (the initial vector 1
-  // of every sample, on the single charge of bond L, goes to row 0 of the slots)
+  // of every sample, on the single charge of bond L, goes to row 0 of the
+  // slots), through the sampler's own pinned buffer (whose last use, the
+  // previous chunk's results, has been waited for)
   const size_t head = o_slot + (size_t)cnt * sizeof(double2);
   const size_t tail_out =
       align256((size_t)cnt * L * sizeof(int)) + align256((size_t)cnt * sizeof(double)) + sizeof(SampleCounts);
-  STCHK(ensure_pin(h->stage_misc, std::max(head, tail_out)));
-  char* stg = static_cast<char*>(h->stage_misc.p);
+  STCHK(ensure_pin(h->stage_samp, std::max(head, tail_out)));
+  char* stg = static_cast<char*>(h->stage_samp.p);
   std::memset(stg, 0, head);
   std::memcpy(stg + o_u, uniforms, (size_t)cnt * L * sizeof(double));
   double* pones = reinterpret_cast<double*>(stg + o_pr);
@@ -2148,6 +2148,8 @@ mps_status mps_sample(mps_t h, int count, const double* uniforms, int* occ, doub
   STCHK(ensure(h, h->envs, etot * sizeof(double2)));
   std::vector<double2*> eb(L + 1);
   for (int b = 0; b <= L; ++b) eb[b] = static_cast<double2*>(h->envs.p) + eoff[b];
+  // the environments run while the host prepares the first chunk (the
+  // sampler stages through its own pinned buffer, so nothing waits for them)
   size_t tail = 0;
   STCHK(left_envs(h, eb, 0, &tail));
   std::vector<double> pr(count);

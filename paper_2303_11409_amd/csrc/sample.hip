@@ -34,13 +34,14 @@ constexpr int kPickRows = 256 / kPickS;
 
 // Plan of one round (one workgroup): the samples' charge positions on bond
 // s+1 are counted per position in LDS; thread 0 lays out the groups in
-// position order (V, W and X offsets, the draw kernel's tiles) and the two
-// product lists, W_k = B_s[block k, block q] V and X_k = E_s[block k] W_k per
-// group q and candidate k (unused entries hold no tiles, so the lists keep a
-// fixed length of nq * kMaxD); then every sample takes a slot in its group.
-// The order of the samples inside a group is arbitrary: every sample's
-// column of the products, its draw and its new vector depend on its own
-// column only.
+// position order (offsets of V, W and X, the draw kernel's tiles, the first
+// tile of every group in the two product lists); then thread q writes group
+// q, thread q * kMaxD + k the product entries of candidate k of group q,
+// W_k = B_s[block k, block q] V and X_k = E_s[block k] W_k (entries without a
+// candidate hold no tiles, so the lists keep a fixed length of nq * kMaxD),
+// and every sample takes a slot in its group.  The order of the samples inside
+// a group is arbitrary: every sample's column of the products, its draw and
+// its new vector depend on its own column only.
 __global__ void __launch_bounds__(1024)
 sample_plan_kernel(const SampleCand* __restrict__ cand, int nq, const int* __restrict__ pos, int cnt,
                    const double2* __restrict__ site, int ldb, const double2* __restrict__ env, int lde,
@@ -48,86 +49,106 @@ sample_plan_kernel(const SampleCand* __restrict__ cand, int nq, const int* __res
                    SampleGroup* __restrict__ groups, GemmWork* __restrict__ g1, GemmWork* __restrict__ g2,
                    SampleCounts* __restrict__ counts) {
   __shared__ int hist[kMaxSampleCharges];
+  __shared__ int id0s[kMaxSampleCharges], tile0s[kMaxSampleCharges], gt0[kMaxSampleCharges];
+  __shared__ long long voffs[kMaxSampleCharges], woffs[kMaxSampleCharges];
   for (int q = threadIdx.x; q < nq; q += blockDim.x) hist[q] = 0;
   __syncthreads();
   for (int j = threadIdx.x; j < cnt; j += blockDim.x) atomicAdd(&hist[pos[j]], 1);
   __syncthreads();
   if (threadIdx.x == 0) {
-    int id0 = 0, tile0 = 0, t1 = 0, t2 = 0;
+    int id0 = 0, tile0 = 0, t = 0;
     long long voff = 0, woff = 0;
     for (int q = 0; q < nq; ++q) {
       const SampleCand& c = cand[q];
-      const int ng = hist[q];
-      const int tn = (ng + kGemmTile - 1) / kGemmTile;
-      SampleGroup g;
-      g.nc = c.nc;
-      g.ng = ng;
-      g.id0 = id0;
-      g.nout = c.nout;
-      g.tile0 = tile0;
-      g.voff = voff;
-      for (int k = 0; k < kMaxD; ++k) {
-        GemmWork a, b;
-        a.opa = a.opb = b.opa = b.opb = 0;
-        a.beta_one = b.beta_one = 0;
-        a.a = b.a = nullptr;
-        a.b = b.b = nullptr;
-        a.c = b.c = nullptr;
-        a.m = a.n = a.k = b.m = b.n = b.k = 0;
-        a.lda = a.ldb = a.ldc = b.lda = b.ldb = b.ldc = 0;
-        a.tiles_n = b.tiles_n = 0;
-        g.loc[k] = g.nr[k] = g.pos[k] = 0;
-        g.woff[k] = 0;
-        if (k < c.nout) {
-          const int nr = c.nr[k], tm = (nr + kGemmTile - 1) / kGemmTile;
-          g.loc[k] = c.loc[k];
-          g.nr[k] = nr;
-          g.pos[k] = c.pos[k];
-          g.woff[k] = woff;
-          a.a = site + (size_t)c.off0[k] * ldb + c.off1;
-          a.lda = ldb;
-          a.b = vbuf + voff;
-          a.ldb = ng;
-          a.c = wbuf + woff;
-          a.ldc = ng;
-          a.m = nr;
-          a.n = ng;
-          a.k = c.nc;
-          a.tiles_n = tn;
-          b.a = env + (size_t)c.off0[k] * lde + c.off0[k];
-          b.lda = lde;
-          b.b = wbuf + woff;
-          b.ldb = ng;
-          b.c = xbuf + woff;
-          b.ldc = ng;
-          b.m = nr;
-          b.n = ng;
-          b.k = nr;
-          b.tiles_n = tn;
-          a.tile_begin = t1;
-          b.tile_begin = t2;
-          t1 += tm * tn;
-          t2 += tm * tn;
-          woff += (long long)nr * ng;
-        } else {
-          a.tile_begin = t1;
-          b.tile_begin = t2;
-        }
-        g1[q * kMaxD + k] = a;
-        g2[q * kMaxD + k] = b;
+      const int ng = hist[q], tn = (ng + kGemmTile - 1) / kGemmTile;
+      id0s[q] = id0;
+      tile0s[q] = tile0;
+      gt0[q] = t;
+      voffs[q] = voff;
+      woffs[q] = woff;
+      for (int k = 0; k < c.nout; ++k) {
+        t += ((c.nr[k] + kGemmTile - 1) / kGemmTile) * tn;
+        woff += (long long)c.nr[k] * ng;
       }
-      groups[q] = g;
-      hist[q] = id0;                        // from here on: the group's next free slot
       voff += (long long)c.nc * ng;
       id0 += ng;
       tile0 += (ng + kPickS - 1) / kPickS;
     }
-    counts->nt1 = t1;
-    counts->nt2 = t2;
+    counts->nt1 = t;
+    counts->nt2 = t;                         // the two lists have the same shapes
     counts->ptiles = tile0;
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < cnt; j += blockDim.x) ids[atomicAdd(&hist[pos[j]], 1)] = j;
+  for (int e = threadIdx.x; e < nq * kMaxD; e += blockDim.x) {
+    const int q = e / kMaxD, k = e % kMaxD;
+    const SampleCand& c = cand[q];
+    const int ng = hist[q], tn = (ng + kGemmTile - 1) / kGemmTile;
+    // this entry's first tile and W offset: the group's plus its earlier candidates'
+    int tb = gt0[q];
+    long long wo = woffs[q];
+    for (int k2 = 0; k2 < k && k2 < c.nout; ++k2) {
+      tb += ((c.nr[k2] + kGemmTile - 1) / kGemmTile) * tn;
+      wo += (long long)c.nr[k2] * ng;
+    }
+    GemmWork a, b;
+    a.opa = a.opb = b.opa = b.opb = 0;
+    a.beta_one = b.beta_one = 0;
+    a.a = b.a = nullptr;
+    a.b = b.b = nullptr;
+    a.c = b.c = nullptr;
+    a.m = a.n = a.k = b.m = b.n = b.k = 0;
+    a.lda = a.ldb = a.ldc = b.lda = b.ldb = b.ldc = 0;
+    a.tiles_n = b.tiles_n = 0;
+    a.tile_begin = b.tile_begin = tb;
+    if (k < c.nout) {
+      const int nr = c.nr[k];
+      a.a = site + (size_t)c.off0[k] * ldb + c.off1;
+      a.lda = ldb;
+      a.b = vbuf + voffs[q];
+      a.ldb = ng;
+      a.c = wbuf + wo;
+      a.ldc = ng;
+      a.m = nr;
+      a.n = ng;
+      a.k = c.nc;
+      a.tiles_n = tn;
+      b.a = env + (size_t)c.off0[k] * lde + c.off0[k];
+      b.lda = lde;
+      b.b = wbuf + wo;
+      b.ldb = ng;
+      b.c = xbuf + wo;
+      b.ldc = ng;
+      b.m = nr;
+      b.n = ng;
+      b.k = nr;
+      b.tiles_n = tn;
+    }
+    g1[e] = a;
+    g2[e] = b;
+  }
+  for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+    const SampleCand& c = cand[q];
+    const int ng = hist[q];
+    SampleGroup g;
+    g.nc = c.nc;
+    g.ng = ng;
+    g.id0 = id0s[q];
+    g.nout = c.nout;
+    g.tile0 = tile0s[q];
+    g.voff = voffs[q];
+    long long wo = woffs[q];
+    for (int k = 0; k < kMaxD; ++k) {
+      const bool on = k < c.nout;
+      g.loc[k] = on ? c.loc[k] : 0;
+      g.nr[k] = on ? c.nr[k] : 0;
+      g.pos[k] = on ? c.pos[k] : 0;
+      g.woff[k] = on ? wo : 0;
+      if (on) wo += (long long)c.nr[k] * ng;
+    }
+    groups[q] = g;
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < cnt; j += blockDim.x) ids[atomicAdd(&id0s[pos[j]], 1)] = j;
 }
 
 // V_g[k][jj] = slots[k][ids[id0 + jj]] for every group (blockIdx.y), k < nc.
