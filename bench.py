@@ -44,16 +44,16 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/cl
 # --samples 4096 --no-tebd`
 # (FETCH_SIZE, WRITE_SIZE; mean over the 43146 launches) scaled by the same
 # counters on a plain 256 MiB copy (`bench.py --copy-probe`: FETCH_SIZE reads
-# 131085.2 KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99980
+# 131085.1 KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99980
 # and writes by 1).  Valid only for the Jacobi source (csrc/jacobi.hip), the
 # inner sweep count per visit (kMaxInnerSweeps in csrc/runtime.cpp) and the
 # block size it was taken on.
 MEASURED_TRAFFIC = {
-    "kernels_sha256": "8a09b0b35d436542976c32865a146013f6c7c119e0c2dfb4ce48f41c7f26da81",
+    "kernels_sha256": "eba5f8fcaa0e8e8be98b4fd628b4cfd179354e4647a98286ab30f78cf8380e00",
     "max_inner": 1,
     "jacobi_block": 8,
-    "fetch_kib": 15295.7, "write_kib": 20491.8,
-    "fetch_scale": 262144.0 / 131085.2, "write_scale": 1.0,
+    "fetch_kib": 15297.8, "write_kib": 20492.5,
+    "fetch_scale": 262144.0 / 131085.1, "write_scale": 1.0,
 }
 
 
@@ -580,14 +580,20 @@ def main() -> int:
     if args.samples > 0:
         log(f"sampling {args.samples} output patterns from the final state ...")
         us = np.random.default_rng(7).random((args.samples, cfg["L"]))
-        states[0].sample(us[:8])                      # workspaces
+        # one untimed call of the same size sizes the pinned staging; then the
+        # median of three timed calls
+        states[0].sample(us)
         torch.cuda.synchronize()
-        ts = time.perf_counter()
-        spats, sprob = states[0].sample(us)
-        sel = time.perf_counter() - ts
+        times = []
+        for _ in range(3):
+            ts = time.perf_counter()
+            spats, sprob = states[0].sample(us)
+            times.append(time.perf_counter() - ts)
+        sel = sorted(times)[1]
         sflops = sample_flops(states[0], spats)
         sampling = {"workload": f"{args.samples} exact samples (chain rule over the left environments, "
-                                "uniforms seed 7) of the final state of one step, host-to-host",
+                                "uniforms seed 7) of the final state of one step, host-to-host, median of 3 "
+                                "calls after one untimed call",
                     "samples": args.samples, "seconds": sel, "value": args.samples / sel, "unit": "samples/s",
                     "distinct_patterns": int(len({tuple(p) for p in spats.tolist()})),
                     "max_prob": float(sprob.max()),

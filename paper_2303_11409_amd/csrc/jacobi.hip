@@ -886,21 +886,25 @@ jacobi_sweep_end(const int* __restrict__ list, int count, JacobiOut* __restrict_
 
 // Between sweeps: order every still-active sector's vectors by descending
 // norm (ties: lower index first), so that blocks hold vectors of similar
-// size.  One workgroup per sector.
+// size.  One workgroup per sector; the norms are compared from LDS (n
+// doubles of dynamic shared memory).
 __global__ void __launch_bounds__(256)
 jacobi_sort(const SectorWork* __restrict__ secs, const int* __restrict__ list,
             const JacobiOut* __restrict__ st, int* __restrict__ perm,
             const double* __restrict__ norm2) {
+  extern __shared__ double jsv[];
   const int sid = list[blockIdx.x];
   if (st[sid].converged) return;
   const SectorWork sw = secs[sid];
   const int n = sw.tall ? sw.c : sw.r;
   const double* nv = norm2 + sw.sig;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) jsv[i] = nv[i];
+  __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double v = nv[i];
+    const double v = jsv[i];
     int rank = 0;
     for (int k = 0; k < n; ++k) {
-      const double w = nv[k];
+      const double w = jsv[k];
       rank += (w > v) || (w == v && k < i);
     }
     perm[sw.sig + rank] = i;
@@ -968,10 +972,11 @@ hipError_t launch_jacobi_init(const SectorWork* secs, const int* list, int count
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count, const JacobiOut* st,
+hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count, int maxrows, const JacobiOut* st,
                               int* perm, const double* norm2, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_sort, dim3(count), dim3(256), 0, s, secs, list, st, perm, norm2);
+  const size_t smem = (size_t)maxrows * sizeof(double);
+  hipLaunchKernelGGL(jacobi_sort, dim3(count), dim3(256), smem, s, secs, list, st, perm, norm2);
   return hipGetLastError();
 }
 

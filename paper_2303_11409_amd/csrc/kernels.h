@@ -23,7 +23,7 @@ hipError_t launch_jacobi_init(const SectorWork* secs, const int* list, int count
 hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiBlockWork* jb, int njb, int npairs,
                               int step, double2* theta, double2* acc, JacobiOut* st, const int* perm,
                               double* norm2, double tol, int max_inner, int block, hipStream_t s);
-hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count, const JacobiOut* st,
+hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count, int maxrows, const JacobiOut* st,
                               int* perm, const double* norm2, hipStream_t s);
 hipError_t launch_jacobi_sweep_end(const int* list, int count, JacobiOut* st, int* active, hipStream_t s);
 // Scalar sweeps on the vectors for sectors the blocked sweeps left unconverged.

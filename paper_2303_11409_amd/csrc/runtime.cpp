@@ -768,7 +768,7 @@ Steps steps_of(const mps_state* h) {
 
 mps_status check_device_limits(mps_state* h, const BatchPlan& P) {
   if ((size_t)P.jmaxrows * sizeof(double) > 64 * 1024)
-    return fail(MPS_E_ARG, "sector with %d vectors exceeds the Jacobi finalize LDS budget", P.jmaxrows);
+    return fail(MPS_E_ARG, "sector with %d vectors exceeds the Jacobi sort and finalize LDS budget", P.jmaxrows);
   (void)h;
   return MPS_OK;
 }
@@ -1020,7 +1020,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
       Timer ta(h, K_JACOBI_AUX);
       STCHK(ta.start());
       HIPCHK(launch_jacobi_sweep_end(d_jlist, ns, d_jst, d_active, h->st));
-      HIPCHK(launch_jacobi_sort(d_secs, d_jlist, ns, d_jst, d_perm, d_norm, h->st));
+      HIPCHK(launch_jacobi_sort(d_secs, d_jlist, ns, P.jmaxrows, d_jst, d_perm, d_norm, h->st));
       STCHK(ta.stop());
       h->stats.jacobi_aux_launches += 2;
       HIPCHK(hipMemcpyAsync(const_cast<int*>(flag) + (sweep & 1), d_active, sizeof(int), hipMemcpyDeviceToHost,
