@@ -85,13 +85,17 @@ __device__ __forceinline__ double jac_tol(double tol_opt, int len) {
   return tol_opt > 0.0 ? tol_opt : (double)max(len, 2 * kJP) * DBL_EPSILON;
 }
 
-// One workgroup per sector: reset state, vector norms, identity order,
-// squared Frobenius norm, A = I.
-__global__ void __launch_bounds__(256)
+// One workgroup of kJacRowThreads per sector: reset state, vector norms (a
+// wavefront per vector), identity order, squared Frobenius norm (the
+// wavefronts' partial sums added in wavefront order), A = I.
+constexpr int kJacRowThreads = 1024;
+
+__global__ void __launch_bounds__(kJacRowThreads)
 jacobi_init(const SectorWork* __restrict__ secs, const int* __restrict__ list,
             const double2* __restrict__ theta, double2* __restrict__ accbuf,
             JacobiOut* __restrict__ st, int* __restrict__ perm, double* __restrict__ norm2) {
-  __shared__ double wsum[4];
+  constexpr int kWaves = kJacRowThreads / 64;
+  __shared__ double wsum[kWaves];
   const int sid = list[blockIdx.x];
   const SectorWork sw = secs[sid];
   const bool tall = sw.tall != 0;
@@ -105,7 +109,7 @@ jacobi_init(const SectorWork* __restrict__ secs, const int* __restrict__ list,
       a[e] = make_double2((e / n) == (e % n) ? 1.0 : 0.0, 0.0);
   }
   double f = 0.0;
-  for (int i = wave; i < n; i += 4) {
+  for (int i = wave; i < n; i += kWaves) {
     const double2* xi = x + (size_t)i * len;
     double ss = 0.0;
     for (int col = lane; col < len; col += 64) {
@@ -129,7 +133,9 @@ jacobi_init(const SectorWork* __restrict__ secs, const int* __restrict__ list,
     o.rot_this_sweep = 0;
     o.gram_units = 0;
     o.apply_units = 0;
-    o.fro2 = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    double fro2 = 0.0;
+    for (int w = 0; w < kWaves; ++w) fro2 += wsum[w];
+    o.fro2 = fro2;
     st[sid] = o;
   }
 }
@@ -911,9 +917,10 @@ jacobi_sort(const SectorWork* __restrict__ secs, const int* __restrict__ list,
   }
 }
 
-// One workgroup per sector: vector norms -> singular values, V^dagger rows
-// into the sector's slot (stride c), order by descending value.
-__global__ void __launch_bounds__(256)
+// One workgroup of kJacRowThreads per sector: vector norms -> singular
+// values (a wavefront per vector), V^dagger rows into the sector's slot
+// (stride c), order by descending value.
+__global__ void __launch_bounds__(kJacRowThreads)
 jacobi_finalize(const SectorWork* __restrict__ secs, const int* __restrict__ list,
                 double2* __restrict__ theta, const double2* __restrict__ accbuf,
                 double* __restrict__ sigma, int* __restrict__ order) {
@@ -968,7 +975,7 @@ hipError_t launch_jacobi_init(const SectorWork* secs, const int* list, int count
                               const double2* theta, double2* acc, JacobiOut* st, int* perm,
                               double* norm2, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(jacobi_init, dim3(count), dim3(256), 0, s, secs, list, theta, acc, st, perm, norm2);
+  hipLaunchKernelGGL(jacobi_init, dim3(count), dim3(kJacRowThreads), 0, s, secs, list, theta, acc, st, perm, norm2);
   return hipGetLastError();
 }
 
@@ -1012,7 +1019,8 @@ hipError_t launch_jacobi_finalize(const SectorWork* secs, const int* list, int c
                                   hipStream_t s) {
   if (count <= 0) return hipSuccess;
   const size_t smem = (size_t)maxrows * sizeof(double);
-  hipLaunchKernelGGL(jacobi_finalize, dim3(count), dim3(256), smem, s, secs, list, theta, acc, sigma, order);
+  hipLaunchKernelGGL(jacobi_finalize, dim3(count), dim3(kJacRowThreads), smem, s, secs, list, theta, acc, sigma,
+                     order);
   return hipGetLastError();
 }
 

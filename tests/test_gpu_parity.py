@@ -475,26 +475,28 @@ def test_batch_rejects_mixed_forms_and_duplicates(mps_cls):
 
 
 # ------------------------------------------------------------ Hamiltonian TEBD
-def run_dense(MPS, cfg):
+def run_dense(MPS, cfg, jacobi_block=0):
     m = MPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"],
-            modulus=cfg.get("modulus", 0))
+            modulus=cfg.get("modulus", 0), jacobi_block=jacobi_block)
     disc = []
     for lay in cfg["layers"]:
         disc.extend(m.apply_layer_dense([g.site for g in lay], [g.g4 for g in lay]))
     return m, np.array(disc)
 
 
+@pytest.mark.parametrize("jacobi_block", [0, 8])
 @pytest.mark.parametrize("model", ["xxz", "bose_hubbard"])
-def test_tebd_dense_gates_vs_oracle(mps_cls, model):
+def test_tebd_dense_gates_vs_oracle(mps_cls, model, jacobi_block):
     """Second-order Trotter evolution (dense two-site gates exp(-i dt h)) with
     truncation: per-gate discarded weight, Schmidt values, bond charges and
-    amplitudes against the dense oracle at the same cut."""
+    amplitudes against the dense oracle at the same cut (Jacobi blocks chosen
+    per update, and blocks of 8 throughout)."""
     from workloads import hamiltonians as ham
     if model == "xxz":
         cfg = ham.config_tebd("xxz", 24, 2, ham.neel(24), 0.2, 10, 20, 1e-12, J=1.0, delta=1.3, hz=0.07)
     else:
         cfg = ham.config_tebd("bose_hubbard", 10, 4, [1, 2] * 5, 0.15, 5, 20, 1e-12, J=1.0, U=1.5, mu=0.1)
-    m, disc = run_dense(mps_cls, cfg)
+    m, disc = run_dense(mps_cls, cfg, jacobi_block)
     ref = dense_mps.DenseMPS(cfg["occupation"], cfg["d"], chi_max=cfg["chi_max"], cutoff=cfg["cutoff"])
     ref.run(cfg["gates"])
     assert min(r.margin for r in ref.records) > 1e-9
