@@ -206,10 +206,13 @@ constexpr int kJB = 16;
 constexpr int kJP = 2 * kJB;
 constexpr int kJB8 = 8;
 
-struct JacobiBlockWork {
+// One block pair of a round-robin step: workgroup p of a step launch takes
+// entry p (the pairs of all sectors, heaviest sector first).
+struct JacobiPairWork {
   int sector;             // SectorWork index
-  int nb;                 // number of blocks, even (an empty block pads odd counts)
-  int pair_begin;         // flattened index of this sector's first block pair
+  int nb;                 // the sector's number of blocks, even (an empty block pads odd counts)
+  int k;                  // pair index within the sector's step (0 .. nb/2 - 1)
+  int pad;
 };
 
 // Per-sector Jacobi state and statistics.

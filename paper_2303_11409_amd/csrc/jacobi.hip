@@ -397,8 +397,8 @@ constexpr double kJacLoose = 1e-8;
 constexpr double kJacNoise = 64.0;
 
 __global__ void __launch_bounds__(256)
-jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __restrict__ jb,
-                  int njb, int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
+jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiPairWork* __restrict__ pairs,
+                  int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
                   JacobiOut* __restrict__ st, const int* __restrict__ perm, double* __restrict__ norm2,
                   double tol_opt, int max_inner) {
   // xs stages column chunks of the vectors; during the eig it is the second G
@@ -413,13 +413,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
   __shared__ int vrow[kJP];
   __shared__ int4 anyf[2];
   int parity = 0;
-  int lo = 0, hi = njb - 1;
-  const int pid = blockIdx.x;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jb[mid].pair_begin <= pid) lo = mid; else hi = mid - 1;
-  }
-  const JacobiBlockWork w = jb[lo];
+  const JacobiPairWork w = pairs[blockIdx.x];
   if (step >= w.nb - 1) return;
   const int sid = w.sector;
   if (st[sid].converged) return;
@@ -431,7 +425,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiBlockWork* __
   const double tol = jac_tol(tol_opt, len);
   const double floor_g = (double)len * DBL_EPSILON * DBL_EPSILON * st[sid].fro2;
   int bi, bj;
-  rr_pair(step, pid - w.pair_begin, w.nb, bi, bj);
+  rr_pair(step, w.k, w.nb, bi, bj);
   const int vI = bi * kJB, vJ = bj * kJB;
   const int nI = max(0, min(kJB, n - vI)), nJ = max(0, min(kJB, n - vJ));
   const int nv = nI + nJ;
@@ -708,8 +702,8 @@ __device__ void jac8_gram_eig(double2 (*gs)[kJP8 + 1], double2 (*ws)[kJP8 + 1], 
 // workgroup of 256 threads per block pair.  Visit rule, thresholds and
 // bookkeeping as in jacobi_block_step.
 __global__ void __launch_bounds__(256)
-jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiBlockWork* __restrict__ jb,
-                   int njb, int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
+jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiPairWork* __restrict__ pairs,
+                   int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
                    JacobiOut* __restrict__ st, const int* __restrict__ perm, double* __restrict__ norm2,
                    double tol_opt, int max_inner) {
   __shared__ double2 xt[4][kJP8][33];
@@ -719,13 +713,7 @@ jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiBlockWork* _
   __shared__ int vrow[kJP8];
   __shared__ int4 anyf[2];
   int parity = 0;
-  int lo = 0, hi = njb - 1;
-  const int pid = blockIdx.x;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jb[mid].pair_begin <= pid) lo = mid; else hi = mid - 1;
-  }
-  const JacobiBlockWork w = jb[lo];
+  const JacobiPairWork w = pairs[blockIdx.x];
   if (step >= w.nb - 1) return;
   const int sid = w.sector;
   if (st[sid].converged) return;
@@ -737,7 +725,7 @@ jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiBlockWork* _
   const double tol = jac_tol(tol_opt, len);
   const double floor_g = (double)len * DBL_EPSILON * DBL_EPSILON * st[sid].fro2;
   int bi, bj;
-  rr_pair(step, pid - w.pair_begin, w.nb, bi, bj);
+  rr_pair(step, w.k, w.nb, bi, bj);
   const int vI = bi * kJB8, vJ = bj * kJB8;
   const int nI = max(0, min(kJB8, n - vI)), nJ = max(0, min(kJB8, n - vJ));
   const int nv = nI + nJ;
@@ -870,10 +858,13 @@ jacobi_polish(const SectorWork* __restrict__ secs, const int* __restrict__ list,
 // After a sweep: a sector with no rotated block pair is converged.  One
 // workgroup; *active receives 1 if any sector still rotates.
 __global__ void __launch_bounds__(1024)
-jacobi_sweep_end(const int* __restrict__ list, int count, JacobiOut* __restrict__ st,
+jacobi_sweep_end(const int* __restrict__ list, const int* __restrict__ nbs, int count, JacobiOut* __restrict__ st,
                  int* __restrict__ active) {
-  __shared__ int act;
-  if (threadIdx.x == 0) act = 0;
+  __shared__ int act, maxnb;
+  if (threadIdx.x == 0) {
+    act = 0;
+    maxnb = 0;
+  }
   __syncthreads();
   for (int i = threadIdx.x; i < count; i += blockDim.x) {
     const int s = list[i];
@@ -881,13 +872,20 @@ jacobi_sweep_end(const int* __restrict__ list, int count, JacobiOut* __restrict_
     if (o.converged) continue;
     o.sweeps += 1;
     o.rotations += o.rot_this_sweep;
-    if (o.rot_this_sweep == 0) o.converged = 1;
-    else atomicOr(&act, 1);
+    if (o.rot_this_sweep == 0) {
+      o.converged = 1;
+    } else {
+      atomicOr(&act, 1);
+      atomicMax(&maxnb, nbs[i]);
+    }
     o.rot_this_sweep = 0;
     st[s] = o;
   }
   __syncthreads();
-  if (threadIdx.x == 0) *active = act;
+  if (threadIdx.x == 0) {
+    active[0] = act;
+    active[1] = maxnb;
+  }
 }
 
 // Between sweeps: order every still-active sector's vectors by descending
@@ -987,23 +985,24 @@ hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiBlockWork* jb, int njb, int npairs,
+hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiPairWork* pairs, int npairs,
                               int step, double2* theta, double2* acc, JacobiOut* st, const int* perm,
                               double* norm2, double tol, int max_inner, int block, hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
   if (block == kJB8)
-    hipLaunchKernelGGL(jacobi_block_step8, dim3(npairs), dim3(256), 0, s, secs, jb, njb, step, theta, acc,
+    hipLaunchKernelGGL(jacobi_block_step8, dim3(npairs), dim3(256), 0, s, secs, pairs, step, theta, acc,
                        st, perm, norm2, tol, max_inner);
   else if (block == kJB)
-    hipLaunchKernelGGL(jacobi_block_step, dim3(npairs), dim3(256), 0, s, secs, jb, njb, step, theta, acc,
+    hipLaunchKernelGGL(jacobi_block_step, dim3(npairs), dim3(256), 0, s, secs, pairs, step, theta, acc,
                        st, perm, norm2, tol, max_inner);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_sweep_end(const int* list, int count, JacobiOut* st, int* active, hipStream_t s) {
-  hipLaunchKernelGGL(jacobi_sweep_end, dim3(1), dim3(1024), 0, s, list, count, st, active);
+hipError_t launch_jacobi_sweep_end(const int* list, const int* nbs, int count, JacobiOut* st, int* active,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(jacobi_sweep_end, dim3(1), dim3(1024), 0, s, list, nbs, count, st, active);
   return hipGetLastError();
 }
 

@@ -20,12 +20,15 @@ hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntile
 hipError_t launch_jacobi_init(const SectorWork* secs, const int* list, int count,
                               const double2* theta, double2* acc, JacobiOut* st, int* perm,
                               double* norm2, hipStream_t s);
-hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiBlockWork* jb, int njb, int npairs,
+hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiPairWork* pairs, int npairs,
                               int step, double2* theta, double2* acc, JacobiOut* st, const int* perm,
                               double* norm2, double tol, int max_inner, int block, hipStream_t s);
 hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count, int maxrows, const JacobiOut* st,
                               int* perm, const double* norm2, hipStream_t s);
-hipError_t launch_jacobi_sweep_end(const int* list, int count, JacobiOut* st, int* active, hipStream_t s);
+// active[0]: a sector still rotates; active[1]: the largest block count nbs[i]
+// among those sectors (list order).
+hipError_t launch_jacobi_sweep_end(const int* list, const int* nbs, int count, JacobiOut* st, int* active,
+                                   hipStream_t s);
 // Scalar sweeps on the vectors for sectors the blocked sweeps left unconverged.
 hipError_t launch_jacobi_polish(const SectorWork* secs, const int* list, int count, double2* theta,
                                 double2* acc, JacobiOut* st, double tol, int max_sweeps, hipStream_t s);

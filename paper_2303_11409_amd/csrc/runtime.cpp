@@ -433,7 +433,8 @@ struct BatchPlan {
   std::vector<double2> coef;
   std::vector<GatePlan> gp;
   std::vector<int> jlist;                 // every sector id
-  std::vector<JacobiBlockWork> jblocks;   // block schedule per sector
+  std::vector<JacobiPairWork> jpairlist;  // every block pair of a step, heaviest sector first
+  std::vector<int> jnb;                   // block count per jlist entry
   int jpairs = 0, jmaxnb = 2, jmaxrows = 1;
   int jblock = kJB8;                      // vectors per Jacobi block (8 or 16)
   std::vector<long long> sel_off;         // global sort scratch offsets
@@ -750,7 +751,8 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
     nb += nb & 1;
     nb = std::max(nb, 2);
     P.jlist.push_back((int)i);
-    P.jblocks.push_back({(int)i, nb, P.jpairs});
+    P.jnb.push_back(nb);
+    for (int k = 0; k < nb / 2; ++k) P.jpairlist.push_back({(int)i, nb, k, 0});
     P.jpairs += nb / 2;
     P.jmaxnb = std::max(P.jmaxnb, nb);
     P.jmaxrows = std::max(P.jmaxrows, nv);
@@ -862,7 +864,8 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   const size_t o_tiles = pk.add(P.tiles.data(), P.tiles.size() * sizeof(ThetaTile));
   const size_t o_coef = pk.add(P.coef.data(), P.coef.size() * sizeof(double2));
   const size_t o_jlist = pk.add(P.jlist.data(), P.jlist.size() * sizeof(int));
-  const size_t o_jblk = pk.add(P.jblocks.data(), P.jblocks.size() * sizeof(JacobiBlockWork));
+  const size_t o_jblk = pk.add(P.jpairlist.data(), P.jpairlist.size() * sizeof(JacobiPairWork));
+  const size_t o_jnb = pk.add(P.jnb.data(), P.jnb.size() * sizeof(int));
   const size_t o_seloff = pk.add(P.sel_off.data(), P.sel_off.size() * sizeof(long long));
   const size_t o_sg = pk.add(P.sg.data(), P.sg.size() * sizeof(SplitGemm));
   const size_t o_spl = pk.add(P.spl.data(), P.spl.size() * sizeof(SplitPlanes));
@@ -870,7 +873,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   const size_t o_kept = pk.add(nullptr, (size_t)ns * sizeof(int));
   const size_t o_cut = pk.add(nullptr, (size_t)ng * sizeof(CutOut));
   const size_t o_jst = pk.add(nullptr, (size_t)ns * sizeof(JacobiOut));
-  const size_t o_active = pk.add(nullptr, sizeof(int));
+  const size_t o_active = pk.add(nullptr, 2 * sizeof(int));
   const size_t upload = o_kept;  // everything before the outputs is uploaded
   STCHK(ensure(h, h->plan, pk.total));
   STCHK(ensure_pin(h->stage_plan, upload));
@@ -954,8 +957,9 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     int* d_perm = static_cast<int*>(h->jperm.p);
     double* d_norm = static_cast<double*>(h->jnorm.p);
     int* d_active = at<int>(h->plan, o_active);
-    // two pinned slots for the per-sweep "still rotating" flag (see below)
-    STCHK(ensure_pin(h->stage_flag, 2 * sizeof(int)));
+    // two pinned slots for the per-sweep "still rotating" flag and largest
+    // block count of the rotating sectors (see below)
+    STCHK(ensure_pin(h->stage_flag, 4 * sizeof(int)));
     volatile int* flag = static_cast<volatile int*>(h->stage_flag.p);
     {
       Timer tm(h, K_JACOBI_AUX);
@@ -985,7 +989,7 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
       HIPCHK(hipStreamBeginCapture(h->cap_st, hipStreamCaptureModeThreadLocal));
       hipError_t ce = hipSuccess;
       for (int step = 0; step < P.jmaxnb - 1 && ce == hipSuccess; ++step)
-        ce = launch_jacobi_step(d_secs, at<JacobiBlockWork>(h->plan, o_jblk), ns, P.jpairs, step, scaled, d_acc,
+        ce = launch_jacobi_step(d_secs, at<JacobiPairWork>(h->plan, o_jblk), P.jpairs, step, scaled, d_acc,
                                 d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, P.jblock, h->cap_st);
       const hipError_t ee = hipStreamEndCapture(h->cap_st, &graph);
       if (ce == hipSuccess) ce = ee;
@@ -993,51 +997,59 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
       if (graph) (void)hipGraphDestroy(graph);
       if (ce != hipSuccess) return fail(MPS_E_DEVICE, "capture of the sweep graph failed: %s", hipGetErrorString(ce));
     }
-    // The host never idles the device between sweeps: sweep k's flag is copied
-    // into pinned slot k % 2 behind it, and the host reads it only once sweep
+    // The host never idles the device between sweeps: sweep k's flag (and the
+    // largest block count of the sectors still rotating) is copied into
+    // pinned slot k % 2 behind it, and the host reads it only once sweep
     // k + 1 is enqueued.  A sweep enqueued after convergence finds every
-    // sector converged and returns at once, so it changes nothing.
+    // sector converged and returns at once, so it changes nothing.  Sweep
+    // k + 2 launches only the steps of the sectors rotating after sweep k
+    // (sectors only ever drop out, so those include every sector still
+    // rotating then); a captured graph keeps the full count.
     hipEvent_t fev[2] = {nullptr, nullptr};
     STCHK(ev_get(h, &fev[0]));
     STCHK(ev_get(h, &fev[1]));
     int still_active = 1;
     int issued = 0;
+    int steps = P.jmaxnb - 1;
     for (int sweep = 0; sweep < blocked; ++sweep) {
       Timer tm(h, P.jblock == kJB8 ? K_JACOBI8 : K_JACOBI);
       STCHK(tm.start());
+      int launched = P.jmaxnb - 1;
       if (gexec) {
         HIPCHK(hipGraphLaunch(gexec, h->st));
         h->stats.graph_launches += 1;
       } else {
-        for (int step = 0; step < P.jmaxnb - 1; ++step)
-          HIPCHK(launch_jacobi_step(d_secs, at<JacobiBlockWork>(h->plan, o_jblk), ns, P.jpairs, step, scaled,
-                                    d_acc, d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, P.jblock,
-                                    h->st));
+        launched = steps;
+        for (int step = 0; step < steps; ++step)
+          HIPCHK(launch_jacobi_step(d_secs, at<JacobiPairWork>(h->plan, o_jblk), P.jpairs, step, scaled, d_acc,
+                                    d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, P.jblock, h->st));
       }
       STCHK(tm.stop());
-      h->stats.jacobi_launches += P.jmaxnb - 1;
-      if (P.jblock == kJB8) h->stats.jacobi8_launches += P.jmaxnb - 1;
+      h->stats.jacobi_launches += launched;
+      if (P.jblock == kJB8) h->stats.jacobi8_launches += launched;
       Timer ta(h, K_JACOBI_AUX);
       STCHK(ta.start());
-      HIPCHK(launch_jacobi_sweep_end(d_jlist, ns, d_jst, d_active, h->st));
+      HIPCHK(launch_jacobi_sweep_end(d_jlist, at<int>(h->plan, o_jnb), ns, d_jst, d_active, h->st));
       HIPCHK(launch_jacobi_sort(d_secs, d_jlist, ns, P.jmaxrows, d_jst, d_perm, d_norm, h->st));
       STCHK(ta.stop());
       h->stats.jacobi_aux_launches += 2;
-      HIPCHK(hipMemcpyAsync(const_cast<int*>(flag) + (sweep & 1), d_active, sizeof(int), hipMemcpyDeviceToHost,
-                            h->st));
+      HIPCHK(hipMemcpyAsync(const_cast<int*>(flag) + 2 * (sweep & 1), d_active, 2 * sizeof(int),
+                            hipMemcpyDeviceToHost, h->st));
       HIPCHK(hipEventRecord(fev[sweep & 1], h->st));
       issued = sweep + 1;
       if (sweep >= 1) {
         HIPCHK(hipEventSynchronize(fev[(sweep - 1) & 1]));
-        if (!flag[(sweep - 1) & 1]) {
+        const volatile int* fl = flag + 2 * ((sweep - 1) & 1);
+        if (!fl[0]) {
           still_active = 0;
           break;
         }
+        steps = std::min(steps, std::max(fl[1] - 1, 1));
       }
     }
     if (still_active && issued > 0) {
       HIPCHK(hipEventSynchronize(fev[(issued - 1) & 1]));
-      still_active = flag[(issued - 1) & 1];
+      still_active = flag[2 * ((issued - 1) & 1)];
     }
     h->pool.push_back(fev[0]);
     h->pool.push_back(fev[1]);
