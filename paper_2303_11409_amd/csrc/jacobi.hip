@@ -502,6 +502,21 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiPairWork* __r
 // first write).
 constexpr int kJP8 = 2 * kJB8;
 constexpr int kJ8Regs = kJP8 * 32 / 64;   // elements of a 16 x 32 chunk per lane
+constexpr int kJ8Waves = 4;               // wavefronts per workgroup (8 measured slower)
+constexpr int kJ8Threads = 64 * kJ8Waves;
+
+// True (uniform) if pred holds on any thread of the workgroup (flags: two
+// alternating sets of per-wavefront words; parity selects the set).
+__device__ __forceinline__ bool jac8_block_any(int pred, int (*flags)[kJ8Waves], int& parity) {
+  const bool w = __ballot(pred) != 0ull;
+  if ((threadIdx.x & 63) == 0) flags[parity][threadIdx.x >> 6] = w ? 1 : 0;
+  __syncthreads();
+  int v = 0;
+#pragma unroll
+  for (int i = 0; i < kJ8Waves; ++i) v |= flags[parity][i];
+  parity ^= 1;
+  return v != 0;
+}
 
 // LDS ordering point within one wavefront: the compiler keeps LDS accesses on
 // their side, and this lane's LDS operations have completed.
@@ -559,7 +574,7 @@ __device__ __forceinline__ void jac8_chunks(double2 (*xt)[33], const double2* x,
 #pragma unroll
     for (int j = 0; j < kJ8Regs; ++j) xt[(lane >> 5) + 2 * j][lane & 31] = ra[j];
     wave_lds_sync();
-    const int nx = ch + 4;
+    const int nx = ch + kJ8Waves;
     if (nx < nch) jac8_fetch(ra, rowp, len, nx * 32);
     body(ch * 32);
     ch = nx;
@@ -596,10 +611,10 @@ __device__ void jac8_gram(double2 (*xt)[kJP8][33], double2 (*gs)[kJP8 + 1], cons
   __syncthreads();
   {
     const int r = tid >> 4, c = tid & 15;
-    if (r <= c) {
+    if (tid < 256 && r <= c) {
       double gr = 0.0, mrc = 0.0, mcr = 0.0;
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
+      for (int w = 0; w < kJ8Waves; ++w) {
         const double* pw = reinterpret_cast<const double*>(&xt[w][0][0]);
         gr += pw[r * 16 + c];
         mrc += pw[256 + r * 16 + c];
@@ -646,11 +661,11 @@ __device__ void jac8_apply(double2 (*xt)[kJP8][33], double2 (*ws)[kJP8 + 1], dou
 
 // True (uniform) if any off-diagonal pair of the 16 x 16 gs is above the
 // threshold: thread t checks entry (t / 16, t % 16).
-__device__ __forceinline__ bool jac8_any_above(double2 (*gs)[kJP8 + 1], double tol, double floor_g, int4* anyf,
-                                               int& parity) {
-  const int p = threadIdx.x >> 4, q = threadIdx.x & 15;
-  const int f = p < q && jac_needs(gs[p][p].x, gs[q][q].x, gs[p][q], tol, floor_g) ? 1 : 0;
-  return block_any(f, anyf, parity);
+__device__ __forceinline__ bool jac8_any_above(double2 (*gs)[kJP8 + 1], double tol, double floor_g,
+                                               int (*anyf)[kJ8Waves], int& parity) {
+  const int p = (threadIdx.x >> 4) & 15, q = threadIdx.x & 15;
+  const int f = threadIdx.x < 256 && p < q && jac_needs(gs[p][p].x, gs[q][q].x, gs[p][q], tol, floor_g) ? 1 : 0;
+  return jac8_block_any(f, anyf, parity);
 }
 
 // Rotations of the 16 x 16 gs by wavefront 0, in place: lane 8 A + B owns
@@ -701,17 +716,17 @@ __device__ void jac8_gram_eig(double2 (*gs)[kJP8 + 1], double2 (*ws)[kJP8 + 1], 
 // One round-robin step over blocks of 8 for every active sector: one
 // workgroup of 256 threads per block pair.  Visit rule, thresholds and
 // bookkeeping as in jacobi_block_step.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kJ8Threads)
 jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiPairWork* __restrict__ pairs,
                    int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
                    JacobiOut* __restrict__ st, const int* __restrict__ perm, double* __restrict__ norm2,
                    double tol_opt, int max_inner) {
-  __shared__ double2 xt[4][kJP8][33];
+  __shared__ double2 xt[kJ8Waves][kJP8][33];
   __shared__ double2 gs[kJP8][kJP8 + 1];
   __shared__ double2 ws[kJP8][kJP8 + 1];
   __shared__ double gmax;
   __shared__ int vrow[kJP8];
-  __shared__ int4 anyf[2];
+  __shared__ int anyf[2][kJ8Waves];
   int parity = 0;
   const JacobiPairWork w = pairs[blockIdx.x];
   if (step >= w.nb - 1) return;
@@ -752,7 +767,7 @@ jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiPairWork* __
     const bool need = jac8_any_above(gs, tol, floor_g, anyf, parity);
     if (!need) break;
     if (pass == 0 && tid == 0) atomicAdd(&st[sid].rot_this_sweep, 1);
-    {
+    if (tid < 256) {
       const int r = tid >> 4, c = tid & 15;
       ws[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
     }
@@ -990,7 +1005,7 @@ hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiPairWork* pair
                               double* norm2, double tol, int max_inner, int block, hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
   if (block == kJB8)
-    hipLaunchKernelGGL(jacobi_block_step8, dim3(npairs), dim3(256), 0, s, secs, pairs, step, theta, acc,
+    hipLaunchKernelGGL(jacobi_block_step8, dim3(npairs), dim3(kJ8Threads), 0, s, secs, pairs, step, theta, acc,
                        st, perm, norm2, tol, max_inner);
   else if (block == kJB)
     hipLaunchKernelGGL(jacobi_block_step, dim3(npairs), dim3(256), 0, s, secs, pairs, step, theta, acc,
