@@ -42,18 +42,18 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/cl
 # rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline
 # --batch-copies 0 --mix-circuits 0 --chi2048-layers 0 --serve-seconds 0
 # --samples 4096 --no-tebd`
-# (FETCH_SIZE, WRITE_SIZE; mean over the 43146 launches) scaled by the same
+# (FETCH_SIZE, WRITE_SIZE; mean over the 42118 launches) scaled by the same
 # counters on a plain 256 MiB copy (`bench.py --copy-probe`: FETCH_SIZE reads
-# 131085.1 KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99980
+# 131085.2 KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99980
 # and writes by 1).  Valid only for the Jacobi source (csrc/jacobi.hip), the
 # inner sweep count per visit (kMaxInnerSweeps in csrc/runtime.cpp) and the
 # block size it was taken on.
 MEASURED_TRAFFIC = {
-    "kernels_sha256": "eba5f8fcaa0e8e8be98b4fd628b4cfd179354e4647a98286ab30f78cf8380e00",
+    "kernels_sha256": "2d2c618587e79bdd925947ae341d7039ba0e90048bb596719f4f43a0a416541b",
     "max_inner": 1,
     "jacobi_block": 8,
-    "fetch_kib": 15297.8, "write_kib": 20492.5,
-    "fetch_scale": 262144.0 / 131085.1, "write_scale": 1.0,
+    "fetch_kib": 15691.5, "write_kib": 20994.8,
+    "fetch_scale": 262144.0 / 131085.2, "write_scale": 1.0,
 }
 
 
