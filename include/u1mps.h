@@ -156,6 +156,20 @@ typedef struct {
                                   its 2b x 2b Gram matrix; smaller blocks make
                                   shorter visits and more of them.  In a batch
                                   the first state's value serves every state. */
+  int jacobi_lockstep;         /* 0 (default): each sector of an update sweeps
+                                  at its own pace -- step launch t runs every
+                                  sector's own next round-robin step, and a
+                                  sector with few blocks starts its next sweep
+                                  while the largest one is still in its first;
+                                  1: all sectors sweep in lockstep, a sweep
+                                  lasting as many launches as the largest
+                                  sector has steps.  The same visits in the
+                                  same order per sector either way, so the
+                                  same results bit for bit.  Lockstep is also
+                                  used with sweep_graph and for sectors of
+                                  more than 4224 vectors (blocks of 8) or 2176
+                                  (blocks of 16).  In a batch the first
+                                  state's value serves every state. */
 } mps_opts;
 
 /* Per-handle counters, accumulated since creation or mps_reset_stats.
@@ -207,7 +221,8 @@ typedef struct {
 
 /* Fill *o with the defaults: chi_max 0, cutoff 0, zero_tol 1e-13,
  * max_sweeps 40, jacobi_tol 0, plain form, modulus 0, blocked_sweeps 0,
- * select_scratch 0, sweep_graph 0, tile_tuning 1, jacobi_block 0. */
+ * select_scratch 0, sweep_graph 0, tile_tuning 1, jacobi_block 0,
+ * jacobi_lockstep 0. */
 void mps_default_opts(mps_opts* o);
 
 /* Create a state of L sites with local dimension d (occupations 0..d-1,

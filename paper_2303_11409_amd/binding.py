@@ -52,7 +52,8 @@ class mps_opts(C.Structure):
     _fields_ = [("chi_max", C.c_int), ("cutoff", C.c_double), ("zero_tol", C.c_double),
                 ("max_sweeps", C.c_int), ("jacobi_tol", C.c_double), ("form", C.c_int),
                 ("modulus", C.c_int), ("blocked_sweeps", C.c_int), ("select_scratch", C.c_int),
-                ("sweep_graph", C.c_int), ("tile_tuning", C.c_int), ("jacobi_block", C.c_int)]
+                ("sweep_graph", C.c_int), ("tile_tuning", C.c_int), ("jacobi_block", C.c_int),
+                ("jacobi_lockstep", C.c_int)]
 
 
 class mps_stats(C.Structure):
@@ -205,7 +206,7 @@ class MPS:
                  zero_tol: float = 1e-13, max_sweeps: int = 40, jacobi_tol: float = 0.0,
                  device: Optional[TorchDevice] = None, form: int = FORM_PLAIN_C128, modulus: int = 0,
                  blocked_sweeps: int = 0, select_scratch: int = 0, sweep_graph: int = 0, charge_map=None,
-                 tile_tuning: int = 1, jacobi_block: int = 0, _handle=None):
+                 tile_tuning: int = 1, jacobi_block: int = 0, jacobi_lockstep: int = 0, _handle=None):
         self._lib = lib()
         self.L = len(occupation)
         self.d = d
@@ -217,7 +218,7 @@ class MPS:
         self._dev_struct = self._dev.struct()
         self._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus),
                               int(blocked_sweeps), int(select_scratch), int(sweep_graph), int(tile_tuning),
-                              int(jacobi_block))
+                              int(jacobi_block), int(jacobi_lockstep))
         self._h = C.c_void_p()
         if _handle is not None:
             self._h = _handle
@@ -245,7 +246,7 @@ class MPS:
                    jacobi_tol: float = 0.0, device: Optional[TorchDevice] = None,
                    form: int = FORM_PLAIN_C128, modulus: int = 0, blocked_sweeps: int = 0,
                    select_scratch: int = 0, sweep_graph: int = 0, tile_tuning: int = 1,
-                   jacobi_block: int = 0) -> "MPS":
+                   jacobi_block: int = 0, jacobi_lockstep: int = 0) -> "MPS":
         L = len(gammas)
         dims = [len(c) for c in bond_charges]
         obj = cls.__new__(cls)
@@ -258,7 +259,7 @@ class MPS:
         obj._dev_struct = obj._dev.struct()
         obj._opts = mps_opts(chi_max, cutoff, zero_tol, max_sweeps, jacobi_tol, int(form), int(modulus),
                              int(blocked_sweeps), int(select_scratch), int(sweep_graph), int(tile_tuning),
-                             int(jacobi_block))
+                             int(jacobi_block), int(jacobi_lockstep))
         obj._h = C.c_void_p()
         c_dims = (C.c_int * (L + 1))(*dims)
         flat = [int(c) for b in bond_charges for c in b]

@@ -220,7 +220,7 @@ struct JacobiOut {
   int sweeps;             // sweeps in which the sector was still active
   int rotations;          // block pairs rotated, summed over sweeps
   int converged;
-  int rot_this_sweep;     // block pairs rotated in the current sweep
+  int rot3[3];            // block pairs rotated in sweep w, at rot3[w % 3] (lockstep launches: rot3[0])
   unsigned long long gram_units;    // sum over evaluated pairs of nv^2 * len
   unsigned long long apply_units;   // sum over rotated pairs of nv^2 * (len + tall accumulator len)
   double fro2;            // squared Frobenius norm of the sector (rotation invariant)

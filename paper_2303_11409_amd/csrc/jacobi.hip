@@ -130,7 +130,7 @@ jacobi_init(const SectorWork* __restrict__ secs, const int* __restrict__ list,
     o.sweeps = 0;
     o.rotations = 0;
     o.converged = n < 2 ? 1 : 0;
-    o.rot_this_sweep = 0;
+    o.rot3[0] = o.rot3[1] = o.rot3[2] = 0;
     o.gram_units = 0;
     o.apply_units = 0;
     double fro2 = 0.0;
@@ -396,11 +396,94 @@ __device__ void jac_gram_eig(double2 (*gs)[kJP + 2], double2 (*g1)[kJP + 2], dou
 constexpr double kJacLoose = 1e-8;
 constexpr double kJacNoise = 64.0;
 
+// Where the workgroup of block pair w (blocks of JB vectors) stands in step
+// launch t, and its rows.  Lockstep launches (desync 0) run step t of every
+// sector's current sweep; the sweep ends in kernels of their own
+// (jacobi_sweep_end, jacobi_sort).  Desynchronised launches run, for every
+// sector, its own step s = t mod (nb - 1) of its sweep t div (nb - 1), so a
+// sector with few blocks starts its next sweep without waiting for the
+// largest one.  There, at s = 0 of every sweep after the first, the sector's
+// workgroups first close the previous sweep as jacobi_sweep_end would (pair
+// 0 keeps the books and counts the sector out of ctr[0], into ctr[1] when it
+// stops unconverged at the sweep limit) and take their rows in the order
+// jacobi_sort would write (descending norm, index order among equals;
+// scratch holds the n norms), writing that order for the sweep's later steps;
+// the sweep's rotation count is rot3[sweep % 3], and its visits leave the
+// vector norms in buffer sweep % 2 of norm2 (nstride doubles apart), so that
+// the first step of the next sweep sorts on the other buffer while visits of
+// that step write theirs.  Sets the slot, the norm buffer nbuf, the rows
+// vrow[0 .. 2 JB) (-1: absent) and returns the number present, or -1
+// (uniform) when the pair has nothing to do.
+template <int JB>
+__device__ int jac_setup(const JacobiPairWork& w, const SectorWork& sw, int sid, int t, int desync, int blocked,
+                         int* __restrict__ ctr, JacobiOut* __restrict__ st, int* __restrict__ perm,
+                         const double* __restrict__ norm2, long long nstride, double* scratch, int* vrow, int& slot,
+                         int& nbuf) {
+  const int tid = threadIdx.x;
+  const int n = sw.tall ? sw.c : sw.r;
+  int s = t, sweep = 0;
+  if (desync) {
+    s = t % (w.nb - 1);
+    sweep = t / (w.nb - 1);
+    if (sweep > blocked || (sweep == blocked && s > 0)) return -1;
+  } else if (s >= w.nb - 1) {
+    return -1;
+  }
+  slot = desync ? sweep % 3 : 0;
+  nbuf = desync ? sweep & 1 : 0;
+  int bi, bj;
+  rr_pair(s, w.k, w.nb, bi, bj);
+  const int vI = bi * JB, vJ = bj * JB;
+  const int nI = max(0, min(JB, n - vI)), nJ = max(0, min(JB, n - vJ));
+  if (desync && s == 0 && sweep > 0) {
+    const int rot = st[sid].rot3[(sweep - 1) % 3];
+    const bool done = rot == 0 || sweep >= blocked;
+    if (w.k == 0 && tid == 0) {
+      JacobiOut* o = st + sid;
+      o->sweeps += 1;
+      o->rotations += rot;
+      if (rot == 0) o->converged = 1;
+      if (done) {
+        atomicSub(&ctr[0], 1);
+        if (rot != 0) atomicAdd(&ctr[1], 1);
+      } else {
+        o->rot3[(sweep + 1) % 3] = 0;
+      }
+    }
+    if (done) return -1;
+    const double* prev = norm2 + (size_t)((sweep - 1) & 1) * nstride + sw.sig;
+    for (int i = tid; i < n; i += blockDim.x) scratch[i] = prev[i];
+    if (tid < 2 * JB) vrow[tid] = -1;
+    __syncthreads();
+    for (int i = tid; i < n; i += blockDim.x) {
+      const double v = scratch[i];
+      int rank = 0;
+      for (int q = 0; q < n; ++q) {
+        const double u = scratch[q];
+        rank += (u > v) || (u == v && q < i);
+      }
+      int at = -1;
+      if (rank >= vI && rank < vI + nI) at = rank - vI;
+      else if (rank >= vJ && rank < vJ + nJ) at = JB + rank - vJ;
+      if (at >= 0) {
+        vrow[at] = i;
+        perm[sw.sig + rank] = i;
+      }
+    }
+  } else if (tid < 2 * JB) {
+    const int pos = tid < JB ? vI + tid : vJ + (tid - JB);
+    const int lim = tid < JB ? vI + nI : vJ + nJ;
+    vrow[tid] = pos < lim ? perm[sw.sig + pos] : -1;
+  }
+  __syncthreads();
+  return nI + nJ;
+}
+
 __global__ void __launch_bounds__(256)
 jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiPairWork* __restrict__ pairs,
-                  int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
-                  JacobiOut* __restrict__ st, const int* __restrict__ perm, double* __restrict__ norm2,
-                  double tol_opt, int max_inner) {
+                  int t, int desync, int blocked, int* __restrict__ ctr, double2* __restrict__ theta,
+                  double2* __restrict__ accbuf, JacobiOut* __restrict__ st, int* __restrict__ perm,
+                  double* __restrict__ norm2, long long nstride, double tol_opt, int max_inner) {
   // xs stages column chunks of the vectors; during the eig it is the second G
   // buffer.  Rows are padded by two elements: with a stride of kJP + 2 the
   // entries one round-robin step reads fall on more distinct LDS banks than
@@ -414,7 +497,6 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiPairWork* __r
   __shared__ int4 anyf[2];
   int parity = 0;
   const JacobiPairWork w = pairs[blockIdx.x];
-  if (step >= w.nb - 1) return;
   const int sid = w.sector;
   if (st[sid].converged) return;
   const SectorWork sw = secs[sid];
@@ -424,21 +506,13 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiPairWork* __r
   double2* x = theta + sw.off;
   const double tol = jac_tol(tol_opt, len);
   const double floor_g = (double)len * DBL_EPSILON * DBL_EPSILON * st[sid].fro2;
-  int bi, bj;
-  rr_pair(step, w.k, w.nb, bi, bj);
-  const int vI = bi * kJB, vJ = bj * kJB;
-  const int nI = max(0, min(kJB, n - vI)), nJ = max(0, min(kJB, n - vJ));
-  const int nv = nI + nJ;
   const int tid = threadIdx.x;
+  // block I holds the vectors at sorted positions 16 I .. 16 I + 15
+  int slot = 0, nbuf = 0;
+  const int nv = jac_setup<kJB>(w, sw, sid, t, desync, blocked, ctr, st, perm, norm2, nstride,
+                                reinterpret_cast<double*>(&xs[0][0]), vrow, slot, nbuf);
   // a block paired with the empty padding block still orthogonalises its own vectors
   if (nv < 2) return;
-  // block I holds the vectors at sorted positions 16 I .. 16 I + 15
-  if (tid < kJP) {
-    const int pos = tid < kJB ? vI + tid : vJ + (tid - kJB);
-    const int lim = tid < kJB ? vI + nI : vJ + nJ;
-    vrow[tid] = pos < lim ? perm[sw.sig + pos] : -1;
-  }
-  __syncthreads();
   bool fresh = false;          // gs holds the Gram matrix of the current vectors
   for (int pass = 0; pass < 2; ++pass) {
     if (!fresh) {
@@ -456,7 +530,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiPairWork* __r
     }
     const bool need = jac_any_above(gs, tol, floor_g, anyf, parity);
     if (!need) break;
-    if (pass == 0 && tid == 0) atomicAdd(&st[sid].rot_this_sweep, 1);
+    if (pass == 0 && tid == 0) atomicAdd(&st[sid].rot3[slot], 1);
     // ---- rotate G (at most max_inner sweeps), W = accumulated product
     for (int e = tid; e < kJP * kJP; e += blockDim.x) {
       const int r = e / kJP, c = e % kJP;
@@ -483,7 +557,7 @@ jacobi_block_step(const SectorWork* __restrict__ secs, const JacobiPairWork* __r
   // latest squared norms of the pair's vectors (the Gram diagonal; after a
   // rotation the rotated Gram's diagonal), for the next sweep's ordering
   __syncthreads();
-  if (tid < kJP && vrow[tid] >= 0) norm2[sw.sig + vrow[tid]] = gs[tid][tid].x;
+  if (tid < kJP && vrow[tid] >= 0) norm2[(size_t)nbuf * nstride + sw.sig + vrow[tid]] = gs[tid][tid].x;
 }
 
 // ---------------------------------------------------------------------------
@@ -718,9 +792,9 @@ __device__ void jac8_gram_eig(double2 (*gs)[kJP8 + 1], double2 (*ws)[kJP8 + 1], 
 // bookkeeping as in jacobi_block_step.
 __global__ void __launch_bounds__(kJ8Threads)
 jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiPairWork* __restrict__ pairs,
-                   int step, double2* __restrict__ theta, double2* __restrict__ accbuf,
-                   JacobiOut* __restrict__ st, const int* __restrict__ perm, double* __restrict__ norm2,
-                   double tol_opt, int max_inner) {
+                   int t, int desync, int blocked, int* __restrict__ ctr, double2* __restrict__ theta,
+                   double2* __restrict__ accbuf, JacobiOut* __restrict__ st, int* __restrict__ perm,
+                   double* __restrict__ norm2, long long nstride, double tol_opt, int max_inner) {
   __shared__ double2 xt[kJ8Waves][kJP8][33];
   __shared__ double2 gs[kJP8][kJP8 + 1];
   __shared__ double2 ws[kJP8][kJP8 + 1];
@@ -729,7 +803,6 @@ jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiPairWork* __
   __shared__ int anyf[2][kJ8Waves];
   int parity = 0;
   const JacobiPairWork w = pairs[blockIdx.x];
-  if (step >= w.nb - 1) return;
   const int sid = w.sector;
   if (st[sid].converged) return;
   const SectorWork sw = secs[sid];
@@ -739,19 +812,11 @@ jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiPairWork* __
   double2* x = theta + sw.off;
   const double tol = jac_tol(tol_opt, len);
   const double floor_g = (double)len * DBL_EPSILON * DBL_EPSILON * st[sid].fro2;
-  int bi, bj;
-  rr_pair(step, w.k, w.nb, bi, bj);
-  const int vI = bi * kJB8, vJ = bj * kJB8;
-  const int nI = max(0, min(kJB8, n - vI)), nJ = max(0, min(kJB8, n - vJ));
-  const int nv = nI + nJ;
   const int tid = threadIdx.x;
+  int slot = 0, nbuf = 0;
+  const int nv = jac_setup<kJB8>(w, sw, sid, t, desync, blocked, ctr, st, perm, norm2, nstride,
+                                 reinterpret_cast<double*>(&xt[0][0][0]), vrow, slot, nbuf);
   if (nv < 2) return;
-  if (tid < kJP8) {
-    const int pos = tid < kJB8 ? vI + tid : vJ + (tid - kJB8);
-    const int lim = tid < kJB8 ? vI + nI : vJ + nJ;
-    vrow[tid] = pos < lim ? perm[sw.sig + pos] : -1;
-  }
-  __syncthreads();
   bool fresh = false;
   for (int pass = 0; pass < 2; ++pass) {
     if (!fresh) {
@@ -766,7 +831,7 @@ jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiPairWork* __
     }
     const bool need = jac8_any_above(gs, tol, floor_g, anyf, parity);
     if (!need) break;
-    if (pass == 0 && tid == 0) atomicAdd(&st[sid].rot_this_sweep, 1);
+    if (pass == 0 && tid == 0) atomicAdd(&st[sid].rot3[slot], 1);
     if (tid < 256) {
       const int r = tid >> 4, c = tid & 15;
       ws[r][c] = make_double2(r == c ? 1.0 : 0.0, 0.0);
@@ -788,7 +853,7 @@ jacobi_block_step8(const SectorWork* __restrict__ secs, const JacobiPairWork* __
     if (pass == 0) break;
   }
   __syncthreads();
-  if (tid < kJP8 && vrow[tid] >= 0) norm2[sw.sig + vrow[tid]] = gs[tid][tid].x;
+  if (tid < kJP8 && vrow[tid] >= 0) norm2[(size_t)nbuf * nstride + sw.sig + vrow[tid]] = gs[tid][tid].x;
 }
 
 // Scalar one-sided Jacobi sweeps on the vectors themselves, for the rare
@@ -886,14 +951,14 @@ jacobi_sweep_end(const int* __restrict__ list, const int* __restrict__ nbs, int 
     JacobiOut o = st[s];
     if (o.converged) continue;
     o.sweeps += 1;
-    o.rotations += o.rot_this_sweep;
-    if (o.rot_this_sweep == 0) {
+    o.rotations += o.rot3[0];
+    if (o.rot3[0] == 0) {
       o.converged = 1;
     } else {
       atomicOr(&act, 1);
       atomicMax(&maxnb, nbs[i]);
     }
-    o.rot_this_sweep = 0;
+    o.rot3[0] = 0;
     st[s] = o;
   }
   __syncthreads();
@@ -1000,16 +1065,21 @@ hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiPairWork* pairs, int npairs,
-                              int step, double2* theta, double2* acc, JacobiOut* st, const int* perm,
-                              double* norm2, double tol, int max_inner, int block, hipStream_t s) {
+int jacobi_desync_rows(int block) {
+  return block == kJB8 ? kJ8Waves * kJP8 * 33 * 2 : kJP * (kJP + 2) * 2;
+}
+
+hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiPairWork* pairs, int npairs, int t,
+                              int desync, int blocked, int* ctr, double2* theta, double2* acc, JacobiOut* st,
+                              int* perm, double* norm2, long long nstride, double tol, int max_inner, int block,
+                              hipStream_t s) {
   if (npairs <= 0) return hipSuccess;
   if (block == kJB8)
-    hipLaunchKernelGGL(jacobi_block_step8, dim3(npairs), dim3(kJ8Threads), 0, s, secs, pairs, step, theta, acc,
-                       st, perm, norm2, tol, max_inner);
+    hipLaunchKernelGGL(jacobi_block_step8, dim3(npairs), dim3(kJ8Threads), 0, s, secs, pairs, t, desync, blocked,
+                       ctr, theta, acc, st, perm, norm2, nstride, tol, max_inner);
   else if (block == kJB)
-    hipLaunchKernelGGL(jacobi_block_step, dim3(npairs), dim3(256), 0, s, secs, pairs, step, theta, acc,
-                       st, perm, norm2, tol, max_inner);
+    hipLaunchKernelGGL(jacobi_block_step, dim3(npairs), dim3(256), 0, s, secs, pairs, t, desync, blocked, ctr,
+                       theta, acc, st, perm, norm2, nstride, tol, max_inner);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

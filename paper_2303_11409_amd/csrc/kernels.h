@@ -20,9 +20,18 @@ hipError_t launch_theta(const GateWork* gates, const ThetaTile* tiles, int ntile
 hipError_t launch_jacobi_init(const SectorWork* secs, const int* list, int count,
                               const double2* theta, double2* acc, JacobiOut* st, int* perm,
                               double* norm2, hipStream_t s);
-hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiPairWork* pairs, int npairs,
-                              int step, double2* theta, double2* acc, JacobiOut* st, const int* perm,
-                              double* norm2, double tol, int max_inner, int block, hipStream_t s);
+// One step launch over every block pair: step t of every sector's sweep
+// (desync 0), or every sector's own step t mod (nb - 1) of its sweep
+// t div (nb - 1) with the sweep ends folded in (desync 1; blocked: the sweep
+// limit; ctr[0] counts the sectors still sweeping, ctr[1] those stopped
+// unconverged; norm2 holds two buffers of nstride doubles, one per sweep
+// parity).  Desynchronised launches need every sector's vector count at most
+// jacobi_desync_rows(block).
+int jacobi_desync_rows(int block);
+hipError_t launch_jacobi_step(const SectorWork* secs, const JacobiPairWork* pairs, int npairs, int t,
+                              int desync, int blocked, int* ctr, double2* theta, double2* acc, JacobiOut* st,
+                              int* perm, double* norm2, long long nstride, double tol, int max_inner, int block,
+                              hipStream_t s);
 hipError_t launch_jacobi_sort(const SectorWork* secs, const int* list, int count, int maxrows, const JacobiOut* st,
                               int* perm, const double* norm2, hipStream_t s);
 // active[0]: a sector still rotates; active[1]: the largest block count nbs[i]

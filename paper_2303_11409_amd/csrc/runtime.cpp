@@ -152,6 +152,9 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr int kMaxInnerSweeps = 1;
 // Blocked sweeps before an unconverged sector is finished by scalar sweeps.
 constexpr int kBlockedSweeps = 32;
+// Desynchronised sweeps: launches between reads of the count of sectors
+// still sweeping.
+constexpr int kDesyncCheck = 4;
 
 }  // namespace
 
@@ -838,7 +841,8 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   STCHK(ensure(h, h->sigma, (size_t)P.sig_elems * sizeof(double)));
   STCHK(ensure(h, h->order, (size_t)P.sig_elems * sizeof(int)));
   STCHK(ensure(h, h->jperm, (size_t)P.sig_elems * sizeof(int)));
-  STCHK(ensure(h, h->jnorm, (size_t)P.sig_elems * sizeof(double)));
+  // two buffers of vector norms (one per sweep parity in desynchronised sweeps)
+  STCHK(ensure(h, h->jnorm, 2 * (size_t)std::max<long long>(P.sig_elems, 1) * sizeof(double)));
   STCHK(ensure(h, h->tbefore, std::max<size_t>(P.tiles.size(), 1) * sizeof(double)));
   double* d_tbefore = static_cast<double*>(h->tbefore.p);
   if (P.split) {
@@ -866,6 +870,11 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
   const size_t o_jlist = pk.add(P.jlist.data(), P.jlist.size() * sizeof(int));
   const size_t o_jblk = pk.add(P.jpairlist.data(), P.jpairlist.size() * sizeof(JacobiPairWork));
   const size_t o_jnb = pk.add(P.jnb.data(), P.jnb.size() * sizeof(int));
+  // desynchronised sweeps: sectors still sweeping (every sector with two or
+  // more vectors), sectors stopped unconverged
+  int ctr0[2] = {0, 0};
+  for (const SectorWork& sw : P.secs) ctr0[0] += std::min(sw.r, sw.c) >= 2 ? 1 : 0;
+  const size_t o_ctr = pk.add(ctr0, sizeof ctr0);
   const size_t o_seloff = pk.add(P.sel_off.data(), P.sel_off.size() * sizeof(long long));
   const size_t o_sg = pk.add(P.sg.data(), P.sg.size() * sizeof(SplitGemm));
   const size_t o_spl = pk.add(P.spl.data(), P.spl.size() * sizeof(SplitPlanes));
@@ -972,6 +981,11 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     // finished by scalar sweeps on its vectors
     const int blocked =
         std::min(h->opts.max_sweeps, h->opts.blocked_sweeps > 0 ? h->opts.blocked_sweeps : kBlockedSweeps);
+    // Sectors sweep at their own pace (below) unless lockstep is asked for, the
+    // sweeps are replayed from a graph, or a sector has more vectors than a
+    // workgroup's staging tiles hold for its norm sort.
+    const bool desync = h->opts.jacobi_lockstep == 0 && !h->opts.sweep_graph &&
+                        P.jmaxrows <= jacobi_desync_rows(P.jblock);
     // The step launches of a sweep are the same every sweep: with sweep_graph
     // they are captured once per update into a HIP graph and replayed on the
     // handle's stream.  Capture runs on a private stream (the null stream
@@ -989,8 +1003,9 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
       HIPCHK(hipStreamBeginCapture(h->cap_st, hipStreamCaptureModeThreadLocal));
       hipError_t ce = hipSuccess;
       for (int step = 0; step < P.jmaxnb - 1 && ce == hipSuccess; ++step)
-        ce = launch_jacobi_step(d_secs, at<JacobiPairWork>(h->plan, o_jblk), P.jpairs, step, scaled, d_acc,
-                                d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, P.jblock, h->cap_st);
+        ce = launch_jacobi_step(d_secs, at<JacobiPairWork>(h->plan, o_jblk), P.jpairs, step, 0, blocked, nullptr,
+                                scaled, d_acc, d_jst, d_perm, d_norm, 0, h->opts.jacobi_tol, kMaxInnerSweeps,
+                                P.jblock, h->cap_st);
       const hipError_t ee = hipStreamEndCapture(h->cap_st, &graph);
       if (ce == hipSuccess) ce = ee;
       if (ce == hipSuccess) ce = hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0);
@@ -1009,47 +1024,95 @@ mps_status apply_batch(const std::vector<GateRef>& refs, double* discarded) {
     STCHK(ev_get(h, &fev[0]));
     STCHK(ev_get(h, &fev[1]));
     int still_active = 1;
-    int issued = 0;
-    int steps = P.jmaxnb - 1;
-    for (int sweep = 0; sweep < blocked; ++sweep) {
+    if (desync) {
+      // Every sector sweeps at its own pace: launch t runs each sector's step
+      // t mod (nb - 1) of its sweep t div (nb - 1), the sweep ends folded
+      // into the sweeps' first steps (jac_setup), so the launches number the
+      // steps of the slowest sector rather than the sweeps of the slowest
+      // times the steps of the largest.  Every kDesyncCheck launches the
+      // count of sectors still sweeping is copied into a pinned slot behind
+      // them; the host reads the previous copy, so it stays a few launches
+      // ahead of the device, and stops once that count reads zero (launches
+      // after that find every sector finished and return at once).
+      int* d_ctr = at<int>(h->plan, o_ctr);
+      const int tmax = blocked * (P.jmaxnb - 1) + 1;
       Timer tm(h, P.jblock == kJB8 ? K_JACOBI8 : K_JACOBI);
       STCHK(tm.start());
-      int launched = P.jmaxnb - 1;
-      if (gexec) {
-        HIPCHK(hipGraphLaunch(gexec, h->st));
-        h->stats.graph_launches += 1;
-      } else {
-        launched = steps;
-        for (int step = 0; step < steps; ++step)
-          HIPCHK(launch_jacobi_step(d_secs, at<JacobiPairWork>(h->plan, o_jblk), P.jpairs, step, scaled, d_acc,
-                                    d_jst, d_perm, d_norm, h->opts.jacobi_tol, kMaxInnerSweeps, P.jblock, h->st));
+      int t = 0, checks = 0;
+      bool over = false;
+      while (t < tmax && !over) {
+        HIPCHK(launch_jacobi_step(d_secs, at<JacobiPairWork>(h->plan, o_jblk), P.jpairs, t, 1, blocked, d_ctr,
+                                  scaled, d_acc, d_jst, d_perm, d_norm, P.sig_elems, h->opts.jacobi_tol,
+                                  kMaxInnerSweeps, P.jblock, h->st));
+        ++t;
+        if (t % kDesyncCheck == 0) {
+          HIPCHK(hipMemcpyAsync(const_cast<int*>(flag) + 2 * (checks & 1), d_ctr, 2 * sizeof(int),
+                                hipMemcpyDeviceToHost, h->st));
+          HIPCHK(hipEventRecord(fev[checks & 1], h->st));
+          if (checks >= 1) {
+            HIPCHK(hipEventSynchronize(fev[(checks - 1) & 1]));
+            if (flag[2 * ((checks - 1) & 1)] == 0) over = true;
+          }
+          ++checks;
+        }
       }
       STCHK(tm.stop());
-      h->stats.jacobi_launches += launched;
-      if (P.jblock == kJB8) h->stats.jacobi8_launches += launched;
-      Timer ta(h, K_JACOBI_AUX);
-      STCHK(ta.start());
-      HIPCHK(launch_jacobi_sweep_end(d_jlist, at<int>(h->plan, o_jnb), ns, d_jst, d_active, h->st));
-      HIPCHK(launch_jacobi_sort(d_secs, d_jlist, ns, P.jmaxrows, d_jst, d_perm, d_norm, h->st));
-      STCHK(ta.stop());
-      h->stats.jacobi_aux_launches += 2;
-      HIPCHK(hipMemcpyAsync(const_cast<int*>(flag) + 2 * (sweep & 1), d_active, 2 * sizeof(int),
+      h->stats.jacobi_launches += t;
+      if (P.jblock == kJB8) h->stats.jacobi8_launches += t;
+      // the counters after the last launch: every sector has finished (at
+      // the latest at its step 0 of sweep `blocked`); still_active when one
+      // stopped unconverged
+      HIPCHK(hipMemcpyAsync(const_cast<int*>(flag) + 2 * (checks & 1), d_ctr, 2 * sizeof(int),
                             hipMemcpyDeviceToHost, h->st));
-      HIPCHK(hipEventRecord(fev[sweep & 1], h->st));
-      issued = sweep + 1;
-      if (sweep >= 1) {
-        HIPCHK(hipEventSynchronize(fev[(sweep - 1) & 1]));
-        const volatile int* fl = flag + 2 * ((sweep - 1) & 1);
-        if (!fl[0]) {
-          still_active = 0;
-          break;
+      HIPCHK(hipEventRecord(fev[checks & 1], h->st));
+      HIPCHK(hipEventSynchronize(fev[checks & 1]));
+      const volatile int* fl = flag + 2 * (checks & 1);
+      if (fl[0] != 0) return fail(MPS_E_DEVICE, "%d Jacobi sectors still sweeping after the last step", fl[0]);
+      still_active = fl[1] > 0 ? 1 : 0;
+    } else {
+      int issued = 0;
+      int steps = P.jmaxnb - 1;
+      for (int sweep = 0; sweep < blocked; ++sweep) {
+        Timer tm(h, P.jblock == kJB8 ? K_JACOBI8 : K_JACOBI);
+        STCHK(tm.start());
+        int launched = P.jmaxnb - 1;
+        if (gexec) {
+          HIPCHK(hipGraphLaunch(gexec, h->st));
+          h->stats.graph_launches += 1;
+        } else {
+          launched = steps;
+          for (int step = 0; step < steps; ++step)
+            HIPCHK(launch_jacobi_step(d_secs, at<JacobiPairWork>(h->plan, o_jblk), P.jpairs, step, 0, blocked,
+                                      nullptr, scaled, d_acc, d_jst, d_perm, d_norm, 0, h->opts.jacobi_tol,
+                                      kMaxInnerSweeps, P.jblock, h->st));
         }
-        steps = std::min(steps, std::max(fl[1] - 1, 1));
+        STCHK(tm.stop());
+        h->stats.jacobi_launches += launched;
+        if (P.jblock == kJB8) h->stats.jacobi8_launches += launched;
+        Timer ta(h, K_JACOBI_AUX);
+        STCHK(ta.start());
+        HIPCHK(launch_jacobi_sweep_end(d_jlist, at<int>(h->plan, o_jnb), ns, d_jst, d_active, h->st));
+        HIPCHK(launch_jacobi_sort(d_secs, d_jlist, ns, P.jmaxrows, d_jst, d_perm, d_norm, h->st));
+        STCHK(ta.stop());
+        h->stats.jacobi_aux_launches += 2;
+        HIPCHK(hipMemcpyAsync(const_cast<int*>(flag) + 2 * (sweep & 1), d_active, 2 * sizeof(int),
+                              hipMemcpyDeviceToHost, h->st));
+        HIPCHK(hipEventRecord(fev[sweep & 1], h->st));
+        issued = sweep + 1;
+        if (sweep >= 1) {
+          HIPCHK(hipEventSynchronize(fev[(sweep - 1) & 1]));
+          const volatile int* fl = flag + 2 * ((sweep - 1) & 1);
+          if (!fl[0]) {
+            still_active = 0;
+            break;
+          }
+          steps = std::min(steps, std::max(fl[1] - 1, 1));
+        }
       }
-    }
-    if (still_active && issued > 0) {
-      HIPCHK(hipEventSynchronize(fev[(issued - 1) & 1]));
-      still_active = flag[2 * ((issued - 1) & 1)];
+      if (still_active && issued > 0) {
+        HIPCHK(hipEventSynchronize(fev[(issued - 1) & 1]));
+        still_active = flag[2 * ((issued - 1) & 1)];
+      }
     }
     h->pool.push_back(fev[0]);
     h->pool.push_back(fev[1]);
@@ -1311,6 +1374,7 @@ void mps_default_opts(mps_opts* o) {
   o->sweep_graph = 0;
   o->tile_tuning = 1;
   o->jacobi_block = 0;
+  o->jacobi_lockstep = 0;
 }
 
 const char* mps_last_error(void) { return g_err.c_str(); }
@@ -1349,6 +1413,7 @@ mps_status create_impl(int L, int d, int n_photons, const int* bond_dim, const i
     return fail(MPS_E_ARG, "tile_tuning must lie in 0..%d", 1 + kSgVariants);
   if (o.jacobi_block != 0 && o.jacobi_block != kJB8 && o.jacobi_block != kJB)
     return fail(MPS_E_ARG, "jacobi_block must be 0, %d or %d", kJB8, kJB);
+  if (o.jacobi_lockstep != 0 && o.jacobi_lockstep != 1) return fail(MPS_E_ARG, "jacobi_lockstep must be 0 or 1");
   if (!(o.cutoff >= 0.0) || !(o.zero_tol >= 0.0)) return fail(MPS_E_ARG, "cutoff and zero_tol must be >= 0");
   if (o.form != MPS_FORM_PLAIN_C128 && o.form != MPS_FORM_SPLIT_BF16X3) return fail(MPS_E_ARG, "unknown form %d", o.form);
   if (o.modulus != 0 && o.modulus != d)

@@ -159,6 +159,22 @@ def test_jacobi_block_option():
     assert not h.value
 
 
+def test_jacobi_lockstep_option():
+    """jacobi_lockstep defaults to 0 (sectors sweep at their own pace); only 0 and
+    1 are accepted, checked on the host."""
+    lib = binding.lib()
+    o = binding.mps_opts()
+    lib.mps_default_opts(C.byref(o))
+    assert o.jacobi_lockstep == 0
+    h = C.c_void_p()
+    occ = (C.c_int * 4)(1, 0, 1, 0)
+    for bad in (-1, 2):
+        o.jacobi_lockstep = bad
+        assert lib.mps_create_product(4, 3, occ, C.byref(o), None, C.byref(h)) == -1
+        assert "jacobi_lockstep" in lib.mps_last_error().decode()
+    assert not h.value
+
+
 def test_last_leaks_argument_errors():
     lib = binding.lib()
     n = C.c_int(-1)

@@ -244,6 +244,40 @@ def test_full_32_mode_circuit_vs_stored_oracle(mps_cls, jacobi_block):
     m.close()
 
 
+@pytest.mark.parametrize("jacobi_block,blocked", [(8, 0), (16, 0), (8, 3)])
+def test_desynchronised_sweeps_equal_lockstep(mps_cls, jacobi_block, blocked):
+    """Sectors sweeping at their own pace run the same visits in the same order
+    per sector as all sectors in lockstep, so the two agree bit for bit:
+    discarded weights, amplitudes, Schmidt values, sweep and rotation counts,
+    over the first 14 layers of the 32-mode circuit; with blocks of 8 and of
+    16, and with the blocked sweeps stopped after 3 so that the scalar finish
+    takes over the sectors still rotating."""
+    cfg = circuits.config_plain_gpu()
+    pats = circuits.sample_patterns(32, 16, 4, 200, 11)
+    out = []
+    for lockstep in (1, 0):
+        m = mps_cls(cfg["occupation"], 4, chi_max=512, cutoff=1e-12, jacobi_block=jacobi_block,
+                    jacobi_lockstep=lockstep, blocked_sweeps=blocked)
+        disc = []
+        for lay in cfg["layers"][:14]:
+            disc.extend(m.apply_layer([g.site for g in lay], [g.u for g in lay]))
+        st = m.stats()
+        out.append((np.array(disc), m.amplitudes(pats), [m.bond_lambda(b) for b in range(1, 32)],
+                    st["sweeps"], st["rotations"], st["polish_launches"], st["jacobi_launches"],
+                    st["jacobi_aux_launches"]))
+        m.close()
+    (d0, a0, l0, sw0, r0, p0, n0, x0), (d1, a1, l1, sw1, r1, p1, n1, x1) = out
+    assert np.array_equal(d0, d1)
+    assert np.array_equal(a0, a1)
+    assert all(np.array_equal(x, y) for x, y in zip(l0, l1))
+    assert (sw0, r0, p0) == (sw1, r1, p1)
+    assert x1 < x0                 # no sweep-end and sort launches
+    if blocked:
+        assert p1 > 0              # the scalar finish ran
+    else:
+        assert n1 <= n0
+
+
 def test_batching_form_equals_each_state_alone(mps_cls):
     """Batching form: the layers of several circuits of different sizes, cuts and
     depths go through mps_apply_batch together; every state ends bitwise equal
