@@ -154,7 +154,7 @@ constexpr int kMaxInnerSweeps = 1;
 constexpr int kBlockedSweeps = 32;
 // Desynchronised sweeps: launches between reads of the count of sectors
 // still sweeping.
-constexpr int kDesyncCheck = 4;
+constexpr int kDesyncCheck = 16;
 
 }  // namespace
 
