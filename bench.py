@@ -42,7 +42,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6     # MI355X: 256 CU x 2.4 GHz x 128 FP64 flop/cl
 # rocprofv3 --pmc runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline
 # --batch-copies 0 --mix-circuits 0 --chi2048-layers 0 --serve-seconds 0
 # --samples 4096 --no-tebd`
-# (FETCH_SIZE, WRITE_SIZE; mean over the 36816 launches) scaled by the same
+# (FETCH_SIZE, WRITE_SIZE; mean over the 37824 launches) scaled by the same
 # counters on a plain 256 MiB copy (`bench.py --copy-probe`: FETCH_SIZE reads
 # 131085.2 KiB and WRITE_SIZE 262144 KiB per copy, so reads scale by 1.99980
 # and writes by 1).  Valid only for the Jacobi source (csrc/jacobi.hip), the
@@ -52,7 +52,7 @@ MEASURED_TRAFFIC = {
     "kernels_sha256": "12dacabb38dad06b357254205d6132dbed451e54da57798eafcafd2e5fcb4414",
     "max_inner": 1,
     "jacobi_block": 8,
-    "fetch_kib": 18094.9, "write_kib": 24042.1,
+    "fetch_kib": 17616.5, "write_kib": 23400.7,
     "fetch_scale": 262144.0 / 131085.2, "write_scale": 1.0,
 }
 
