@@ -105,10 +105,12 @@ typedef struct {
  *   modulus    0 (default): U(1), the charge of Eqs. (E2)-(E4) is the particle
  *              number.  n >= 2: a discrete Abelian charge Z_n (the paper's
  *              general Abelian symmetries, Sec. I), the particle number mod n,
- *              with d == n: every local occupation is a distinct charge, bond
+ *              with d <= n (every local occupation a distinct charge): bond
  *              charges lie in 0..n-1, the charge balance of Eq. (E4) holds mod
- *              n (bond 0 carries n_photons mod n), and every left/right charge
- *              pair of a site is allowed with occupation (cL - cR) mod n.  A
+ *              n (bond 0 carries n_photons mod n), and a left/right charge
+ *              pair of a site is allowed when (cL - cR) mod n is an occupation
+ *              (with d == n every pair; with d < n a sector's rows and columns
+ *              are the charges within d of its middle charge, cyclically).  A
  *              Z_n state takes dense gates only (mps_apply_layer_dense).
  * The kept count is K = max(1, min(chi_max, K_eps, K_zero)). */
 typedef enum { MPS_FORM_PLAIN_C128 = 0, MPS_FORM_SPLIT_BF16X3 = 1 } mps_form;
@@ -122,7 +124,7 @@ typedef struct {
   int form;                    /* mps_form */
   int modulus;                 /* 0: U(1), the charge is the particle number;
                                   n >= 2: Z_n, the particle number mod n
-                                  (requires d == n; bond charges 0..n-1) */
+                                  (requires d <= n; bond charges 0..n-1) */
   int blocked_sweeps;          /* blocked Jacobi sweeps before the scalar
                                   finish (0: the default, 32); at most
                                   max_sweeps.  A diagnostic: a small value

@@ -198,7 +198,7 @@ def _close_all() -> None:
 
 class MPS:
     """A U(1)-symmetric MPS on the GPU, created as a Fock product state.
-    modulus n >= 2 (with d == n) makes the charge the particle number mod n;
+    modulus n >= 2 (with d <= n) makes the charge the particle number mod n;
     charge_map (d x K integers, K = 1 or 2) gives every local state its own
     charge with K independent U(1) components (mps_create_product_charges)."""
 

@@ -80,7 +80,7 @@ inline int cwrap(int mod, int c) { return mod ? ((c % mod) + mod) % mod : c; }
 // entry of a site tensor between left charge cL and right charge cR is allowed
 // when cL - cR is some step[p] (mod n for Z_n), and then p is its local state:
 // Eq. (E2), with the occupation in the Kronecker delta replaced by the local
-// state's charge.  U(1) photon number: step[p] = p.  Z_n (d = n): the same
+// state's charge.  U(1) photon number: step[p] = p.  Z_n (d <= n): the same
 // steps, charges mod n.  Two U(1) charges (the general Abelian case): a charge
 // (c1, c2) is the integer key c1 * radix + c2 with radix above twice every
 // second component, so keys add like the pairs, a difference of keys fixes
@@ -160,7 +160,7 @@ constexpr int kDesyncCheck = 16;
 
 struct mps_state {
   int L = 0, d = 0, N = 0;
-  int mod = 0;                   // 0: U(1) particle number; n: particle number mod n (d == n)
+  int mod = 0;                   // 0: U(1) particle number; n: particle number mod n (d <= n)
   int device = 0;                // the GPU current when the handle was created
   int cus = 256;                 // compute units of that GPU
   ChargeRule rule;               // charges of the local states (U(1), Z_n, or two U(1) components)
@@ -531,8 +531,9 @@ mps_status plan_batch(const std::vector<GateRef>& refs, BatchPlan& P) {
     gw.zero_tol = h->opts.zero_tol;
     // sectors: every middle charge m with rows (charges cL of bond s with
     // cL - m a local charge) and columns (charges cR of bond s+2 with m - cR a
-    // local charge).  U(1): cL in [m, m+d-1], cR in [m-d+1, m]; Z_n (d = n):
-    // every row and every column belongs to every m.  The rows of Theta(m)
+    // local charge).  U(1): cL in [m, m+d-1], cR in [m-d+1, m]; Z_n: the same
+    // mod n (with d = n every row and every column belongs to every m; with
+    // d < n a range that wraps past n-1 is two blocks of the frame).  The rows of Theta(m)
     // are its row blocks in ascending charge order, packed; blocks adjacent
     // in the frame are merged (so a U(1) or Z_n sector is one row block and
     // one column block).
@@ -1416,8 +1417,10 @@ mps_status create_impl(int L, int d, int n_photons, const int* bond_dim, const i
   if (o.jacobi_lockstep != 0 && o.jacobi_lockstep != 1) return fail(MPS_E_ARG, "jacobi_lockstep must be 0 or 1");
   if (!(o.cutoff >= 0.0) || !(o.zero_tol >= 0.0)) return fail(MPS_E_ARG, "cutoff and zero_tol must be >= 0");
   if (o.form != MPS_FORM_PLAIN_C128 && o.form != MPS_FORM_SPLIT_BF16X3) return fail(MPS_E_ARG, "unknown form %d", o.form);
-  if (o.modulus != 0 && o.modulus != d)
-    return fail(MPS_E_ARG, "a Z_n charge needs n equal to the local dimension (modulus %d, d %d)", o.modulus, d);
+  // a Z_n charge gives each local occupation its own charge: n >= d
+  if (o.modulus != 0 && (o.modulus < 2 || o.modulus < d))
+    return fail(MPS_E_ARG, "a Z_n charge needs n >= 2 and n at least the local dimension (modulus %d, d %d)",
+                o.modulus, d);
   const int zn = o.modulus;
   const int nq = zn ? n_photons % zn : n_photons;     // charge of bond 0
   ChargeRule R;
@@ -1913,8 +1916,8 @@ mps_status plan_envs(mps_state* h, const std::vector<double2*>& eb, double2* tbu
     size_t toff = 0;
     for (size_t i = 0; i < B1.charge.size(); ++i) {
       const int cp = B1.charge[i];
-      // rows of bond s reaching charge cp: charges cp + step[p] (Z_n with d = n:
-      // all).  The range from the smallest to the largest such charge may hold
+      // rows of bond s reaching charge cp: charges cp + step[p] (Z_n: taken
+      // as all).  The range from the smallest to the largest such charge may hold
       // other charges too; their entries of B[s] are structural zeros, so they
       // add nothing (U(1): exactly the charges cp..cp+d-1)
       const int w0 = h->mod ? 0 : B0.off[B0.lower(cp + h->rule.minstep)];

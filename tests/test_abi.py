@@ -105,17 +105,20 @@ def test_form_option():
 
 
 def test_modulus_option():
-    """The default charge is U(1) (modulus 0); a Z_n charge needs n == d, and its
-    bond charges must lie in 0..n-1 -- both refused before any device work."""
+    """The default charge is U(1) (modulus 0); a Z_n charge needs n >= 2 and
+    n >= d (each local occupation its own charge), and its bond charges must
+    lie in 0..n-1 -- all refused before any device work."""
     lib = binding.lib()
     o = binding.mps_opts()
     lib.mps_default_opts(C.byref(o))
     assert o.modulus == 0
     h = C.c_void_p()
     occ = (C.c_int * 4)(1, 0, 1, 0)
-    o.modulus = 3
-    assert lib.mps_create_product(4, 2, occ, C.byref(o), None, C.byref(h)) == -1
-    assert "Z_n" in lib.mps_last_error().decode()
+    for bad, d in ((3, 4), (1, 2), (-2, 2)):
+        o.modulus = bad
+        assert lib.mps_create_product(4, d, occ, C.byref(o), None, C.byref(h)) == -1
+        assert "Z_n" in lib.mps_last_error().decode() or "modulus" in lib.mps_last_error().decode()
+    assert not h.value
     o.modulus = 2
     cd = (C.c_int * 4)(1, 1, 1, 1)
     cc = (C.c_int * 4)(0, 2, 1, 0)

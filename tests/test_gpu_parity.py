@@ -1005,6 +1005,80 @@ def test_zn_random_gates_vs_brute_force(mps_cls, d):
     m.close()
 
 
+def _zn_gates_below_modulus(d, n, L, layers, seed):
+    """Brickwork layers of random gates conserving (p + q) mod n, p, q < d."""
+    from workloads import hamiltonians as ham
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(layers):
+        out.append([ham.DenseGate(s, ham.random_zn_gate(d, int(rng.integers(1 << 30)), modulus=n))
+                    for s in range(k % 2, L - 1, 2)])
+    return out
+
+
+@pytest.mark.parametrize("d,n", [(2, 3), (3, 4), (3, 5), (4, 6)])
+def test_zn_below_modulus_vs_brute_force(mps_cls, d, n):
+    """Z_n with d < n: a sector's rows and columns are the bond charges within d
+    of its middle charge, cyclically, so some charge pairs of a site are not
+    allowed and a sector's frame range can wrap past n-1.  Random gates without
+    truncation against the Fock-space brute force (every amplitude, Schmidt
+    ranks per bond charge); strings of another class mod n give exactly zero.
+    With 2(d-1) < n the gates also keep the particle number, but the bond
+    charges still wrap mod n."""
+    from workloads import hamiltonians as ham
+    L = 6
+    rng = np.random.default_rng(60 + 10 * d + n)
+    occ = [int(x) for x in rng.integers(0, d, size=L)]
+    layers = _zn_gates_below_modulus(d, n, L, 6, 70 + 10 * d + n)
+    m = mps_cls(occ, d, modulus=n)
+    for lay in layers:
+        m.apply_layer_dense([g.site for g in lay], [g.g4 for g in lay])
+    st = fock.run(occ, d, [g for lay in layers for g in lay], modulus=n)
+    pats = np.array(st.basis, dtype=np.int32)
+    got = m.amplitudes(pats)
+    assert np.max(np.abs(got - st.psi)) < 1e-12
+    assert abs(m.norm2() - 1.0) < 1e-12
+    for b in range(L + 1):
+        assert m.bond_sectors(b) == st.schmidt_ranks(b), b
+    other = ham.zn_patterns(L, d, sum(occ) + 1, 50, 7, modulus=n)
+    assert np.all(m.amplitudes(other) == 0)
+    m.close()
+
+
+@pytest.mark.parametrize("d,n,L,chi", [(3, 4, 10, 8), (2, 3, 12, 6)])
+def test_zn_below_modulus_truncated_vs_oracle(mps_cls, d, n, L, chi):
+    """Z_n with d < n and the bond cap binding: discarded weights, Schmidt
+    values, per-bond charges, amplitudes and exact samples against the dense
+    oracle with the same charge."""
+    from oracle import sampling
+    from workloads import hamiltonians as ham
+    rng = np.random.default_rng(80 + d + n)
+    occ = [int(x) for x in rng.integers(0, d, size=L)]
+    layers = _zn_gates_below_modulus(d, n, L, 6, 90 + d + n)
+    m = mps_cls(occ, d, chi_max=chi, cutoff=1e-12, modulus=n)
+    disc = []
+    for lay in layers:
+        disc.extend(m.apply_layer_dense([g.site for g in lay], [g.g4 for g in lay]))
+    ref = dense_mps.DenseMPS(occ, d, chi_max=chi, cutoff=1e-12, modulus=n).run([g for lay in layers for g in lay])
+    assert min(r.margin for r in ref.records) > 1e-9
+    odisc = np.array([r.discarded for r in ref.records])
+    assert odisc.max() > 1e-4
+    assert np.max(np.abs(np.array(disc) - odisc)) <= 1e-12
+    pats = ham.zn_patterns(L, d, sum(occ), 300, 8, modulus=n)
+    close_amps(m.amplitudes(pats), ref.amplitudes(pats))
+    assert abs(m.norm2() - ref.norm2()) <= TOL
+    check_bookkeeping(m, ref)
+    check_lambdas(m, ref)
+    u = np.random.default_rng(75).random((200, L))
+    sp, sprob = m.sample(u)
+    rp, rprob, marg = sampling.mps_samples(ref, u, margins=True)
+    clear = marg > SAMPLE_MARGIN
+    assert np.array_equal(sp[clear], rp[clear])
+    assert np.max(np.abs(sprob - rprob) / rprob) <= 1e-10
+    assert np.all(sp.sum(axis=1) % n == sum(occ) % n) and sp.max() < d
+    m.close()
+
+
 def test_zn_rules(mps_cls):
     """A Z_n state refuses mode unitaries and gates that change the charge mod
     n, and accepts gates that change the particle number by n."""

@@ -137,3 +137,49 @@ def test_u1_gate_is_a_zn_gate_but_not_conversely():
     assert abs(st.amplitude([1, 1, 1])) > 1e-3
     with pytest.raises(ValueError):
         fock.FockState([0, 0, 1], 2).apply_dense(0, g)
+
+
+@pytest.mark.parametrize("d,n", [(2, 3), (3, 4), (3, 5), (4, 5), (4, 6)])
+def test_zn_below_modulus_against_the_full_space(d, n):
+    """Z_n with d < n (several local states can no longer share a residue, but
+    a charge difference need not be an occupation): random gates that conserve
+    (p + q) mod n applied in the full d^L space by Kronecker products.  The
+    state stays in the input's class mod n; the brute force and the dense oracle
+    reproduce it; the audit is clean and each bond's charges (right-hand
+    occupation sums mod n) carry the ranks of the full state's blocks."""
+    L = 5
+    rng = np.random.default_rng(500 + 10 * d + n)
+    occ = [int(x) for x in rng.integers(0, d, size=L)]
+    gates = [ham.DenseGate(int(rng.integers(0, L - 1)), ham.random_zn_gate(d, int(rng.integers(1 << 30)), modulus=n))
+             for _ in range(14)]
+    psi = np.zeros(d ** L, dtype=np.complex128)
+    psi[sum(o * d ** (L - 1 - s) for s, o in enumerate(occ))] = 1.0
+    for g in gates:
+        op = np.kron(np.kron(np.eye(d ** g.site), g.g4), np.eye(d ** (L - g.site - 2)))
+        psi = op @ psi
+    strings = list(itertools.product(range(d), repeat=L))
+    inside = np.array([sum(t) % n == sum(occ) % n for t in strings])
+    assert np.max(np.abs(psi[~inside])) < 1e-13
+    totals = {sum(t) for t, a in zip(strings, psi) if abs(a) > 1e-6}
+    # two sites change their total only when it can wrap past n: 2(d-1) >= n
+    assert (len(totals) > 1) == (2 * (d - 1) >= n), totals
+    st = fock.run(occ, d, gates, modulus=n)
+    ex = np.array([psi[sum(o * d ** (L - 1 - s) for s, o in enumerate(t))] for t in st.basis])
+    assert len(st.basis) == int(inside.sum())
+    assert np.max(np.abs(st.psi - ex)) < 1e-13
+    m = dense_mps.DenseMPS(occ, d, modulus=n).run(gates)
+    assert np.max(np.abs(m.amplitudes(np.array(st.basis)) - ex)) < 1e-12
+    for b in range(L + 1):
+        M = psi.reshape(d ** b, d ** (L - b))
+        right = list(itertools.product(range(d), repeat=L - b))
+        ranks = {}
+        for c in range(n):
+            cols = [j for j, t in enumerate(right) if sum(t) % n == c]
+            if cols:
+                sv = np.linalg.svd(M[:, cols], compute_uv=False)
+                r = int(np.sum(sv > 1e-10))
+                if r:
+                    ranks[c] = r
+        assert m.audit_clean(b), b
+        assert m.bond_charges(b) == ranks, (b, m.bond_charges(b), ranks)
+        assert st.schmidt_ranks(b) == ranks, b

@@ -64,6 +64,18 @@ def test_zn_input_generators():
             for c in range(d * d):
                 if (r // d + r % d - c // d - c % d) % d:
                     assert g[r, c] == 0
+    # n above d: the charge classes of p + q mod n (some of them one pair long)
+    for d, n in ((2, 3), (3, 4), (3, 5)):
+        g = ham.random_zn_gate(d, 6, modulus=n)
+        assert np.max(np.abs(g.conj().T @ g - np.eye(d * d))) < 1e-13
+        for r in range(d * d):
+            for c in range(d * d):
+                if (r // d + r % d - c // d - c % d) % n:
+                    assert g[r, c] == 0
+        # a class holding more than one pair mixes it: not a diagonal gate
+        assert np.count_nonzero(np.abs(g) > 1e-12) > d * d
+    pats = ham.zn_patterns(5, 3, 2, 300, 2, modulus=5)
+    assert pats.max() < 3 and np.all(pats.sum(axis=1) % 5 == 2)
 
 
 def test_charge_map_patterns_uniform_over_the_sector():

@@ -269,14 +269,16 @@ def config_clock_quench() -> dict:
     return config_tebd("clock", 64, 3, [0] * 64, 0.05, 60, 256, 1e-12, J=1.0, f=0.3)
 
 
-def zn_patterns(L: int, d: int, charge: int, count: int, seed: int) -> np.ndarray:
+def zn_patterns(L: int, d: int, charge: int, count: int, seed: int, modulus: int = 0) -> np.ndarray:
     """count uniform occupation strings (occupations < d) whose particle number
-    is `charge` mod d (rejection sampling, numpy.random.default_rng(seed))."""
+    is `charge` mod n, n = modulus or d when 0 (rejection sampling,
+    numpy.random.default_rng(seed))."""
+    n = modulus or d
     rng = np.random.default_rng(seed)
     out = []
     while len(out) < count:
         t = rng.integers(0, d, size=L)
-        if int(t.sum()) % d == charge % d:
+        if int(t.sum()) % n == charge % n:
             out.append(t)
     return np.array(out, dtype=np.int32)
 
@@ -319,14 +321,19 @@ def charge_map_patterns(L: int, charge_map, total, count: int, seed: int) -> np.
     return out
 
 
-def random_zn_gate(d: int, seed: int, unitary: bool = True) -> np.ndarray:
-    """A random d^2 x d^2 gate that conserves p + q mod d (a Z_d charge): a
-    Haar-random (or complex Gaussian) block for each total mod d."""
+def random_zn_gate(d: int, seed: int, unitary: bool = True, modulus: int = 0) -> np.ndarray:
+    """A random d^2 x d^2 gate that conserves p + q mod n, n = modulus or d when
+    0 (a Z_n charge, n >= d): a Haar-random (or complex Gaussian) block for each
+    total mod n, over the pairs (p, q) of occupations below d with that total."""
+    n = modulus or d
     rng = np.random.default_rng(seed)
     g = np.zeros((d * d, d * d), dtype=np.complex128)
-    for n in range(d):
-        idx = [p * d + (n - p) % d for p in range(d)]
-        z = (rng.standard_normal((d, d)) + 1j * rng.standard_normal((d, d))) / np.sqrt(2)
+    for tot in range(n):
+        idx = [p * d + q for p in range(d) for q in range(d) if (p + q) % n == tot]
+        if not idx:
+            continue
+        k = len(idx)
+        z = (rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))) / np.sqrt(2)
         if unitary:
             q, r = np.linalg.qr(z)
             z = q * (np.diag(r) / np.abs(np.diag(r)))
