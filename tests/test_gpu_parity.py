@@ -1079,6 +1079,41 @@ def test_zn_below_modulus_truncated_vs_oracle(mps_cls, d, n, L, chi):
     m.close()
 
 
+def test_zn_below_modulus_forms(mps_cls):
+    """The d < n truncated brickwork through the other settings of the update:
+    sectors in lockstep give bitwise the default's state, Jacobi blocks of 8 and
+    of 16 each meet the oracle, and the split-BF16 form stays within its bar of
+    the plain form."""
+    from paper_2303_11409_amd.binding import FORM_SPLIT_BF16X3
+    from workloads import hamiltonians as ham
+    d, n, L, chi = 3, 4, 10, 8
+    rng = np.random.default_rng(80 + d + n)
+    occ = [int(x) for x in rng.integers(0, d, size=L)]
+    layers = _zn_gates_below_modulus(d, n, L, 6, 90 + d + n)
+    pats = ham.zn_patterns(L, d, sum(occ), 300, 9, modulus=n)
+
+    def run(**kw):
+        m = mps_cls(occ, d, chi_max=chi, cutoff=1e-12, modulus=n, **kw)
+        disc = []
+        for lay in layers:
+            disc.extend(m.apply_layer_dense([g.site for g in lay], [g.g4 for g in lay]))
+        amps = m.amplitudes(pats)
+        m.close()
+        return amps, np.array(disc)
+
+    ref = dense_mps.DenseMPS(occ, d, chi_max=chi, cutoff=1e-12, modulus=n).run([g for lay in layers for g in lay])
+    ramps = ref.amplitudes(pats)
+    base, bdisc = run()
+    lock, ldisc = run(jacobi_lockstep=1)
+    assert np.array_equal(base, lock) and np.array_equal(bdisc, ldisc)
+    for jb in (8, 16):
+        amps, disc = run(jacobi_block=jb)
+        close_amps(amps, ramps)
+        assert np.max(np.abs(disc - np.array([r.discarded for r in ref.records]))) <= 1e-12
+    split, _ = run(form=FORM_SPLIT_BF16X3)
+    close_amps(split, base, TOL_SPLIT)
+
+
 def test_zn_rules(mps_cls):
     """A Z_n state refuses mode unitaries and gates that change the charge mod
     n, and accepts gates that change the particle number by n."""
